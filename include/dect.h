@@ -1,0 +1,215 @@
+/*
+ * dect.h -- C-ABI of the MI355X (gfx950) library for one-step iterative
+ * estimation of effective atomic number Z and relative electron density rho_e
+ * from dual-energy fan-beam sinograms.
+ *
+ * Method: Wang et al., "One-step Iterative Estimation of Effective Atomic
+ * Number and Electron Density for Dual Energy CT" (arXiv 2308.01290):
+ * objective (10) with its gradient-L0 regularisers on f1, f2, rho_e and Z^m,
+ * split by half-quadratic splitting into subproblems (13a)-(13d) and iterated
+ * as Algorithm 1.  Here the two image-domain data terms of (10) are replaced by
+ * projection-domain terms eta*||A(f1 mu1(E_k) + f2 mu2(E_k)) - p_k||^2, A the
+ * fan-beam projector and p_k the post-log sinograms, so every iteration runs a
+ * forward projection and a matched back-projection of both energy channels.
+ *
+ * Conventions shared by every entry point
+ *   - Array pointers are DEVICE pointers (hipMalloc / torch CUDA tensors) owned
+ *     by the caller; the library never frees them.  Host pointers are marked.
+ *   - Images are float32 [batch][n_y][n_x], sinograms float32
+ *     [batch][n_views][n_det], row-major and contiguous.  Image row i, column k
+ *     is the half-open square [x0 + k*d, x0 + (k+1)*d) x [y0 + i*d, y0 + (i+1)*d)
+ *     with x0 = -n_x*d/2, y0 = -n_y*d/2 (mm), d = pixel_mm.
+ *   - Sinogram values are post-log line integrals p = -ln(I/I0) (dimensionless);
+ *     attenuation images are in 1/mm; system-matrix entries in mm.
+ *   - Calls validate their arguments on the host and return a negative status
+ *     before anything is enqueued; otherwise they only ENQUEUE work on `stream`
+ *     and return DECT_OK.  Results are valid after the caller synchronises the
+ *     stream.  Asynchronous device faults surface at that synchronisation.
+ *   - dect_last_error() returns a thread-local message for the last failure.
+ *   - No exception crosses the ABI.  Calls are reentrant given distinct
+ *     workspaces / solver handles; one handle must not be used from two host
+ *     threads at once.
+ */
+#ifndef DECT_H
+#define DECT_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    DECT_OK = 0,
+    DECT_EINVAL = -1,       /* invalid argument or geometry                 */
+    DECT_EWORKSPACE = -2,   /* caller workspace too small or misaligned     */
+    DECT_ENOMEM = -3,       /* device allocation failed                     */
+    DECT_EDEVICE = -4,      /* a HIP runtime call failed                    */
+    DECT_EUNSUPPORTED = -5  /* valid request this build does not implement  */
+};
+
+/* Fan-beam geometry (mm, radians).
+ * View v has angle theta_v = angle0_rad + v*arc_rad/n_views; the source sits at
+ * sid_mm*(cos, sin) theta_v; the flat detector is centred at
+ * -(sdd_mm - sid_mm)*(cos, sin) theta_v with axis e = (-sin, cos) theta_v, and
+ * bin j is centred at u_j = (j - (n_det-1)/2)*det_pitch_mm + det_offset_mm
+ * along e.  Ray (v, j) is the line from the source to that bin centre.
+ * det_pitch_mm = 0 selects the pitch whose fan just covers the image corners:
+ * 2*sdd*tan(asin(R/sid))/n_det, R = pixel_mm*hypot(n_x, n_y)/2.
+ * Valid geometry: all sizes >= 1, pixel_mm > 0, sdd_mm > sid_mm > 0, and the
+ * image half-diagonal R < sid_mm and R < sdd_mm - sid_mm. */
+typedef struct dect_geometry {
+    int32_t n_x, n_y;
+    double pixel_mm;
+    int32_t n_views;
+    double angle0_rad, arc_rad;
+    int32_t n_det;
+    double det_pitch_mm, det_offset_mm;
+    double sid_mm, sdd_mm;
+} dect_geometry;
+
+/* Method parameters.  Zero in the marked fields selects the default.
+ *   E_lo_keV, E_hi_keV   effective acquisition energies (60, 90)
+ *   E1_keV, E2_keV       synthesis energies of eq. (2a,b) (50, 200)
+ *   m, n, Cp             photoelectric model rho_e*Cp*Z^m/E^n, Section II-B
+ *                        (3.94, 3.2, 9.8e-24); the coefficient is normalised
+ *                        to water, Cp*Z_w^(3.8 - m), so water keeps the
+ *                        printed m = 3.8 value
+ *   Z_w                  effective atomic number of water (7.42)
+ *   basis_Z, basis_rho   the two basis materials of eq. (1a,b)
+ *                        (SB3 cortical bone 14.14/1.69, water 7.42/1.00)
+ *   lambda               gradient-L0 weight of eq. (5)/(10) (0.01)
+ *   beta0, beta_max      relaxation schedule of Algorithm 1 (0 -> 2*lambda, 1e5)
+ *   kappa                beta growth rate (0 -> (beta_max/beta0)^(1/n_iter))
+ *   eta, xi              projection-data and coupling weights (0 -> the
+ *                        normalisations that give water unit curvature)
+ *   n_iter               outer iterations K of Algorithm 1 (>= 1)
+ *   f_inner              steepest-descent/CG steps on the f-subproblem per
+ *                        outer iteration (this build: 1)
+ *   t_tol, t_maxit       PCG tolerance (relative residual) and cap of the
+ *                        Z^m subproblem (1e-6, 200)
+ *   rho_min, t_min       output mask: Z = 0 where rho_e < rho_min; t' clamp
+ *                        (0.1, 1e-6) */
+typedef struct dect_params {
+    double E_lo_keV, E_hi_keV, E1_keV, E2_keV;
+    double m, n, Cp, Z_w;
+    double basis_Z[2], basis_rho[2];
+    double lambda, beta0, beta_max, kappa;
+    double eta, xi;
+    int32_t n_iter, f_inner;
+    double t_tol;
+    int32_t t_maxit;
+    double rho_min, t_min;
+} dect_params;
+
+/* Fill *p with the defaults listed above (HOST pointer). */
+void dect_default_params(dect_params* p);
+
+/* Validate *g (HOST pointer) and replace det_pitch_mm = 0 by the
+ * corner-covering pitch.  Returns DECT_OK or DECT_EINVAL. */
+int dect_resolve_geometry(dect_geometry* g);
+
+/* Linear attenuation (1/mm) at E_lo and E_hi of n materials with given
+ * (Z, rho_e), from the model of Section II-B (eq. (3a,b) scaled by the
+ * electron density of water).  HOST pointers, FP64.  Used to synthesise
+ * inputs; not part of the solve. */
+int dect_attenuation(const dect_params* p, const double* Z, const double* rho_e, int64_t n,
+                     double* mu_lo, double* mu_hi);
+
+/* Forward projection sino = A img: for every ray, the sum of pixel values
+ * times the ray's chord length through each pixel square (exact, Siddon-type
+ * traversal, FP32 with compensated ray sums).  img [batch][n_y][n_x] ->
+ * sino [batch][n_views][n_det].  Needs a device-side table the library keeps
+ * per geometry (allocated on first use). */
+int dect_project(const dect_geometry* g, const float* img, float* sino, int32_t batch,
+                 hipStream_t stream);
+
+/* Back-projection img = A^T sino with the same chord lengths as dect_project
+ * (the exact adjoint up to FP32 rounding; voxel-driven gather, deterministic). */
+int dect_backproject(const dect_geometry* g, const float* sino, float* img, int32_t batch,
+                     hipStream_t stream);
+
+/* Flat-detector fan-beam filtered back-projection (cosine weighting, Ram-Lak
+ * filter, distance-weighted back-projection with linear interpolation): the
+ * attenuation images that Algorithm 1 requires as input, reconstructed from
+ * the sinograms.  sino [batch][n_views][n_det] -> img [batch][n_y][n_x]. */
+int dect_fbp(const dect_geometry* g, const float* sino, float* img, int32_t batch,
+             hipStream_t stream);
+
+/* One half-quadratic-splitting step of the gradient-L0 model, eq. (5)-(9):
+ *   (h, v) = hard threshold (9) of the periodic forward differences of g^(k)
+ *            ((h, v) = 0 where dx^2 + dy^2 <= lambda/beta, decided in FP32);
+ *   g^(k+1) = argmin ||w*g - g_tilde||^2 + beta*||D g - (h, v)||^2,
+ * i.e. (diag(w^2) + beta D^T D) g = w*g_tilde + beta D^T (h, v), periodic.
+ * weight == NULL means w = 1 and uses the FFT closed form of Section II-C;
+ * otherwise preconditioned CG to relative residual `tol` (at most `max_iter`
+ * iterations).  g is in/out ([batch][n_y][n_x]); h_out, v_out may be NULL.
+ * ws/ws_bytes: device workspace of at least dect_l0_step_workspace_bytes()
+ * bytes, 256-byte aligned; NULL lets the library allocate it (stream-ordered).
+ * Sizes: n_x, n_y of the form 2^a*3^b with b <= 1, 8 <= n <= 1024. */
+size_t dect_l0_step_workspace_bytes(int32_t n_y, int32_t n_x, int32_t batch, int weighted);
+int dect_l0_step(const float* g_tilde, const float* weight, float* g, float* h_out, float* v_out,
+                 int32_t n_y, int32_t n_x, int32_t batch, double lambda, double beta,
+                 double tol, int32_t max_iter, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---- solver -------------------------------------------------------------
+ * A solver holds one batch of slices that share geometry and parameters, and
+ * all per-iteration state on the device: basis images f1, f2, rho_e, the
+ * normalised t' = Z^m/Z_w^m, the combined residual sinograms and scratch.
+ * Algorithm 1, sinogram form, per outer iteration k (all updates read iterate k):
+ *   f-step   one steepest-descent step with exact line search on the
+ *            f-subproblem (13a) with projection data terms (one back-projection
+ *            of the residuals, one forward projection of the direction);
+ *   rho step subproblem (13b) by the FFT closed form;
+ *   t' step  subproblem (13c) by preconditioned CG;
+ *   beta <- kappa*beta.
+ * Initialisation: FBP of both sinograms, then the per-pixel closed forms of
+ * Algorithm 1's initialisation. */
+typedef struct dect_solver dect_solver;
+
+/* Workspace bytes a solver needs for this geometry/params/batch. */
+size_t dect_solve_workspace_bytes(const dect_geometry* g, const dect_params* p, int32_t batch);
+
+/* Create a solver bound to `stream`.  ws == NULL: the library allocates the
+ * workspace; otherwise the caller's device buffer of >= the size above (256-
+ * byte aligned) is used and must outlive the solver.  *out is a HOST handle. */
+int dect_solver_create(const dect_geometry* g, const dect_params* p, int32_t batch, void* ws,
+                       size_t ws_bytes, hipStream_t stream, dect_solver** out);
+int dect_solver_destroy(dect_solver* s);
+
+/* Initialise from the sinograms (FBP + closed forms); k = 0. */
+int dect_solver_init(dect_solver* s, const float* sino_lo, const float* sino_hi);
+
+/* Load an explicit state (f1, f2, rho_e, t' images) at outer iteration k
+ * together with the sinograms it is fitted to. */
+int dect_solver_set_state(dect_solver* s, const float* sino_lo, const float* sino_hi,
+                          const float* f1, const float* f2, const float* rho, const float* t,
+                          int32_t k);
+
+/* Run n outer iterations (k -> k + n). */
+int dect_solver_iterate(dect_solver* s, int32_t n);
+
+/* Copy the state images out (any pointer may be NULL). */
+int dect_solver_get_state(const dect_solver* s, float* f1, float* f2, float* rho, float* t);
+
+/* Output maps: rho_e, and Z = Z_w*max(t', t_min)^(1/m) with Z = 0 where
+ * rho_e < rho_min. */
+int dect_solver_finish(dect_solver* s, float* Z, float* rho_e);
+
+/* Number of outer iterations done and the PCG iterations spent in the last
+ * t' step (HOST query; synchronises the solver's stream). */
+int dect_solver_stats(const dect_solver* s, int32_t* k, int32_t* last_pcg_iters);
+
+/* Whole solve: create, init, n_iter iterations, finish, destroy. */
+int dect_solve(const float* sino_lo, const float* sino_hi, const dect_geometry* g,
+               const dect_params* p, float* Z_out, float* rho_out, int32_t batch, void* ws,
+               size_t ws_bytes, hipStream_t stream);
+
+const char* dect_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DECT_H */

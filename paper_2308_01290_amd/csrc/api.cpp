@@ -1,0 +1,825 @@
+// C-ABI of libdect: argument validation, physics constants, workspace plans
+// and the launch sequence of Algorithm 1 (sinogram form) on one HIP stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "dect_internal.h"
+
+namespace dect {
+
+static thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+// ---------------------------------------------------------------------------
+// geometry
+// ---------------------------------------------------------------------------
+static double corner_pitch(const dect_geometry& g) {
+    const double R = 0.5 * g.pixel_mm * std::hypot((double)g.n_x, (double)g.n_y);
+    return 2.0 * g.sdd_mm * std::tan(std::asin(R / g.sid_mm)) / g.n_det;
+}
+
+int resolve_geometry(const dect_geometry* in, Geom* out) {
+    if (!in) return fail(DECT_EINVAL, "geometry is NULL");
+    const dect_geometry& g = *in;
+    if (g.n_x < 1 || g.n_y < 1 || g.n_views < 1 || g.n_det < 1)
+        return fail(DECT_EINVAL, "geometry sizes must be >= 1 (n_x=%d n_y=%d n_views=%d n_det=%d)",
+                    g.n_x, g.n_y, g.n_views, g.n_det);
+    if (g.n_x > 16384 || g.n_y > 16384 || g.n_det > 65536 || g.n_views > 65536)
+        return fail(DECT_EINVAL, "geometry sizes too large");
+    if (!(g.pixel_mm > 0) || !(g.sid_mm > 0) || !(g.sdd_mm > g.sid_mm))
+        return fail(DECT_EINVAL, "need pixel_mm > 0 and sdd_mm > sid_mm > 0");
+    if (!std::isfinite(g.angle0_rad) || !std::isfinite(g.arc_rad) || g.arc_rad == 0.0 ||
+        !std::isfinite(g.det_offset_mm) || !(g.det_pitch_mm >= 0))
+        return fail(DECT_EINVAL, "non-finite angle, zero arc, or negative pitch");
+    const double R = 0.5 * g.pixel_mm * std::hypot((double)g.n_x, (double)g.n_y);
+    if (!(R < g.sid_mm) || !(R < g.sdd_mm - g.sid_mm))
+        return fail(DECT_EINVAL,
+                    "image half-diagonal %.3f mm must lie strictly between source (%.3f) and "
+                    "detector (%.3f)",
+                    R, g.sid_mm, g.sdd_mm - g.sid_mm);
+    out->nx = g.n_x;
+    out->ny = g.n_y;
+    out->nv = g.n_views;
+    out->nd = g.n_det;
+    out->dx = g.pixel_mm;
+    out->angle0 = g.angle0_rad;
+    out->arc = g.arc_rad;
+    out->pitch = g.det_pitch_mm > 0 ? g.det_pitch_mm : corner_pitch(g);
+    out->offset = g.det_offset_mm;
+    out->sid = g.sid_mm;
+    out->sdd = g.sdd_mm;
+    return DECT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// physics (Section II-B), FP64
+// ---------------------------------------------------------------------------
+static const double kR0 = 2.818e-13;          // cm
+static const double kMe = 510.975;            // keV
+static const double kNeWater = 6.02214076e23 * 10.0 / 18.01528;   // electrons / cm^3
+static const double kMPrinted = 3.8;
+
+static double kn(double E) {
+    const double g = E / kMe;
+    const double l = std::log1p(2.0 * g);
+    const double c0 = 2.0 * M_PI * kR0 * kR0;
+    return c0 * ((1.0 + g) / (g * g) * (2.0 * (1.0 + g) / (1.0 + 2.0 * g) - l / g) + l / (2.0 * g) -
+                 (1.0 + 3.0 * g) / ((1.0 + 2.0 * g) * (1.0 + 2.0 * g)));
+}
+
+static double sigma(const dect_params& p, double Z, double E) {
+    return p.Cp * std::pow(p.Z_w, kMPrinted - p.m) * std::pow(Z, p.m) / std::pow(E, p.n) + kn(E);
+}
+
+static double mu_of(const dect_params& p, double Z, double rho, double E) {
+    return 0.1 * kNeWater * rho * sigma(p, Z, E);
+}
+
+static int check_params(const dect_params* p) {
+    if (!p) return fail(DECT_EINVAL, "params is NULL");
+    const double e[4] = {p->E_lo_keV, p->E_hi_keV, p->E1_keV, p->E2_keV};
+    for (double v : e)
+        if (!(v > 0) || !std::isfinite(v)) return fail(DECT_EINVAL, "energies must be > 0");
+    if (!(p->m > 0) || !(p->n > 0) || !(p->Cp > 0) || !(p->Z_w > 0))
+        return fail(DECT_EINVAL, "m, n, Cp, Z_w must be > 0");
+    for (int i = 0; i < 2; ++i)
+        if (!(p->basis_Z[i] > 0) || !(p->basis_rho[i] > 0))
+            return fail(DECT_EINVAL, "basis materials need Z > 0 and rho_e > 0");
+    if (!(p->lambda >= 0) || !(p->beta0 >= 0) || !(p->beta_max > 0) || !(p->kappa >= 0) ||
+        !(p->eta >= 0) || !(p->xi >= 0))
+        return fail(DECT_EINVAL, "lambda, beta0, kappa, eta, xi must be >= 0 and beta_max > 0");
+    if (p->n_iter < 1) return fail(DECT_EINVAL, "n_iter must be >= 1");
+    if (p->f_inner != 1)
+        return fail(DECT_EUNSUPPORTED, "f_inner = %d: this build runs one f-step per iteration",
+                    p->f_inner);
+    if (!(p->t_tol > 0) || p->t_maxit < 1) return fail(DECT_EINVAL, "t_tol > 0 and t_maxit >= 1");
+    if (!(p->t_min > 0)) return fail(DECT_EINVAL, "t_min must be > 0");
+    return DECT_OK;
+}
+
+int build_model(const dect_params& p, Model* M) {
+    const double El[2] = {p.E_lo_keV, p.E_hi_keV};
+    const double Es[2] = {p.E1_keV, p.E2_keV};
+    for (int k = 0; k < 2; ++k)
+        for (int i = 0; i < 2; ++i) M->C[k][i] = mu_of(p, p.basis_Z[i], p.basis_rho[i], El[k]);
+    for (int j = 0; j < 2; ++j)
+        for (int i = 0; i < 2; ++i) M->Ms[j][i] = p.basis_rho[i] * sigma(p, p.basis_Z[i], Es[j]) * 1e24;
+    for (int j = 0; j < 2; ++j) M->psi[j] = kn(Es[j]) * 1e24;
+    M->cpb = p.Cp * std::pow(p.Z_w, kMPrinted - p.m) * 1e24;
+    M->Zw = p.Z_w;
+    M->m = p.m;
+    M->e1n = std::pow(p.E1_keV, p.n);
+    M->e2n = std::pow(p.E2_keV, p.n);
+    const double zwm = std::pow(p.Z_w, p.m);
+    M->a[0] = M->cpb * zwm / M->e1n;
+    M->a[1] = M->cpb * zwm / M->e2n;
+    M->crho = M->psi[0] * M->e1n - M->psi[1] * M->e2n;
+    M->Ww = M->cpb * zwm * (M->psi[0] / M->e2n - M->psi[1] / M->e1n);
+    const double det = M->C[0][0] * M->C[1][1] - M->C[1][0] * M->C[0][1];
+    if (!(std::fabs(det) > 0) || !(std::fabs(M->crho) > 0) || !(std::fabs(M->Ww) > 0))
+        return fail(DECT_EINVAL, "degenerate basis or energies (singular decomposition)");
+    return DECT_OK;
+}
+
+// resolved copy of the parameters (defaults filled in)
+struct Resolved {
+    dect_params p;
+    double eta, xi, beta0, kappa;
+};
+
+static int resolve_params(const dect_params* in, const Geom& g, const Model& M, Resolved* r) {
+    r->p = *in;
+    r->beta0 = in->beta0 > 0 ? in->beta0 : 2.0 * in->lambda;
+    if (!(r->beta0 > 0)) return fail(DECT_EINVAL, "beta0 = 0 needs lambda > 0");
+    r->kappa = in->kappa > 0 ? in->kappa : std::pow(in->beta_max / r->beta0, 1.0 / in->n_iter);
+    if (in->eta > 0) {
+        r->eta = in->eta;
+    } else {
+        const double mwl = mu_of(*in, in->Z_w, 1.0, in->E_lo_keV);
+        const double mwh = mu_of(*in, in->Z_w, 1.0, in->E_hi_keV);
+        r->eta = g.pitch * g.sid / (g.nv * g.dx * g.dx * g.dx * g.sdd * (mwl * mwl + mwh * mwh));
+    }
+    if (in->xi > 0) {
+        r->xi = in->xi;
+    } else {
+        const double s1 = sigma(*in, in->Z_w, in->E1_keV) * 1e24;
+        const double s2 = sigma(*in, in->Z_w, in->E2_keV) * 1e24;
+        r->xi = 1.0 / (s1 * s1 + s2 * s2);
+    }
+    (void)M;
+    return DECT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// per-geometry ray tables for the stand-alone operators
+// ---------------------------------------------------------------------------
+struct TableEntry {
+    Geom g;
+    int device;
+    void* mem;
+    RayTable t;
+};
+static std::mutex g_tab_mu;
+static std::vector<TableEntry> g_tabs;
+
+static bool same_geom(const Geom& a, const Geom& b) {
+    return a.nx == b.nx && a.ny == b.ny && a.nv == b.nv && a.nd == b.nd && a.dx == b.dx &&
+           a.angle0 == b.angle0 && a.arc == b.arc && a.pitch == b.pitch && a.offset == b.offset &&
+           a.sid == b.sid && a.sdd == b.sdd;
+}
+
+static void carve_table(const Geom& g, void* mem, RayTable* t) {
+    char* p = static_cast<char*>(mem);
+    const size_t nr = (size_t)g.nv * g.nd;
+    t->fix = reinterpret_cast<int4*>(p);
+    p += nr * sizeof(int4);
+    t->flt = reinterpret_cast<float2*>(p);
+    p += nr * sizeof(float2);
+    t->span = reinterpret_cast<int2*>(p);
+    p += nr * sizeof(int2);
+    t->view = reinterpret_cast<float4*>(p);
+}
+
+static int get_table(const Geom& g, hipStream_t st, RayTable* out) {
+    int dev = 0;
+    DECT_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_tab_mu);
+    for (auto& e : g_tabs)
+        if (e.device == dev && same_geom(e.g, g)) {
+            *out = e.t;
+            return DECT_OK;
+        }
+    if (g_tabs.size() >= 16) {
+        DECT_HIP(hipDeviceSynchronize());
+        DECT_HIP(hipFree(g_tabs.front().mem));
+        g_tabs.erase(g_tabs.begin());
+    }
+    TableEntry e;
+    e.g = g;
+    e.device = dev;
+    if (hipMalloc(&e.mem, ray_table_bytes(g)) != hipSuccess)
+        return fail(DECT_ENOMEM, "could not allocate the ray table (%zu bytes)", ray_table_bytes(g));
+    carve_table(g, e.mem, &e.t);
+    launch_build_ray_table(g, e.t, st);
+    DECT_HIP(hipGetLastError());
+    DECT_HIP(hipStreamSynchronize(st));   // the table may be used from other streams
+    g_tabs.push_back(e);
+    *out = e.t;
+    return DECT_OK;
+}
+
+// stream-ordered temporary buffer
+struct TempBuf {
+    void* p = nullptr;
+    hipStream_t st = nullptr;
+    ~TempBuf() {
+        if (p) (void)hipFreeAsync(p, st);
+    }
+};
+static int temp_alloc(TempBuf* b, size_t bytes, hipStream_t st) {
+    b->st = st;
+    if (hipMallocAsync(&b->p, bytes, st) != hipSuccess) {
+        b->p = nullptr;
+        return fail(DECT_ENOMEM, "could not allocate %zu bytes of scratch", bytes);
+    }
+    return DECT_OK;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// ---------------------------------------------------------------------------
+// workspace of the L0 step and the solver
+// ---------------------------------------------------------------------------
+struct Carver {
+    char* base;
+    size_t off = 0;
+    template <typename T>
+    T* take(size_t n) {
+        T* p = reinterpret_cast<T*>(base ? base + off : nullptr);
+        off += align256(n * sizeof(T));
+        return p;
+    }
+};
+
+struct PcgBufs {
+    float *r, *z, *p0, *p1, *q, *w2;
+    double* partials;
+    unsigned* counter;
+    PcgState* st;
+};
+
+static void carve_pcg(Carver& c, int ny, int nx, int batch, PcgBufs* b) {
+    const size_t n = (size_t)ny * nx * batch;
+    b->r = c.take<float>(n);
+    b->z = c.take<float>(n);
+    b->p0 = c.take<float>(n);
+    b->p1 = c.take<float>(n);
+    b->q = c.take<float>(n);
+    b->w2 = c.take<float>(n);
+    b->partials = c.take<double>((size_t)batch * pcg_nblocks(ny, nx) * 4);
+    b->counter = c.take<unsigned>((size_t)batch);
+    b->st = c.take<PcgState>((size_t)batch);
+}
+
+static const double kJacobiBelow = 1.0;   // beta below which Jacobi beats the FFT preconditioner
+
+// Runs PCG iterations until every slice converged or max_iter; returns the
+// largest iteration count, or a negative status.
+static int run_pcg(PcgArgs& a, int max_iter, float2* fft_scratch, int* host_done_buf,
+                   hipStream_t st, int* iters_out) {
+    FftArgs fa;
+    fa.src = FFT_SRC_PLAIN;
+    fa.in = a.r;
+    fa.out = a.z;
+    fa.beta = a.beta;
+    fa.c_dev = &a.st[0].cshift;
+    fa.skip = &a.st[0].done;
+    if (!a.jacobi) {
+        launch_fft_solve(a.ny, a.nx, a.batch, fa, fft_scratch, st);
+        launch_pcg_after_prec_init(a, st);
+    }
+    int it = 0;
+    const int chunk = 8;
+    std::vector<PcgState> hs(a.batch);
+    while (true) {
+        for (int c = 0; c < chunk && it < max_iter; ++c, ++it) {
+            launch_pcg_matvec(a, it & 1, it == 0, st);
+            launch_pcg_update(a, it & 1, st);
+            if (!a.jacobi) {
+                launch_fft_solve(a.ny, a.nx, a.batch, fa, fft_scratch, st);
+                launch_pcg_after_prec(a, st);
+            }
+        }
+        DECT_HIP(hipGetLastError());
+        DECT_HIP(hipMemcpyAsync(hs.data(), a.st, sizeof(PcgState) * a.batch, hipMemcpyDeviceToHost, st));
+        DECT_HIP(hipStreamSynchronize(st));
+        bool all = true;
+        for (int z = 0; z < a.batch; ++z) all = all && hs[z].done;
+        if (all || it >= max_iter) break;
+    }
+    int mx = 0;
+    for (int z = 0; z < a.batch; ++z) mx = std::max(mx, hs[z].iters);
+    if (iters_out) *iters_out = mx;
+    (void)host_done_buf;
+    return DECT_OK;
+}
+
+}  // namespace dect
+
+using namespace dect;
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+struct dect_solver {
+    Geom g;
+    Resolved rp;
+    Model M;
+    int batch;
+    hipStream_t st;
+    void* ws;
+    bool owns_ws;
+    RayTable tab;
+    float2 *f, *B, *dN, *dT, *S, *zq, *fft;
+    float *rho, *t, *muL, *muH, *fbpq;
+    double *part_img, *part_proj, *alpha;
+    unsigned* cnt_proj;
+    PcgBufs pcg;
+    int k;
+    double beta;
+    int last_pcg;
+};
+
+extern "C" {
+
+void dect_default_params(dect_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->E_lo_keV = 60.0;
+    p->E_hi_keV = 90.0;
+    p->E1_keV = 50.0;
+    p->E2_keV = 200.0;
+    p->m = 3.94;
+    p->n = 3.2;
+    p->Cp = 9.8e-24;
+    p->Z_w = 7.42;
+    p->basis_Z[0] = 14.14;
+    p->basis_rho[0] = 1.69;
+    p->basis_Z[1] = 7.42;
+    p->basis_rho[1] = 1.00;
+    p->lambda = 0.01;
+    p->beta0 = 0.0;
+    p->beta_max = 1e5;
+    p->kappa = 0.0;
+    p->eta = 0.0;
+    p->xi = 0.0;
+    p->n_iter = 50;
+    p->f_inner = 1;
+    p->t_tol = 1e-6;
+    p->t_maxit = 200;
+    p->rho_min = 0.1;
+    p->t_min = 1e-6;
+}
+
+int dect_resolve_geometry(dect_geometry* g) {
+    Geom r;
+    const int rc = resolve_geometry(g, &r);
+    if (rc) return rc;
+    g->det_pitch_mm = r.pitch;
+    return DECT_OK;
+}
+
+int dect_attenuation(const dect_params* p, const double* Z, const double* rho_e, int64_t n,
+                     double* mu_lo, double* mu_hi) {
+    if (int rc = check_params(p)) return rc;
+    if (n < 0 || (n > 0 && (!Z || !rho_e || !mu_lo || !mu_hi)))
+        return fail(DECT_EINVAL, "dect_attenuation: bad arrays");
+    for (int64_t i = 0; i < n; ++i) {
+        mu_lo[i] = mu_of(*p, Z[i], rho_e[i], p->E_lo_keV);
+        mu_hi[i] = mu_of(*p, Z[i], rho_e[i], p->E_hi_keV);
+    }
+    return DECT_OK;
+}
+
+int dect_project(const dect_geometry* gin, const float* img, float* sino, int32_t batch,
+                 hipStream_t st) {
+    Geom g;
+    if (int rc = resolve_geometry(gin, &g)) return rc;
+    if (batch < 0) return fail(DECT_EINVAL, "batch must be >= 0");
+    if (batch == 0) return DECT_OK;
+    if (!img || !sino) return fail(DECT_EINVAL, "dect_project: NULL array");
+    RayTable t;
+    if (int rc = get_table(g, st, &t)) return rc;
+    const int np = (batch + 1) / 2;
+    TempBuf tmp;
+    const size_t nN = padN_elems(g) * np, nT = padT_elems(g) * np;
+    if (int rc = temp_alloc(&tmp, (nN + nT) * sizeof(float2), st)) return rc;
+    float2* pN = static_cast<float2*>(tmp.p);
+    float2* pT = pN + nN;
+    launch_pack_pairs(g, img, batch, pN, pT, st);
+    ProjArgs a;
+    a.out = sino;
+    a.nout = batch;
+    launch_project(g, t, pN, pT, np, PROJ_PLAIN, a, st);
+    DECT_HIP(hipGetLastError());
+    return DECT_OK;
+}
+
+int dect_backproject(const dect_geometry* gin, const float* sino, float* img, int32_t batch,
+                     hipStream_t st) {
+    Geom g;
+    if (int rc = resolve_geometry(gin, &g)) return rc;
+    if (batch < 0) return fail(DECT_EINVAL, "batch must be >= 0");
+    if (batch == 0) return DECT_OK;
+    if (!img || !sino) return fail(DECT_EINVAL, "dect_backproject: NULL array");
+    RayTable t;
+    if (int rc = get_table(g, st, &t)) return rc;
+    const int np = (batch + 1) / 2;
+    TempBuf tmp;
+    const size_t nray = (size_t)g.nv * g.nd;
+    if (int rc = temp_alloc(&tmp, nray * np * sizeof(float2), st)) return rc;
+    float2* sp = static_cast<float2*>(tmp.p);
+    launch_pair_sinos(g, sino, batch, sp, st);
+    launch_backproject(g, t, sp, np, nullptr, img, batch, st);
+    DECT_HIP(hipGetLastError());
+    return DECT_OK;
+}
+
+int dect_fbp(const dect_geometry* gin, const float* sino, float* img, int32_t batch,
+             hipStream_t st) {
+    Geom g;
+    if (int rc = resolve_geometry(gin, &g)) return rc;
+    if (batch < 0) return fail(DECT_EINVAL, "batch must be >= 0");
+    if (batch == 0) return DECT_OK;
+    if (!img || !sino) return fail(DECT_EINVAL, "dect_fbp: NULL array");
+    if (g.nd > 8192) return fail(DECT_EINVAL, "dect_fbp: n_det > 8192");
+    TempBuf tmp;
+    if (int rc = temp_alloc(&tmp, (size_t)g.nv * g.nd * batch * sizeof(float), st)) return rc;
+    launch_fbp(g, sino, batch, static_cast<float*>(tmp.p), img, st);
+    DECT_HIP(hipGetLastError());
+    return DECT_OK;
+}
+
+size_t dect_l0_step_workspace_bytes(int32_t n_y, int32_t n_x, int32_t batch, int weighted) {
+    if (n_y < 1 || n_x < 1 || batch < 1) return 0;
+    Carver c{nullptr};
+    c.take<float2>(fft_scratch_bytes(n_y, n_x, batch) / sizeof(float2));
+    if (weighted) {
+        PcgBufs b;
+        carve_pcg(c, n_y, n_x, batch, &b);
+    }
+    return c.off;
+}
+
+int dect_l0_step(const float* g_tilde, const float* weight, float* g, float* h_out, float* v_out,
+                 int32_t n_y, int32_t n_x, int32_t batch, double lambda, double beta, double tol,
+                 int32_t max_iter, void* ws, size_t ws_bytes, hipStream_t st) {
+    if (batch < 0) return fail(DECT_EINVAL, "batch must be >= 0");
+    if (batch == 0) return DECT_OK;
+    if (!g_tilde || !g) return fail(DECT_EINVAL, "dect_l0_step: NULL g_tilde or g");
+    if (!fft_size_ok(n_x) || !fft_size_ok(n_y))
+        return fail(DECT_EINVAL, "dect_l0_step: n_x=%d n_y=%d must be 2^a*3^b (b<=1) in [8, 1024]",
+                    n_x, n_y);
+    if (!(lambda >= 0) || !(beta > 0)) return fail(DECT_EINVAL, "need lambda >= 0 and beta > 0");
+    if (weight && (!(tol > 0) || max_iter < 1)) return fail(DECT_EINVAL, "need tol > 0, max_iter >= 1");
+    const size_t need = dect_l0_step_workspace_bytes(n_y, n_x, batch, weight != nullptr);
+    TempBuf tmp;
+    if (!ws) {
+        if (int rc = temp_alloc(&tmp, need, st)) return rc;
+        ws = tmp.p;
+    } else if (ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255)) {
+        return fail(DECT_EWORKSPACE, "dect_l0_step: workspace needs %zu bytes, 256-aligned", need);
+    }
+    Carver c{static_cast<char*>(ws)};
+    float2* fft = c.take<float2>(fft_scratch_bytes(n_y, n_x, batch) / sizeof(float2));
+    const float thr = (float)(lambda / beta);
+    if (!weight) {
+        FftArgs a;
+        a.src = FFT_SRC_L0;
+        a.in = g_tilde;
+        a.g_cur = g;
+        a.h_out = h_out;
+        a.v_out = v_out;
+        a.beta = (float)beta;
+        a.thr = thr;
+        a.c = 1.0;
+        a.out = g;
+        launch_fft_solve(n_y, n_x, batch, a, fft, st);
+        DECT_HIP(hipGetLastError());
+        return DECT_OK;
+    }
+    PcgBufs b;
+    carve_pcg(c, n_y, n_x, batch, &b);
+    DECT_HIP(hipMemsetAsync(b.counter, 0, sizeof(unsigned) * batch, st));
+    PcgArgs a;
+    a.ny = n_y;
+    a.nx = n_x;
+    a.batch = batch;
+    a.beta = (float)beta;
+    a.thr = thr;
+    a.tol2 = tol * tol;
+    a.jacobi = beta < kJacobiBelow;
+    a.x = g;
+    a.r = b.r;
+    a.z = b.z;
+    a.p0 = b.p0;
+    a.p1 = b.p1;
+    a.q = b.q;
+    a.w2 = b.w2;
+    a.partials = b.partials;
+    a.counter = b.counter;
+    a.st = b.st;
+    launch_pcg_init_plain(a, weight, g_tilde, h_out, v_out, st);
+    int iters = 0;
+    return run_pcg(a, max_iter, fft, nullptr, st, &iters);
+}
+
+// ---- solver ---------------------------------------------------------------
+static size_t solver_layout(const Geom& g, int batch, char* base, dect_solver* s) {
+    Carver c{base};
+    const size_t npix = (size_t)g.nx * g.ny * batch;
+    const size_t nray = (size_t)g.nv * g.nd * batch;
+    RayTable t;
+    void* tab = c.take<char>(ray_table_bytes(g));
+    float2* f = c.take<float2>(npix);
+    float2* B = c.take<float2>(npix);
+    float2* dN = c.take<float2>(padN_elems(g) * batch);
+    float2* dT = c.take<float2>(padT_elems(g) * batch);
+    float2* S = c.take<float2>(nray);
+    float2* zq = c.take<float2>(nray);   // also the FBP filter scratch at init
+    float2* fft = c.take<float2>(npix);
+    float* rho = c.take<float>(npix);
+    float* tt = c.take<float>(npix);
+    double* part_img = c.take<double>((size_t)batch * grad_nblocks(g.ny, g.nx) * 3);
+    double* part_proj = c.take<double>((size_t)batch * proj_nblocks(g));
+    double* alpha = c.take<double>((size_t)batch);
+    unsigned* cnt = c.take<unsigned>((size_t)batch);
+    PcgBufs pb;
+    carve_pcg(c, g.ny, g.nx, batch, &pb);
+    if (s) {
+        carve_table(g, tab, &t);
+        s->tab = t;
+        s->f = f;
+        s->B = B;
+        s->dN = dN;
+        s->dT = dT;
+        s->S = S;
+        s->zq = zq;
+        s->fft = fft;
+        s->rho = rho;
+        s->t = tt;
+        s->muL = pb.r;   // init-time aliases
+        s->muH = pb.z;
+        s->fbpq = reinterpret_cast<float*>(zq);
+        s->part_img = part_img;
+        s->part_proj = part_proj;
+        s->alpha = alpha;
+        s->cnt_proj = cnt;
+        s->pcg = pb;
+    }
+    return c.off;
+}
+
+size_t dect_solve_workspace_bytes(const dect_geometry* gin, const dect_params* p, int32_t batch) {
+    Geom g;
+    if (resolve_geometry(gin, &g) || !p || batch < 1) return 0;
+    return solver_layout(g, batch, nullptr, nullptr);
+}
+
+int dect_solver_create(const dect_geometry* gin, const dect_params* p, int32_t batch, void* ws,
+                       size_t ws_bytes, hipStream_t st, dect_solver** out) {
+    if (!out) return fail(DECT_EINVAL, "out is NULL");
+    *out = nullptr;
+    Geom g;
+    if (int rc = resolve_geometry(gin, &g)) return rc;
+    if (int rc = check_params(p)) return rc;
+    if (batch < 1) return fail(DECT_EINVAL, "batch must be >= 1");
+    if (!fft_size_ok(g.nx) || !fft_size_ok(g.ny))
+        return fail(DECT_EINVAL, "image sizes must be 2^a*3^b (b <= 1) in [8, 1024], got %dx%d", g.nx,
+                    g.ny);
+    dect_solver* s = new dect_solver();
+    s->g = g;
+    s->batch = batch;
+    s->st = st;
+    if (int rc = build_model(*p, &s->M)) {
+        delete s;
+        return rc;
+    }
+    if (int rc = resolve_params(p, g, s->M, &s->rp)) {
+        delete s;
+        return rc;
+    }
+    const size_t need = solver_layout(g, batch, nullptr, nullptr);
+    if (ws) {
+        if (ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255)) {
+            delete s;
+            return fail(DECT_EWORKSPACE, "solver workspace needs %zu bytes, 256-aligned", need);
+        }
+        s->ws = ws;
+        s->owns_ws = false;
+    } else {
+        if (hipMallocAsync(&s->ws, need, st) != hipSuccess) {
+            delete s;
+            return fail(DECT_ENOMEM, "could not allocate %zu bytes of solver workspace", need);
+        }
+        s->owns_ws = true;
+    }
+    solver_layout(g, batch, static_cast<char*>(s->ws), s);
+    // zero borders of the padded direction layouts, counters and scalars once
+    hipError_t e = hipSuccess;
+    e = e != hipSuccess ? e : hipMemsetAsync(s->dN, 0, padN_elems(g) * batch * sizeof(float2), st);
+    e = e != hipSuccess ? e : hipMemsetAsync(s->dT, 0, padT_elems(g) * batch * sizeof(float2), st);
+    e = e != hipSuccess ? e : hipMemsetAsync(s->cnt_proj, 0, sizeof(unsigned) * batch, st);
+    e = e != hipSuccess ? e : hipMemsetAsync(s->pcg.counter, 0, sizeof(unsigned) * batch, st);
+    e = e != hipSuccess ? e : hipMemsetAsync(s->pcg.st, 0, sizeof(PcgState) * batch, st);
+    if (e != hipSuccess) {
+        if (s->owns_ws) (void)hipFreeAsync(s->ws, st);
+        delete s;
+        return fail(DECT_EDEVICE, "hipMemsetAsync failed: %s", hipGetErrorString(e));
+    }
+    launch_build_ray_table(g, s->tab, st);
+    s->k = 0;
+    s->beta = s->rp.beta0;
+    s->last_pcg = 0;
+    *out = s;
+    DECT_HIP(hipGetLastError());
+    return DECT_OK;
+}
+
+int dect_solver_destroy(dect_solver* s) {
+    if (!s) return DECT_OK;
+    if (s->owns_ws) (void)hipFreeAsync(s->ws, s->st);
+    delete s;
+    return DECT_OK;
+}
+
+static void project_residual(dect_solver* s, const float* lo, const float* hi) {
+    launch_pack_f2(s->g, s->f, s->batch, s->dN, s->dT, s->st);
+    ProjArgs a;
+    a.p_lo = lo;
+    a.p_hi = hi;
+    a.res = s->S;
+    a.c00 = (float)s->M.C[0][0];
+    a.c01 = (float)s->M.C[0][1];
+    a.c10 = (float)s->M.C[1][0];
+    a.c11 = (float)s->M.C[1][1];
+    launch_project(s->g, s->tab, s->dN, s->dT, s->batch, PROJ_RESID, a, s->st);
+}
+
+int dect_solver_init(dect_solver* s, const float* lo, const float* hi) {
+    if (!s || !lo || !hi) return fail(DECT_EINVAL, "dect_solver_init: NULL argument");
+    const Geom& g = s->g;
+    launch_fbp(g, lo, s->batch, s->fbpq, s->muL, s->st);
+    launch_fbp(g, hi, s->batch, s->fbpq, s->muH, s->st);
+    launch_init_state(s->M, g.ny, g.nx, s->batch, s->muL, s->muH, (float)s->rp.p.rho_min, s->f,
+                      s->rho, s->t, s->st);
+    project_residual(s, lo, hi);
+    s->k = 0;
+    s->beta = s->rp.beta0;
+    DECT_HIP(hipGetLastError());
+    return DECT_OK;
+}
+
+int dect_solver_set_state(dect_solver* s, const float* lo, const float* hi, const float* f1,
+                          const float* f2, const float* rho, const float* t, int32_t k) {
+    if (!s || !lo || !hi || !f1 || !f2 || !rho || !t || k < 0)
+        return fail(DECT_EINVAL, "dect_solver_set_state: NULL argument or k < 0");
+    const size_t npix = (size_t)s->g.nx * s->g.ny * s->batch;
+    launch_join_f2(s->g.nx * s->g.ny, s->batch, f1, f2, s->f, s->st);
+    DECT_HIP(hipMemcpyAsync(s->rho, rho, npix * sizeof(float), hipMemcpyDeviceToDevice, s->st));
+    DECT_HIP(hipMemcpyAsync(s->t, t, npix * sizeof(float), hipMemcpyDeviceToDevice, s->st));
+    project_residual(s, lo, hi);
+    s->k = k;
+    s->beta = s->rp.beta0;
+    for (int i = 0; i < k; ++i) s->beta *= s->rp.kappa;
+    DECT_HIP(hipGetLastError());
+    return DECT_OK;
+}
+
+static int one_iteration(dect_solver* s) {
+    const Geom& g = s->g;
+    const Resolved& R = s->rp;
+    const double beta = s->beta;
+    ImgArgs a;
+    a.ny = g.ny;
+    a.nx = g.nx;
+    a.nv = g.nv;
+    a.nd = g.nd;
+    a.batch = s->batch;
+    a.eta2 = (float)(2.0 * R.eta);
+    a.xi2 = (float)(2.0 * R.xi);
+    a.beta2 = (float)(2.0 * beta);
+    a.thr = (float)(R.p.lambda / beta);
+    a.beta = (float)beta;
+    // f-step: A^T of the combined residuals, gradient, A of the direction
+    launch_backproject(g, s->tab, s->S, s->batch, s->B, nullptr, 0, s->st);
+    launch_grad(s->M, a, s->f, s->B, s->rho, s->t, s->dN, s->dT, s->part_img, s->st);
+    ProjArgs pa;
+    pa.res = s->zq;
+    pa.c00 = (float)s->M.C[0][0];
+    pa.c01 = (float)s->M.C[0][1];
+    pa.c10 = (float)s->M.C[1][0];
+    pa.c11 = (float)s->M.C[1][1];
+    pa.partials = s->part_proj;
+    pa.img_partials = s->part_img;
+    pa.img_nblocks = grad_nblocks(g.ny, g.nx);
+    pa.w_data = 2.0 * R.eta;
+    pa.w_coup = 2.0 * R.xi;
+    pa.w_reg = 2.0 * beta;
+    pa.alpha = s->alpha;
+    pa.counter = s->cnt_proj;
+    launch_project(g, s->tab, s->dN, s->dT, s->batch, PROJ_LINESEARCH, pa, s->st);
+    // rho_e step (reads f^(k), rho^(k))
+    FftArgs fa;
+    fa.src = FFT_SRC_RHO;
+    fa.f = s->f;
+    fa.rho = s->rho;
+    fa.m00 = s->M.Ms[0][0];
+    fa.m01 = s->M.Ms[0][1];
+    fa.m10 = s->M.Ms[1][0];
+    fa.m11 = s->M.Ms[1][1];
+    fa.e1n = s->M.e1n;
+    fa.e2n = s->M.e2n;
+    fa.inv_crho = 1.0 / s->M.crho;
+    fa.beta = (float)beta;
+    fa.thr = a.thr;
+    fa.c = 1.0;
+    fa.out = s->rho;
+    launch_fft_solve(g.ny, g.nx, s->batch, fa, s->fft, s->st);
+    // t' step (reads f^(k), t'^(k); in place)
+    PcgArgs pc;
+    pc.ny = g.ny;
+    pc.nx = g.nx;
+    pc.batch = s->batch;
+    pc.beta = (float)beta;
+    pc.thr = a.thr;
+    pc.tol2 = R.p.t_tol * R.p.t_tol;
+    pc.jacobi = beta < kJacobiBelow;
+    pc.x = s->t;
+    pc.r = s->pcg.r;
+    pc.z = s->pcg.z;
+    pc.p0 = s->pcg.p0;
+    pc.p1 = s->pcg.p1;
+    pc.q = s->pcg.q;
+    pc.w2 = s->pcg.w2;
+    pc.partials = s->pcg.partials;
+    pc.counter = s->pcg.counter;
+    pc.st = s->pcg.st;
+    launch_pcg_init_model(s->M, pc, s->f, s->st);
+    int iters = 0;
+    if (int rc = run_pcg(pc, R.p.t_maxit, s->fft, nullptr, s->st, &iters)) return rc;
+    s->last_pcg = iters;
+    // f^(k+1), residual sinograms
+    launch_update(a, s->alpha, s->dN, s->f, s->S, s->zq, s->st);
+    s->beta *= R.kappa;
+    s->k += 1;
+    DECT_HIP(hipGetLastError());
+    return DECT_OK;
+}
+
+int dect_solver_iterate(dect_solver* s, int32_t n) {
+    if (!s || n < 0) return fail(DECT_EINVAL, "dect_solver_iterate: bad arguments");
+    for (int i = 0; i < n; ++i)
+        if (int rc = one_iteration(s)) return rc;
+    return DECT_OK;
+}
+
+int dect_solver_get_state(const dect_solver* s, float* f1, float* f2, float* rho, float* t) {
+    if (!s) return fail(DECT_EINVAL, "solver is NULL");
+    const int npix = s->g.nx * s->g.ny;
+    if (f1 || f2) launch_split_f2(npix, s->batch, s->f, f1, f2, s->st);
+    const size_t bytes = (size_t)npix * s->batch * sizeof(float);
+    if (rho) DECT_HIP(hipMemcpyAsync(rho, s->rho, bytes, hipMemcpyDeviceToDevice, s->st));
+    if (t) DECT_HIP(hipMemcpyAsync(t, s->t, bytes, hipMemcpyDeviceToDevice, s->st));
+    DECT_HIP(hipGetLastError());
+    return DECT_OK;
+}
+
+int dect_solver_finish(dect_solver* s, float* Z, float* rho_e) {
+    if (!s || (!Z && !rho_e)) return fail(DECT_EINVAL, "dect_solver_finish: bad arguments");
+    launch_finish(s->M, s->g.ny, s->g.nx, s->batch, s->rho, s->t, (float)s->rp.p.rho_min,
+                  s->rp.p.t_min, Z, rho_e, s->st);
+    DECT_HIP(hipGetLastError());
+    return DECT_OK;
+}
+
+int dect_solver_stats(const dect_solver* s, int32_t* k, int32_t* last_pcg_iters) {
+    if (!s) return fail(DECT_EINVAL, "solver is NULL");
+    DECT_HIP(hipStreamSynchronize(s->st));
+    if (k) *k = s->k;
+    if (last_pcg_iters) *last_pcg_iters = s->last_pcg;
+    return DECT_OK;
+}
+
+int dect_solve(const float* lo, const float* hi, const dect_geometry* g, const dect_params* p,
+               float* Z, float* rho, int32_t batch, void* ws, size_t ws_bytes, hipStream_t st) {
+    if (!lo || !hi || (!Z && !rho)) return fail(DECT_EINVAL, "dect_solve: NULL array");
+    dect_solver* s = nullptr;
+    if (int rc = dect_solver_create(g, p, batch, ws, ws_bytes, st, &s)) return rc;
+    int rc = dect_solver_init(s, lo, hi);
+    if (!rc) rc = dect_solver_iterate(s, p->n_iter);
+    if (!rc) rc = dect_solver_finish(s, Z, rho);
+    dect_solver_destroy(s);
+    return rc;
+}
+
+const char* dect_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

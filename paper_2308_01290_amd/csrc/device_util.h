@@ -1,0 +1,79 @@
+// Device helpers shared by the library's kernels (wave64 reductions,
+// deterministic block partials, last-block completion).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace dect {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// Sum of `v` over a 1-D block of NT threads, fixed order; result valid in
+// thread 0.  `sh` holds NT/64 doubles of LDS.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x % kWave) == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NT / kWave; ++i) r += sh[i];
+    }
+    __syncthreads();
+    return r;
+}
+
+// Called by every thread of a block after thread 0 stored the block's
+// partials.  Returns true in every thread of the last block to arrive; its
+// loads after this call see all blocks' partials.  The last block resets the
+// counter for the next launch.
+__device__ __forceinline__ bool last_block_arrive(unsigned* counter, unsigned nblocks) {
+    __shared__ int am_last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned prev = atomicAdd(counter, 1u);
+        am_last = (prev == nblocks - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    const bool last = am_last != 0;
+    if (last) {
+        __threadfence();
+        if (threadIdx.x == 0) atomicExch(counter, 0u);
+    }
+    return last;
+}
+
+// Deterministic sum of n doubles at stride `stride` (fixed tree order), done
+// by all threads of a block of NT threads; result valid in thread 0.
+template <int NT>
+__device__ __forceinline__ double block_sum_array(const double* a, int n, int stride, double* sh) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += NT) v += a[(size_t)i * stride];
+    return block_sum<NT>(v, sh);
+}
+
+__device__ __forceinline__ int wrap(int i, int n) {
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+}  // namespace dect

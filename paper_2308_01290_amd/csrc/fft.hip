@@ -1,0 +1,282 @@
+// Periodic solve (c + beta*D^T D) x = rhs by 2-D FFT, the closed form of the
+// g-subproblem in Section II-C (F(1) read as 1) and of the rho_e subproblem:
+// X = F(rhs) / (c + beta*(|F dx|^2 + |F dy|^2)), |F dx|^2 = 4 sin^2(pi kx/nx).
+//
+// Three passes over a complex scratch image:
+//   rows_fwd: build the right-hand side of one row (fused with the hard
+//             threshold of eq. (9) and D^T), FFT along x;
+//   cols:     FFT along y, spectral division, inverse FFT along y;
+//   rows_inv: inverse FFT along x, real part / (nx*ny).
+// Transforms are Stockham autosort (radix 4, 3, 2) in LDS; twiddles come from
+// FP64 sincos rounded to FP32.
+#include "dect_internal.h"
+#include "device_util.h"
+
+namespace dect {
+
+struct FftPlan {
+    int n;
+    int nst;
+    int rad[12];
+};
+
+static bool make_plan(int n, FftPlan* p) {
+    if (n < 8 || n > 1024) return false;
+    int m = n, a = 0, b = 0;
+    while (m % 2 == 0) {
+        m /= 2;
+        ++a;
+    }
+    while (m % 3 == 0) {
+        m /= 3;
+        ++b;
+    }
+    if (m != 1 || b > 1) return false;
+    p->n = n;
+    p->nst = 0;
+    if (b) p->rad[p->nst++] = 3;
+    while (a >= 2) {
+        p->rad[p->nst++] = 4;
+        a -= 2;
+    }
+    if (a) p->rad[p->nst++] = 2;
+    return true;
+}
+
+bool fft_size_ok(int n) {
+    FftPlan p;
+    return make_plan(n, &p);
+}
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// tw[e] = exp(-2 pi i e / n)
+__device__ void fill_twiddles(float2* tw, int n) {
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        double s, c;
+        sincospi(-2.0 * (double)e / (double)n, &s, &c);
+        tw[e] = make_float2((float)c, (float)s);
+    }
+}
+
+// nb interleaved transforms of length P.n: element e of transform t at e*nb + t.
+// INV = false: forward (e^{-i}); true: inverse without 1/n.  Returns the buffer
+// that holds the result.  Ends with a barrier.
+template <bool INV>
+__device__ float2* fft_lds(float2* a, float2* b, const float2* tw, const FftPlan& P, int nb) {
+    int p = 1;
+    const int n = P.n;
+    for (int s = 0; s < P.nst; ++s) {
+        const int r = P.rad[s];
+        const int m = n / r;
+        const int tstep = n / (p * r);
+        for (int idx = threadIdx.x; idx < m * nb; idx += blockDim.x) {
+            const int i = idx / nb, t = idx - (idx / nb) * nb;
+            const int k = i % p;
+            float2 x[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (q < r) x[q] = a[(size_t)(i + q * m) * nb + t];
+#pragma unroll
+            for (int q = 1; q < 4; ++q) {
+                if (q < r) {
+                    float2 w = tw[(q * k * tstep) % n];
+                    if (INV) w.y = -w.y;
+                    x[q] = cmul(x[q], w);
+                }
+            }
+            float2 y[4];
+            if (r == 2) {
+                y[0] = make_float2(x[0].x + x[1].x, x[0].y + x[1].y);
+                y[1] = make_float2(x[0].x - x[1].x, x[0].y - x[1].y);
+            } else if (r == 3) {
+                const float h = 0.86602540378443865f;   // sqrt(3)/2
+                const float2 t1 = make_float2(x[1].x + x[2].x, x[1].y + x[2].y);
+                const float2 t2 = make_float2(x[1].x - x[2].x, x[1].y - x[2].y);
+                y[0] = make_float2(x[0].x + t1.x, x[0].y + t1.y);
+                const float2 m1 = make_float2(x[0].x - 0.5f * t1.x, x[0].y - 0.5f * t1.y);
+                // forward: m2 = -i*h*t2; inverse: +i*h*t2
+                const float2 m2 = INV ? make_float2(-h * t2.y, h * t2.x) : make_float2(h * t2.y, -h * t2.x);
+                y[1] = make_float2(m1.x + m2.x, m1.y + m2.y);
+                y[2] = make_float2(m1.x - m2.x, m1.y - m2.y);
+            } else {
+                const float2 aa = make_float2(x[0].x + x[2].x, x[0].y + x[2].y);
+                const float2 bb = make_float2(x[0].x - x[2].x, x[0].y - x[2].y);
+                const float2 cc = make_float2(x[1].x + x[3].x, x[1].y + x[3].y);
+                const float2 dd = make_float2(x[1].x - x[3].x, x[1].y - x[3].y);
+                // forward: y1 = bb - i dd, y3 = bb + i dd
+                const float2 mid = INV ? make_float2(-dd.y, dd.x) : make_float2(dd.y, -dd.x);
+                y[0] = make_float2(aa.x + cc.x, aa.y + cc.y);
+                y[2] = make_float2(aa.x - cc.x, aa.y - cc.y);
+                y[1] = make_float2(bb.x + mid.x, bb.y + mid.y);
+                y[3] = make_float2(bb.x - mid.x, bb.y - mid.y);
+            }
+            const int jj = (i - k) * r + k;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (q < r) b[(size_t)(jj + q * p) * nb + t] = y[q];
+        }
+        __syncthreads();
+        float2* tmp = a;
+        a = b;
+        b = tmp;
+        p *= r;
+    }
+    return a;
+}
+
+// hard threshold (9) at (row ra, column k) of an image held as rows ra, rb
+// (rb = the next row down): returns kept (dx, dy) or (0, 0).  The decision is
+// taken in FP32 with separately rounded squares.
+__device__ __forceinline__ float2 ht_pair(const float* ra, const float* rb, int k, int nx,
+                                          float thr) {
+    const int k1 = (k + 1 == nx) ? 0 : k + 1;
+    const float dx = ra[k1] - ra[k];
+    const float dy = rb[k] - ra[k];
+    const float s = __fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy));
+    return s > thr ? make_float2(dx, dy) : make_float2(0.f, 0.f);
+}
+
+__global__ __launch_bounds__(256) void k_fft_rows_fwd(FftPlan P, int ny, FftArgs a,
+                                                      float2* __restrict__ scratch) {
+    extern __shared__ float2 sm2[];
+    const int nx = P.n;
+    float2* A = sm2;
+    float2* B = sm2 + nx;
+    float2* tw = sm2 + 2 * nx;
+    float* rows = reinterpret_cast<float*>(sm2 + 3 * nx);   // 3 rows of the HT input
+    const int i = blockIdx.x, z = blockIdx.y;
+    if (a.skip && a.skip[(size_t)z * (sizeof(PcgState) / sizeof(int))]) return;
+    const size_t npix = (size_t)nx * ny;
+    fill_twiddles(tw, nx);
+    if (a.src == FFT_SRC_PLAIN) {
+        for (int k = threadIdx.x; k < nx; k += blockDim.x)
+            A[k] = make_float2(a.in[z * npix + (size_t)i * nx + k], 0.f);
+    } else {
+        const float* src = (a.src == FFT_SRC_RHO) ? a.rho : a.g_cur;
+        const int im = (i == 0) ? ny - 1 : i - 1, ip = (i + 1 == ny) ? 0 : i + 1;
+        for (int k = threadIdx.x; k < nx; k += blockDim.x) {
+            rows[k] = src[z * npix + (size_t)im * nx + k];
+            rows[nx + k] = src[z * npix + (size_t)i * nx + k];
+            rows[2 * nx + k] = src[z * npix + (size_t)ip * nx + k];
+        }
+        __syncthreads();
+        const float* rm = rows;
+        const float* r0 = rows + nx;
+        const float* rp = rows + 2 * nx;
+        for (int k = threadIdx.x; k < nx; k += blockDim.x) {
+            const int km = (k == 0) ? nx - 1 : k - 1;
+            const float2 hc = ht_pair(r0, rp, k, nx, a.thr);    // (h, v) at (i, k)
+            const float2 hl = ht_pair(r0, rp, km, nx, a.thr);   // at (i, k-1)
+            const float2 hu = ht_pair(rm, r0, k, nx, a.thr);    // at (i-1, k)
+            const float dth = (hl.x - hc.x) + (hu.y - hc.y);
+            float base;
+            if (a.src == FFT_SRC_RHO) {
+                const float2 f = a.f[z * npix + (size_t)i * nx + k];
+                const double M1 = a.m00 * (double)f.x + a.m01 * (double)f.y;
+                const double M2 = a.m10 * (double)f.x + a.m11 * (double)f.y;
+                base = (float)((M1 * a.e1n - M2 * a.e2n) * a.inv_crho);
+            } else {
+                base = a.in[z * npix + (size_t)i * nx + k];
+                if (a.h_out) a.h_out[z * npix + (size_t)i * nx + k] = hc.x;
+                if (a.v_out) a.v_out[z * npix + (size_t)i * nx + k] = hc.y;
+            }
+            A[k] = make_float2(base + a.beta * dth, 0.f);
+        }
+    }
+    __syncthreads();
+    const float2* R = fft_lds<false>(A, B, tw, P, 1);
+    for (int k = threadIdx.x; k < nx; k += blockDim.x) scratch[z * npix + (size_t)i * nx + k] = R[k];
+}
+
+__global__ __launch_bounds__(256) void k_fft_cols(FftPlan P, int nx, int cols, FftArgs a,
+                                                  float2* __restrict__ scratch) {
+    extern __shared__ float2 sm2[];
+    const int ny = P.n;
+    float2* A = sm2;
+    float2* B = sm2 + (size_t)ny * cols;
+    float2* tw = sm2 + (size_t)2 * ny * cols;
+    float* lamy = reinterpret_cast<float*>(tw + ny);
+    float* lamx = lamy + ny;
+    const int c0 = blockIdx.x * cols, z = blockIdx.y;
+    if (a.skip && a.skip[(size_t)z * (sizeof(PcgState) / sizeof(int))]) return;
+    const size_t npix = (size_t)nx * ny;
+    fill_twiddles(tw, ny);
+    for (int e = threadIdx.x; e < ny; e += blockDim.x) {
+        const double s = sinpi((double)e / (double)ny);
+        lamy[e] = (float)(4.0 * s * s);
+    }
+    for (int c = threadIdx.x; c < cols; c += blockDim.x) {
+        const double s = sinpi((double)(c0 + c) / (double)nx);
+        lamx[c] = (float)(4.0 * s * s);
+    }
+    for (int idx = threadIdx.x; idx < ny * cols; idx += blockDim.x) {
+        const int e = idx / cols, c = idx - (idx / cols) * cols;
+        A[idx] = (c0 + c < nx) ? scratch[z * npix + (size_t)e * nx + c0 + c] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    float2* R = fft_lds<false>(A, B, tw, P, cols);
+    float2* S = (R == A) ? B : A;
+    const float cz = (float)(a.c_dev ? a.c_dev[(size_t)z * (sizeof(PcgState) / sizeof(double))] : a.c);
+    for (int idx = threadIdx.x; idx < ny * cols; idx += blockDim.x) {
+        const int e = idx / cols, c = idx - (idx / cols) * cols;
+        const float den = cz + a.beta * (lamx[c] + lamy[e]);
+        const float sc = 1.0f / den;
+        R[idx] = make_float2(R[idx].x * sc, R[idx].y * sc);
+    }
+    __syncthreads();
+    const float2* O = fft_lds<true>(R, S, tw, P, cols);
+    for (int idx = threadIdx.x; idx < ny * cols; idx += blockDim.x) {
+        const int e = idx / cols, c = idx - (idx / cols) * cols;
+        if (c0 + c < nx) scratch[z * npix + (size_t)e * nx + c0 + c] = O[idx];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fft_rows_inv(FftPlan P, int ny, FftArgs a,
+                                                      const float2* __restrict__ scratch) {
+    extern __shared__ float2 sm2[];
+    const int nx = P.n;
+    float2* A = sm2;
+    float2* B = sm2 + nx;
+    float2* tw = sm2 + 2 * nx;
+    const int i = blockIdx.x, z = blockIdx.y;
+    if (a.skip && a.skip[(size_t)z * (sizeof(PcgState) / sizeof(int))]) return;
+    const size_t npix = (size_t)nx * ny;
+    fill_twiddles(tw, nx);
+    for (int k = threadIdx.x; k < nx; k += blockDim.x) A[k] = scratch[z * npix + (size_t)i * nx + k];
+    __syncthreads();
+    const float2* R = fft_lds<true>(A, B, tw, P, 1);
+    const float sc = (float)(1.0 / ((double)nx * (double)ny));
+    for (int k = threadIdx.x; k < nx; k += blockDim.x) a.out[z * npix + (size_t)i * nx + k] = R[k].x * sc;
+}
+
+size_t fft_scratch_bytes(int ny, int nx, int batch) {
+    return (size_t)batch * ny * nx * sizeof(float2);
+}
+
+static int cols_for(int ny) {
+    // two ping-pong buffers of ny*cols complex values within 64 KiB of LDS
+    int cols = 8;
+    while (cols > 1 && (size_t)2 * ny * cols * sizeof(float2) + ny * 16 > 64 * 1024) cols /= 2;
+    return cols;
+}
+
+void launch_fft_solve(int ny, int nx, int batch, const FftArgs& a, float2* scratch,
+                      hipStream_t st) {
+    FftPlan px, py;
+    make_plan(nx, &px);
+    make_plan(ny, &py);
+    const size_t lds_row = (size_t)3 * nx * sizeof(float2) + (size_t)3 * nx * sizeof(float);
+    hipLaunchKernelGGL(k_fft_rows_fwd, dim3(ny, batch), dim3(256), lds_row, st, px, ny, a, scratch);
+    const int cols = cols_for(ny);
+    const size_t lds_col = (size_t)2 * ny * cols * sizeof(float2) + ny * sizeof(float2) +
+                           (size_t)ny * sizeof(float) + (size_t)cols * sizeof(float);
+    hipLaunchKernelGGL(k_fft_cols, dim3((nx + cols - 1) / cols, batch), dim3(256), lds_col, st, py, nx,
+                       cols, a, scratch);
+    const size_t lds_inv = (size_t)3 * nx * sizeof(float2);
+    hipLaunchKernelGGL(k_fft_rows_inv, dim3(ny, batch), dim3(256), lds_inv, st, px, ny, a, scratch);
+}
+
+}  // namespace dect

@@ -1,0 +1,408 @@
+// Fan-beam system matrix A on gfx950: ray table, ray-driven forward projector
+// and the matched voxel-driven back-projector.
+//
+// Both operators evaluate the same chord lengths from the same FP32 ray table:
+// a ray advances along its major pixel axis (|slope| <= 1), so inside one
+// major step it crosses at most one minor grid line; the step's chord L is
+// split between minor pixels r0 and r0 +/- 1 in proportion w0 : 1 - w0, where
+// w0 is the fraction of the step spent before the crossing.  This reproduces
+// the exact intersection lengths of the ray with the half-open pixel squares
+// (Siddon 1985) while giving every lane of a wavefront the same trip count.
+// The minor coordinate is a 32.32 fixed-point integer that each step advances
+// by the slope exactly, so crossings are placed to 2^-32 pixel however flat
+// the ray; projector and back-projector derive identical weights from it.
+#include <climits>
+
+#include "dect_internal.h"
+#include "device_util.h"
+
+namespace dect {
+
+size_t ray_table_bytes(const Geom& g) {
+    const size_t nr = (size_t)g.nv * g.nd;
+    return nr * (sizeof(int4) + sizeof(float2) + sizeof(int2)) + (size_t)g.nv * sizeof(float4);
+}
+
+__device__ __forceinline__ long long fix_a0(int4 f) {
+    return (long long)(((unsigned long long)(unsigned)f.y << 32) | (unsigned)f.x);
+}
+__device__ __forceinline__ long long fix_s(int4 f) {
+    return (long long)(((unsigned long long)(unsigned)f.w << 32) | (unsigned)f.z);
+}
+// Fraction of the major step [y, y + s] spent in pixel floor(y): (1 - frac)/s
+// when s >= 0, frac/|s| when s < 0, capped at 1.  lo = fractional bits of y.
+__device__ __forceinline__ float first_weight(unsigned lo, bool up, float ainv) {
+    const float fdown = (float)lo * 0x1p-32f;
+    const float fup = lo ? (float)(0u - lo) * 0x1p-32f : 1.0f;
+    return fminf((up ? fup : fdown) * ainv, 1.0f);
+}
+
+// ---------------------------------------------------------------------------
+// ray table (FP64 geometry, FP32 storage)
+// ---------------------------------------------------------------------------
+__global__ void k_build_ray_table(Geom g, int4* __restrict__ fix, float2* __restrict__ flt,
+                                  int2* __restrict__ span, float4* __restrict__ view) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y;
+    const double th = g.angle0 + (double)v * (g.arc / (double)g.nv);
+    double sn, cs;
+    sincos(th, &sn, &cs);
+    if (j == 0) {
+        const double h = 0.5 * g.dx;
+        view[v] = make_float4((float)cs, (float)sn, (float)(h * (fabs(cs) + fabs(sn))), 0.f);
+    }
+    if (j >= g.nd) return;
+    const double u = ((double)j - 0.5 * (double)(g.nd - 1)) * g.pitch + g.offset;
+    const double Sx = g.sid * cs, Sy = g.sid * sn;
+    const double Qx = -(g.sdd - g.sid) * cs - u * sn;
+    const double Qy = -(g.sdd - g.sid) * sn + u * cs;
+    const double dxr = Qx - Sx, dyr = Qy - Sy;
+    // source in pixel units from the image corner
+    const double sx = (Sx + 0.5 * g.nx * g.dx) / g.dx;
+    const double sy = (Sy + 0.5 * g.ny * g.dx) / g.dx;
+    const bool xmaj = fabs(dxr) >= fabs(dyr);
+    double slope;
+    int nmaj, nmin;
+    if (xmaj) {
+        slope = dyr / dxr;
+        nmaj = g.nx;
+        nmin = g.ny;
+    } else {
+        slope = dxr / dyr;
+        nmaj = g.ny;
+        nmin = g.nx;
+    }
+    if (fabs(slope) < 0x1p-30) slope = 0.0;   // keeps sign(S) == sign(slope)
+    const double a0 = xmaj ? sy - sx * slope : sx - sy * slope;
+    const double L = g.dx * sqrt(1.0 + slope * slope);
+    int klo, khi;
+    if (slope == 0.0) {
+        if (a0 >= 0.0 && a0 < (double)nmin) {
+            klo = 0;
+            khi = nmaj - 1;
+        } else {
+            klo = 1;
+            khi = 0;
+        }
+    } else {
+        double xa = (0.0 - a0) / slope, xb = ((double)nmin - a0) / slope;
+        if (xa > xb) {
+            const double t = xa;
+            xa = xb;
+            xb = t;
+        }
+        double lo = floor(xa) - 1.0, hi = ceil(xb);
+        lo = fmax(lo, 0.0);
+        hi = fmin(hi, (double)(nmaj - 1));
+        if (lo > hi) {
+            klo = 1;
+            khi = 0;
+        } else {
+            klo = (int)lo;
+            khi = (int)hi;
+        }
+    }
+    const long long A0 = llrint(a0 * 4294967296.0);
+    const long long S = llrint(slope * 4294967296.0);
+    const size_t r = (size_t)v * g.nd + j;
+    fix[r] = make_int4((int)(unsigned)(A0 & 0xffffffffLL), (int)(A0 >> 32),
+                       (int)(unsigned)(S & 0xffffffffLL), (int)(S >> 32));
+    flt[r] = make_float2(slope == 0.0 ? __builtin_inff() : (float)fabs(1.0 / slope),
+                         xmaj ? (float)L : -(float)L);
+    span[r] = make_int2(klo, khi);
+}
+
+void launch_build_ray_table(const Geom& g, RayTable t, hipStream_t st) {
+    dim3 grid((g.nd + 255) / 256, g.nv);
+    hipLaunchKernelGGL(k_build_ray_table, grid, dim3(256), 0, st, g, t.fix, t.flt, t.span, t.view);
+}
+
+// ---------------------------------------------------------------------------
+// packing into the padded pair layouts
+// ---------------------------------------------------------------------------
+template <typename SRC>
+__global__ __launch_bounds__(256) void k_pack(const SRC* __restrict__ src, int nsrc, int nx, int ny,
+                                              float2* __restrict__ padN, float2* __restrict__ padT) {
+    __shared__ float2 tile[32][33];
+    const int z = blockIdx.z;
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    const size_t npix = (size_t)nx * ny;
+    float2* pn = padN + (size_t)z * ny * (nx + 2);
+    float2* pt = padT + (size_t)z * nx * (ny + 2);
+    for (int r = ty; r < 32; r += 8) {
+        const int i = by + r, k = bx + tx;
+        float2 val = make_float2(0.f, 0.f);
+        if (i < ny && k < nx) {
+            if constexpr (sizeof(SRC) == sizeof(float2)) {
+                val = reinterpret_cast<const float2*>(src)[(size_t)z * npix + (size_t)i * nx + k];
+            } else {
+                const float* s = reinterpret_cast<const float*>(src);
+                val.x = s[(size_t)(2 * z) * npix + (size_t)i * nx + k];
+                if (2 * z + 1 < nsrc) val.y = s[(size_t)(2 * z + 1) * npix + (size_t)i * nx + k];
+            }
+            pn[(size_t)i * (nx + 2) + k + 1] = val;
+        }
+        tile[r][tx] = val;
+        if (i < ny && tx == 0) {
+            if (blockIdx.x == 0) pn[(size_t)i * (nx + 2)] = make_float2(0.f, 0.f);
+            if (blockIdx.x == gridDim.x - 1) pn[(size_t)i * (nx + 2) + nx + 1] = make_float2(0.f, 0.f);
+        }
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int k = bx + r, i = by + tx;
+        if (k < nx && i < ny) pt[(size_t)k * (ny + 2) + i + 1] = tile[tx][r];
+        if (k < nx && tx == 0) {
+            if (blockIdx.y == 0) pt[(size_t)k * (ny + 2)] = make_float2(0.f, 0.f);
+            if (blockIdx.y == gridDim.y - 1) pt[(size_t)k * (ny + 2) + ny + 1] = make_float2(0.f, 0.f);
+        }
+    }
+}
+
+void launch_pack_pairs(const Geom& g, const float* img, int nimg, float2* padN, float2* padT,
+                       hipStream_t st) {
+    dim3 grid((g.nx + 31) / 32, (g.ny + 31) / 32, (nimg + 1) / 2);
+    hipLaunchKernelGGL(k_pack<float>, grid, dim3(256), 0, st, img, nimg, g.nx, g.ny, padN, padT);
+}
+
+void launch_pack_f2(const Geom& g, const float2* src, int npairs, float2* padN, float2* padT,
+                    hipStream_t st) {
+    dim3 grid((g.nx + 31) / 32, (g.ny + 31) / 32, npairs);
+    hipLaunchKernelGGL(k_pack<float2>, grid, dim3(256), 0, st, src, 2 * npairs, g.nx, g.ny, padN,
+                       padT);
+}
+
+__global__ void k_pair_sinos(const float* __restrict__ s, int nsino, size_t nray,
+                             float2* __restrict__ out) {
+    const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int z = blockIdx.y;
+    if (r >= nray) return;
+    float2 v;
+    v.x = s[(size_t)(2 * z) * nray + r];
+    v.y = (2 * z + 1 < nsino) ? s[(size_t)(2 * z + 1) * nray + r] : 0.f;
+    out[(size_t)z * nray + r] = v;
+}
+
+void launch_pair_sinos(const Geom& g, const float* sino, int nsino, float2* out, hipStream_t st) {
+    const size_t nray = (size_t)g.nv * g.nd;
+    dim3 grid((unsigned)((nray + 255) / 256), (nsino + 1) / 2);
+    hipLaunchKernelGGL(k_pair_sinos, grid, dim3(256), 0, st, sino, nsino, nray, out);
+}
+
+// ---------------------------------------------------------------------------
+// forward projector: one lane per ray, 256 adjacent bins of one view per block
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
+    const float y = x - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+int proj_nblocks(const Geom& g) { return ((g.nd + 255) / 256) * g.nv; }
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_project(const float2* __restrict__ padN,
+                                                 const float2* __restrict__ padT,
+                                                 const int4* __restrict__ fix,
+                                                 const float2* __restrict__ flt,
+                                                 const int2* __restrict__ span, int nx, int ny,
+                                                 int nv, int nd, ProjArgs a) {
+    const int v = blockIdx.y, z = blockIdx.z;
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    const bool valid = j < nd;
+    const size_t r = (size_t)v * nd + j;
+    const int4 fx = valid ? fix[r] : make_int4(0, 0, 0, 0);
+    const float2 fl = valid ? flt[r] : make_float2(__builtin_inff(), 1.f);
+    const int2 sp = valid ? span[r] : make_int2(1, 0);
+    const bool xmaj = fl.y > 0.f;
+    const float L = fabsf(fl.y);
+    const float ainv = fl.x;
+    const long long S = fix_s(fx);
+    const bool up = S >= 0;
+    const int nmin = xmaj ? ny : nx;
+    const int nmaj = xmaj ? nx : ny;
+    const int stride = nmin + 2;
+    const float2* base = xmaj ? padT + (size_t)z * nx * (ny + 2) : padN + (size_t)z * ny * (nx + 2);
+    base += 1;
+    const int rlo = up ? -1 : 0, rhi = up ? nmin - 1 : nmin;
+    const int step = up ? 1 : -1;
+    // weight of the first pixel when the step lies wholly above / below the image
+    const float w_above = up ? 0.f : 1.f, w_below = up ? 1.f : 0.f;
+    int klo = sp.x, khi = sp.y;
+    if (klo > khi) {
+        klo = INT_MAX;
+        khi = INT_MIN;
+    }
+    const int ks = wave_min(klo), ke = wave_max(khi);
+    long long y = fix_a0(fx) + (long long)(ks == INT_MAX ? 0 : ks) * S;
+    float s1 = 0.f, c1 = 0.f, s2 = 0.f, c2 = 0.f;
+    for (int k = ks; k <= ke; ++k, y += S) {
+        const int kk = min(k, nmaj - 1);
+        const int hi = (int)(y >> 32);
+        int r0;
+        float w0;
+        if (hi > rhi) {
+            r0 = rhi;
+            w0 = w_above;
+        } else if (hi < rlo) {
+            r0 = rlo;
+            w0 = w_below;
+        } else {
+            r0 = hi;
+            w0 = first_weight((unsigned)y, up, ainv);
+        }
+        const float2* row = base + (size_t)kk * stride;
+        const float2 gA = row[r0];
+        const float2 gB = row[r0 + step];
+        const float v1 = fmaf(w0, gA.x - gB.x, gB.x);
+        const float v2 = fmaf(w0, gA.y - gB.y, gB.y);
+        if (k >= klo && k <= khi) {
+            kahan_add(s1, c1, v1);
+            kahan_add(s2, c2, v2);
+        }
+    }
+    const double Y1 = (double)L * ((double)s1 - (double)c1);
+    const double Y2 = (double)L * ((double)s2 - (double)c2);
+    const size_t nray = (size_t)nv * nd;
+    if constexpr (MODE == PROJ_PLAIN) {
+        if (valid) {
+            a.out[(size_t)(2 * z) * nray + r] = (float)Y1;
+            if (2 * z + 1 < a.nout) a.out[(size_t)(2 * z + 1) * nray + r] = (float)Y2;
+        }
+    } else if constexpr (MODE == PROJ_RESID) {
+        if (valid) {
+            const double rl = (double)a.c00 * Y1 + (double)a.c01 * Y2 - (double)a.p_lo[(size_t)z * nray + r];
+            const double rh = (double)a.c10 * Y1 + (double)a.c11 * Y2 - (double)a.p_hi[(size_t)z * nray + r];
+            a.res[(size_t)z * nray + r] = make_float2((float)((double)a.c00 * rl + (double)a.c10 * rh),
+                                                      (float)((double)a.c01 * rl + (double)a.c11 * rh));
+        }
+    } else {   // PROJ_LINESEARCH
+        __shared__ double sh[4];
+        double part = 0.0;
+        if (valid) {
+            const double yl = (double)a.c00 * Y1 + (double)a.c01 * Y2;
+            const double yh = (double)a.c10 * Y1 + (double)a.c11 * Y2;
+            a.res[(size_t)z * nray + r] = make_float2((float)((double)a.c00 * yl + (double)a.c10 * yh),
+                                                      (float)((double)a.c01 * yl + (double)a.c11 * yh));
+            part = yl * yl + yh * yh;
+        }
+        const int nblk = gridDim.x * gridDim.y;
+        const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+        const double bs = block_sum<256>(part, sh);
+        if (threadIdx.x == 0) a.partials[(size_t)z * nblk + bid] = bs;
+        if (last_block_arrive(a.counter + z, (unsigned)nblk)) {
+            const double den_data = block_sum_array<256>(a.partials + (size_t)z * nblk, nblk, 1, sh);
+            const double* ip = a.img_partials + (size_t)z * a.img_nblocks * 3;
+            const double num = block_sum_array<256>(ip + 0, a.img_nblocks, 3, sh);
+            const double coup = block_sum_array<256>(ip + 1, a.img_nblocks, 3, sh);
+            const double reg = block_sum_array<256>(ip + 2, a.img_nblocks, 3, sh);
+            if (threadIdx.x == 0) {
+                const double den = a.w_data * den_data + a.w_coup * coup + a.w_reg * reg;
+                a.alpha[z] = den > 0.0 ? num / den : 0.0;
+            }
+        }
+    }
+}
+
+void launch_project(const Geom& g, const RayTable& t, const float2* padN, const float2* padT,
+                    int npairs, int mode, const ProjArgs& a, hipStream_t st) {
+    dim3 grid((g.nd + 255) / 256, g.nv, npairs);
+    if (mode == PROJ_PLAIN)
+        hipLaunchKernelGGL(k_project<PROJ_PLAIN>, grid, dim3(256), 0, st, padN, padT, t.fix, t.flt,
+                           t.span, g.nx, g.ny, g.nv, g.nd, a);
+    else if (mode == PROJ_RESID)
+        hipLaunchKernelGGL(k_project<PROJ_RESID>, grid, dim3(256), 0, st, padN, padT, t.fix, t.flt,
+                           t.span, g.nx, g.ny, g.nv, g.nd, a);
+    else
+        hipLaunchKernelGGL(k_project<PROJ_LINESEARCH>, grid, dim3(256), 0, st, padN, padT, t.fix,
+                           t.flt, t.span, g.nx, g.ny, g.nv, g.nd, a);
+}
+
+// ---------------------------------------------------------------------------
+// back-projector: one lane per pixel, 16 x 16 pixels per block (four 8 x 8
+// wavefronts), all views; per view the pixel's detector footprint bounds the
+// bins whose chords are evaluated with the projector's own formula.
+// ---------------------------------------------------------------------------
+constexpr int kViewChunk = 512;
+
+__global__ __launch_bounds__(256) void k_backproject(const float2* __restrict__ sino,
+                                                     const int4* __restrict__ fix,
+                                                     const float2* __restrict__ flt,
+                                                     const float4* __restrict__ view, int nx, int ny,
+                                                     int nv, int nd, float sid, float sdd, float dxmm,
+                                                     float u0, float inv_pitch,
+                                                     float2* __restrict__ out_pairs,
+                                                     float* __restrict__ out_split, int nout) {
+    __shared__ float4 vs[kViewChunk];
+    const int z = blockIdx.z;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int ty = (w >> 1) * 8 + (lane >> 3), tx = (w & 1) * 8 + (lane & 7);
+    const int i = blockIdx.y * 16 + ty, k = blockIdx.x * 16 + tx;
+    const bool inside = i < ny && k < nx;
+    const float x = ((float)k - 0.5f * (float)(nx - 1)) * dxmm;
+    const float y = ((float)i - 0.5f * (float)(ny - 1)) * dxmm;
+    const float2* sz = sino + (size_t)z * nv * nd;
+    float acc1 = 0.f, acc2 = 0.f;
+    for (int v0 = 0; v0 < nv; v0 += kViewChunk) {
+        const int nvc = min(kViewChunk, nv - v0);
+        __syncthreads();
+        for (int q = threadIdx.x; q < nvc; q += 256) vs[q] = view[v0 + q];
+        __syncthreads();
+        if (!inside) continue;
+        for (int vv = 0; vv < nvc; ++vv) {
+            const float4 vc = vs[vv];
+            const float U = sid - (x * vc.x + y * vc.y);
+            const float W = y * vc.x - x * vc.y;
+            const float rm = __builtin_amdgcn_rcpf(U - vc.z);
+            const float rp = __builtin_amdgcn_rcpf(U + vc.z);
+            const float hi = W + vc.z, lo = W - vc.z;
+            const float umax = sdd * hi * (hi >= 0.f ? rm : rp);
+            const float umin = sdd * lo * (lo >= 0.f ? rp : rm);
+            const int jl = max((int)ceilf((umin - u0) * inv_pitch - 1e-3f), 0);
+            const int jh = min((int)floorf((umax - u0) * inv_pitch + 1e-3f), nd - 1);
+            const int v = v0 + vv;
+            const int4* fv = fix + (size_t)v * nd;
+            const float2* lv = flt + (size_t)v * nd;
+            const float2* sv = sz + (size_t)v * nd;
+            for (int j = jl; j <= jh; ++j) {
+                const int4 fx = fv[j];
+                const float2 fl = lv[j];
+                const bool xm = fl.y > 0.f;
+                const int maj = xm ? k : i, mnr = xm ? i : k;
+                const long long S = fix_s(fx);
+                const bool up = S >= 0;
+                const long long yq = fix_a0(fx) + (long long)maj * S;
+                const int r0 = (int)(yq >> 32);
+                const float w0 = first_weight((unsigned)yq, up, fl.x);
+                const int partner = up ? r0 + 1 : r0 - 1;
+                float ch = (mnr == r0) ? w0 : ((mnr == partner) ? 1.f - w0 : 0.f);
+                ch *= fabsf(fl.y);
+                const float2 sval = sv[j];
+                acc1 = fmaf(ch, sval.x, acc1);
+                acc2 = fmaf(ch, sval.y, acc2);
+            }
+        }
+    }
+    if (!inside) return;
+    const size_t npix = (size_t)nx * ny;
+    const size_t p = (size_t)i * nx + k;
+    if (out_pairs) {
+        out_pairs[(size_t)z * npix + p] = make_float2(acc1, acc2);
+    } else {
+        out_split[(size_t)(2 * z) * npix + p] = acc1;
+        if (2 * z + 1 < nout) out_split[(size_t)(2 * z + 1) * npix + p] = acc2;
+    }
+}
+
+void launch_backproject(const Geom& g, const RayTable& t, const float2* sino, int npairs,
+                        float2* out_pairs, float* out_split, int nout, hipStream_t st) {
+    dim3 grid((g.nx + 15) / 16, (g.ny + 15) / 16, npairs);
+    const float u0 = (float)(-0.5 * (g.nd - 1) * g.pitch + g.offset);
+    hipLaunchKernelGGL(k_backproject, grid, dim3(256), 0, st, sino, t.fix, t.flt, t.view, g.nx, g.ny, g.nv,
+                       g.nd, (float)g.sid, (float)g.sdd, (float)g.dx, u0, (float)(1.0 / g.pitch),
+                       out_pairs, out_split, nout);
+}
+
+}  // namespace dect

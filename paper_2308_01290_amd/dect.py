@@ -1,0 +1,351 @@
+"""Thin ctypes binding of libdect.so (C-ABI in include/dect.h).
+
+Only argument marshalling lives here: torch CUDA tensors provide device
+memory and the current HIP stream; every step of the computation runs in the
+library's HIP kernels.  Importing this module fails loudly when the library
+is not built; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from dataclasses import dataclass, field, fields
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdect.so")
+
+DECT_OK = 0
+
+
+class DectError(RuntimeError):
+    pass
+
+
+class _Geometry(C.Structure):
+    _fields_ = [("n_x", C.c_int32), ("n_y", C.c_int32), ("pixel_mm", C.c_double),
+                ("n_views", C.c_int32), ("angle0_rad", C.c_double), ("arc_rad", C.c_double),
+                ("n_det", C.c_int32), ("det_pitch_mm", C.c_double), ("det_offset_mm", C.c_double),
+                ("sid_mm", C.c_double), ("sdd_mm", C.c_double)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("E_lo_keV", C.c_double), ("E_hi_keV", C.c_double), ("E1_keV", C.c_double),
+                ("E2_keV", C.c_double), ("m", C.c_double), ("n", C.c_double), ("Cp", C.c_double),
+                ("Z_w", C.c_double), ("basis_Z", C.c_double * 2), ("basis_rho", C.c_double * 2),
+                ("lambda_", C.c_double), ("beta0", C.c_double), ("beta_max", C.c_double),
+                ("kappa", C.c_double), ("eta", C.c_double), ("xi", C.c_double),
+                ("n_iter", C.c_int32), ("f_inner", C.c_int32), ("t_tol", C.c_double),
+                ("t_maxit", C.c_int32), ("rho_min", C.c_double), ("t_min", C.c_double)]
+
+
+EXPORTS = [
+    "dect_default_params", "dect_resolve_geometry", "dect_attenuation", "dect_project",
+    "dect_backproject", "dect_fbp", "dect_l0_step_workspace_bytes", "dect_l0_step",
+    "dect_solve_workspace_bytes", "dect_solver_create", "dect_solver_destroy", "dect_solver_init",
+    "dect_solver_set_state", "dect_solver_iterate", "dect_solver_get_state", "dect_solver_finish",
+    "dect_solver_stats", "dect_solve", "dect_last_error",
+]
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"libdect.so is not built ({path}); run __graft_entry__.build() "
+                          "or python paper_2308_01290_amd/build.py")
+    L = C.CDLL(path)
+    P, vp = C.POINTER, C.c_void_p
+    G, Pp = P(_Geometry), P(_Params)
+    L.dect_default_params.argtypes = [Pp]
+    L.dect_default_params.restype = None
+    L.dect_resolve_geometry.argtypes = [G]
+    L.dect_attenuation.argtypes = [Pp, P(C.c_double), P(C.c_double), C.c_int64, P(C.c_double), P(C.c_double)]
+    for name in ("dect_project", "dect_backproject", "dect_fbp"):
+        getattr(L, name).argtypes = [G, vp, vp, C.c_int32, vp]
+    L.dect_l0_step_workspace_bytes.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int]
+    L.dect_l0_step_workspace_bytes.restype = C.c_size_t
+    L.dect_l0_step.argtypes = [vp, vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_double,
+                               C.c_double, C.c_double, C.c_int32, vp, C.c_size_t, vp]
+    L.dect_solve_workspace_bytes.argtypes = [G, Pp, C.c_int32]
+    L.dect_solve_workspace_bytes.restype = C.c_size_t
+    L.dect_solver_create.argtypes = [G, Pp, C.c_int32, vp, C.c_size_t, vp, P(vp)]
+    L.dect_solver_destroy.argtypes = [vp]
+    L.dect_solver_init.argtypes = [vp, vp, vp]
+    L.dect_solver_set_state.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.c_int32]
+    L.dect_solver_iterate.argtypes = [vp, C.c_int32]
+    L.dect_solver_get_state.argtypes = [vp, vp, vp, vp, vp]
+    L.dect_solver_finish.argtypes = [vp, vp, vp]
+    L.dect_solver_stats.argtypes = [vp, P(C.c_int32), P(C.c_int32)]
+    L.dect_solve.argtypes = [vp, vp, G, Pp, vp, vp, C.c_int32, vp, C.c_size_t, vp]
+    L.dect_last_error.argtypes = []
+    L.dect_last_error.restype = C.c_char_p
+    return L
+
+
+_lib: Optional[C.CDLL] = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is None:
+        _lib = load_library()
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != DECT_OK:
+        msg = lib().dect_last_error().decode(errors="replace")
+        raise DectError(f"{what} failed ({rc}): {msg}")
+
+
+# ---------------------------------------------------------------------------
+# configuration objects
+# ---------------------------------------------------------------------------
+@dataclass
+class Geometry:
+    n_x: int
+    n_y: int
+    pixel_mm: float
+    n_views: int
+    n_det: int
+    sid_mm: float
+    sdd_mm: float
+    det_pitch_mm: float = 0.0
+    det_offset_mm: float = 0.0
+    angle0_rad: float = 0.0
+    arc_rad: float = 2.0 * math.pi
+
+    @staticmethod
+    def of(obj) -> "Geometry":
+        return Geometry(**{f.name: getattr(obj, f.name) for f in fields(Geometry)})
+
+    def c(self) -> _Geometry:
+        return _Geometry(self.n_x, self.n_y, self.pixel_mm, self.n_views, self.angle0_rad,
+                         self.arc_rad, self.n_det, self.det_pitch_mm, self.det_offset_mm,
+                         self.sid_mm, self.sdd_mm)
+
+
+_PARAM_NAMES = [f[0] for f in _Params._fields_]
+
+
+def default_params(**overrides) -> _Params:
+    p = _Params()
+    lib().dect_default_params(C.byref(p))
+    for k, v in overrides.items():
+        key = "lambda_" if k in ("lambda", "lam") else k
+        if key not in _PARAM_NAMES:
+            raise KeyError(k)
+        if key in ("basis_Z", "basis_rho"):
+            getattr(p, key)[0], getattr(p, key)[1] = v
+        else:
+            setattr(p, key, v)
+    return p
+
+
+def resolve_geometry(geom) -> Geometry:
+    g = Geometry.of(geom).c()
+    _check(lib().dect_resolve_geometry(C.byref(g)), "dect_resolve_geometry")
+    return Geometry(g.n_x, g.n_y, g.pixel_mm, g.n_views, g.n_det, g.sid_mm, g.sdd_mm,
+                    g.det_pitch_mm, g.det_offset_mm, g.angle0_rad, g.arc_rad)
+
+
+def attenuation(params: _Params, Z, rho_e):
+    """Host FP64 model: (mu_lo, mu_hi) in 1/mm for arrays of (Z, rho_e)."""
+    import numpy as np
+    Z = np.ascontiguousarray(Z, dtype=np.float64)
+    R = np.ascontiguousarray(rho_e, dtype=np.float64)
+    shape = np.broadcast(Z, R).shape
+    Z = np.ascontiguousarray(np.broadcast_to(Z, shape))
+    R = np.ascontiguousarray(np.broadcast_to(R, shape))
+    lo = np.empty(shape)
+    hi = np.empty(shape)
+    dp = C.POINTER(C.c_double)
+    _check(lib().dect_attenuation(C.byref(params), Z.ctypes.data_as(dp), R.ctypes.data_as(dp),
+                                  Z.size, lo.ctypes.data_as(dp), hi.ctypes.data_as(dp)),
+           "dect_attenuation")
+    return lo, hi
+
+
+# ---------------------------------------------------------------------------
+# tensor helpers
+# ---------------------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dev_f32(t, shape_tail, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape[-len(shape_tail):]) != tuple(shape_tail):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected [..., {shape_tail}]")
+    return t
+
+
+def _batch(t, ndim_tail=2):
+    n = 1
+    for s in t.shape[:-ndim_tail]:
+        n *= int(s)
+    return n
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+# ---------------------------------------------------------------------------
+# operators
+# ---------------------------------------------------------------------------
+def project(geom, img, out=None, stream=None):
+    """sino = A img, img [..., n_y, n_x] -> [..., n_views, n_det] (float32)."""
+    torch = _torch()
+    g = Geometry.of(geom)
+    _dev_f32(img, (g.n_y, g.n_x), "img")
+    if out is None:
+        out = torch.empty(img.shape[:-2] + (g.n_views, g.n_det), device=img.device, dtype=torch.float32)
+    _dev_f32(out, (g.n_views, g.n_det), "out")
+    gc = g.c()
+    _check(lib().dect_project(C.byref(gc), _ptr(img), _ptr(out), _batch(img), C.c_void_p(_stream(stream))),
+           "dect_project")
+    return out
+
+
+def backproject(geom, sino, out=None, stream=None):
+    """img = A^T sino, [..., n_views, n_det] -> [..., n_y, n_x] (float32)."""
+    torch = _torch()
+    g = Geometry.of(geom)
+    _dev_f32(sino, (g.n_views, g.n_det), "sino")
+    if out is None:
+        out = torch.empty(sino.shape[:-2] + (g.n_y, g.n_x), device=sino.device, dtype=torch.float32)
+    _dev_f32(out, (g.n_y, g.n_x), "out")
+    gc = g.c()
+    _check(lib().dect_backproject(C.byref(gc), _ptr(sino), _ptr(out), _batch(sino),
+                                  C.c_void_p(_stream(stream))), "dect_backproject")
+    return out
+
+
+def fbp(geom, sino, out=None, stream=None):
+    """Fan-beam FBP, [..., n_views, n_det] -> attenuation image [..., n_y, n_x]."""
+    torch = _torch()
+    g = Geometry.of(geom)
+    _dev_f32(sino, (g.n_views, g.n_det), "sino")
+    if out is None:
+        out = torch.empty(sino.shape[:-2] + (g.n_y, g.n_x), device=sino.device, dtype=torch.float32)
+    gc = g.c()
+    _check(lib().dect_fbp(C.byref(gc), _ptr(sino), _ptr(out), _batch(sino), C.c_void_p(_stream(stream))),
+           "dect_fbp")
+    return out
+
+
+def l0_step(g_tilde, g, lam, beta, weight=None, tol=1e-6, max_iter=200, return_hv=False,
+            stream=None):
+    """One HQS step of the gradient-L0 model (in place on g); see include/dect.h."""
+    torch = _torch()
+    ny, nx = g.shape[-2:]
+    _dev_f32(g, (ny, nx), "g")
+    _dev_f32(g_tilde, (ny, nx), "g_tilde")
+    if weight is not None:
+        _dev_f32(weight, (ny, nx), "weight")
+    h = v = None
+    if return_hv:
+        h = torch.empty_like(g)
+        v = torch.empty_like(g)
+    _check(lib().dect_l0_step(_ptr(g_tilde), _ptr(weight), _ptr(g), _ptr(h), _ptr(v), ny, nx,
+                               _batch(g), float(lam), float(beta), float(tol), int(max_iter), None, 0,
+                               C.c_void_p(_stream(stream))), "dect_l0_step")
+    return (g, h, v) if return_hv else g
+
+
+class Solver:
+    """A batch of slices with shared geometry and parameters, state on device."""
+
+    def __init__(self, geom, params=None, batch: int = 1, device="cuda", stream=None):
+        self.geom = Geometry.of(geom)
+        self.params = params if params is not None else default_params()
+        self.batch = int(batch)
+        self.device = device
+        self._stream = stream
+        h = C.c_void_p()
+        gc = self.geom.c()
+        _check(lib().dect_solver_create(C.byref(gc), C.byref(self.params), self.batch, None, 0,
+                                        C.c_void_p(_stream(stream)), C.byref(h)), "dect_solver_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dect_solver_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _img(self, n=1):
+        torch = _torch()
+        return torch.empty((self.batch, self.geom.n_y, self.geom.n_x), device=self.device,
+                           dtype=torch.float32)
+
+    def init(self, sino_lo, sino_hi):
+        _dev_f32(sino_lo, (self.geom.n_views, self.geom.n_det), "sino_lo")
+        _dev_f32(sino_hi, (self.geom.n_views, self.geom.n_det), "sino_hi")
+        _check(lib().dect_solver_init(self._h, _ptr(sino_lo), _ptr(sino_hi)), "dect_solver_init")
+        self._keep = (sino_lo, sino_hi)
+        return self
+
+    def set_state(self, sino_lo, sino_hi, f1, f2, rho, t, k=0):
+        for name, a in (("f1", f1), ("f2", f2), ("rho", rho), ("t", t)):
+            _dev_f32(a, (self.geom.n_y, self.geom.n_x), name)
+        _check(lib().dect_solver_set_state(self._h, _ptr(sino_lo), _ptr(sino_hi), _ptr(f1), _ptr(f2),
+                                           _ptr(rho), _ptr(t), int(k)), "dect_solver_set_state")
+        self._keep = (sino_lo, sino_hi, f1, f2, rho, t)
+        return self
+
+    def iterate(self, n: int = 1):
+        _check(lib().dect_solver_iterate(self._h, int(n)), "dect_solver_iterate")
+        return self
+
+    def state(self):
+        f1, f2, rho, t = self._img(), self._img(), self._img(), self._img()
+        _check(lib().dect_solver_get_state(self._h, _ptr(f1), _ptr(f2), _ptr(rho), _ptr(t)),
+               "dect_solver_get_state")
+        return f1, f2, rho, t
+
+    def finish(self):
+        Z, rho = self._img(), self._img()
+        _check(lib().dect_solver_finish(self._h, _ptr(Z), _ptr(rho)), "dect_solver_finish")
+        return Z, rho
+
+    def stats(self):
+        k = C.c_int32()
+        it = C.c_int32()
+        _check(lib().dect_solver_stats(self._h, C.byref(k), C.byref(it)), "dect_solver_stats")
+        return int(k.value), int(it.value)
+
+
+def solve(sino_lo, sino_hi, geom, params=None, stream=None):
+    """Whole solve -> (Z, rho_e), each [batch, n_y, n_x]."""
+    torch = _torch()
+    g = Geometry.of(geom)
+    p = params if params is not None else default_params()
+    _dev_f32(sino_lo, (g.n_views, g.n_det), "sino_lo")
+    _dev_f32(sino_hi, (g.n_views, g.n_det), "sino_hi")
+    b = _batch(sino_lo)
+    Z = torch.empty((b, g.n_y, g.n_x), device=sino_lo.device, dtype=torch.float32)
+    R = torch.empty_like(Z)
+    gc = g.c()
+    _check(lib().dect_solve(_ptr(sino_lo), _ptr(sino_hi), C.byref(gc), C.byref(p), _ptr(Z), _ptr(R), b,
+                            None, 0, C.c_void_p(_stream(stream))), "dect_solve")
+    return Z, R

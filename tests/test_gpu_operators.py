@@ -1,0 +1,125 @@
+"""GPU parity of the fan-beam operators against the FP64 oracle: forward
+projection, matched back-projection, adjointness, FBP.  Inputs are identical
+FP32 arrays on both sides (the oracle promotes them to FP64)."""
+import numpy as np
+import pytest
+
+from oracle import operators as ops
+from paper_2308_01290_amd import dect
+from paper_2308_01290_amd import phantoms as P
+from tests.gpu_util import cuda, host, ragged_geometry, rel_inf, workload
+
+pytestmark = pytest.mark.gpu
+
+# per-projection tolerance: sup-norm error relative to the sup-norm of the
+# oracle's projection
+PROJ_TOL = 1e-5
+
+
+def geoms():
+    return {"small": P.geometry_small(), "ragged": ragged_geometry()}
+
+
+@pytest.mark.parametrize("name", ["small", "ragged"])
+@pytest.mark.parametrize("batch", [1, 3])
+def test_project_matches_oracle_random(name, batch):
+    g = geoms()[name]
+    rng = np.random.default_rng(100 + batch)
+    img = rng.uniform(0.0, 1.0, (batch, g.n_y, g.n_x)).astype(np.float32)
+    got = host(dect.project(g, cuda(img)))
+    ref = ops.project(g, img.astype(np.float64))
+    assert got.shape == ref.shape
+    for b in range(batch):
+        assert rel_inf(got[b], ref[b]) <= PROJ_TOL, (name, b)
+
+
+def test_project_matches_oracle_per_ray_on_phantom():
+    g, ph, _, _ = workload("small")
+    from oracle.physics import Physics
+    muL, _ = P.mu_maps(ph, g, Physics().mu_pair, supersample=2)
+    img = muL.astype(np.float32)
+    got = host(dect.project(g, cuda(img)))
+    ref = ops.project(g, img.astype(np.float64))
+    assert rel_inf(got, ref) <= PROJ_TOL
+    big = ref >= 1e-3 * ref.max()
+    assert np.max(np.abs(got - ref)[big] / ref[big]) <= PROJ_TOL
+
+
+@pytest.mark.parametrize("name", ["small", "ragged"])
+@pytest.mark.parametrize("batch", [1, 2, 3])
+def test_backproject_matches_oracle(name, batch):
+    g = geoms()[name]
+    rng = np.random.default_rng(7 + batch)
+    s = rng.standard_normal((batch, g.n_views, g.n_det)).astype(np.float32)
+    got = host(dect.backproject(g, cuda(s)))
+    ref = ops.backproject(g, s.astype(np.float64))
+    for b in range(batch):
+        assert rel_inf(got[b], ref[b]) <= PROJ_TOL, (name, b)
+
+
+@pytest.mark.parametrize("name", ["small", "ragged"])
+def test_adjointness_on_gpu(name):
+    g = geoms()[name]
+    rng = np.random.default_rng(21)
+    x = rng.standard_normal((g.n_y, g.n_x)).astype(np.float32)
+    y = rng.standard_normal((g.n_views, g.n_det)).astype(np.float32)
+    Ax = host(dect.project(g, cuda(x)))
+    Aty = host(dect.backproject(g, cuda(y)))
+    lhs = float(np.sum(Ax * y.astype(np.float64)))
+    rhs = float(np.sum(x.astype(np.float64) * Aty))
+    assert abs(lhs - rhs) <= 1e-6 * np.linalg.norm(Ax) * np.linalg.norm(y)
+
+
+def test_operators_are_deterministic():
+    g = P.geometry_small()
+    rng = np.random.default_rng(5)
+    x = cuda(rng.uniform(0, 1, (2, g.n_y, g.n_x)))
+    y = cuda(rng.standard_normal((2, g.n_views, g.n_det)))
+    assert np.array_equal(host(dect.project(g, x)), host(dect.project(g, x)))
+    assert np.array_equal(host(dect.backproject(g, y)), host(dect.backproject(g, y)))
+
+
+def test_empty_batch_is_a_no_op():
+    import torch
+    g = P.geometry_small()
+    img = torch.empty((0, g.n_y, g.n_x), device="cuda")
+    out = dect.project(g, img)
+    assert out.shape == (0, g.n_views, g.n_det)
+
+
+@pytest.mark.parametrize("name", ["small", "ragged"])
+def test_fbp_matches_oracle(name):
+    g = geoms()[name]
+    if name == "small":
+        _, _, pL, pH = workload("small")
+        s = np.stack([pL, pH])
+    else:
+        rng = np.random.default_rng(9)
+        s = rng.uniform(0, 2, (2, g.n_views, g.n_det)).astype(np.float32)
+    got = host(dect.fbp(g, cuda(s)))
+    ref = ops.fbp(g, s.astype(np.float64))
+    for b in range(2):
+        assert rel_inf(got[b], ref[b]) <= PROJ_TOL, (name, b)
+
+
+# ---- the 512^2 / 720-view / 736-bin slice, at full size ----------------------
+
+def test_slice512_project_and_backproject():
+    g, ph, pL, _ = workload("slice512")
+    from oracle.physics import Physics
+    muL, muH = P.mu_maps(ph, g, Physics().mu_pair)
+    img = np.stack([muL, muH]).astype(np.float32)
+    got = host(dect.project(g, cuda(img)))
+    ref = ops.project(g, img.astype(np.float64))
+    for b in range(2):
+        assert rel_inf(got[b], ref[b]) <= PROJ_TOL
+    got_bp = host(dect.backproject(g, cuda(pL[None])))
+    ref_bp = ops.backproject(g, pL[None].astype(np.float64))
+    assert rel_inf(got_bp, ref_bp) <= PROJ_TOL
+
+
+def test_slice512_fbp():
+    g, _, pL, _ = workload("slice512")
+    got = host(dect.fbp(g, cuda(pL[None])))
+    ref = ops.fbp(g, pL[None].astype(np.float64))
+    assert rel_inf(got, ref) <= PROJ_TOL
