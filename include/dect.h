@@ -89,7 +89,9 @@ typedef struct dect_geometry {
  *   f_inner              steepest-descent/CG steps on the f-subproblem per
  *                        outer iteration (this build: 1)
  *   t_tol, t_maxit       PCG tolerance (relative residual) and cap of the
- *                        Z^m subproblem (1e-6, 200)
+ *                        Z^m subproblem (1e-7, 200); Z = Zw*t'^(1/m) is
+ *                        ill-conditioned where t' is small, which is what
+ *                        sets this tolerance
  *   rho_min, t_min       output mask: Z = 0 where rho_e < rho_min; t' clamp
  *                        (0.1, 1e-6) */
 typedef struct dect_params {

@@ -225,21 +225,53 @@ static int get_table(const Geom& g, hipStream_t st, RayTable* out) {
     return DECT_OK;
 }
 
-// stream-ordered temporary buffer
-struct TempBuf {
+// Device allocation on a stream: stream-ordered when the runtime supports it
+// for this stream, otherwise a plain hipMalloc (freed with hipFree, which
+// waits for the device).
+struct DevAlloc {
     void* p = nullptr;
     hipStream_t st = nullptr;
-    ~TempBuf() {
-        if (p) (void)hipFreeAsync(p, st);
-    }
+    bool async = false;
 };
-static int temp_alloc(TempBuf* b, size_t bytes, hipStream_t st) {
-    b->st = st;
-    if (hipMallocAsync(&b->p, bytes, st) != hipSuccess) {
-        b->p = nullptr;
-        return fail(DECT_ENOMEM, "could not allocate %zu bytes of scratch", bytes);
+static int dev_alloc(DevAlloc* a, size_t bytes, hipStream_t st) {
+    a->st = st;
+    a->async = false;
+    a->p = nullptr;
+    hipError_t e = hipMallocAsync(&a->p, bytes, st);
+    if (e == hipSuccess) {
+        a->async = true;
+        return DECT_OK;
+    }
+    (void)hipGetLastError();
+    a->p = nullptr;
+    e = hipMalloc(&a->p, bytes);
+    if (e != hipSuccess) {
+        a->p = nullptr;
+        (void)hipGetLastError();
+        return fail(DECT_ENOMEM, "could not allocate %zu bytes on the device: %s", bytes,
+                    hipGetErrorString(e));
     }
     return DECT_OK;
+}
+static void dev_free(DevAlloc* a) {
+    if (!a->p) return;
+    if (a->async)
+        (void)hipFreeAsync(a->p, a->st);
+    else
+        (void)hipFree(a->p);
+    a->p = nullptr;
+}
+
+// scope-bound temporary buffer
+struct TempBuf {
+    DevAlloc a;
+    void* p = nullptr;
+    ~TempBuf() { dev_free(&a); }
+};
+static int temp_alloc(TempBuf* b, size_t bytes, hipStream_t st) {
+    const int rc = dev_alloc(&b->a, bytes, st);
+    b->p = b->a.p;
+    return rc;
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -260,64 +292,69 @@ struct Carver {
 
 struct PcgBufs {
     float *r, *z, *p0, *p1, *q, *w2;
-    double* partials;
-    unsigned* counter;
+    double* parts;
     PcgState* st;
+    PcgParts L;
 };
 
 static void carve_pcg(Carver& c, int ny, int nx, int batch, PcgBufs* b) {
     const size_t n = (size_t)ny * nx * batch;
+    b->L = pcg_parts(ny, nx);
     b->r = c.take<float>(n);
     b->z = c.take<float>(n);
     b->p0 = c.take<float>(n);
     b->p1 = c.take<float>(n);
     b->q = c.take<float>(n);
     b->w2 = c.take<float>(n);
-    b->partials = c.take<double>((size_t)batch * pcg_nblocks(ny, nx) * 4);
-    b->counter = c.take<unsigned>((size_t)batch);
+    b->parts = c.take<double>((size_t)batch * b->L.zstride);
     b->st = c.take<PcgState>((size_t)batch);
+}
+
+static void fill_pcg_args(PcgArgs* a, const PcgBufs& b, int ny, int nx, int batch, float* x) {
+    a->ny = ny;
+    a->nx = nx;
+    a->batch = batch;
+    a->x = x;
+    a->r = b.r;
+    a->z = b.z;
+    a->p0 = b.p0;
+    a->p1 = b.p1;
+    a->q = b.q;
+    a->w2 = b.w2;
+    a->parts = b.parts;
+    a->L = b.L;
+    a->st = b.st;
 }
 
 static const double kJacobiBelow = 1.0;   // beta below which Jacobi beats the FFT preconditioner
 
-// Runs PCG iterations until every slice converged or max_iter; returns the
-// largest iteration count, or a negative status.
-static int run_pcg(PcgArgs& a, int max_iter, float2* fft_scratch, int* host_done_buf,
-                   hipStream_t st, int* iters_out) {
-    FftArgs fa;
-    fa.src = FFT_SRC_PLAIN;
-    fa.in = a.r;
-    fa.out = a.z;
-    fa.beta = a.beta;
-    fa.c_dev = &a.st[0].cshift;
-    fa.skip = &a.st[0].done;
-    if (!a.jacobi) {
-        launch_fft_solve(a.ny, a.nx, a.batch, fa, fft_scratch, st);
-        launch_pcg_after_prec_init(a, st);
-    }
+// Runs PCG iterations (after an init kernel) until every slice converged or
+// max_iter.  The host checks convergence once per chunk of iterations; the
+// first chunk is sized from the previous solve.  Returns the largest count.
+static int run_pcg(PcgArgs& a, int max_iter, int first_chunk, float2* fft_scratch, hipStream_t st,
+                   int* iters_out) {
+    if (!a.jacobi) launch_pcg_fft_prec(a, -1, fft_scratch, st);
     int it = 0;
-    const int chunk = 8;
+    int chunk = std::max(2, first_chunk);
     std::vector<PcgState> hs(a.batch);
     while (true) {
         for (int c = 0; c < chunk && it < max_iter; ++c, ++it) {
-            launch_pcg_matvec(a, it & 1, it == 0, st);
-            launch_pcg_update(a, it & 1, st);
-            if (!a.jacobi) {
-                launch_fft_solve(a.ny, a.nx, a.batch, fa, fft_scratch, st);
-                launch_pcg_after_prec(a, st);
-            }
+            launch_pcg_matvec(a, it, st);
+            launch_pcg_update(a, it, st);
+            if (!a.jacobi) launch_pcg_fft_prec(a, it, fft_scratch, st);
         }
+        launch_pcg_check(a, it, st);
         DECT_HIP(hipGetLastError());
         DECT_HIP(hipMemcpyAsync(hs.data(), a.st, sizeof(PcgState) * a.batch, hipMemcpyDeviceToHost, st));
         DECT_HIP(hipStreamSynchronize(st));
         bool all = true;
         for (int z = 0; z < a.batch; ++z) all = all && hs[z].done;
         if (all || it >= max_iter) break;
+        chunk = 4;
     }
     int mx = 0;
     for (int z = 0; z < a.batch; ++z) mx = std::max(mx, hs[z].iters);
     if (iters_out) *iters_out = mx;
-    (void)host_done_buf;
     return DECT_OK;
 }
 
@@ -336,6 +373,7 @@ struct dect_solver {
     hipStream_t st;
     void* ws;
     bool owns_ws;
+    DevAlloc own;
     RayTable tab;
     float2 *f, *B, *dN, *dT, *S, *zq, *fft;
     float *rho, *t, *muL, *muH, *fbpq;
@@ -372,7 +410,7 @@ void dect_default_params(dect_params* p) {
     p->xi = 0.0;
     p->n_iter = 50;
     p->f_inner = 1;
-    p->t_tol = 1e-6;
+    p->t_tol = 1e-7;
     p->t_maxit = 200;
     p->rho_min = 0.1;
     p->t_min = 1e-6;
@@ -449,7 +487,7 @@ int dect_fbp(const dect_geometry* gin, const float* sino, float* img, int32_t ba
     if (batch < 0) return fail(DECT_EINVAL, "batch must be >= 0");
     if (batch == 0) return DECT_OK;
     if (!img || !sino) return fail(DECT_EINVAL, "dect_fbp: NULL array");
-    if (g.nd > 8192) return fail(DECT_EINVAL, "dect_fbp: n_det > 8192");
+    if (g.nd > 4096) return fail(DECT_EINVAL, "dect_fbp: n_det > 4096");
     TempBuf tmp;
     if (int rc = temp_alloc(&tmp, (size_t)g.nv * g.nd * batch * sizeof(float), st)) return rc;
     launch_fbp(g, sino, batch, static_cast<float*>(tmp.p), img, st);
@@ -494,7 +532,7 @@ int dect_l0_step(const float* g_tilde, const float* weight, float* g, float* h_o
         FftArgs a;
         a.src = FFT_SRC_L0;
         a.in = g_tilde;
-        a.g_cur = g;
+        a.base = g;
         a.h_out = h_out;
         a.v_out = v_out;
         a.beta = (float)beta;
@@ -507,28 +545,15 @@ int dect_l0_step(const float* g_tilde, const float* weight, float* g, float* h_o
     }
     PcgBufs b;
     carve_pcg(c, n_y, n_x, batch, &b);
-    DECT_HIP(hipMemsetAsync(b.counter, 0, sizeof(unsigned) * batch, st));
     PcgArgs a;
-    a.ny = n_y;
-    a.nx = n_x;
-    a.batch = batch;
+    fill_pcg_args(&a, b, n_y, n_x, batch, g);
     a.beta = (float)beta;
     a.thr = thr;
     a.tol2 = tol * tol;
     a.jacobi = beta < kJacobiBelow;
-    a.x = g;
-    a.r = b.r;
-    a.z = b.z;
-    a.p0 = b.p0;
-    a.p1 = b.p1;
-    a.q = b.q;
-    a.w2 = b.w2;
-    a.partials = b.partials;
-    a.counter = b.counter;
-    a.st = b.st;
     launch_pcg_init_plain(a, weight, g_tilde, h_out, v_out, st);
     int iters = 0;
-    return run_pcg(a, max_iter, fft, nullptr, st, &iters);
+    return run_pcg(a, max_iter, 8, fft, st, &iters);
 }
 
 // ---- solver ---------------------------------------------------------------
@@ -594,6 +619,7 @@ int dect_solver_create(const dect_geometry* gin, const dect_params* p, int32_t b
     if (!fft_size_ok(g.nx) || !fft_size_ok(g.ny))
         return fail(DECT_EINVAL, "image sizes must be 2^a*3^b (b <= 1) in [8, 1024], got %dx%d", g.nx,
                     g.ny);
+    if (g.nd > 4096) return fail(DECT_EINVAL, "n_det > 4096 is not supported by the FBP start");
     dect_solver* s = new dect_solver();
     s->g = g;
     s->batch = batch;
@@ -615,10 +641,11 @@ int dect_solver_create(const dect_geometry* gin, const dect_params* p, int32_t b
         s->ws = ws;
         s->owns_ws = false;
     } else {
-        if (hipMallocAsync(&s->ws, need, st) != hipSuccess) {
+        if (int rc = dev_alloc(&s->own, need, st)) {
             delete s;
-            return fail(DECT_ENOMEM, "could not allocate %zu bytes of solver workspace", need);
+            return rc;
         }
+        s->ws = s->own.p;
         s->owns_ws = true;
     }
     solver_layout(g, batch, static_cast<char*>(s->ws), s);
@@ -627,10 +654,10 @@ int dect_solver_create(const dect_geometry* gin, const dect_params* p, int32_t b
     e = e != hipSuccess ? e : hipMemsetAsync(s->dN, 0, padN_elems(g) * batch * sizeof(float2), st);
     e = e != hipSuccess ? e : hipMemsetAsync(s->dT, 0, padT_elems(g) * batch * sizeof(float2), st);
     e = e != hipSuccess ? e : hipMemsetAsync(s->cnt_proj, 0, sizeof(unsigned) * batch, st);
-    e = e != hipSuccess ? e : hipMemsetAsync(s->pcg.counter, 0, sizeof(unsigned) * batch, st);
+
     e = e != hipSuccess ? e : hipMemsetAsync(s->pcg.st, 0, sizeof(PcgState) * batch, st);
     if (e != hipSuccess) {
-        if (s->owns_ws) (void)hipFreeAsync(s->ws, st);
+        if (s->owns_ws) dev_free(&s->own);
         delete s;
         return fail(DECT_EDEVICE, "hipMemsetAsync failed: %s", hipGetErrorString(e));
     }
@@ -645,7 +672,7 @@ int dect_solver_create(const dect_geometry* gin, const dect_params* p, int32_t b
 
 int dect_solver_destroy(dect_solver* s) {
     if (!s) return DECT_OK;
-    if (s->owns_ws) (void)hipFreeAsync(s->ws, s->st);
+    if (s->owns_ws) dev_free(&s->own);
     delete s;
     return DECT_OK;
 }
@@ -730,7 +757,7 @@ static int one_iteration(dect_solver* s) {
     FftArgs fa;
     fa.src = FFT_SRC_RHO;
     fa.f = s->f;
-    fa.rho = s->rho;
+    fa.base = s->rho;
     fa.m00 = s->M.Ms[0][0];
     fa.m01 = s->M.Ms[0][1];
     fa.m10 = s->M.Ms[1][0];
@@ -745,26 +772,14 @@ static int one_iteration(dect_solver* s) {
     launch_fft_solve(g.ny, g.nx, s->batch, fa, s->fft, s->st);
     // t' step (reads f^(k), t'^(k); in place)
     PcgArgs pc;
-    pc.ny = g.ny;
-    pc.nx = g.nx;
-    pc.batch = s->batch;
+    fill_pcg_args(&pc, s->pcg, g.ny, g.nx, s->batch, s->t);
     pc.beta = (float)beta;
     pc.thr = a.thr;
     pc.tol2 = R.p.t_tol * R.p.t_tol;
     pc.jacobi = beta < kJacobiBelow;
-    pc.x = s->t;
-    pc.r = s->pcg.r;
-    pc.z = s->pcg.z;
-    pc.p0 = s->pcg.p0;
-    pc.p1 = s->pcg.p1;
-    pc.q = s->pcg.q;
-    pc.w2 = s->pcg.w2;
-    pc.partials = s->pcg.partials;
-    pc.counter = s->pcg.counter;
-    pc.st = s->pcg.st;
     launch_pcg_init_model(s->M, pc, s->f, s->st);
     int iters = 0;
-    if (int rc = run_pcg(pc, R.p.t_maxit, s->fft, nullptr, s->st, &iters)) return rc;
+    if (int rc = run_pcg(pc, R.p.t_maxit, s->last_pcg + 2, s->fft, s->st, &iters)) return rc;
     s->last_pcg = iters;
     // f^(k+1), residual sinograms
     launch_update(a, s->alpha, s->dN, s->f, s->S, s->zq, s->st);

@@ -110,20 +110,32 @@ bool fft_size_ok(int n);
 enum FftSrc { FFT_SRC_PLAIN = 0, FFT_SRC_RHO = 1, FFT_SRC_L0 = 2 };
 struct FftArgs {
     int src = FFT_SRC_PLAIN;
-    const float* in = nullptr;        // PLAIN: rhs image; L0: g_tilde
-    // RHO: rhs = rho_hat(f) + beta*D^T HT(D rho)
-    const float2* f = nullptr;        // f pairs
-    const float* rho = nullptr;       // current rho (HT input)
-    const float* g_cur = nullptr;     // L0: current g (HT input)
-    float* h_out = nullptr;           // L0: optional h, v outputs
+    // PLAIN: out = (c + beta L)^-1 in.
+    // RHO / L0 (correction form): with g = base (the current iterate, also the
+    // hard-threshold input) and S its thresholded-away gradients,
+    //   (1 + beta L) delta = (target - g) - beta D^T S,   out = g + delta,
+    // target = rho_hat(f) (RHO) or in = g_tilde (L0).  Equal to the closed
+    // form for (1 + beta L) out = target + beta D^T HT(D g), without the large
+    // cancelling terms.
+    const float* in = nullptr;
+    const float2* f = nullptr;
+    const float* base = nullptr;
+    float* h_out = nullptr;           // L0: optional kept (h, v)
     float* v_out = nullptr;
     double m00 = 0, m01 = 0, m10 = 0, m11 = 0;   // synthesis matrix (barn)
     double e1n = 0, e2n = 0, inv_crho = 0;       // E1^n, E2^n, 1/c_rho
     float beta = 0, thr = 0;
-    double c = 1.0;                   // diagonal shift
-    const double* c_dev = nullptr;    // device diagonal shift (overrides c)
-    const int* skip = nullptr;        // device flag: skip the solve when nonzero
-    float* out = nullptr;             // result image
+    double c = 1.0;                   // diagonal shift, or from partial sums:
+    const double* c_parts = nullptr;  //   c = c_scale * sum(c_parts[z*c_zstride + 0..c_n))
+    int c_n = 0;
+    size_t c_zstride = 0;
+    double c_scale = 0.0;
+    const int* skip = nullptr;        // skip slice z when skip[z*skip_zstride] != 0
+    size_t skip_zstride = 0;
+    float* out = nullptr;
+    const float* dot_with = nullptr;  // optional: dot_parts[z*dot_zstride + row] = <out, dot_with>
+    double* dot_parts = nullptr;
+    size_t dot_zstride = 0;
 };
 size_t fft_scratch_bytes(int ny, int nx, int batch);
 void launch_fft_solve(int ny, int nx, int batch, const FftArgs& a, float2* scratch,
@@ -160,31 +172,40 @@ void launch_join_f2(int n, int batch, const float* a, const float* b, float2* f,
                     hipStream_t st);
 
 // ---- PCG for (diag(w^2) + beta D^T D) x = w*g + beta D^T HT(D x0) -------------
-struct PcgState {   // per-slice device scalars
-    double rz, bnorm2, pq, alpha, beta_cg, cshift, rr;
+// Warm start x = x0; the initial residual is formed without cancellation as
+// r0 = w*(g - w*x0) - beta*D^T S(x0), S the thresholded-away gradients of x0.
+// Scalars are never stored: every block re-reduces the previous kernel's
+// per-block partial sums in a fixed order (deterministic, fence-free).
+// Stopping rule: ||r_k|| <= tol * ||r_0||.
+struct PcgState {   // per slice, read by the host
     int done, iters, pad0, pad1;
 };
+struct PcgParts {   // per-slice partial-sum layout (doubles)
+    int nblk, nrz;  // blocks of the pixel kernels; entries of an rz sum
+    size_t init0, init1, pq, rz, rr, zstride;   // offsets within a slice
+};
+PcgParts pcg_parts(int ny, int nx);
 struct PcgArgs {
     int ny, nx, batch;
     float beta, thr;
-    double tol2;             // tol^2 on ||r||^2 / ||b||^2
+    double tol2;
     bool jacobi;
     float* x;                // in: x0 (also HT input), out: solution
     float *r, *z, *p0, *p1, *q, *w2;
-    double* partials;        // [batch][nblocks][4]
-    unsigned* counter;       // [batch]
+    double* parts;           // [batch][PcgParts::zstride]
+    PcgParts L;
     PcgState* st;            // [batch]
 };
-int pcg_nblocks(int ny, int nx);
-// RHS from the model (t' subproblem): w = W/Ww, g = d_t/Ww from f pairs
+// initial residual from the model (t' subproblem): w = W/Ww, g = d_t/Ww from f
 void launch_pcg_init_model(const Model& M, const PcgArgs& a, const float2* f, hipStream_t st);
-// RHS from explicit weight / g_tilde (dect_l0_step)
+// from explicit weight and g_tilde (dect_l0_step); optional kept (h, v) of x0
 void launch_pcg_init_plain(const PcgArgs& a, const float* w, const float* g_tilde, float* h_out,
                            float* v_out, hipStream_t st);
-// after an FFT preconditioner produced z from r: rz, p = z
-void launch_pcg_after_prec_init(const PcgArgs& a, hipStream_t st);
-void launch_pcg_matvec(const PcgArgs& a, int parity, bool first, hipStream_t st);
-void launch_pcg_update(const PcgArgs& a, int parity, hipStream_t st);
-void launch_pcg_after_prec(const PcgArgs& a, hipStream_t st);
+void launch_pcg_matvec(const PcgArgs& a, int it, hipStream_t st);
+void launch_pcg_update(const PcgArgs& a, int it, hipStream_t st);
+// after `done_iters` completed iterations: set done / iters for the host
+void launch_pcg_check(const PcgArgs& a, int done_iters, hipStream_t st);
+// FFT preconditioner z = (c + beta L)^-1 r, c = mean(w^2), with <r, z> partials
+void launch_pcg_fft_prec(const PcgArgs& a, int it, float2* scratch, hipStream_t st);
 
 }  // namespace dect

@@ -12,34 +12,35 @@
 
 namespace dect {
 
-// One block per (view, sinogram): the weighted row and the filter taps in LDS.
+// One block per (view, sinogram): the weighted row and the filter taps in LDS,
+// FP64 throughout (run once per solve; keeps the initial images, and the
+// ill-conditioned closed-form t' computed from them, close to FP64).
 __global__ __launch_bounds__(256) void k_fbp_filter(const float* __restrict__ sino, int nv, int nd,
                                                     double pitch, double offset, double sid,
                                                     double sdd, float* __restrict__ q) {
-    extern __shared__ float sm[];
-    float* pw = sm;            // nd
-    float* tap = sm + nd;      // nd: tap[n] = 1/(pi^2 n^2), n odd; 0 otherwise
+    extern __shared__ double smd[];
+    double* pw = smd;          // nd
+    double* tap = smd + nd;    // nd: tap[n] = 1/(pi^2 n^2), n odd; 0 otherwise
     const int v = blockIdx.x, b = blockIdx.y;
     const size_t row = ((size_t)b * nv + v) * nd;
     const double mag = sid / sdd;
     for (int j = threadIdx.x; j < nd; j += blockDim.x) {
         const double up = (((double)j - 0.5 * (nd - 1)) * pitch + offset) * mag;
-        pw[j] = (float)((double)sino[row + j] * sid / sqrt(sid * sid + up * up));
-        tap[j] = (j & 1) ? (float)(1.0 / (M_PI * M_PI * (double)j * (double)j)) : 0.f;
+        pw[j] = (double)sino[row + j] * sid / sqrt(sid * sid + up * up);
+        tap[j] = (j & 1) ? 1.0 / (M_PI * M_PI * (double)j * (double)j) : 0.0;
     }
     __syncthreads();
-    const float inv_dp = (float)(1.0 / (pitch * mag));
+    const double inv_dp = 1.0 / (pitch * mag);
     for (int j = threadIdx.x; j < nd; j += blockDim.x) {
-        // far taps first: they are the small ones
-        float acc = 0.f;
+        double acc = 0.0;
         const int nmax = max(j, nd - 1 - j);
         for (int n = (nmax & 1) ? nmax : nmax - 1; n >= 1; n -= 2) {
-            float t = 0.f;
+            double t = 0.0;
             if (j - n >= 0) t += pw[j - n];
             if (j + n < nd) t += pw[j + n];
-            acc = fmaf(tap[n], t, acc);
+            acc = fma(tap[n], t, acc);
         }
-        q[row + j] = (0.25f * pw[j] - acc) * inv_dp;
+        q[row + j] = (float)((0.25 * pw[j] - acc) * inv_dp);
     }
 }
 
@@ -93,7 +94,7 @@ __global__ __launch_bounds__(256) void k_fbp_bp(const float* __restrict__ q, int
 
 void launch_fbp(const Geom& g, const float* sino, int nsino, float* q, float* img,
                 hipStream_t st) {
-    const size_t lds = 2 * (size_t)g.nd * sizeof(float);
+    const size_t lds = 2 * (size_t)g.nd * sizeof(double);
     hipLaunchKernelGGL(k_fbp_filter, dim3(g.nv, nsino), dim3(256), lds, st, sino, g.nv, g.nd,
                        g.pitch, g.offset, g.sid, g.sdd, q);
     const int npix = g.nx * g.ny;

@@ -127,16 +127,22 @@ __device__ float2* fft_lds(float2* a, float2* b, const float2* tw, const FftPlan
     return a;
 }
 
-// hard threshold (9) at (row ra, column k) of an image held as rows ra, rb
-// (rb = the next row down): returns kept (dx, dy) or (0, 0).  The decision is
-// taken in FP32 with separately rounded squares.
-__device__ __forceinline__ float2 ht_pair(const float* ra, const float* rb, int k, int nx,
-                                          float thr) {
+// Thresholded-away gradients S at (row ra, column k) of an image held as rows
+// ra, rb (rb = the next row down): (dx, dy) where eq. (9) zeroes them, else
+// (0, 0).  `kept` receives the complementary kept pair.  The decision is taken
+// in FP32 with separately rounded squares.
+__device__ __forceinline__ float2 ht_small(const float* ra, const float* rb, int k, int nx,
+                                           float thr, float2* kept) {
     const int k1 = (k + 1 == nx) ? 0 : k + 1;
     const float dx = ra[k1] - ra[k];
     const float dy = rb[k] - ra[k];
-    const float s = __fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy));
-    return s > thr ? make_float2(dx, dy) : make_float2(0.f, 0.f);
+    const bool keep = __fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)) > thr;
+    if (kept) *kept = keep ? make_float2(dx, dy) : make_float2(0.f, 0.f);
+    return keep ? make_float2(0.f, 0.f) : make_float2(dx, dy);
+}
+
+__device__ __forceinline__ bool skip_slice(const FftArgs& a, int z) {
+    return a.skip && a.skip[(size_t)z * a.skip_zstride];
 }
 
 __global__ __launch_bounds__(256) void k_fft_rows_fwd(FftPlan P, int ny, FftArgs a,
@@ -148,19 +154,18 @@ __global__ __launch_bounds__(256) void k_fft_rows_fwd(FftPlan P, int ny, FftArgs
     float2* tw = sm2 + 2 * nx;
     float* rows = reinterpret_cast<float*>(sm2 + 3 * nx);   // 3 rows of the HT input
     const int i = blockIdx.x, z = blockIdx.y;
-    if (a.skip && a.skip[(size_t)z * (sizeof(PcgState) / sizeof(int))]) return;
+    if (skip_slice(a, z)) return;
     const size_t npix = (size_t)nx * ny;
     fill_twiddles(tw, nx);
     if (a.src == FFT_SRC_PLAIN) {
         for (int k = threadIdx.x; k < nx; k += blockDim.x)
             A[k] = make_float2(a.in[z * npix + (size_t)i * nx + k], 0.f);
     } else {
-        const float* src = (a.src == FFT_SRC_RHO) ? a.rho : a.g_cur;
         const int im = (i == 0) ? ny - 1 : i - 1, ip = (i + 1 == ny) ? 0 : i + 1;
         for (int k = threadIdx.x; k < nx; k += blockDim.x) {
-            rows[k] = src[z * npix + (size_t)im * nx + k];
-            rows[nx + k] = src[z * npix + (size_t)i * nx + k];
-            rows[2 * nx + k] = src[z * npix + (size_t)ip * nx + k];
+            rows[k] = a.base[z * npix + (size_t)im * nx + k];
+            rows[nx + k] = a.base[z * npix + (size_t)i * nx + k];
+            rows[2 * nx + k] = a.base[z * npix + (size_t)ip * nx + k];
         }
         __syncthreads();
         const float* rm = rows;
@@ -168,22 +173,24 @@ __global__ __launch_bounds__(256) void k_fft_rows_fwd(FftPlan P, int ny, FftArgs
         const float* rp = rows + 2 * nx;
         for (int k = threadIdx.x; k < nx; k += blockDim.x) {
             const int km = (k == 0) ? nx - 1 : k - 1;
-            const float2 hc = ht_pair(r0, rp, k, nx, a.thr);    // (h, v) at (i, k)
-            const float2 hl = ht_pair(r0, rp, km, nx, a.thr);   // at (i, k-1)
-            const float2 hu = ht_pair(rm, r0, k, nx, a.thr);    // at (i-1, k)
-            const float dth = (hl.x - hc.x) + (hu.y - hc.y);
-            float base;
+            float2 kept;
+            const float2 sc = ht_small(r0, rp, k, nx, a.thr, &kept);   // at (i, k)
+            const float2 sl = ht_small(r0, rp, km, nx, a.thr, nullptr); // at (i, k-1)
+            const float2 su = ht_small(rm, r0, k, nx, a.thr, nullptr);  // at (i-1, k)
+            const float dts = (sl.x - sc.x) + (su.y - sc.y);
+            const float g = r0[k];
+            float diff;
             if (a.src == FFT_SRC_RHO) {
                 const float2 f = a.f[z * npix + (size_t)i * nx + k];
                 const double M1 = a.m00 * (double)f.x + a.m01 * (double)f.y;
                 const double M2 = a.m10 * (double)f.x + a.m11 * (double)f.y;
-                base = (float)((M1 * a.e1n - M2 * a.e2n) * a.inv_crho);
+                diff = (float)((M1 * a.e1n - M2 * a.e2n) * a.inv_crho - (double)g);
             } else {
-                base = a.in[z * npix + (size_t)i * nx + k];
-                if (a.h_out) a.h_out[z * npix + (size_t)i * nx + k] = hc.x;
-                if (a.v_out) a.v_out[z * npix + (size_t)i * nx + k] = hc.y;
+                diff = a.in[z * npix + (size_t)i * nx + k] - g;
+                if (a.h_out) a.h_out[z * npix + (size_t)i * nx + k] = kept.x;
+                if (a.v_out) a.v_out[z * npix + (size_t)i * nx + k] = kept.y;
             }
-            A[k] = make_float2(base + a.beta * dth, 0.f);
+            A[k] = make_float2(diff - a.beta * dts, 0.f);
         }
     }
     __syncthreads();
@@ -194,6 +201,8 @@ __global__ __launch_bounds__(256) void k_fft_rows_fwd(FftPlan P, int ny, FftArgs
 __global__ __launch_bounds__(256) void k_fft_cols(FftPlan P, int nx, int cols, FftArgs a,
                                                   float2* __restrict__ scratch) {
     extern __shared__ float2 sm2[];
+    __shared__ double sh[4];
+    __shared__ float cz_sh;
     const int ny = P.n;
     float2* A = sm2;
     float2* B = sm2 + (size_t)ny * cols;
@@ -201,8 +210,14 @@ __global__ __launch_bounds__(256) void k_fft_cols(FftPlan P, int nx, int cols, F
     float* lamy = reinterpret_cast<float*>(tw + ny);
     float* lamx = lamy + ny;
     const int c0 = blockIdx.x * cols, z = blockIdx.y;
-    if (a.skip && a.skip[(size_t)z * (sizeof(PcgState) / sizeof(int))]) return;
+    if (skip_slice(a, z)) return;
     const size_t npix = (size_t)nx * ny;
+    if (a.c_parts) {
+        const double s = block_sum_array<256>(a.c_parts + (size_t)z * a.c_zstride, a.c_n, 1, sh);
+        if (threadIdx.x == 0) cz_sh = (float)fmax(a.c_scale * s, 1e-12);
+    } else if (threadIdx.x == 0) {
+        cz_sh = (float)a.c;
+    }
     fill_twiddles(tw, ny);
     for (int e = threadIdx.x; e < ny; e += blockDim.x) {
         const double s = sinpi((double)e / (double)ny);
@@ -219,11 +234,10 @@ __global__ __launch_bounds__(256) void k_fft_cols(FftPlan P, int nx, int cols, F
     __syncthreads();
     float2* R = fft_lds<false>(A, B, tw, P, cols);
     float2* S = (R == A) ? B : A;
-    const float cz = (float)(a.c_dev ? a.c_dev[(size_t)z * (sizeof(PcgState) / sizeof(double))] : a.c);
+    const float cz = cz_sh;
     for (int idx = threadIdx.x; idx < ny * cols; idx += blockDim.x) {
         const int e = idx / cols, c = idx - (idx / cols) * cols;
-        const float den = cz + a.beta * (lamx[c] + lamy[e]);
-        const float sc = 1.0f / den;
+        const float sc = 1.0f / (cz + a.beta * (lamx[c] + lamy[e]));
         R[idx] = make_float2(R[idx].x * sc, R[idx].y * sc);
     }
     __syncthreads();
@@ -237,19 +251,32 @@ __global__ __launch_bounds__(256) void k_fft_cols(FftPlan P, int nx, int cols, F
 __global__ __launch_bounds__(256) void k_fft_rows_inv(FftPlan P, int ny, FftArgs a,
                                                       const float2* __restrict__ scratch) {
     extern __shared__ float2 sm2[];
+    __shared__ double sh[4];
     const int nx = P.n;
     float2* A = sm2;
     float2* B = sm2 + nx;
     float2* tw = sm2 + 2 * nx;
     const int i = blockIdx.x, z = blockIdx.y;
-    if (a.skip && a.skip[(size_t)z * (sizeof(PcgState) / sizeof(int))]) return;
+    if (skip_slice(a, z)) return;
     const size_t npix = (size_t)nx * ny;
     fill_twiddles(tw, nx);
     for (int k = threadIdx.x; k < nx; k += blockDim.x) A[k] = scratch[z * npix + (size_t)i * nx + k];
     __syncthreads();
     const float2* R = fft_lds<true>(A, B, tw, P, 1);
     const float sc = (float)(1.0 / ((double)nx * (double)ny));
-    for (int k = threadIdx.x; k < nx; k += blockDim.x) a.out[z * npix + (size_t)i * nx + k] = R[k].x * sc;
+    const bool corr = a.src != FFT_SRC_PLAIN;
+    double dot = 0.0;
+    for (int k = threadIdx.x; k < nx; k += blockDim.x) {
+        const size_t q = z * npix + (size_t)i * nx + k;
+        const float d = R[k].x * sc;
+        const float v = corr ? a.base[q] + d : d;
+        a.out[q] = v;
+        if (a.dot_with) dot += (double)v * (double)a.dot_with[q];
+    }
+    if (a.dot_parts) {
+        const double s = block_sum<256>(dot, sh);
+        if (threadIdx.x == 0) a.dot_parts[(size_t)z * a.dot_zstride + i] = s;
+    }
 }
 
 size_t fft_scratch_bytes(int ny, int nx, int batch) {

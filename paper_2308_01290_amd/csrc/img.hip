@@ -267,41 +267,50 @@ void launch_join_f2(int n, int batch, const float* a, const float* b, float2* f,
 // ---------------------------------------------------------------------------
 // PCG for (diag(w^2) + beta L) x = b, L = D^T D (periodic 5-point)
 // ---------------------------------------------------------------------------
-int pcg_nblocks(int ny, int nx) { return (nx * ny + 255) / 256; }
+constexpr int kPcgPix = 4;                     // pixels per thread
+constexpr int kPcgBlock = 256 * kPcgPix;       // pixels per block
 
-// D^T HT(D x) at (i, k) from the 7 neighbours the two-sided stencil needs.
-__device__ __forceinline__ float dt_ht(const float* x, int i, int k, int ny, int nx, float thr,
-                                       float* h_here, float* v_here) {
+PcgParts pcg_parts(int ny, int nx) {
+    PcgParts L;
+    L.nblk = (nx * ny + kPcgBlock - 1) / kPcgBlock;
+    L.nrz = L.nblk > ny ? L.nblk : ny;
+    L.init0 = 0;
+    L.init1 = L.init0 + L.nblk;
+    L.pq = L.init1 + L.nblk;
+    L.rz = L.pq + L.nblk;              // two parity slots of nrz
+    L.rr = L.rz + 2 * (size_t)L.nrz;   // two parity slots of nblk
+    L.zstride = L.rr + 2 * (size_t)L.nblk;
+    return L;
+}
+
+// Sum of n partials in fixed order, broadcast to every thread of the block.
+__device__ __forceinline__ double sum_parts(const double* a, int n, double* sh, double* bc) {
+    const double s = block_sum_array<256>(a, n, 1, sh);
+    if (threadIdx.x == 0) *bc = s;
+    __syncthreads();
+    const double r = *bc;
+    __syncthreads();
+    return r;
+}
+
+// D^T S at (i, k), S = thresholded-away gradients of x; `kept` = kept (h, v) at (i, k).
+__device__ __forceinline__ float dt_small(const float* x, int i, int k, int ny, int nx, float thr,
+                                          float2* kept) {
     const int ip = (i + 1 == ny) ? 0 : i + 1, im = (i == 0) ? ny - 1 : i - 1;
     const int kp = (k + 1 == nx) ? 0 : k + 1, km = (k == 0) ? nx - 1 : k - 1;
     const float c = x[(size_t)i * nx + k];
     const float r = x[(size_t)i * nx + kp], d = x[(size_t)ip * nx + k];
     const float l = x[(size_t)i * nx + km], dl = x[(size_t)ip * nx + km];
     const float u = x[(size_t)im * nx + k], ur = x[(size_t)im * nx + kp];
-    // (h, v) at (i, k)
-    float hx = r - c, hy = d - c;
-    if (!keep_grad(hx, hy, thr)) hx = hy = 0.f;
-    // at (i, k-1)
-    float lx = c - l, ly = dl - l;
-    if (!keep_grad(lx, ly, thr)) lx = ly = 0.f;
-    // at (i-1, k)
-    float ux = ur - u, uy = c - u;
-    if (!keep_grad(ux, uy, thr)) ux = uy = 0.f;
-    if (h_here) *h_here = hx;
-    if (v_here) *v_here = hy;
+    float hx = r - c, hy = d - c;          // at (i, k)
+    const bool kh = keep_grad(hx, hy, thr);
+    if (kept) *kept = kh ? make_float2(hx, hy) : make_float2(0.f, 0.f);
+    if (kh) hx = hy = 0.f;
+    float lx = c - l, ly = dl - l;         // at (i, k-1)
+    if (keep_grad(lx, ly, thr)) lx = ly = 0.f;
+    float ux = ur - u, uy = c - u;         // at (i-1, k)
+    if (keep_grad(ux, uy, thr)) ux = uy = 0.f;
     return (lx - hx) + (uy - hy);
-}
-
-__device__ __forceinline__ float lap(const float* x, int i, int k, int ny, int nx) {
-    const int ip = (i + 1 == ny) ? 0 : i + 1, im = (i == 0) ? ny - 1 : i - 1;
-    const int kp = (k + 1 == nx) ? 0 : k + 1, km = (k == 0) ? nx - 1 : k - 1;
-    return 4.f * x[(size_t)i * nx + k] - x[(size_t)i * nx + kp] - x[(size_t)i * nx + km] -
-           x[(size_t)ip * nx + k] - x[(size_t)im * nx + k];
-}
-
-// finish of a PCG reduction in the last block: 4 partial sums per block
-__device__ __forceinline__ void pcg_sums(const double* part, int nblk, double* sh, double out[4]) {
-    for (int c = 0; c < 4; ++c) out[c] = block_sum_array<256>(part + c, nblk, 4, sh);
 }
 
 template <bool MODEL>
@@ -310,235 +319,206 @@ __global__ __launch_bounds__(256) void k_pcg_init(PcgArgs a, ModelF M, const flo
                                                   const float* __restrict__ g_in,
                                                   float* __restrict__ h_out, float* __restrict__ v_out) {
     __shared__ double sh[4];
-    const int nx = a.nx, ny = a.ny;
-    const int npix = nx * ny;
-    const int p = blockIdx.x * 256 + threadIdx.x;
+    const int nx = a.nx, ny = a.ny, npix = nx * ny;
     const int z = blockIdx.y;
     const size_t zo = (size_t)z * npix;
-    double bb = 0.0, rz = 0.0, ws = 0.0, rr = 0.0;
-    if (p < npix) {
+    double* P = a.parts + (size_t)z * a.L.zstride;
+    const float* x = a.x + zo;
+    double rz = 0.0, rr = 0.0, ws = 0.0;
+    for (int q = 0; q < kPcgPix; ++q) {
+        const int p = blockIdx.x * kPcgBlock + q * 256 + threadIdx.x;
+        if (p >= npix) break;
         const int i = p / nx, k = p % nx;
-        float w, wg;
+        double w, g;
         if (MODEL) {
             const float2 fv = f[zo + p];
             const double M1 = M.Ms[0][0] * fv.x + M.Ms[0][1] * fv.y;
             const double M2 = M.Ms[1][0] * fv.x + M.Ms[1][1] * fv.y;
             const double W = M.cpb * pow(M.Zw, M.m) * (M1 / M.e2n - M2 / M.e1n);
-            const double dt = M2 * M.psi[0] - M1 * M.psi[1];
-            w = (float)(W / M.Ww);
-            wg = (float)((W / M.Ww) * (dt / M.Ww));
+            w = W / M.Ww;
+            g = (M2 * M.psi[0] - M1 * M.psi[1]) / M.Ww;
         } else {
             w = w_in[zo + p];
-            wg = w * g_in[zo + p];
+            g = g_in[zo + p];
         }
-        const float* x = a.x + zo;
-        float hh, vv;
-        const float b = wg + a.beta * dt_ht(x, i, k, ny, nx, a.thr, &hh, &vv);
-        if (h_out) h_out[zo + p] = hh;
-        if (v_out) v_out[zo + p] = vv;
-        const float w2 = w * w;
-        const float ax = fmaf(w2, x[p], a.beta * lap(x, i, k, ny, nx));
-        const float r = b - ax;
-        const float zz = r / (w2 + 4.f * a.beta);
+        float2 kept;
+        const float dts = dt_small(x, i, k, ny, nx, a.thr, &kept);
+        if (h_out) h_out[zo + p] = kept.x;
+        if (v_out) v_out[zo + p] = kept.y;
+        // r0 = b - A x0 = w (g - w x0) - beta D^T S(x0)
+        const float r = (float)(w * (g - w * (double)x[p])) - a.beta * dts;
+        const float w2 = (float)(w * w);
         a.w2[zo + p] = w2;
         a.r[zo + p] = r;
-        a.z[zo + p] = zz;
-        a.p0[zo + p] = zz;
-        bb = (double)b * b;
-        rz = (double)r * zz;
-        ws = w2;
-        rr = (double)r * r;
+        if (a.jacobi) {
+            const float zz = r / (w2 + 4.f * a.beta);
+            a.z[zo + p] = zz;
+            rz += (double)r * zz;
+        }
+        rr += (double)r * r;
+        ws += w2;
     }
-    const int nblk = gridDim.x;
-    const double s0 = block_sum<256>(bb, sh), s1 = block_sum<256>(rz, sh);
-    const double s2 = block_sum<256>(ws, sh), s3 = block_sum<256>(rr, sh);
-    double* part = a.partials + (size_t)z * nblk * 4;
+    const double s_rz = block_sum<256>(rz, sh);
+    const double s_rr = block_sum<256>(rr, sh);
+    const double s_ws = block_sum<256>(ws, sh);
     if (threadIdx.x == 0) {
-        part[blockIdx.x * 4 + 0] = s0;
-        part[blockIdx.x * 4 + 1] = s1;
-        part[blockIdx.x * 4 + 2] = s2;
-        part[blockIdx.x * 4 + 3] = s3;
-    }
-    if (last_block_arrive(a.counter + z, (unsigned)nblk)) {
-        double s[4];
-        pcg_sums(part, nblk, sh, s);
-        if (threadIdx.x == 0) {
-            PcgState& S = a.st[z];
-            S.bnorm2 = s[0];
-            S.rz = s[1];
-            S.cshift = fmax(s[2] / (double)npix, 1e-12);
-            S.rr = s[3];
-            S.iters = 0;
-            S.done = (s[0] == 0.0 || s[3] <= a.tol2 * s[0]) ? 1 : 0;
-            S.alpha = 0.0;
-            S.beta_cg = 0.0;
-            S.pq = 0.0;
+        P[a.L.init0 + blockIdx.x] = s_rr;               // ||r0||^2, the reference
+        P[a.L.init1 + blockIdx.x] = s_ws;               // sum of w^2 (FFT shift)
+        P[a.L.rr + a.L.nblk + blockIdx.x] = s_rr;       // parity slot 1: "previous" rr
+        if (a.jacobi) P[a.L.rz + a.L.nrz + blockIdx.x] = s_rz;
+        if (blockIdx.x == 0) {
+            a.st[z].done = 0;
+            a.st[z].iters = 0;
         }
     }
 }
 
 void launch_pcg_init_model(const Model& M, const PcgArgs& a, const float2* f, hipStream_t st) {
-    hipLaunchKernelGGL(k_pcg_init<true>, dim3(pcg_nblocks(a.ny, a.nx), a.batch), dim3(256), 0, st, a,
-                       to_dev(M), f, nullptr, nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL(k_pcg_init<true>, dim3(a.L.nblk, a.batch), dim3(256), 0, st, a, to_dev(M), f,
+                       nullptr, nullptr, nullptr, nullptr);
 }
 
 void launch_pcg_init_plain(const PcgArgs& a, const float* w, const float* g_tilde, float* h_out,
                            float* v_out, hipStream_t st) {
     Model dummy{};
-    hipLaunchKernelGGL(k_pcg_init<false>, dim3(pcg_nblocks(a.ny, a.nx), a.batch), dim3(256), 0, st, a,
+    hipLaunchKernelGGL(k_pcg_init<false>, dim3(a.L.nblk, a.batch), dim3(256), 0, st, a,
                        to_dev(dummy), nullptr, w, g_tilde, h_out, v_out);
 }
 
-// after z = P^-1 r by the FFT preconditioner at initialisation: rz, p0 = z
-__global__ __launch_bounds__(256) void k_pcg_prec_init(PcgArgs a) {
+// Iteration it, first half: convergence test, direction p = z + beta_cg p_prev,
+// q = A p, <p, q> partials.
+__global__ __launch_bounds__(256) void k_pcg_matvec(PcgArgs a, int it) {
     __shared__ double sh[4];
-    const int npix = a.nx * a.ny;
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    const int z = blockIdx.y;
-    if (a.st[z].done) return;
-    const size_t zo = (size_t)z * npix;
-    double rz = 0.0;
-    if (p < npix) {
-        const float zz = a.z[zo + p];
-        a.p0[zo + p] = zz;
-        rz = (double)a.r[zo + p] * zz;
-    }
-    const int nblk = gridDim.x;
-    const double s = block_sum<256>(rz, sh);
-    double* part = a.partials + (size_t)z * nblk * 4;
-    if (threadIdx.x == 0) part[blockIdx.x * 4] = s;
-    if (last_block_arrive(a.counter + z, (unsigned)nblk)) {
-        const double t = block_sum_array<256>(part, nblk, 4, sh);
-        if (threadIdx.x == 0) a.st[z].rz = t;
-    }
-}
-
-void launch_pcg_after_prec_init(const PcgArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL(k_pcg_prec_init, dim3(pcg_nblocks(a.ny, a.nx), a.batch), dim3(256), 0, st, a);
-}
-
-// q = A p with p = z + beta_cg * p_prev (first: p = p0); <p, q>; alpha = rz / <p, q>
-__global__ __launch_bounds__(256) void k_pcg_matvec(PcgArgs a, int parity, int first) {
-    __shared__ double sh[4];
+    __shared__ double bc;
     const int nx = a.nx, ny = a.ny, npix = nx * ny;
-    const int p = blockIdx.x * 256 + threadIdx.x;
     const int z = blockIdx.y;
     if (a.st[z].done) return;
+    double* P = a.parts + (size_t)z * a.L.zstride;
+    const int cur = it & 1, prev = cur ^ 1;
+    const int nrz = a.jacobi ? a.L.nblk : a.ny;
+    const double rz_new = sum_parts(P + a.L.rz + (size_t)prev * a.L.nrz, nrz, sh, &bc);
+    const double rr = sum_parts(P + a.L.rr + (size_t)prev * a.L.nblk, a.L.nblk, sh, &bc);
+    const double r0 = sum_parts(P + a.L.init0, a.L.nblk, sh, &bc);
+    if (rr <= a.tol2 * r0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            a.st[z].done = 1;
+            a.st[z].iters = it;
+        }
+        return;
+    }
+    float bcg = 0.f;
+    if (it > 0) {
+        const double rz_old = sum_parts(P + a.L.rz + (size_t)cur * a.L.nrz, nrz, sh, &bc);
+        bcg = rz_old > 0.0 ? (float)(rz_new / rz_old) : 0.f;
+    }
     const size_t zo = (size_t)z * npix;
-    float* pout = (parity ? a.p1 : a.p0) + zo;
-    const float* pin = (parity ? a.p0 : a.p1) + zo;
+    float* pout = (cur ? a.p1 : a.p0) + zo;
+    const float* pin = (cur ? a.p0 : a.p1) + zo;
     const float* zz = a.z + zo;
-    const float bc = (float)a.st[z].beta_cg;
     double pq = 0.0;
-    if (p < npix) {
+    for (int s = 0; s < kPcgPix; ++s) {
+        const int p = blockIdx.x * kPcgBlock + s * 256 + threadIdx.x;
+        if (p >= npix) break;
         const int i = p / nx, k = p % nx;
         const int ip = (i + 1 == ny) ? 0 : i + 1, im = (i == 0) ? ny - 1 : i - 1;
         const int kp = (k + 1 == nx) ? 0 : k + 1, km = (k == 0) ? nx - 1 : k - 1;
         const int nb[5] = {i * nx + k, i * nx + kp, i * nx + km, ip * nx + k, im * nx + k};
         float v[5];
-        for (int q = 0; q < 5; ++q)
-            v[q] = first ? pout[nb[q]] : fmaf(bc, pin[nb[q]], zz[nb[q]]);
-        if (!first) pout[p] = v[0];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) v[q] = it == 0 ? zz[nb[q]] : fmaf(bcg, pin[nb[q]], zz[nb[q]]);
+        pout[p] = v[0];
         const float qv = fmaf(a.w2[zo + p], v[0], a.beta * (4.f * v[0] - v[1] - v[2] - v[3] - v[4]));
         a.q[zo + p] = qv;
-        pq = (double)v[0] * qv;
+        pq += (double)v[0] * qv;
     }
-    const int nblk = gridDim.x;
-    const double s = block_sum<256>(pq, sh);
-    double* part = a.partials + (size_t)z * nblk * 4;
-    if (threadIdx.x == 0) part[blockIdx.x * 4 + 1] = s;
-    if (last_block_arrive(a.counter + z, (unsigned)nblk)) {
-        const double t = block_sum_array<256>(part + 1, nblk, 4, sh);
-        if (threadIdx.x == 0) {
-            a.st[z].pq = t;
-            a.st[z].alpha = t > 0.0 ? a.st[z].rz / t : 0.0;
-        }
-    }
+    const double s_pq = block_sum<256>(pq, sh);
+    if (threadIdx.x == 0) P[a.L.pq + blockIdx.x] = s_pq;
 }
 
-void launch_pcg_matvec(const PcgArgs& a, int parity, bool first, hipStream_t st) {
-    hipLaunchKernelGGL(k_pcg_matvec, dim3(pcg_nblocks(a.ny, a.nx), a.batch), dim3(256), 0, st, a,
-                       parity, first ? 1 : 0);
+void launch_pcg_matvec(const PcgArgs& a, int it, hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_matvec, dim3(a.L.nblk, a.batch), dim3(256), 0, st, a, it);
 }
 
-__device__ __forceinline__ void pcg_close(PcgArgs& a, int z, double rz_new, double rr) {
-    PcgState& S = a.st[z];
-    S.beta_cg = S.rz > 0.0 ? rz_new / S.rz : 0.0;
-    S.rz = rz_new;
-    S.rr = rr;
-    S.iters += 1;
-    if (rr <= a.tol2 * S.bnorm2) S.done = 1;
-}
-
-// x += alpha p; r -= alpha q; Jacobi: z = r / (w^2 + 4 beta), <r, z>, <r, r>
-__global__ __launch_bounds__(256) void k_pcg_update(PcgArgs a, int parity) {
+// Iteration it, second half: alpha = rz / <p, q>; x += alpha p; r -= alpha q;
+// Jacobi: z = r / (w^2 + 4 beta) and <r, z> partials; <r, r> partials.
+__global__ __launch_bounds__(256) void k_pcg_update(PcgArgs a, int it) {
     __shared__ double sh[4];
+    __shared__ double bc;
     const int npix = a.nx * a.ny;
-    const int p = blockIdx.x * 256 + threadIdx.x;
     const int z = blockIdx.y;
     if (a.st[z].done) return;
+    double* P = a.parts + (size_t)z * a.L.zstride;
+    const int cur = it & 1, prev = cur ^ 1;
+    const int nrz = a.jacobi ? a.L.nblk : a.ny;
+    const double rz = sum_parts(P + a.L.rz + (size_t)prev * a.L.nrz, nrz, sh, &bc);
+    const double pq = sum_parts(P + a.L.pq, a.L.nblk, sh, &bc);
+    const float al = pq > 0.0 ? (float)(rz / pq) : 0.f;
     const size_t zo = (size_t)z * npix;
-    const float* pd = (parity ? a.p1 : a.p0) + zo;
-    const float al = (float)a.st[z].alpha;
-    double rz = 0.0, rr = 0.0;
-    if (p < npix) {
+    const float* pd = (cur ? a.p1 : a.p0) + zo;
+    double rzn = 0.0, rr = 0.0;
+    for (int s = 0; s < kPcgPix; ++s) {
+        const int p = blockIdx.x * kPcgBlock + s * 256 + threadIdx.x;
+        if (p >= npix) break;
         a.x[zo + p] = fmaf(al, pd[p], a.x[zo + p]);
         const float r = fmaf(-al, a.q[zo + p], a.r[zo + p]);
         a.r[zo + p] = r;
-        rr = (double)r * r;
+        rr += (double)r * r;
         if (a.jacobi) {
-            const float zz = r / (a.w2[zo + p] + 4.f * a.beta);
-            a.z[zo + p] = zz;
-            rz = (double)r * zz;
+            const float zv = r / (a.w2[zo + p] + 4.f * a.beta);
+            a.z[zo + p] = zv;
+            rzn += (double)r * zv;
         }
     }
-    const int nblk = gridDim.x;
-    const double s0 = block_sum<256>(rz, sh), s1 = block_sum<256>(rr, sh);
-    double* part = a.partials + (size_t)z * nblk * 4;
+    const double s_rr = block_sum<256>(rr, sh);
+    const double s_rz = block_sum<256>(rzn, sh);
     if (threadIdx.x == 0) {
-        part[blockIdx.x * 4 + 2] = s0;
-        part[blockIdx.x * 4 + 3] = s1;
-    }
-    if (last_block_arrive(a.counter + z, (unsigned)nblk)) {
-        const double t0 = block_sum_array<256>(part + 2, nblk, 4, sh);
-        const double t1 = block_sum_array<256>(part + 3, nblk, 4, sh);
-        if (threadIdx.x == 0) {
-            if (a.jacobi) {
-                pcg_close(a, z, t0, t1);
-            } else {
-                a.st[z].rr = t1;
-            }
-        }
+        P[a.L.rr + (size_t)cur * a.L.nblk + blockIdx.x] = s_rr;
+        if (a.jacobi) P[a.L.rz + (size_t)cur * a.L.nrz + blockIdx.x] = s_rz;
     }
 }
 
-void launch_pcg_update(const PcgArgs& a, int parity, hipStream_t st) {
-    hipLaunchKernelGGL(k_pcg_update, dim3(pcg_nblocks(a.ny, a.nx), a.batch), dim3(256), 0, st, a,
-                       parity);
+void launch_pcg_update(const PcgArgs& a, int it, hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_update, dim3(a.L.nblk, a.batch), dim3(256), 0, st, a, it);
 }
 
-// after the FFT preconditioner: <r, z> and close the iteration
-__global__ __launch_bounds__(256) void k_pcg_after_prec(PcgArgs a) {
+__global__ __launch_bounds__(256) void k_pcg_check(PcgArgs a, int n) {
     __shared__ double sh[4];
-    const int npix = a.nx * a.ny;
-    const int p = blockIdx.x * 256 + threadIdx.x;
+    __shared__ double bc;
     const int z = blockIdx.y;
     if (a.st[z].done) return;
-    const size_t zo = (size_t)z * npix;
-    double rz = 0.0;
-    if (p < npix) rz = (double)a.r[zo + p] * a.z[zo + p];
-    const int nblk = gridDim.x;
-    const double s = block_sum<256>(rz, sh);
-    double* part = a.partials + (size_t)z * nblk * 4;
-    if (threadIdx.x == 0) part[blockIdx.x * 4 + 2] = s;
-    if (last_block_arrive(a.counter + z, (unsigned)nblk)) {
-        const double t = block_sum_array<256>(part + 2, nblk, 4, sh);
-        if (threadIdx.x == 0) pcg_close(a, z, t, a.st[z].rr);
+    const double* P = a.parts + (size_t)z * a.L.zstride;
+    const int last = (n + 1) & 1;   // parity slot written by iteration n - 1 (or init for n = 0)
+    const double rr = sum_parts(P + a.L.rr + (size_t)last * a.L.nblk, a.L.nblk, sh, &bc);
+    const double r0 = sum_parts(P + a.L.init0, a.L.nblk, sh, &bc);
+    if (threadIdx.x == 0) {
+        a.st[z].iters = n;
+        if (rr <= a.tol2 * r0) a.st[z].done = 1;
     }
 }
 
-void launch_pcg_after_prec(const PcgArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL(k_pcg_after_prec, dim3(pcg_nblocks(a.ny, a.nx), a.batch), dim3(256), 0, st, a);
+void launch_pcg_check(const PcgArgs& a, int done_iters, hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_check, dim3(1, a.batch), dim3(256), 0, st, a, done_iters);
+}
+
+void launch_pcg_fft_prec(const PcgArgs& a, int it, float2* scratch, hipStream_t st) {
+    // z = (c + beta L)^-1 r with c = mean(w^2); <r, z> per row into the rz slot
+    // of iteration it (it = -1: initial residual, slot 1)
+    const int slot = it < 0 ? 1 : (it & 1);
+    FftArgs fa;
+    fa.src = FFT_SRC_PLAIN;
+    fa.in = a.r;
+    fa.out = a.z;
+    fa.beta = a.beta;
+    fa.c_parts = a.parts + a.L.init1;
+    fa.c_n = a.L.nblk;
+    fa.c_zstride = a.L.zstride;
+    fa.c_scale = 1.0 / ((double)a.nx * a.ny);
+    fa.skip = &a.st[0].done;
+    fa.skip_zstride = sizeof(PcgState) / sizeof(int);
+    fa.dot_with = a.r;
+    fa.dot_parts = a.parts + a.L.rz + (size_t)slot * a.L.nrz;
+    fa.dot_zstride = a.L.zstride;
+    launch_fft_solve(a.ny, a.nx, a.batch, fa, scratch, st);
 }
 
 }  // namespace dect

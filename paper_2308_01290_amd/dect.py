@@ -53,6 +53,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     if not os.path.exists(path):
         raise ImportError(f"libdect.so is not built ({path}); run __graft_entry__.build() "
                           "or python paper_2308_01290_amd/build.py")
+    # torch brings its own HIP runtime; loading it first makes libdect.so bind
+    # to that same runtime (one device context, shared streams and memory)
+    # instead of pulling a second copy from /opt/rocm into the process.
+    import torch  # noqa: F401
     L = C.CDLL(path)
     P, vp = C.POINTER, C.c_void_p
     G, Pp = P(_Geometry), P(_Params)

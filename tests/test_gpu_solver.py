@@ -1,0 +1,241 @@
+"""GPU parity of the gradient-L0 step and of Algorithm 1 (sinogram form)
+against the FP64 oracle, step by step and after the fixed iteration count."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import l0, solve as S
+from oracle.physics import Physics
+from paper_2308_01290_amd import dect
+from paper_2308_01290_amd import phantoms as P
+from tests.gpu_util import cuda, host, rel_inf, workload
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+# after the fixed iteration count (per pixel, on the shared body mask)
+TOL_Z = 0.02
+TOL_RHO = 1e-3
+
+
+def f32(x):
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+# ---------------------------------------------------------------------------
+# gradient-L0 step
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("shape,batch", [((128, 128), 1), ((64, 96), 2), ((512, 512), 1), ((24, 16), 3)])
+@pytest.mark.parametrize("beta", [0.05, 40.0])
+def test_l0_step_fft_matches_oracle(shape, batch, beta):
+    rng = np.random.default_rng(shape[0] + batch)
+    ny, nx = shape
+    clean = np.zeros((batch, ny, nx))
+    clean[:, :, nx // 3: 2 * nx // 3] = 1.0
+    gt = (clean + 0.05 * rng.standard_normal(clean.shape)).astype(np.float32)
+    g0 = (clean + 0.02 * rng.standard_normal(clean.shape)).astype(np.float32)
+    lam = 0.01
+    g_dev = cuda(g0)
+    out, h, v = dect.l0_step(cuda(gt), g_dev, lam, beta, return_hv=True)
+    got, gh, gv = host(out), host(h), host(v)
+    for b in range(batch):
+        ref, rh, rv = l0.l0_step(f32(gt[b]), f32(g0[b]), lam, beta)
+        # the hard-threshold decisions are identical (same FP32 rule on the same inputs)
+        assert np.array_equal((gh[b] != 0) | (gv[b] != 0), (rh != 0) | (rv != 0))
+        assert np.allclose(gh[b], rh, rtol=1e-6, atol=1e-7) and np.allclose(gv[b], rv, rtol=1e-6, atol=1e-7)
+        assert rel_inf(got[b], ref) <= 1e-5, (shape, b)
+
+
+@pytest.mark.parametrize("beta", [0.05, 3.0, 500.0])
+def test_l0_step_weighted_matches_oracle(beta):
+    rng = np.random.default_rng(int(beta * 10))
+    ny, nx = 128, 96
+    w = rng.uniform(0.2, 1.8, (ny, nx)).astype(np.float32)
+    w[:10, :20] = 0.0
+    gt = rng.standard_normal((ny, nx)).astype(np.float32)
+    g0 = (0.1 * rng.standard_normal((ny, nx))).astype(np.float32)
+    lam = 0.01
+    out = host(dect.l0_step(cuda(gt), cuda(g0), lam, beta, weight=cuda(w), tol=1e-7, max_iter=2000))
+    h, v = l0.ht_of(f32(g0), lam, beta)
+    ref, _, res = l0.weighted_solve(f32(w), f32(gt), h, v, beta, x0=f32(g0), rtol=1e-12)
+    assert rel_inf(out, ref) <= 2e-4
+
+
+# ---------------------------------------------------------------------------
+# solver: initialisation, one iteration, full solve
+# ---------------------------------------------------------------------------
+def oracle_params(n_iter):
+    return S.Params(n_iter=n_iter)
+
+
+def lib_params(n_iter, **kw):
+    return dect.default_params(n_iter=n_iter, **kw)
+
+
+def body_mask(rho_ref, rho_got, rho_min=0.1, margin=0.02):
+    return (rho_ref >= rho_min + margin) & (rho_got >= rho_min + margin)
+
+
+def test_init_matches_oracle():
+    g, ph, pL, pH = workload("small")
+    phys = Physics()
+    params = oracle_params(10).resolved(phys, g)
+    st = S.init_state(f32(pL), f32(pH), g, phys, params)
+    sol = dect.Solver(g, lib_params(10)).init(cuda(pL[None]), cuda(pH[None]))
+    f1, f2, rho, t = (host(a)[0] for a in sol.state())
+    assert rel_inf(f1, st.f1) <= 1e-4 and rel_inf(f2, st.f2) <= 1e-4
+    assert rel_inf(rho, st.rho) <= 1e-4
+    m = body_mask(st.rho, rho) & (np.abs(phys.W(*phys.synth(st.f1, st.f2)) / phys.W_water()) > 0.3)
+    assert np.abs(t - st.t)[m].max() <= 1e-2 * max(1.0, np.abs(st.t[m]).max())
+
+
+@pytest.mark.parametrize("k", [0, 7])
+def test_one_iteration_matches_oracle(k):
+    """From an identical FP32 state, one outer iteration (f-step, rho step,
+    t' step, beta update) on the GPU equals the oracle's."""
+    g, ph, pL, pH = workload("small")
+    phys = Physics()
+    params = oracle_params(10).resolved(phys, g)
+    st0 = S.init_state(f32(pL), f32(pH), g, phys, params)
+    beta = params.beta0
+    for _ in range(k):
+        beta *= params.kappa
+    st0 = S.State(f32(st0.f1), f32(st0.f2), f32(st0.rho), f32(st0.t), beta, k)
+    ref = S.iterate(st0, f32(pL), f32(pH), g, phys, params)
+    sol = dect.Solver(g, lib_params(10))
+    sol.set_state(cuda(pL[None]), cuda(pH[None]), cuda(st0.f1[None]), cuda(st0.f2[None]),
+                  cuda(st0.rho[None]), cuda(st0.t[None]), k=k)
+    sol.iterate(1)
+    f1, f2, rho, t = (host(a)[0] for a in sol.state())
+    assert rel_inf(f1, ref.f1) <= 1e-5 and rel_inf(f2, ref.f2) <= 1e-5
+    assert rel_inf(rho, ref.rho) <= 1e-5
+    m = body_mask(ref.rho, rho)
+    assert np.abs(t - ref.t)[m].max() <= 2e-3 * max(1.0, np.abs(ref.t[m]).max())
+
+
+def phantom_body(ph, g, erode=2):
+    from scipy.ndimage import binary_erosion
+    lab = P.label_map(ph, g)
+    return lab, binary_erosion(lab[1:].sum(0) > 0.999, iterations=erode)
+
+
+def test_lockstep_small_all_iterations():
+    """Every outer iteration of the oracle's own trajectory, replayed on the GPU
+    from the oracle's FP32-rounded state, agrees to FP32 precision (f, rho_e)
+    and to the PCG tolerance (t')."""
+    g, ph, pL, pH = workload("small")
+    phys = Physics()
+    params = oracle_params(10).resolved(phys, g)
+    _, body = phantom_body(ph, g)
+    st = S.init_state(f32(pL), f32(pH), g, phys, params)
+    lo, hi = cuda(pL[None]), cuda(pH[None])
+    for k in range(params.n_iter):
+        s32 = S.State(f32(st.f1), f32(st.f2), f32(st.rho), f32(st.t), st.beta, k)
+        ref = S.iterate(s32, f32(pL), f32(pH), g, phys, params)
+        sol = dect.Solver(g, lib_params(params.n_iter)).set_state(
+            lo, hi, *(cuda(a[None]) for a in (s32.f1, s32.f2, s32.rho, s32.t)), k=k)
+        sol.iterate(1)
+        f1, f2, rho, t = (host(a)[0] for a in sol.state())
+        assert rel_inf(f1, ref.f1) <= 1e-5 and rel_inf(f2, ref.f2) <= 1e-5, k
+        assert rel_inf(rho, ref.rho) <= 1e-5, k
+        assert np.abs(t - ref.t)[body].max() <= 5e-4 * max(1.0, np.abs(ref.t[body]).max()), k
+        st = ref
+
+
+def check_end_to_end(Z, R, Zr, Rr, ph, g, tag, max_rho_violation_frac):
+    """Spec tolerances: |dZ| <= 0.02 and rel(rho_e) <= 1e-3.  Checked on
+    each insert's mean (eroded by 2 pixels), and pointwise on the eroded body:
+    Z where Z >= 2 in both (Z = Zw t'^(1/m) is unbounded in slope as t' -> 0,
+    which holds only noise outliers), rho_e everywhere, allowing the stated
+    fraction of isolated hard-threshold flips (the method is discontinuous:
+    the FP64 oracle itself moves that many pixels under 1e-6 input changes)."""
+    from scipy.ndimage import binary_erosion
+    lab, body = phantom_body(ph, g)
+    for idx, e in enumerate(ph.ellipses()):
+        mm = binary_erosion(lab[idx + 1] > 0.999, iterations=2)
+        if mm.sum() < 4:
+            continue
+        assert abs(Z[mm].mean() - Zr[mm].mean()) <= TOL_Z, (tag, idx)
+        assert abs(R[mm].mean() - Rr[mm].mean()) <= TOL_RHO * abs(Rr[mm].mean()), (tag, idx)
+    mz = body & (Zr >= 2.0) & (Z >= 2.0)
+    dz = np.abs(Z - Zr)[mz]
+    dr = (np.abs(R - Rr) / np.abs(Rr))[body]
+    nbad = int((dr > TOL_RHO).sum())
+    print(f"{tag}: max|dZ|(Z>=2)={dz.max():.3g} p99={np.quantile(dz, 0.99):.3g}; "
+          f"rel rho max={dr.max():.3g} p99={np.quantile(dr, 0.99):.3g} over {nbad}/{body.sum()}")
+    assert mz.sum() > 0.5 * body.sum()
+    assert dz.max() <= TOL_Z
+    assert nbad <= max_rho_violation_frac * body.sum()
+
+
+def test_full_solve_small_matches_oracle():
+    g, ph, pL, pH = workload("small")
+    phys = Physics()
+    Zr, Rr = S.solve(f32(pL), f32(pH), g, phys, oracle_params(10))
+    sol = dect.Solver(g, lib_params(10)).init(cuda(pL[None]), cuda(pH[None]))
+    iters = []
+    for _ in range(10):
+        sol.iterate(1)
+        iters.append(sol.stats()[1])
+    Z, R = (host(x)[0] for x in sol.finish())
+    print(f"small K=10 pcg iterations {iters}")
+    check_end_to_end(Z, R, Zr, Rr, ph, g, "small K=10", 0.0)
+
+
+def test_solver_batch_equals_single():
+    """A slice solved alone equals the same slice inside a batch (bitwise:
+    reductions are per slice and in a fixed order)."""
+    g, ph, pL, pH = workload("small")
+    lo = np.stack([pL, pL * 0.9, pL])
+    hi = np.stack([pH, pH * 0.9, pH])
+    Zb, Rb = dect.solve(cuda(lo), cuda(hi), g, lib_params(4))
+    Z1, R1 = dect.solve(cuda(pL[None]), cuda(pH[None]), g, lib_params(4))
+    Zb, Rb, Z1, R1 = host(Zb), host(Rb), host(Z1), host(R1)
+    assert np.array_equal(Zb[0], Z1[0]) and np.array_equal(Rb[0], R1[0])
+    assert np.array_equal(Zb[2], Z1[0])
+
+
+def test_solver_is_deterministic_and_resumable():
+    g, ph, pL, pH = workload("small")
+    lo, hi = cuda(pL[None]), cuda(pH[None])
+    a = dect.Solver(g, lib_params(6)).init(lo, hi).iterate(6)
+    Za, Ra = (host(x) for x in a.finish())
+    b = dect.Solver(g, lib_params(6)).init(lo, hi).iterate(2)
+    f1, f2, rho, t = b.state()
+    c = dect.Solver(g, lib_params(6)).set_state(lo, hi, f1, f2, rho, t, k=2).iterate(4)
+    Zc, Rc = (host(x) for x in c.finish())
+    assert np.array_equal(Za, host(dect.Solver(g, lib_params(6)).init(lo, hi).iterate(6).finish()[0]))
+    # resume: the residual sinograms are recomputed from the state, so agreement
+    # is to FP32 rounding rather than bitwise
+    m = Ra[0] > 0.2
+    assert np.abs(Zc - Za)[0][m].max() <= 1e-2 and np.abs(Rc - Ra)[0][m].max() <= 1e-4
+
+
+def test_full_solve_slice512_matches_stored_oracle():
+    """512^2 / 720 / 736 slice, 50 iterations, against the stored oracle result
+    written by tests/golden/make_golden.py (oracle only)."""
+    gold = np.load(os.path.join(HERE, "golden", "slice512_K50.npz"))
+    g, ph, pL, pH = workload("slice512")
+    Z, R = dect.solve(cuda(pL[None]), cuda(pH[None]), g, lib_params(50))
+    Z, R = host(Z)[0], host(R)[0]
+    check_end_to_end(Z, R, gold["Z"].astype(np.float64), gold["rho"].astype(np.float64), ph, g,
+                     "slice512 K=50", 1e-4)
+
+
+def test_lockstep_slice512_first_iteration():
+    g, ph, pL, pH = workload("slice512")
+    phys = Physics()
+    params = oracle_params(50).resolved(phys, g)
+    st = S.init_state(f32(pL), f32(pH), g, phys, params)
+    s32 = S.State(f32(st.f1), f32(st.f2), f32(st.rho), f32(st.t), st.beta, 0)
+    ref = S.iterate(s32, f32(pL), f32(pH), g, phys, params, nthreads=None)
+    sol = dect.Solver(g, lib_params(50)).set_state(
+        cuda(pL[None]), cuda(pH[None]), *(cuda(a[None]) for a in (s32.f1, s32.f2, s32.rho, s32.t)), k=0)
+    sol.iterate(1)
+    f1, f2, rho, t = (host(a)[0] for a in sol.state())
+    _, body = phantom_body(ph, g)
+    assert rel_inf(f1, ref.f1) <= 1e-5 and rel_inf(f2, ref.f2) <= 1e-5
+    assert rel_inf(rho, ref.rho) <= 1e-5
+    assert np.abs(t - ref.t)[body].max() <= 5e-4 * max(1.0, np.abs(ref.t[body]).max())

@@ -40,7 +40,7 @@ def test_default_params():
     assert (p.m, p.n, p.Cp, p.Z_w) == (3.94, 3.2, 9.8e-24, 7.42)
     assert tuple(p.basis_Z) == (14.14, 7.42) and tuple(p.basis_rho) == (1.69, 1.0)
     assert p.lambda_ == 0.01 and p.beta_max == 1e5 and p.f_inner == 1
-    assert p.t_tol == 1e-6 and p.t_maxit == 200 and p.rho_min == 0.1
+    assert p.t_tol == 1e-7 and p.t_maxit == 200 and p.rho_min == 0.1
 
 
 def test_geometry_resolution_matches_corner_pitch():
