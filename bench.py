@@ -1,0 +1,180 @@
+#!/usr/bin/env python3
+"""Benchmark: whole-slice solves per second on the 512^2 slice.
+
+Workload: 512x512 image at 0.8 mm, 720 views over 360 deg, 736 detector bins,
+SID 1000 mm, SDD 1500 mm, dual-energy sinograms of an elliptical water body
+with 40 bone / soft-tissue / lung inserts, Poisson noise 5e4 / 1e5, 50 outer
+iterations of the sinogram-form Algorithm 1.  A step is one whole solve of one
+slice (FBP start, 50 iterations, output maps) with the sinograms already in
+HBM.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+N_ITER = 50
+PEAK_FP32_TFLOPS = 157.3      # MI355X dense FP32 vector (published)
+PEAK_HBM_GBS = 8000.0
+
+
+def count_nonzeros(g) -> int:
+    """Nonzeros of the system matrix: ray-pixel intersections, counted as
+    (grid lines crossed inside the image) + 1 per ray that meets the image."""
+    from paper_2308_01290_amd import phantoms as P
+    src, dst = P.ray_endpoints(g)
+    S = np.broadcast_to(src[:, None, :], dst.shape).reshape(-1, 2)
+    d = dst.reshape(-1, 2) - S
+    half = np.array([g.n_x, g.n_y]) * g.pixel_mm / 2
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ta = (-half[None, :] - S) / d
+        tb = (half[None, :] - S) / d
+    t0 = np.max(np.minimum(ta, tb), axis=1)
+    t1 = np.min(np.maximum(ta, tb), axis=1)
+    hit = t1 > t0
+    total = 0
+    for a, n in ((0, g.n_x), (1, g.n_y)):
+        c0 = (S[:, a] + t0 * d[:, a] + half[a]) / g.pixel_mm
+        c1 = (S[:, a] + t1 * d[:, a] + half[a]) / g.pixel_mm
+        lo, hi = np.minimum(c0, c1), np.maximum(c0, c1)
+        cross = np.clip(np.ceil(hi) - 1, 0, n) - np.clip(np.floor(lo) + 1, 0, n) + 1
+        total += int(np.sum(np.where(hit, np.maximum(cross, 0), 0)))
+    return total + int(hit.sum())
+
+
+def cpu_baseline(g, pL, pH, iters: int):
+    """The FP64 oracle (as it stands) on the host cores: FBP start plus `iters`
+    outer iterations, extrapolated to the 50-iteration solve."""
+    from oracle import solve as S
+    from oracle.physics import Physics
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    phys = Physics()
+    params = S.Params(n_iter=N_ITER).resolved(phys, g)
+    a = pL.astype(np.float64)
+    b = pH.astype(np.float64)
+    t0 = time.perf_counter()
+    st = S.init_state(a, b, g, phys, params, nthreads=threads)
+    t1 = time.perf_counter()
+    for _ in range(iters):
+        st = S.iterate(st, a, b, g, phys, params, nthreads=threads)
+    t2 = time.perf_counter()
+    per_slice = (t1 - t0) + N_ITER * (t2 - t1) / iters
+    return {"value": 1.0 / per_slice, "unit": "slices/s", "cores": threads, "kind": "oracle",
+            "sample": f"FBP start + {iters} of {N_ITER} outer iterations on the same 512^2 slice "
+                      f"({t2 - t0:.1f} s), extrapolated to {N_ITER} iterations "
+                      f"({per_slice:.1f} s per slice)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=2)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "slices are independent solves, so more GPUs would each take whole slices",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2308_01290_amd import dect
+    from paper_2308_01290_amd import phantoms as P
+
+    params = dect.default_params(n_iter=N_ITER)
+    g, ph, pL, pH = P.workload_slice512(lambda Z, R: dect.attenuation(params, Z, R))
+    pL = pL.astype(np.float32)
+    pH = pH.astype(np.float32)
+    dev = torch.device("cuda:0")
+    lo = torch.as_tensor(pL[None], device=dev)
+    hi = torch.as_tensor(pH[None], device=dev)
+    sol = dect.Solver(g, params, batch=1)
+    Z = torch.empty((1, g.n_y, g.n_x), device=dev)
+    R = torch.empty_like(Z)
+
+    def step():
+        sol.init(lo, hi)
+        sol.iterate(N_ITER)
+        dect._check(dect.lib().dect_solver_finish(sol._h, dect._ptr(Z), dect._ptr(R)), "finish")
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    sol.enable_timing(True)
+    sol.timing()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    bp_ms, bp_n, fp_ms, fp_n = sol.timing()
+    sol.enable_timing(False)
+
+    elapsed = t1 - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = args.steps / elapsed
+    nnz = count_nonzeros(g)
+    bp_avg_s = bp_ms / max(bp_n, 1) / 1e3
+    fp_avg_s = fp_ms / max(fp_n, 1) / 1e3
+    # algorithmic work of one back-projection launch: both channels of the
+    # sparse transpose product, one multiply-add per nonzero and channel
+    bp_flops = 2 * 2 * nnz
+    achieved = bp_flops / bp_avg_s / 1e12
+    nray = g.n_views * g.n_det
+    npix = g.n_x * g.n_y
+    bp_bytes = nray * 8 + npix * 8
+    fp_bytes = npix * 8 + nray * 8
+    out = {
+        "metric": "512^2 slices/s (720 views, 50 iters)",
+        "value": value,
+        "unit": "slices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "512x512 slice at 0.8 mm, 720 views, 736 bins, SID 1000 / SDD 1500 mm, "
+                               "water body + 40 inserts, Poisson 5e4/1e5, 50 outer iterations",
+                   "image": [g.n_y, g.n_x], "views": g.n_views, "bins": g.n_det,
+                   "iterations": N_ITER, "slices_per_solve": 1},
+        "rays_per_s": 4.0 * nray * N_ITER * value,
+        "projector": {
+            "system_matrix_nonzeros": nnz,
+            "backproject_ms": 1e3 * bp_avg_s,
+            "project_ms": 1e3 * fp_avg_s,
+            "backproject_visits_per_s": 2 * nnz / bp_avg_s,
+            "project_visits_per_s": 2 * nnz / fp_avg_s,
+            "backproject_algorithmic_hbm_gbs": bp_bytes / bp_avg_s / 1e9,
+            "project_algorithmic_hbm_gbs": fp_bytes / fp_avg_s / 1e9,
+        },
+        "roofline": {"kernel": "k_backproject", "bound": "alu", "achieved": achieved,
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(g, pL, pH, args.cpu_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -204,6 +204,15 @@ int dect_solver_finish(dect_solver* s, float* Z, float* rho_e);
  * t' step (HOST query; synchronises the solver's stream). */
 int dect_solver_stats(const dect_solver* s, int32_t* k, int32_t* last_pcg_iters);
 
+/* Optional timing of the two system-matrix kernels: when enabled, the solver
+ * records HIP events on its stream around every back-projection and forward
+ * projection launch of the outer iterations.  dect_solver_timing synchronises
+ * the stream, returns the summed durations (ms) and launch counts since the
+ * last call, and resets them.  Any output pointer may be NULL. */
+int dect_solver_enable_timing(dect_solver* s, int enable);
+int dect_solver_timing(dect_solver* s, double* backproject_ms, int32_t* backproject_launches,
+                       double* project_ms, int32_t* project_launches);
+
 /* Whole solve: create, init, n_iter iterations, finish, destroy. */
 int dect_solve(const float* sino_lo, const float* sino_hi, const dect_geometry* g,
                const dect_params* p, float* Z_out, float* rho_out, int32_t batch, void* ws,

@@ -326,7 +326,7 @@ static void fill_pcg_args(PcgArgs* a, const PcgBufs& b, int ny, int nx, int batc
     a->st = b.st;
 }
 
-static const double kJacobiBelow = 1.0;   // beta below which Jacobi beats the FFT preconditioner
+static const double kJacobiBelow = 1.5;   // beta below which Jacobi PCG is cheaper than scaled-FFT PCG
 
 // Runs PCG iterations (after an init kernel) until every slice converged or
 // max_iter.  The host checks convergence once per chunk of iterations; the
@@ -383,7 +383,40 @@ struct dect_solver {
     int k;
     double beta;
     int last_pcg;
+    // optional kernel timing: event pairs in launch order
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_bp, ev_fp;
 };
+
+static hipEvent_t take_event(dect_solver* s) {
+    hipEvent_t e = nullptr;
+    if (!s->ev_pool.empty()) {
+        e = s->ev_pool.back();
+        s->ev_pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        e = nullptr;
+    }
+    return e;
+}
+
+// record a start event (returns nullptr when timing is off)
+static hipEvent_t mark(dect_solver* s) {
+    if (!s->timing) return nullptr;
+    hipEvent_t e = take_event(s);
+    if (e) (void)hipEventRecord(e, s->st);
+    return e;
+}
+static void mark_end(dect_solver* s, hipEvent_t start, std::vector<std::pair<hipEvent_t, hipEvent_t>>& v) {
+    if (!start) return;
+    hipEvent_t e = take_event(s);
+    if (!e) {
+        s->ev_pool.push_back(start);
+        return;
+    }
+    (void)hipEventRecord(e, s->st);
+    v.emplace_back(start, e);
+}
 
 extern "C" {
 
@@ -672,6 +705,16 @@ int dect_solver_create(const dect_geometry* gin, const dect_params* p, int32_t b
 
 int dect_solver_destroy(dect_solver* s) {
     if (!s) return DECT_OK;
+    if (!s->ev_bp.empty() || !s->ev_fp.empty()) (void)hipStreamSynchronize(s->st);
+    for (auto& p : s->ev_bp) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    for (auto& p : s->ev_fp) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
     if (s->owns_ws) dev_free(&s->own);
     delete s;
     return DECT_OK;
@@ -736,7 +779,9 @@ static int one_iteration(dect_solver* s) {
     a.thr = (float)(R.p.lambda / beta);
     a.beta = (float)beta;
     // f-step: A^T of the combined residuals, gradient, A of the direction
+    hipEvent_t t0 = mark(s);
     launch_backproject(g, s->tab, s->S, s->batch, s->B, nullptr, 0, s->st);
+    mark_end(s, t0, s->ev_bp);
     launch_grad(s->M, a, s->f, s->B, s->rho, s->t, s->dN, s->dT, s->part_img, s->st);
     ProjArgs pa;
     pa.res = s->zq;
@@ -752,7 +797,9 @@ static int one_iteration(dect_solver* s) {
     pa.w_reg = 2.0 * beta;
     pa.alpha = s->alpha;
     pa.counter = s->cnt_proj;
+    hipEvent_t t1 = mark(s);
     launch_project(g, s->tab, s->dN, s->dT, s->batch, PROJ_LINESEARCH, pa, s->st);
+    mark_end(s, t1, s->ev_fp);
     // rho_e step (reads f^(k), rho^(k))
     FftArgs fa;
     fa.src = FFT_SRC_RHO;
@@ -821,6 +868,33 @@ int dect_solver_stats(const dect_solver* s, int32_t* k, int32_t* last_pcg_iters)
     if (k) *k = s->k;
     if (last_pcg_iters) *last_pcg_iters = s->last_pcg;
     return DECT_OK;
+}
+
+int dect_solver_enable_timing(dect_solver* s, int enable) {
+    if (!s) return fail(DECT_EINVAL, "solver is NULL");
+    s->timing = enable != 0;
+    return DECT_OK;
+}
+
+int dect_solver_timing(dect_solver* s, double* bp_ms, int32_t* bp_n, double* fp_ms, int32_t* fp_n) {
+    if (!s) return fail(DECT_EINVAL, "solver is NULL");
+    DECT_HIP(hipStreamSynchronize(s->st));
+    auto sum = [s](std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, double* ms, int32_t* n) -> int {
+        double tot = 0.0;
+        for (auto& p : v) {
+            float e = 0.f;
+            DECT_HIP(hipEventElapsedTime(&e, p.first, p.second));
+            tot += e;
+            s->ev_pool.push_back(p.first);
+            s->ev_pool.push_back(p.second);
+        }
+        if (ms) *ms = tot;
+        if (n) *n = (int32_t)v.size();
+        v.clear();
+        return DECT_OK;
+    };
+    if (int rc = sum(s->ev_bp, bp_ms, bp_n)) return rc;
+    return sum(s->ev_fp, fp_ms, fp_n);
 }
 
 int dect_solve(const float* lo, const float* hi, const dect_geometry* g, const dect_params* p,

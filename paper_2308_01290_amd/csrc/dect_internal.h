@@ -127,6 +127,10 @@ struct FftArgs {
     float beta = 0, thr = 0;
     double c = 1.0;                   // diagonal shift, or from partial sums:
     const double* c_parts = nullptr;  //   c = c_scale * sum(c_parts[z*c_zstride + 0..c_n))
+    // PLAIN: symmetric diagonal scaling s = sqrt((c + 4 beta) / (w2 + 4 beta)),
+    // out = s (c + beta L)^-1 (s in): Jacobi-like where beta is small, the
+    // plain FFT inverse where it is large
+    const float* scale_w2 = nullptr;
     int c_n = 0;
     size_t c_zstride = 0;
     double c_scale = 0.0;

@@ -41,6 +41,28 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return r;
 }
 
+// Sums of N values per thread over a 1-D block of NT threads in one LDS
+// round, fixed order; results broadcast to every thread.  `sh` holds
+// N * NT/64 doubles of LDS.
+template <int NT, int N>
+__device__ __forceinline__ void block_sum_n(double (&v)[N], double* sh) {
+    const int w = threadIdx.x / kWave;
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+        const double t = wave_sum(v[c]);
+        if ((threadIdx.x % kWave) == 0) sh[c * (NT / kWave) + w] = t;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+        double r = 0.0;
+#pragma unroll
+        for (int i = 0; i < NT / kWave; ++i) r += sh[c * (NT / kWave) + i];
+        v[c] = r;
+    }
+    __syncthreads();
+}
+
 // Called by every thread of a block after thread 0 stored the block's
 // partials.  Returns true in every thread of the last block to arrive; its
 // loads after this call see all blocks' partials.  The last block resets the

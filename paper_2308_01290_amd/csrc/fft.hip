@@ -52,12 +52,12 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// tw[e] = exp(-2 pi i e / n)
+// tw[e] = exp(-2 pi i e / n); 2e/n is exact in FP32 for n <= 1024
 __device__ void fill_twiddles(float2* tw, int n) {
     for (int e = threadIdx.x; e < n; e += blockDim.x) {
-        double s, c;
-        sincospi(-2.0 * (double)e / (double)n, &s, &c);
-        tw[e] = make_float2((float)c, (float)s);
+        float s, c;
+        sincospif(-2.0f * (float)e / (float)n, &s, &c);
+        tw[e] = make_float2(c, s);
     }
 }
 
@@ -145,6 +145,19 @@ __device__ __forceinline__ bool skip_slice(const FftArgs& a, int z) {
     return a.skip && a.skip[(size_t)z * a.skip_zstride];
 }
 
+// diagonal shift c of slice z (all threads; uses LDS and barriers)
+__device__ float shift_of(const FftArgs& a, int z) {
+    __shared__ double shs[4];
+    if (!a.c_parts) return (float)a.c;
+    const double s = block_sum_array<256>(a.c_parts + (size_t)z * a.c_zstride, a.c_n, 1, shs);
+    __shared__ float bc;
+    if (threadIdx.x == 0) bc = (float)fmax(a.c_scale * s, 1e-12);
+    __syncthreads();
+    const float r = bc;
+    __syncthreads();
+    return r;
+}
+
 __global__ __launch_bounds__(256) void k_fft_rows_fwd(FftPlan P, int ny, FftArgs a,
                                                       float2* __restrict__ scratch) {
     extern __shared__ float2 sm2[];
@@ -158,8 +171,13 @@ __global__ __launch_bounds__(256) void k_fft_rows_fwd(FftPlan P, int ny, FftArgs
     const size_t npix = (size_t)nx * ny;
     fill_twiddles(tw, nx);
     if (a.src == FFT_SRC_PLAIN) {
-        for (int k = threadIdx.x; k < nx; k += blockDim.x)
-            A[k] = make_float2(a.in[z * npix + (size_t)i * nx + k], 0.f);
+        const float cz = a.scale_w2 ? shift_of(a, z) : 0.f;
+        for (int k = threadIdx.x; k < nx; k += blockDim.x) {
+            const size_t q = z * npix + (size_t)i * nx + k;
+            float v = a.in[q];
+            if (a.scale_w2) v *= sqrtf((cz + 4.f * a.beta) / (a.scale_w2[q] + 4.f * a.beta));
+            A[k] = make_float2(v, 0.f);
+        }
     } else {
         const int im = (i == 0) ? ny - 1 : i - 1, ip = (i + 1 == ny) ? 0 : i + 1;
         for (int k = threadIdx.x; k < nx; k += blockDim.x) {
@@ -212,20 +230,18 @@ __global__ __launch_bounds__(256) void k_fft_cols(FftPlan P, int nx, int cols, F
     const int c0 = blockIdx.x * cols, z = blockIdx.y;
     if (skip_slice(a, z)) return;
     const size_t npix = (size_t)nx * ny;
-    if (a.c_parts) {
-        const double s = block_sum_array<256>(a.c_parts + (size_t)z * a.c_zstride, a.c_n, 1, sh);
-        if (threadIdx.x == 0) cz_sh = (float)fmax(a.c_scale * s, 1e-12);
-    } else if (threadIdx.x == 0) {
-        cz_sh = (float)a.c;
+    {
+        const float c = shift_of(a, z);
+        if (threadIdx.x == 0) cz_sh = c;
     }
     fill_twiddles(tw, ny);
     for (int e = threadIdx.x; e < ny; e += blockDim.x) {
-        const double s = sinpi((double)e / (double)ny);
-        lamy[e] = (float)(4.0 * s * s);
+        const float s = sinpif((float)e / (float)ny);
+        lamy[e] = 4.0f * s * s;
     }
     for (int c = threadIdx.x; c < cols; c += blockDim.x) {
-        const double s = sinpi((double)(c0 + c) / (double)nx);
-        lamx[c] = (float)(4.0 * s * s);
+        const float s = sinpif((float)(c0 + c) / (float)nx);
+        lamx[c] = 4.0f * s * s;
     }
     for (int idx = threadIdx.x; idx < ny * cols; idx += blockDim.x) {
         const int e = idx / cols, c = idx - (idx / cols) * cols;
@@ -265,10 +281,12 @@ __global__ __launch_bounds__(256) void k_fft_rows_inv(FftPlan P, int ny, FftArgs
     const float2* R = fft_lds<true>(A, B, tw, P, 1);
     const float sc = (float)(1.0 / ((double)nx * (double)ny));
     const bool corr = a.src != FFT_SRC_PLAIN;
+    const float cz = a.scale_w2 ? shift_of(a, z) : 0.f;
     double dot = 0.0;
     for (int k = threadIdx.x; k < nx; k += blockDim.x) {
         const size_t q = z * npix + (size_t)i * nx + k;
-        const float d = R[k].x * sc;
+        float d = R[k].x * sc;
+        if (a.scale_w2) d *= sqrtf((cz + 4.f * a.beta) / (a.scale_w2[q] + 4.f * a.beta));
         const float v = corr ? a.base[q] + d : d;
         a.out[q] = v;
         if (a.dot_with) dot += (double)v * (double)a.dot_with[q];

@@ -389,16 +389,30 @@ void launch_pcg_init_plain(const PcgArgs& a, const float* w, const float* g_tild
 // q = A p, <p, q> partials.
 __global__ __launch_bounds__(256) void k_pcg_matvec(PcgArgs a, int it) {
     __shared__ double sh[4];
-    __shared__ double bc;
+    __shared__ double shn[16];
     const int nx = a.nx, ny = a.ny, npix = nx * ny;
     const int z = blockIdx.y;
     if (a.st[z].done) return;
     double* P = a.parts + (size_t)z * a.L.zstride;
     const int cur = it & 1, prev = cur ^ 1;
     const int nrz = a.jacobi ? a.L.nblk : a.ny;
-    const double rz_new = sum_parts(P + a.L.rz + (size_t)prev * a.L.nrz, nrz, sh, &bc);
-    const double rr = sum_parts(P + a.L.rr + (size_t)prev * a.L.nblk, a.L.nblk, sh, &bc);
-    const double r0 = sum_parts(P + a.L.init0, a.L.nblk, sh, &bc);
+    double v[4] = {0.0, 0.0, 0.0, 0.0};   // rz_new, rr, r0^2, rz_old
+    {
+        const double* rzn = P + a.L.rz + (size_t)prev * a.L.nrz;
+        const double* rzo = P + a.L.rz + (size_t)cur * a.L.nrz;
+        const double* rrp = P + a.L.rr + (size_t)prev * a.L.nblk;
+        const double* r0p = P + a.L.init0;
+        for (int t = threadIdx.x; t < nrz; t += 256) {
+            v[0] += rzn[t];
+            if (it > 0) v[3] += rzo[t];
+        }
+        for (int t = threadIdx.x; t < a.L.nblk; t += 256) {
+            v[1] += rrp[t];
+            v[2] += r0p[t];
+        }
+    }
+    block_sum_n<256, 4>(v, shn);
+    const double rz_new = v[0], rr = v[1], r0 = v[2];
     if (rr <= a.tol2 * r0) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             a.st[z].done = 1;
@@ -407,10 +421,7 @@ __global__ __launch_bounds__(256) void k_pcg_matvec(PcgArgs a, int it) {
         return;
     }
     float bcg = 0.f;
-    if (it > 0) {
-        const double rz_old = sum_parts(P + a.L.rz + (size_t)cur * a.L.nrz, nrz, sh, &bc);
-        bcg = rz_old > 0.0 ? (float)(rz_new / rz_old) : 0.f;
-    }
+    if (it > 0) bcg = v[3] > 0.0 ? (float)(rz_new / v[3]) : 0.f;
     const size_t zo = (size_t)z * npix;
     float* pout = (cur ? a.p1 : a.p0) + zo;
     const float* pin = (cur ? a.p0 : a.p1) + zo;
@@ -443,16 +454,18 @@ void launch_pcg_matvec(const PcgArgs& a, int it, hipStream_t st) {
 // Jacobi: z = r / (w^2 + 4 beta) and <r, z> partials; <r, r> partials.
 __global__ __launch_bounds__(256) void k_pcg_update(PcgArgs a, int it) {
     __shared__ double sh[4];
-    __shared__ double bc;
+    __shared__ double shn[8];
     const int npix = a.nx * a.ny;
     const int z = blockIdx.y;
     if (a.st[z].done) return;
     double* P = a.parts + (size_t)z * a.L.zstride;
     const int cur = it & 1, prev = cur ^ 1;
     const int nrz = a.jacobi ? a.L.nblk : a.ny;
-    const double rz = sum_parts(P + a.L.rz + (size_t)prev * a.L.nrz, nrz, sh, &bc);
-    const double pq = sum_parts(P + a.L.pq, a.L.nblk, sh, &bc);
-    const float al = pq > 0.0 ? (float)(rz / pq) : 0.f;
+    double v[2] = {0.0, 0.0};   // rz, <p, q>
+    for (int t = threadIdx.x; t < nrz; t += 256) v[0] += P[a.L.rz + (size_t)prev * a.L.nrz + t];
+    for (int t = threadIdx.x; t < a.L.nblk; t += 256) v[1] += P[a.L.pq + t];
+    block_sum_n<256, 2>(v, shn);
+    const float al = v[1] > 0.0 ? (float)(v[0] / v[1]) : 0.f;
     const size_t zo = (size_t)z * npix;
     const float* pd = (cur ? a.p1 : a.p0) + zo;
     double rzn = 0.0, rr = 0.0;
@@ -515,6 +528,7 @@ void launch_pcg_fft_prec(const PcgArgs& a, int it, float2* scratch, hipStream_t 
     fa.c_scale = 1.0 / ((double)a.nx * a.ny);
     fa.skip = &a.st[0].done;
     fa.skip_zstride = sizeof(PcgState) / sizeof(int);
+    fa.scale_w2 = a.w2;
     fa.dot_with = a.r;
     fa.dot_parts = a.parts + a.L.rz + (size_t)slot * a.L.nrz;
     fa.dot_zstride = a.L.zstride;

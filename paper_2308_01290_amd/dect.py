@@ -45,7 +45,8 @@ EXPORTS = [
     "dect_backproject", "dect_fbp", "dect_l0_step_workspace_bytes", "dect_l0_step",
     "dect_solve_workspace_bytes", "dect_solver_create", "dect_solver_destroy", "dect_solver_init",
     "dect_solver_set_state", "dect_solver_iterate", "dect_solver_get_state", "dect_solver_finish",
-    "dect_solver_stats", "dect_solve", "dect_last_error",
+    "dect_solver_stats", "dect_solver_enable_timing", "dect_solver_timing", "dect_solve",
+    "dect_last_error",
 ]
 
 
@@ -80,6 +81,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.dect_solver_get_state.argtypes = [vp, vp, vp, vp, vp]
     L.dect_solver_finish.argtypes = [vp, vp, vp]
     L.dect_solver_stats.argtypes = [vp, P(C.c_int32), P(C.c_int32)]
+    L.dect_solver_enable_timing.argtypes = [vp, C.c_int]
+    L.dect_solver_timing.argtypes = [vp, P(C.c_double), P(C.c_int32), P(C.c_double), P(C.c_int32)]
     L.dect_solve.argtypes = [vp, vp, G, Pp, vp, vp, C.c_int32, vp, C.c_size_t, vp]
     L.dect_last_error.argtypes = []
     L.dect_last_error.restype = C.c_char_p
@@ -331,6 +334,18 @@ class Solver:
         Z, rho = self._img(), self._img()
         _check(lib().dect_solver_finish(self._h, _ptr(Z), _ptr(rho)), "dect_solver_finish")
         return Z, rho
+
+    def enable_timing(self, on: bool = True):
+        _check(lib().dect_solver_enable_timing(self._h, 1 if on else 0), "dect_solver_enable_timing")
+        return self
+
+    def timing(self):
+        """(backproject_ms, n_bp, project_ms, n_fp) since the last call (synchronises)."""
+        bms, fms = C.c_double(), C.c_double()
+        bn, fn = C.c_int32(), C.c_int32()
+        _check(lib().dect_solver_timing(self._h, C.byref(bms), C.byref(bn), C.byref(fms), C.byref(fn)),
+               "dect_solver_timing")
+        return bms.value, bn.value, fms.value, fn.value
 
     def stats(self):
         k = C.c_int32()
