@@ -93,7 +93,12 @@ typedef struct dect_geometry {
  *                        ill-conditioned where t' is small, which is what
  *                        sets this tolerance
  *   rho_min, t_min       output mask: Z = 0 where rho_e < rho_min; t' clamp
- *                        (0.1, 1e-6) */
+ *                        (0.1, 1e-6)
+ *   t_precond            preconditioner of the Z^m PCG, a DECT_PRECOND_*
+ *                        value (DECT_PRECOND_AUTO: the multigrid V-cycle
+ *                        where the image sizes admit it, else Jacobi below
+ *                        beta = 1.5 and the scaled FFT inverse above).  The
+ *                        choice changes the iterate only within t_tol. */
 typedef struct dect_params {
     double E_lo_keV, E_hi_keV, E1_keV, E2_keV;
     double m, n, Cp, Z_w;
@@ -104,7 +109,19 @@ typedef struct dect_params {
     double t_tol;
     int32_t t_maxit;
     double rho_min, t_min;
+    int32_t t_precond;
 } dect_params;
+
+/* Values of dect_params.t_precond.  DECT_PRECOND_MULTIGRID needs every image
+ * side above 64 to be a multiple of 16 down to 64 (sides halve per level) and
+ * a coarsest grid (first odd side, or 1 x 1) of at most 64 pixels; otherwise
+ * the solver returns DECT_EUNSUPPORTED. */
+enum {
+    DECT_PRECOND_AUTO = 0,
+    DECT_PRECOND_JACOBI = 1,
+    DECT_PRECOND_FFT = 2,
+    DECT_PRECOND_MULTIGRID = 3
+};
 
 /* Fill *p with the defaults listed above (HOST pointer). */
 void dect_default_params(dect_params* p);

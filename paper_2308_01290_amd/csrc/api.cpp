@@ -111,6 +111,9 @@ static int check_params(const dect_params* p) {
                     p->f_inner);
     if (!(p->t_tol > 0) || p->t_maxit < 1) return fail(DECT_EINVAL, "t_tol > 0 and t_maxit >= 1");
     if (!(p->t_min > 0)) return fail(DECT_EINVAL, "t_min must be > 0");
+    if (p->t_precond < DECT_PRECOND_AUTO || p->t_precond > DECT_PRECOND_MULTIGRID)
+        return fail(DECT_EINVAL, "t_precond = %d: must be one of the DECT_PRECOND_* values",
+                    p->t_precond);
     return DECT_OK;
 }
 
@@ -295,6 +298,8 @@ struct PcgBufs {
     double* parts;
     PcgState* st;
     PcgParts L;
+    MgPlan mg_plan;     // multigrid levels (mg_plan.ok: the sizes admit them)
+    float* mg;          // level buffers, [batch][mg_plan.zstride]
 };
 
 static void carve_pcg(Carver& c, int ny, int nx, int batch, PcgBufs* b) {
@@ -308,6 +313,8 @@ static void carve_pcg(Carver& c, int ny, int nx, int batch, PcgBufs* b) {
     b->w2 = c.take<float>(n);
     b->parts = c.take<double>((size_t)batch * b->L.zstride);
     b->st = c.take<PcgState>((size_t)batch);
+    b->mg_plan = mg_plan(ny, nx);
+    b->mg = b->mg_plan.ok ? c.take<float>((size_t)batch * b->mg_plan.zstride) : nullptr;
 }
 
 static void fill_pcg_args(PcgArgs* a, const PcgBufs& b, int ny, int nx, int batch, float* x) {
@@ -326,14 +333,39 @@ static void fill_pcg_args(PcgArgs* a, const PcgBufs& b, int ny, int nx, int batc
     a->st = b.st;
 }
 
-static const double kJacobiBelow = 1.5;   // beta below which Jacobi PCG is cheaper than scaled-FFT PCG
+static const double kJacobiBelow = 1.5;   // beta below which Jacobi PCG beats scaled-FFT PCG
+
+// Preconditioner of the t' PCG.  Automatic: the multigrid V-cycle where the
+// image sizes admit it (it needs 7-10 iterations at every beta of the
+// schedule), else Jacobi at small beta and the scaled FFT inverse above.
+static int choose_prec(int want, const PcgBufs& b, double beta, PcgArgs* a) {
+    int prec = want;
+    if (prec == DECT_PRECOND_AUTO)
+        prec = b.mg_plan.ok ? PREC_MG : (beta < kJacobiBelow ? PREC_JACOBI : PREC_FFT);
+    if (prec == PREC_MG && !b.mg_plan.ok)
+        return fail(DECT_EUNSUPPORTED,
+                    "multigrid preconditioner: n_x=%d n_y=%d unsupported (sides above 64 must be "
+                    "multiples of 16 down to 64, and the coarsest grid at most 64 pixels)",
+                    a->nx, a->ny);
+    a->prec = prec;
+    a->nrz_used = prec == PREC_JACOBI ? a->L.nblk : (prec == PREC_FFT ? a->ny : b.mg_plan.nrz);
+    if (prec == PREC_MG) DECT_HIP(mg_init());
+    return DECT_OK;
+}
+
+static void apply_prec(const PcgArgs& a, int it, const PcgBufs& b, float2* fft_scratch,
+                       hipStream_t st) {
+    if (a.prec == PREC_FFT) launch_pcg_fft_prec(a, it, fft_scratch, st);
+    if (a.prec == PREC_MG) launch_pcg_mg_prec(a, it, b.mg_plan, b.mg, st);
+}
 
 // Runs PCG iterations (after an init kernel) until every slice converged or
 // max_iter.  The host checks convergence once per chunk of iterations; the
 // first chunk is sized from the previous solve.  Returns the largest count.
-static int run_pcg(PcgArgs& a, int max_iter, int first_chunk, float2* fft_scratch, hipStream_t st,
-                   int* iters_out) {
-    if (!a.jacobi) launch_pcg_fft_prec(a, -1, fft_scratch, st);
+static int run_pcg(PcgArgs& a, const PcgBufs& b, int max_iter, int first_chunk,
+                   float2* fft_scratch, hipStream_t st, int* iters_out) {
+    if (a.prec == PREC_MG) launch_mg_setup(b.mg_plan, a.w2, b.mg, a.batch, st);
+    apply_prec(a, -1, b, fft_scratch, st);
     int it = 0;
     int chunk = std::max(2, first_chunk);
     std::vector<PcgState> hs(a.batch);
@@ -341,7 +373,7 @@ static int run_pcg(PcgArgs& a, int max_iter, int first_chunk, float2* fft_scratc
         for (int c = 0; c < chunk && it < max_iter; ++c, ++it) {
             launch_pcg_matvec(a, it, st);
             launch_pcg_update(a, it, st);
-            if (!a.jacobi) launch_pcg_fft_prec(a, it, fft_scratch, st);
+            apply_prec(a, it, b, fft_scratch, st);
         }
         launch_pcg_check(a, it, st);
         DECT_HIP(hipGetLastError());
@@ -447,6 +479,7 @@ void dect_default_params(dect_params* p) {
     p->t_maxit = 200;
     p->rho_min = 0.1;
     p->t_min = 1e-6;
+    p->t_precond = DECT_PRECOND_AUTO;
 }
 
 int dect_resolve_geometry(dect_geometry* g) {
@@ -583,10 +616,10 @@ int dect_l0_step(const float* g_tilde, const float* weight, float* g, float* h_o
     a.beta = (float)beta;
     a.thr = thr;
     a.tol2 = tol * tol;
-    a.jacobi = beta < kJacobiBelow;
+    if (int rc = choose_prec(DECT_PRECOND_AUTO, b, beta, &a)) return rc;
     launch_pcg_init_plain(a, weight, g_tilde, h_out, v_out, st);
     int iters = 0;
-    return run_pcg(a, max_iter, 8, fft, st, &iters);
+    return run_pcg(a, b, max_iter, 8, fft, st, &iters);
 }
 
 // ---- solver ---------------------------------------------------------------
@@ -653,6 +686,9 @@ int dect_solver_create(const dect_geometry* gin, const dect_params* p, int32_t b
         return fail(DECT_EINVAL, "image sizes must be 2^a*3^b (b <= 1) in [8, 1024], got %dx%d", g.nx,
                     g.ny);
     if (g.nd > 4096) return fail(DECT_EINVAL, "n_det > 4096 is not supported by the FBP start");
+    if (p->t_precond == DECT_PRECOND_MULTIGRID && !mg_plan(g.ny, g.nx).ok)
+        return fail(DECT_EUNSUPPORTED, "multigrid preconditioner: image %dx%d unsupported", g.nx,
+                    g.ny);
     dect_solver* s = new dect_solver();
     s->g = g;
     s->batch = batch;
@@ -823,10 +859,10 @@ static int one_iteration(dect_solver* s) {
     pc.beta = (float)beta;
     pc.thr = a.thr;
     pc.tol2 = R.p.t_tol * R.p.t_tol;
-    pc.jacobi = beta < kJacobiBelow;
+    if (int rc = choose_prec(R.p.t_precond, s->pcg, beta, &pc)) return rc;
     launch_pcg_init_model(s->M, pc, s->f, s->st);
     int iters = 0;
-    if (int rc = run_pcg(pc, R.p.t_maxit, s->last_pcg + 2, s->fft, s->st, &iters)) return rc;
+    if (int rc = run_pcg(pc, s->pcg, R.p.t_maxit, s->last_pcg + 2, s->fft, s->st, &iters)) return rc;
     s->last_pcg = iters;
     // f^(k+1), residual sinograms
     launch_update(a, s->alpha, s->dN, s->f, s->S, s->zq, s->st);

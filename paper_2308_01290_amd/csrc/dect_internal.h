@@ -189,11 +189,13 @@ struct PcgParts {   // per-slice partial-sum layout (doubles)
     size_t init0, init1, pq, rz, rr, zstride;   // offsets within a slice
 };
 PcgParts pcg_parts(int ny, int nx);
+enum PcgPrec { PREC_JACOBI = 1, PREC_FFT = 2, PREC_MG = 3 };
 struct PcgArgs {
     int ny, nx, batch;
     float beta, thr;
     double tol2;
-    bool jacobi;
+    int prec;                // PcgPrec
+    int nrz_used;            // entries of the <r, z> partial sums this preconditioner writes
     float* x;                // in: x0 (also HT input), out: solution
     float *r, *z, *p0, *p1, *q, *w2;
     double* parts;           // [batch][PcgParts::zstride]
@@ -211,5 +213,30 @@ void launch_pcg_update(const PcgArgs& a, int it, hipStream_t st);
 void launch_pcg_check(const PcgArgs& a, int done_iters, hipStream_t st);
 // FFT preconditioner z = (c + beta L)^-1 r, c = mean(w^2), with <r, z> partials
 void launch_pcg_fft_prec(const PcgArgs& a, int it, float2* scratch, hipStream_t st);
+
+// ---- multigrid V-cycle preconditioner for diag(c) + beta L -----------------------
+constexpr int kMgMaxLevels = 12;
+constexpr int kMgDenseMax = 64;      // unknowns of the coarsest grid (dense solve)
+struct MgPlan {
+    bool ok = false;                 // sizes admit the V-cycle
+    int nlev = 0, ngrid = 0, ncoarse = 0;   // all levels; tile-kernel levels; in-LDS levels
+    int ny[kMgMaxLevels] = {}, nx[kMgMaxLevels] = {};
+    // per-slice offsets (floats) into the level buffer: xs0 = saved iterate of
+    // level 0; b, c, xs, e of tile levels 1..ngrid
+    size_t xs0 = 0, b[kMgMaxLevels] = {}, c[kMgMaxLevels] = {}, xs[kMgMaxLevels] = {},
+           e[kMgMaxLevels] = {};
+    size_t zstride = 0;              // floats per slice
+    size_t coarse_lds = 0;           // dynamic LDS bytes of the in-LDS kernel
+    int nrz = 0;                     // <r, z> partials one V-cycle writes
+};
+MgPlan mg_plan(int ny, int nx);
+hipError_t mg_init();                // once per process: LDS limit of the in-LDS kernel
+// c pyramid of the tile levels from w2 (once per linear solve)
+void launch_mg_setup(const MgPlan& P, const float* w2, float* mg, int batch, hipStream_t st);
+// z = V(r); <r, z> partials into dot[z*dot_zstride + 0..P.nrz)
+void launch_mg_vcycle(const MgPlan& P, const float* r, const float* w2, float* z, float* mg,
+                      int batch, float beta, const int* skip, size_t skip_zstride, double* dot,
+                      size_t dot_zstride, hipStream_t st);
+void launch_pcg_mg_prec(const PcgArgs& a, int it, const MgPlan& P, float* mg, hipStream_t st);
 
 }  // namespace dect

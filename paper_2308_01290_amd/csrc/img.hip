@@ -13,6 +13,7 @@
 //   finish      Z = Zw*max(t', t_min)^(1/m), masked where rho_e < rho_min.
 //   pcg_*       preconditioned CG for subproblem (13c):
 //               (diag(w^2) + beta D^T D) t' = w*g + beta D^T HT(D t'^(k)).
+#include <algorithm>
 #include <cmath>
 
 #include "dect_internal.h"
@@ -273,7 +274,8 @@ constexpr int kPcgBlock = 256 * kPcgPix;       // pixels per block
 PcgParts pcg_parts(int ny, int nx) {
     PcgParts L;
     L.nblk = (nx * ny + kPcgBlock - 1) / kPcgBlock;
-    L.nrz = L.nblk > ny ? L.nblk : ny;
+    const int tiles = ((ny + 15) / 16) * ((nx + 15) / 16);   // multigrid finest-level tiles
+    L.nrz = std::max(std::max(L.nblk, ny), tiles);
     L.init0 = 0;
     L.init1 = L.init0 + L.nblk;
     L.pq = L.init1 + L.nblk;
@@ -350,7 +352,7 @@ __global__ __launch_bounds__(256) void k_pcg_init(PcgArgs a, ModelF M, const flo
         const float w2 = (float)(w * w);
         a.w2[zo + p] = w2;
         a.r[zo + p] = r;
-        if (a.jacobi) {
+        if (a.prec == PREC_JACOBI) {
             const float zz = r / (w2 + 4.f * a.beta);
             a.z[zo + p] = zz;
             rz += (double)r * zz;
@@ -365,7 +367,7 @@ __global__ __launch_bounds__(256) void k_pcg_init(PcgArgs a, ModelF M, const flo
         P[a.L.init0 + blockIdx.x] = s_rr;               // ||r0||^2, the reference
         P[a.L.init1 + blockIdx.x] = s_ws;               // sum of w^2 (FFT shift)
         P[a.L.rr + a.L.nblk + blockIdx.x] = s_rr;       // parity slot 1: "previous" rr
-        if (a.jacobi) P[a.L.rz + a.L.nrz + blockIdx.x] = s_rz;
+        if (a.prec == PREC_JACOBI) P[a.L.rz + a.L.nrz + blockIdx.x] = s_rz;
         if (blockIdx.x == 0) {
             a.st[z].done = 0;
             a.st[z].iters = 0;
@@ -395,7 +397,7 @@ __global__ __launch_bounds__(256) void k_pcg_matvec(PcgArgs a, int it) {
     if (a.st[z].done) return;
     double* P = a.parts + (size_t)z * a.L.zstride;
     const int cur = it & 1, prev = cur ^ 1;
-    const int nrz = a.jacobi ? a.L.nblk : a.ny;
+    const int nrz = a.nrz_used;
     double v[4] = {0.0, 0.0, 0.0, 0.0};   // rz_new, rr, r0^2, rz_old
     {
         const double* rzn = P + a.L.rz + (size_t)prev * a.L.nrz;
@@ -460,7 +462,7 @@ __global__ __launch_bounds__(256) void k_pcg_update(PcgArgs a, int it) {
     if (a.st[z].done) return;
     double* P = a.parts + (size_t)z * a.L.zstride;
     const int cur = it & 1, prev = cur ^ 1;
-    const int nrz = a.jacobi ? a.L.nblk : a.ny;
+    const int nrz = a.nrz_used;
     double v[2] = {0.0, 0.0};   // rz, <p, q>
     for (int t = threadIdx.x; t < nrz; t += 256) v[0] += P[a.L.rz + (size_t)prev * a.L.nrz + t];
     for (int t = threadIdx.x; t < a.L.nblk; t += 256) v[1] += P[a.L.pq + t];
@@ -476,7 +478,7 @@ __global__ __launch_bounds__(256) void k_pcg_update(PcgArgs a, int it) {
         const float r = fmaf(-al, a.q[zo + p], a.r[zo + p]);
         a.r[zo + p] = r;
         rr += (double)r * r;
-        if (a.jacobi) {
+        if (a.prec == PREC_JACOBI) {
             const float zv = r / (a.w2[zo + p] + 4.f * a.beta);
             a.z[zo + p] = zv;
             rzn += (double)r * zv;
@@ -486,7 +488,7 @@ __global__ __launch_bounds__(256) void k_pcg_update(PcgArgs a, int it) {
     const double s_rz = block_sum<256>(rzn, sh);
     if (threadIdx.x == 0) {
         P[a.L.rr + (size_t)cur * a.L.nblk + blockIdx.x] = s_rr;
-        if (a.jacobi) P[a.L.rz + (size_t)cur * a.L.nrz + blockIdx.x] = s_rz;
+        if (a.prec == PREC_JACOBI) P[a.L.rz + (size_t)cur * a.L.nrz + blockIdx.x] = s_rz;
     }
 }
 

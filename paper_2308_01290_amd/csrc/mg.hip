@@ -1,0 +1,468 @@
+// Geometric multigrid V-cycle, the preconditioner of the PCG that solves the
+// Z^m subproblem (13c): A = diag(c) + beta L, c = w^2, L = D^T D on the
+// periodic pixel grid.
+//
+// Level l is the grid coarsened 2^l times per axis (cell-centred), with the
+// operator re-discretised as A_l = diag(c_l) + (beta / 4^l) L and c_l the 2x2
+// average of c_(l-1).  Transfers: restriction = 2x2 average, prolongation =
+// piecewise constant (R = P^T / 4).  Smoothing: two damped-Jacobi sweeps
+// (omega = 0.8) before the coarse correction, starting from zero, and two
+// after it.  The coarsest grid (an odd side, or 1 x 1; at most 64 unknowns) is
+// solved exactly by Gaussian elimination.  The V-cycle is therefore a fixed
+// symmetric linear map, as PCG requires; it has no atomics, so it is
+// deterministic.
+//
+// Kernels: for every level whose larger side exceeds 64, one fused kernel
+// going down (two sweeps, residual, restriction) and one going up
+// (prolongation, two sweeps), on 16 x 16 tiles with a two-pixel halo; all
+// smaller levels run in one workgroup per slice with every level resident in
+// LDS.
+#include <algorithm>
+
+#include "dect_internal.h"
+#include "device_util.h"
+
+namespace dect {
+
+constexpr float kOmega = 0.8f;
+constexpr int kMgCoarseMax = 64;          // larger side at which the in-LDS kernel takes over
+constexpr int kMgCoarseThreads = 1024;
+constexpr size_t kMgLdsMax = 160 * 1024;  // LDS of one workgroup on gfx950
+constexpr size_t kMgLdsStatic = 1024;     // reserved for the in-LDS kernel's static arrays
+
+// one damped-Jacobi sweep at a pixel: x + omega (b - A x) / diag(A)
+__device__ __forceinline__ float jac(float x, float b, float c, float beta, float nsum) {
+    const float d = c + 4.f * beta;
+    return x + kOmega * (b - (c * x + beta * (4.f * x - nsum))) / d;
+}
+
+MgPlan mg_plan(int ny, int nx) {
+    MgPlan P;
+    P.ny[0] = ny;
+    P.nx[0] = nx;
+    if (ny < 1 || nx < 1) return P;
+    int l = 0;
+    bool ok = true;
+    while (std::max(ny, nx) > kMgCoarseMax) {   // tile levels
+        if (ny % 16 || nx % 16 || l + 1 >= kMgMaxLevels) {
+            ok = false;
+            break;
+        }
+        ny /= 2;
+        nx /= 2;
+        ++l;
+        ++P.ngrid;
+        P.ny[l] = ny;
+        P.nx[l] = nx;
+    }
+    P.ncoarse = 1;
+    while (ok && ny % 2 == 0 && nx % 2 == 0 && l + 1 < kMgMaxLevels) {
+        ny /= 2;
+        nx /= 2;
+        ++l;
+        ++P.ncoarse;
+        P.ny[l] = ny;
+        P.nx[l] = nx;
+    }
+    P.nlev = l + 1;
+    const int nc = ny * nx;
+    ok = ok && nc <= kMgDenseMax;
+    size_t off = 0;
+    P.xs0 = off;
+    off += (size_t)P.ny[0] * P.nx[0];
+    for (int q = 1; q <= P.ngrid; ++q) {
+        const size_t n = (size_t)P.ny[q] * P.nx[q];
+        P.b[q] = off;
+        off += n;
+        P.c[q] = off;
+        off += n;
+        P.xs[q] = off;
+        off += n;
+        P.e[q] = off;
+        off += n;
+    }
+    P.zstride = (off + 63) & ~(size_t)63;
+    size_t lds = 0;
+    for (int q = P.ngrid; q < P.nlev; ++q) lds += 3 * (size_t)P.ny[q] * P.nx[q];
+    lds += 2 * (size_t)P.ny[P.ngrid] * P.nx[P.ngrid];
+    lds += (size_t)nc * (nc + 1) + 2 * (size_t)nc;
+    P.coarse_lds = lds * sizeof(float);
+    ok = ok && P.coarse_lds + kMgLdsStatic <= kMgLdsMax;
+    P.nrz = P.ngrid > 0 ? (P.ny[0] / 16) * (P.nx[0] / 16) : 1;
+    P.ok = ok;
+    return P;
+}
+
+__device__ __forceinline__ bool mg_skip(const int* skip, size_t stride, int z) {
+    return skip && skip[(size_t)z * stride];
+}
+
+__device__ __forceinline__ int wrap_near(int i, int n) {   // i in [-n, 2n)
+    return i < 0 ? i + n : (i >= n ? i - n : i);
+}
+
+// ---------------------------------------------------------------------------
+// c_(l+1) = 2x2 average of c_l on the tile levels (once per linear solve)
+// ---------------------------------------------------------------------------
+__global__ void k_mg_restrict_c(const float* __restrict__ cf, size_t cf_zstride, int nyf, int nxf,
+                                float* __restrict__ cc, size_t cc_zstride) {
+    const int nyc = nyf / 2, nxc = nxf / 2;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int z = blockIdx.y;
+    if (p >= nyc * nxc) return;
+    const int i = p / nxc, k = p % nxc;
+    const float* f = cf + (size_t)z * cf_zstride;
+    const size_t a = (size_t)(2 * i) * nxf + 2 * k;
+    cc[(size_t)z * cc_zstride + p] = 0.25f * (f[a] + f[a + 1] + f[a + nxf] + f[a + nxf + 1]);
+}
+
+// ---------------------------------------------------------------------------
+// tile kernels: 16 x 16 pixels of one level per workgroup, two-pixel halo
+// ---------------------------------------------------------------------------
+struct MgLevel {
+    const float* b;   // right-hand side
+    const float* c;   // diagonal
+    float* xs;        // saved pre-smoothed iterate (down: written, up: read)
+    float* out;       // down: coarse right-hand side; up: this level's correction
+    const float* e;   // up: coarse correction
+    size_t zs_b, zs_c, zs_xs, zs_out, zs_e;   // per-slice strides (floats)
+    int ny, nx;
+    float beta;
+};
+
+__global__ __launch_bounds__(256) void k_mg_down(MgLevel L, const int* skip, size_t skip_zstride) {
+    __shared__ float B[20][21], C[20][21], X1[20][21], X2[18][19], R[16][17];
+    const int z = blockIdx.z;
+    if (mg_skip(skip, skip_zstride, z)) return;
+    const int i0 = blockIdx.y * 16, k0 = blockIdx.x * 16;
+    const float* b = L.b + (size_t)z * L.zs_b;
+    const float* c = L.c + (size_t)z * L.zs_c;
+    const float be = L.beta;
+    for (int t = threadIdx.x; t < 400; t += 256) {
+        const int r = t / 20, s = t % 20;
+        const size_t g = (size_t)wrap_near(i0 - 2 + r, L.ny) * L.nx + wrap_near(k0 - 2 + s, L.nx);
+        const float bb = b[g], cc = c[g];
+        B[r][s] = bb;
+        C[r][s] = cc;
+        X1[r][s] = kOmega * bb / (cc + 4.f * be);   // first sweep from zero
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < 324; t += 256) {
+        const int r = t / 18 + 1, s = t % 18 + 1;
+        const float ns = X1[r - 1][s] + X1[r + 1][s] + X1[r][s - 1] + X1[r][s + 1];
+        X2[r - 1][s - 1] = jac(X1[r][s], B[r][s], C[r][s], be, ns);
+    }
+    __syncthreads();
+    {
+        const int r = threadIdx.x / 16 + 2, s = threadIdx.x % 16 + 2;
+        const float x = X2[r - 1][s - 1];
+        const float ns = X2[r - 2][s - 1] + X2[r][s - 1] + X2[r - 1][s - 2] + X2[r - 1][s];
+        R[r - 2][s - 2] = B[r][s] - (C[r][s] * x + be * (4.f * x - ns));
+        L.xs[(size_t)z * L.zs_xs + (size_t)(i0 + r - 2) * L.nx + (k0 + s - 2)] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int a = threadIdx.x / 8, q = threadIdx.x % 8;
+        const float v = 0.25f * (R[2 * a][2 * q] + R[2 * a + 1][2 * q] + R[2 * a][2 * q + 1] +
+                                 R[2 * a + 1][2 * q + 1]);
+        L.out[(size_t)z * L.zs_out + (size_t)(i0 / 2 + a) * (L.nx / 2) + (k0 / 2 + q)] = v;
+    }
+}
+
+// y0 = xs + P e; two sweeps; out = y2.  With `dot` (finest level) the tile's
+// <b, out> goes to dot[z*dot_zstride + tile].
+__global__ __launch_bounds__(256) void k_mg_up(MgLevel L, const int* skip, size_t skip_zstride,
+                                               double* dot, size_t dot_zstride) {
+    __shared__ float B[20][21], C[20][21], Y0[20][21], Y1[18][19];
+    __shared__ double sh[4];
+    const int z = blockIdx.z;
+    if (mg_skip(skip, skip_zstride, z)) return;
+    const int i0 = blockIdx.y * 16, k0 = blockIdx.x * 16;
+    const float* b = L.b + (size_t)z * L.zs_b;
+    const float* c = L.c + (size_t)z * L.zs_c;
+    const float* xs = L.xs + (size_t)z * L.zs_xs;
+    const float* e = L.e + (size_t)z * L.zs_e;
+    const int nxc = L.nx / 2;
+    const float be = L.beta;
+    for (int t = threadIdx.x; t < 400; t += 256) {
+        const int r = t / 20, s = t % 20;
+        const int gi = wrap_near(i0 - 2 + r, L.ny), gk = wrap_near(k0 - 2 + s, L.nx);
+        const size_t g = (size_t)gi * L.nx + gk;
+        B[r][s] = b[g];
+        C[r][s] = c[g];
+        Y0[r][s] = xs[g] + e[(size_t)(gi / 2) * nxc + gk / 2];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < 324; t += 256) {
+        const int r = t / 18 + 1, s = t % 18 + 1;
+        const float ns = Y0[r - 1][s] + Y0[r + 1][s] + Y0[r][s - 1] + Y0[r][s + 1];
+        Y1[r - 1][s - 1] = jac(Y0[r][s], B[r][s], C[r][s], be, ns);
+    }
+    __syncthreads();
+    const int r = threadIdx.x / 16 + 2, s = threadIdx.x % 16 + 2;
+    const float ns = Y1[r - 2][s - 1] + Y1[r][s - 1] + Y1[r - 1][s - 2] + Y1[r - 1][s];
+    const float y = jac(Y1[r - 1][s - 1], B[r][s], C[r][s], be, ns);
+    L.out[(size_t)z * L.zs_out + (size_t)(i0 + r - 2) * L.nx + (k0 + s - 2)] = y;
+    if (dot) {
+        const double v = block_sum<256>((double)y * (double)B[r][s], sh);
+        if (threadIdx.x == 0) dot[(size_t)z * dot_zstride + blockIdx.y * gridDim.x + blockIdx.x] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// all levels with larger side <= 64 in one workgroup per slice, in LDS
+// ---------------------------------------------------------------------------
+struct MgCoarse {
+    const float* b;       // right-hand side of the first in-LDS level
+    const float* c;       // its diagonal
+    float* e;             // its correction (output)
+    size_t zs_b, zs_c, zs_e;
+    float beta;           // beta of the first in-LDS level
+    int nlev;             // in-LDS levels (>= 1); the last is solved exactly
+    int ny[kMgMaxLevels], nx[kMgMaxLevels];
+    double* dot;          // optional <b, e> (when this is the finest level)
+    size_t dot_zstride;
+};
+
+// y = one damped-Jacobi sweep of x (x = 0 when from_zero), periodic grid
+__device__ void lds_sweep(const float* x, const float* b, const float* c, float* y, int ny, int nx,
+                          float beta, bool from_zero) {
+    for (int t = threadIdx.x; t < ny * nx; t += blockDim.x) {
+        if (from_zero) {
+            y[t] = kOmega * b[t] / (c[t] + 4.f * beta);
+            continue;
+        }
+        const int i = t / nx, k = t % nx;
+        const int ip = (i + 1 == ny) ? 0 : i + 1, im = (i == 0) ? ny - 1 : i - 1;
+        const int kp = (k + 1 == nx) ? 0 : k + 1, km = (k == 0) ? nx - 1 : k - 1;
+        const float ns = x[ip * nx + k] + x[im * nx + k] + x[i * nx + kp] + x[i * nx + km];
+        y[t] = jac(x[t], b[t], c[t], beta, ns);
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kMgCoarseThreads) void k_mg_coarse(MgCoarse G, const int* skip,
+                                                                 size_t skip_zstride) {
+    extern __shared__ float lds[];
+    __shared__ double sh[kMgCoarseThreads / kWave];
+    __shared__ int s_ny[kMgMaxLevels], s_nx[kMgMaxLevels], s_off[kMgMaxLevels + 1];
+    const int z = blockIdx.x;
+    if (mg_skip(skip, skip_zstride, z)) return;
+    if (threadIdx.x == 0) {   // level l: b, c, x at lds + s_off[l] + {0, 1, 2} * n_l
+        int o = 0;
+        for (int l = 0; l < kMgMaxLevels; ++l) {
+            s_ny[l] = G.ny[l];
+            s_nx[l] = G.nx[l];
+            s_off[l] = o;
+            if (l < G.nlev) o += 3 * G.ny[l] * G.nx[l];
+        }
+        s_off[kMgMaxLevels] = o;
+    }
+    __syncthreads();
+    auto bl = [&](int l) { return lds + s_off[l]; };
+    auto cl = [&](int l) { return lds + s_off[l] + s_ny[l] * s_nx[l]; };
+    auto xl = [&](int l) { return lds + s_off[l] + 2 * s_ny[l] * s_nx[l]; };
+    const int n0 = s_ny[0] * s_nx[0];
+    float* t0 = lds + s_off[kMgMaxLevels];
+    float* t1 = t0 + n0;
+    float* dense = t0 + 2 * n0;
+    for (int t = threadIdx.x; t < n0; t += blockDim.x) {
+        bl(0)[t] = G.b[(size_t)z * G.zs_b + t];
+        cl(0)[t] = G.c[(size_t)z * G.zs_c + t];
+    }
+    __syncthreads();
+    for (int l = 0; l + 1 < G.nlev; ++l) {
+        const int nyc = s_ny[l + 1], nxc = s_nx[l + 1], nxf = s_nx[l];
+        for (int t = threadIdx.x; t < nyc * nxc; t += blockDim.x) {
+            const int i = t / nxc, k = t % nxc;
+            const int a = (2 * i) * nxf + 2 * k;
+            cl(l + 1)[t] = 0.25f * (cl(l)[a] + cl(l)[a + 1] + cl(l)[a + nxf] + cl(l)[a + nxf + 1]);
+        }
+        __syncthreads();
+    }
+    // down: two sweeps from zero, residual, restriction
+    float beta = G.beta;
+    for (int l = 0; l + 1 < G.nlev; ++l, beta *= 0.25f) {
+        const int ny = s_ny[l], nx = s_nx[l];
+        lds_sweep(nullptr, bl(l), cl(l), t0, ny, nx, beta, true);
+        lds_sweep(t0, bl(l), cl(l), xl(l), ny, nx, beta, false);
+        const float* x = xl(l);
+        for (int t = threadIdx.x; t < ny * nx; t += blockDim.x) {
+            const int i = t / nx, k = t % nx;
+            const int ip = (i + 1 == ny) ? 0 : i + 1, im = (i == 0) ? ny - 1 : i - 1;
+            const int kp = (k + 1 == nx) ? 0 : k + 1, km = (k == 0) ? nx - 1 : k - 1;
+            const float ns = x[ip * nx + k] + x[im * nx + k] + x[i * nx + kp] + x[i * nx + km];
+            t0[t] = bl(l)[t] - (cl(l)[t] * x[t] + beta * (4.f * x[t] - ns));
+        }
+        __syncthreads();
+        const int nyc = s_ny[l + 1], nxc = s_nx[l + 1];
+        for (int t = threadIdx.x; t < nyc * nxc; t += blockDim.x) {
+            const int i = t / nxc, k = t % nxc;
+            const int a = (2 * i) * nx + 2 * k;
+            bl(l + 1)[t] = 0.25f * (t0[a] + t0[a + 1] + t0[a + nx] + t0[a + nx + 1]);
+        }
+        __syncthreads();
+    }
+    // coarsest grid: Gaussian elimination (the matrix is SPD), result in xl(last)
+    {
+        const int l = G.nlev - 1;
+        const int ny = s_ny[l], nx = s_nx[l], nc = ny * nx, ld = nc + 1;
+        float* A = dense;
+        float* rhs = A + nc * ld;
+        float* lc = rhs + nc;
+        for (int t = threadIdx.x; t < nc; t += blockDim.x) {   // row t, owned by one thread
+            float* row = A + t * ld;
+            for (int j = 0; j < nc; ++j) row[j] = 0.f;
+            const int i = t / nx, k = t % nx;
+            const int ip = (i + 1 == ny) ? 0 : i + 1, im = (i == 0) ? ny - 1 : i - 1;
+            const int kp = (k + 1 == nx) ? 0 : k + 1, km = (k == 0) ? nx - 1 : k - 1;
+            const int nb[4] = {ip * nx + k, im * nx + k, i * nx + kp, i * nx + km};
+            float d = cl(l)[t];   // a neighbour that wraps onto t itself adds nothing
+            for (int q = 0; q < 4; ++q) {
+                if (nb[q] == t) continue;
+                row[nb[q]] -= beta;
+                d += beta;
+            }
+            row[t] = d;
+            rhs[t] = bl(l)[t];
+        }
+        __syncthreads();
+        for (int k = 0; k + 1 < nc; ++k) {
+            const float piv = A[k * ld + k];
+            const float inv = piv > 0.f ? 1.f / piv : 0.f;
+            for (int i = k + 1 + threadIdx.x; i < nc; i += blockDim.x) lc[i] = A[i * ld + k] * inv;
+            __syncthreads();
+            const int w = nc - k;   // columns k..nc-1; column k carries the rhs update
+            for (int idx = threadIdx.x; idx < (nc - k - 1) * w; idx += blockDim.x) {
+                const int i = k + 1 + idx / w, j = k + idx % w;
+                if (j == k)
+                    rhs[i] -= lc[i] * rhs[k];
+                else
+                    A[i * ld + j] -= lc[i] * A[k * ld + j];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x < kWave) {   // back substitution, one lane per unknown
+            const int lane = threadIdx.x;
+            float xv = 0.f;
+            for (int i = nc - 1; i >= 0; --i) {
+                const float part = (lane > i && lane < nc) ? A[i * ld + lane] * xv : 0.f;
+                const float s = wave_sum(part);
+                if (lane == i) {
+                    const float piv = A[i * ld + i];
+                    xv = piv > 0.f ? (rhs[i] - s) / piv : 0.f;
+                }
+            }
+            if (lane < nc) xl(l)[lane] = xv;
+        }
+        __syncthreads();
+    }
+    // up: y0 = xs_l + P e_(l+1) (e_(l+1) is in xl(l+1)); two sweeps into xl(l)
+    for (int l = G.nlev - 2; l >= 0; --l) {
+        beta *= 4.f;
+        const int ny = s_ny[l], nx = s_nx[l], nxc = s_nx[l + 1];
+        for (int t = threadIdx.x; t < ny * nx; t += blockDim.x) {
+            const int i = t / nx, k = t % nx;
+            t0[t] = xl(l)[t] + xl(l + 1)[(i / 2) * nxc + k / 2];
+        }
+        __syncthreads();
+        lds_sweep(t0, bl(l), cl(l), t1, ny, nx, beta, false);
+        lds_sweep(t1, bl(l), cl(l), xl(l), ny, nx, beta, false);
+    }
+    double dot = 0.0;
+    for (int t = threadIdx.x; t < n0; t += blockDim.x) {
+        G.e[(size_t)z * G.zs_e + t] = xl(0)[t];
+        dot += (double)xl(0)[t] * (double)bl(0)[t];
+    }
+    if (G.dot) {
+        const double v = block_sum<kMgCoarseThreads>(dot, sh);
+        if (threadIdx.x == 0) G.dot[(size_t)z * G.dot_zstride] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+hipError_t mg_init() {
+    static hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mg_coarse),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                                              (int)(kMgLdsMax - kMgLdsStatic));
+    return e;
+}
+
+void launch_mg_setup(const MgPlan& P, const float* w2, float* mg, int batch, hipStream_t st) {
+    const size_t n0 = (size_t)P.ny[0] * P.nx[0];
+    for (int l = 0; l < P.ngrid; ++l) {
+        const float* cf = l == 0 ? w2 : mg + P.c[l];
+        const size_t cfz = l == 0 ? n0 : P.zstride;
+        const int n = P.ny[l + 1] * P.nx[l + 1];
+        hipLaunchKernelGGL(k_mg_restrict_c, dim3((n + 255) / 256, batch), dim3(256), 0, st, cf, cfz,
+                           P.ny[l], P.nx[l], mg + P.c[l + 1], P.zstride);
+    }
+}
+
+void launch_mg_vcycle(const MgPlan& P, const float* r, const float* w2, float* z, float* mg,
+                      int batch, float beta, const int* skip, size_t skip_zstride, double* dot,
+                      size_t dot_zstride, hipStream_t st) {
+    const size_t n0 = (size_t)P.ny[0] * P.nx[0];
+    auto level = [&](int l, float bl) {
+        MgLevel L;
+        L.b = l == 0 ? r : mg + P.b[l];
+        L.zs_b = l == 0 ? n0 : P.zstride;
+        L.c = l == 0 ? w2 : mg + P.c[l];
+        L.zs_c = l == 0 ? n0 : P.zstride;
+        L.xs = l == 0 ? mg + P.xs0 : mg + P.xs[l];
+        L.zs_xs = P.zstride;
+        L.out = nullptr;
+        L.zs_out = P.zstride;
+        L.e = nullptr;
+        L.zs_e = P.zstride;
+        L.ny = P.ny[l];
+        L.nx = P.nx[l];
+        L.beta = bl;
+        return L;
+    };
+    float bl = beta;
+    for (int l = 0; l < P.ngrid; ++l, bl *= 0.25f) {
+        MgLevel L = level(l, bl);
+        L.out = mg + P.b[l + 1];
+        hipLaunchKernelGGL(k_mg_down, dim3(P.nx[l] / 16, P.ny[l] / 16, batch), dim3(256), 0, st, L,
+                           skip, skip_zstride);
+    }
+    MgCoarse G;
+    const int g0 = P.ngrid;
+    G.b = g0 == 0 ? r : mg + P.b[g0];
+    G.zs_b = g0 == 0 ? n0 : P.zstride;
+    G.c = g0 == 0 ? w2 : mg + P.c[g0];
+    G.zs_c = g0 == 0 ? n0 : P.zstride;
+    G.e = g0 == 0 ? z : mg + P.e[g0];
+    G.zs_e = g0 == 0 ? n0 : P.zstride;
+    G.beta = bl;
+    G.nlev = P.ncoarse;
+    for (int q = 0; q < kMgMaxLevels; ++q) {
+        G.ny[q] = q < P.ncoarse ? P.ny[g0 + q] : 0;
+        G.nx[q] = q < P.ncoarse ? P.nx[g0 + q] : 0;
+    }
+    G.dot = g0 == 0 ? dot : nullptr;
+    G.dot_zstride = dot_zstride;
+    hipLaunchKernelGGL(k_mg_coarse, dim3(batch), dim3(kMgCoarseThreads), P.coarse_lds, st, G, skip,
+                       skip_zstride);
+    for (int l = P.ngrid - 1; l >= 0; --l) {
+        bl *= 4.f;
+        MgLevel L = level(l, bl);
+        L.e = mg + P.e[l + 1];
+        L.out = l == 0 ? z : mg + P.e[l];
+        L.zs_out = l == 0 ? n0 : P.zstride;
+        hipLaunchKernelGGL(k_mg_up, dim3(P.nx[l] / 16, P.ny[l] / 16, batch), dim3(256), 0, st, L,
+                           skip, skip_zstride, l == 0 ? dot : nullptr, dot_zstride);
+    }
+}
+
+void launch_pcg_mg_prec(const PcgArgs& a, int it, const MgPlan& P, float* mg, hipStream_t st) {
+    // z = V(r); <r, z> partials into the rz slot of iteration it (it = -1:
+    // the initial residual, slot 1)
+    const int slot = it < 0 ? 1 : (it & 1);
+    launch_mg_vcycle(P, a.r, a.w2, a.z, mg, a.batch, a.beta, &a.st[0].done,
+                     sizeof(PcgState) / sizeof(int), a.parts + a.L.rz + (size_t)slot * a.L.nrz,
+                     a.L.zstride, st);
+}
+
+}  // namespace dect

@@ -37,7 +37,8 @@ class _Params(C.Structure):
                 ("lambda_", C.c_double), ("beta0", C.c_double), ("beta_max", C.c_double),
                 ("kappa", C.c_double), ("eta", C.c_double), ("xi", C.c_double),
                 ("n_iter", C.c_int32), ("f_inner", C.c_int32), ("t_tol", C.c_double),
-                ("t_maxit", C.c_int32), ("rho_min", C.c_double), ("t_min", C.c_double)]
+                ("t_maxit", C.c_int32), ("rho_min", C.c_double), ("t_min", C.c_double),
+                ("t_precond", C.c_int32)]
 
 
 EXPORTS = [

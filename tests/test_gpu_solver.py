@@ -48,10 +48,13 @@ def test_l0_step_fft_matches_oracle(shape, batch, beta):
         assert rel_inf(got[b], ref) <= 1e-5, (shape, b)
 
 
+# (128, 96): multigrid with one tile level; (48, 32): multigrid entirely in
+# LDS; (96, 24): sizes the V-cycle cannot coarsen, Jacobi / scaled-FFT PCG
+@pytest.mark.parametrize("shape", [(128, 96), (48, 32), (96, 24)])
 @pytest.mark.parametrize("beta", [0.05, 3.0, 500.0])
-def test_l0_step_weighted_matches_oracle(beta):
+def test_l0_step_weighted_matches_oracle(shape, beta):
     rng = np.random.default_rng(int(beta * 10))
-    ny, nx = 128, 96
+    ny, nx = shape
     w = rng.uniform(0.2, 1.8, (ny, nx)).astype(np.float32)
     w[:10, :20] = 0.0
     gt = rng.standard_normal((ny, nx)).astype(np.float32)
@@ -91,10 +94,12 @@ def test_init_matches_oracle():
     assert np.abs(t - st.t)[m].max() <= 1e-2 * max(1.0, np.abs(st.t[m]).max())
 
 
+@pytest.mark.parametrize("precond", [0, 1, 2, 3])
 @pytest.mark.parametrize("k", [0, 7])
-def test_one_iteration_matches_oracle(k):
+def test_one_iteration_matches_oracle(k, precond):
     """From an identical FP32 state, one outer iteration (f-step, rho step,
-    t' step, beta update) on the GPU equals the oracle's."""
+    t' step, beta update) on the GPU equals the oracle's, with every
+    preconditioner of the t' PCG (automatic, Jacobi, scaled FFT, multigrid)."""
     g, ph, pL, pH = workload("small")
     phys = Physics()
     params = oracle_params(10).resolved(phys, g)
@@ -104,7 +109,7 @@ def test_one_iteration_matches_oracle(k):
         beta *= params.kappa
     st0 = S.State(f32(st0.f1), f32(st0.f2), f32(st0.rho), f32(st0.t), beta, k)
     ref = S.iterate(st0, f32(pL), f32(pH), g, phys, params)
-    sol = dect.Solver(g, lib_params(10))
+    sol = dect.Solver(g, lib_params(10, t_precond=precond))
     sol.set_state(cuda(pL[None]), cuda(pH[None]), cuda(st0.f1[None]), cuda(st0.f2[None]),
                   cuda(st0.rho[None]), cuda(st0.t[None]), k=k)
     sol.iterate(1)

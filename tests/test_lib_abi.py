@@ -41,6 +41,7 @@ def test_default_params():
     assert tuple(p.basis_Z) == (14.14, 7.42) and tuple(p.basis_rho) == (1.69, 1.0)
     assert p.lambda_ == 0.01 and p.beta_max == 1e5 and p.f_inner == 1
     assert p.t_tol == 1e-7 and p.t_maxit == 200 and p.rho_min == 0.1
+    assert p.t_precond == 0   # DECT_PRECOND_AUTO
 
 
 def test_geometry_resolution_matches_corner_pitch():
@@ -92,6 +93,13 @@ def test_entry_points_reject_bad_arguments_before_enqueueing():
     p = dect.default_params()
     assert L.dect_solver_create(C.byref(bad), C.byref(p), 1, None, 0, None, C.byref(h)) == -1
     assert b"2^a*3^b" in L.dect_last_error()
+    # preconditioner selector: out of range; multigrid on sizes it cannot coarsen
+    p = dect.default_params(t_precond=7)
+    assert L.dect_solver_create(C.byref(g), C.byref(p), 1, None, 0, None, C.byref(h)) == -1
+    odd = dect.Geometry.of(P.FanGeometry(**{**P.geometry_small().__dict__, "n_x": 96, "n_y": 24})).c()
+    p = dect.default_params(t_precond=3)
+    assert L.dect_solver_create(C.byref(odd), C.byref(p), 1, None, 0, None, C.byref(h)) == -5
+    assert b"multigrid" in L.dect_last_error()
     # l0 step: unsupported FFT size, NULL input
     assert L.dect_l0_step(None, None, None, None, None, 16, 16, 1, 0.1, 1.0, 1e-6, 10, None, 0, None) == -1
     assert L.dect_l0_step(C.c_void_p(1), None, C.c_void_p(1), None, None, 10, 16, 1, 0.1, 1.0, 1e-6,
