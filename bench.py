@@ -84,6 +84,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first copy a device buffer of this many MiB once: the reference "
+                         "kernel of known traffic for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -95,6 +98,14 @@ def main():
     import torch
     from paper_2308_01290_amd import dect
     from paper_2308_01290_amd import phantoms as P
+
+    if args.copy_mib > 0:
+        src = torch.ones(args.copy_mib << 18, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     params = dect.default_params(n_iter=N_ITER)
     g, ph, pL, pH = P.workload_slice512(lambda Z, R: dect.attenuation(params, Z, R))

@@ -321,78 +321,136 @@ void launch_project(const Geom& g, const RayTable& t, const float2* padN, const 
 }
 
 // ---------------------------------------------------------------------------
-// back-projector: one lane per pixel, 16 x 16 pixels per block (four 8 x 8
-// wavefronts), all views; per view the pixel's detector footprint bounds the
-// bins whose chords are evaluated with the projector's own formula.
+// back-projector: voxel-driven, exact transpose of the projector's weights.
+// A block covers a 16 x 16 pixel tile with 8 wavefronts; each lane owns a
+// 2 x 2 pixel quad (so one ray-table read serves four pixels) and wavefront
+// w takes views w, w + 8, ...  Per view, the lanes' detector footprints
+// (bounding box of the quad, projected from the source) give each lane its
+// candidate bins; the union window is staged once per wavefront in LDS, so
+// the candidate loop reads LDS only.  The 8 partial sums of every pixel are
+// added in a fixed order at the end (deterministic, no atomics).
 // ---------------------------------------------------------------------------
-constexpr int kViewChunk = 512;
+constexpr int kBpWaves = 8;
+constexpr int kBpViewChunk = 256;
 
-__global__ __launch_bounds__(256) void k_backproject(const float2* __restrict__ sino,
-                                                     const int4* __restrict__ fix,
-                                                     const float2* __restrict__ flt,
-                                                     const float4* __restrict__ view, int nx, int ny,
-                                                     int nv, int nd, float sid, float sdd, float dxmm,
-                                                     float u0, float inv_pitch,
-                                                     float2* __restrict__ out_pairs,
-                                                     float* __restrict__ out_split, int nout) {
-    __shared__ float4 vs[kViewChunk];
+__global__ __launch_bounds__(kBpWaves * 64) void k_backproject(
+    const float2* __restrict__ sino, const int4* __restrict__ fix, const float2* __restrict__ flt,
+    const float4* __restrict__ view, int nx, int ny, int nv, int nd, float sid, float sdd,
+    float dxmm, float u0, float inv_pitch, float2* __restrict__ out_pairs,
+    float* __restrict__ out_split, int nout) {
+    __shared__ float4 vs[kBpViewChunk];
+    __shared__ int4 sfix[kBpWaves][64];
+    __shared__ float4 sray[kBpWaves][64];      // (|1/s|, +-L, sino lo, sino hi)
+    __shared__ float red[kBpWaves][8][64];
     const int z = blockIdx.z;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int ty = (w >> 1) * 8 + (lane >> 3), tx = (w & 1) * 8 + (lane & 7);
-    const int i = blockIdx.y * 16 + ty, k = blockIdx.x * 16 + tx;
-    const bool inside = i < ny && k < nx;
-    const float x = ((float)k - 0.5f * (float)(nx - 1)) * dxmm;
-    const float y = ((float)i - 0.5f * (float)(ny - 1)) * dxmm;
+    const int i0 = blockIdx.y * 16 + 2 * (lane >> 3), k0 = blockIdx.x * 16 + 2 * (lane & 7);
+    // quad centre (between pixels k0, k0 + 1 and rows i0, i0 + 1)
+    const float x = ((float)k0 + 0.5f - 0.5f * (float)(nx - 1)) * dxmm;
+    const float y = ((float)i0 + 0.5f - 0.5f * (float)(ny - 1)) * dxmm;
     const float2* sz = sino + (size_t)z * nv * nd;
-    float acc1 = 0.f, acc2 = 0.f;
-    for (int v0 = 0; v0 < nv; v0 += kViewChunk) {
-        const int nvc = min(kViewChunk, nv - v0);
+    // acc[di][dk]: pixel (i0 + di, k0 + dk), both channels
+    float a00x = 0.f, a00y = 0.f, a01x = 0.f, a01y = 0.f;
+    float a10x = 0.f, a10y = 0.f, a11x = 0.f, a11y = 0.f;
+    for (int v0 = 0; v0 < nv; v0 += kBpViewChunk) {
+        const int nvc = min(kBpViewChunk, nv - v0);
         __syncthreads();
-        for (int q = threadIdx.x; q < nvc; q += 256) vs[q] = view[v0 + q];
+        for (int q = threadIdx.x; q < nvc; q += kBpWaves * 64) vs[q] = view[v0 + q];
         __syncthreads();
-        if (!inside) continue;
-        for (int vv = 0; vv < nvc; ++vv) {
+        for (int vv = w; vv < nvc; vv += kBpWaves) {
             const float4 vc = vs[vv];
+            const float e = 2.f * vc.z;   // half-extent of the quad along both view axes
             const float U = sid - (x * vc.x + y * vc.y);
             const float W = y * vc.x - x * vc.y;
-            const float rm = __builtin_amdgcn_rcpf(U - vc.z);
-            const float rp = __builtin_amdgcn_rcpf(U + vc.z);
-            const float hi = W + vc.z, lo = W - vc.z;
+            const float rm = __builtin_amdgcn_rcpf(U - e);
+            const float rp = __builtin_amdgcn_rcpf(U + e);
+            const float hi = W + e, lo = W - e;
             const float umax = sdd * hi * (hi >= 0.f ? rm : rp);
             const float umin = sdd * lo * (lo >= 0.f ? rp : rm);
-            const int jl = max((int)ceilf((umin - u0) * inv_pitch - 1e-3f), 0);
-            const int jh = min((int)floorf((umax - u0) * inv_pitch + 1e-3f), nd - 1);
+            int jl = max((int)ceilf((umin - u0) * inv_pitch - 1e-3f), 0);
+            int jh = min((int)floorf((umax - u0) * inv_pitch + 1e-3f), nd - 1);
+            if (jl > jh) {
+                jl = INT_MAX;
+                jh = INT_MIN;
+            }
+            const int Jlo = wave_min(jl), Jhi = wave_max(jh);
+            if (Jlo > Jhi) continue;   // wave-uniform
             const int v = v0 + vv;
-            const int4* fv = fix + (size_t)v * nd;
-            const float2* lv = flt + (size_t)v * nd;
-            const float2* sv = sz + (size_t)v * nd;
-            for (int j = jl; j <= jh; ++j) {
-                const int4 fx = fv[j];
-                const float2 fl = lv[j];
-                const bool xm = fl.y > 0.f;
-                const int maj = xm ? k : i, mnr = xm ? i : k;
-                const long long S = fix_s(fx);
-                const bool up = S >= 0;
-                const long long yq = fix_a0(fx) + (long long)maj * S;
-                const int r0 = (int)(yq >> 32);
-                const float w0 = first_weight((unsigned)yq, up, fl.x);
-                const int partner = up ? r0 + 1 : r0 - 1;
-                float ch = (mnr == r0) ? w0 : ((mnr == partner) ? 1.f - w0 : 0.f);
-                ch *= fabsf(fl.y);
-                const float2 sval = sv[j];
-                acc1 = fmaf(ch, sval.x, acc1);
-                acc2 = fmaf(ch, sval.y, acc2);
+            for (int base = Jlo; base <= Jhi; base += 64) {
+                const int jj = base + lane;
+                if (jj <= Jhi) {
+                    const size_t r = (size_t)v * nd + jj;
+                    const float2 fl = flt[r];
+                    const float2 sv = sz[r];
+                    sfix[w][lane] = fix[r];
+                    sray[w][lane] = make_float4(fl.x, fl.y, sv.x, sv.y);
+                }
+                __builtin_amdgcn_wave_barrier();
+                const int ja = max(jl, base), jb = min(jh, base + 63);
+                for (int j = ja; j <= jb; ++j) {
+                    const int4 fx = sfix[w][j - base];
+                    const float4 fs = sray[w][j - base];
+                    const bool xm = fs.y > 0.f;
+                    const long long S = fix_s(fx);
+                    const bool up = S >= 0;
+                    const int maj0 = xm ? k0 : i0, mnr0 = xm ? i0 : k0;
+                    const long long ya = fix_a0(fx) + (long long)maj0 * S;
+                    const long long yb = ya + S;
+                    const float wa = first_weight((unsigned)ya, up, fs.x);
+                    const float wb = first_weight((unsigned)yb, up, fs.x);
+                    // minor row r0 = floor(y) gets w0, its neighbour r0 +- 1 gets 1 - w0;
+                    // e = r0 - mnr0, and row n of the quad is the neighbour when e == o_n
+                    const int ea = (int)(ya >> 32) - mnr0, eb = (int)(yb >> 32) - mnr0;
+                    const int o0 = up ? -1 : 1, o1 = up ? 0 : 2;
+                    const float ca0 = ea == 0 ? wa : (ea == o0 ? 1.f - wa : 0.f);
+                    const float ca1 = ea == 1 ? wa : (ea == o1 ? 1.f - wa : 0.f);
+                    const float cb0 = eb == 0 ? wb : (eb == o0 ? 1.f - wb : 0.f);
+                    const float cb1 = eb == 1 ? wb : (eb == o1 ? 1.f - wb : 0.f);
+                    // (major, minor) offsets -> (row, column) offsets of the quad
+                    const float c01 = xm ? cb0 : ca1, c10 = xm ? ca1 : cb0;
+                    const float L = fabsf(fs.y);
+                    const float s1 = L * fs.z, s2 = L * fs.w;
+                    a00x = fmaf(ca0, s1, a00x);
+                    a00y = fmaf(ca0, s2, a00y);
+                    a01x = fmaf(c01, s1, a01x);
+                    a01y = fmaf(c01, s2, a01y);
+                    a10x = fmaf(c10, s1, a10x);
+                    a10y = fmaf(c10, s2, a10y);
+                    a11x = fmaf(cb1, s1, a11x);
+                    a11y = fmaf(cb1, s2, a11y);
+                }
+                __builtin_amdgcn_wave_barrier();
             }
         }
     }
-    if (!inside) return;
+    red[w][0][lane] = a00x;
+    red[w][1][lane] = a00y;
+    red[w][2][lane] = a01x;
+    red[w][3][lane] = a01y;
+    red[w][4][lane] = a10x;
+    red[w][5][lane] = a10y;
+    red[w][6][lane] = a11x;
+    red[w][7][lane] = a11y;
+    __syncthreads();
+    if (threadIdx.x >= 256) return;
+    const int ti = threadIdx.x >> 4, tk = threadIdx.x & 15;
+    const int i = blockIdx.y * 16 + ti, k = blockIdx.x * 16 + tk;
+    if (i >= ny || k >= nx) return;
+    const int ql = (ti >> 1) * 8 + (tk >> 1);
+    const int slot = ((ti & 1) * 2 + (tk & 1)) * 2;
+    float s1 = 0.f, s2 = 0.f;
+#pragma unroll
+    for (int q = 0; q < kBpWaves; ++q) {
+        s1 += red[q][slot][ql];
+        s2 += red[q][slot + 1][ql];
+    }
     const size_t npix = (size_t)nx * ny;
     const size_t p = (size_t)i * nx + k;
     if (out_pairs) {
-        out_pairs[(size_t)z * npix + p] = make_float2(acc1, acc2);
+        out_pairs[(size_t)z * npix + p] = make_float2(s1, s2);
     } else {
-        out_split[(size_t)(2 * z) * npix + p] = acc1;
-        if (2 * z + 1 < nout) out_split[(size_t)(2 * z + 1) * npix + p] = acc2;
+        out_split[(size_t)(2 * z) * npix + p] = s1;
+        if (2 * z + 1 < nout) out_split[(size_t)(2 * z + 1) * npix + p] = s2;
     }
 }
 
@@ -400,9 +458,9 @@ void launch_backproject(const Geom& g, const RayTable& t, const float2* sino, in
                         float2* out_pairs, float* out_split, int nout, hipStream_t st) {
     dim3 grid((g.nx + 15) / 16, (g.ny + 15) / 16, npairs);
     const float u0 = (float)(-0.5 * (g.nd - 1) * g.pitch + g.offset);
-    hipLaunchKernelGGL(k_backproject, grid, dim3(256), 0, st, sino, t.fix, t.flt, t.view, g.nx, g.ny, g.nv,
-                       g.nd, (float)g.sid, (float)g.sdd, (float)g.dx, u0, (float)(1.0 / g.pitch),
-                       out_pairs, out_split, nout);
+    hipLaunchKernelGGL(k_backproject, grid, dim3(kBpWaves * 64), 0, st, sino, t.fix, t.flt, t.view,
+                       g.nx, g.ny, g.nv, g.nd, (float)g.sid, (float)g.sdd, (float)g.dx, u0,
+                       (float)(1.0 / g.pitch), out_pairs, out_split, nout);
 }
 
 }  // namespace dect
