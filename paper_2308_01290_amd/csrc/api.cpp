@@ -407,7 +407,7 @@ struct dect_solver {
     bool owns_ws;
     DevAlloc own;
     RayTable tab;
-    float2 *f, *B, *dN, *dT, *S, *zq, *fft;
+    float2 *f, *B, *dpad, *S, *zq, *fft;   // dpad: search direction in projector pair blocks
     float *rho, *t, *muL, *muH, *fbpq;
     double *part_img, *part_proj, *alpha;
     unsigned* cnt_proj;
@@ -513,15 +513,13 @@ int dect_project(const dect_geometry* gin, const float* img, float* sino, int32_
     if (int rc = get_table(g, st, &t)) return rc;
     const int np = (batch + 1) / 2;
     TempBuf tmp;
-    const size_t nN = padN_elems(g) * np, nT = padT_elems(g) * np;
-    if (int rc = temp_alloc(&tmp, (nN + nT) * sizeof(float2), st)) return rc;
-    float2* pN = static_cast<float2*>(tmp.p);
-    float2* pT = pN + nN;
-    launch_pack_pairs(g, img, batch, pN, pT, st);
+    if (int rc = temp_alloc(&tmp, pad_elems(g) * np * sizeof(float2), st)) return rc;
+    float2* pad = static_cast<float2*>(tmp.p);
+    launch_pack_pairs(g, img, batch, pad, st);
     ProjArgs a;
     a.out = sino;
     a.nout = batch;
-    launch_project(g, t, pN, pT, np, PROJ_PLAIN, a, st);
+    launch_project(g, t, pad, np, PROJ_PLAIN, a, st);
     DECT_HIP(hipGetLastError());
     return DECT_OK;
 }
@@ -631,8 +629,7 @@ static size_t solver_layout(const Geom& g, int batch, char* base, dect_solver* s
     void* tab = c.take<char>(ray_table_bytes(g));
     float2* f = c.take<float2>(npix);
     float2* B = c.take<float2>(npix);
-    float2* dN = c.take<float2>(padN_elems(g) * batch);
-    float2* dT = c.take<float2>(padT_elems(g) * batch);
+    float2* dpad = c.take<float2>(pad_elems(g) * batch);
     float2* S = c.take<float2>(nray);
     float2* zq = c.take<float2>(nray);   // also the FBP filter scratch at init
     float2* fft = c.take<float2>(npix);
@@ -649,8 +646,7 @@ static size_t solver_layout(const Geom& g, int batch, char* base, dect_solver* s
         s->tab = t;
         s->f = f;
         s->B = B;
-        s->dN = dN;
-        s->dT = dT;
+        s->dpad = dpad;
         s->S = S;
         s->zq = zq;
         s->fft = fft;
@@ -720,8 +716,7 @@ int dect_solver_create(const dect_geometry* gin, const dect_params* p, int32_t b
     solver_layout(g, batch, static_cast<char*>(s->ws), s);
     // zero borders of the padded direction layouts, counters and scalars once
     hipError_t e = hipSuccess;
-    e = e != hipSuccess ? e : hipMemsetAsync(s->dN, 0, padN_elems(g) * batch * sizeof(float2), st);
-    e = e != hipSuccess ? e : hipMemsetAsync(s->dT, 0, padT_elems(g) * batch * sizeof(float2), st);
+    e = e != hipSuccess ? e : hipMemsetAsync(s->dpad, 0, pad_elems(g) * batch * sizeof(float2), st);
     e = e != hipSuccess ? e : hipMemsetAsync(s->cnt_proj, 0, sizeof(unsigned) * batch, st);
 
     e = e != hipSuccess ? e : hipMemsetAsync(s->pcg.st, 0, sizeof(PcgState) * batch, st);
@@ -757,7 +752,7 @@ int dect_solver_destroy(dect_solver* s) {
 }
 
 static void project_residual(dect_solver* s, const float* lo, const float* hi) {
-    launch_pack_f2(s->g, s->f, s->batch, s->dN, s->dT, s->st);
+    launch_pack_f2(s->g, s->f, s->batch, s->dpad, s->st);
     ProjArgs a;
     a.p_lo = lo;
     a.p_hi = hi;
@@ -766,7 +761,7 @@ static void project_residual(dect_solver* s, const float* lo, const float* hi) {
     a.c01 = (float)s->M.C[0][1];
     a.c10 = (float)s->M.C[1][0];
     a.c11 = (float)s->M.C[1][1];
-    launch_project(s->g, s->tab, s->dN, s->dT, s->batch, PROJ_RESID, a, s->st);
+    launch_project(s->g, s->tab, s->dpad, s->batch, PROJ_RESID, a, s->st);
 }
 
 int dect_solver_init(dect_solver* s, const float* lo, const float* hi) {
@@ -818,7 +813,7 @@ static int one_iteration(dect_solver* s) {
     hipEvent_t t0 = mark(s);
     launch_backproject(g, s->tab, s->S, s->batch, s->B, nullptr, 0, s->st);
     mark_end(s, t0, s->ev_bp);
-    launch_grad(s->M, a, s->f, s->B, s->rho, s->t, s->dN, s->dT, s->part_img, s->st);
+    launch_grad(s->M, a, pad_layout(g), s->f, s->B, s->rho, s->t, s->dpad, s->part_img, s->st);
     ProjArgs pa;
     pa.res = s->zq;
     pa.c00 = (float)s->M.C[0][0];
@@ -834,7 +829,7 @@ static int one_iteration(dect_solver* s) {
     pa.alpha = s->alpha;
     pa.counter = s->cnt_proj;
     hipEvent_t t1 = mark(s);
-    launch_project(g, s->tab, s->dN, s->dT, s->batch, PROJ_LINESEARCH, pa, s->st);
+    launch_project(g, s->tab, s->dpad, s->batch, PROJ_LINESEARCH, pa, s->st);
     mark_end(s, t1, s->ev_fp);
     // rho_e step (reads f^(k), rho^(k))
     FftArgs fa;
@@ -865,7 +860,7 @@ static int one_iteration(dect_solver* s) {
     if (int rc = run_pcg(pc, s->pcg, R.p.t_maxit, s->last_pcg + 2, s->fft, s->st, &iters)) return rc;
     s->last_pcg = iters;
     // f^(k+1), residual sinograms
-    launch_update(a, s->alpha, s->dN, s->f, s->S, s->zq, s->st);
+    launch_update(a, pad_layout(g), s->alpha, s->dpad, s->f, s->S, s->zq, s->st);
     s->beta *= R.kappa;
     s->k += 1;
     DECT_HIP(hipGetLastError());

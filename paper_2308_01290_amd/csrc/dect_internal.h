@@ -54,19 +54,38 @@ void launch_build_ray_table(const Geom& g, RayTable t, hipStream_t st);
 
 // ---- packed image layouts for the projector --------------------------------
 // Two images travel together as float2.  The projector reads them from two
-// zero-padded layouts so that every ray step is a coalesced pair of loads:
-//   padN: [ny][nx + 2]  (row-major, one zero column on each side)
-//   padT: [nx][ny + 2]  (transposed, one zero row-entry on each side)
-inline size_t padN_elems(const Geom& g) { return (size_t)g.ny * (g.nx + 2); }
-inline size_t padT_elems(const Geom& g) { return (size_t)g.nx * (g.ny + 2); }
+// zero-padded layouts, stored back to back for each pair z:
+//   padN: [max(nx, ny)][nx + 2*kPad]  (row-major)
+//   padT: [max(nx, ny)][ny + 2*kPad]  (transposed)
+// with kPad zero entries at both ends of every line, so a ray step whose
+// minor coordinate is clamped into [-kPad, n + kPad) reads zeros only, and
+// zero lines past the last row (padN) or column (padT) of a non-square
+// image, so that every ray of a wavefront can step over the wavefront's
+// common major range.
+constexpr int kPad = 2;
+struct PadLayout {
+    int ldN, ldT;     // line strides (elements) of padN and padT
+    int lines;        // lines of each layout, max(nx, ny)
+    size_t offT;      // offset of padT within a pair block
+    size_t pair;      // elements per pair block
+};
+inline PadLayout pad_layout(const Geom& g) {
+    PadLayout L;
+    L.ldN = g.nx + 2 * kPad;
+    L.ldT = g.ny + 2 * kPad;
+    L.lines = g.nx > g.ny ? g.nx : g.ny;
+    L.offT = (size_t)L.lines * L.ldN;
+    L.pair = L.offT + (size_t)L.lines * L.ldT;
+    return L;
+}
+inline size_t pad_elems(const Geom& g) { return pad_layout(g).pair; }
 
-// pack img[2z], img[2z+1] ([ny][nx] each, f32) into padN/padT pairs z;
+// pack img[2z], img[2z+1] ([ny][nx] each, f32) into pair blocks z of `pad`
+// (every element of the blocks is written, the zero entries included);
 // nimg = number of source images (odd: the last pair's second channel is 0).
-void launch_pack_pairs(const Geom& g, const float* img, int nimg, float2* padN, float2* padT,
-                       hipStream_t st);
-// pack a float2 image [ny][nx] (pairs) into padN/padT
-void launch_pack_f2(const Geom& g, const float2* src, int npairs, float2* padN, float2* padT,
-                    hipStream_t st);
+void launch_pack_pairs(const Geom& g, const float* img, int nimg, float2* pad, hipStream_t st);
+// pack a float2 image [ny][nx] (pairs) into pair blocks
+void launch_pack_f2(const Geom& g, const float2* src, int npairs, float2* pad, hipStream_t st);
 // interleave sinograms s[2z], s[2z+1] into pairs (second channel 0 if missing)
 void launch_pair_sinos(const Geom& g, const float* sino, int nsino, float2* out, hipStream_t st);
 
@@ -91,8 +110,8 @@ struct ProjArgs {
     unsigned* counter = nullptr;                 // [z]
 };
 int proj_nblocks(const Geom& g);  // blocks per pair
-void launch_project(const Geom& g, const RayTable& t, const float2* padN, const float2* padT,
-                    int npairs, int mode, const ProjArgs& a, hipStream_t st);
+void launch_project(const Geom& g, const RayTable& t, const float2* pad, int npairs, int mode,
+                    const ProjArgs& a, hipStream_t st);
 
 // ---- back-projector -------------------------------------------------------------
 // sino pairs [z][nv][nd] -> out pairs [z][ny][nx] (float2) or split images.
@@ -164,11 +183,12 @@ int grad_nblocks(int ny, int nx);
 void launch_init_state(const Model& M, int ny, int nx, int batch, const float* muL,
                        const float* muH, float rho_min, float2* f, float* rho, float* t,
                        hipStream_t st);
-void launch_grad(const Model& M, const ImgArgs& a, const float2* f, const float2* B,
-                 const float* rho, const float* t, float2* dN, float2* dT, double* partials,
-                 hipStream_t st);
-void launch_update(const ImgArgs& a, const double* alpha, const float2* dN, float2* f,
-                   float2* S, const float2* zq, hipStream_t st);
+// the search direction is written into the projector's pair blocks `dpad`
+void launch_grad(const Model& M, const ImgArgs& a, const PadLayout& P, const float2* f,
+                 const float2* B, const float* rho, const float* t, float2* dpad,
+                 double* partials, hipStream_t st);
+void launch_update(const ImgArgs& a, const PadLayout& P, const double* alpha, const float2* dpad,
+                   float2* f, float2* S, const float2* zq, hipStream_t st);
 void launch_finish(const Model& M, int ny, int nx, int batch, const float* rho, const float* t,
                    float rho_min, double t_min, float* Z, float* rho_out, hipStream_t st);
 void launch_split_f2(int n, int batch, const float2* f, float* a, float* b, hipStream_t st);

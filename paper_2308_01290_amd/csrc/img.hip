@@ -91,11 +91,12 @@ __device__ __forceinline__ bool keep_grad(float dx, float dy, float thr) {
     return __fadd_rn(__fmul_rn(dx, dx), __fmul_rn(dy, dy)) > thr;
 }
 
-__global__ __launch_bounds__(256) void k_grad(ImgArgs a, GradConst gc, const float2* __restrict__ f,
+__global__ __launch_bounds__(256) void k_grad(ImgArgs a, GradConst gc, PadLayout P,
+                                              const float2* __restrict__ f,
                                               const float2* __restrict__ B,
                                               const float* __restrict__ rho,
-                                              const float* __restrict__ t, float2* __restrict__ dN,
-                                              float2* __restrict__ dT, double* __restrict__ partials) {
+                                              const float* __restrict__ t, float2* __restrict__ dpad,
+                                              double* __restrict__ partials) {
     __shared__ float2 fL[19][19];
     __shared__ float4 eL[18][18];
     __shared__ float2 dL[17][17];
@@ -144,7 +145,7 @@ __global__ __launch_bounds__(256) void k_grad(ImgArgs a, GradConst gc, const flo
             const double e1 = (double)gc.ms00 * d.x + (double)gc.ms01 * d.y;
             const double e2 = (double)gc.ms10 * d.x + (double)gc.ms11 * d.y;
             cq += e1 * e1 + e2 * e2;
-            dN[z * (size_t)ny * (nx + 2) + (size_t)(i0 + r) * (nx + 2) + (k0 + c) + 1] = d;
+            dpad[z * P.pair + (size_t)(i0 + r) * P.ldN + (k0 + c) + kPad] = d;
         }
     }
     __syncthreads();
@@ -157,7 +158,7 @@ __global__ __launch_bounds__(256) void k_grad(ImgArgs a, GradConst gc, const flo
         }
         // transposed layout: row k, entries i
         if (k0 + ty < nx && i0 + tx < ny)
-            dT[z * (size_t)nx * (ny + 2) + (size_t)(k0 + ty) * (ny + 2) + (i0 + tx) + 1] = dL[tx][ty];
+            dpad[z * P.pair + P.offT + (size_t)(k0 + ty) * P.ldT + (i0 + tx) + kPad] = dL[tx][ty];
     }
     const int nblk = gridDim.x * gridDim.y;
     const int bid = blockIdx.y * gridDim.x + blockIdx.x;
@@ -172,9 +173,9 @@ __global__ __launch_bounds__(256) void k_grad(ImgArgs a, GradConst gc, const flo
     }
 }
 
-void launch_grad(const Model& M, const ImgArgs& a, const float2* f, const float2* B,
-                 const float* rho, const float* t, float2* dN, float2* dT, double* partials,
-                 hipStream_t st) {
+void launch_grad(const Model& M, const ImgArgs& a, const PadLayout& P, const float2* f,
+                 const float2* B, const float* rho, const float* t, float2* dpad,
+                 double* partials, hipStream_t st) {
     GradConst gc;
     gc.ms00 = (float)M.Ms[0][0];
     gc.ms01 = (float)M.Ms[0][1];
@@ -185,12 +186,12 @@ void launch_grad(const Model& M, const ImgArgs& a, const float2* f, const float2
     gc.psi0 = (float)M.psi[0];
     gc.psi1 = (float)M.psi[1];
     dim3 grid((a.nx + 15) / 16, (a.ny + 15) / 16, a.batch);
-    hipLaunchKernelGGL(k_grad, grid, dim3(256), 0, st, a, gc, f, B, rho, t, dN, dT, partials);
+    hipLaunchKernelGGL(k_grad, grid, dim3(256), 0, st, a, gc, P, f, B, rho, t, dpad, partials);
 }
 
 // ---------------------------------------------------------------------------
-__global__ void k_update(int ny, int nx, size_t nray, const double* __restrict__ alpha,
-                         const float2* __restrict__ dN, float2* __restrict__ f,
+__global__ void k_update(int ny, int nx, size_t nray, PadLayout P, const double* __restrict__ alpha,
+                         const float2* __restrict__ dpad, float2* __restrict__ f,
                          float2* __restrict__ S, const float2* __restrict__ zq) {
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int z = blockIdx.y;
@@ -198,7 +199,7 @@ __global__ void k_update(int ny, int nx, size_t nray, const double* __restrict__
     const float al = (float)alpha[z];
     if (idx < npix) {
         const int i = (int)(idx / nx), k = (int)(idx % nx);
-        const float2 d = dN[z * (size_t)ny * (nx + 2) + (size_t)i * (nx + 2) + k + 1];
+        const float2 d = dpad[z * P.pair + (size_t)i * P.ldN + k + kPad];
         float2 v = f[z * npix + idx];
         v.x = fmaf(al, d.x, v.x);
         v.y = fmaf(al, d.y, v.y);
@@ -213,11 +214,11 @@ __global__ void k_update(int ny, int nx, size_t nray, const double* __restrict__
     }
 }
 
-void launch_update(const ImgArgs& a, const double* alpha, const float2* dN, float2* f, float2* S,
-                   const float2* zq, hipStream_t st) {
+void launch_update(const ImgArgs& a, const PadLayout& P, const double* alpha, const float2* dpad,
+                   float2* f, float2* S, const float2* zq, hipStream_t st) {
     const size_t n = (size_t)a.nx * a.ny + (size_t)a.nv * a.nd;
     hipLaunchKernelGGL(k_update, dim3((unsigned)((n + 255) / 256), a.batch), dim3(256), 0, st, a.ny,
-                       a.nx, (size_t)a.nv * a.nd, alpha, dN, f, S, zq);
+                       a.nx, (size_t)a.nv * a.nd, P, alpha, dpad, f, S, zq);
 }
 
 // ---------------------------------------------------------------------------

@@ -30,11 +30,11 @@ __device__ __forceinline__ long long fix_s(int4 f) {
     return (long long)(((unsigned long long)(unsigned)f.w << 32) | (unsigned)f.z);
 }
 // Fraction of the major step [y, y + s] spent in pixel floor(y): (1 - frac)/s
-// when s >= 0, frac/|s| when s < 0, capped at 1.  lo = fractional bits of y.
-__device__ __forceinline__ float first_weight(unsigned lo, bool up, float ainv) {
-    const float fdown = (float)lo * 0x1p-32f;
-    const float fup = lo ? (float)(0u - lo) * 0x1p-32f : 1.0f;
-    return fminf((up ? fup : fdown) * ainv, 1.0f);
+// when s >= 0, frac/|s| when s < 0, capped at 1.  lo = fractional bits of y;
+// xmask = ~0 when s >= 0 (then lo ^ xmask = 2^32 - 1 - lo, which is 1 - frac
+// to 2^-32), else 0; ainv32 = 2^-32 / |s| (table entry).
+__device__ __forceinline__ float first_weight(unsigned lo, unsigned xmask, float ainv32) {
+    return fminf((float)(lo ^ xmask) * ainv32, 1.0f);
 }
 
 // ---------------------------------------------------------------------------
@@ -107,7 +107,7 @@ __global__ void k_build_ray_table(Geom g, int4* __restrict__ fix, float2* __rest
     const size_t r = (size_t)v * g.nd + j;
     fix[r] = make_int4((int)(unsigned)(A0 & 0xffffffffLL), (int)(A0 >> 32),
                        (int)(unsigned)(S & 0xffffffffLL), (int)(S >> 32));
-    flt[r] = make_float2(slope == 0.0 ? __builtin_inff() : (float)fabs(1.0 / slope),
+    flt[r] = make_float2(slope == 0.0 ? __builtin_inff() : (float)(fabs(1.0 / slope) * 0x1p-32),
                          xmaj ? (float)L : -(float)L);
     span[r] = make_int2(klo, khi);
 }
@@ -122,17 +122,18 @@ void launch_build_ray_table(const Geom& g, RayTable t, hipStream_t st) {
 // ---------------------------------------------------------------------------
 template <typename SRC>
 __global__ __launch_bounds__(256) void k_pack(const SRC* __restrict__ src, int nsrc, int nx, int ny,
-                                              float2* __restrict__ padN, float2* __restrict__ padT) {
+                                              PadLayout P, float2* __restrict__ pad) {
     __shared__ float2 tile[32][33];
     const int z = blockIdx.z;
     const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
     const size_t npix = (size_t)nx * ny;
-    float2* pn = padN + (size_t)z * ny * (nx + 2);
-    float2* pt = padT + (size_t)z * nx * (ny + 2);
+    float2* pn = pad + (size_t)z * P.pair;
+    float2* pt = pn + P.offT;
+    const float2 zero = make_float2(0.f, 0.f);
     for (int r = ty; r < 32; r += 8) {
         const int i = by + r, k = bx + tx;
-        float2 val = make_float2(0.f, 0.f);
+        float2 val = zero;
         if (i < ny && k < nx) {
             if constexpr (sizeof(SRC) == sizeof(float2)) {
                 val = reinterpret_cast<const float2*>(src)[(size_t)z * npix + (size_t)i * nx + k];
@@ -141,36 +142,56 @@ __global__ __launch_bounds__(256) void k_pack(const SRC* __restrict__ src, int n
                 val.x = s[(size_t)(2 * z) * npix + (size_t)i * nx + k];
                 if (2 * z + 1 < nsrc) val.y = s[(size_t)(2 * z + 1) * npix + (size_t)i * nx + k];
             }
-            pn[(size_t)i * (nx + 2) + k + 1] = val;
+            pn[(size_t)i * P.ldN + k + kPad] = val;
         }
         tile[r][tx] = val;
-        if (i < ny && tx == 0) {
-            if (blockIdx.x == 0) pn[(size_t)i * (nx + 2)] = make_float2(0.f, 0.f);
-            if (blockIdx.x == gridDim.x - 1) pn[(size_t)i * (nx + 2) + nx + 1] = make_float2(0.f, 0.f);
+        if (i < ny && tx < kPad) {   // zero ends of row i
+            if (blockIdx.x == 0) pn[(size_t)i * P.ldN + tx] = zero;
+            if (blockIdx.x == gridDim.x - 1) pn[(size_t)i * P.ldN + kPad + nx + tx] = zero;
         }
     }
     __syncthreads();
     for (int r = ty; r < 32; r += 8) {
         const int k = bx + r, i = by + tx;
-        if (k < nx && i < ny) pt[(size_t)k * (ny + 2) + i + 1] = tile[tx][r];
-        if (k < nx && tx == 0) {
-            if (blockIdx.y == 0) pt[(size_t)k * (ny + 2)] = make_float2(0.f, 0.f);
-            if (blockIdx.y == gridDim.y - 1) pt[(size_t)k * (ny + 2) + ny + 1] = make_float2(0.f, 0.f);
+        if (k < nx && i < ny) pt[(size_t)k * P.ldT + i + kPad] = tile[tx][r];
+        if (k < nx && tx < kPad) {   // zero ends of column k
+            if (blockIdx.y == 0) pt[(size_t)k * P.ldT + tx] = zero;
+            if (blockIdx.y == gridDim.y - 1) pt[(size_t)k * P.ldT + kPad + ny + tx] = zero;
         }
     }
 }
 
-void launch_pack_pairs(const Geom& g, const float* img, int nimg, float2* padN, float2* padT,
-                       hipStream_t st) {
-    dim3 grid((g.nx + 31) / 32, (g.ny + 31) / 32, (nimg + 1) / 2);
-    hipLaunchKernelGGL(k_pack<float>, grid, dim3(256), 0, st, img, nimg, g.nx, g.ny, padN, padT);
+// zero lines of a non-square image's layouts: padN rows ny.., padT columns nx..
+__global__ void k_zero_lines(PadLayout P, int nx, int ny, float2* __restrict__ pad) {
+    const size_t nN = (size_t)(P.lines - ny) * P.ldN, nT = (size_t)(P.lines - nx) * P.ldT;
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float2* b = pad + (size_t)blockIdx.y * P.pair;
+    if (e < nN)
+        b[(size_t)ny * P.ldN + e] = make_float2(0.f, 0.f);
+    else if (e < nN + nT)
+        b[P.offT + (size_t)nx * P.ldT + (e - nN)] = make_float2(0.f, 0.f);
 }
 
-void launch_pack_f2(const Geom& g, const float2* src, int npairs, float2* padN, float2* padT,
-                    hipStream_t st) {
+static void launch_zero_lines(const Geom& g, int npairs, float2* pad, hipStream_t st) {
+    if (g.nx == g.ny) return;
+    const PadLayout P = pad_layout(g);
+    const size_t n = (size_t)(P.lines - g.ny) * P.ldN + (size_t)(P.lines - g.nx) * P.ldT;
+    hipLaunchKernelGGL(k_zero_lines, dim3((unsigned)((n + 255) / 256), npairs), dim3(256), 0, st, P,
+                       g.nx, g.ny, pad);
+}
+
+void launch_pack_pairs(const Geom& g, const float* img, int nimg, float2* pad, hipStream_t st) {
+    dim3 grid((g.nx + 31) / 32, (g.ny + 31) / 32, (nimg + 1) / 2);
+    hipLaunchKernelGGL(k_pack<float>, grid, dim3(256), 0, st, img, nimg, g.nx, g.ny, pad_layout(g),
+                       pad);
+    launch_zero_lines(g, (nimg + 1) / 2, pad, st);
+}
+
+void launch_pack_f2(const Geom& g, const float2* src, int npairs, float2* pad, hipStream_t st) {
     dim3 grid((g.nx + 31) / 32, (g.ny + 31) / 32, npairs);
-    hipLaunchKernelGGL(k_pack<float2>, grid, dim3(256), 0, st, src, 2 * npairs, g.nx, g.ny, padN,
-                       padT);
+    hipLaunchKernelGGL(k_pack<float2>, grid, dim3(256), 0, st, src, 2 * npairs, g.nx, g.ny,
+                       pad_layout(g), pad);
+    launch_zero_lines(g, npairs, pad, st);
 }
 
 __global__ void k_pair_sinos(const float* __restrict__ s, int nsino, size_t nray,
@@ -193,6 +214,13 @@ void launch_pair_sinos(const Geom& g, const float* sino, int nsino, float2* out,
 // ---------------------------------------------------------------------------
 // forward projector: one lane per ray, 256 adjacent bins of one view per block
 // ---------------------------------------------------------------------------
+// clamp to [lo, hi] (lo <= hi) in one VALU operation
+__device__ __forceinline__ int clamp_med3(int x, int lo, int hi) {
+    int r;
+    asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "v"(hi));
+    return r;
+}
+
 __device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
     const float y = x - c;
     const float t = s + y;
@@ -203,8 +231,7 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
 int proj_nblocks(const Geom& g) { return ((g.nd + 255) / 256) * g.nv; }
 
 template <int MODE>
-__global__ __launch_bounds__(256) void k_project(const float2* __restrict__ padN,
-                                                 const float2* __restrict__ padT,
+__global__ __launch_bounds__(256) void k_project(const float2* __restrict__ pad, PadLayout P,
                                                  const int4* __restrict__ fix,
                                                  const float2* __restrict__ flt,
                                                  const int2* __restrict__ span, int nx, int ny,
@@ -218,50 +245,64 @@ __global__ __launch_bounds__(256) void k_project(const float2* __restrict__ padN
     const int2 sp = valid ? span[r] : make_int2(1, 0);
     const bool xmaj = fl.y > 0.f;
     const float L = fabsf(fl.y);
-    const float ainv = fl.x;
+    const float ainv32 = fl.x;
     const long long S = fix_s(fx);
     const bool up = S >= 0;
+    const unsigned xmask = up ? ~0u : 0u;
     const int nmin = xmaj ? ny : nx;
-    const int nmaj = xmaj ? nx : ny;
-    const int stride = nmin + 2;
-    const float2* base = xmaj ? padT + (size_t)z * nx * (ny + 2) : padN + (size_t)z * ny * (nx + 2);
-    base += 1;
-    const int rlo = up ? -1 : 0, rhi = up ? nmin - 1 : nmin;
-    const int step = up ? 1 : -1;
-    // weight of the first pixel when the step lies wholly above / below the image
-    const float w_above = up ? 0.f : 1.f, w_below = up ? 1.f : 0.f;
+    // Step k reads minor entries r' and r' + 1 of major line k, r' = r0 (s >= 0:
+    // pixels r0, r0 + 1) or r0 - 1 (s < 0: pixels r0, r0 - 1), with r0 = floor(y)
+    // clamped so that both entries stay inside the line's zero ends; a clamped
+    // step reads zeros only.  Byte offsets are 32-bit, relative to the pair block.
+    const int rlo = up ? -kPad : 1 - kPad, rhi = up ? nmin : nmin + 1;
+    const float wa = up ? 0.f : 1.f, wb = up ? 1.f : -1.f;   // weight of entry r': wa + wb * w0
+    const unsigned lstep = 8u * (unsigned)(xmaj ? P.ldT : P.ldN);
     int klo = sp.x, khi = sp.y;
     if (klo > khi) {
         klo = INT_MAX;
         khi = INT_MIN;
     }
     const int ks = wave_min(klo), ke = wave_max(khi);
-    long long y = fix_a0(fx) + (long long)(ks == INT_MAX ? 0 : ks) * S;
+    const int k0 = ks == INT_MAX ? 0 : ks;
+    long long y = fix_a0(fx) + (long long)k0 * S;
+    unsigned loff = 8u * (unsigned)((xmaj ? P.offT : 0) + kPad + (up ? 0 : -1)) + (unsigned)k0 * lstep;
+    const char* zb = reinterpret_cast<const char*>(pad + (size_t)z * P.pair);
     float s1 = 0.f, c1 = 0.f, s2 = 0.f, c2 = 0.f;
-    for (int k = ks; k <= ke; ++k, y += S) {
-        const int kk = min(k, nmaj - 1);
-        const int hi = (int)(y >> 32);
-        int r0;
-        float w0;
-        if (hi > rhi) {
-            r0 = rhi;
-            w0 = w_above;
-        } else if (hi < rlo) {
-            r0 = rlo;
-            w0 = w_below;
-        } else {
-            r0 = hi;
-            w0 = first_weight((unsigned)y, up, ainv);
+    const int nstep = ks <= ke ? ke - ks + 1 : 0;   // wave-uniform
+    int k = 0;
+    for (; k + 4 <= nstep; k += 4) {
+        float2 A[4], B[4];
+        float W[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int r0 = clamp_med3((int)(y >> 32), rlo, rhi);
+            const unsigned off = loff + ((unsigned)r0 << 3);
+            A[u] = *reinterpret_cast<const float2*>(zb + off);
+            B[u] = *reinterpret_cast<const float2*>(zb + off + 8);
+            W[u] = fmaf(wb, first_weight((unsigned)y, xmask, ainv32), wa);
+            y += S;
+            loff += lstep;
         }
-        const float2* row = base + (size_t)kk * stride;
-        const float2 gA = row[r0];
-        const float2 gB = row[r0 + step];
-        const float v1 = fmaf(w0, gA.x - gB.x, gB.x);
-        const float v2 = fmaf(w0, gA.y - gB.y, gB.y);
-        if (k >= klo && k <= khi) {
-            kahan_add(s1, c1, v1);
-            kahan_add(s2, c2, v2);
+        // four steps summed pairwise, the group sum added with compensation
+        float v1[4], v2[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            v1[u] = fmaf(W[u], A[u].x - B[u].x, B[u].x);
+            v2[u] = fmaf(W[u], A[u].y - B[u].y, B[u].y);
         }
+        kahan_add(s1, c1, (v1[0] + v1[1]) + (v1[2] + v1[3]));
+        kahan_add(s2, c2, (v2[0] + v2[1]) + (v2[2] + v2[3]));
+    }
+    for (; k < nstep; ++k) {
+        const int r0 = clamp_med3((int)(y >> 32), rlo, rhi);
+        const unsigned off = loff + ((unsigned)r0 << 3);
+        const float2 A = *reinterpret_cast<const float2*>(zb + off);
+        const float2 B = *reinterpret_cast<const float2*>(zb + off + 8);
+        const float W = fmaf(wb, first_weight((unsigned)y, xmask, ainv32), wa);
+        kahan_add(s1, c1, fmaf(W, A.x - B.x, B.x));
+        kahan_add(s2, c2, fmaf(W, A.y - B.y, B.y));
+        y += S;
+        loff += lstep;
     }
     const double Y1 = (double)L * ((double)s1 - (double)c1);
     const double Y2 = (double)L * ((double)s2 - (double)c2);
@@ -306,18 +347,19 @@ __global__ __launch_bounds__(256) void k_project(const float2* __restrict__ padN
     }
 }
 
-void launch_project(const Geom& g, const RayTable& t, const float2* padN, const float2* padT,
-                    int npairs, int mode, const ProjArgs& a, hipStream_t st) {
+void launch_project(const Geom& g, const RayTable& t, const float2* pad, int npairs, int mode,
+                    const ProjArgs& a, hipStream_t st) {
     dim3 grid((g.nd + 255) / 256, g.nv, npairs);
+    const PadLayout P = pad_layout(g);
     if (mode == PROJ_PLAIN)
-        hipLaunchKernelGGL(k_project<PROJ_PLAIN>, grid, dim3(256), 0, st, padN, padT, t.fix, t.flt,
+        hipLaunchKernelGGL(k_project<PROJ_PLAIN>, grid, dim3(256), 0, st, pad, P, t.fix, t.flt,
                            t.span, g.nx, g.ny, g.nv, g.nd, a);
     else if (mode == PROJ_RESID)
-        hipLaunchKernelGGL(k_project<PROJ_RESID>, grid, dim3(256), 0, st, padN, padT, t.fix, t.flt,
+        hipLaunchKernelGGL(k_project<PROJ_RESID>, grid, dim3(256), 0, st, pad, P, t.fix, t.flt,
                            t.span, g.nx, g.ny, g.nv, g.nd, a);
     else
-        hipLaunchKernelGGL(k_project<PROJ_LINESEARCH>, grid, dim3(256), 0, st, padN, padT, t.fix,
-                           t.flt, t.span, g.nx, g.ny, g.nv, g.nd, a);
+        hipLaunchKernelGGL(k_project<PROJ_LINESEARCH>, grid, dim3(256), 0, st, pad, P, t.fix, t.flt,
+                           t.span, g.nx, g.ny, g.nv, g.nd, a);
 }
 
 // ---------------------------------------------------------------------------
@@ -340,7 +382,7 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_backproject(
     float* __restrict__ out_split, int nout) {
     __shared__ float4 vs[kBpViewChunk];
     __shared__ int4 sfix[kBpWaves][64];
-    __shared__ float4 sray[kBpWaves][64];      // (|1/s|, +-L, sino lo, sino hi)
+    __shared__ float4 sray[kBpWaves][64];      // (2^-32/|s|, +-L, sino lo, sino hi)
     __shared__ float red[kBpWaves][8][64];
     const int z = blockIdx.z;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -396,8 +438,9 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_backproject(
                     const int maj0 = xm ? k0 : i0, mnr0 = xm ? i0 : k0;
                     const long long ya = fix_a0(fx) + (long long)maj0 * S;
                     const long long yb = ya + S;
-                    const float wa = first_weight((unsigned)ya, up, fs.x);
-                    const float wb = first_weight((unsigned)yb, up, fs.x);
+                    const unsigned xmask = up ? ~0u : 0u;
+                    const float wa = first_weight((unsigned)ya, xmask, fs.x);
+                    const float wb = first_weight((unsigned)yb, xmask, fs.x);
                     // minor row r0 = floor(y) gets w0, its neighbour r0 +- 1 gets 1 - w0;
                     // e = r0 - mnr0, and row n of the quad is the neighbour when e == o_n
                     const int ea = (int)(ya >> 32) - mnr0, eb = (int)(yb >> 32) - mnr0;
