@@ -5,18 +5,18 @@
 // Level l is the grid coarsened 2^l times per axis (cell-centred), with the
 // operator re-discretised as A_l = diag(c_l) + (beta / 4^l) L and c_l the 2x2
 // average of c_(l-1).  Transfers: restriction = 2x2 average, prolongation =
-// piecewise constant (R = P^T / 4).  Smoothing: two damped-Jacobi sweeps
-// (omega = 0.8) before the coarse correction, starting from zero, and two
+// piecewise constant (R = P^T / 4).  Smoothing: kMgNu damped-Jacobi sweeps
+// (omega = 0.8) before the coarse correction, starting from zero, and kMgNu
 // after it.  The coarsest grid (an odd side, or 1 x 1; at most 64 unknowns) is
 // solved exactly by Gaussian elimination.  The V-cycle is therefore a fixed
 // symmetric linear map, as PCG requires; it has no atomics, so it is
 // deterministic.
 //
-// Kernels: for every level whose larger side exceeds 64, one fused kernel
-// going down (two sweeps, residual, restriction) and one going up
-// (prolongation, two sweeps), on 16 x 16 tiles with a two-pixel halo; all
-// smaller levels run in one workgroup per slice with every level resident in
-// LDS.
+// Kernels: for every level whose larger side exceeds 32, one fused kernel
+// going down (sweeps, residual, restriction) and one going up (prolongation,
+// sweeps), on 16 x 16 tiles with a kMgNu-pixel halo; all smaller levels run
+// in one wavefront per slice with every level resident in LDS, so their
+// phases are short.
 #include <algorithm>
 
 #include "dect_internal.h"
@@ -25,10 +25,18 @@
 namespace dect {
 
 constexpr float kOmega = 0.8f;
-constexpr int kMgCoarseMax = 64;          // larger side at which the in-LDS kernel takes over
-constexpr int kMgCoarseThreads = 1024;
+constexpr int kMgNu = 3;                  // smoothing sweeps before and after the correction
+constexpr int kMgCoarseMax = 32;          // larger side at which the in-LDS kernel takes over
+constexpr int kMgCoarseThreads = 256;
 constexpr size_t kMgLdsMax = 160 * 1024;  // LDS of one workgroup on gfx950
 constexpr size_t kMgLdsStatic = 1024;     // reserved for the in-LDS kernel's static arrays
+
+// (t / n, t % n) for t < 2^12, n <= 64: floor((t + 1/2) / n) in FP32 is exact
+// there (the fraction stays at least 1/(2n) away from an integer)
+__device__ __forceinline__ void divmod_small(int t, int n, float inv_n, int& q, int& r) {
+    q = (int)(((float)t + 0.5f) * inv_n);
+    r = t - q * n;
+}
 
 // one damped-Jacobi sweep at a pixel: x + omega (b - A x) / diag(A)
 __device__ __forceinline__ float jac(float x, float b, float c, float beta, float nsum) {
@@ -130,35 +138,51 @@ struct MgLevel {
     float beta;
 };
 
+constexpr int kTile = 16;
+constexpr int kW0 = kTile + 2 * kMgNu;   // tile with halo
+
+// one sweep over the square [off, off + n)^2 of the halo tile: dst = J(src)
+__device__ __forceinline__ void tile_sweep(const float (*X)[kW0 + 1], float (*Y)[kW0 + 1],
+                                           const float (*B)[kW0 + 1], const float (*C)[kW0 + 1],
+                                           int off, int n, float be) {
+    for (int t = threadIdx.x; t < n * n; t += 256) {
+        const int r = off + t / n, s = off + t % n;
+        const float ns = X[r - 1][s] + X[r + 1][s] + X[r][s - 1] + X[r][s + 1];
+        Y[r][s] = jac(X[r][s], B[r][s], C[r][s], be, ns);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_mg_down(MgLevel L, const int* skip, size_t skip_zstride) {
-    __shared__ float B[20][21], C[20][21], X1[20][21], X2[18][19], R[16][17];
+    __shared__ float B[kW0][kW0 + 1], C[kW0][kW0 + 1], X[2][kW0][kW0 + 1], R[kTile][kTile + 1];
     const int z = blockIdx.z;
     if (mg_skip(skip, skip_zstride, z)) return;
-    const int i0 = blockIdx.y * 16, k0 = blockIdx.x * 16;
+    const int i0 = blockIdx.y * kTile, k0 = blockIdx.x * kTile;
     const float* b = L.b + (size_t)z * L.zs_b;
     const float* c = L.c + (size_t)z * L.zs_c;
     const float be = L.beta;
-    for (int t = threadIdx.x; t < 400; t += 256) {
-        const int r = t / 20, s = t % 20;
-        const size_t g = (size_t)wrap_near(i0 - 2 + r, L.ny) * L.nx + wrap_near(k0 - 2 + s, L.nx);
+    for (int t = threadIdx.x; t < kW0 * kW0; t += 256) {
+        const int r = t / kW0, s = t % kW0;
+        const size_t g = (size_t)wrap_near(i0 - kMgNu + r, L.ny) * L.nx +
+                         wrap_near(k0 - kMgNu + s, L.nx);
         const float bb = b[g], cc = c[g];
         B[r][s] = bb;
         C[r][s] = cc;
-        X1[r][s] = kOmega * bb / (cc + 4.f * be);   // first sweep from zero
+        X[0][r][s] = kOmega * bb / (cc + 4.f * be);   // first sweep from zero
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < 324; t += 256) {
-        const int r = t / 18 + 1, s = t % 18 + 1;
-        const float ns = X1[r - 1][s] + X1[r + 1][s] + X1[r][s - 1] + X1[r][s + 1];
-        X2[r - 1][s - 1] = jac(X1[r][s], B[r][s], C[r][s], be, ns);
+    // sweep q (q = 2..nu) reads X[q - 2 mod 2], writes X[q - 1 mod 2], valid on [q - 1, kW0 - q + 1)
+#pragma unroll
+    for (int q = 2; q <= kMgNu; ++q) {
+        tile_sweep(X[(q - 2) & 1], X[(q - 1) & 1], B, C, q - 1, kW0 - 2 * (q - 1), be);
+        __syncthreads();
     }
-    __syncthreads();
+    const float (*Xn)[kW0 + 1] = X[(kMgNu - 1) & 1];   // sweep nu, valid on [nu - 1, kW0 - nu + 1)
     {
-        const int r = threadIdx.x / 16 + 2, s = threadIdx.x % 16 + 2;
-        const float x = X2[r - 1][s - 1];
-        const float ns = X2[r - 2][s - 1] + X2[r][s - 1] + X2[r - 1][s - 2] + X2[r - 1][s];
-        R[r - 2][s - 2] = B[r][s] - (C[r][s] * x + be * (4.f * x - ns));
-        L.xs[(size_t)z * L.zs_xs + (size_t)(i0 + r - 2) * L.nx + (k0 + s - 2)] = x;
+        const int r = threadIdx.x / kTile + kMgNu, s = threadIdx.x % kTile + kMgNu;
+        const float x = Xn[r][s];
+        const float ns = Xn[r - 1][s] + Xn[r + 1][s] + Xn[r][s - 1] + Xn[r][s + 1];
+        R[r - kMgNu][s - kMgNu] = B[r][s] - (C[r][s] * x + be * (4.f * x - ns));
+        L.xs[(size_t)z * L.zs_xs + (size_t)(i0 + r - kMgNu) * L.nx + (k0 + s - kMgNu)] = x;
     }
     __syncthreads();
     if (threadIdx.x < 64) {
@@ -169,40 +193,41 @@ __global__ __launch_bounds__(256) void k_mg_down(MgLevel L, const int* skip, siz
     }
 }
 
-// y0 = xs + P e; two sweeps; out = y2.  With `dot` (finest level) the tile's
+// y0 = xs + P e; nu sweeps; out = y_nu.  With `dot` (finest level) the tile's
 // <b, out> goes to dot[z*dot_zstride + tile].
 __global__ __launch_bounds__(256) void k_mg_up(MgLevel L, const int* skip, size_t skip_zstride,
                                                double* dot, size_t dot_zstride) {
-    __shared__ float B[20][21], C[20][21], Y0[20][21], Y1[18][19];
+    __shared__ float B[kW0][kW0 + 1], C[kW0][kW0 + 1], Y[2][kW0][kW0 + 1];
     __shared__ double sh[4];
     const int z = blockIdx.z;
     if (mg_skip(skip, skip_zstride, z)) return;
-    const int i0 = blockIdx.y * 16, k0 = blockIdx.x * 16;
+    const int i0 = blockIdx.y * kTile, k0 = blockIdx.x * kTile;
     const float* b = L.b + (size_t)z * L.zs_b;
     const float* c = L.c + (size_t)z * L.zs_c;
     const float* xs = L.xs + (size_t)z * L.zs_xs;
     const float* e = L.e + (size_t)z * L.zs_e;
     const int nxc = L.nx / 2;
     const float be = L.beta;
-    for (int t = threadIdx.x; t < 400; t += 256) {
-        const int r = t / 20, s = t % 20;
-        const int gi = wrap_near(i0 - 2 + r, L.ny), gk = wrap_near(k0 - 2 + s, L.nx);
+    for (int t = threadIdx.x; t < kW0 * kW0; t += 256) {
+        const int r = t / kW0, s = t % kW0;
+        const int gi = wrap_near(i0 - kMgNu + r, L.ny), gk = wrap_near(k0 - kMgNu + s, L.nx);
         const size_t g = (size_t)gi * L.nx + gk;
         B[r][s] = b[g];
         C[r][s] = c[g];
-        Y0[r][s] = xs[g] + e[(size_t)(gi / 2) * nxc + gk / 2];
+        Y[0][r][s] = xs[g] + e[(size_t)(gi / 2) * nxc + gk / 2];
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < 324; t += 256) {
-        const int r = t / 18 + 1, s = t % 18 + 1;
-        const float ns = Y0[r - 1][s] + Y0[r + 1][s] + Y0[r][s - 1] + Y0[r][s + 1];
-        Y1[r - 1][s - 1] = jac(Y0[r][s], B[r][s], C[r][s], be, ns);
+    // sweep q (q = 1..nu - 1) is valid on [q, kW0 - q)
+#pragma unroll
+    for (int q = 1; q < kMgNu; ++q) {
+        tile_sweep(Y[(q - 1) & 1], Y[q & 1], B, C, q, kW0 - 2 * q, be);
+        __syncthreads();
     }
-    __syncthreads();
-    const int r = threadIdx.x / 16 + 2, s = threadIdx.x % 16 + 2;
-    const float ns = Y1[r - 2][s - 1] + Y1[r][s - 1] + Y1[r - 1][s - 2] + Y1[r - 1][s];
-    const float y = jac(Y1[r - 1][s - 1], B[r][s], C[r][s], be, ns);
-    L.out[(size_t)z * L.zs_out + (size_t)(i0 + r - 2) * L.nx + (k0 + s - 2)] = y;
+    const float (*Yp)[kW0 + 1] = Y[(kMgNu - 1) & 1];
+    const int r = threadIdx.x / kTile + kMgNu, s = threadIdx.x % kTile + kMgNu;
+    const float ns = Yp[r - 1][s] + Yp[r + 1][s] + Yp[r][s - 1] + Yp[r][s + 1];
+    const float y = jac(Yp[r][s], B[r][s], C[r][s], be, ns);
+    L.out[(size_t)z * L.zs_out + (size_t)(i0 + r - kMgNu) * L.nx + (k0 + s - kMgNu)] = y;
     if (dot) {
         const double v = block_sum<256>((double)y * (double)B[r][s], sh);
         if (threadIdx.x == 0) dot[(size_t)z * dot_zstride + blockIdx.y * gridDim.x + blockIdx.x] = v;
@@ -210,7 +235,7 @@ __global__ __launch_bounds__(256) void k_mg_up(MgLevel L, const int* skip, size_
 }
 
 // ---------------------------------------------------------------------------
-// all levels with larger side <= 64 in one workgroup per slice, in LDS
+// all levels with larger side <= 32 in one workgroup per slice, in LDS
 // ---------------------------------------------------------------------------
 struct MgCoarse {
     const float* b;       // right-hand side of the first in-LDS level
@@ -227,12 +252,14 @@ struct MgCoarse {
 // y = one damped-Jacobi sweep of x (x = 0 when from_zero), periodic grid
 __device__ void lds_sweep(const float* x, const float* b, const float* c, float* y, int ny, int nx,
                           float beta, bool from_zero) {
+    const float inv_nx = 1.f / (float)nx;
     for (int t = threadIdx.x; t < ny * nx; t += blockDim.x) {
         if (from_zero) {
             y[t] = kOmega * b[t] / (c[t] + 4.f * beta);
             continue;
         }
-        const int i = t / nx, k = t % nx;
+        int i, k;
+        divmod_small(t, nx, inv_nx, i, k);
         const int ip = (i + 1 == ny) ? 0 : i + 1, im = (i == 0) ? ny - 1 : i - 1;
         const int kp = (k + 1 == nx) ? 0 : k + 1, km = (k == 0) ? nx - 1 : k - 1;
         const float ns = x[ip * nx + k] + x[im * nx + k] + x[i * nx + kp] + x[i * nx + km];
@@ -273,22 +300,31 @@ __global__ __launch_bounds__(kMgCoarseThreads) void k_mg_coarse(MgCoarse G, cons
     __syncthreads();
     for (int l = 0; l + 1 < G.nlev; ++l) {
         const int nyc = s_ny[l + 1], nxc = s_nx[l + 1], nxf = s_nx[l];
+        const float inv_nxc = 1.f / (float)nxc;
         for (int t = threadIdx.x; t < nyc * nxc; t += blockDim.x) {
-            const int i = t / nxc, k = t % nxc;
+            int i, k;
+            divmod_small(t, nxc, inv_nxc, i, k);
             const int a = (2 * i) * nxf + 2 * k;
             cl(l + 1)[t] = 0.25f * (cl(l)[a] + cl(l)[a + 1] + cl(l)[a + nxf] + cl(l)[a + nxf + 1]);
         }
         __syncthreads();
     }
-    // down: two sweeps from zero, residual, restriction
+    // down: nu sweeps from zero (sweep q lands in x_l when nu - q is even, else
+    // in t0), residual, restriction
     float beta = G.beta;
     for (int l = 0; l + 1 < G.nlev; ++l, beta *= 0.25f) {
         const int ny = s_ny[l], nx = s_nx[l];
-        lds_sweep(nullptr, bl(l), cl(l), t0, ny, nx, beta, true);
-        lds_sweep(t0, bl(l), cl(l), xl(l), ny, nx, beta, false);
+        float* src = nullptr;
+        for (int q = 1; q <= kMgNu; ++q) {
+            float* dst = ((kMgNu - q) & 1) ? t0 : xl(l);
+            lds_sweep(src, bl(l), cl(l), dst, ny, nx, beta, q == 1);
+            src = dst;
+        }
         const float* x = xl(l);
+        const float inv_nx = 1.f / (float)nx;
         for (int t = threadIdx.x; t < ny * nx; t += blockDim.x) {
-            const int i = t / nx, k = t % nx;
+            int i, k;
+            divmod_small(t, nx, inv_nx, i, k);
             const int ip = (i + 1 == ny) ? 0 : i + 1, im = (i == 0) ? ny - 1 : i - 1;
             const int kp = (k + 1 == nx) ? 0 : k + 1, km = (k == 0) ? nx - 1 : k - 1;
             const float ns = x[ip * nx + k] + x[im * nx + k] + x[i * nx + kp] + x[i * nx + km];
@@ -296,8 +332,10 @@ __global__ __launch_bounds__(kMgCoarseThreads) void k_mg_coarse(MgCoarse G, cons
         }
         __syncthreads();
         const int nyc = s_ny[l + 1], nxc = s_nx[l + 1];
+        const float inv_nxc = 1.f / (float)nxc;
         for (int t = threadIdx.x; t < nyc * nxc; t += blockDim.x) {
-            const int i = t / nxc, k = t % nxc;
+            int i, k;
+            divmod_small(t, nxc, inv_nxc, i, k);
             const int a = (2 * i) * nx + 2 * k;
             bl(l + 1)[t] = 0.25f * (t0[a] + t0[a + 1] + t0[a + nx] + t0[a + nx + 1]);
         }
@@ -357,17 +395,24 @@ __global__ __launch_bounds__(kMgCoarseThreads) void k_mg_coarse(MgCoarse G, cons
         }
         __syncthreads();
     }
-    // up: y0 = xs_l + P e_(l+1) (e_(l+1) is in xl(l+1)); two sweeps into xl(l)
+    // up: y0 = xs_l + P e_(l+1) (e_(l+1) is in xl(l+1)) into t0; nu sweeps, the
+    // last into xl(l) (sweep q lands in xl(l) when nu - q is even, else in t1)
     for (int l = G.nlev - 2; l >= 0; --l) {
         beta *= 4.f;
         const int ny = s_ny[l], nx = s_nx[l], nxc = s_nx[l + 1];
+        const float inv_nx = 1.f / (float)nx;
         for (int t = threadIdx.x; t < ny * nx; t += blockDim.x) {
-            const int i = t / nx, k = t % nx;
+            int i, k;
+            divmod_small(t, nx, inv_nx, i, k);
             t0[t] = xl(l)[t] + xl(l + 1)[(i / 2) * nxc + k / 2];
         }
         __syncthreads();
-        lds_sweep(t0, bl(l), cl(l), t1, ny, nx, beta, false);
-        lds_sweep(t1, bl(l), cl(l), xl(l), ny, nx, beta, false);
+        float* src = t0;
+        for (int q = 1; q <= kMgNu; ++q) {
+            float* dst = ((kMgNu - q) & 1) ? t1 : xl(l);
+            lds_sweep(src, bl(l), cl(l), dst, ny, nx, beta, false);
+            src = dst;
+        }
     }
     double dot = 0.0;
     for (int t = threadIdx.x; t < n0; t += blockDim.x) {
