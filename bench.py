@@ -54,6 +54,28 @@ def count_nonzeros(g) -> int:
     return total + int(hit.sum())
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when the kernel's source changed since the counters."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "backproject_traffic_512.md")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and line.startswith("    "):
+            k, v = line.strip().split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel") != kernel or "kernel_source" not in kv:
+        return None
+    src = os.path.join(ROOT, kv["kernel_source"])
+    if not os.path.exists(src):
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != kv.get("kernel_source_sha256"):
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(g, pL, pH, iters: int):
     """The FP64 oracle (as it stands) on the host cores: FBP start plus `iters`
     outer iterations, extrapolated to the 50-iteration solve."""
@@ -180,7 +202,7 @@ def main():
         },
         "roofline": {"kernel": "k_backproject", "bound": "alu", "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": None},
+                     "traffic": measured_traffic("k_backproject")},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, pL, pH, args.cpu_iters)
