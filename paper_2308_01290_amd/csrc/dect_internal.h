@@ -248,6 +248,7 @@ struct MgPlan {
     size_t zstride = 0;              // floats per slice
     size_t coarse_lds = 0;           // dynamic LDS bytes of the in-LDS kernel
     int nrz = 0;                     // <r, z> partials one V-cycle writes
+    bool pair[kMgMaxLevels] = {};    // tile levels l and l + 1 run in one kernel each way
 };
 MgPlan mg_plan(int ny, int nx);
 hipError_t mg_init();                // once per process: LDS limit of the in-LDS kernel

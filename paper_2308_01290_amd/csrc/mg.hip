@@ -12,11 +12,13 @@
 // symmetric linear map, as PCG requires; it has no atomics, so it is
 // deterministic.
 //
-// Kernels: for every level whose larger side exceeds 32, one fused kernel
-// going down (sweeps, residual, restriction) and one going up (prolongation,
-// sweeps), on 16 x 16 tiles with a kMgNu-pixel halo; all smaller levels run
-// in one wavefront per slice with every level resident in LDS, so their
-// phases are short.
+// Kernels: levels whose larger side exceeds 32 run as tile kernels going
+// down (sweeps, residual, restriction) and up (prolongation, sweeps), two
+// levels per kernel where the finer one splits into 32 x 32 cores (its halo
+// then covers both levels' sweeps, so the coarser level needs no launch of
+// its own), else one level on 16 x 16 tiles with a kMgNu-pixel halo; all
+// levels of 32 and below run in one workgroup per slice with every level
+// resident in LDS.
 #include <algorithm>
 
 #include "dect_internal.h"
@@ -96,7 +98,18 @@ MgPlan mg_plan(int ny, int nx) {
     lds += (size_t)nc * (nc + 1) + 2 * (size_t)nc;
     P.coarse_lds = lds * sizeof(float);
     ok = ok && P.coarse_lds + kMgLdsStatic <= kMgLdsMax;
-    P.nrz = P.ngrid > 0 ? (P.ny[0] / 16) * (P.nx[0] / 16) : 1;
+    // pair tile levels from the top: l and l + 1 share a kernel when level l
+    // splits into 32 x 32 cores
+    for (int q = 0; q < P.ngrid;) {
+        if (q + 1 < P.ngrid && P.ny[q] % 32 == 0 && P.nx[q] % 32 == 0) {
+            P.pair[q] = true;
+            q += 2;
+        } else {
+            q += 1;
+        }
+    }
+    P.nrz = P.ngrid == 0 ? 1 : (P.pair[0] ? (P.ny[0] / 32) * (P.nx[0] / 32)
+                                          : (P.ny[0] / 16) * (P.nx[0] / 16));
     P.ok = ok;
     return P;
 }
@@ -230,6 +243,207 @@ __global__ __launch_bounds__(256) void k_mg_up(MgLevel L, const int* skip, size_
     L.out[(size_t)z * L.zs_out + (size_t)(i0 + r - kMgNu) * L.nx + (k0 + s - kMgNu)] = y;
     if (dot) {
         const double v = block_sum<256>((double)y * (double)B[r][s], sh);
+        if (threadIdx.x == 0) dot[(size_t)z * dot_zstride + blockIdx.y * gridDim.x + blockIdx.x] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// two-level tile kernels: 32 x 32 core at level l, 16 x 16 at level l + 1
+// ---------------------------------------------------------------------------
+constexpr int kCore2 = 32;
+constexpr int kPairThreads = 512;
+// down: level-l inputs on the core plus 3*nu (level l + 1 needs its residual on
+// a nu halo, i.e. 2*nu at level l, whose sweeps need nu more)
+constexpr int kD0 = kCore2 + 6 * kMgNu;
+constexpr int kD1 = kTile + 2 * kMgNu;
+// up: level l needs y0 on a nu halo, i.e. e_(l+1) on a ceil(nu/2) halo, whose
+// sweeps need nu more at level l + 1
+constexpr int kUh1 = (kMgNu + 1) / 2;
+constexpr int kU0 = kCore2 + 2 * kMgNu;
+constexpr int kU1 = kTile + 2 * (kUh1 + kMgNu);
+
+template <int W>
+__device__ __forceinline__ void pair_sweep(const float (*X)[W + 1], float (*Y)[W + 1],
+                                           const float (*B)[W + 1], const float (*C)[W + 1],
+                                           int off, int n, float be) {
+    for (int t = threadIdx.x; t < n * n; t += kPairThreads) {
+        const int r = off + t / n, s = off + t % n;
+        const float ns = X[r - 1][s] + X[r + 1][s] + X[r][s - 1] + X[r][s + 1];
+        Y[r][s] = jac(X[r][s], B[r][s], C[r][s], be, ns);
+    }
+}
+
+struct MgPair {
+    const float* b0;   // level l: right-hand side, diagonal, saved iterate, correction out
+    const float* c0;
+    float* xs0;
+    float* e0;
+    size_t zs_b0, zs_c0, zs_xs0, zs_e0;
+    int ny0, nx0;
+    float beta0;
+    float* b1;         // level l + 1 (level buffer): rhs (down writes), diagonal, saved iterate
+    const float* c1;
+    float* xs1;
+    float* b2;         // down: level l + 2 rhs out
+    const float* e2;   // up: level l + 2 correction in
+    size_t zsm;        // per-slice stride of the level buffer
+};
+
+__global__ __launch_bounds__(kPairThreads) void k_mg_down2(MgPair A, const int* skip,
+                                                           size_t skip_zstride) {
+    __shared__ float B0[kD0][kD0 + 1], C0[kD0][kD0 + 1], X0[2][kD0][kD0 + 1];
+    __shared__ float B1[kD1][kD1 + 1], C1[kD1][kD1 + 1], X1[2][kD1][kD1 + 1];
+    __shared__ float R1[kTile][kTile + 1];
+    const int z = blockIdx.z;
+    if (mg_skip(skip, skip_zstride, z)) return;
+    constexpr int H0 = 3 * kMgNu;
+    const int ny0 = A.ny0, nx0 = A.nx0, ny1 = ny0 / 2, nx1 = nx0 / 2;
+    const int i0 = blockIdx.y * kCore2, k0 = blockIdx.x * kCore2;
+    const float be0 = A.beta0, be1 = 0.25f * A.beta0;
+    const float* b0 = A.b0 + (size_t)z * A.zs_b0;
+    const float* c0 = A.c0 + (size_t)z * A.zs_c0;
+    for (int t = threadIdx.x; t < kD0 * kD0; t += kPairThreads) {
+        const int r = t / kD0, s = t % kD0;
+        const size_t g = (size_t)wrap_near(i0 - H0 + r, ny0) * nx0 + wrap_near(k0 - H0 + s, nx0);
+        const float bb = b0[g], cc = c0[g];
+        B0[r][s] = bb;
+        C0[r][s] = cc;
+        X0[0][r][s] = kOmega * bb / (cc + 4.f * be0);
+    }
+    const float* c1 = A.c1 + (size_t)z * A.zsm;
+    for (int t = threadIdx.x; t < kD1 * kD1; t += kPairThreads) {
+        const int r = t / kD1, s = t % kD1;
+        C1[r][s] = c1[(size_t)wrap_near(i0 / 2 - kMgNu + r, ny1) * nx1 +
+                      wrap_near(k0 / 2 - kMgNu + s, nx1)];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 2; q <= kMgNu; ++q) {
+        pair_sweep<kD0>(X0[(q - 2) & 1], X0[(q - 1) & 1], B0, C0, q - 1, kD0 - 2 * (q - 1), be0);
+        __syncthreads();
+    }
+    // level-l residual on [nu, kD0 - nu) into the free buffer; saved iterate on the core
+    const float (*Xn)[kD0 + 1] = X0[(kMgNu - 1) & 1];
+    float (*Rr)[kD0 + 1] = X0[kMgNu & 1];
+    constexpr int nr = kD0 - 2 * kMgNu;
+    float* xs0 = A.xs0 + (size_t)z * A.zs_xs0;
+    for (int t = threadIdx.x; t < nr * nr; t += kPairThreads) {
+        const int r = kMgNu + t / nr, s = kMgNu + t % nr;
+        const float x = Xn[r][s];
+        const float ns = Xn[r - 1][s] + Xn[r + 1][s] + Xn[r][s - 1] + Xn[r][s + 1];
+        Rr[r][s] = B0[r][s] - (C0[r][s] * x + be0 * (4.f * x - ns));
+        if (r >= H0 && r < H0 + kCore2 && s >= H0 && s < H0 + kCore2)
+            xs0[(size_t)(i0 + r - H0) * nx0 + (k0 + s - H0)] = x;
+    }
+    __syncthreads();
+    // level l + 1 on [-nu, 16 + nu): rhs = restricted residual, first sweep from zero
+    float* b1 = A.b1 + (size_t)z * A.zsm;
+    for (int t = threadIdx.x; t < kD1 * kD1; t += kPairThreads) {
+        const int r = t / kD1, s = t % kD1;
+        const int a = kMgNu + 2 * r, c = kMgNu + 2 * s;
+        const float v = 0.25f * (Rr[a][c] + Rr[a + 1][c] + Rr[a][c + 1] + Rr[a + 1][c + 1]);
+        B1[r][s] = v;
+        X1[0][r][s] = kOmega * v / (C1[r][s] + 4.f * be1);
+        if (r >= kMgNu && r < kMgNu + kTile && s >= kMgNu && s < kMgNu + kTile)
+            b1[(size_t)(i0 / 2 + r - kMgNu) * nx1 + (k0 / 2 + s - kMgNu)] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 2; q <= kMgNu; ++q) {
+        pair_sweep<kD1>(X1[(q - 2) & 1], X1[(q - 1) & 1], B1, C1, q - 1, kD1 - 2 * (q - 1), be1);
+        __syncthreads();
+    }
+    const float (*Xm)[kD1 + 1] = X1[(kMgNu - 1) & 1];
+    float* xs1 = A.xs1 + (size_t)z * A.zsm;
+    if (threadIdx.x < kTile * kTile) {
+        const int r = threadIdx.x / kTile + kMgNu, s = threadIdx.x % kTile + kMgNu;
+        const float x = Xm[r][s];
+        const float ns = Xm[r - 1][s] + Xm[r + 1][s] + Xm[r][s - 1] + Xm[r][s + 1];
+        R1[r - kMgNu][s - kMgNu] = B1[r][s] - (C1[r][s] * x + be1 * (4.f * x - ns));
+        xs1[(size_t)(i0 / 2 + r - kMgNu) * nx1 + (k0 / 2 + s - kMgNu)] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int a = threadIdx.x / 8, q = threadIdx.x % 8;
+        const float v = 0.25f * (R1[2 * a][2 * q] + R1[2 * a + 1][2 * q] + R1[2 * a][2 * q + 1] +
+                                 R1[2 * a + 1][2 * q + 1]);
+        A.b2[(size_t)z * A.zsm + (size_t)(i0 / 4 + a) * (nx1 / 2) + (k0 / 4 + q)] = v;
+    }
+}
+
+// up: level l + 1 from its saved iterate and e_(l+2), then level l; with `dot`
+// (finest level) the block's <b0, out> goes to dot[z*dot_zstride + block]
+__global__ __launch_bounds__(kPairThreads) void k_mg_up2(MgPair A, const int* skip,
+                                                         size_t skip_zstride, double* dot,
+                                                         size_t dot_zstride) {
+    __shared__ float B0[kU0][kU0 + 1], C0[kU0][kU0 + 1], Y0[2][kU0][kU0 + 1];
+    __shared__ float B1[kU1][kU1 + 1], C1[kU1][kU1 + 1], Y1[2][kU1][kU1 + 1];
+    __shared__ double sh[kPairThreads / kWave];
+    const int z = blockIdx.z;
+    if (mg_skip(skip, skip_zstride, z)) return;
+    const int ny0 = A.ny0, nx0 = A.nx0, ny1 = ny0 / 2, nx1 = nx0 / 2, nx2 = nx1 / 2;
+    const int i0 = blockIdx.y * kCore2, k0 = blockIdx.x * kCore2;
+    const float be0 = A.beta0, be1 = 0.25f * A.beta0;
+    constexpr int H1 = kUh1 + kMgNu;   // level-(l+1) halo of the loaded region
+    {
+        const float* b1 = A.b1 + (size_t)z * A.zsm;
+        const float* c1 = A.c1 + (size_t)z * A.zsm;
+        const float* xs1 = A.xs1 + (size_t)z * A.zsm;
+        const float* e2 = A.e2 + (size_t)z * A.zsm;
+        for (int t = threadIdx.x; t < kU1 * kU1; t += kPairThreads) {
+            const int r = t / kU1, s = t % kU1;
+            const int gi = wrap_near(i0 / 2 - H1 + r, ny1), gk = wrap_near(k0 / 2 - H1 + s, nx1);
+            const size_t g = (size_t)gi * nx1 + gk;
+            B1[r][s] = b1[g];
+            C1[r][s] = c1[g];
+            Y1[0][r][s] = xs1[g] + e2[(size_t)(gi / 2) * nx2 + gk / 2];
+        }
+        const float* b0 = A.b0 + (size_t)z * A.zs_b0;
+        const float* c0 = A.c0 + (size_t)z * A.zs_c0;
+        for (int t = threadIdx.x; t < kU0 * kU0; t += kPairThreads) {
+            const int r = t / kU0, s = t % kU0;
+            const size_t g = (size_t)wrap_near(i0 - kMgNu + r, ny0) * nx0 +
+                             wrap_near(k0 - kMgNu + s, nx0);
+            B0[r][s] = b0[g];
+            C0[r][s] = c0[g];
+        }
+    }
+    __syncthreads();
+    // level l + 1: nu sweeps; sweep q is valid on [q, kU1 - q)
+#pragma unroll
+    for (int q = 1; q <= kMgNu; ++q) {
+        pair_sweep<kU1>(Y1[(q - 1) & 1], Y1[q & 1], B1, C1, q, kU1 - 2 * q, be1);
+        __syncthreads();
+    }
+    const float (*E1)[kU1 + 1] = Y1[kMgNu & 1];   // e_(l+1), valid on [nu, kU1 - nu)
+    // level l: y0 = xs0 + P e_(l+1) on [-nu, 32 + nu)
+    const float* xs0 = A.xs0 + (size_t)z * A.zs_xs0;
+    for (int t = threadIdx.x; t < kU0 * kU0; t += kPairThreads) {
+        const int r = t / kU0, s = t % kU0;
+        const size_t g = (size_t)wrap_near(i0 - kMgNu + r, ny0) * nx0 +
+                         wrap_near(k0 - kMgNu + s, nx0);
+        // parent of level-l row i0 - nu + r, relative to i0 / 2, plus the region offset H1
+        const int pr = ((r + kMgNu) >> 1) - kMgNu + H1, ps = ((s + kMgNu) >> 1) - kMgNu + H1;
+        Y0[0][r][s] = xs0[g] + E1[pr][ps];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 1; q < kMgNu; ++q) {
+        pair_sweep<kU0>(Y0[(q - 1) & 1], Y0[q & 1], B0, C0, q, kU0 - 2 * q, be0);
+        __syncthreads();
+    }
+    const float (*Yp)[kU0 + 1] = Y0[(kMgNu - 1) & 1];
+    float* out = A.e0 + (size_t)z * A.zs_e0;
+    double part = 0.0;
+    for (int t = threadIdx.x; t < kCore2 * kCore2; t += kPairThreads) {
+        const int r = kMgNu + t / kCore2, s = kMgNu + t % kCore2;
+        const float ns = Yp[r - 1][s] + Yp[r + 1][s] + Yp[r][s - 1] + Yp[r][s + 1];
+        const float y = jac(Yp[r][s], B0[r][s], C0[r][s], be0, ns);
+        out[(size_t)(i0 + r - kMgNu) * nx0 + (k0 + s - kMgNu)] = y;
+        part += (double)y * (double)B0[r][s];
+    }
+    if (dot) {
+        const double v = block_sum<kPairThreads>(part, sh);
         if (threadIdx.x == 0) dot[(size_t)z * dot_zstride + blockIdx.y * gridDim.x + blockIdx.x] = v;
     }
 }
@@ -448,7 +662,10 @@ void launch_mg_vcycle(const MgPlan& P, const float* r, const float* w2, float* z
                       int batch, float beta, const int* skip, size_t skip_zstride, double* dot,
                       size_t dot_zstride, hipStream_t st) {
     const size_t n0 = (size_t)P.ny[0] * P.nx[0];
-    auto level = [&](int l, float bl) {
+    float bl[kMgMaxLevels];
+    bl[0] = beta;
+    for (int l = 1; l < kMgMaxLevels; ++l) bl[l] = 0.25f * bl[l - 1];
+    auto level = [&](int l) {
         MgLevel L;
         L.b = l == 0 ? r : mg + P.b[l];
         L.zs_b = l == 0 ? n0 : P.zstride;
@@ -462,15 +679,42 @@ void launch_mg_vcycle(const MgPlan& P, const float* r, const float* w2, float* z
         L.zs_e = P.zstride;
         L.ny = P.ny[l];
         L.nx = P.nx[l];
-        L.beta = bl;
+        L.beta = bl[l];
         return L;
     };
-    float bl = beta;
-    for (int l = 0; l < P.ngrid; ++l, bl *= 0.25f) {
-        MgLevel L = level(l, bl);
-        L.out = mg + P.b[l + 1];
-        hipLaunchKernelGGL(k_mg_down, dim3(P.nx[l] / 16, P.ny[l] / 16, batch), dim3(256), 0, st, L,
-                           skip, skip_zstride);
+    auto pair = [&](int l) {
+        MgPair A;
+        A.b0 = l == 0 ? r : mg + P.b[l];
+        A.zs_b0 = l == 0 ? n0 : P.zstride;
+        A.c0 = l == 0 ? w2 : mg + P.c[l];
+        A.zs_c0 = l == 0 ? n0 : P.zstride;
+        A.xs0 = l == 0 ? mg + P.xs0 : mg + P.xs[l];
+        A.zs_xs0 = P.zstride;
+        A.e0 = l == 0 ? z : mg + P.e[l];
+        A.zs_e0 = l == 0 ? n0 : P.zstride;
+        A.ny0 = P.ny[l];
+        A.nx0 = P.nx[l];
+        A.beta0 = bl[l];
+        A.b1 = mg + P.b[l + 1];
+        A.c1 = mg + P.c[l + 1];
+        A.xs1 = mg + P.xs[l + 1];
+        A.b2 = mg + P.b[l + 2];
+        A.e2 = mg + P.e[l + 2];
+        A.zsm = P.zstride;
+        return A;
+    };
+    for (int l = 0; l < P.ngrid;) {
+        if (P.pair[l]) {
+            hipLaunchKernelGGL(k_mg_down2, dim3(P.nx[l] / kCore2, P.ny[l] / kCore2, batch),
+                               dim3(kPairThreads), 0, st, pair(l), skip, skip_zstride);
+            l += 2;
+        } else {
+            MgLevel L = level(l);
+            L.out = mg + P.b[l + 1];
+            hipLaunchKernelGGL(k_mg_down, dim3(P.nx[l] / 16, P.ny[l] / 16, batch), dim3(256), 0, st,
+                               L, skip, skip_zstride);
+            l += 1;
+        }
     }
     MgCoarse G;
     const int g0 = P.ngrid;
@@ -480,7 +724,7 @@ void launch_mg_vcycle(const MgPlan& P, const float* r, const float* w2, float* z
     G.zs_c = g0 == 0 ? n0 : P.zstride;
     G.e = g0 == 0 ? z : mg + P.e[g0];
     G.zs_e = g0 == 0 ? n0 : P.zstride;
-    G.beta = bl;
+    G.beta = bl[g0];
     G.nlev = P.ncoarse;
     for (int q = 0; q < kMgMaxLevels; ++q) {
         G.ny[q] = q < P.ncoarse ? P.ny[g0 + q] : 0;
@@ -490,14 +734,24 @@ void launch_mg_vcycle(const MgPlan& P, const float* r, const float* w2, float* z
     G.dot_zstride = dot_zstride;
     hipLaunchKernelGGL(k_mg_coarse, dim3(batch), dim3(kMgCoarseThreads), P.coarse_lds, st, G, skip,
                        skip_zstride);
-    for (int l = P.ngrid - 1; l >= 0; --l) {
-        bl *= 4.f;
-        MgLevel L = level(l, bl);
-        L.e = mg + P.e[l + 1];
-        L.out = l == 0 ? z : mg + P.e[l];
-        L.zs_out = l == 0 ? n0 : P.zstride;
-        hipLaunchKernelGGL(k_mg_up, dim3(P.nx[l] / 16, P.ny[l] / 16, batch), dim3(256), 0, st, L,
-                           skip, skip_zstride, l == 0 ? dot : nullptr, dot_zstride);
+    // up: walk the same grouping from the bottom
+    int top[kMgMaxLevels], ntop = 0;
+    for (int l = 0; l < P.ngrid; l += P.pair[l] ? 2 : 1) top[ntop++] = l;
+    for (int q = ntop - 1; q >= 0; --q) {
+        const int l = top[q];
+        double* d = l == 0 ? dot : nullptr;
+        if (P.pair[l]) {
+            hipLaunchKernelGGL(k_mg_up2, dim3(P.nx[l] / kCore2, P.ny[l] / kCore2, batch),
+                               dim3(kPairThreads), 0, st, pair(l), skip, skip_zstride, d,
+                               dot_zstride);
+        } else {
+            MgLevel L = level(l);
+            L.e = mg + P.e[l + 1];
+            L.out = l == 0 ? z : mg + P.e[l];
+            L.zs_out = l == 0 ? n0 : P.zstride;
+            hipLaunchKernelGGL(k_mg_up, dim3(P.nx[l] / 16, P.ny[l] / 16, batch), dim3(256), 0, st, L,
+                               skip, skip_zstride, d, dot_zstride);
+        }
     }
 }
 
