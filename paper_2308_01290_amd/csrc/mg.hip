@@ -29,7 +29,7 @@ namespace dect {
 constexpr float kOmega = 0.8f;
 constexpr int kMgNu = 3;                  // smoothing sweeps before and after the correction
 constexpr int kMgCoarseMax = 32;          // larger side at which the in-LDS kernel takes over
-constexpr int kMgCoarseThreads = 256;
+constexpr int kMgCoarseThreads = 1024;
 constexpr size_t kMgLdsMax = 160 * 1024;  // LDS of one workgroup on gfx950
 constexpr size_t kMgLdsStatic = 1024;     // reserved for the in-LDS kernel's static arrays
 
@@ -463,11 +463,29 @@ struct MgCoarse {
     size_t dot_zstride;
 };
 
+// Work split of the in-LDS kernel: levels with more than 64 pixels use the whole
+// workgroup (phases end in a workgroup barrier); the smaller ones run on the
+// first wavefront alone, whose LDS accesses are ordered among themselves, so
+// their phases end in a wavefront-level fence only.
+struct Team {
+    int tid, n;
+    bool wave;
+    __device__ void sync() const {
+        if (wave) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        } else {
+            __syncthreads();
+        }
+    }
+};
+
 // y = one damped-Jacobi sweep of x (x = 0 when from_zero), periodic grid
-__device__ void lds_sweep(const float* x, const float* b, const float* c, float* y, int ny, int nx,
-                          float beta, bool from_zero) {
+__device__ void lds_sweep(const Team& T, const float* x, const float* b, const float* c, float* y,
+                          int ny, int nx, float beta, bool from_zero) {
     const float inv_nx = 1.f / (float)nx;
-    for (int t = threadIdx.x; t < ny * nx; t += blockDim.x) {
+    for (int t = T.tid; t < ny * nx; t += T.n) {
         if (from_zero) {
             y[t] = kOmega * b[t] / (c[t] + 4.f * beta);
             continue;
@@ -479,7 +497,131 @@ __device__ void lds_sweep(const float* x, const float* b, const float* c, float*
         const float ns = x[ip * nx + k] + x[im * nx + k] + x[i * nx + kp] + x[i * nx + km];
         y[t] = jac(x[t], b[t], c[t], beta, ns);
     }
-    __syncthreads();
+    T.sync();
+}
+
+// 2x2 average of a level-l array (row length nxf) into the next level
+__device__ void lds_restrict(const Team& T, const float* f, int nxf, float* cg, int nyc, int nxc) {
+    const float inv_nxc = 1.f / (float)nxc;
+    for (int t = T.tid; t < nyc * nxc; t += T.n) {
+        int i, k;
+        divmod_small(t, nxc, inv_nxc, i, k);
+        const int a = (2 * i) * nxf + 2 * k;
+        cg[t] = 0.25f * (f[a] + f[a + 1] + f[a + nxf] + f[a + nxf + 1]);
+    }
+    T.sync();
+}
+
+struct CoarseLds {
+    float* base;
+    const int *ny, *nx, *off;
+    __device__ float* b(int l) const { return base + off[l]; }
+    __device__ float* c(int l) const { return base + off[l] + ny[l] * nx[l]; }
+    __device__ float* x(int l) const { return base + off[l] + 2 * ny[l] * nx[l]; }
+};
+
+// down at level l: nu sweeps from zero (sweep q lands in x_l when nu - q is
+// even, else in t0), residual into t0, restriction into b_(l+1)
+__device__ void coarse_down(const Team& T, const CoarseLds& S, int l, float beta, float* t0) {
+    const int ny = S.ny[l], nx = S.nx[l];
+    float* src = nullptr;
+    for (int q = 1; q <= kMgNu; ++q) {
+        float* dst = ((kMgNu - q) & 1) ? t0 : S.x(l);
+        lds_sweep(T, src, S.b(l), S.c(l), dst, ny, nx, beta, q == 1);
+        src = dst;
+    }
+    const float* x = S.x(l);
+    const float* bb = S.b(l);
+    const float* cc = S.c(l);
+    const float inv_nx = 1.f / (float)nx;
+    for (int t = T.tid; t < ny * nx; t += T.n) {
+        int i, k;
+        divmod_small(t, nx, inv_nx, i, k);
+        const int ip = (i + 1 == ny) ? 0 : i + 1, im = (i == 0) ? ny - 1 : i - 1;
+        const int kp = (k + 1 == nx) ? 0 : k + 1, km = (k == 0) ? nx - 1 : k - 1;
+        const float ns = x[ip * nx + k] + x[im * nx + k] + x[i * nx + kp] + x[i * nx + km];
+        t0[t] = bb[t] - (cc[t] * x[t] + beta * (4.f * x[t] - ns));
+    }
+    T.sync();
+    lds_restrict(T, t0, nx, S.b(l + 1), S.ny[l + 1], S.nx[l + 1]);
+}
+
+// up at level l: y0 = xs_l + P e_(l+1) (e_(l+1) is in x_(l+1)) into t0; nu
+// sweeps, the last into x_l (sweep q lands in x_l when nu - q is even, else t1)
+__device__ void coarse_up(const Team& T, const CoarseLds& S, int l, float beta, float* t0,
+                          float* t1) {
+    const int ny = S.ny[l], nx = S.nx[l], nxc = S.nx[l + 1];
+    const float inv_nx = 1.f / (float)nx;
+    const float* xc = S.x(l + 1);
+    float* xf = S.x(l);
+    for (int t = T.tid; t < ny * nx; t += T.n) {
+        int i, k;
+        divmod_small(t, nx, inv_nx, i, k);
+        t0[t] = xf[t] + xc[(i / 2) * nxc + k / 2];
+    }
+    T.sync();
+    float* src = t0;
+    for (int q = 1; q <= kMgNu; ++q) {
+        float* dst = ((kMgNu - q) & 1) ? t1 : xf;
+        lds_sweep(T, src, S.b(l), S.c(l), dst, ny, nx, beta, false);
+        src = dst;
+    }
+}
+
+// coarsest level l: Gaussian elimination (the matrix is SPD), result in x_l;
+// one thread owns each row while the matrix is built, one lane per unknown in
+// the back substitution (nc <= 64, so that runs on the first wavefront)
+__device__ void coarse_solve(const Team& T, const CoarseLds& S, int l, float beta, float* dense) {
+    const int ny = S.ny[l], nx = S.nx[l], nc = ny * nx, ld = nc + 1;
+    float* A = dense;
+    float* rhs = A + nc * ld;
+    float* lc = rhs + nc;
+    for (int t = T.tid; t < nc; t += T.n) {
+        float* row = A + t * ld;
+        for (int j = 0; j < nc; ++j) row[j] = 0.f;
+        const int i = t / nx, k = t % nx;
+        const int ip = (i + 1 == ny) ? 0 : i + 1, im = (i == 0) ? ny - 1 : i - 1;
+        const int kp = (k + 1 == nx) ? 0 : k + 1, km = (k == 0) ? nx - 1 : k - 1;
+        const int nb[4] = {ip * nx + k, im * nx + k, i * nx + kp, i * nx + km};
+        float d = S.c(l)[t];   // a neighbour that wraps onto t itself adds nothing
+        for (int q = 0; q < 4; ++q) {
+            if (nb[q] == t) continue;
+            row[nb[q]] -= beta;
+            d += beta;
+        }
+        row[t] = d;
+        rhs[t] = S.b(l)[t];
+    }
+    T.sync();
+    for (int k = 0; k + 1 < nc; ++k) {
+        const float piv = A[k * ld + k];
+        const float inv = piv > 0.f ? 1.f / piv : 0.f;
+        for (int i = k + 1 + T.tid; i < nc; i += T.n) lc[i] = A[i * ld + k] * inv;
+        T.sync();
+        const int w = nc - k;   // columns k..nc-1; column k carries the rhs update
+        for (int idx = T.tid; idx < (nc - k - 1) * w; idx += T.n) {
+            const int i = k + 1 + idx / w, j = k + idx % w;
+            if (j == k)
+                rhs[i] -= lc[i] * rhs[k];
+            else
+                A[i * ld + j] -= lc[i] * A[k * ld + j];
+        }
+        T.sync();
+    }
+    if (T.tid < kWave) {
+        const int lane = T.tid;
+        float xv = 0.f;
+        for (int i = nc - 1; i >= 0; --i) {
+            const float part = (lane > i && lane < nc) ? A[i * ld + lane] * xv : 0.f;
+            const float s = wave_sum(part);
+            if (lane == i) {
+                const float piv = A[i * ld + i];
+                xv = piv > 0.f ? (rhs[i] - s) / piv : 0.f;
+            }
+        }
+        if (lane < nc) S.x(l)[lane] = xv;
+    }
+    T.sync();
 }
 
 __global__ __launch_bounds__(kMgCoarseThreads) void k_mg_coarse(MgCoarse G, const int* skip,
@@ -500,138 +642,40 @@ __global__ __launch_bounds__(kMgCoarseThreads) void k_mg_coarse(MgCoarse G, cons
         s_off[kMgMaxLevels] = o;
     }
     __syncthreads();
-    auto bl = [&](int l) { return lds + s_off[l]; };
-    auto cl = [&](int l) { return lds + s_off[l] + s_ny[l] * s_nx[l]; };
-    auto xl = [&](int l) { return lds + s_off[l] + 2 * s_ny[l] * s_nx[l]; };
+    const CoarseLds S{lds, s_ny, s_nx, s_off};
     const int n0 = s_ny[0] * s_nx[0];
     float* t0 = lds + s_off[kMgMaxLevels];
     float* t1 = t0 + n0;
     float* dense = t0 + 2 * n0;
+    // first level with at most 64 pixels: it and all below run on one wavefront
+    int cut = 0;
+    while (cut < G.nlev && s_ny[cut] * s_nx[cut] > kWave) ++cut;
+    const Team B{(int)threadIdx.x, (int)blockDim.x, false};
+    const Team W{(int)threadIdx.x, kWave, true};
     for (int t = threadIdx.x; t < n0; t += blockDim.x) {
-        bl(0)[t] = G.b[(size_t)z * G.zs_b + t];
-        cl(0)[t] = G.c[(size_t)z * G.zs_c + t];
+        S.b(0)[t] = G.b[(size_t)z * G.zs_b + t];
+        S.c(0)[t] = G.c[(size_t)z * G.zs_c + t];
     }
     __syncthreads();
-    for (int l = 0; l + 1 < G.nlev; ++l) {
-        const int nyc = s_ny[l + 1], nxc = s_nx[l + 1], nxf = s_nx[l];
-        const float inv_nxc = 1.f / (float)nxc;
-        for (int t = threadIdx.x; t < nyc * nxc; t += blockDim.x) {
-            int i, k;
-            divmod_small(t, nxc, inv_nxc, i, k);
-            const int a = (2 * i) * nxf + 2 * k;
-            cl(l + 1)[t] = 0.25f * (cl(l)[a] + cl(l)[a + 1] + cl(l)[a + nxf] + cl(l)[a + nxf + 1]);
-        }
-        __syncthreads();
+    float beta[kMgMaxLevels];
+    beta[0] = G.beta;
+    for (int l = 1; l < kMgMaxLevels; ++l) beta[l] = 0.25f * beta[l - 1];
+    for (int l = 0; l + 1 < cut; ++l) lds_restrict(B, S.c(l), s_nx[l], S.c(l + 1), s_ny[l + 1], s_nx[l + 1]);
+    for (int l = 0; l < cut && l + 1 < G.nlev; ++l) coarse_down(B, S, l, beta[l], t0);
+    if (threadIdx.x < kWave) {
+        for (int l = cut > 0 ? cut - 1 : 0; l + 1 < G.nlev; ++l)
+            if (l + 1 >= cut)
+                lds_restrict(W, S.c(l), s_nx[l], S.c(l + 1), s_ny[l + 1], s_nx[l + 1]);
+        for (int l = cut; l + 1 < G.nlev; ++l) coarse_down(W, S, l, beta[l], t0);
+        coarse_solve(W, S, G.nlev - 1, beta[G.nlev - 1], dense);
+        for (int l = G.nlev - 2; l >= cut; --l) coarse_up(W, S, l, beta[l], t0, t1);
     }
-    // down: nu sweeps from zero (sweep q lands in x_l when nu - q is even, else
-    // in t0), residual, restriction
-    float beta = G.beta;
-    for (int l = 0; l + 1 < G.nlev; ++l, beta *= 0.25f) {
-        const int ny = s_ny[l], nx = s_nx[l];
-        float* src = nullptr;
-        for (int q = 1; q <= kMgNu; ++q) {
-            float* dst = ((kMgNu - q) & 1) ? t0 : xl(l);
-            lds_sweep(src, bl(l), cl(l), dst, ny, nx, beta, q == 1);
-            src = dst;
-        }
-        const float* x = xl(l);
-        const float inv_nx = 1.f / (float)nx;
-        for (int t = threadIdx.x; t < ny * nx; t += blockDim.x) {
-            int i, k;
-            divmod_small(t, nx, inv_nx, i, k);
-            const int ip = (i + 1 == ny) ? 0 : i + 1, im = (i == 0) ? ny - 1 : i - 1;
-            const int kp = (k + 1 == nx) ? 0 : k + 1, km = (k == 0) ? nx - 1 : k - 1;
-            const float ns = x[ip * nx + k] + x[im * nx + k] + x[i * nx + kp] + x[i * nx + km];
-            t0[t] = bl(l)[t] - (cl(l)[t] * x[t] + beta * (4.f * x[t] - ns));
-        }
-        __syncthreads();
-        const int nyc = s_ny[l + 1], nxc = s_nx[l + 1];
-        const float inv_nxc = 1.f / (float)nxc;
-        for (int t = threadIdx.x; t < nyc * nxc; t += blockDim.x) {
-            int i, k;
-            divmod_small(t, nxc, inv_nxc, i, k);
-            const int a = (2 * i) * nx + 2 * k;
-            bl(l + 1)[t] = 0.25f * (t0[a] + t0[a + 1] + t0[a + nx] + t0[a + nx + 1]);
-        }
-        __syncthreads();
-    }
-    // coarsest grid: Gaussian elimination (the matrix is SPD), result in xl(last)
-    {
-        const int l = G.nlev - 1;
-        const int ny = s_ny[l], nx = s_nx[l], nc = ny * nx, ld = nc + 1;
-        float* A = dense;
-        float* rhs = A + nc * ld;
-        float* lc = rhs + nc;
-        for (int t = threadIdx.x; t < nc; t += blockDim.x) {   // row t, owned by one thread
-            float* row = A + t * ld;
-            for (int j = 0; j < nc; ++j) row[j] = 0.f;
-            const int i = t / nx, k = t % nx;
-            const int ip = (i + 1 == ny) ? 0 : i + 1, im = (i == 0) ? ny - 1 : i - 1;
-            const int kp = (k + 1 == nx) ? 0 : k + 1, km = (k == 0) ? nx - 1 : k - 1;
-            const int nb[4] = {ip * nx + k, im * nx + k, i * nx + kp, i * nx + km};
-            float d = cl(l)[t];   // a neighbour that wraps onto t itself adds nothing
-            for (int q = 0; q < 4; ++q) {
-                if (nb[q] == t) continue;
-                row[nb[q]] -= beta;
-                d += beta;
-            }
-            row[t] = d;
-            rhs[t] = bl(l)[t];
-        }
-        __syncthreads();
-        for (int k = 0; k + 1 < nc; ++k) {
-            const float piv = A[k * ld + k];
-            const float inv = piv > 0.f ? 1.f / piv : 0.f;
-            for (int i = k + 1 + threadIdx.x; i < nc; i += blockDim.x) lc[i] = A[i * ld + k] * inv;
-            __syncthreads();
-            const int w = nc - k;   // columns k..nc-1; column k carries the rhs update
-            for (int idx = threadIdx.x; idx < (nc - k - 1) * w; idx += blockDim.x) {
-                const int i = k + 1 + idx / w, j = k + idx % w;
-                if (j == k)
-                    rhs[i] -= lc[i] * rhs[k];
-                else
-                    A[i * ld + j] -= lc[i] * A[k * ld + j];
-            }
-            __syncthreads();
-        }
-        if (threadIdx.x < kWave) {   // back substitution, one lane per unknown
-            const int lane = threadIdx.x;
-            float xv = 0.f;
-            for (int i = nc - 1; i >= 0; --i) {
-                const float part = (lane > i && lane < nc) ? A[i * ld + lane] * xv : 0.f;
-                const float s = wave_sum(part);
-                if (lane == i) {
-                    const float piv = A[i * ld + i];
-                    xv = piv > 0.f ? (rhs[i] - s) / piv : 0.f;
-                }
-            }
-            if (lane < nc) xl(l)[lane] = xv;
-        }
-        __syncthreads();
-    }
-    // up: y0 = xs_l + P e_(l+1) (e_(l+1) is in xl(l+1)) into t0; nu sweeps, the
-    // last into xl(l) (sweep q lands in xl(l) when nu - q is even, else in t1)
-    for (int l = G.nlev - 2; l >= 0; --l) {
-        beta *= 4.f;
-        const int ny = s_ny[l], nx = s_nx[l], nxc = s_nx[l + 1];
-        const float inv_nx = 1.f / (float)nx;
-        for (int t = threadIdx.x; t < ny * nx; t += blockDim.x) {
-            int i, k;
-            divmod_small(t, nx, inv_nx, i, k);
-            t0[t] = xl(l)[t] + xl(l + 1)[(i / 2) * nxc + k / 2];
-        }
-        __syncthreads();
-        float* src = t0;
-        for (int q = 1; q <= kMgNu; ++q) {
-            float* dst = ((kMgNu - q) & 1) ? t1 : xl(l);
-            lds_sweep(src, bl(l), cl(l), dst, ny, nx, beta, false);
-            src = dst;
-        }
-    }
+    __syncthreads();
+    for (int l = min(cut, G.nlev - 1) - 1; l >= 0; --l) coarse_up(B, S, l, beta[l], t0, t1);
     double dot = 0.0;
     for (int t = threadIdx.x; t < n0; t += blockDim.x) {
-        G.e[(size_t)z * G.zs_e + t] = xl(0)[t];
-        dot += (double)xl(0)[t] * (double)bl(0)[t];
+        G.e[(size_t)z * G.zs_e + t] = S.x(0)[t];
+        dot += (double)S.x(0)[t] * (double)S.b(0)[t];
     }
     if (G.dot) {
         const double v = block_sum<kMgCoarseThreads>(dot, sh);
