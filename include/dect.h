@@ -174,8 +174,9 @@ int dect_l0_step(const float* g_tilde, const float* weight, float* g, float* h_o
                  double tol, int32_t max_iter, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* ---- solver -------------------------------------------------------------
- * A solver holds one batch of slices that share geometry and parameters, and
- * all per-iteration state on the device: basis images f1, f2, rho_e, the
+ * A solver holds one batch of slices that share parameters and the image grid
+ * (n_x, n_y, pixel_mm), and all per-iteration state on the device: basis
+ * images f1, f2, rho_e, the
  * normalised t' = Z^m/Z_w^m, the combined residual sinograms and scratch.
  * Algorithm 1, sinogram form, per outer iteration k (all updates read iterate k):
  *   f-step   one steepest-descent step with exact line search on the
@@ -196,6 +197,20 @@ size_t dect_solve_workspace_bytes(const dect_geometry* g, const dect_params* p, 
  * byte aligned) is used and must outlive the solver.  *out is a HOST handle. */
 int dect_solver_create(const dect_geometry* g, const dect_params* p, int32_t batch, void* ws,
                        size_t ws_bytes, hipStream_t stream, dect_solver** out);
+
+/* Batches of uneven slices: geoms is a HOST array of `batch` geometries that
+ * share n_x, n_y and pixel_mm; views, bins, detector and distances may
+ * differ per slice (DECT_EINVAL otherwise).  Every launch of an iteration
+ * covers all slices.  The sinogram arguments of dect_solver_init /
+ * set_state are then the slices' sinograms back to back: slice z starts at
+ * element sum over z' < z of n_views(z') * n_det(z').  Images stay
+ * [batch][n_y][n_x].  Each slice follows the iteration it follows alone: its
+ * own data weight eta (from its geometry unless set), its own line search and
+ * PCG stopping test; beta schedule and parameters are shared. */
+size_t dect_solve_workspace_bytes_multi(const dect_geometry* geoms, const dect_params* p,
+                                        int32_t batch);
+int dect_solver_create_multi(const dect_geometry* geoms, const dect_params* p, int32_t batch,
+                             void* ws, size_t ws_bytes, hipStream_t stream, dect_solver** out);
 int dect_solver_destroy(dect_solver* s);
 
 /* Initialise from the sinograms (FBP + closed forms); k = 0. */
@@ -234,6 +249,10 @@ int dect_solver_timing(dect_solver* s, double* backproject_ms, int32_t* backproj
 int dect_solve(const float* sino_lo, const float* sino_hi, const dect_geometry* g,
                const dect_params* p, float* Z_out, float* rho_out, int32_t batch, void* ws,
                size_t ws_bytes, hipStream_t stream);
+/* The same for a batch of uneven slices (see dect_solver_create_multi). */
+int dect_solve_multi(const float* sino_lo, const float* sino_hi, const dect_geometry* geoms,
+                     const dect_params* p, float* Z_out, float* rho_out, int32_t batch, void* ws,
+                     size_t ws_bytes, hipStream_t stream);
 
 const char* dect_last_error(void);
 

@@ -147,18 +147,20 @@ struct Resolved {
     double eta, xi, beta0, kappa;
 };
 
+// projection-data weight eta for geometry g (the explicit value if given)
+static double eta_of(const dect_params* in, const Geom& g) {
+    if (in->eta > 0) return in->eta;
+    const double mwl = mu_of(*in, in->Z_w, 1.0, in->E_lo_keV);
+    const double mwh = mu_of(*in, in->Z_w, 1.0, in->E_hi_keV);
+    return g.pitch * g.sid / (g.nv * g.dx * g.dx * g.dx * g.sdd * (mwl * mwl + mwh * mwh));
+}
+
 static int resolve_params(const dect_params* in, const Geom& g, const Model& M, Resolved* r) {
     r->p = *in;
     r->beta0 = in->beta0 > 0 ? in->beta0 : 2.0 * in->lambda;
     if (!(r->beta0 > 0)) return fail(DECT_EINVAL, "beta0 = 0 needs lambda > 0");
     r->kappa = in->kappa > 0 ? in->kappa : std::pow(in->beta_max / r->beta0, 1.0 / in->n_iter);
-    if (in->eta > 0) {
-        r->eta = in->eta;
-    } else {
-        const double mwl = mu_of(*in, in->Z_w, 1.0, in->E_lo_keV);
-        const double mwh = mu_of(*in, in->Z_w, 1.0, in->E_hi_keV);
-        r->eta = g.pitch * g.sid / (g.nv * g.dx * g.dx * g.dx * g.sdd * (mwl * mwl + mwh * mwh));
-    }
+    r->eta = eta_of(in, g);
     if (in->xi > 0) {
         r->xi = in->xi;
     } else {
@@ -173,11 +175,13 @@ static int resolve_params(const dect_params* in, const Geom& g, const Model& M, 
 // ---------------------------------------------------------------------------
 // per-geometry ray tables for the stand-alone operators
 // ---------------------------------------------------------------------------
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
 struct TableEntry {
     Geom g;
     int device;
     void* mem;
-    RayTable t;
+    RayTable t;   // one shared descriptor; pair z's sinograms at z * nv * nd
 };
 static std::mutex g_tab_mu;
 static std::vector<TableEntry> g_tabs;
@@ -217,10 +221,19 @@ static int get_table(const Geom& g, hipStream_t st, RayTable* out) {
     TableEntry e;
     e.g = g;
     e.device = dev;
-    if (hipMalloc(&e.mem, ray_table_bytes(g)) != hipSuccess)
+    const size_t tb = align256(ray_table_bytes(g));
+    if (hipMalloc(&e.mem, tb + sizeof(SliceDesc)) != hipSuccess)
         return fail(DECT_ENOMEM, "could not allocate the ray table (%zu bytes)", ray_table_bytes(g));
     carve_table(g, e.mem, &e.t);
+    SliceDesc* dd = reinterpret_cast<SliceDesc*>(static_cast<char*>(e.mem) + tb);
+    const SliceDesc hd = make_slice_desc(g, 0, 0, 0, 1.0);
+    e.t.desc = dd;
+    e.t.desc_stride = 0;
+    e.t.sino_zstride = (long long)g.nv * g.nd;
+    e.t.nv_max = g.nv;
+    e.t.nd_max = g.nd;
     launch_build_ray_table(g, e.t, st);
+    DECT_HIP(hipMemcpyAsync(dd, &hd, sizeof(SliceDesc), hipMemcpyHostToDevice, st));
     DECT_HIP(hipGetLastError());
     DECT_HIP(hipStreamSynchronize(st));   // the table may be used from other streams
     g_tabs.push_back(e);
@@ -277,7 +290,6 @@ static int temp_alloc(TempBuf* b, size_t bytes, hipStream_t st) {
     return rc;
 }
 
-static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // ---------------------------------------------------------------------------
 // workspace of the L0 step and the solver
@@ -397,8 +409,59 @@ using namespace dect;
 // ===========================================================================
 // C-ABI
 // ===========================================================================
+// Slices of one image grid with their own fan geometries: distinct
+// geometries get one ray table each, back to back; slice z's sinograms start
+// at sino0[z] in the concatenated inputs and residuals.
+struct BatchGeo {
+    std::vector<Geom> g;            // per slice
+    std::vector<int> uniq;          // slice -> distinct geometry
+    std::vector<Geom> distinct;
+    std::vector<int> ray0, view0;   // per distinct geometry
+    std::vector<long long> sino0;   // per slice
+    size_t rays = 0, views = 0;
+    long long sino_total = 0;
+    int nv_max = 0, nd_max = 0;
+};
+
+static int make_batch(const dect_geometry* gin, int batch, BatchGeo* B) {
+    if (!gin) return fail(DECT_EINVAL, "geometry is NULL");
+    if (batch < 1) return fail(DECT_EINVAL, "batch must be >= 1");
+    B->g.resize(batch);
+    B->uniq.resize(batch);
+    B->sino0.resize(batch);
+    for (int z = 0; z < batch; ++z) {
+        if (int rc = resolve_geometry(&gin[z], &B->g[z])) return rc;
+        const Geom& a = B->g[z];
+        const Geom& b = B->g[0];
+        if (a.nx != b.nx || a.ny != b.ny || a.dx != b.dx)
+            return fail(DECT_EINVAL, "slice %d: image %dx%d at %g mm differs from slice 0 (%dx%d at %g mm)",
+                        z, a.nx, a.ny, a.dx, b.nx, b.ny, b.dx);
+        if (a.nd > 4096) return fail(DECT_EINVAL, "slice %d: n_det > 4096 is not supported by the FBP start", z);
+        int u = -1;
+        for (size_t d = 0; d < B->distinct.size(); ++d)
+            if (same_geom(B->distinct[d], a)) u = (int)d;
+        if (u < 0) {
+            u = (int)B->distinct.size();
+            B->distinct.push_back(a);
+            B->ray0.push_back((int)B->rays);
+            B->view0.push_back((int)B->views);
+            B->rays += (size_t)a.nv * a.nd;
+            B->views += (size_t)a.nv;
+        }
+        B->uniq[z] = u;
+        B->sino0[z] = B->sino_total;
+        B->sino_total += (long long)a.nv * a.nd;
+        B->nv_max = std::max(B->nv_max, a.nv);
+        B->nd_max = std::max(B->nd_max, a.nd);
+    }
+    if (B->rays > (size_t)INT32_MAX) return fail(DECT_EINVAL, "batch ray tables exceed 2^31 rays");
+    return DECT_OK;
+}
+
 struct dect_solver {
-    Geom g;
+    Geom g;                          // image grid (and slice 0's fan geometry)
+    BatchGeo geo;
+    std::vector<SliceDesc> hdesc;    // host copy of the device descriptors
     Resolved rp;
     Model M;
     int batch;
@@ -621,31 +684,41 @@ int dect_l0_step(const float* g_tilde, const float* weight, float* g, float* h_o
 }
 
 // ---- solver ---------------------------------------------------------------
-static size_t solver_layout(const Geom& g, int batch, char* base, dect_solver* s) {
+static size_t solver_layout(const BatchGeo& B, char* base, dect_solver* s) {
+    const Geom& g = B.g[0];
+    const int batch = (int)B.g.size();
     Carver c{base};
     const size_t npix = (size_t)g.nx * g.ny * batch;
-    const size_t nray = (size_t)g.nv * g.nd * batch;
+    const size_t nsino = (size_t)B.sino_total;
     RayTable t;
-    void* tab = c.take<char>(ray_table_bytes(g));
+    t.fix = c.take<int4>(B.rays);
+    t.flt = c.take<float2>(B.rays);
+    t.span = c.take<int2>(B.rays);
+    t.view = c.take<float4>(B.views);
+    SliceDesc* desc = c.take<SliceDesc>((size_t)batch);
     float2* f = c.take<float2>(npix);
-    float2* B = c.take<float2>(npix);
+    float2* Bimg = c.take<float2>(npix);
     float2* dpad = c.take<float2>(pad_elems(g) * batch);
-    float2* S = c.take<float2>(nray);
-    float2* zq = c.take<float2>(nray);   // also the FBP filter scratch at init
+    float2* S = c.take<float2>(nsino);
+    float2* zq = c.take<float2>(nsino);   // also the FBP filter scratch at init
     float2* fft = c.take<float2>(npix);
     float* rho = c.take<float>(npix);
     float* tt = c.take<float>(npix);
     double* part_img = c.take<double>((size_t)batch * grad_nblocks(g.ny, g.nx) * 3);
-    double* part_proj = c.take<double>((size_t)batch * proj_nblocks(g));
+    double* part_proj = c.take<double>((size_t)batch * proj_nblocks(B.nv_max, B.nd_max));
     double* alpha = c.take<double>((size_t)batch);
     unsigned* cnt = c.take<unsigned>((size_t)batch);
     PcgBufs pb;
     carve_pcg(c, g.ny, g.nx, batch, &pb);
     if (s) {
-        carve_table(g, tab, &t);
+        t.desc = desc;
+        t.desc_stride = 1;
+        t.sino_zstride = 0;
+        t.nv_max = B.nv_max;
+        t.nd_max = B.nd_max;
         s->tab = t;
         s->f = f;
-        s->B = B;
+        s->B = Bimg;
         s->dpad = dpad;
         s->S = S;
         s->zq = zq;
@@ -664,29 +737,36 @@ static size_t solver_layout(const Geom& g, int batch, char* base, dect_solver* s
     return c.off;
 }
 
-size_t dect_solve_workspace_bytes(const dect_geometry* gin, const dect_params* p, int32_t batch) {
-    Geom g;
-    if (resolve_geometry(gin, &g) || !p || batch < 1) return 0;
-    return solver_layout(g, batch, nullptr, nullptr);
+size_t dect_solve_workspace_bytes_multi(const dect_geometry* geoms, const dect_params* p,
+                                        int32_t batch) {
+    BatchGeo B;
+    if (!p || make_batch(geoms, batch, &B)) return 0;
+    return solver_layout(B, nullptr, nullptr);
 }
 
-int dect_solver_create(const dect_geometry* gin, const dect_params* p, int32_t batch, void* ws,
-                       size_t ws_bytes, hipStream_t st, dect_solver** out) {
+size_t dect_solve_workspace_bytes(const dect_geometry* gin, const dect_params* p, int32_t batch) {
+    if (!gin || batch < 1) return 0;
+    std::vector<dect_geometry> gs((size_t)batch, *gin);
+    return dect_solve_workspace_bytes_multi(gs.data(), p, batch);
+}
+
+int dect_solver_create_multi(const dect_geometry* geoms, const dect_params* p, int32_t batch,
+                             void* ws, size_t ws_bytes, hipStream_t st, dect_solver** out) {
     if (!out) return fail(DECT_EINVAL, "out is NULL");
     *out = nullptr;
-    Geom g;
-    if (int rc = resolve_geometry(gin, &g)) return rc;
+    BatchGeo B;
+    if (int rc = make_batch(geoms, batch, &B)) return rc;
+    const Geom& g = B.g[0];
     if (int rc = check_params(p)) return rc;
-    if (batch < 1) return fail(DECT_EINVAL, "batch must be >= 1");
     if (!fft_size_ok(g.nx) || !fft_size_ok(g.ny))
         return fail(DECT_EINVAL, "image sizes must be 2^a*3^b (b <= 1) in [8, 1024], got %dx%d", g.nx,
                     g.ny);
-    if (g.nd > 4096) return fail(DECT_EINVAL, "n_det > 4096 is not supported by the FBP start");
     if (p->t_precond == DECT_PRECOND_MULTIGRID && !mg_plan(g.ny, g.nx).ok)
         return fail(DECT_EUNSUPPORTED, "multigrid preconditioner: image %dx%d unsupported", g.nx,
                     g.ny);
     dect_solver* s = new dect_solver();
     s->g = g;
+    s->geo = B;
     s->batch = batch;
     s->st = st;
     if (int rc = build_model(*p, &s->M)) {
@@ -697,7 +777,7 @@ int dect_solver_create(const dect_geometry* gin, const dect_params* p, int32_t b
         delete s;
         return rc;
     }
-    const size_t need = solver_layout(g, batch, nullptr, nullptr);
+    const size_t need = solver_layout(B, nullptr, nullptr);
     if (ws) {
         if (ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255)) {
             delete s;
@@ -713,25 +793,49 @@ int dect_solver_create(const dect_geometry* gin, const dect_params* p, int32_t b
         s->ws = s->own.p;
         s->owns_ws = true;
     }
-    solver_layout(g, batch, static_cast<char*>(s->ws), s);
+    solver_layout(B, static_cast<char*>(s->ws), s);
+    s->hdesc.resize(batch);
+    for (int z = 0; z < batch; ++z) {
+        const int u = B.uniq[z];
+        s->hdesc[z] = make_slice_desc(B.g[z], B.ray0[u], B.view0[u], B.sino0[z], eta_of(p, B.g[z]));
+    }
     // zero borders of the padded direction layouts, counters and scalars once
     hipError_t e = hipSuccess;
     e = e != hipSuccess ? e : hipMemsetAsync(s->dpad, 0, pad_elems(g) * batch * sizeof(float2), st);
     e = e != hipSuccess ? e : hipMemsetAsync(s->cnt_proj, 0, sizeof(unsigned) * batch, st);
-
     e = e != hipSuccess ? e : hipMemsetAsync(s->pcg.st, 0, sizeof(PcgState) * batch, st);
+    e = e != hipSuccess ? e
+                        : hipMemcpyAsync(const_cast<SliceDesc*>(s->tab.desc), s->hdesc.data(),
+                                         sizeof(SliceDesc) * batch, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) {
         if (s->owns_ws) dev_free(&s->own);
         delete s;
-        return fail(DECT_EDEVICE, "hipMemsetAsync failed: %s", hipGetErrorString(e));
+        return fail(DECT_EDEVICE, "setting up the solver workspace failed: %s", hipGetErrorString(e));
     }
-    launch_build_ray_table(g, s->tab, st);
+    for (size_t d = 0; d < B.distinct.size(); ++d) {
+        RayTable t = s->tab;
+        t.fix += B.ray0[d];
+        t.flt += B.ray0[d];
+        t.span += B.ray0[d];
+        t.view += B.view0[d];
+        launch_build_ray_table(B.distinct[d], t, st);
+    }
     s->k = 0;
     s->beta = s->rp.beta0;
     s->last_pcg = 0;
     *out = s;
     DECT_HIP(hipGetLastError());
     return DECT_OK;
+}
+
+int dect_solver_create(const dect_geometry* gin, const dect_params* p, int32_t batch, void* ws,
+                       size_t ws_bytes, hipStream_t st, dect_solver** out) {
+    if (!out) return fail(DECT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!gin) return fail(DECT_EINVAL, "geometry is NULL");
+    if (batch < 1) return fail(DECT_EINVAL, "batch must be >= 1");
+    std::vector<dect_geometry> gs((size_t)batch, *gin);
+    return dect_solver_create_multi(gs.data(), p, batch, ws, ws_bytes, st, out);
 }
 
 int dect_solver_destroy(dect_solver* s) {
@@ -767,8 +871,15 @@ static void project_residual(dect_solver* s, const float* lo, const float* hi) {
 int dect_solver_init(dect_solver* s, const float* lo, const float* hi) {
     if (!s || !lo || !hi) return fail(DECT_EINVAL, "dect_solver_init: NULL argument");
     const Geom& g = s->g;
-    launch_fbp(g, lo, s->batch, s->fbpq, s->muL, s->st);
-    launch_fbp(g, hi, s->batch, s->fbpq, s->muH, s->st);
+    const BatchGeo& B = s->geo;
+    const size_t npix = (size_t)g.nx * g.ny;
+    for (int z = 0; z < s->batch;) {   // one FBP per run of slices with the same geometry
+        int e = z + 1;
+        while (e < s->batch && B.uniq[e] == B.uniq[z]) ++e;
+        launch_fbp(B.g[z], lo + B.sino0[z], e - z, s->fbpq, s->muL + z * npix, s->st);
+        launch_fbp(B.g[z], hi + B.sino0[z], e - z, s->fbpq, s->muH + z * npix, s->st);
+        z = e;
+    }
     launch_init_state(s->M, g.ny, g.nx, s->batch, s->muL, s->muH, (float)s->rp.p.rho_min, s->f,
                       s->rho, s->t, s->st);
     project_residual(s, lo, hi);
@@ -801,10 +912,10 @@ static int one_iteration(dect_solver* s) {
     ImgArgs a;
     a.ny = g.ny;
     a.nx = g.nx;
-    a.nv = g.nv;
-    a.nd = g.nd;
+    a.nv = s->tab.nv_max;
+    a.nd = s->tab.nd_max;
     a.batch = s->batch;
-    a.eta2 = (float)(2.0 * R.eta);
+    a.eta2 = 2.0f;   // each slice's eta is carried by its residual sinograms
     a.xi2 = (float)(2.0 * R.xi);
     a.beta2 = (float)(2.0 * beta);
     a.thr = (float)(R.p.lambda / beta);
@@ -823,7 +934,7 @@ static int one_iteration(dect_solver* s) {
     pa.partials = s->part_proj;
     pa.img_partials = s->part_img;
     pa.img_nblocks = grad_nblocks(g.ny, g.nx);
-    pa.w_data = 2.0 * R.eta;
+    pa.w_data = 2.0;
     pa.w_coup = 2.0 * R.xi;
     pa.w_reg = 2.0 * beta;
     pa.alpha = s->alpha;
@@ -860,7 +971,7 @@ static int one_iteration(dect_solver* s) {
     if (int rc = run_pcg(pc, s->pcg, R.p.t_maxit, s->last_pcg + 2, s->fft, s->st, &iters)) return rc;
     s->last_pcg = iters;
     // f^(k+1), residual sinograms
-    launch_update(a, pad_layout(g), s->alpha, s->dpad, s->f, s->S, s->zq, s->st);
+    launch_update(a, pad_layout(g), s->tab, s->alpha, s->dpad, s->f, s->S, s->zq, s->st);
     s->beta *= R.kappa;
     s->k += 1;
     DECT_HIP(hipGetLastError());
@@ -926,6 +1037,19 @@ int dect_solver_timing(dect_solver* s, double* bp_ms, int32_t* bp_n, double* fp_
     };
     if (int rc = sum(s->ev_bp, bp_ms, bp_n)) return rc;
     return sum(s->ev_fp, fp_ms, fp_n);
+}
+
+int dect_solve_multi(const float* lo, const float* hi, const dect_geometry* geoms,
+                     const dect_params* p, float* Z, float* rho, int32_t batch, void* ws,
+                     size_t ws_bytes, hipStream_t st) {
+    if (!lo || !hi || (!Z && !rho)) return fail(DECT_EINVAL, "dect_solve_multi: NULL array");
+    dect_solver* s = nullptr;
+    if (int rc = dect_solver_create_multi(geoms, p, batch, ws, ws_bytes, st, &s)) return rc;
+    int rc = dect_solver_init(s, lo, hi);
+    if (!rc) rc = dect_solver_iterate(s, p->n_iter);
+    if (!rc) rc = dect_solver_finish(s, Z, rho);
+    dect_solver_destroy(s);
+    return rc;
 }
 
 int dect_solve(const float* lo, const float* hi, const dect_geometry* g, const dect_params* p,

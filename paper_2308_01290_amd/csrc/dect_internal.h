@@ -43,12 +43,31 @@ int resolve_geometry(const dect_geometry* in, Geom* out);
 //                    (inclusive, one step of margin; k_lo > k_hi: none);
 //   view[v]        = {cos, sin, h*(|cos| + |sin|), 0} for the voxel-driven
 //                    footprint (h = half pixel, mm).
+//
+// A batch may hold slices of different fan geometry (same image grid): the
+// tables of its distinct geometries sit back to back, and a per-slice
+// descriptor gives each slice's sizes, table offsets and sinogram offset.
+struct SliceDesc {
+    int nv, nd;            // views, bins
+    int ray0, view0;       // first ray / view of this slice's table
+    long long sino0;       // first element of this slice's sinograms and residuals
+    float sid, sdd;        // source-isocentre, source-detector distance (mm)
+    float u0, inv_pitch;   // detector coordinate of bin 0 (mm), 1 / bin pitch
+    double eta;            // projection-data weight of eq. (10) for this geometry
+};
 struct RayTable {
     int4* fix = nullptr;
     float2* flt = nullptr;
     int2* span = nullptr;
     float4* view = nullptr;
+    // device descriptors: slice / pair z uses desc[desc_stride * z], its
+    // sinograms start at desc.sino0 + z * sino_zstride
+    const SliceDesc* desc = nullptr;
+    int desc_stride = 0;
+    long long sino_zstride = 0;
+    int nv_max = 0, nd_max = 0;   // largest slice (launch grid)
 };
+SliceDesc make_slice_desc(const Geom& g, int ray0, int view0, long long sino0, double eta);
 size_t ray_table_bytes(const Geom& g);
 void launch_build_ray_table(const Geom& g, RayTable t, hipStream_t st);
 
@@ -92,11 +111,13 @@ void launch_pair_sinos(const Geom& g, const float* sino, int nsino, float2* out,
 // ---- projector ----------------------------------------------------------------
 enum ProjMode { PROJ_PLAIN = 0, PROJ_RESID = 1, PROJ_LINESEARCH = 2 };
 struct ProjArgs {
-    // PROJ_PLAIN: write channel 0 to out[2z], channel 1 to out[2z+1] (< nout)
+    // PROJ_PLAIN (one geometry, sino_zstride = nv*nd): channel 0 to out[2z],
+    // channel 1 to out[2z+1] (< nout)
     float* out = nullptr;
     int nout = 0;
-    // PROJ_RESID: S = C^T (C Y - p) from p_lo/p_hi [z][nv][nd] -> res (float2)
-    // PROJ_LINESEARCH: zq = C^T C Y -> res; block partials of ||C Y||^2
+    // PROJ_RESID: S = eta C^T (C Y - p) from p_lo/p_hi -> res (float2)
+    // PROJ_LINESEARCH: zq = eta C^T C Y -> res; block partials of eta ||C Y||^2
+    // (eta of the slice's descriptor: the data weight travels with the residual)
     const float* p_lo = nullptr;
     const float* p_hi = nullptr;
     float2* res = nullptr;
@@ -105,11 +126,11 @@ struct ProjArgs {
     // line-search finish (last block): alpha[z] = num / den
     const double* img_partials = nullptr;        // [z][img_nblocks][3]
     int img_nblocks = 0;
-    double w_data = 0, w_coup = 0, w_reg = 0;    // 2 eta, 2 xi, 2 beta
+    double w_data = 0, w_coup = 0, w_reg = 0;    // 2, 2 xi, 2 beta
     double* alpha = nullptr;                     // [z]
     unsigned* counter = nullptr;                 // [z]
 };
-int proj_nblocks(const Geom& g);  // blocks per pair
+int proj_nblocks(int nv_max, int nd_max);  // blocks per pair
 void launch_project(const Geom& g, const RayTable& t, const float2* pad, int npairs, int mode,
                     const ProjArgs& a, hipStream_t st);
 
@@ -176,7 +197,7 @@ int build_model(const dect_params& p, Model* out);
 
 struct ImgArgs {
     int ny, nx, nv, nd, batch;
-    float eta2, xi2, beta2, thr;   // 2*eta, 2*xi, 2*beta, lambda/beta (FP32)
+    float eta2, xi2, beta2, thr;   // 2 (the residual carries eta), 2*xi, 2*beta, lambda/beta
     float beta;
 };
 int grad_nblocks(int ny, int nx);
@@ -187,8 +208,8 @@ void launch_init_state(const Model& M, int ny, int nx, int batch, const float* m
 void launch_grad(const Model& M, const ImgArgs& a, const PadLayout& P, const float2* f,
                  const float2* B, const float* rho, const float* t, float2* dpad,
                  double* partials, hipStream_t st);
-void launch_update(const ImgArgs& a, const PadLayout& P, const double* alpha, const float2* dpad,
-                   float2* f, float2* S, const float2* zq, hipStream_t st);
+void launch_update(const ImgArgs& a, const PadLayout& P, const RayTable& T, const double* alpha,
+                   const float2* dpad, float2* f, float2* S, const float2* zq, hipStream_t st);
 void launch_finish(const Model& M, int ny, int nx, int batch, const float* rho, const float* t,
                    float rho_min, double t_min, float* Z, float* rho_out, hipStream_t st);
 void launch_split_f2(int n, int batch, const float2* f, float* a, float* b, hipStream_t st);

@@ -190,7 +190,7 @@ void launch_grad(const Model& M, const ImgArgs& a, const PadLayout& P, const flo
 }
 
 // ---------------------------------------------------------------------------
-__global__ void k_update(int ny, int nx, size_t nray, PadLayout P, const double* __restrict__ alpha,
+__global__ void k_update(int ny, int nx, PadLayout P, RayTable T, const double* __restrict__ alpha,
                          const float2* __restrict__ dpad, float2* __restrict__ f,
                          float2* __restrict__ S, const float2* __restrict__ zq) {
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -204,21 +204,25 @@ __global__ void k_update(int ny, int nx, size_t nray, PadLayout P, const double*
         v.x = fmaf(al, d.x, v.x);
         v.y = fmaf(al, d.y, v.y);
         f[z * npix + idx] = v;
-    } else if (idx < npix + nray) {
-        const size_t r = idx - npix;
-        const float2 q = zq[z * nray + r];
-        float2 v = S[z * nray + r];
+        return;
+    }
+    const SliceDesc D = T.desc[T.desc_stride * z];
+    const size_t r = idx - npix;
+    if (r < (size_t)D.nv * D.nd) {
+        const size_t o = (size_t)(D.sino0 + (long long)z * T.sino_zstride) + r;
+        const float2 q = zq[o];
+        float2 v = S[o];
         v.x = fmaf(al, q.x, v.x);
         v.y = fmaf(al, q.y, v.y);
-        S[z * nray + r] = v;
+        S[o] = v;
     }
 }
 
-void launch_update(const ImgArgs& a, const PadLayout& P, const double* alpha, const float2* dpad,
-                   float2* f, float2* S, const float2* zq, hipStream_t st) {
-    const size_t n = (size_t)a.nx * a.ny + (size_t)a.nv * a.nd;
+void launch_update(const ImgArgs& a, const PadLayout& P, const RayTable& T, const double* alpha,
+                   const float2* dpad, float2* f, float2* S, const float2* zq, hipStream_t st) {
+    const size_t n = (size_t)a.nx * a.ny + (size_t)T.nv_max * T.nd_max;
     hipLaunchKernelGGL(k_update, dim3((unsigned)((n + 255) / 256), a.batch), dim3(256), 0, st, a.ny,
-                       a.nx, (size_t)a.nv * a.nd, P, alpha, dpad, f, S, zq);
+                       a.nx, P, T, alpha, dpad, f, S, zq);
 }
 
 // ---------------------------------------------------------------------------

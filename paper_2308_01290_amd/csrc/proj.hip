@@ -112,6 +112,21 @@ __global__ void k_build_ray_table(Geom g, int4* __restrict__ fix, float2* __rest
     span[r] = make_int2(klo, khi);
 }
 
+SliceDesc make_slice_desc(const Geom& g, int ray0, int view0, long long sino0, double eta) {
+    SliceDesc d;
+    d.nv = g.nv;
+    d.nd = g.nd;
+    d.ray0 = ray0;
+    d.view0 = view0;
+    d.sino0 = sino0;
+    d.sid = (float)g.sid;
+    d.sdd = (float)g.sdd;
+    d.u0 = (float)(-0.5 * (g.nd - 1) * g.pitch + g.offset);
+    d.inv_pitch = (float)(1.0 / g.pitch);
+    d.eta = eta;
+    return d;
+}
+
 void launch_build_ray_table(const Geom& g, RayTable t, hipStream_t st) {
     dim3 grid((g.nd + 255) / 256, g.nv);
     hipLaunchKernelGGL(k_build_ray_table, grid, dim3(256), 0, st, g, t.fix, t.flt, t.span, t.view);
@@ -228,21 +243,22 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
     s = t;
 }
 
-int proj_nblocks(const Geom& g) { return ((g.nd + 255) / 256) * g.nv; }
+int proj_nblocks(int nv, int nd) { return ((nd + 255) / 256) * nv; }
 
 template <int MODE>
 __global__ __launch_bounds__(256) void k_project(const float2* __restrict__ pad, PadLayout P,
-                                                 const int4* __restrict__ fix,
-                                                 const float2* __restrict__ flt,
-                                                 const int2* __restrict__ span, int nx, int ny,
-                                                 int nv, int nd, ProjArgs a) {
+                                                 RayTable T, int nx, int ny, ProjArgs a) {
     const int v = blockIdx.y, z = blockIdx.z;
+    const SliceDesc D = T.desc[T.desc_stride * z];
+    const int nd = D.nd;
     const int j = blockIdx.x * 256 + threadIdx.x;
-    const bool valid = j < nd;
-    const size_t r = (size_t)v * nd + j;
-    const int4 fx = valid ? fix[r] : make_int4(0, 0, 0, 0);
-    const float2 fl = valid ? flt[r] : make_float2(__builtin_inff(), 1.f);
-    const int2 sp = valid ? span[r] : make_int2(1, 0);
+    const bool valid = j < nd && v < D.nv;   // the grid covers the batch's largest slice
+    const size_t r = (size_t)v * nd + j;     // ray within the slice
+    const size_t rt = (size_t)D.ray0 + r;    // its table entry
+    const long long s0 = D.sino0 + (long long)z * T.sino_zstride;
+    const int4 fx = valid ? T.fix[rt] : make_int4(0, 0, 0, 0);
+    const float2 fl = valid ? T.flt[rt] : make_float2(__builtin_inff(), 1.f);
+    const int2 sp = valid ? T.span[rt] : make_int2(1, 0);
     const bool xmaj = fl.y > 0.f;
     const float L = fabsf(fl.y);
     const float ainv32 = fl.x;
@@ -306,18 +322,18 @@ __global__ __launch_bounds__(256) void k_project(const float2* __restrict__ pad,
     }
     const double Y1 = (double)L * ((double)s1 - (double)c1);
     const double Y2 = (double)L * ((double)s2 - (double)c2);
-    const size_t nray = (size_t)nv * nd;
+    const size_t nray = (size_t)D.nv * nd;
     if constexpr (MODE == PROJ_PLAIN) {
         if (valid) {
-            a.out[(size_t)(2 * z) * nray + r] = (float)Y1;
-            if (2 * z + 1 < a.nout) a.out[(size_t)(2 * z + 1) * nray + r] = (float)Y2;
+            a.out[(size_t)(2 * s0) + r] = (float)Y1;
+            if (2 * z + 1 < a.nout) a.out[(size_t)(2 * s0) + nray + r] = (float)Y2;
         }
     } else if constexpr (MODE == PROJ_RESID) {
         if (valid) {
-            const double rl = (double)a.c00 * Y1 + (double)a.c01 * Y2 - (double)a.p_lo[(size_t)z * nray + r];
-            const double rh = (double)a.c10 * Y1 + (double)a.c11 * Y2 - (double)a.p_hi[(size_t)z * nray + r];
-            a.res[(size_t)z * nray + r] = make_float2((float)((double)a.c00 * rl + (double)a.c10 * rh),
-                                                      (float)((double)a.c01 * rl + (double)a.c11 * rh));
+            const double rl = (double)a.c00 * Y1 + (double)a.c01 * Y2 - (double)a.p_lo[s0 + r];
+            const double rh = (double)a.c10 * Y1 + (double)a.c11 * Y2 - (double)a.p_hi[s0 + r];
+            a.res[s0 + r] = make_float2((float)(D.eta * ((double)a.c00 * rl + (double)a.c10 * rh)),
+                                        (float)(D.eta * ((double)a.c01 * rl + (double)a.c11 * rh)));
         }
     } else {   // PROJ_LINESEARCH
         __shared__ double sh[4];
@@ -325,16 +341,21 @@ __global__ __launch_bounds__(256) void k_project(const float2* __restrict__ pad,
         if (valid) {
             const double yl = (double)a.c00 * Y1 + (double)a.c01 * Y2;
             const double yh = (double)a.c10 * Y1 + (double)a.c11 * Y2;
-            a.res[(size_t)z * nray + r] = make_float2((float)((double)a.c00 * yl + (double)a.c10 * yh),
-                                                      (float)((double)a.c01 * yl + (double)a.c11 * yh));
-            part = yl * yl + yh * yh;
+            a.res[s0 + r] = make_float2((float)(D.eta * ((double)a.c00 * yl + (double)a.c10 * yh)),
+                                        (float)(D.eta * ((double)a.c01 * yl + (double)a.c11 * yh)));
+            part = D.eta * (yl * yl + yh * yh);
         }
-        const int nblk = gridDim.x * gridDim.y;
-        const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+        // partials in the slice's own block order (the launch may cover a larger
+        // slice of the batch), so a slice reduces exactly as it does alone
+        const int nbx = (nd + 255) / 256;
+        if (v >= D.nv || (int)blockIdx.x >= nbx) return;
+        const int nblk = nbx * D.nv;
+        const int bid = v * nbx + blockIdx.x;
+        double* zp = a.partials + (size_t)z * gridDim.x * gridDim.y;
         const double bs = block_sum<256>(part, sh);
-        if (threadIdx.x == 0) a.partials[(size_t)z * nblk + bid] = bs;
+        if (threadIdx.x == 0) zp[bid] = bs;
         if (last_block_arrive(a.counter + z, (unsigned)nblk)) {
-            const double den_data = block_sum_array<256>(a.partials + (size_t)z * nblk, nblk, 1, sh);
+            const double den_data = block_sum_array<256>(zp, nblk, 1, sh);
             const double* ip = a.img_partials + (size_t)z * a.img_nblocks * 3;
             const double num = block_sum_array<256>(ip + 0, a.img_nblocks, 3, sh);
             const double coup = block_sum_array<256>(ip + 1, a.img_nblocks, 3, sh);
@@ -349,17 +370,15 @@ __global__ __launch_bounds__(256) void k_project(const float2* __restrict__ pad,
 
 void launch_project(const Geom& g, const RayTable& t, const float2* pad, int npairs, int mode,
                     const ProjArgs& a, hipStream_t st) {
-    dim3 grid((g.nd + 255) / 256, g.nv, npairs);
+    dim3 grid((t.nd_max + 255) / 256, t.nv_max, npairs);
     const PadLayout P = pad_layout(g);
     if (mode == PROJ_PLAIN)
-        hipLaunchKernelGGL(k_project<PROJ_PLAIN>, grid, dim3(256), 0, st, pad, P, t.fix, t.flt,
-                           t.span, g.nx, g.ny, g.nv, g.nd, a);
+        hipLaunchKernelGGL(k_project<PROJ_PLAIN>, grid, dim3(256), 0, st, pad, P, t, g.nx, g.ny, a);
     else if (mode == PROJ_RESID)
-        hipLaunchKernelGGL(k_project<PROJ_RESID>, grid, dim3(256), 0, st, pad, P, t.fix, t.flt,
-                           t.span, g.nx, g.ny, g.nv, g.nd, a);
+        hipLaunchKernelGGL(k_project<PROJ_RESID>, grid, dim3(256), 0, st, pad, P, t, g.nx, g.ny, a);
     else
-        hipLaunchKernelGGL(k_project<PROJ_LINESEARCH>, grid, dim3(256), 0, st, pad, P, t.fix, t.flt,
-                           t.span, g.nx, g.ny, g.nv, g.nd, a);
+        hipLaunchKernelGGL(k_project<PROJ_LINESEARCH>, grid, dim3(256), 0, st, pad, P, t, g.nx,
+                           g.ny, a);
 }
 
 // ---------------------------------------------------------------------------
@@ -376,21 +395,25 @@ constexpr int kBpWaves = 8;
 constexpr int kBpViewChunk = 256;
 
 __global__ __launch_bounds__(kBpWaves * 64) void k_backproject(
-    const float2* __restrict__ sino, const int4* __restrict__ fix, const float2* __restrict__ flt,
-    const float4* __restrict__ view, int nx, int ny, int nv, int nd, float sid, float sdd,
-    float dxmm, float u0, float inv_pitch, float2* __restrict__ out_pairs,
-    float* __restrict__ out_split, int nout) {
+    const float2* __restrict__ sino, RayTable T, int nx, int ny, float dxmm,
+    float2* __restrict__ out_pairs, float* __restrict__ out_split, int nout) {
     __shared__ float4 vs[kBpViewChunk];
     __shared__ int4 sfix[kBpWaves][64];
     __shared__ float4 sray[kBpWaves][64];      // (2^-32/|s|, +-L, sino lo, sino hi)
     __shared__ float red[kBpWaves][8][64];
     const int z = blockIdx.z;
+    const SliceDesc D = T.desc[T.desc_stride * z];
+    const int nv = D.nv, nd = D.nd;
+    const float sid = D.sid, sdd = D.sdd, u0 = D.u0, inv_pitch = D.inv_pitch;
+    const int4* __restrict__ fix = T.fix + D.ray0;
+    const float2* __restrict__ flt = T.flt + D.ray0;
+    const float4* __restrict__ view = T.view + D.view0;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int i0 = blockIdx.y * 16 + 2 * (lane >> 3), k0 = blockIdx.x * 16 + 2 * (lane & 7);
     // quad centre (between pixels k0, k0 + 1 and rows i0, i0 + 1)
     const float x = ((float)k0 + 0.5f - 0.5f * (float)(nx - 1)) * dxmm;
     const float y = ((float)i0 + 0.5f - 0.5f * (float)(ny - 1)) * dxmm;
-    const float2* sz = sino + (size_t)z * nv * nd;
+    const float2* sz = sino + (D.sino0 + (long long)z * T.sino_zstride);
     // acc[di][dk]: pixel (i0 + di, k0 + dk), both channels
     float a00x = 0.f, a00y = 0.f, a01x = 0.f, a01y = 0.f;
     float a10x = 0.f, a10y = 0.f, a11x = 0.f, a11y = 0.f;
@@ -500,10 +523,8 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_backproject(
 void launch_backproject(const Geom& g, const RayTable& t, const float2* sino, int npairs,
                         float2* out_pairs, float* out_split, int nout, hipStream_t st) {
     dim3 grid((g.nx + 15) / 16, (g.ny + 15) / 16, npairs);
-    const float u0 = (float)(-0.5 * (g.nd - 1) * g.pitch + g.offset);
-    hipLaunchKernelGGL(k_backproject, grid, dim3(kBpWaves * 64), 0, st, sino, t.fix, t.flt, t.view,
-                       g.nx, g.ny, g.nv, g.nd, (float)g.sid, (float)g.sdd, (float)g.dx, u0,
-                       (float)(1.0 / g.pitch), out_pairs, out_split, nout);
+    hipLaunchKernelGGL(k_backproject, grid, dim3(kBpWaves * 64), 0, st, sino, t, g.nx, g.ny,
+                       (float)g.dx, out_pairs, out_split, nout);
 }
 
 }  // namespace dect

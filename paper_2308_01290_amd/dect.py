@@ -47,6 +47,7 @@ EXPORTS = [
     "dect_solve_workspace_bytes", "dect_solver_create", "dect_solver_destroy", "dect_solver_init",
     "dect_solver_set_state", "dect_solver_iterate", "dect_solver_get_state", "dect_solver_finish",
     "dect_solver_stats", "dect_solver_enable_timing", "dect_solver_timing", "dect_solve",
+    "dect_solve_workspace_bytes_multi", "dect_solver_create_multi", "dect_solve_multi",
     "dect_last_error",
 ]
 
@@ -85,6 +86,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.dect_solver_enable_timing.argtypes = [vp, C.c_int]
     L.dect_solver_timing.argtypes = [vp, P(C.c_double), P(C.c_int32), P(C.c_double), P(C.c_int32)]
     L.dect_solve.argtypes = [vp, vp, G, Pp, vp, vp, C.c_int32, vp, C.c_size_t, vp]
+    L.dect_solve_workspace_bytes_multi.argtypes = [G, Pp, C.c_int32]
+    L.dect_solve_workspace_bytes_multi.restype = C.c_size_t
+    L.dect_solver_create_multi.argtypes = [G, Pp, C.c_int32, vp, C.c_size_t, vp, P(vp)]
+    L.dect_solve_multi.argtypes = [vp, vp, G, Pp, vp, vp, C.c_int32, vp, C.c_size_t, vp]
     L.dect_last_error.argtypes = []
     L.dect_last_error.restype = C.c_char_p
     return L
@@ -275,20 +280,65 @@ def l0_step(g_tilde, g, lam, beta, weight=None, tol=1e-6, max_iter=200, return_h
     return (g, h, v) if return_hv else g
 
 
+def _geometry_array(geoms):
+    gs = [Geometry.of(g) for g in geoms]
+    arr = (_Geometry * len(gs))(*[g.c() for g in gs])
+    return gs, arr
+
+
+def sinogram_elements(geoms) -> int:
+    """Length of the back-to-back sinograms of a batch of uneven slices."""
+    return sum(int(g.n_views) * int(g.n_det) for g in geoms)
+
+
+def concat_sinograms(sinos):
+    """Slices' [n_views, n_det] sinograms back to back (the layout of the
+    uneven-batch entry points)."""
+    torch = _torch()
+    return torch.cat([t.reshape(-1) for t in sinos]).contiguous()
+
+
 class Solver:
-    """A batch of slices with shared geometry and parameters, state on device."""
+    """A batch of slices with shared parameters and image grid, state on device.
+
+    `geom` is one geometry (with `batch` slices of it) or a sequence of
+    per-slice geometries (uneven batch; sinograms then go back to back, see
+    concat_sinograms)."""
 
     def __init__(self, geom, params=None, batch: int = 1, device="cuda", stream=None):
-        self.geom = Geometry.of(geom)
         self.params = params if params is not None else default_params()
-        self.batch = int(batch)
         self.device = device
         self._stream = stream
         h = C.c_void_p()
-        gc = self.geom.c()
-        _check(lib().dect_solver_create(C.byref(gc), C.byref(self.params), self.batch, None, 0,
-                                        C.c_void_p(_stream(stream)), C.byref(h)), "dect_solver_create")
+        if isinstance(geom, (list, tuple)):
+            self.geoms, arr = _geometry_array(geom)
+            self.geom = self.geoms[0]
+            self.batch = len(self.geoms)
+            self.uneven = True
+            _check(lib().dect_solver_create_multi(arr, C.byref(self.params), self.batch, None, 0,
+                                                  C.c_void_p(_stream(stream)), C.byref(h)),
+                   "dect_solver_create_multi")
+        else:
+            self.geom = Geometry.of(geom)
+            self.batch = int(batch)
+            self.geoms = [self.geom] * self.batch
+            self.uneven = False
+            gc = self.geom.c()
+            _check(lib().dect_solver_create(C.byref(gc), C.byref(self.params), self.batch, None, 0,
+                                            C.c_void_p(_stream(stream)), C.byref(h)),
+                   "dect_solver_create")
         self._h = h
+
+    def _check_sinos(self, lo, hi):
+        if self.uneven:
+            n = sinogram_elements(self.geoms)
+            for name, t in (("sino_lo", lo), ("sino_hi", hi)):
+                _dev_f32(t, (t.shape[-1],), name)
+                if t.numel() != n:
+                    raise ValueError(f"{name} has {t.numel()} elements, the batch needs {n}")
+        else:
+            _dev_f32(lo, (self.geom.n_views, self.geom.n_det), "sino_lo")
+            _dev_f32(hi, (self.geom.n_views, self.geom.n_det), "sino_hi")
 
     def close(self):
         if getattr(self, "_h", None):
@@ -307,13 +357,13 @@ class Solver:
                            dtype=torch.float32)
 
     def init(self, sino_lo, sino_hi):
-        _dev_f32(sino_lo, (self.geom.n_views, self.geom.n_det), "sino_lo")
-        _dev_f32(sino_hi, (self.geom.n_views, self.geom.n_det), "sino_hi")
+        self._check_sinos(sino_lo, sino_hi)
         _check(lib().dect_solver_init(self._h, _ptr(sino_lo), _ptr(sino_hi)), "dect_solver_init")
         self._keep = (sino_lo, sino_hi)
         return self
 
     def set_state(self, sino_lo, sino_hi, f1, f2, rho, t, k=0):
+        self._check_sinos(sino_lo, sino_hi)
         for name, a in (("f1", f1), ("f2", f2), ("rho", rho), ("t", t)):
             _dev_f32(a, (self.geom.n_y, self.geom.n_x), name)
         _check(lib().dect_solver_set_state(self._h, _ptr(sino_lo), _ptr(sino_hi), _ptr(f1), _ptr(f2),
@@ -368,4 +418,23 @@ def solve(sino_lo, sino_hi, geom, params=None, stream=None):
     gc = g.c()
     _check(lib().dect_solve(_ptr(sino_lo), _ptr(sino_hi), C.byref(gc), C.byref(p), _ptr(Z), _ptr(R), b,
                             None, 0, C.c_void_p(_stream(stream))), "dect_solve")
+    return Z, R
+
+
+def solve_multi(sino_lo, sino_hi, geoms, params=None, stream=None):
+    """Whole solve of a batch of uneven slices (sinograms back to back, see
+    concat_sinograms) -> (Z, rho_e), each [batch, n_y, n_x]."""
+    torch = _torch()
+    gs, arr = _geometry_array(geoms)
+    p = params if params is not None else default_params()
+    n = sinogram_elements(gs)
+    for name, t in (("sino_lo", sino_lo), ("sino_hi", sino_hi)):
+        _dev_f32(t, (t.shape[-1],), name)
+        if t.numel() != n:
+            raise ValueError(f"{name} has {t.numel()} elements, the batch needs {n}")
+    b = len(gs)
+    Z = torch.empty((b, gs[0].n_y, gs[0].n_x), device=sino_lo.device, dtype=torch.float32)
+    R = torch.empty_like(Z)
+    _check(lib().dect_solve_multi(_ptr(sino_lo), _ptr(sino_hi), arr, C.byref(p), _ptr(Z), _ptr(R), b,
+                                  None, 0, C.c_void_p(_stream(stream))), "dect_solve_multi")
     return Z, R

@@ -349,3 +349,37 @@ def workload_slice512(mu_of: MuFn, seed: int = 2308, noise_seeds=(2309, 2310), I
     ph = phantom_body_inserts(seed)
     pL, pH = analytic_sinograms(ph, geom, mu_of)
     return geom, ph, poisson_log(pL, I0[0], noise_seeds[0]), poisson_log(pH, I0[1], noise_seeds[1])
+
+
+# --------------------------------------------------------------------------
+# batches of uneven slices
+# --------------------------------------------------------------------------
+UNEVEN_SIZES = (256, 384, 512)
+UNEVEN_VIEWS = (360, 720, 984)
+UNEVEN_BINS = (512, 888)
+
+
+def geometry_uneven(seed: int) -> FanGeometry:
+    """One slice of an uneven batch: n in {256, 384, 512} at 0.8 mm, views in
+    {360, 720, 984} over 360 deg, bins uniform in 512..888, SID 1000, SDD 1500."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = int(rng.choice(UNEVEN_SIZES))
+    v = int(rng.choice(UNEVEN_VIEWS))
+    d = int(rng.integers(UNEVEN_BINS[0], UNEVEN_BINS[1] + 1))
+    return FanGeometry(n_x=n, n_y=n, pixel_mm=0.8, n_views=v, n_det=d, sid_mm=1000.0,
+                       sdd_mm=1500.0).resolved()
+
+
+def slice_uneven(seed: int, mu_of: MuFn, I0=(5e4, 1e5)):
+    """(geometry, phantom, p_lo, p_hi) of uneven-batch slice `seed`: the body
+    phantom of the 512^2 slice scaled to the slice's field of view."""
+    geom = geometry_uneven(seed)
+    s = geom.n_x / 512.0
+    ph = phantom_body_inserts(seed, body_ax=(180.0 * s, 140.0 * s), semi=(3.0 * s, 18.0 * s))
+    pL, pH = analytic_sinograms(ph, geom, mu_of)
+    return (geom, ph, poisson_log(pL, I0[0], 2 * seed + 1), poisson_log(pH, I0[1], 2 * seed + 2))
+
+
+def workload_uneven(mu_of: MuFn, n_slices: int = 64, seed0: int = 3000):
+    """The uneven batch: slices seed0, seed0 + 1, ... (list of slice_uneven tuples)."""
+    return [slice_uneven(seed0 + i, mu_of) for i in range(n_slices)]

@@ -100,6 +100,14 @@ def test_entry_points_reject_bad_arguments_before_enqueueing():
     p = dect.default_params(t_precond=3)
     assert L.dect_solver_create(C.byref(odd), C.byref(p), 1, None, 0, None, C.byref(h)) == -5
     assert b"multigrid" in L.dect_last_error()
+    # uneven batch: the image grid must agree across slices
+    ga = dect.Geometry.of(P.geometry_small())
+    gb = dect.Geometry.of(P.FanGeometry(**{**P.geometry_small().__dict__, "n_x": 96}))
+    arr = (dect._Geometry * 2)(ga.c(), gb.c())
+    p = dect.default_params()
+    assert L.dect_solver_create_multi(arr, C.byref(p), 2, None, 0, None, C.byref(h)) == -1
+    assert b"differs from slice 0" in L.dect_last_error()
+    assert L.dect_solve_workspace_bytes_multi(arr, C.byref(p), 2) == 0
     # l0 step: unsupported FFT size, NULL input
     assert L.dect_l0_step(None, None, None, None, None, 16, 16, 1, 0.1, 1.0, 1e-6, 10, None, 0, None) == -1
     assert L.dect_l0_step(C.c_void_p(1), None, C.c_void_p(1), None, None, 10, 16, 1, 0.1, 1.0, 1e-6,
@@ -116,4 +124,13 @@ def test_workspace_sizes_are_consistent():
     # 512^2 slice, 720 x 736 sinogram: a few tens of MB per slice
     assert 20e6 < one < 120e6
     assert L.dect_l0_step_workspace_bytes(512, 512, 1, 0) >= 512 * 512 * 8
+    # uneven batch of one geometry repeated == the plain batch
+    arr = (dect._Geometry * 4)(*([g] * 4))
+    assert L.dect_solve_workspace_bytes_multi(arr, C.byref(p), 4) == four
+    # a second geometry with more views and bins needs more
+    g2 = dect.Geometry.of(P.FanGeometry(**{**P.geometry_slice512().__dict__, "n_views": 984,
+                                           "n_det": 888, "det_pitch_mm": 0.0})).c()
+    arr = (dect._Geometry * 2)(g, g2)
+    assert L.dect_solve_workspace_bytes_multi(arr, C.byref(p), 2) > L.dect_solve_workspace_bytes(
+        C.byref(g), C.byref(p), 2)
     assert L.dect_l0_step_workspace_bytes(512, 512, 1, 1) > L.dect_l0_step_workspace_bytes(512, 512, 1, 0)
