@@ -1,6 +1,11 @@
 #!/usr/bin/env python3
 """Benchmark: whole-slice solves per second on the 512^2 slice.
 
+With --workload uneven64 it times instead the batch of 64 uneven slices
+(image 256/384/512 at 0.8 mm, 360/720/984 views, 512-888 bins): slices of
+one image size run as one batch (one launch per kernel and iteration for
+all of them), against the same 64 slices solved one at a time.
+
 Workload: 512x512 image at 0.8 mm, 720 views over 360 deg, 736 detector bins,
 SID 1000 mm, SDD 1500 mm, dual-energy sinograms of an elliptical water body
 with 40 bone / soft-tissue / lung inserts, Poisson noise 5e4 / 1e5, 50 outer
@@ -99,6 +104,82 @@ def cpu_baseline(g, pL, pH, iters: int):
                       f"({per_slice:.1f} s per slice)"}
 
 
+def _uneven_slice(i):
+    from paper_2308_01290_amd import dect
+    from paper_2308_01290_amd import phantoms as P
+    params = dect.default_params()
+    g, ph, pL, pH = P.slice_uneven(3000 + i, lambda Z, R: dect.attenuation(params, Z, R))
+    return g, pL.astype(np.float32), pH.astype(np.float32)
+
+
+def bench_uneven(args):
+    """64 uneven slices, 50 iterations each: batched by image size against one
+    slice at a time; a step solves all 64 slices."""
+    import multiprocessing as mp
+    import torch
+    from paper_2308_01290_amd import dect
+    n_slices = 64
+    workers = min(16, os.cpu_count() or 1)
+    with mp.get_context("spawn").Pool(workers) as pool:
+        data = pool.map(_uneven_slice, range(n_slices))
+    params = dect.default_params(n_iter=N_ITER)
+    dev = torch.device("cuda:0")
+    groups = {}
+    for i, (g, pL, pH) in enumerate(data):
+        groups.setdefault(g.n_x, []).append(i)
+    batched = []
+    for n, idx in sorted(groups.items()):
+        geoms = [data[i][0] for i in idx]
+        lo = dect.concat_sinograms([torch.as_tensor(data[i][1], device=dev) for i in idx])
+        hi = dect.concat_sinograms([torch.as_tensor(data[i][2], device=dev) for i in idx])
+        batched.append((dect.Solver(geoms, params), lo, hi))
+    single = []
+    for g, pL, pH in data:
+        single.append((dect.Solver(g, params), torch.as_tensor(pL[None], device=dev),
+                       torch.as_tensor(pH[None], device=dev)))
+
+    def run(solvers):
+        out = []
+        for sol, lo, hi in solvers:
+            sol.init(lo, hi)
+            sol.iterate(N_ITER)
+            out.append(sol.finish())
+        return out
+
+    def timed(solvers, steps, warmup):
+        for _ in range(warmup):
+            run(solvers)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res = run(solvers)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, res
+
+    t_b, res_b = timed(batched, args.steps, args.warmup)
+    t_s, res_s = timed(single, max(1, args.steps // 2), 1)
+    # the batch must give each slice's own result
+    same = True
+    for (n, idx), (Zb, Rb) in zip(sorted(groups.items()), res_b):
+        for j, i in enumerate(idx):
+            Zs, Rs = res_s[i]
+            same = same and bool(torch.equal(Zb[j], Zs[0])) and bool(torch.equal(Rb[j], Rs[0]))
+    out = {
+        "metric": "uneven batch slices/s (64 slices, 256-512^2, 360-984 views, 50 iters)",
+        "value": n_slices / t_b, "unit": "slices/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * t_b, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "64 uneven slices: n in {256, 384, 512} at 0.8 mm, views in "
+                               "{360, 720, 984}, bins 512-888, scaled body phantom with 40 inserts, "
+                               "Poisson 5e4/1e5, 50 outer iterations",
+                   "groups": {str(n): len(idx) for n, idx in sorted(groups.items())}},
+        "one_slice_at_a_time": {"value": n_slices / t_s, "unit": "slices/s", "ms_per_step": 1e3 * t_s},
+        "speedup": t_s / t_b,
+        "results_identical_to_one_at_a_time": same,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +187,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--workload", choices=["slice512", "uneven64"], default="slice512")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first copy a device buffer of this many MiB once: the reference "
                          "kernel of known traffic for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
@@ -120,6 +202,9 @@ def main():
     import torch
     from paper_2308_01290_amd import dect
     from paper_2308_01290_amd import phantoms as P
+    if args.workload == "uneven64":
+        bench_uneven(args)
+        return
 
     if args.copy_mib > 0:
         src = torch.ones(args.copy_mib << 18, device="cuda:0")
