@@ -473,6 +473,7 @@ struct dect_solver {
     float2 *f, *B, *dpad, *S, *zq, *fft;   // dpad: search direction in projector pair blocks
     float *rho, *t, *muL, *muH, *fbpq;
     double *part_img, *part_proj, *alpha;
+    double *beta_d, *kappa_d;        // per-slice beta and its growth rate (device)
     unsigned* cnt_proj;
     PcgBufs pcg;
     int k;
@@ -707,10 +708,14 @@ static size_t solver_layout(const BatchGeo& B, char* base, dect_solver* s) {
     double* part_img = c.take<double>((size_t)batch * grad_nblocks(g.ny, g.nx) * 3);
     double* part_proj = c.take<double>((size_t)batch * proj_nblocks(B.nv_max, B.nd_max));
     double* alpha = c.take<double>((size_t)batch);
+    double* beta_d = c.take<double>((size_t)batch);
+    double* kappa_d = c.take<double>((size_t)batch);
     unsigned* cnt = c.take<unsigned>((size_t)batch);
     PcgBufs pb;
     carve_pcg(c, g.ny, g.nx, batch, &pb);
     if (s) {
+        s->beta_d = beta_d;
+        s->kappa_d = kappa_d;
         t.desc = desc;
         t.desc_stride = 1;
         t.sino_zstride = 0;
@@ -885,6 +890,7 @@ int dect_solver_init(dect_solver* s, const float* lo, const float* hi) {
     project_residual(s, lo, hi);
     s->k = 0;
     s->beta = s->rp.beta0;
+    launch_set_beta(s->beta_d, s->kappa_d, 0, s->batch, s->beta, s->rp.kappa, s->st);
     DECT_HIP(hipGetLastError());
     return DECT_OK;
 }
@@ -901,6 +907,7 @@ int dect_solver_set_state(dect_solver* s, const float* lo, const float* hi, cons
     s->k = k;
     s->beta = s->rp.beta0;
     for (int i = 0; i < k; ++i) s->beta *= s->rp.kappa;
+    launch_set_beta(s->beta_d, s->kappa_d, 0, s->batch, s->beta, s->rp.kappa, s->st);
     DECT_HIP(hipGetLastError());
     return DECT_OK;
 }
@@ -920,6 +927,8 @@ static int one_iteration(dect_solver* s) {
     a.beta2 = (float)(2.0 * beta);
     a.thr = (float)(R.p.lambda / beta);
     a.beta = (float)beta;
+    a.beta_z = s->beta_d;   // every kernel takes its slice's beta from here
+    a.lam = R.p.lambda;
     // f-step: A^T of the combined residuals, gradient, A of the direction
     hipEvent_t t0 = mark(s);
     launch_backproject(g, s->tab, s->S, s->batch, s->B, nullptr, 0, s->st);
@@ -937,6 +946,7 @@ static int one_iteration(dect_solver* s) {
     pa.w_data = 2.0;
     pa.w_coup = 2.0 * R.xi;
     pa.w_reg = 2.0 * beta;
+    pa.beta_z = s->beta_d;
     pa.alpha = s->alpha;
     pa.counter = s->cnt_proj;
     hipEvent_t t1 = mark(s);
@@ -956,6 +966,8 @@ static int one_iteration(dect_solver* s) {
     fa.inv_crho = 1.0 / s->M.crho;
     fa.beta = (float)beta;
     fa.thr = a.thr;
+    fa.beta_z = s->beta_d;
+    fa.lam = R.p.lambda;
     fa.c = 1.0;
     fa.out = s->rho;
     launch_fft_solve(g.ny, g.nx, s->batch, fa, s->fft, s->st);
@@ -965,13 +977,16 @@ static int one_iteration(dect_solver* s) {
     pc.beta = (float)beta;
     pc.thr = a.thr;
     pc.tol2 = R.p.t_tol * R.p.t_tol;
+    pc.beta_z = s->beta_d;
+    pc.lam = R.p.lambda;
     if (int rc = choose_prec(R.p.t_precond, s->pcg, beta, &pc)) return rc;
     launch_pcg_init_model(s->M, pc, s->f, s->st);
     int iters = 0;
     if (int rc = run_pcg(pc, s->pcg, R.p.t_maxit, s->last_pcg + 2, s->fft, s->st, &iters)) return rc;
     s->last_pcg = iters;
     // f^(k+1), residual sinograms
-    launch_update(a, pad_layout(g), s->tab, s->alpha, s->dpad, s->f, s->S, s->zq, s->st);
+    launch_update(a, pad_layout(g), s->tab, s->alpha, s->dpad, s->f, s->S, s->zq, s->beta_d,
+                  s->kappa_d, s->st);
     s->beta *= R.kappa;
     s->k += 1;
     DECT_HIP(hipGetLastError());

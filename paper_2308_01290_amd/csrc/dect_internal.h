@@ -127,6 +127,7 @@ struct ProjArgs {
     const double* img_partials = nullptr;        // [z][img_nblocks][3]
     int img_nblocks = 0;
     double w_data = 0, w_coup = 0, w_reg = 0;    // 2, 2 xi, 2 beta
+    const double* beta_z = nullptr;              // per-slice beta (then w_reg = 2 beta_z[z])
     double* alpha = nullptr;                     // [z]
     unsigned* counter = nullptr;                 // [z]
 };
@@ -165,6 +166,8 @@ struct FftArgs {
     double m00 = 0, m01 = 0, m10 = 0, m11 = 0;   // synthesis matrix (barn)
     double e1n = 0, e2n = 0, inv_crho = 0;       // E1^n, E2^n, 1/c_rho
     float beta = 0, thr = 0;
+    const double* beta_z = nullptr;   // per-slice beta: then beta = beta_z[z], thr = lam / beta_z[z]
+    double lam = 0.0;
     double c = 1.0;                   // diagonal shift, or from partial sums:
     const double* c_parts = nullptr;  //   c = c_scale * sum(c_parts[z*c_zstride + 0..c_n))
     // PLAIN: symmetric diagonal scaling s = sqrt((c + 4 beta) / (w2 + 4 beta)),
@@ -185,6 +188,18 @@ size_t fft_scratch_bytes(int ny, int nx, int batch);
 void launch_fft_solve(int ny, int nx, int batch, const FftArgs& a, float2* scratch,
                       hipStream_t st);
 
+// Per-slice relaxation weight: a batch whose slices sit at different outer
+// iterations carries beta per slice on the device; kernels take their slice's
+// value (the threshold lambda/beta is formed the same way as on the host).
+template <typename A>
+__device__ __forceinline__ void slice_beta_thr(A& a, int z) {
+    if (a.beta_z) {
+        const double b = a.beta_z[z];
+        a.beta = (float)b;
+        a.thr = (float)(a.lam / b);
+    }
+}
+
 // ---- image-domain kernels of the solver ------------------------------------------
 struct Model {      // FP64 constants of the attenuation model (host)
     double C[2][2];     // C[k][i] = mu_i(E_k), 1/mm
@@ -199,6 +214,8 @@ struct ImgArgs {
     int ny, nx, nv, nd, batch;
     float eta2, xi2, beta2, thr;   // 2 (the residual carries eta), 2*xi, 2*beta, lambda/beta
     float beta;
+    const double* beta_z = nullptr;   // per-slice beta (overrides beta2, thr, beta)
+    double lam = 0.0;
 };
 int grad_nblocks(int ny, int nx);
 void launch_init_state(const Model& M, int ny, int nx, int batch, const float* muL,
@@ -208,8 +225,13 @@ void launch_init_state(const Model& M, int ny, int nx, int batch, const float* m
 void launch_grad(const Model& M, const ImgArgs& a, const PadLayout& P, const float2* f,
                  const float2* B, const float* rho, const float* t, float2* dpad,
                  double* partials, hipStream_t st);
+// also steps each slice's beta: beta_z[z] *= kappa_z[z] (when beta_z is given)
 void launch_update(const ImgArgs& a, const PadLayout& P, const RayTable& T, const double* alpha,
-                   const float2* dpad, float2* f, float2* S, const float2* zq, hipStream_t st);
+                   const float2* dpad, float2* f, float2* S, const float2* zq, double* beta_z,
+                   const double* kappa_z, hipStream_t st);
+// beta_z[z0 .. z0+n) = beta, kappa_z[...] = kappa
+void launch_set_beta(double* beta_z, double* kappa_z, int z0, int n, double beta, double kappa,
+                     hipStream_t st);
 void launch_finish(const Model& M, int ny, int nx, int batch, const float* rho, const float* t,
                    float rho_min, double t_min, float* Z, float* rho_out, hipStream_t st);
 void launch_split_f2(int n, int batch, const float2* f, float* a, float* b, hipStream_t st);
@@ -234,6 +256,8 @@ enum PcgPrec { PREC_JACOBI = 1, PREC_FFT = 2, PREC_MG = 3 };
 struct PcgArgs {
     int ny, nx, batch;
     float beta, thr;
+    const double* beta_z = nullptr;   // per-slice beta: then beta = beta_z[z], thr = lam / beta_z[z]
+    double lam = 0.0;
     double tol2;
     int prec;                // PcgPrec
     int nrz_used;            // entries of the <r, z> partial sums this preconditioner writes
@@ -277,8 +301,8 @@ hipError_t mg_init();                // once per process: LDS limit of the in-LD
 void launch_mg_setup(const MgPlan& P, const float* w2, float* mg, int batch, hipStream_t st);
 // z = V(r); <r, z> partials into dot[z*dot_zstride + 0..P.nrz)
 void launch_mg_vcycle(const MgPlan& P, const float* r, const float* w2, float* z, float* mg,
-                      int batch, float beta, const int* skip, size_t skip_zstride, double* dot,
-                      size_t dot_zstride, hipStream_t st);
+                      int batch, float beta, const double* beta_z, const int* skip,
+                      size_t skip_zstride, double* dot, size_t dot_zstride, hipStream_t st);
 void launch_pcg_mg_prec(const PcgArgs& a, int it, const MgPlan& P, float* mg, hipStream_t st);
 
 }  // namespace dect

@@ -167,6 +167,7 @@ __global__ __launch_bounds__(256) void k_fft_rows_fwd(FftPlan P, int ny, FftArgs
     float2* tw = sm2 + 2 * nx;
     float* rows = reinterpret_cast<float*>(sm2 + 3 * nx);   // 3 rows of the HT input
     const int i = blockIdx.x, z = blockIdx.y;
+    slice_beta_thr(a, z);
     if (skip_slice(a, z)) return;
     const size_t npix = (size_t)nx * ny;
     fill_twiddles(tw, nx);
@@ -228,6 +229,7 @@ __global__ __launch_bounds__(256) void k_fft_cols(FftPlan P, int nx, int cols, F
     float* lamy = reinterpret_cast<float*>(tw + ny);
     float* lamx = lamy + ny;
     const int c0 = blockIdx.x * cols, z = blockIdx.y;
+    slice_beta_thr(a, z);
     if (skip_slice(a, z)) return;
     const size_t npix = (size_t)nx * ny;
     {
@@ -273,6 +275,7 @@ __global__ __launch_bounds__(256) void k_fft_rows_inv(FftPlan P, int ny, FftArgs
     float2* B = sm2 + nx;
     float2* tw = sm2 + 2 * nx;
     const int i = blockIdx.x, z = blockIdx.y;
+    slice_beta_thr(a, z);
     if (skip_slice(a, z)) return;
     const size_t npix = (size_t)nx * ny;
     fill_twiddles(tw, nx);

@@ -103,6 +103,12 @@ __global__ __launch_bounds__(256) void k_grad(ImgArgs a, GradConst gc, PadLayout
     __shared__ double sh[4];
     const int nx = a.nx, ny = a.ny;
     const int z = blockIdx.z;
+    if (a.beta_z) {
+        const double b = a.beta_z[z];
+        a.beta = (float)b;
+        a.beta2 = (float)(2.0 * b);
+        a.thr = (float)(a.lam / b);
+    }
     const int i0 = blockIdx.y * 16, k0 = blockIdx.x * 16;
     const size_t npix = (size_t)nx * ny;
     const float2* fz = f + z * npix;
@@ -192,11 +198,13 @@ void launch_grad(const Model& M, const ImgArgs& a, const PadLayout& P, const flo
 // ---------------------------------------------------------------------------
 __global__ void k_update(int ny, int nx, PadLayout P, RayTable T, const double* __restrict__ alpha,
                          const float2* __restrict__ dpad, float2* __restrict__ f,
-                         float2* __restrict__ S, const float2* __restrict__ zq) {
+                         float2* __restrict__ S, const float2* __restrict__ zq,
+                         double* __restrict__ beta_z, const double* __restrict__ kappa_z) {
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int z = blockIdx.y;
     const size_t npix = (size_t)nx * ny;
     const float al = (float)alpha[z];
+    if (idx == 0 && beta_z) beta_z[z] *= kappa_z[z];   // continuation: the slice's next beta
     if (idx < npix) {
         const int i = (int)(idx / nx), k = (int)(idx % nx);
         const float2 d = dpad[z * P.pair + (size_t)i * P.ldN + k + kPad];
@@ -219,10 +227,25 @@ __global__ void k_update(int ny, int nx, PadLayout P, RayTable T, const double* 
 }
 
 void launch_update(const ImgArgs& a, const PadLayout& P, const RayTable& T, const double* alpha,
-                   const float2* dpad, float2* f, float2* S, const float2* zq, hipStream_t st) {
+                   const float2* dpad, float2* f, float2* S, const float2* zq, double* beta_z,
+                   const double* kappa_z, hipStream_t st) {
     const size_t n = (size_t)a.nx * a.ny + (size_t)T.nv_max * T.nd_max;
     hipLaunchKernelGGL(k_update, dim3((unsigned)((n + 255) / 256), a.batch), dim3(256), 0, st, a.ny,
-                       a.nx, P, T, alpha, dpad, f, S, zq);
+                       a.nx, P, T, alpha, dpad, f, S, zq, beta_z, kappa_z);
+}
+
+__global__ void k_set_beta(double* beta_z, double* kappa_z, int z0, int n, double beta, double kappa) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        beta_z[z0 + i] = beta;
+        kappa_z[z0 + i] = kappa;
+    }
+}
+
+void launch_set_beta(double* beta_z, double* kappa_z, int z0, int n, double beta, double kappa,
+                     hipStream_t st) {
+    hipLaunchKernelGGL(k_set_beta, dim3((n + 255) / 256), dim3(256), 0, st, beta_z, kappa_z, z0, n,
+                       beta, kappa);
 }
 
 // ---------------------------------------------------------------------------
@@ -328,6 +351,7 @@ __global__ __launch_bounds__(256) void k_pcg_init(PcgArgs a, ModelF M, const flo
     __shared__ double sh[4];
     const int nx = a.nx, ny = a.ny, npix = nx * ny;
     const int z = blockIdx.y;
+    slice_beta_thr(a, z);
     const size_t zo = (size_t)z * npix;
     double* P = a.parts + (size_t)z * a.L.zstride;
     const float* x = a.x + zo;
@@ -399,6 +423,7 @@ __global__ __launch_bounds__(256) void k_pcg_matvec(PcgArgs a, int it) {
     __shared__ double shn[16];
     const int nx = a.nx, ny = a.ny, npix = nx * ny;
     const int z = blockIdx.y;
+    slice_beta_thr(a, z);
     if (a.st[z].done) return;
     double* P = a.parts + (size_t)z * a.L.zstride;
     const int cur = it & 1, prev = cur ^ 1;
@@ -464,6 +489,7 @@ __global__ __launch_bounds__(256) void k_pcg_update(PcgArgs a, int it) {
     __shared__ double shn[8];
     const int npix = a.nx * a.ny;
     const int z = blockIdx.y;
+    slice_beta_thr(a, z);
     if (a.st[z].done) return;
     double* P = a.parts + (size_t)z * a.L.zstride;
     const int cur = it & 1, prev = cur ^ 1;
@@ -529,6 +555,8 @@ void launch_pcg_fft_prec(const PcgArgs& a, int it, float2* scratch, hipStream_t 
     fa.in = a.r;
     fa.out = a.z;
     fa.beta = a.beta;
+    fa.beta_z = a.beta_z;
+    fa.lam = a.lam;
     fa.c_parts = a.parts + a.L.init1;
     fa.c_n = a.L.nblk;
     fa.c_zstride = a.L.zstride;

@@ -148,7 +148,9 @@ struct MgLevel {
     const float* e;   // up: coarse correction
     size_t zs_b, zs_c, zs_xs, zs_out, zs_e;   // per-slice strides (floats)
     int ny, nx;
-    float beta;
+    float beta;                  // beta of this level, or with beta_z:
+    const double* beta_z;        //   beta_z[z] * scale (per-slice beta)
+    float scale;
 };
 
 constexpr int kTile = 16;
@@ -172,7 +174,7 @@ __global__ __launch_bounds__(256) void k_mg_down(MgLevel L, const int* skip, siz
     const int i0 = blockIdx.y * kTile, k0 = blockIdx.x * kTile;
     const float* b = L.b + (size_t)z * L.zs_b;
     const float* c = L.c + (size_t)z * L.zs_c;
-    const float be = L.beta;
+    const float be = L.beta_z ? (float)L.beta_z[z] * L.scale : L.beta;
     for (int t = threadIdx.x; t < kW0 * kW0; t += 256) {
         const int r = t / kW0, s = t % kW0;
         const size_t g = (size_t)wrap_near(i0 - kMgNu + r, L.ny) * L.nx +
@@ -220,7 +222,7 @@ __global__ __launch_bounds__(256) void k_mg_up(MgLevel L, const int* skip, size_
     const float* xs = L.xs + (size_t)z * L.zs_xs;
     const float* e = L.e + (size_t)z * L.zs_e;
     const int nxc = L.nx / 2;
-    const float be = L.beta;
+    const float be = L.beta_z ? (float)L.beta_z[z] * L.scale : L.beta;
     for (int t = threadIdx.x; t < kW0 * kW0; t += 256) {
         const int r = t / kW0, s = t % kW0;
         const int gi = wrap_near(i0 - kMgNu + r, L.ny), gk = wrap_near(k0 - kMgNu + s, L.nx);
@@ -280,7 +282,9 @@ struct MgPair {
     float* e0;
     size_t zs_b0, zs_c0, zs_xs0, zs_e0;
     int ny0, nx0;
-    float beta0;
+    float beta0;         // beta of level l, or with beta_z: beta_z[z] * scale
+    const double* beta_z;
+    float scale;
     float* b1;         // level l + 1 (level buffer): rhs (down writes), diagonal, saved iterate
     const float* c1;
     float* xs1;
@@ -299,7 +303,7 @@ __global__ __launch_bounds__(kPairThreads) void k_mg_down2(MgPair A, const int* 
     constexpr int H0 = 3 * kMgNu;
     const int ny0 = A.ny0, nx0 = A.nx0, ny1 = ny0 / 2, nx1 = nx0 / 2;
     const int i0 = blockIdx.y * kCore2, k0 = blockIdx.x * kCore2;
-    const float be0 = A.beta0, be1 = 0.25f * A.beta0;
+    const float be0 = A.beta_z ? (float)A.beta_z[z] * A.scale : A.beta0, be1 = 0.25f * be0;
     const float* b0 = A.b0 + (size_t)z * A.zs_b0;
     const float* c0 = A.c0 + (size_t)z * A.zs_c0;
     for (int t = threadIdx.x; t < kD0 * kD0; t += kPairThreads) {
@@ -383,7 +387,7 @@ __global__ __launch_bounds__(kPairThreads) void k_mg_up2(MgPair A, const int* sk
     if (mg_skip(skip, skip_zstride, z)) return;
     const int ny0 = A.ny0, nx0 = A.nx0, ny1 = ny0 / 2, nx1 = nx0 / 2, nx2 = nx1 / 2;
     const int i0 = blockIdx.y * kCore2, k0 = blockIdx.x * kCore2;
-    const float be0 = A.beta0, be1 = 0.25f * A.beta0;
+    const float be0 = A.beta_z ? (float)A.beta_z[z] * A.scale : A.beta0, be1 = 0.25f * be0;
     constexpr int H1 = kUh1 + kMgNu;   // level-(l+1) halo of the loaded region
     {
         const float* b1 = A.b1 + (size_t)z * A.zsm;
@@ -456,7 +460,9 @@ struct MgCoarse {
     const float* c;       // its diagonal
     float* e;             // its correction (output)
     size_t zs_b, zs_c, zs_e;
-    float beta;           // beta of the first in-LDS level
+    float beta;           // beta of the first in-LDS level, or with beta_z:
+    const double* beta_z; //   beta_z[z] * scale
+    float scale;
     int nlev;             // in-LDS levels (>= 1); the last is solved exactly
     int ny[kMgMaxLevels], nx[kMgMaxLevels];
     double* dot;          // optional <b, e> (when this is the finest level)
@@ -658,7 +664,7 @@ __global__ __launch_bounds__(kMgCoarseThreads) void k_mg_coarse(MgCoarse G, cons
     }
     __syncthreads();
     float beta[kMgMaxLevels];
-    beta[0] = G.beta;
+    beta[0] = G.beta_z ? (float)G.beta_z[z] * G.scale : G.beta;
     for (int l = 1; l < kMgMaxLevels; ++l) beta[l] = 0.25f * beta[l - 1];
     for (int l = 0; l + 1 < cut; ++l) lds_restrict(B, S.c(l), s_nx[l], S.c(l + 1), s_ny[l + 1], s_nx[l + 1]);
     for (int l = 0; l < cut && l + 1 < G.nlev; ++l) coarse_down(B, S, l, beta[l], t0);
@@ -703,12 +709,16 @@ void launch_mg_setup(const MgPlan& P, const float* w2, float* mg, int batch, hip
 }
 
 void launch_mg_vcycle(const MgPlan& P, const float* r, const float* w2, float* z, float* mg,
-                      int batch, float beta, const int* skip, size_t skip_zstride, double* dot,
-                      size_t dot_zstride, hipStream_t st) {
+                      int batch, float beta, const double* beta_z, const int* skip,
+                      size_t skip_zstride, double* dot, size_t dot_zstride, hipStream_t st) {
     const size_t n0 = (size_t)P.ny[0] * P.nx[0];
-    float bl[kMgMaxLevels];
+    float bl[kMgMaxLevels], sc[kMgMaxLevels];   // level beta; level scale 4^-l
     bl[0] = beta;
-    for (int l = 1; l < kMgMaxLevels; ++l) bl[l] = 0.25f * bl[l - 1];
+    sc[0] = 1.f;
+    for (int l = 1; l < kMgMaxLevels; ++l) {
+        bl[l] = 0.25f * bl[l - 1];
+        sc[l] = 0.25f * sc[l - 1];
+    }
     auto level = [&](int l) {
         MgLevel L;
         L.b = l == 0 ? r : mg + P.b[l];
@@ -724,6 +734,8 @@ void launch_mg_vcycle(const MgPlan& P, const float* r, const float* w2, float* z
         L.ny = P.ny[l];
         L.nx = P.nx[l];
         L.beta = bl[l];
+        L.beta_z = beta_z;
+        L.scale = sc[l];
         return L;
     };
     auto pair = [&](int l) {
@@ -739,6 +751,8 @@ void launch_mg_vcycle(const MgPlan& P, const float* r, const float* w2, float* z
         A.ny0 = P.ny[l];
         A.nx0 = P.nx[l];
         A.beta0 = bl[l];
+        A.beta_z = beta_z;
+        A.scale = sc[l];
         A.b1 = mg + P.b[l + 1];
         A.c1 = mg + P.c[l + 1];
         A.xs1 = mg + P.xs[l + 1];
@@ -769,6 +783,8 @@ void launch_mg_vcycle(const MgPlan& P, const float* r, const float* w2, float* z
     G.e = g0 == 0 ? z : mg + P.e[g0];
     G.zs_e = g0 == 0 ? n0 : P.zstride;
     G.beta = bl[g0];
+    G.beta_z = beta_z;
+    G.scale = sc[g0];
     G.nlev = P.ncoarse;
     for (int q = 0; q < kMgMaxLevels; ++q) {
         G.ny[q] = q < P.ncoarse ? P.ny[g0 + q] : 0;
@@ -803,7 +819,7 @@ void launch_pcg_mg_prec(const PcgArgs& a, int it, const MgPlan& P, float* mg, hi
     // z = V(r); <r, z> partials into the rz slot of iteration it (it = -1:
     // the initial residual, slot 1)
     const int slot = it < 0 ? 1 : (it & 1);
-    launch_mg_vcycle(P, a.r, a.w2, a.z, mg, a.batch, a.beta, &a.st[0].done,
+    launch_mg_vcycle(P, a.r, a.w2, a.z, mg, a.batch, a.beta, a.beta_z, &a.st[0].done,
                      sizeof(PcgState) / sizeof(int), a.parts + a.L.rz + (size_t)slot * a.L.nrz,
                      a.L.zstride, st);
 }

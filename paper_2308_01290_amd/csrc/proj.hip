@@ -361,7 +361,8 @@ __global__ __launch_bounds__(256) void k_project(const float2* __restrict__ pad,
             const double coup = block_sum_array<256>(ip + 1, a.img_nblocks, 3, sh);
             const double reg = block_sum_array<256>(ip + 2, a.img_nblocks, 3, sh);
             if (threadIdx.x == 0) {
-                const double den = a.w_data * den_data + a.w_coup * coup + a.w_reg * reg;
+                const double wr = a.beta_z ? 2.0 * a.beta_z[z] : a.w_reg;
+                const double den = a.w_data * den_data + a.w_coup * coup + wr * reg;
                 a.alpha[z] = den > 0.0 ? num / den : 0.0;
             }
         }
