@@ -47,7 +47,8 @@ enum {
     DECT_EWORKSPACE = -2,   /* caller workspace too small or misaligned     */
     DECT_ENOMEM = -3,       /* device allocation failed                     */
     DECT_EDEVICE = -4,      /* a HIP runtime call failed                    */
-    DECT_EUNSUPPORTED = -5  /* valid request this build does not implement  */
+    DECT_EUNSUPPORTED = -5, /* valid request this build does not implement  */
+    DECT_EBUSY = -6         /* no free slot (dect_engine_admit)             */
 };
 
 /* Fan-beam geometry (mm, radians).
@@ -253,6 +254,39 @@ int dect_solve(const float* sino_lo, const float* sino_hi, const dect_geometry* 
 int dect_solve_multi(const float* sino_lo, const float* sino_hi, const dect_geometry* geoms,
                      const dect_params* p, float* Z_out, float* rho_out, int32_t batch, void* ws,
                      size_t ws_bytes, hipStream_t stream);
+
+/* ---- continuous batching ------------------------------------------------
+ * An engine is a pool of `slots` slots on one image grid (n_x, n_y, pixel_mm)
+ * for serving single-slice requests as they arrive.  Each slot holds one
+ * request at its own outer iteration: its own fan geometry (at most
+ * max_views x max_det), data weight eta, iteration budget n_iter and beta
+ * schedule (beta0 -> beta_max over n_iter iterations; params->kappa must be
+ * 0).  A step advances every occupied slot by one iteration of Algorithm 1
+ * (sinogram form) in the same launches; a slot that completes its budget
+ * enqueues its Z and rho_e maps into the caller's buffers and becomes free.
+ * A request's result is the same as dect_solve of that slice alone (bit for
+ * bit).  All calls enqueue on the engine's stream; outputs are valid after
+ * the caller synchronises it. */
+typedef struct dect_engine dect_engine;
+size_t dect_engine_workspace_bytes(int32_t n_x, int32_t n_y, double pixel_mm, int32_t slots,
+                                   int32_t max_views, int32_t max_det, const dect_params* p);
+int dect_engine_create(int32_t n_x, int32_t n_y, double pixel_mm, int32_t slots,
+                       int32_t max_views, int32_t max_det, const dect_params* p, void* ws,
+                       size_t ws_bytes, hipStream_t stream, dect_engine** out);
+int dect_engine_destroy(dect_engine* e);
+/* Admit a request (sinograms [n_views][n_det], DEVICE, read during this call's
+ * enqueued work only; Z_out / rho_out [n_y][n_x] DEVICE, written when the
+ * request completes).  DECT_EBUSY when every slot is occupied; *slot_out
+ * (HOST, nullable) receives the slot. */
+int dect_engine_admit(dect_engine* e, const dect_geometry* g, const float* sino_lo,
+                      const float* sino_hi, int32_t n_iter, float* Z_out, float* rho_out,
+                      int32_t* slot_out);
+/* One outer iteration of every occupied slot. */
+int dect_engine_step(dect_engine* e);
+/* Occupied and free slots (HOST pointers, nullable). */
+int dect_engine_status(const dect_engine* e, int32_t* active, int32_t* free_slots);
+/* Slots completed since the last call, oldest first (HOST array of cap). */
+int dect_engine_completed(dect_engine* e, int32_t* slots, int32_t cap, int32_t* n);
 
 const char* dect_last_error(void);
 

@@ -423,7 +423,9 @@ struct BatchGeo {
     int nv_max = 0, nd_max = 0;
 };
 
-static int make_batch(const dect_geometry* gin, int batch, BatchGeo* B) {
+// dedupe = false: every slice gets a table of its own (slots that change
+// geometry over time)
+static int make_batch(const dect_geometry* gin, int batch, BatchGeo* B, bool dedupe = true) {
     if (!gin) return fail(DECT_EINVAL, "geometry is NULL");
     if (batch < 1) return fail(DECT_EINVAL, "batch must be >= 1");
     B->g.resize(batch);
@@ -438,8 +440,9 @@ static int make_batch(const dect_geometry* gin, int batch, BatchGeo* B) {
                         z, a.nx, a.ny, a.dx, b.nx, b.ny, b.dx);
         if (a.nd > 4096) return fail(DECT_EINVAL, "slice %d: n_det > 4096 is not supported by the FBP start", z);
         int u = -1;
-        for (size_t d = 0; d < B->distinct.size(); ++d)
-            if (same_geom(B->distinct[d], a)) u = (int)d;
+        if (dedupe)
+            for (size_t d = 0; d < B->distinct.size(); ++d)
+                if (same_geom(B->distinct[d], a)) u = (int)d;
         if (u < 0) {
             u = (int)B->distinct.size();
             B->distinct.push_back(a);
@@ -474,6 +477,7 @@ struct dect_solver {
     float *rho, *t, *muL, *muH, *fbpq;
     double *part_img, *part_proj, *alpha;
     double *beta_d, *kappa_d;        // per-slice beta and its growth rate (device)
+    int* active_d = nullptr;         // per-slice activity (engine slots); null: all active
     unsigned* cnt_proj;
     PcgBufs pcg;
     int k;
@@ -755,12 +759,13 @@ size_t dect_solve_workspace_bytes(const dect_geometry* gin, const dect_params* p
     return dect_solve_workspace_bytes_multi(gs.data(), p, batch);
 }
 
-int dect_solver_create_multi(const dect_geometry* geoms, const dect_params* p, int32_t batch,
-                             void* ws, size_t ws_bytes, hipStream_t st, dect_solver** out) {
+static int solver_create(const dect_geometry* geoms, const dect_params* p, int32_t batch,
+                         void* ws, size_t ws_bytes, hipStream_t st, dect_solver** out,
+                         bool dedupe) {
     if (!out) return fail(DECT_EINVAL, "out is NULL");
     *out = nullptr;
     BatchGeo B;
-    if (int rc = make_batch(geoms, batch, &B)) return rc;
+    if (int rc = make_batch(geoms, batch, &B, dedupe)) return rc;
     const Geom& g = B.g[0];
     if (int rc = check_params(p)) return rc;
     if (!fft_size_ok(g.nx) || !fft_size_ok(g.ny))
@@ -831,6 +836,11 @@ int dect_solver_create_multi(const dect_geometry* geoms, const dect_params* p, i
     *out = s;
     DECT_HIP(hipGetLastError());
     return DECT_OK;
+}
+
+int dect_solver_create_multi(const dect_geometry* geoms, const dect_params* p, int32_t batch,
+                             void* ws, size_t ws_bytes, hipStream_t st, dect_solver** out) {
+    return solver_create(geoms, p, batch, ws, ws_bytes, st, out, true);
 }
 
 int dect_solver_create(const dect_geometry* gin, const dect_params* p, int32_t batch, void* ws,
@@ -979,6 +989,7 @@ static int one_iteration(dect_solver* s) {
     pc.tol2 = R.p.t_tol * R.p.t_tol;
     pc.beta_z = s->beta_d;
     pc.lam = R.p.lambda;
+    pc.active = s->active_d;
     if (int rc = choose_prec(R.p.t_precond, s->pcg, beta, &pc)) return rc;
     launch_pcg_init_model(s->M, pc, s->f, s->st);
     int iters = 0;
@@ -1082,3 +1093,229 @@ int dect_solve(const float* lo, const float* hi, const dect_geometry* g, const d
 const char* dect_last_error(void) { return g_last_error.c_str(); }
 
 }  // extern "C"
+
+// ===========================================================================
+// Continuous batching: a pool of slots on one image grid.  Each slot holds one
+// request at its own outer iteration (own geometry, beta, iteration budget);
+// a step advances every active slot by one iteration in the same launches, and
+// a slot that reaches its budget writes its maps and frees itself.
+// ===========================================================================
+struct dect_engine {
+    dect_solver* s = nullptr;
+    int slots = 0, cap_views = 0, cap_det = 0;
+    size_t cap_rays = 0;
+    dect_params p;
+    std::vector<int> k, K;
+    std::vector<char> busy;
+    std::vector<float*> Zout, Rout;
+    std::vector<int> done;
+    DevAlloc act;
+};
+
+static dect_geometry capacity_geometry(int32_t n_x, int32_t n_y, double pixel_mm, int32_t views,
+                                       int32_t det) {
+    dect_geometry g{};
+    g.n_x = n_x;
+    g.n_y = n_y;
+    g.pixel_mm = pixel_mm;
+    g.n_views = views;
+    g.arc_rad = 6.283185307179586;   // full circle
+    g.n_det = det;
+    g.sid_mm = 1000.0;
+    g.sdd_mm = 1500.0;
+    // keep the placeholder geometry valid for any image: source outside the
+    // image's circumcircle with room to the detector
+    const double R = 0.5 * pixel_mm * std::hypot((double)n_x, (double)n_y);
+    if (R >= 0.9 * g.sid_mm) {
+        g.sid_mm = 2.0 * R;
+        g.sdd_mm = 4.0 * R;
+    }
+    return g;
+}
+
+size_t dect_engine_workspace_bytes(int32_t n_x, int32_t n_y, double pixel_mm, int32_t slots,
+                                   int32_t max_views, int32_t max_det, const dect_params* p) {
+    if (slots < 1 || max_views < 1 || max_det < 1 || !p) return 0;
+    std::vector<dect_geometry> gs((size_t)slots, capacity_geometry(n_x, n_y, pixel_mm, max_views, max_det));
+    BatchGeo B;
+    if (make_batch(gs.data(), slots, &B, false)) return 0;
+    return solver_layout(B, nullptr, nullptr);
+}
+
+int dect_engine_create(int32_t n_x, int32_t n_y, double pixel_mm, int32_t slots, int32_t max_views,
+                       int32_t max_det, const dect_params* p, void* ws, size_t ws_bytes,
+                       hipStream_t st, dect_engine** out) {
+    if (!out) return fail(DECT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (slots < 1 || max_views < 1 || max_det < 1)
+        return fail(DECT_EINVAL, "need slots, max_views, max_det >= 1");
+    if (!p) return fail(DECT_EINVAL, "params is NULL");
+    if (p->kappa > 0)
+        return fail(DECT_EINVAL, "engine: kappa follows each request's iteration budget (set 0)");
+    std::vector<dect_geometry> gs((size_t)slots, capacity_geometry(n_x, n_y, pixel_mm, max_views, max_det));
+    dect_engine* e = new dect_engine();
+    if (int rc = solver_create(gs.data(), p, slots, ws, ws_bytes, st, &e->s, false)) {
+        delete e;
+        return rc;
+    }
+    e->slots = slots;
+    e->cap_views = max_views;
+    e->cap_det = max_det;
+    e->cap_rays = (size_t)max_views * max_det;
+    e->p = *p;
+    e->k.assign(slots, 0);
+    e->K.assign(slots, 0);
+    e->busy.assign(slots, 0);
+    e->Zout.assign(slots, nullptr);
+    e->Rout.assign(slots, nullptr);
+    dect_solver* s = e->s;
+    if (int rc = dev_alloc(&e->act, sizeof(int) * slots, st)) {
+        dect_solver_destroy(s);
+        delete e;
+        return rc;
+    }
+    s->active_d = static_cast<int*>(e->act.p);
+    // every slot starts empty: no views, inactive, zero state
+    SliceDesc none = s->hdesc[0];
+    none.nv = 0;
+    none.nd = 0;
+    const size_t npix = (size_t)s->g.nx * s->g.ny;
+    hipError_t he = hipSuccess;
+    he = he != hipSuccess ? he : hipMemsetAsync(s->f, 0, sizeof(float2) * npix * slots, st);
+    he = he != hipSuccess ? he : hipMemsetAsync(s->rho, 0, sizeof(float) * npix * slots, st);
+    he = he != hipSuccess ? he : hipMemsetAsync(s->t, 0, sizeof(float) * npix * slots, st);
+    if (he != hipSuccess) {
+        dev_free(&e->act);
+        dect_solver_destroy(s);
+        delete e;
+        return fail(DECT_EDEVICE, "engine set-up failed: %s", hipGetErrorString(he));
+    }
+    for (int z = 0; z < slots; ++z) {
+        launch_set_desc(const_cast<SliceDesc*>(s->tab.desc), z, none, st);
+        launch_set_int(s->active_d + z, 0, st);
+    }
+    launch_set_beta(s->beta_d, s->kappa_d, 0, slots, s->rp.beta0, 1.0, st);
+    *out = e;
+    DECT_HIP(hipGetLastError());
+    return DECT_OK;
+}
+
+int dect_engine_destroy(dect_engine* e) {
+    if (!e) return DECT_OK;
+    if (e->s) (void)hipStreamSynchronize(e->s->st);
+    dev_free(&e->act);
+    dect_solver_destroy(e->s);
+    delete e;
+    return DECT_OK;
+}
+
+int dect_engine_admit(dect_engine* e, const dect_geometry* gin, const float* lo, const float* hi,
+                      int32_t n_iter, float* Z, float* rho_e, int32_t* slot_out) {
+    if (!e || !gin || !lo || !hi || (!Z && !rho_e) || n_iter < 1)
+        return fail(DECT_EINVAL, "dect_engine_admit: bad arguments");
+    dect_solver* s = e->s;
+    Geom g;
+    if (int rc = resolve_geometry(gin, &g)) return rc;
+    if (g.nx != s->g.nx || g.ny != s->g.ny || g.dx != s->g.dx)
+        return fail(DECT_EINVAL, "dect_engine_admit: image %dx%d at %g mm, engine holds %dx%d at %g mm",
+                    g.nx, g.ny, g.dx, s->g.nx, s->g.ny, s->g.dx);
+    if (g.nv > e->cap_views || g.nd > e->cap_det)
+        return fail(DECT_EINVAL, "dect_engine_admit: %d views x %d bins exceed the slot capacity %d x %d",
+                    g.nv, g.nd, e->cap_views, e->cap_det);
+    int z = -1;
+    for (int q = 0; q < e->slots && z < 0; ++q)
+        if (!e->busy[q]) z = q;
+    if (z < 0) return fail(DECT_EBUSY, "dect_engine_admit: all %d slots busy", e->slots);
+    hipStream_t st = s->st;
+    const size_t npix = (size_t)g.nx * g.ny;
+    const long long s0 = (long long)z * (long long)e->cap_rays;
+    // this slot's ray table and descriptor
+    RayTable t = s->tab;
+    t.fix += (size_t)z * e->cap_rays;
+    t.flt += (size_t)z * e->cap_rays;
+    t.span += (size_t)z * e->cap_rays;
+    t.view += (size_t)z * e->cap_views;
+    launch_build_ray_table(g, t, st);
+    const SliceDesc d = make_slice_desc(g, (int)(z * e->cap_rays), z * e->cap_views, s0, eta_of(&e->p, g));
+    launch_set_desc(const_cast<SliceDesc*>(s->tab.desc), z, d, st);
+    // FBP start and closed forms for this slot only
+    float* q = reinterpret_cast<float*>(s->zq + s0);
+    launch_fbp(g, lo, 1, q, s->muL + z * npix, st);
+    launch_fbp(g, hi, 1, q, s->muH + z * npix, st);
+    launch_init_state(s->M, g.ny, g.nx, 1, s->muL + z * npix, s->muH + z * npix,
+                      (float)s->rp.p.rho_min, s->f + z * npix, s->rho + z * npix, s->t + z * npix, st);
+    // residual sinograms of the start
+    const PadLayout P = pad_layout(g);
+    launch_pack_f2(g, s->f + z * npix, 1, s->dpad + z * P.pair, st);
+    RayTable tz = s->tab;
+    tz.desc = s->tab.desc + z;
+    tz.desc_stride = 0;
+    tz.sino_zstride = 0;
+    tz.nv_max = g.nv;
+    tz.nd_max = g.nd;
+    ProjArgs a;
+    a.p_lo = lo;
+    a.p_hi = hi;
+    a.p_base = s0;
+    a.res = s->S;
+    a.c00 = (float)s->M.C[0][0];
+    a.c01 = (float)s->M.C[0][1];
+    a.c10 = (float)s->M.C[1][0];
+    a.c11 = (float)s->M.C[1][1];
+    launch_project(g, tz, s->dpad + z * P.pair, 1, PROJ_RESID, a, st);
+    // continuation schedule of this request
+    const double kappa = std::pow(e->p.beta_max / s->rp.beta0, 1.0 / n_iter);
+    launch_set_beta(s->beta_d, s->kappa_d, z, 1, s->rp.beta0, kappa, st);
+    launch_set_int(s->active_d + z, 1, st);
+    DECT_HIP(hipGetLastError());
+    e->busy[z] = 1;
+    e->k[z] = 0;
+    e->K[z] = n_iter;
+    e->Zout[z] = Z;
+    e->Rout[z] = rho_e;
+    if (slot_out) *slot_out = z;
+    return DECT_OK;
+}
+
+int dect_engine_step(dect_engine* e) {
+    if (!e) return fail(DECT_EINVAL, "engine is NULL");
+    bool any = false;
+    for (int z = 0; z < e->slots; ++z) any = any || e->busy[z];
+    if (!any) return DECT_OK;
+    dect_solver* s = e->s;
+    if (int rc = one_iteration(s)) return rc;
+    const size_t npix = (size_t)s->g.nx * s->g.ny;
+    SliceDesc none = s->hdesc[0];
+    none.nv = 0;
+    none.nd = 0;
+    for (int z = 0; z < e->slots; ++z) {
+        if (!e->busy[z]) continue;
+        if (++e->k[z] < e->K[z]) continue;
+        launch_finish(s->M, s->g.ny, s->g.nx, 1, s->rho + z * npix, s->t + z * npix,
+                      (float)s->rp.p.rho_min, s->rp.p.t_min, e->Zout[z], e->Rout[z], s->st);
+        launch_set_desc(const_cast<SliceDesc*>(s->tab.desc), z, none, s->st);
+        launch_set_int(s->active_d + z, 0, s->st);
+        e->busy[z] = 0;
+        e->done.push_back(z);
+    }
+    DECT_HIP(hipGetLastError());
+    return DECT_OK;
+}
+
+int dect_engine_status(const dect_engine* e, int32_t* active, int32_t* free_slots) {
+    if (!e) return fail(DECT_EINVAL, "engine is NULL");
+    int n = 0;
+    for (int z = 0; z < e->slots; ++z) n += e->busy[z] ? 1 : 0;
+    if (active) *active = n;
+    if (free_slots) *free_slots = e->slots - n;
+    return DECT_OK;
+}
+
+int dect_engine_completed(dect_engine* e, int32_t* slots, int32_t cap, int32_t* n) {
+    if (!e || !n || (cap > 0 && !slots)) return fail(DECT_EINVAL, "dect_engine_completed: bad arguments");
+    const int m = std::min<int>(cap, (int)e->done.size());
+    for (int i = 0; i < m; ++i) slots[i] = e->done[i];
+    e->done.erase(e->done.begin(), e->done.begin() + m);
+    *n = m;
+    return DECT_OK;
+}

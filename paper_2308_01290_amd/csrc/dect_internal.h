@@ -68,6 +68,8 @@ struct RayTable {
     int nv_max = 0, nd_max = 0;   // largest slice (launch grid)
 };
 SliceDesc make_slice_desc(const Geom& g, int ray0, int view0, long long sino0, double eta);
+void launch_set_desc(SliceDesc* desc, int z, const SliceDesc& d, hipStream_t st);
+void launch_set_int(int* p, int value, hipStream_t st);
 size_t ray_table_bytes(const Geom& g);
 void launch_build_ray_table(const Geom& g, RayTable t, hipStream_t st);
 
@@ -120,6 +122,7 @@ struct ProjArgs {
     // (eta of the slice's descriptor: the data weight travels with the residual)
     const float* p_lo = nullptr;
     const float* p_hi = nullptr;
+    long long p_base = 0;   // p_lo / p_hi hold the slice's sinograms from element desc.sino0 - p_base
     float2* res = nullptr;
     float c00 = 0, c01 = 0, c10 = 0, c11 = 0;   // C[k][i] = mu_i(E_k)
     double* partials = nullptr;                  // [z][nblocks]
@@ -258,6 +261,7 @@ struct PcgArgs {
     float beta, thr;
     const double* beta_z = nullptr;   // per-slice beta: then beta = beta_z[z], thr = lam / beta_z[z]
     double lam = 0.0;
+    const int* active = nullptr;      // slices with active[z] == 0 start done (no PCG work)
     double tol2;
     int prec;                // PcgPrec
     int nrz_used;            // entries of the <r, z> partial sums this preconditioner writes

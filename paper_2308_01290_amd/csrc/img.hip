@@ -398,7 +398,7 @@ __global__ __launch_bounds__(256) void k_pcg_init(PcgArgs a, ModelF M, const flo
         P[a.L.rr + a.L.nblk + blockIdx.x] = s_rr;       // parity slot 1: "previous" rr
         if (a.prec == PREC_JACOBI) P[a.L.rz + a.L.nrz + blockIdx.x] = s_rz;
         if (blockIdx.x == 0) {
-            a.st[z].done = 0;
+            a.st[z].done = (a.active && !a.active[z]) ? 1 : 0;
             a.st[z].iters = 0;
         }
     }

@@ -127,6 +127,17 @@ SliceDesc make_slice_desc(const Geom& g, int ray0, int view0, long long sino0, d
     return d;
 }
 
+__global__ void k_set_desc(SliceDesc* desc, int z, SliceDesc d) { desc[z] = d; }
+__global__ void k_set_int(int* p, int value) { *p = value; }
+
+void launch_set_desc(SliceDesc* desc, int z, const SliceDesc& d, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_desc, dim3(1), dim3(1), 0, st, desc, z, d);
+}
+
+void launch_set_int(int* p, int value, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, p, value);
+}
+
 void launch_build_ray_table(const Geom& g, RayTable t, hipStream_t st) {
     dim3 grid((g.nd + 255) / 256, g.nv);
     hipLaunchKernelGGL(k_build_ray_table, grid, dim3(256), 0, st, g, t.fix, t.flt, t.span, t.view);
@@ -330,8 +341,8 @@ __global__ __launch_bounds__(256) void k_project(const float2* __restrict__ pad,
         }
     } else if constexpr (MODE == PROJ_RESID) {
         if (valid) {
-            const double rl = (double)a.c00 * Y1 + (double)a.c01 * Y2 - (double)a.p_lo[s0 + r];
-            const double rh = (double)a.c10 * Y1 + (double)a.c11 * Y2 - (double)a.p_hi[s0 + r];
+            const double rl = (double)a.c00 * Y1 + (double)a.c01 * Y2 - (double)a.p_lo[s0 - a.p_base + r];
+            const double rh = (double)a.c10 * Y1 + (double)a.c11 * Y2 - (double)a.p_hi[s0 - a.p_base + r];
             a.res[s0 + r] = make_float2((float)(D.eta * ((double)a.c00 * rl + (double)a.c10 * rh)),
                                         (float)(D.eta * ((double)a.c01 * rl + (double)a.c11 * rh)));
         }

@@ -48,8 +48,12 @@ EXPORTS = [
     "dect_solver_set_state", "dect_solver_iterate", "dect_solver_get_state", "dect_solver_finish",
     "dect_solver_stats", "dect_solver_enable_timing", "dect_solver_timing", "dect_solve",
     "dect_solve_workspace_bytes_multi", "dect_solver_create_multi", "dect_solve_multi",
+    "dect_engine_workspace_bytes", "dect_engine_create", "dect_engine_destroy", "dect_engine_admit",
+    "dect_engine_step", "dect_engine_status", "dect_engine_completed",
     "dect_last_error",
 ]
+
+DECT_EBUSY = -6
 
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:
@@ -90,6 +94,15 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.dect_solve_workspace_bytes_multi.restype = C.c_size_t
     L.dect_solver_create_multi.argtypes = [G, Pp, C.c_int32, vp, C.c_size_t, vp, P(vp)]
     L.dect_solve_multi.argtypes = [vp, vp, G, Pp, vp, vp, C.c_int32, vp, C.c_size_t, vp]
+    i32 = C.c_int32
+    L.dect_engine_workspace_bytes.argtypes = [i32, i32, C.c_double, i32, i32, i32, Pp]
+    L.dect_engine_workspace_bytes.restype = C.c_size_t
+    L.dect_engine_create.argtypes = [i32, i32, C.c_double, i32, i32, i32, Pp, vp, C.c_size_t, vp, P(vp)]
+    L.dect_engine_destroy.argtypes = [vp]
+    L.dect_engine_admit.argtypes = [vp, G, vp, vp, i32, vp, vp, P(i32)]
+    L.dect_engine_step.argtypes = [vp]
+    L.dect_engine_status.argtypes = [vp, P(i32), P(i32)]
+    L.dect_engine_completed.argtypes = [vp, P(i32), i32, P(i32)]
     L.dect_last_error.argtypes = []
     L.dect_last_error.restype = C.c_char_p
     return L
@@ -438,3 +451,72 @@ def solve_multi(sino_lo, sino_hi, geoms, params=None, stream=None):
     _check(lib().dect_solve_multi(_ptr(sino_lo), _ptr(sino_hi), arr, C.byref(p), _ptr(Z), _ptr(R), b,
                                   None, 0, C.c_void_p(_stream(stream))), "dect_solve_multi")
     return Z, R
+
+
+class Engine:
+    """Continuous batching: a pool of slots on one image grid, each holding one
+    request at its own outer iteration (see include/dect.h)."""
+
+    def __init__(self, n_x, n_y, pixel_mm, slots, max_views, max_det, params=None, device="cuda",
+                 stream=None):
+        self.params = params if params is not None else default_params()
+        self.n_x, self.n_y, self.slots = int(n_x), int(n_y), int(slots)
+        self.device = device
+        h = C.c_void_p()
+        _check(lib().dect_engine_create(self.n_x, self.n_y, float(pixel_mm), self.slots, int(max_views),
+                                        int(max_det), C.byref(self.params), None, 0,
+                                        C.c_void_p(_stream(stream)), C.byref(h)), "dect_engine_create")
+        self._h = h
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dect_engine_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def admit(self, geom, sino_lo, sino_hi, n_iter, Z=None, rho=None):
+        """Slot of the admitted request, or None when every slot is busy.
+        Z / rho: [n_y, n_x] float32 device outputs (allocated when omitted)."""
+        torch = _torch()
+        g = Geometry.of(geom)
+        _dev_f32(sino_lo, (g.n_views, g.n_det), "sino_lo")
+        _dev_f32(sino_hi, (g.n_views, g.n_det), "sino_hi")
+        if Z is None:
+            Z = torch.empty((self.n_y, self.n_x), device=self.device, dtype=torch.float32)
+        if rho is None:
+            rho = torch.empty((self.n_y, self.n_x), device=self.device, dtype=torch.float32)
+        slot = C.c_int32(-1)
+        gc = g.c()
+        rc = lib().dect_engine_admit(self._h, C.byref(gc), _ptr(sino_lo), _ptr(sino_hi), int(n_iter),
+                                     _ptr(Z), _ptr(rho), C.byref(slot))
+        if rc == DECT_EBUSY:
+            return None
+        _check(rc, "dect_engine_admit")
+        self._keep[slot.value] = (sino_lo, sino_hi, Z, rho)
+        return slot.value
+
+    def step(self):
+        _check(lib().dect_engine_step(self._h), "dect_engine_step")
+
+    def status(self):
+        a, f = C.c_int32(), C.c_int32()
+        _check(lib().dect_engine_status(self._h, C.byref(a), C.byref(f)), "dect_engine_status")
+        return a.value, f.value
+
+    def completed(self):
+        """[(slot, Z, rho)] of requests completed since the last call (their maps
+        are enqueued on the stream)."""
+        buf = (C.c_int32 * max(self.slots, 1))()
+        n = C.c_int32()
+        _check(lib().dect_engine_completed(self._h, buf, self.slots, C.byref(n)), "dect_engine_completed")
+        out = []
+        for i in range(n.value):
+            lo, hi, Z, rho = self._keep.pop(buf[i])
+            out.append((buf[i], Z, rho))
+        return out

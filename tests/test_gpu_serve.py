@@ -1,0 +1,67 @@
+"""Continuous batching: requests of different geometry and iteration budget
+enter and leave a slot pool while others are mid-solve; each result must equal
+the same slice solved alone."""
+import numpy as np
+import pytest
+
+from oracle.physics import Physics
+from paper_2308_01290_amd import dect
+from paper_2308_01290_amd import phantoms as P
+from tests.gpu_util import cuda, host
+
+pytestmark = pytest.mark.gpu
+
+
+def requests():
+    phys = Physics()
+    specs = [(120, 200, 0.0, 3), (180, 256, 0.3, 5), (150, 300, -0.2, 4), (240, 220, 0.1, 2),
+             (200, 280, 0.0, 6)]
+    out = []
+    for i, (v, d, off, K) in enumerate(specs):
+        g = P.FanGeometry(n_x=128, n_y=128, pixel_mm=1.0, n_views=v, n_det=d, sid_mm=1000.0,
+                          sdd_mm=1500.0, det_offset_mm=off, angle0_rad=0.1 * i).resolved()
+        ph = P.phantom_disk_inserts(seed=40 + i)
+        pL, pH = P.analytic_sinograms(ph, g, phys.mu_pair)
+        out.append((g, P.poisson_log(pL, 1e5, 50 + i).astype(np.float32),
+                    P.poisson_log(pH, 1e5, 60 + i).astype(np.float32), K))
+    return out
+
+
+def test_requests_in_the_mix_equal_each_alone():
+    reqs = requests()
+    eng = dect.Engine(128, 128, 1.0, slots=3, max_views=240, max_det=300)
+    pending = list(range(len(reqs)))
+    slot_of, results = {}, {}
+    steps = 0
+    while len(results) < len(reqs):
+        # admit while slots are free (later requests join slots mid-solve of others)
+        while pending and (steps > 0 or len(slot_of) < 2):
+            i = pending[0]
+            g, pL, pH, K = reqs[i]
+            s = eng.admit(g, cuda(pL), cuda(pH), K)
+            if s is None:
+                break
+            slot_of[s] = i
+            pending.pop(0)
+        eng.step()
+        steps += 1
+        for s, Z, R in eng.completed():
+            results[slot_of.pop(s)] = (host(Z), host(R))
+        assert steps < 100
+    for i, (g, pL, pH, K) in enumerate(reqs):
+        Z1, R1 = (host(x)[0] for x in dect.solve(cuda(pL[None]), cuda(pH[None]), g,
+                                                  dect.default_params(n_iter=K)))
+        assert np.array_equal(results[i][0], Z1) and np.array_equal(results[i][1], R1), i
+
+
+def test_engine_rejects_what_it_cannot_hold():
+    eng = dect.Engine(128, 128, 1.0, slots=1, max_views=100, max_det=128)
+    g, pL, pH, K = requests()[0]            # 120 views > 100
+    with pytest.raises(dect.DectError):
+        eng.admit(g, cuda(pL), cuda(pH), K)
+    small = P.FanGeometry(n_x=128, n_y=128, pixel_mm=1.0, n_views=90, n_det=128, sid_mm=1000.0,
+                          sdd_mm=1500.0).resolved()
+    z = np.zeros((90, 128), np.float32)
+    assert eng.admit(small, cuda(z), cuda(z), 2) == 0
+    assert eng.admit(small, cuda(z), cuda(z), 2) is None   # the only slot is busy
+    assert eng.status() == (1, 0)

@@ -108,6 +108,14 @@ def test_entry_points_reject_bad_arguments_before_enqueueing():
     assert L.dect_solver_create_multi(arr, C.byref(p), 2, None, 0, None, C.byref(h)) == -1
     assert b"differs from slice 0" in L.dect_last_error()
     assert L.dect_solve_workspace_bytes_multi(arr, C.byref(p), 2) == 0
+    # engine: kappa follows each request's budget; sizes checked on the host
+    eh = C.c_void_p()
+    p = dect.default_params(kappa=1.5)
+    assert L.dect_engine_create(128, 128, 1.0, 4, 180, 256, C.byref(p), None, 0, None, C.byref(eh)) == -1
+    p = dect.default_params()
+    assert L.dect_engine_create(128, 128, 1.0, 0, 180, 256, C.byref(p), None, 0, None, C.byref(eh)) == -1
+    assert L.dect_engine_workspace_bytes(128, 128, 1.0, 4, 180, 256, C.byref(p)) > \
+        L.dect_engine_workspace_bytes(128, 128, 1.0, 2, 180, 256, C.byref(p)) > 0
     # l0 step: unsupported FFT size, NULL input
     assert L.dect_l0_step(None, None, None, None, None, 16, 16, 1, 0.1, 1.0, 1e-6, 10, None, 0, None) == -1
     assert L.dect_l0_step(C.c_void_p(1), None, C.c_void_p(1), None, None, 10, 16, 1, 0.1, 1.0, 1e-6,
