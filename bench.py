@@ -6,6 +6,11 @@ With --workload uneven64 it times instead the batch of 64 uneven slices
 one image size run as one batch (one launch per kernel and iteration for
 all of them), against the same 64 slices solved one at a time.
 
+With --workload serve it replays Poisson arrival streams of single-slice
+requests (image 256-768, 360-1152 views, 20-80 iterations) through the
+continuous-batching server and reports latency percentiles and slices/s per
+arrival rate.
+
 Workload: 512x512 image at 0.8 mm, 720 views over 360 deg, 736 detector bins,
 SID 1000 mm, SDD 1500 mm, dual-energy sinograms of an elliptical water body
 with 40 bone / soft-tissue / lung inserts, Poisson noise 5e4 / 1e5, 50 outer
@@ -180,6 +185,86 @@ def bench_uneven(args):
     print(json.dumps(out), flush=True)
 
 
+SERVE_SIZES = (256, 384, 512, 768)
+
+
+def _serve_slice(args):
+    """One pool slice for the serving stream: image n at 0.8 mm, views and bins
+    drawn from the seed, the body phantom scaled to the field of view."""
+    n, seed = args
+    from paper_2308_01290_amd import dect
+    from paper_2308_01290_amd import phantoms as P
+    params = dect.default_params()
+    rng = np.random.Generator(np.random.PCG64(seed))
+    g = P.FanGeometry(n_x=n, n_y=n, pixel_mm=0.8, n_views=int(rng.integers(360, 1153)),
+                      n_det=int(rng.integers(512, 1025)), sid_mm=1000.0, sdd_mm=1500.0).resolved()
+    s = n / 512.0
+    ph = P.phantom_body_inserts(seed, body_ax=(180.0 * s, 140.0 * s), semi=(3.0 * s, 18.0 * s))
+    pL, pH = P.analytic_sinograms(ph, g, lambda Z, R: dect.attenuation(params, Z, R))
+    return (g, P.poisson_log(pL, 5e4, 2 * seed + 1).astype(np.float32),
+            P.poisson_log(pH, 1e5, 2 * seed + 2).astype(np.float32))
+
+
+def bench_serve(args):
+    """Poisson streams of single-slice requests through the continuous-batching
+    server; per rate: latency p50/p99 (arrival to maps ready) and slices/s."""
+    import multiprocessing as mp
+    import torch
+    from paper_2308_01290_amd import dect
+    from paper_2308_01290_amd.serve import EngineSpec, Request, Server
+    per_size = 4
+    jobs = [(n, 5000 + 10 * n + i) for n in SERVE_SIZES for i in range(per_size)]
+    with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
+        data = pool.map(_serve_slice, jobs)
+    dev = torch.device("cuda:0")
+    pool_dev = [(g, torch.as_tensor(pL, device=dev), torch.as_tensor(pH, device=dev))
+                for g, pL, pH in data]
+    params = dect.default_params()
+    specs = [EngineSpec(n, 0.8, 16, 1152, 1024) for n in SERVE_SIZES]
+    rng = np.random.Generator(np.random.PCG64(20230801))
+    results = []
+    checked = 0
+    identical = True
+    for rate in [float(r) for r in args.rates.split(",")]:
+        server = Server(specs, params)
+        t = 0.0
+        reqs = []
+        for i in range(args.requests):
+            t += rng.exponential(1.0 / rate)
+            g, lo, hi = pool_dev[int(rng.integers(len(pool_dev)))]
+            reqs.append(Request(g, lo, hi, int(rng.integers(20, 81)), arrival=t, tag=i))
+        t0 = time.perf_counter()
+        server.run(reqs)
+        wall = time.perf_counter() - t0
+        lat = np.array([r.latency for r in reqs])
+        results.append({"rate_req_s": rate, "requests": len(reqs),
+                        "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+                        "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                        "mean_ms": 1e3 * float(lat.mean()),
+                        "slices_per_s": len(reqs) / wall,
+                        "hbm_gb": server.hbm_bytes / 1e9})
+        # a served request equals the same slice solved alone
+        for r in reqs[:2]:
+            Z1, R1 = dect.solve(r.sino_lo[None], r.sino_hi[None], r.geom, dect.default_params(n_iter=r.n_iter))
+            identical = identical and bool(torch.equal(Z1[0], r.Z)) and bool(torch.equal(R1[0], r.rho))
+            checked += 1
+        del server
+    mid = results[len(results) // 2]
+    out = {
+        "metric": "served p99 latency (single-slice requests, 256-768^2, 360-1152 views, 20-80 iters)",
+        "value": mid["p99_ms"], "unit": "ms", "n_gpus": 1, "steps": len(results), "warmup": 0,
+        "ms_per_step": None, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "Poisson arrivals of single-slice requests: image 256/384/512/768 at "
+                               "0.8 mm, views 360-1152, bins 512-1024, iterations 20-80; one "
+                               "16-slot engine per image size under a 200 GB HBM budget",
+                   "value_at_rate_req_s": mid["rate_req_s"]},
+        "per_rate": results,
+        "served_equals_alone": {"checked": checked, "identical": identical},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -187,7 +272,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=2)
-    ap.add_argument("--workload", choices=["slice512", "uneven64"], default="slice512")
+    ap.add_argument("--workload", choices=["slice512", "uneven64", "serve"], default="slice512")
+    ap.add_argument("--rates", default="20,50,100,200", help="serve: arrival rates (req/s)")
+    ap.add_argument("--requests", type=int, default=96, help="serve: requests per rate")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first copy a device buffer of this many MiB once: the reference "
                          "kernel of known traffic for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
@@ -204,6 +291,9 @@ def main():
     from paper_2308_01290_amd import phantoms as P
     if args.workload == "uneven64":
         bench_uneven(args)
+        return
+    if args.workload == "serve":
+        bench_serve(args)
         return
 
     if args.copy_mib > 0:

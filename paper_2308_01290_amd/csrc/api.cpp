@@ -1283,7 +1283,15 @@ int dect_engine_step(dect_engine* e) {
     for (int z = 0; z < e->slots; ++z) any = any || e->busy[z];
     if (!any) return DECT_OK;
     dect_solver* s = e->s;
-    if (int rc = one_iteration(s)) return rc;
+    // launches cover the slots up to the highest occupied one (admission fills
+    // the lowest free slot first)
+    int hw = 0;
+    for (int z = 0; z < e->slots; ++z)
+        if (e->busy[z]) hw = z + 1;
+    s->batch = hw;
+    const int rc = one_iteration(s);
+    s->batch = e->slots;
+    if (rc) return rc;
     const size_t npix = (size_t)s->g.nx * s->g.ny;
     SliceDesc none = s->hdesc[0];
     none.nv = 0;
