@@ -6,6 +6,9 @@ With --workload uneven64 it times instead the batch of 64 uneven slices
 one image size run as one batch (one launch per kernel and iteration for
 all of them), against the same 64 slices solved one at a time.
 
+With --workload image512 it times the image-domain form (Algorithm 1 on the
+attenuation image pair of the same 512^2 phantom, 50 iterations).
+
 With --workload serve it replays Poisson arrival streams of single-slice
 requests (image 256-768, 360-1152 views, 20-80 iterations) through the
 continuous-batching server and reports latency percentiles and slices/s per
@@ -265,6 +268,91 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_image(args):
+    """The image-domain form on the 512^2 phantom's attenuation image pair: a
+    step is one whole solve (closed-form start, 50 iterations, output maps)
+    with the images already in HBM."""
+    import torch
+    from paper_2308_01290_amd import dect
+    from paper_2308_01290_amd import phantoms as P
+    params = dect.default_params(n_iter=N_ITER)
+    g, ph, L, H = P.workload_image512(lambda Z, R: dect.attenuation(params, Z, R))
+    dev = torch.device("cuda:0")
+    lo = torch.as_tensor(L[None].astype(np.float32), device=dev)
+    hi = torch.as_tensor(H[None].astype(np.float32), device=dev)
+    sol = dect.ImageSolver(g.n_x, g.n_y, params)
+    Z = torch.empty((1, g.n_y, g.n_x), device=dev)
+    R = torch.empty_like(Z)
+
+    def step():
+        sol.init(lo, hi)
+        sol.iterate(N_ITER)
+        dect._check(dect.lib().dect_solver_finish(sol._h, dect._ptr(Z), dect._ptr(R)), "finish")
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    sol.enable_timing(True)
+    sol.timing()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fs_ms, fs_n, _, _ = sol.timing()
+    sol.enable_timing(False)
+    elapsed = t1 - t0
+    value = args.steps / elapsed
+    npix = g.n_x * g.n_y
+    fs_avg_s = fs_ms / max(fs_n, 1) / 1e3
+    # algorithmic HBM bytes of one f-step (both closed forms): per basis, read
+    # f (8 B), mu_L, mu_H, rho_e, t' (16 B) and write f_i (4 B) per pixel
+    fs_bytes = 2 * 28 * npix
+    achieved = fs_bytes / fs_avg_s / 1e9
+    out = {
+        "metric": "512^2 image-domain solves/s (50 iters)",
+        "value": value,
+        "unit": "slices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "512x512 attenuation image pair at 0.8 mm (water body + 40 inserts, "
+                               "15/10 HU white noise), image-domain Algorithm 1, 50 outer iterations",
+                   "image": [g.n_y, g.n_x], "iterations": N_ITER, "slices_per_solve": 1},
+        "f_step_ms": 1e3 * fs_avg_s,
+        "roofline": {"kernel": "f-step (k_fft_rows_fwd + k_fft_cols + k_fft_rows_inv, both bases)",
+                     "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import image as I
+        from oracle.physics import Physics
+        from oracle.solve import Params
+        phys = Physics()
+        p = I.resolved(Params(n_iter=N_ITER), phys)
+        a, b = L.astype(np.float32).astype(np.float64), H.astype(np.float32).astype(np.float64)
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        c0 = time.perf_counter()
+        st = I.init_from_mu(a, b, phys, p)
+        c1 = time.perf_counter()
+        for _ in range(args.cpu_iters):
+            st = I.iterate(st, a, b, phys, p)
+        c2 = time.perf_counter()
+        per = (c1 - c0) + N_ITER * (c2 - c1) / args.cpu_iters
+        out["cpu_baseline"] = {"value": 1.0 / per, "unit": "slices/s", "cores": threads, "kind": "oracle",
+                               "sample": f"closed-form start + {args.cpu_iters} of {N_ITER} outer "
+                                         f"iterations on the same image pair ({c2 - c0:.1f} s), "
+                                         f"extrapolated ({per:.1f} s per slice)"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -272,7 +360,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=2)
-    ap.add_argument("--workload", choices=["slice512", "uneven64", "serve"], default="slice512")
+    ap.add_argument("--workload", choices=["slice512", "uneven64", "serve", "image512"],
+                    default="slice512")
     ap.add_argument("--rates", default="20,50,100,200", help="serve: arrival rates (req/s)")
     ap.add_argument("--requests", type=int, default=96, help="serve: requests per rate")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -294,6 +383,9 @@ def main():
         return
     if args.workload == "serve":
         bench_serve(args)
+        return
+    if args.workload == "image512":
+        bench_image(args)
         return
 
     if args.copy_mib > 0:

@@ -241,7 +241,9 @@ int dect_solver_stats(const dect_solver* s, int32_t* k, int32_t* last_pcg_iters)
  * records HIP events on its stream around every back-projection and forward
  * projection launch of the outer iterations.  dect_solver_timing synchronises
  * the stream, returns the summed durations (ms) and launch counts since the
- * last call, and resets them.  Any output pointer may be NULL. */
+ * last call, and resets them.  Any output pointer may be NULL.  For an
+ * image-domain solver the first pair times each iteration's f-step (both FFT
+ * closed forms, one interval per iteration) and the second stays zero. */
 int dect_solver_enable_timing(dect_solver* s, int enable);
 int dect_solver_timing(dect_solver* s, double* backproject_ms, int32_t* backproject_launches,
                        double* project_ms, int32_t* project_launches);
@@ -252,6 +254,39 @@ int dect_solve(const float* sino_lo, const float* sino_hi, const dect_geometry* 
                size_t ws_bytes, hipStream_t stream);
 /* The same for a batch of uneven slices (see dect_solver_create_multi). */
 int dect_solve_multi(const float* sino_lo, const float* sino_hi, const dect_geometry* geoms,
+                     const dect_params* p, float* Z_out, float* rho_out, int32_t batch, void* ws,
+                     size_t ws_bytes, hipStream_t stream);
+
+/* ---- image-domain form ----------------------------------------------------
+ * Algorithm 1 as the paper prints it, on attenuation images instead of
+ * sinograms: the data terms of objective (10) are eta_i*||C_k1 f1 + C_k2 f2 -
+ * mu_k||^2 for the two acquisition energies, and the f-subproblem (13a) is
+ * solved by the printed FFT closed forms, f1 with f2 at iterate k and f2 with
+ * f1 at iterate k:
+ *   (c_i + beta D^T D) f_i = b_i + beta D^T HT(D f_i^(k)),
+ *   c_i = eta_i sum_k C_ki^2 + xi sum_j Ms_ji^2,
+ *   b_i = eta_i sum_k C_ki (mu_k - C_ko f_o) + xi sum_j Ms_ji (T_j - Ms_jo f_o).
+ * The rho_e and t' steps, the beta schedule, the initialisation (the per-pixel
+ * closed forms) and the output are those of the sinogram form.  eta = 0 in
+ * dect_params selects eta_i = 1 / (mu_w(E_lo)^2 + mu_w(E_hi)^2), water's
+ * unit curvature in f2.
+ * Inputs mu_lo, mu_hi: [batch][n_y][n_x] attenuation images (1/mm, DEVICE),
+ * copied into the workspace by init / set_state (the caller's buffers are
+ * free once that enqueued work has run).  n_x, n_y as for dect_l0_step.  The
+ * handle is a dect_solver: dect_solver_iterate, _get_state, _finish, _stats
+ * and _destroy apply to it; dect_solver_init and _set_state reject it (and
+ * the two calls below reject a sinogram solver) with DECT_EINVAL. */
+size_t dect_image_workspace_bytes(int32_t n_x, int32_t n_y, const dect_params* p, int32_t batch);
+int dect_image_solver_create(int32_t n_x, int32_t n_y, const dect_params* p, int32_t batch,
+                             void* ws, size_t ws_bytes, hipStream_t stream, dect_solver** out);
+/* Initialise from the attenuation images (closed forms); k = 0. */
+int dect_image_solver_init(dect_solver* s, const float* mu_lo, const float* mu_hi);
+/* Load an explicit state at outer iteration k with the images it is fitted to. */
+int dect_image_solver_set_state(dect_solver* s, const float* mu_lo, const float* mu_hi,
+                                const float* f1, const float* f2, const float* rho, const float* t,
+                                int32_t k);
+/* Whole solve: create, init, n_iter iterations, finish, destroy. */
+int dect_solve_image(const float* mu_lo, const float* mu_hi, int32_t n_x, int32_t n_y,
                      const dect_params* p, float* Z_out, float* rho_out, int32_t batch, void* ws,
                      size_t ws_bytes, hipStream_t stream);
 

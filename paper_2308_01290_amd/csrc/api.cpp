@@ -155,12 +155,21 @@ static double eta_of(const dect_params* in, const Geom& g) {
     return g.pitch * g.sid / (g.nv * g.dx * g.dx * g.dx * g.sdd * (mwl * mwl + mwh * mwh));
 }
 
-static int resolve_params(const dect_params* in, const Geom& g, const Model& M, Resolved* r) {
+// image-domain data weight: unit water curvature in f2, 1 / (mu_w(E_lo)^2 + mu_w(E_hi)^2)
+static double eta_image(const dect_params* in) {
+    if (in->eta > 0) return in->eta;
+    const double mwl = mu_of(*in, in->Z_w, 1.0, in->E_lo_keV);
+    const double mwh = mu_of(*in, in->Z_w, 1.0, in->E_hi_keV);
+    return 1.0 / (mwl * mwl + mwh * mwh);
+}
+
+// g == nullptr: the image-domain form (no projector)
+static int resolve_params(const dect_params* in, const Geom* g, const Model& M, Resolved* r) {
     r->p = *in;
     r->beta0 = in->beta0 > 0 ? in->beta0 : 2.0 * in->lambda;
     if (!(r->beta0 > 0)) return fail(DECT_EINVAL, "beta0 = 0 needs lambda > 0");
     r->kappa = in->kappa > 0 ? in->kappa : std::pow(in->beta_max / r->beta0, 1.0 / in->n_iter);
-    r->eta = eta_of(in, g);
+    r->eta = g ? eta_of(in, *g) : eta_image(in);
     if (in->xi > 0) {
         r->xi = in->xi;
     } else {
@@ -478,6 +487,8 @@ struct dect_solver {
     double *part_img, *part_proj, *alpha;
     double *beta_d, *kappa_d;        // per-slice beta and its growth rate (device)
     int* active_d = nullptr;         // per-slice activity (engine slots); null: all active
+    bool image = false;              // image-domain form: inputs are mu_lo, mu_hi in muL, muH;
+                                     // B holds f^(k+1) during an iteration
     unsigned* cnt_proj;
     PcgBufs pcg;
     int k;
@@ -783,7 +794,7 @@ static int solver_create(const dect_geometry* geoms, const dect_params* p, int32
         delete s;
         return rc;
     }
-    if (int rc = resolve_params(p, g, s->M, &s->rp)) {
+    if (int rc = resolve_params(p, &g, s->M, &s->rp)) {
         delete s;
         return rc;
     }
@@ -885,6 +896,7 @@ static void project_residual(dect_solver* s, const float* lo, const float* hi) {
 
 int dect_solver_init(dect_solver* s, const float* lo, const float* hi) {
     if (!s || !lo || !hi) return fail(DECT_EINVAL, "dect_solver_init: NULL argument");
+    if (s->image) return fail(DECT_EINVAL, "dect_solver_init: image-domain solver (use dect_image_solver_init)");
     const Geom& g = s->g;
     const BatchGeo& B = s->geo;
     const size_t npix = (size_t)g.nx * g.ny;
@@ -909,6 +921,8 @@ int dect_solver_set_state(dect_solver* s, const float* lo, const float* hi, cons
                           const float* f2, const float* rho, const float* t, int32_t k) {
     if (!s || !lo || !hi || !f1 || !f2 || !rho || !t || k < 0)
         return fail(DECT_EINVAL, "dect_solver_set_state: NULL argument or k < 0");
+    if (s->image)
+        return fail(DECT_EINVAL, "dect_solver_set_state: image-domain solver (use dect_image_solver_set_state)");
     const size_t npix = (size_t)s->g.nx * s->g.ny * s->batch;
     launch_join_f2(s->g.nx * s->g.ny, s->batch, f1, f2, s->f, s->st);
     DECT_HIP(hipMemcpyAsync(s->rho, rho, npix * sizeof(float), hipMemcpyDeviceToDevice, s->st));
@@ -922,7 +936,107 @@ int dect_solver_set_state(dect_solver* s, const float* lo, const float* hi, cons
     return DECT_OK;
 }
 
+// rho_e step, subproblem (13b) by the FFT closed form (reads f^(k), rho^(k);
+// writes rho^(k+1) in place)
+static void rho_step(dect_solver* s) {
+    const Geom& g = s->g;
+    const Resolved& R = s->rp;
+    FftArgs fa;
+    fa.src = FFT_SRC_RHO;
+    fa.f = s->f;
+    fa.base = s->rho;
+    fa.m00 = s->M.Ms[0][0];
+    fa.m01 = s->M.Ms[0][1];
+    fa.m10 = s->M.Ms[1][0];
+    fa.m11 = s->M.Ms[1][1];
+    fa.e1n = s->M.e1n;
+    fa.e2n = s->M.e2n;
+    fa.inv_crho = 1.0 / s->M.crho;
+    fa.beta = (float)s->beta;
+    fa.thr = (float)(R.p.lambda / s->beta);
+    fa.beta_z = s->beta_d;
+    fa.lam = R.p.lambda;
+    fa.c = 1.0;
+    fa.out = s->rho;
+    launch_fft_solve(g.ny, g.nx, s->batch, fa, s->fft, s->st);
+}
+
+// t' step, subproblem (13c) by PCG (reads f^(k), t'^(k); in place)
+static int t_step(dect_solver* s) {
+    const Geom& g = s->g;
+    const Resolved& R = s->rp;
+    PcgArgs pc;
+    fill_pcg_args(&pc, s->pcg, g.ny, g.nx, s->batch, s->t);
+    pc.beta = (float)s->beta;
+    pc.thr = (float)(R.p.lambda / s->beta);
+    pc.tol2 = R.p.t_tol * R.p.t_tol;
+    pc.beta_z = s->beta_d;
+    pc.lam = R.p.lambda;
+    pc.active = s->active_d;
+    if (int rc = choose_prec(R.p.t_precond, s->pcg, s->beta, &pc)) return rc;
+    launch_pcg_init_model(s->M, pc, s->f, s->st);
+    int iters = 0;
+    if (int rc = run_pcg(pc, s->pcg, R.p.t_maxit, s->last_pcg + 2, s->fft, s->st, &iters)) return rc;
+    s->last_pcg = iters;
+    return DECT_OK;
+}
+
+// One outer iteration of the image-domain form: f1 and f2 by the FFT closed
+// forms of (13a) (each with the other basis at iterate k), then the rho_e and
+// t' steps, all reading iterate k; f^(k+1) is built in B and swapped in.
+static int one_iteration_image(dect_solver* s) {
+    const Geom& g = s->g;
+    const Resolved& R = s->rp;
+    const Model& M = s->M;
+    hipEvent_t t0 = mark(s);
+    for (int comp = 0; comp < 2; ++comp) {
+        FftArgs fa;
+        fa.src = FFT_SRC_IMGF;
+        fa.comp = comp;
+        fa.f = s->f;
+        fa.base = reinterpret_cast<const float*>(s->f) + comp;
+        fa.bstride = 2;
+        fa.out = reinterpret_cast<float*>(s->B) + comp;
+        fa.ostride = 2;
+        fa.mu_lo = s->muL;
+        fa.mu_hi = s->muH;
+        fa.rho_in = s->rho;
+        fa.t_in = s->t;
+        fa.cL0 = M.C[0][0];
+        fa.cL1 = M.C[0][1];
+        fa.cH0 = M.C[1][0];
+        fa.cH1 = M.C[1][1];
+        fa.m00 = M.Ms[0][0];
+        fa.m01 = M.Ms[0][1];
+        fa.m10 = M.Ms[1][0];
+        fa.m11 = M.Ms[1][1];
+        fa.ta0 = M.a[0];
+        fa.ta1 = M.a[1];
+        fa.tpsi0 = M.psi[0];
+        fa.tpsi1 = M.psi[1];
+        fa.eta_img = R.eta;
+        fa.xi_img = R.xi;
+        fa.c = R.eta * (M.C[0][comp] * M.C[0][comp] + M.C[1][comp] * M.C[1][comp]) +
+               R.xi * (M.Ms[0][comp] * M.Ms[0][comp] + M.Ms[1][comp] * M.Ms[1][comp]);
+        fa.beta = (float)s->beta;
+        fa.thr = (float)(R.p.lambda / s->beta);
+        fa.beta_z = s->beta_d;
+        fa.lam = R.p.lambda;
+        launch_fft_solve(g.ny, g.nx, s->batch, fa, s->fft, s->st);
+    }
+    mark_end(s, t0, s->ev_bp);
+    rho_step(s);
+    if (int rc = t_step(s)) return rc;
+    std::swap(s->f, s->B);
+    s->beta *= R.kappa;
+    s->k += 1;
+    launch_set_beta(s->beta_d, s->kappa_d, 0, s->batch, s->beta, R.kappa, s->st);
+    DECT_HIP(hipGetLastError());
+    return DECT_OK;
+}
+
 static int one_iteration(dect_solver* s) {
+    if (s->image) return one_iteration_image(s);
     const Geom& g = s->g;
     const Resolved& R = s->rp;
     const double beta = s->beta;
@@ -962,39 +1076,8 @@ static int one_iteration(dect_solver* s) {
     hipEvent_t t1 = mark(s);
     launch_project(g, s->tab, s->dpad, s->batch, PROJ_LINESEARCH, pa, s->st);
     mark_end(s, t1, s->ev_fp);
-    // rho_e step (reads f^(k), rho^(k))
-    FftArgs fa;
-    fa.src = FFT_SRC_RHO;
-    fa.f = s->f;
-    fa.base = s->rho;
-    fa.m00 = s->M.Ms[0][0];
-    fa.m01 = s->M.Ms[0][1];
-    fa.m10 = s->M.Ms[1][0];
-    fa.m11 = s->M.Ms[1][1];
-    fa.e1n = s->M.e1n;
-    fa.e2n = s->M.e2n;
-    fa.inv_crho = 1.0 / s->M.crho;
-    fa.beta = (float)beta;
-    fa.thr = a.thr;
-    fa.beta_z = s->beta_d;
-    fa.lam = R.p.lambda;
-    fa.c = 1.0;
-    fa.out = s->rho;
-    launch_fft_solve(g.ny, g.nx, s->batch, fa, s->fft, s->st);
-    // t' step (reads f^(k), t'^(k); in place)
-    PcgArgs pc;
-    fill_pcg_args(&pc, s->pcg, g.ny, g.nx, s->batch, s->t);
-    pc.beta = (float)beta;
-    pc.thr = a.thr;
-    pc.tol2 = R.p.t_tol * R.p.t_tol;
-    pc.beta_z = s->beta_d;
-    pc.lam = R.p.lambda;
-    pc.active = s->active_d;
-    if (int rc = choose_prec(R.p.t_precond, s->pcg, beta, &pc)) return rc;
-    launch_pcg_init_model(s->M, pc, s->f, s->st);
-    int iters = 0;
-    if (int rc = run_pcg(pc, s->pcg, R.p.t_maxit, s->last_pcg + 2, s->fft, s->st, &iters)) return rc;
-    s->last_pcg = iters;
+    rho_step(s);
+    if (int rc = t_step(s)) return rc;
     // f^(k+1), residual sinograms
     launch_update(a, pad_layout(g), s->tab, s->alpha, s->dpad, s->f, s->S, s->zq, s->beta_d,
                   s->kappa_d, s->st);
@@ -1084,6 +1167,155 @@ int dect_solve(const float* lo, const float* hi, const dect_geometry* g, const d
     dect_solver* s = nullptr;
     if (int rc = dect_solver_create(g, p, batch, ws, ws_bytes, st, &s)) return rc;
     int rc = dect_solver_init(s, lo, hi);
+    if (!rc) rc = dect_solver_iterate(s, p->n_iter);
+    if (!rc) rc = dect_solver_finish(s, Z, rho);
+    dect_solver_destroy(s);
+    return rc;
+}
+
+// ---- image-domain form -----------------------------------------------------
+static size_t image_layout(int nx, int ny, int batch, char* base, dect_solver* s) {
+    Carver c{base};
+    const size_t npix = (size_t)nx * ny * batch;
+    float2* f = c.take<float2>(npix);
+    float2* fnext = c.take<float2>(npix);
+    float2* fft = c.take<float2>(npix);
+    float* rho = c.take<float>(npix);
+    float* tt = c.take<float>(npix);
+    float* muL = c.take<float>(npix);
+    float* muH = c.take<float>(npix);
+    double* beta_d = c.take<double>((size_t)batch);
+    double* kappa_d = c.take<double>((size_t)batch);
+    PcgBufs pb;
+    carve_pcg(c, ny, nx, batch, &pb);
+    if (s) {
+        s->f = f;
+        s->B = fnext;
+        s->fft = fft;
+        s->rho = rho;
+        s->t = tt;
+        s->muL = muL;
+        s->muH = muH;
+        s->beta_d = beta_d;
+        s->kappa_d = kappa_d;
+        s->pcg = pb;
+    }
+    return c.off;
+}
+
+static int check_image_args(int32_t n_x, int32_t n_y, const dect_params* p, int32_t batch) {
+    if (batch < 1) return fail(DECT_EINVAL, "batch must be >= 1");
+    if (int rc = check_params(p)) return rc;
+    if (!fft_size_ok(n_x) || !fft_size_ok(n_y))
+        return fail(DECT_EINVAL, "image sizes must be 2^a*3^b (b <= 1) in [8, 1024], got %dx%d", n_x,
+                    n_y);
+    if (p->t_precond == DECT_PRECOND_MULTIGRID && !mg_plan(n_y, n_x).ok)
+        return fail(DECT_EUNSUPPORTED, "multigrid preconditioner: image %dx%d unsupported", n_x, n_y);
+    return DECT_OK;
+}
+
+size_t dect_image_workspace_bytes(int32_t n_x, int32_t n_y, const dect_params* p, int32_t batch) {
+    if (check_image_args(n_x, n_y, p, batch)) return 0;
+    return image_layout(n_x, n_y, batch, nullptr, nullptr);
+}
+
+int dect_image_solver_create(int32_t n_x, int32_t n_y, const dect_params* p, int32_t batch,
+                             void* ws, size_t ws_bytes, hipStream_t st, dect_solver** out) {
+    if (!out) return fail(DECT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (int rc = check_image_args(n_x, n_y, p, batch)) return rc;
+    dect_solver* s = new dect_solver();
+    s->image = true;
+    s->g = Geom{};
+    s->g.nx = n_x;
+    s->g.ny = n_y;
+    s->g.dx = 1.0;
+    s->batch = batch;
+    s->st = st;
+    if (int rc = build_model(*p, &s->M)) {
+        delete s;
+        return rc;
+    }
+    if (int rc = resolve_params(p, nullptr, s->M, &s->rp)) {
+        delete s;
+        return rc;
+    }
+    const size_t need = image_layout(n_x, n_y, batch, nullptr, nullptr);
+    if (ws) {
+        if (ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255)) {
+            delete s;
+            return fail(DECT_EWORKSPACE, "image solver workspace needs %zu bytes, 256-aligned", need);
+        }
+        s->ws = ws;
+        s->owns_ws = false;
+    } else {
+        if (int rc = dev_alloc(&s->own, need, st)) {
+            delete s;
+            return rc;
+        }
+        s->ws = s->own.p;
+        s->owns_ws = true;
+    }
+    image_layout(n_x, n_y, batch, static_cast<char*>(s->ws), s);
+    const hipError_t e = hipMemsetAsync(s->pcg.st, 0, sizeof(PcgState) * batch, st);
+    if (e != hipSuccess) {
+        if (s->owns_ws) dev_free(&s->own);
+        delete s;
+        return fail(DECT_EDEVICE, "setting up the solver workspace failed: %s", hipGetErrorString(e));
+    }
+    s->k = 0;
+    s->beta = s->rp.beta0;
+    s->last_pcg = 0;
+    *out = s;
+    return DECT_OK;
+}
+
+static int load_mu(dect_solver* s, const float* mu_lo, const float* mu_hi) {
+    const size_t bytes = (size_t)s->g.nx * s->g.ny * s->batch * sizeof(float);
+    DECT_HIP(hipMemcpyAsync(s->muL, mu_lo, bytes, hipMemcpyDeviceToDevice, s->st));
+    DECT_HIP(hipMemcpyAsync(s->muH, mu_hi, bytes, hipMemcpyDeviceToDevice, s->st));
+    return DECT_OK;
+}
+
+int dect_image_solver_init(dect_solver* s, const float* mu_lo, const float* mu_hi) {
+    if (!s || !mu_lo || !mu_hi) return fail(DECT_EINVAL, "dect_image_solver_init: NULL argument");
+    if (!s->image) return fail(DECT_EINVAL, "dect_image_solver_init: not an image-domain solver");
+    if (int rc = load_mu(s, mu_lo, mu_hi)) return rc;
+    launch_init_state(s->M, s->g.ny, s->g.nx, s->batch, s->muL, s->muH, (float)s->rp.p.rho_min, s->f,
+                      s->rho, s->t, s->st);
+    s->k = 0;
+    s->beta = s->rp.beta0;
+    launch_set_beta(s->beta_d, s->kappa_d, 0, s->batch, s->beta, s->rp.kappa, s->st);
+    DECT_HIP(hipGetLastError());
+    return DECT_OK;
+}
+
+int dect_image_solver_set_state(dect_solver* s, const float* mu_lo, const float* mu_hi,
+                                const float* f1, const float* f2, const float* rho, const float* t,
+                                int32_t k) {
+    if (!s || !mu_lo || !mu_hi || !f1 || !f2 || !rho || !t || k < 0)
+        return fail(DECT_EINVAL, "dect_image_solver_set_state: NULL argument or k < 0");
+    if (!s->image) return fail(DECT_EINVAL, "dect_image_solver_set_state: not an image-domain solver");
+    if (int rc = load_mu(s, mu_lo, mu_hi)) return rc;
+    const size_t npix = (size_t)s->g.nx * s->g.ny * s->batch;
+    launch_join_f2(s->g.nx * s->g.ny, s->batch, f1, f2, s->f, s->st);
+    DECT_HIP(hipMemcpyAsync(s->rho, rho, npix * sizeof(float), hipMemcpyDeviceToDevice, s->st));
+    DECT_HIP(hipMemcpyAsync(s->t, t, npix * sizeof(float), hipMemcpyDeviceToDevice, s->st));
+    s->k = k;
+    s->beta = s->rp.beta0;
+    for (int i = 0; i < k; ++i) s->beta *= s->rp.kappa;
+    launch_set_beta(s->beta_d, s->kappa_d, 0, s->batch, s->beta, s->rp.kappa, s->st);
+    DECT_HIP(hipGetLastError());
+    return DECT_OK;
+}
+
+int dect_solve_image(const float* mu_lo, const float* mu_hi, int32_t n_x, int32_t n_y,
+                     const dect_params* p, float* Z, float* rho, int32_t batch, void* ws,
+                     size_t ws_bytes, hipStream_t st) {
+    if (!mu_lo || !mu_hi || (!Z && !rho)) return fail(DECT_EINVAL, "dect_solve_image: NULL array");
+    dect_solver* s = nullptr;
+    if (int rc = dect_image_solver_create(n_x, n_y, p, batch, ws, ws_bytes, st, &s)) return rc;
+    int rc = dect_image_solver_init(s, mu_lo, mu_hi);
     if (!rc) rc = dect_solver_iterate(s, p->n_iter);
     if (!rc) rc = dect_solver_finish(s, Z, rho);
     dect_solver_destroy(s);

@@ -151,7 +151,7 @@ void launch_fbp(const Geom& g, const float* sino, int nsino, float* q, float* im
 // ---- FFT solve of (c + beta*D^T D) x = rhs, periodic ----------------------------
 // Sizes n = 2^a * 3^b (b <= 1), 8 <= n <= 1024.
 bool fft_size_ok(int n);
-enum FftSrc { FFT_SRC_PLAIN = 0, FFT_SRC_RHO = 1, FFT_SRC_L0 = 2 };
+enum FftSrc { FFT_SRC_PLAIN = 0, FFT_SRC_RHO = 1, FFT_SRC_L0 = 2, FFT_SRC_IMGF = 3 };
 struct FftArgs {
     int src = FFT_SRC_PLAIN;
     // PLAIN: out = (c + beta L)^-1 in.
@@ -161,6 +161,11 @@ struct FftArgs {
     // target = rho_hat(f) (RHO) or in = g_tilde (L0).  Equal to the closed
     // form for (1 + beta L) out = target + beta D^T HT(D g), without the large
     // cancelling terms.
+    // IMGF (image-domain f-subproblem (13a), basis `comp` with the other basis
+    // at iterate k): (c + beta L) delta = r - beta D^T S, r = b - c g, where
+    //   r = eta_i sum_k C_k,comp (mu_k - (C f)_k) + xi sum_j Ms_j,comp (T_j - (Ms f)_j),
+    //   T_j = rho (ta_j t' + tpsi_j), c = eta_i sum_k C_k,comp^2 + xi sum_j Ms_j,comp^2,
+    // f (interleaved f1, f2) at iterate k; g = base = component comp of f.
     const float* in = nullptr;
     const float2* f = nullptr;
     const float* base = nullptr;
@@ -183,6 +188,16 @@ struct FftArgs {
     const int* skip = nullptr;        // skip slice z when skip[z*skip_zstride] != 0
     size_t skip_zstride = 0;
     float* out = nullptr;
+    int bstride = 1, ostride = 1;     // element strides of base and out (2: one half of a float2)
+    // IMGF inputs
+    const float* mu_lo = nullptr;
+    const float* mu_hi = nullptr;
+    const float* rho_in = nullptr;
+    const float* t_in = nullptr;
+    int comp = 0;
+    double cL0 = 0, cL1 = 0, cH0 = 0, cH1 = 0;   // attenuation matrix rows (E_lo, E_hi)
+    double ta0 = 0, ta1 = 0, tpsi0 = 0, tpsi1 = 0;
+    double eta_img = 0, xi_img = 0;
     const float* dot_with = nullptr;  // optional: dot_parts[z*dot_zstride + row] = <out, dot_with>
     double* dot_parts = nullptr;
     size_t dot_zstride = 0;

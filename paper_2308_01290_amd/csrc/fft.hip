@@ -141,6 +141,22 @@ __device__ __forceinline__ float2 ht_small(const float* ra, const float* rb, int
     return keep ? make_float2(0.f, 0.f) : make_float2(dx, dy);
 }
 
+// r = b - c g of the image-domain f-subproblem at pixel q (FP64 per pixel:
+// the data and coupling residuals cancel to small values near convergence)
+__device__ __forceinline__ float imgf_residual(const FftArgs& a, size_t q) {
+    const float2 f = a.f[q];
+    const double f1 = f.x, f2 = f.y;
+    const double rL = (double)a.mu_lo[q] - (a.cL0 * f1 + a.cL1 * f2);
+    const double rH = (double)a.mu_hi[q] - (a.cH0 * f1 + a.cH1 * f2);
+    const double r = a.rho_in[q], t = a.t_in[q];
+    const double c1 = r * (a.ta0 * t + a.tpsi0) - (a.m00 * f1 + a.m01 * f2);
+    const double c2 = r * (a.ta1 * t + a.tpsi1) - (a.m10 * f1 + a.m11 * f2);
+    const double v = a.comp == 0
+                         ? a.eta_img * (a.cL0 * rL + a.cH0 * rH) + a.xi_img * (a.m00 * c1 + a.m10 * c2)
+                         : a.eta_img * (a.cL1 * rL + a.cH1 * rH) + a.xi_img * (a.m01 * c1 + a.m11 * c2);
+    return (float)v;
+}
+
 __device__ __forceinline__ bool skip_slice(const FftArgs& a, int z) {
     return a.skip && a.skip[(size_t)z * a.skip_zstride];
 }
@@ -181,10 +197,11 @@ __global__ __launch_bounds__(256) void k_fft_rows_fwd(FftPlan P, int ny, FftArgs
         }
     } else {
         const int im = (i == 0) ? ny - 1 : i - 1, ip = (i + 1 == ny) ? 0 : i + 1;
+        const size_t bs = (size_t)a.bstride;
         for (int k = threadIdx.x; k < nx; k += blockDim.x) {
-            rows[k] = a.base[z * npix + (size_t)im * nx + k];
-            rows[nx + k] = a.base[z * npix + (size_t)i * nx + k];
-            rows[2 * nx + k] = a.base[z * npix + (size_t)ip * nx + k];
+            rows[k] = a.base[(z * npix + (size_t)im * nx + k) * bs];
+            rows[nx + k] = a.base[(z * npix + (size_t)i * nx + k) * bs];
+            rows[2 * nx + k] = a.base[(z * npix + (size_t)ip * nx + k) * bs];
         }
         __syncthreads();
         const float* rm = rows;
@@ -204,6 +221,8 @@ __global__ __launch_bounds__(256) void k_fft_rows_fwd(FftPlan P, int ny, FftArgs
                 const double M1 = a.m00 * (double)f.x + a.m01 * (double)f.y;
                 const double M2 = a.m10 * (double)f.x + a.m11 * (double)f.y;
                 diff = (float)((M1 * a.e1n - M2 * a.e2n) * a.inv_crho - (double)g);
+            } else if (a.src == FFT_SRC_IMGF) {
+                diff = imgf_residual(a, z * npix + (size_t)i * nx + k);
             } else {
                 diff = a.in[z * npix + (size_t)i * nx + k] - g;
                 if (a.h_out) a.h_out[z * npix + (size_t)i * nx + k] = kept.x;
@@ -290,8 +309,8 @@ __global__ __launch_bounds__(256) void k_fft_rows_inv(FftPlan P, int ny, FftArgs
         const size_t q = z * npix + (size_t)i * nx + k;
         float d = R[k].x * sc;
         if (a.scale_w2) d *= sqrtf((cz + 4.f * a.beta) / (a.scale_w2[q] + 4.f * a.beta));
-        const float v = corr ? a.base[q] + d : d;
-        a.out[q] = v;
+        const float v = corr ? a.base[q * a.bstride] + d : d;
+        a.out[q * a.ostride] = v;
         if (a.dot_with) dot += (double)v * (double)a.dot_with[q];
     }
     if (a.dot_parts) {

@@ -50,6 +50,8 @@ EXPORTS = [
     "dect_solve_workspace_bytes_multi", "dect_solver_create_multi", "dect_solve_multi",
     "dect_engine_workspace_bytes", "dect_engine_create", "dect_engine_destroy", "dect_engine_admit",
     "dect_engine_step", "dect_engine_status", "dect_engine_completed",
+    "dect_image_workspace_bytes", "dect_image_solver_create", "dect_image_solver_init",
+    "dect_image_solver_set_state", "dect_solve_image",
     "dect_last_error",
 ]
 
@@ -103,6 +105,12 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.dect_engine_step.argtypes = [vp]
     L.dect_engine_status.argtypes = [vp, P(i32), P(i32)]
     L.dect_engine_completed.argtypes = [vp, P(i32), i32, P(i32)]
+    L.dect_image_workspace_bytes.argtypes = [i32, i32, Pp, i32]
+    L.dect_image_workspace_bytes.restype = C.c_size_t
+    L.dect_image_solver_create.argtypes = [i32, i32, Pp, i32, vp, C.c_size_t, vp, P(vp)]
+    L.dect_image_solver_init.argtypes = [vp, vp, vp]
+    L.dect_image_solver_set_state.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32]
+    L.dect_solve_image.argtypes = [vp, vp, i32, i32, Pp, vp, vp, i32, vp, C.c_size_t, vp]
     L.dect_last_error.argtypes = []
     L.dect_last_error.restype = C.c_char_p
     return L
@@ -416,6 +424,75 @@ class Solver:
         it = C.c_int32()
         _check(lib().dect_solver_stats(self._h, C.byref(k), C.byref(it)), "dect_solver_stats")
         return int(k.value), int(it.value)
+
+
+class ImageSolver(Solver):
+    """The image-domain form of Algorithm 1: a batch of [n_y, n_x] attenuation
+    image pairs, state on device.  iterate / state / finish / stats as Solver."""
+
+    def __init__(self, n_x: int, n_y: int, params=None, batch: int = 1, device="cuda", stream=None):
+        self.params = params if params is not None else default_params()
+        self.device = device
+        self._stream = stream
+        self.batch = int(batch)
+        self.n_x, self.n_y = int(n_x), int(n_y)
+        self.geom = _ImageGrid(self.n_x, self.n_y)
+        self.uneven = False
+        h = C.c_void_p()
+        _check(lib().dect_image_solver_create(self.n_x, self.n_y, C.byref(self.params), self.batch,
+                                              None, 0, C.c_void_p(_stream(stream)), C.byref(h)),
+               "dect_image_solver_create")
+        self._h = h
+
+    def _check_mu(self, mu_lo, mu_hi):
+        for name, a in (("mu_lo", mu_lo), ("mu_hi", mu_hi)):
+            _dev_f32(a, (self.n_y, self.n_x), name)
+            if _batch(a) != self.batch:
+                raise ValueError(f"{name} holds {_batch(a)} images, the solver {self.batch}")
+
+    def init(self, mu_lo, mu_hi):
+        self._check_mu(mu_lo, mu_hi)
+        _check(lib().dect_image_solver_init(self._h, _ptr(mu_lo), _ptr(mu_hi)), "dect_image_solver_init")
+        self._keep = (mu_lo, mu_hi)
+        return self
+
+    def set_state(self, mu_lo, mu_hi, f1, f2, rho, t, k=0):
+        self._check_mu(mu_lo, mu_hi)
+        for name, a in (("f1", f1), ("f2", f2), ("rho", rho), ("t", t)):
+            _dev_f32(a, (self.n_y, self.n_x), name)
+            if _batch(a) != self.batch:
+                raise ValueError(f"{name} holds {_batch(a)} images, the solver {self.batch}")
+        _check(lib().dect_image_solver_set_state(self._h, _ptr(mu_lo), _ptr(mu_hi), _ptr(f1), _ptr(f2),
+                                                 _ptr(rho), _ptr(t), int(k)),
+               "dect_image_solver_set_state")
+        self._keep = (mu_lo, mu_hi, f1, f2, rho, t)
+        return self
+
+
+@dataclass
+class _ImageGrid:
+    n_x: int
+    n_y: int
+
+
+def solve_image(mu_lo, mu_hi, params=None, stream=None):
+    """Whole image-domain solve of [batch,] n_y x n_x attenuation image pairs
+    -> (Z, rho_e), each [batch, n_y, n_x]."""
+    torch = _torch()
+    if mu_lo.dim() < 2:
+        raise ValueError("mu_lo must be [batch,] n_y x n_x")
+    n_y, n_x = int(mu_lo.shape[-2]), int(mu_lo.shape[-1])
+    _dev_f32(mu_lo, (n_y, n_x), "mu_lo")
+    _dev_f32(mu_hi, (n_y, n_x), "mu_hi")
+    b = _batch(mu_lo)
+    if _batch(mu_hi) != b:
+        raise ValueError("mu_lo and mu_hi hold different numbers of images")
+    p = params if params is not None else default_params()
+    Z = torch.empty((b, n_y, n_x), device=mu_lo.device, dtype=torch.float32)
+    R = torch.empty_like(Z)
+    _check(lib().dect_solve_image(_ptr(mu_lo), _ptr(mu_hi), n_x, n_y, C.byref(p), _ptr(Z), _ptr(R), b,
+                                  None, 0, C.c_void_p(_stream(stream))), "dect_solve_image")
+    return Z, R
 
 
 def solve(sino_lo, sino_hi, geom, params=None, stream=None):

@@ -383,3 +383,43 @@ def slice_uneven(seed: int, mu_of: MuFn, I0=(5e4, 1e5)):
 def workload_uneven(mu_of: MuFn, n_slices: int = 64, seed0: int = 3000):
     """The uneven batch: slices seed0, seed0 + 1, ... (list of slice_uneven tuples)."""
     return [slice_uneven(seed0 + i, mu_of) for i in range(n_slices)]
+
+
+# --------------------------------------------------------------------------
+# image-domain inputs (attenuation image pairs)
+# --------------------------------------------------------------------------
+# Relative noise of the two attenuation images, in units of water's
+# attenuation at each energy: the per-pixel noise level of a clinical
+# reconstruction (about 15 and 10 HU).
+IMAGE_NOISE_REL = (0.015, 0.010)
+
+
+def noisy_mu_pair(ph: Phantom, geom: FanGeometry, mu_of: MuFn, seed: int,
+                  rel=IMAGE_NOISE_REL, supersample: int = 2):
+    """(mu_L, mu_H) of a phantom on the image grid (coverage-weighted, 2x2
+    supersampled) plus independent white Gaussian noise of standard deviation
+    rel[k] * mu_water(E_k), seeded."""
+    muL, muH = mu_maps(ph, geom, mu_of, supersample)
+    wL, wH = mu_of(np.array([WATER_Z]), np.array([WATER_RHO]))
+    rng = np.random.default_rng(seed)
+    nL = rng.standard_normal(muL.shape) * (rel[0] * float(wL[0]))
+    nH = rng.standard_normal(muH.shape) * (rel[1] * float(wH[0]))
+    return muL + nL, muH + nH
+
+
+def workload_image_small(mu_of: MuFn, seed: int = 1290, noise_seed: int = 1293):
+    """128^2 / 1 mm water disk with 8 inserts (the small phantom) as noisy
+    attenuation images."""
+    geom = geometry_small()
+    ph = phantom_disk_inserts(seed)
+    muL, muH = noisy_mu_pair(ph, geom, mu_of, noise_seed)
+    return geom, ph, muL, muH
+
+
+def workload_image512(mu_of: MuFn, seed: int = 2308, noise_seed: int = 2311):
+    """512^2 / 0.8 mm body with 40 inserts (the 512^2 slice's phantom) as noisy
+    attenuation images."""
+    geom = geometry_slice512()
+    ph = phantom_body_inserts(seed)
+    muL, muH = noisy_mu_pair(ph, geom, mu_of, noise_seed)
+    return geom, ph, muL, muH

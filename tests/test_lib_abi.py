@@ -116,10 +116,30 @@ def test_entry_points_reject_bad_arguments_before_enqueueing():
     assert L.dect_engine_create(128, 128, 1.0, 0, 180, 256, C.byref(p), None, 0, None, C.byref(eh)) == -1
     assert L.dect_engine_workspace_bytes(128, 128, 1.0, 4, 180, 256, C.byref(p)) > \
         L.dect_engine_workspace_bytes(128, 128, 1.0, 2, 180, 256, C.byref(p)) > 0
+    # image-domain form: sizes, params and NULL arrays are checked on the host
+    p = dect.default_params()
+    assert L.dect_image_solver_create(100, 128, C.byref(p), 1, None, 0, None, C.byref(h)) == -1
+    assert b"2^a*3^b" in L.dect_last_error()
+    assert L.dect_image_solver_create(128, 128, C.byref(p), 0, None, 0, None, C.byref(h)) == -1
+    p = dect.default_params(t_precond=3)
+    assert L.dect_image_solver_create(96, 24, C.byref(p), 1, None, 0, None, C.byref(h)) == -5
+    p = dect.default_params()
+    assert L.dect_solve_image(None, None, 128, 128, C.byref(p), None, None, 1, None, 0, None) == -1
+    assert L.dect_image_solver_init(None, None, None) == -1
+    assert L.dect_image_workspace_bytes(100, 128, C.byref(p), 1) == 0
     # l0 step: unsupported FFT size, NULL input
     assert L.dect_l0_step(None, None, None, None, None, 16, 16, 1, 0.1, 1.0, 1e-6, 10, None, 0, None) == -1
     assert L.dect_l0_step(C.c_void_p(1), None, C.c_void_p(1), None, None, 10, 16, 1, 0.1, 1.0, 1e-6,
                           10, None, 0, None) == -1
+
+
+def test_image_workspace_sizes():
+    L = dect.lib()
+    p = dect.default_params()
+    one = L.dect_image_workspace_bytes(512, 512, C.byref(p), 1)
+    two = L.dect_image_workspace_bytes(512, 512, C.byref(p), 2)
+    # f, f^(k+1), FFT scratch (2 floats each), rho, t', mu_L, mu_H, PCG vectors
+    assert 512 * 512 * 4 * 10 < one < two <= 2 * one + 4096 * 64
 
 
 def test_workspace_sizes_are_consistent():
