@@ -22,6 +22,7 @@ slice (FBP start, 50 iterations, output maps) with the sinograms already in
 HBM.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu-baseline]
+                    [--storage fp32|bf16|bf16_state]
 """
 from __future__ import annotations
 
@@ -362,6 +363,9 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=2)
     ap.add_argument("--workload", choices=["slice512", "uneven64", "serve", "image512"],
                     default="slice512")
+    ap.add_argument("--storage", choices=["fp32", "bf16", "bf16_state"], default="fp32",
+                    help="slice512: storage of the projector operands (bf16) and also of the "
+                         "state images (bf16_state)")
     ap.add_argument("--rates", default="20,50,100,200", help="serve: arrival rates (req/s)")
     ap.add_argument("--requests", type=int, default=96, help="serve: requests per rate")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -396,7 +400,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    params = dect.default_params(n_iter=N_ITER)
+    storage = {"fp32": dect.DECT_STORAGE_FP32, "bf16": dect.DECT_STORAGE_BF16,
+               "bf16_state": dect.DECT_STORAGE_BF16_STATE}[args.storage]
+    params = dect.default_params(n_iter=N_ITER, storage=storage)
     g, ph, pL, pH = P.workload_slice512(lambda Z, R: dect.attenuation(params, Z, R))
     pL = pL.astype(np.float32)
     pH = pH.astype(np.float32)
@@ -456,7 +462,7 @@ def main():
         "config": {"workload": "512x512 slice at 0.8 mm, 720 views, 736 bins, SID 1000 / SDD 1500 mm, "
                                "water body + 40 inserts, Poisson 5e4/1e5, 50 outer iterations",
                    "image": [g.n_y, g.n_x], "views": g.n_views, "bins": g.n_det,
-                   "iterations": N_ITER, "slices_per_solve": 1},
+                   "iterations": N_ITER, "slices_per_solve": 1, "storage": args.storage},
         "rays_per_s": 4.0 * nray * N_ITER * value,
         "projector": {
             "system_matrix_nonzeros": nnz,
@@ -469,7 +475,7 @@ def main():
         },
         "roofline": {"kernel": "k_backproject", "bound": "alu", "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": measured_traffic("k_backproject")},
+                     "traffic": measured_traffic("k_backproject") if storage == 0 else None},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, pL, pH, args.cpu_iters)

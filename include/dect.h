@@ -99,7 +99,10 @@ typedef struct dect_geometry {
  *                        value (DECT_PRECOND_AUTO: the multigrid V-cycle
  *                        where the image sizes admit it, else Jacobi below
  *                        beta = 1.5 and the scaled FFT inverse above).  The
- *                        choice changes the iterate only within t_tol. */
+ *                        choice changes the iterate only within t_tol.
+ *   storage              precision of stored iterates, a DECT_STORAGE_* value
+ *                        (sinogram form only; the image-domain form returns
+ *                        DECT_EUNSUPPORTED for anything but FP32). */
 typedef struct dect_params {
     double E_lo_keV, E_hi_keV, E1_keV, E2_keV;
     double m, n, Cp, Z_w;
@@ -111,7 +114,29 @@ typedef struct dect_params {
     int32_t t_maxit;
     double rho_min, t_min;
     int32_t t_precond;
+    int32_t storage;
 } dect_params;
+
+/* Values of dect_params.storage.  Arithmetic is FP32 (FP64 where stated) in
+ * every mode; only what is stored between kernels changes.
+ *   DECT_STORAGE_FP32        everything in FP32 (default)
+ *   DECT_STORAGE_BF16        the projector operands in BF16, rounded to
+ *                            nearest even when written: the search direction
+ *                            the forward projector reads, the residual
+ *                            sinograms the back-projector reads, and the
+ *                            line-search sinograms; ray sums and
+ *                            back-projection accumulate in FP32, the line
+ *                            search uses the stored direction
+ *   DECT_STORAGE_BF16_STATE  as BF16, and the state images f1, f2, rho_e, t'
+ *                            rounded to BF16 after every write (start and
+ *                            each outer iteration); the residual sinograms
+ *                            are updated incrementally as in FP32 mode, so
+ *                            they carry the projection of the f rounding */
+enum {
+    DECT_STORAGE_FP32 = 0,
+    DECT_STORAGE_BF16 = 1,
+    DECT_STORAGE_BF16_STATE = 2
+};
 
 /* Values of dect_params.t_precond.  DECT_PRECOND_MULTIGRID needs every image
  * side above 64 to be a multiple of 16 down to 64 (sides halve per level) and

@@ -114,6 +114,8 @@ static int check_params(const dect_params* p) {
     if (p->t_precond < DECT_PRECOND_AUTO || p->t_precond > DECT_PRECOND_MULTIGRID)
         return fail(DECT_EINVAL, "t_precond = %d: must be one of the DECT_PRECOND_* values",
                     p->t_precond);
+    if (p->storage < DECT_STORAGE_FP32 || p->storage > DECT_STORAGE_BF16_STATE)
+        return fail(DECT_EINVAL, "storage = %d: must be one of the DECT_STORAGE_* values", p->storage);
     return DECT_OK;
 }
 
@@ -487,6 +489,8 @@ struct dect_solver {
     double *part_img, *part_proj, *alpha;
     double *beta_d, *kappa_d;        // per-slice beta and its growth rate (device)
     int* active_d = nullptr;         // per-slice activity (engine slots); null: all active
+    int storage = DECT_STORAGE_FP32;
+    unsigned* dpad16 = nullptr;      // BF16 storage: the direction's pair blocks, one word per entry
     bool image = false;              // image-domain form: inputs are mu_lo, mu_hi in muL, muH;
                                      // B holds f^(k+1) during an iteration
     unsigned* cnt_proj;
@@ -700,7 +704,7 @@ int dect_l0_step(const float* g_tilde, const float* weight, float* g, float* h_o
 }
 
 // ---- solver ---------------------------------------------------------------
-static size_t solver_layout(const BatchGeo& B, char* base, dect_solver* s) {
+static size_t solver_layout(const BatchGeo& B, char* base, dect_solver* s, int storage) {
     const Geom& g = B.g[0];
     const int batch = (int)B.g.size();
     Carver c{base};
@@ -726,9 +730,11 @@ static size_t solver_layout(const BatchGeo& B, char* base, dect_solver* s) {
     double* beta_d = c.take<double>((size_t)batch);
     double* kappa_d = c.take<double>((size_t)batch);
     unsigned* cnt = c.take<unsigned>((size_t)batch);
+    unsigned* dpad16 = storage != DECT_STORAGE_FP32 ? c.take<unsigned>(pad_elems(g) * batch) : nullptr;
     PcgBufs pb;
     carve_pcg(c, g.ny, g.nx, batch, &pb);
     if (s) {
+        s->dpad16 = dpad16;
         s->beta_d = beta_d;
         s->kappa_d = kappa_d;
         t.desc = desc;
@@ -761,7 +767,7 @@ size_t dect_solve_workspace_bytes_multi(const dect_geometry* geoms, const dect_p
                                         int32_t batch) {
     BatchGeo B;
     if (!p || make_batch(geoms, batch, &B)) return 0;
-    return solver_layout(B, nullptr, nullptr);
+    return solver_layout(B, nullptr, nullptr, p->storage);
 }
 
 size_t dect_solve_workspace_bytes(const dect_geometry* gin, const dect_params* p, int32_t batch) {
@@ -798,7 +804,8 @@ static int solver_create(const dect_geometry* geoms, const dect_params* p, int32
         delete s;
         return rc;
     }
-    const size_t need = solver_layout(B, nullptr, nullptr);
+    s->storage = p->storage;
+    const size_t need = solver_layout(B, nullptr, nullptr, s->storage);
     if (ws) {
         if (ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255)) {
             delete s;
@@ -814,7 +821,7 @@ static int solver_create(const dect_geometry* geoms, const dect_params* p, int32
         s->ws = s->own.p;
         s->owns_ws = true;
     }
-    solver_layout(B, static_cast<char*>(s->ws), s);
+    solver_layout(B, static_cast<char*>(s->ws), s, s->storage);
     s->hdesc.resize(batch);
     for (int z = 0; z < batch; ++z) {
         const int u = B.uniq[z];
@@ -823,6 +830,8 @@ static int solver_create(const dect_geometry* geoms, const dect_params* p, int32
     // zero borders of the padded direction layouts, counters and scalars once
     hipError_t e = hipSuccess;
     e = e != hipSuccess ? e : hipMemsetAsync(s->dpad, 0, pad_elems(g) * batch * sizeof(float2), st);
+    if (s->dpad16)
+        e = e != hipSuccess ? e : hipMemsetAsync(s->dpad16, 0, pad_elems(g) * batch * sizeof(unsigned), st);
     e = e != hipSuccess ? e : hipMemsetAsync(s->cnt_proj, 0, sizeof(unsigned) * batch, st);
     e = e != hipSuccess ? e : hipMemsetAsync(s->pcg.st, 0, sizeof(PcgState) * batch, st);
     e = e != hipSuccess ? e
@@ -891,7 +900,15 @@ static void project_residual(dect_solver* s, const float* lo, const float* hi) {
     a.c01 = (float)s->M.C[0][1];
     a.c10 = (float)s->M.C[1][0];
     a.c11 = (float)s->M.C[1][1];
+    a.res_bf16 = s->storage != DECT_STORAGE_FP32;
     launch_project(s->g, s->tab, s->dpad, s->batch, PROJ_RESID, a, s->st);
+}
+
+// BF16 state storage: the state images hold BF16 values from here on
+static void round_state(dect_solver* s, int z0, int n) {
+    if (s->storage != DECT_STORAGE_BF16_STATE || n < 1) return;
+    const size_t npix = (size_t)s->g.nx * s->g.ny;
+    launch_round_state(npix * n, s->f + z0 * npix, s->rho + z0 * npix, s->t + z0 * npix, s->st);
 }
 
 int dect_solver_init(dect_solver* s, const float* lo, const float* hi) {
@@ -909,6 +926,7 @@ int dect_solver_init(dect_solver* s, const float* lo, const float* hi) {
     }
     launch_init_state(s->M, g.ny, g.nx, s->batch, s->muL, s->muH, (float)s->rp.p.rho_min, s->f,
                       s->rho, s->t, s->st);
+    round_state(s, 0, s->batch);
     project_residual(s, lo, hi);
     s->k = 0;
     s->beta = s->rp.beta0;
@@ -927,6 +945,7 @@ int dect_solver_set_state(dect_solver* s, const float* lo, const float* hi, cons
     launch_join_f2(s->g.nx * s->g.ny, s->batch, f1, f2, s->f, s->st);
     DECT_HIP(hipMemcpyAsync(s->rho, rho, npix * sizeof(float), hipMemcpyDeviceToDevice, s->st));
     DECT_HIP(hipMemcpyAsync(s->t, t, npix * sizeof(float), hipMemcpyDeviceToDevice, s->st));
+    round_state(s, 0, s->batch);
     project_residual(s, lo, hi);
     s->k = k;
     s->beta = s->rp.beta0;
@@ -1053,11 +1072,13 @@ static int one_iteration(dect_solver* s) {
     a.beta = (float)beta;
     a.beta_z = s->beta_d;   // every kernel takes its slice's beta from here
     a.lam = R.p.lambda;
+    a.bf16 = s->storage != DECT_STORAGE_FP32;
+    void* dir = a.bf16 ? static_cast<void*>(s->dpad16) : static_cast<void*>(s->dpad);
     // f-step: A^T of the combined residuals, gradient, A of the direction
     hipEvent_t t0 = mark(s);
-    launch_backproject(g, s->tab, s->S, s->batch, s->B, nullptr, 0, s->st);
+    launch_backproject(g, s->tab, s->S, s->batch, s->B, nullptr, 0, s->st, a.bf16);
     mark_end(s, t0, s->ev_bp);
-    launch_grad(s->M, a, pad_layout(g), s->f, s->B, s->rho, s->t, s->dpad, s->part_img, s->st);
+    launch_grad(s->M, a, pad_layout(g), s->f, s->B, s->rho, s->t, dir, s->part_img, s->st);
     ProjArgs pa;
     pa.res = s->zq;
     pa.c00 = (float)s->M.C[0][0];
@@ -1073,14 +1094,16 @@ static int one_iteration(dect_solver* s) {
     pa.beta_z = s->beta_d;
     pa.alpha = s->alpha;
     pa.counter = s->cnt_proj;
+    pa.pad_bf16 = pa.res_bf16 = a.bf16;
     hipEvent_t t1 = mark(s);
-    launch_project(g, s->tab, s->dpad, s->batch, PROJ_LINESEARCH, pa, s->st);
+    launch_project(g, s->tab, dir, s->batch, PROJ_LINESEARCH, pa, s->st);
     mark_end(s, t1, s->ev_fp);
     rho_step(s);
     if (int rc = t_step(s)) return rc;
     // f^(k+1), residual sinograms
-    launch_update(a, pad_layout(g), s->tab, s->alpha, s->dpad, s->f, s->S, s->zq, s->beta_d,
+    launch_update(a, pad_layout(g), s->tab, s->alpha, dir, s->f, s->S, s->zq, s->beta_d,
                   s->kappa_d, s->st);
+    round_state(s, 0, s->batch);
     s->beta *= R.kappa;
     s->k += 1;
     DECT_HIP(hipGetLastError());
@@ -1211,6 +1234,8 @@ static int check_image_args(int32_t n_x, int32_t n_y, const dect_params* p, int3
                     n_y);
     if (p->t_precond == DECT_PRECOND_MULTIGRID && !mg_plan(n_y, n_x).ok)
         return fail(DECT_EUNSUPPORTED, "multigrid preconditioner: image %dx%d unsupported", n_x, n_y);
+    if (p->storage != DECT_STORAGE_FP32)
+        return fail(DECT_EUNSUPPORTED, "image-domain form: storage must be DECT_STORAGE_FP32");
     return DECT_OK;
 }
 
@@ -1371,7 +1396,7 @@ size_t dect_engine_workspace_bytes(int32_t n_x, int32_t n_y, double pixel_mm, in
     std::vector<dect_geometry> gs((size_t)slots, capacity_geometry(n_x, n_y, pixel_mm, max_views, max_det));
     BatchGeo B;
     if (make_batch(gs.data(), slots, &B, false)) return 0;
-    return solver_layout(B, nullptr, nullptr);
+    return solver_layout(B, nullptr, nullptr, p->storage);
 }
 
 int dect_engine_create(int32_t n_x, int32_t n_y, double pixel_mm, int32_t slots, int32_t max_views,
@@ -1476,6 +1501,7 @@ int dect_engine_admit(dect_engine* e, const dect_geometry* gin, const float* lo,
     launch_fbp(g, hi, 1, q, s->muH + z * npix, st);
     launch_init_state(s->M, g.ny, g.nx, 1, s->muL + z * npix, s->muH + z * npix,
                       (float)s->rp.p.rho_min, s->f + z * npix, s->rho + z * npix, s->t + z * npix, st);
+    round_state(s, z, 1);
     // residual sinograms of the start
     const PadLayout P = pad_layout(g);
     launch_pack_f2(g, s->f + z * npix, 1, s->dpad + z * P.pair, st);
@@ -1494,6 +1520,7 @@ int dect_engine_admit(dect_engine* e, const dect_geometry* gin, const float* lo,
     a.c01 = (float)s->M.C[0][1];
     a.c10 = (float)s->M.C[1][0];
     a.c11 = (float)s->M.C[1][1];
+    a.res_bf16 = s->storage != DECT_STORAGE_FP32;
     launch_project(g, tz, s->dpad + z * P.pair, 1, PROJ_RESID, a, st);
     // continuation schedule of this request
     const double kappa = std::pow(e->p.beta_max / s->rp.beta0, 1.0 / n_iter);

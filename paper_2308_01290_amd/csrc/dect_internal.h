@@ -133,15 +133,22 @@ struct ProjArgs {
     const double* beta_z = nullptr;              // per-slice beta (then w_reg = 2 beta_z[z])
     double* alpha = nullptr;                     // [z]
     unsigned* counter = nullptr;                 // [z]
+    // BF16 storage: res holds one 32-bit word of two BF16 values per ray
+    // (RESID, LINESEARCH); LINESEARCH also reads BF16 pair blocks
+    bool res_bf16 = false;
+    bool pad_bf16 = false;
 };
 int proj_nblocks(int nv_max, int nd_max);  // blocks per pair
-void launch_project(const Geom& g, const RayTable& t, const float2* pad, int npairs, int mode,
+// pad: float2 pair blocks, or with a.pad_bf16 one 32-bit BF16 pair per entry
+void launch_project(const Geom& g, const RayTable& t, const void* pad, int npairs, int mode,
                     const ProjArgs& a, hipStream_t st);
 
 // ---- back-projector -------------------------------------------------------------
-// sino pairs [z][nv][nd] -> out pairs [z][ny][nx] (float2) or split images.
-void launch_backproject(const Geom& g, const RayTable& t, const float2* sino, int npairs,
-                        float2* out_pairs, float* out_split, int nout, hipStream_t st);
+// sino pairs [z][nv][nd] (float2, or BF16 pairs in 32-bit words) -> out pairs
+// [z][ny][nx] (float2) or split images.
+void launch_backproject(const Geom& g, const RayTable& t, const void* sino, int npairs,
+                        float2* out_pairs, float* out_split, int nout, hipStream_t st,
+                        bool sino_bf16 = false);
 
 // ---- FBP ---------------------------------------------------------------------
 // q = filtered sinograms (scratch, [nsino][nv][nd]); img [nsino][ny][nx]
@@ -234,19 +241,23 @@ struct ImgArgs {
     float beta;
     const double* beta_z = nullptr;   // per-slice beta (overrides beta2, thr, beta)
     double lam = 0.0;
+    bool bf16 = false;   // direction pair blocks and residual / line-search sinograms in BF16
 };
 int grad_nblocks(int ny, int nx);
 void launch_init_state(const Model& M, int ny, int nx, int batch, const float* muL,
                        const float* muH, float rho_min, float2* f, float* rho, float* t,
                        hipStream_t st);
 // the search direction is written into the projector's pair blocks `dpad`
+// (float2 entries, or one 32-bit BF16 pair per entry with a.bf16)
 void launch_grad(const Model& M, const ImgArgs& a, const PadLayout& P, const float2* f,
-                 const float2* B, const float* rho, const float* t, float2* dpad,
+                 const float2* B, const float* rho, const float* t, void* dpad,
                  double* partials, hipStream_t st);
-// also steps each slice's beta: beta_z[z] *= kappa_z[z] (when beta_z is given)
+// also steps each slice's beta: beta_z[z] *= kappa_z[z] (when beta_z is given);
+// with a.bf16, dpad, S and zq hold BF16 pairs
 void launch_update(const ImgArgs& a, const PadLayout& P, const RayTable& T, const double* alpha,
-                   const float2* dpad, float2* f, float2* S, const float2* zq, double* beta_z,
+                   const void* dpad, float2* f, void* S, const void* zq, double* beta_z,
                    const double* kappa_z, hipStream_t st);
+void launch_round_state(size_t n, float2* f, float* rho, float* t, hipStream_t st);
 // beta_z[z0 .. z0+n) = beta, kappa_z[...] = kappa
 void launch_set_beta(double* beta_z, double* kappa_z, int z0, int n, double beta, double kappa,
                      hipStream_t st);

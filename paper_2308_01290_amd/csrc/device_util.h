@@ -98,6 +98,20 @@ __device__ __forceinline__ double block_sum_array(const double* a, int n, int st
     return block_sum<NT>(v, sh);
 }
 
+// BF16 storage: two values in one 32-bit word, x in the low half.  Rounding
+// to nearest, ties to even (finite inputs); widening is exact.
+__device__ __forceinline__ unsigned bf16_bits(float x) {
+    const unsigned u = __float_as_uint(x);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ unsigned bf16x2_pack(float x, float y) {
+    return bf16_bits(x) | (bf16_bits(y) << 16);
+}
+__device__ __forceinline__ float bf16_lo(unsigned w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(unsigned w) { return __uint_as_float(w & 0xffff0000u); }
+__device__ __forceinline__ float2 bf16x2_unpack(unsigned w) { return make_float2(bf16_lo(w), bf16_hi(w)); }
+__device__ __forceinline__ float bf16_round(float x) { return __uint_as_float(bf16_bits(x) << 16); }
+
 __device__ __forceinline__ int wrap(int i, int n) {
     i %= n;
     return i < 0 ? i + n : i;

@@ -95,8 +95,10 @@ __global__ __launch_bounds__(256) void k_grad(ImgArgs a, GradConst gc, PadLayout
                                               const float2* __restrict__ f,
                                               const float2* __restrict__ B,
                                               const float* __restrict__ rho,
-                                              const float* __restrict__ t, float2* __restrict__ dpad,
+                                              const float* __restrict__ t, void* __restrict__ dpad_v,
                                               double* __restrict__ partials) {
+    float2* dpad = static_cast<float2*>(dpad_v);
+    unsigned* dpad16 = static_cast<unsigned*>(dpad_v);
     __shared__ float2 fL[19][19];
     __shared__ float4 eL[18][18];
     __shared__ float2 dL[17][17];
@@ -144,14 +146,20 @@ __global__ __launch_bounds__(256) void k_grad(ImgArgs a, GradConst gc, PadLayout
         const float c2 = fmaf(gc.ms10, fp.x, gc.ms11 * fp.y) - T2;
         const float G1 = a.eta2 * bp.x + a.xi2 * fmaf(gc.ms00, c1, gc.ms10 * c2) + a.beta2 * dte1;
         const float G2 = a.eta2 * bp.y + a.xi2 * fmaf(gc.ms01, c1, gc.ms11 * c2) + a.beta2 * dte2;
-        const float2 d = make_float2(-G1, -G2);
+        // the direction as stored (rounded to BF16 in that mode): the line
+        // search and the update both use the stored value
+        const float2 d = a.bf16 ? make_float2(bf16_round(-G1), bf16_round(-G2)) : make_float2(-G1, -G2);
         dL[r][c] = d;
         if (r < 16 && c < 16 && i0 + r < ny && k0 + c < nx) {
-            gg += (double)G1 * G1 + (double)G2 * G2;
+            gg -= (double)G1 * d.x + (double)G2 * d.y;   // -<grad, d>
             const double e1 = (double)gc.ms00 * d.x + (double)gc.ms01 * d.y;
             const double e2 = (double)gc.ms10 * d.x + (double)gc.ms11 * d.y;
             cq += e1 * e1 + e2 * e2;
-            dpad[z * P.pair + (size_t)(i0 + r) * P.ldN + (k0 + c) + kPad] = d;
+            const size_t o = z * P.pair + (size_t)(i0 + r) * P.ldN + (k0 + c) + kPad;
+            if (a.bf16)
+                dpad16[o] = bf16x2_pack(d.x, d.y);
+            else
+                dpad[o] = d;
         }
     }
     __syncthreads();
@@ -163,8 +171,14 @@ __global__ __launch_bounds__(256) void k_grad(ImgArgs a, GradConst gc, PadLayout
             rr = ax * ax + ay * ay + bx * bx + by * by;
         }
         // transposed layout: row k, entries i
-        if (k0 + ty < nx && i0 + tx < ny)
-            dpad[z * P.pair + P.offT + (size_t)(k0 + ty) * P.ldT + (i0 + tx) + kPad] = dL[tx][ty];
+        if (k0 + ty < nx && i0 + tx < ny) {
+            const size_t o = z * P.pair + P.offT + (size_t)(k0 + ty) * P.ldT + (i0 + tx) + kPad;
+            const float2 d = dL[tx][ty];
+            if (a.bf16)
+                dpad16[o] = bf16x2_pack(d.x, d.y);
+            else
+                dpad[o] = d;
+        }
     }
     const int nblk = gridDim.x * gridDim.y;
     const int bid = blockIdx.y * gridDim.x + blockIdx.x;
@@ -180,7 +194,7 @@ __global__ __launch_bounds__(256) void k_grad(ImgArgs a, GradConst gc, PadLayout
 }
 
 void launch_grad(const Model& M, const ImgArgs& a, const PadLayout& P, const float2* f,
-                 const float2* B, const float* rho, const float* t, float2* dpad,
+                 const float2* B, const float* rho, const float* t, void* dpad,
                  double* partials, hipStream_t st) {
     GradConst gc;
     gc.ms00 = (float)M.Ms[0][0];
@@ -196,9 +210,10 @@ void launch_grad(const Model& M, const ImgArgs& a, const PadLayout& P, const flo
 }
 
 // ---------------------------------------------------------------------------
+template <bool BF>
 __global__ void k_update(int ny, int nx, PadLayout P, RayTable T, const double* __restrict__ alpha,
-                         const float2* __restrict__ dpad, float2* __restrict__ f,
-                         float2* __restrict__ S, const float2* __restrict__ zq,
+                         const void* __restrict__ dpad_v, float2* __restrict__ f,
+                         void* __restrict__ S_v, const void* __restrict__ zq_v,
                          double* __restrict__ beta_z, const double* __restrict__ kappa_z) {
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int z = blockIdx.y;
@@ -207,7 +222,9 @@ __global__ void k_update(int ny, int nx, PadLayout P, RayTable T, const double* 
     if (idx == 0 && beta_z) beta_z[z] *= kappa_z[z];   // continuation: the slice's next beta
     if (idx < npix) {
         const int i = (int)(idx / nx), k = (int)(idx % nx);
-        const float2 d = dpad[z * P.pair + (size_t)i * P.ldN + k + kPad];
+        const size_t o = z * P.pair + (size_t)i * P.ldN + k + kPad;
+        const float2 d = BF ? bf16x2_unpack(static_cast<const unsigned*>(dpad_v)[o])
+                            : static_cast<const float2*>(dpad_v)[o];
         float2 v = f[z * npix + idx];
         v.x = fmaf(al, d.x, v.x);
         v.y = fmaf(al, d.y, v.y);
@@ -218,20 +235,47 @@ __global__ void k_update(int ny, int nx, PadLayout P, RayTable T, const double* 
     const size_t r = idx - npix;
     if (r < (size_t)D.nv * D.nd) {
         const size_t o = (size_t)(D.sino0 + (long long)z * T.sino_zstride) + r;
-        const float2 q = zq[o];
-        float2 v = S[o];
-        v.x = fmaf(al, q.x, v.x);
-        v.y = fmaf(al, q.y, v.y);
-        S[o] = v;
+        if constexpr (BF) {
+            const float2 q = bf16x2_unpack(static_cast<const unsigned*>(zq_v)[o]);
+            unsigned* S = static_cast<unsigned*>(S_v);
+            const float2 v = bf16x2_unpack(S[o]);
+            S[o] = bf16x2_pack(fmaf(al, q.x, v.x), fmaf(al, q.y, v.y));
+        } else {
+            const float2 q = static_cast<const float2*>(zq_v)[o];
+            float2* S = static_cast<float2*>(S_v);
+            float2 v = S[o];
+            v.x = fmaf(al, q.x, v.x);
+            v.y = fmaf(al, q.y, v.y);
+            S[o] = v;
+        }
     }
 }
 
 void launch_update(const ImgArgs& a, const PadLayout& P, const RayTable& T, const double* alpha,
-                   const float2* dpad, float2* f, float2* S, const float2* zq, double* beta_z,
+                   const void* dpad, float2* f, void* S, const void* zq, double* beta_z,
                    const double* kappa_z, hipStream_t st) {
     const size_t n = (size_t)a.nx * a.ny + (size_t)T.nv_max * T.nd_max;
-    hipLaunchKernelGGL(k_update, dim3((unsigned)((n + 255) / 256), a.batch), dim3(256), 0, st, a.ny,
-                       a.nx, P, T, alpha, dpad, f, S, zq, beta_z, kappa_z);
+    if (a.bf16)
+        hipLaunchKernelGGL(k_update<true>, dim3((unsigned)((n + 255) / 256), a.batch), dim3(256), 0, st,
+                           a.ny, a.nx, P, T, alpha, dpad, f, S, zq, beta_z, kappa_z);
+    else
+        hipLaunchKernelGGL(k_update<false>, dim3((unsigned)((n + 255) / 256), a.batch), dim3(256), 0,
+                           st, a.ny, a.nx, P, T, alpha, dpad, f, S, zq, beta_z, kappa_z);
+}
+
+// state images rounded to BF16 (the values BF16 storage of f1, f2, rho_e, t' holds)
+__global__ void k_round_state(size_t n, float2* __restrict__ f, float* __restrict__ rho,
+                              float* __restrict__ t) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float2 v = f[i];
+    f[i] = make_float2(bf16_round(v.x), bf16_round(v.y));
+    rho[i] = bf16_round(rho[i]);
+    t[i] = bf16_round(t[i]);
+}
+
+void launch_round_state(size_t n, float2* f, float* rho, float* t, hipStream_t st) {
+    hipLaunchKernelGGL(k_round_state, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, f, rho, t);
 }
 
 __global__ void k_set_beta(double* beta_z, double* kappa_z, int z0, int n, double beta, double kappa) {

@@ -256,9 +256,33 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
 
 int proj_nblocks(int nv, int nd) { return ((nd + 255) / 256) * nv; }
 
-template <int MODE>
-__global__ __launch_bounds__(256) void k_project(const float2* __restrict__ pad, PadLayout P,
+// the two minor entries of one major step: float2 (f1, f2) per pixel, or one
+// 32-bit word of two BF16 values per pixel
+template <bool PB>
+__device__ __forceinline__ void load_step(const char* zb, unsigned off, float2& A, float2& B) {
+    if constexpr (PB) {
+        A = bf16x2_unpack(*reinterpret_cast<const unsigned*>(zb + off));
+        B = bf16x2_unpack(*reinterpret_cast<const unsigned*>(zb + off + 4));
+    } else {
+        A = *reinterpret_cast<const float2*>(zb + off);
+        B = *reinterpret_cast<const float2*>(zb + off + 8);
+    }
+}
+
+template <bool RB>
+__device__ __forceinline__ void store_res(float2* res, long long i, float x, float y) {
+    if constexpr (RB)
+        reinterpret_cast<unsigned*>(res)[i] = bf16x2_pack(x, y);
+    else
+        res[i] = make_float2(x, y);
+}
+
+// PB: the pair blocks hold BF16 pairs; RB: the output sinogram pairs are BF16
+template <int MODE, bool PB, bool RB>
+__global__ __launch_bounds__(256) void k_project(const void* __restrict__ pad, PadLayout P,
                                                  RayTable T, int nx, int ny, ProjArgs a) {
+    constexpr unsigned ES = PB ? 4u : 8u;   // bytes per pixel entry
+    constexpr int LS = PB ? 2 : 3;
     const int v = blockIdx.y, z = blockIdx.z;
     const SliceDesc D = T.desc[T.desc_stride * z];
     const int nd = D.nd;
@@ -283,7 +307,7 @@ __global__ __launch_bounds__(256) void k_project(const float2* __restrict__ pad,
     // step reads zeros only.  Byte offsets are 32-bit, relative to the pair block.
     const int rlo = up ? -kPad : 1 - kPad, rhi = up ? nmin : nmin + 1;
     const float wa = up ? 0.f : 1.f, wb = up ? 1.f : -1.f;   // weight of entry r': wa + wb * w0
-    const unsigned lstep = 8u * (unsigned)(xmaj ? P.ldT : P.ldN);
+    const unsigned lstep = ES * (unsigned)(xmaj ? P.ldT : P.ldN);
     int klo = sp.x, khi = sp.y;
     if (klo > khi) {
         klo = INT_MAX;
@@ -292,8 +316,8 @@ __global__ __launch_bounds__(256) void k_project(const float2* __restrict__ pad,
     const int ks = wave_min(klo), ke = wave_max(khi);
     const int k0 = ks == INT_MAX ? 0 : ks;
     long long y = fix_a0(fx) + (long long)k0 * S;
-    unsigned loff = 8u * (unsigned)((xmaj ? P.offT : 0) + kPad + (up ? 0 : -1)) + (unsigned)k0 * lstep;
-    const char* zb = reinterpret_cast<const char*>(pad + (size_t)z * P.pair);
+    unsigned loff = ES * (unsigned)((xmaj ? P.offT : 0) + kPad + (up ? 0 : -1)) + (unsigned)k0 * lstep;
+    const char* zb = reinterpret_cast<const char*>(pad) + (size_t)z * P.pair * ES;
     float s1 = 0.f, c1 = 0.f, s2 = 0.f, c2 = 0.f;
     const int nstep = ks <= ke ? ke - ks + 1 : 0;   // wave-uniform
     int k = 0;
@@ -303,9 +327,7 @@ __global__ __launch_bounds__(256) void k_project(const float2* __restrict__ pad,
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int r0 = clamp_med3((int)(y >> 32), rlo, rhi);
-            const unsigned off = loff + ((unsigned)r0 << 3);
-            A[u] = *reinterpret_cast<const float2*>(zb + off);
-            B[u] = *reinterpret_cast<const float2*>(zb + off + 8);
+            load_step<PB>(zb, loff + ((unsigned)r0 << LS), A[u], B[u]);
             W[u] = fmaf(wb, first_weight((unsigned)y, xmask, ainv32), wa);
             y += S;
             loff += lstep;
@@ -322,9 +344,8 @@ __global__ __launch_bounds__(256) void k_project(const float2* __restrict__ pad,
     }
     for (; k < nstep; ++k) {
         const int r0 = clamp_med3((int)(y >> 32), rlo, rhi);
-        const unsigned off = loff + ((unsigned)r0 << 3);
-        const float2 A = *reinterpret_cast<const float2*>(zb + off);
-        const float2 B = *reinterpret_cast<const float2*>(zb + off + 8);
+        float2 A, B;
+        load_step<PB>(zb, loff + ((unsigned)r0 << LS), A, B);
         const float W = fmaf(wb, first_weight((unsigned)y, xmask, ainv32), wa);
         kahan_add(s1, c1, fmaf(W, A.x - B.x, B.x));
         kahan_add(s2, c2, fmaf(W, A.y - B.y, B.y));
@@ -343,8 +364,8 @@ __global__ __launch_bounds__(256) void k_project(const float2* __restrict__ pad,
         if (valid) {
             const double rl = (double)a.c00 * Y1 + (double)a.c01 * Y2 - (double)a.p_lo[s0 - a.p_base + r];
             const double rh = (double)a.c10 * Y1 + (double)a.c11 * Y2 - (double)a.p_hi[s0 - a.p_base + r];
-            a.res[s0 + r] = make_float2((float)(D.eta * ((double)a.c00 * rl + (double)a.c10 * rh)),
-                                        (float)(D.eta * ((double)a.c01 * rl + (double)a.c11 * rh)));
+            store_res<RB>(a.res, s0 + r, (float)(D.eta * ((double)a.c00 * rl + (double)a.c10 * rh)),
+                          (float)(D.eta * ((double)a.c01 * rl + (double)a.c11 * rh)));
         }
     } else {   // PROJ_LINESEARCH
         __shared__ double sh[4];
@@ -352,8 +373,8 @@ __global__ __launch_bounds__(256) void k_project(const float2* __restrict__ pad,
         if (valid) {
             const double yl = (double)a.c00 * Y1 + (double)a.c01 * Y2;
             const double yh = (double)a.c10 * Y1 + (double)a.c11 * Y2;
-            a.res[s0 + r] = make_float2((float)(D.eta * ((double)a.c00 * yl + (double)a.c10 * yh)),
-                                        (float)(D.eta * ((double)a.c01 * yl + (double)a.c11 * yh)));
+            store_res<RB>(a.res, s0 + r, (float)(D.eta * ((double)a.c00 * yl + (double)a.c10 * yh)),
+                          (float)(D.eta * ((double)a.c01 * yl + (double)a.c11 * yh)));
             part = D.eta * (yl * yl + yh * yh);
         }
         // partials in the slice's own block order (the launch may cover a larger
@@ -380,17 +401,25 @@ __global__ __launch_bounds__(256) void k_project(const float2* __restrict__ pad,
     }
 }
 
-void launch_project(const Geom& g, const RayTable& t, const float2* pad, int npairs, int mode,
+void launch_project(const Geom& g, const RayTable& t, const void* pad, int npairs, int mode,
                     const ProjArgs& a, hipStream_t st) {
     dim3 grid((t.nd_max + 255) / 256, t.nv_max, npairs);
     const PadLayout P = pad_layout(g);
     if (mode == PROJ_PLAIN)
-        hipLaunchKernelGGL(k_project<PROJ_PLAIN>, grid, dim3(256), 0, st, pad, P, t, g.nx, g.ny, a);
+        hipLaunchKernelGGL((k_project<PROJ_PLAIN, false, false>), grid, dim3(256), 0, st, pad, P, t,
+                           g.nx, g.ny, a);
+    else if (mode == PROJ_RESID && a.res_bf16)
+        hipLaunchKernelGGL((k_project<PROJ_RESID, false, true>), grid, dim3(256), 0, st, pad, P, t,
+                           g.nx, g.ny, a);
     else if (mode == PROJ_RESID)
-        hipLaunchKernelGGL(k_project<PROJ_RESID>, grid, dim3(256), 0, st, pad, P, t, g.nx, g.ny, a);
+        hipLaunchKernelGGL((k_project<PROJ_RESID, false, false>), grid, dim3(256), 0, st, pad, P, t,
+                           g.nx, g.ny, a);
+    else if (a.pad_bf16)
+        hipLaunchKernelGGL((k_project<PROJ_LINESEARCH, true, true>), grid, dim3(256), 0, st, pad, P,
+                           t, g.nx, g.ny, a);
     else
-        hipLaunchKernelGGL(k_project<PROJ_LINESEARCH>, grid, dim3(256), 0, st, pad, P, t, g.nx,
-                           g.ny, a);
+        hipLaunchKernelGGL((k_project<PROJ_LINESEARCH, false, false>), grid, dim3(256), 0, st, pad,
+                           P, t, g.nx, g.ny, a);
 }
 
 // ---------------------------------------------------------------------------
@@ -406,8 +435,10 @@ void launch_project(const Geom& g, const RayTable& t, const float2* pad, int npa
 constexpr int kBpWaves = 8;
 constexpr int kBpViewChunk = 256;
 
+// SB: the sinogram pairs are BF16 (one 32-bit word per ray)
+template <bool SB>
 __global__ __launch_bounds__(kBpWaves * 64) void k_backproject(
-    const float2* __restrict__ sino, RayTable T, int nx, int ny, float dxmm,
+    const void* __restrict__ sino, RayTable T, int nx, int ny, float dxmm,
     float2* __restrict__ out_pairs, float* __restrict__ out_split, int nout) {
     __shared__ float4 vs[kBpViewChunk];
     __shared__ int4 sfix[kBpWaves][64];
@@ -425,7 +456,9 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_backproject(
     // quad centre (between pixels k0, k0 + 1 and rows i0, i0 + 1)
     const float x = ((float)k0 + 0.5f - 0.5f * (float)(nx - 1)) * dxmm;
     const float y = ((float)i0 + 0.5f - 0.5f * (float)(ny - 1)) * dxmm;
-    const float2* sz = sino + (D.sino0 + (long long)z * T.sino_zstride);
+    const long long sbase = D.sino0 + (long long)z * T.sino_zstride;
+    const float2* sz = reinterpret_cast<const float2*>(sino) + sbase;
+    const unsigned* szb = reinterpret_cast<const unsigned*>(sino) + sbase;
     // acc[di][dk]: pixel (i0 + di, k0 + dk), both channels
     float a00x = 0.f, a00y = 0.f, a01x = 0.f, a01y = 0.f;
     float a10x = 0.f, a10y = 0.f, a11x = 0.f, a11y = 0.f;
@@ -458,7 +491,7 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_backproject(
                 if (jj <= Jhi) {
                     const size_t r = (size_t)v * nd + jj;
                     const float2 fl = flt[r];
-                    const float2 sv = sz[r];
+                    const float2 sv = SB ? bf16x2_unpack(szb[r]) : sz[r];
                     sfix[w][lane] = fix[r];
                     sray[w][lane] = make_float4(fl.x, fl.y, sv.x, sv.y);
                 }
@@ -532,11 +565,16 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_backproject(
     }
 }
 
-void launch_backproject(const Geom& g, const RayTable& t, const float2* sino, int npairs,
-                        float2* out_pairs, float* out_split, int nout, hipStream_t st) {
+void launch_backproject(const Geom& g, const RayTable& t, const void* sino, int npairs,
+                        float2* out_pairs, float* out_split, int nout, hipStream_t st,
+                        bool sino_bf16) {
     dim3 grid((g.nx + 15) / 16, (g.ny + 15) / 16, npairs);
-    hipLaunchKernelGGL(k_backproject, grid, dim3(kBpWaves * 64), 0, st, sino, t, g.nx, g.ny,
-                       (float)g.dx, out_pairs, out_split, nout);
+    if (sino_bf16)
+        hipLaunchKernelGGL(k_backproject<true>, grid, dim3(kBpWaves * 64), 0, st, sino, t, g.nx, g.ny,
+                           (float)g.dx, out_pairs, out_split, nout);
+    else
+        hipLaunchKernelGGL(k_backproject<false>, grid, dim3(kBpWaves * 64), 0, st, sino, t, g.nx,
+                           g.ny, (float)g.dx, out_pairs, out_split, nout);
 }
 
 }  // namespace dect

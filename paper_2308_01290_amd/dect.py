@@ -38,7 +38,7 @@ class _Params(C.Structure):
                 ("kappa", C.c_double), ("eta", C.c_double), ("xi", C.c_double),
                 ("n_iter", C.c_int32), ("f_inner", C.c_int32), ("t_tol", C.c_double),
                 ("t_maxit", C.c_int32), ("rho_min", C.c_double), ("t_min", C.c_double),
-                ("t_precond", C.c_int32)]
+                ("t_precond", C.c_int32), ("storage", C.c_int32)]
 
 
 EXPORTS = [
@@ -56,6 +56,9 @@ EXPORTS = [
 ]
 
 DECT_EBUSY = -6
+DECT_STORAGE_FP32 = 0
+DECT_STORAGE_BF16 = 1
+DECT_STORAGE_BF16_STATE = 2
 
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:

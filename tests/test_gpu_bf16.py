@@ -1,0 +1,144 @@
+"""BF16 storage variants of the sinogram form: what changes against FP32
+storage, and the accuracy each reaches against the FP64 oracle.
+
+DECT_STORAGE_BF16 stores the projector operands (search direction, residual
+and line-search sinograms) in BF16; DECT_STORAGE_BF16_STATE also rounds the
+state images f1, f2, rho_e, t' to BF16 after every write.  BF16 keeps 8
+significant bits, so a stored value is within 2^-8 of its FP32 value
+(relative, round to nearest: the unit roundoff)."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import solve as S
+from oracle.physics import Physics
+from paper_2308_01290_amd import dect
+from tests.gpu_util import cuda, host, workload
+from tests.test_gpu_solver import phantom_body
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+U_BF16 = 2.0 ** -8   # unit roundoff of BF16 (8 significant bits, round to nearest)
+
+
+def f32(x):
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+def one_step(storage, k=3):
+    g, ph, pL, pH = workload("small")
+    phys = Physics()
+    params = S.Params(n_iter=10).resolved(phys, g)
+    st = S.init_state(f32(pL), f32(pH), g, phys, params)
+    sol = dect.Solver(g, dect.default_params(n_iter=10, storage=storage))
+    sol.set_state(cuda(pL[None]), cuda(pH[None]), *(cuda(a[None]) for a in (st.f1, st.f2, st.rho, st.t)),
+                  k=k)
+    sol.iterate(1)
+    return st, [host(a)[0] for a in sol.state()]
+
+
+def is_bf16(x):
+    b = np.asarray(x, dtype=np.float32).view(np.uint32)
+    return bool(np.all((b & 0xFFFF) == 0))
+
+
+def test_bf16_operands_change_only_the_f_step():
+    """One iteration from the same state: the rho_e and t' steps read only the
+    state, so they are bitwise those of FP32 storage; f moves by the same
+    step up to the BF16 rounding of the direction and residuals."""
+    st, (f1a, f2a, ra, ta) = one_step(dect.DECT_STORAGE_FP32)
+    _, (f1b, f2b, rb, tb) = one_step(dect.DECT_STORAGE_BF16)
+    assert np.array_equal(ra, rb) and np.array_equal(ta, tb)
+    for fa, fb, f0 in ((f1a, f1b, st.f1), (f2a, f2b, st.f2)):
+        step = np.abs(fa - f32(f0)).max()
+        assert step > 0
+        # direction entries, residuals and line-search sums each carry <= U_BF16
+        # relative rounding; the step is their product and ratio
+        assert np.abs(fb - fa).max() <= 4 * U_BF16 * step
+
+
+def test_bf16_state_rounds_the_state():
+    _, out = one_step(dect.DECT_STORAGE_BF16_STATE)
+    for a in out:
+        assert is_bf16(a)
+
+
+def test_bf16_state_set_state_stores_rounded_values():
+    g, ph, pL, pH = workload("small")
+    rng = np.random.default_rng(5)
+    imgs = [f32(1.0 + 0.1 * rng.standard_normal((g.n_y, g.n_x))) for _ in range(4)]
+    sol = dect.Solver(g, dect.default_params(n_iter=4, storage=dect.DECT_STORAGE_BF16_STATE))
+    sol.set_state(cuda(pL[None]), cuda(pH[None]), *(cuda(a[None]) for a in imgs), k=0)
+    for a, ref in zip((host(x)[0] for x in sol.state()), imgs):
+        assert is_bf16(a)
+        assert np.abs(a - ref).max() <= U_BF16 * np.abs(ref).max()
+
+
+def test_bf16_batch_equals_single():
+    """Per-slice results do not depend on the batch in BF16 storage either."""
+    g, ph, pL, pH = workload("small")
+    p = dect.default_params(n_iter=3, storage=dect.DECT_STORAGE_BF16)
+    Zb, Rb = (host(x) for x in dect.solve(cuda(np.stack([pL, 0.9 * pL])), cuda(np.stack([pH, 0.9 * pH])), g, p))
+    Z1, R1 = (host(x) for x in dect.solve(cuda(pL[None]), cuda(pH[None]), g, p))
+    assert np.array_equal(Zb[0], Z1[0]) and np.array_equal(Rb[0], R1[0])
+
+
+def accuracy(Z, R, Zr, Rr, ph, g):
+    """Pointwise figures on the eroded body (as the FP32 end-to-end check) and
+    the worst per-insert mean errors."""
+    from scipy.ndimage import binary_erosion
+    lab, body = phantom_body(ph, g)
+    mz = body & (Zr >= 2) & (Z >= 2)
+    dz = np.abs(Z - Zr)[mz]
+    dr = (np.abs(R - Rr) / np.abs(Rr))[body]
+    mean_dz = mean_dr = 0.0
+    for idx in range(1, lab.shape[0]):
+        mm = binary_erosion(lab[idx] > 0.999, iterations=2)
+        if mm.sum() < 4:
+            continue
+        mean_dz = max(mean_dz, abs(Z[mm].mean() - Zr[mm].mean()))
+        mean_dr = max(mean_dr, abs(R[mm].mean() - Rr[mm].mean()) / abs(Rr[mm].mean()))
+    return {"max_dz": dz.max(), "p99_dz": np.quantile(dz, 0.99), "max_drho": dr.max(),
+            "p99_drho": np.quantile(dr, 0.99), "frac_drho_gt_1e-3": float((dr > 1e-3).mean()),
+            "insert_mean_dz": mean_dz, "insert_mean_drho": mean_dr}
+
+
+def report(tag, a):
+    print(tag + ": " + ", ".join(f"{k}={v:.3g}" for k, v in a.items()))
+
+
+# The benchmark spec's tolerances (|dZ| <= 0.02, rel rho_e <= 1e-3) are met by BF16
+# operand storage on each insert's mean; pointwise a few per cent of pixels
+# exceed them (the residuals lose bits the converged iterate depends on), and
+# BF16 state storage exceeds them almost everywhere (an update below half a
+# BF16 ulp of the iterate is rounded away, so the iteration stalls near its
+# start).  These tests pin the first statement and record the figures.
+TOL_Z, TOL_RHO = 0.02, 1e-3
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+def test_bf16_small_against_oracle(storage):
+    g, ph, pL, pH = workload("small")
+    Zr, Rr = S.solve(f32(pL), f32(pH), g, Physics(), S.Params(n_iter=10))
+    Z, R = (host(x)[0] for x in dect.solve(cuda(pL[None]), cuda(pH[None]), g,
+                                           dect.default_params(n_iter=10, storage=storage)))
+    a = accuracy(Z, R, Zr, Rr, ph, g)
+    report(f"storage={storage} small K=10", a)
+    assert np.isfinite(Z).all() and np.isfinite(R).all()
+    if storage == dect.DECT_STORAGE_BF16:
+        assert a["insert_mean_dz"] <= TOL_Z and a["insert_mean_drho"] <= TOL_RHO
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+def test_bf16_slice512_against_stored_oracle(storage):
+    gold = np.load(os.path.join(HERE, "golden", "slice512_K50.npz"))
+    g, ph, pL, pH = workload("slice512")
+    Z, R = (host(x)[0] for x in dect.solve(cuda(pL[None]), cuda(pH[None]), g,
+                                           dect.default_params(n_iter=50, storage=storage)))
+    a = accuracy(Z, R, gold["Z"].astype(np.float64), gold["rho"].astype(np.float64), ph, g)
+    report(f"storage={storage} slice512 K=50", a)
+    assert np.isfinite(Z).all() and np.isfinite(R).all()
+    if storage == dect.DECT_STORAGE_BF16:
+        assert a["insert_mean_dz"] <= TOL_Z and a["insert_mean_drho"] <= TOL_RHO

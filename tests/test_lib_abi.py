@@ -42,6 +42,7 @@ def test_default_params():
     assert p.lambda_ == 0.01 and p.beta_max == 1e5 and p.f_inner == 1
     assert p.t_tol == 1e-7 and p.t_maxit == 200 and p.rho_min == 0.1
     assert p.t_precond == 0   # DECT_PRECOND_AUTO
+    assert p.storage == dect.DECT_STORAGE_FP32
 
 
 def test_geometry_resolution_matches_corner_pitch():
@@ -116,6 +117,12 @@ def test_entry_points_reject_bad_arguments_before_enqueueing():
     assert L.dect_engine_create(128, 128, 1.0, 0, 180, 256, C.byref(p), None, 0, None, C.byref(eh)) == -1
     assert L.dect_engine_workspace_bytes(128, 128, 1.0, 4, 180, 256, C.byref(p)) > \
         L.dect_engine_workspace_bytes(128, 128, 1.0, 2, 180, 256, C.byref(p)) > 0
+    # storage selector: out of range; BF16 needs the projector (sinogram form)
+    p = dect.default_params(storage=3)
+    assert L.dect_solver_create(C.byref(g), C.byref(p), 1, None, 0, None, C.byref(h)) == -1
+    assert b"storage" in L.dect_last_error()
+    p = dect.default_params(storage=dect.DECT_STORAGE_BF16)
+    assert L.dect_image_solver_create(128, 128, C.byref(p), 1, None, 0, None, C.byref(h)) == -5
     # image-domain form: sizes, params and NULL arrays are checked on the host
     p = dect.default_params()
     assert L.dect_image_solver_create(100, 128, C.byref(p), 1, None, 0, None, C.byref(h)) == -1
@@ -131,6 +138,17 @@ def test_entry_points_reject_bad_arguments_before_enqueueing():
     assert L.dect_l0_step(None, None, None, None, None, 16, 16, 1, 0.1, 1.0, 1e-6, 10, None, 0, None) == -1
     assert L.dect_l0_step(C.c_void_p(1), None, C.c_void_p(1), None, None, 10, 16, 1, 0.1, 1.0, 1e-6,
                           10, None, 0, None) == -1
+
+
+def test_bf16_storage_workspace():
+    """BF16 storage adds the direction's BF16 pair blocks: about 4 bytes per
+    padded entry, a small fraction of the FP32 workspace."""
+    L = dect.lib()
+    g = dect.Geometry.of(P.geometry_slice512()).c()
+    a = L.dect_solve_workspace_bytes(C.byref(g), C.byref(dect.default_params()), 2)
+    b = L.dect_solve_workspace_bytes(C.byref(g), C.byref(dect.default_params(storage=1)), 2)
+    pad = 2 * 512 * (512 + 4)   # two padded layouts per image
+    assert 2 * pad * 4 <= b - a <= 2 * pad * 4 + 512
 
 
 def test_image_workspace_sizes():
