@@ -247,7 +247,11 @@ __global__ __launch_bounds__(256) void k_fft_cols(FftPlan P, int nx, int cols, F
     float2* tw = sm2 + (size_t)2 * ny * cols;
     float* lamy = reinterpret_cast<float*>(tw + ny);
     float* lamx = lamy + ny;
-    const int c0 = blockIdx.x * cols, z = blockIdx.y;
+    // workgroups go round-robin to the 8 XCDs; give each XCD a contiguous run
+    // of columns so that the row segments it reads share L2 lines
+    const int nbx = gridDim.x;
+    const int bx = (nbx & 7) == 0 ? (blockIdx.x & 7) * (nbx >> 3) + (blockIdx.x >> 3) : blockIdx.x;
+    const int c0 = bx * cols, z = blockIdx.y;
     slice_beta_thr(a, z);
     if (skip_slice(a, z)) return;
     const size_t npix = (size_t)nx * ny;
@@ -323,10 +327,12 @@ size_t fft_scratch_bytes(int ny, int nx, int batch) {
     return (size_t)batch * ny * nx * sizeof(float2);
 }
 
-static int cols_for(int ny) {
-    // two ping-pong buffers of ny*cols complex values within 64 KiB of LDS
+static int cols_for(int ny, int nx, int batch) {
+    // two ping-pong buffers of ny*cols complex values within 64 KiB of LDS, and
+    // at least 256 workgroups (one per CU) where the image allows
     int cols = 8;
     while (cols > 1 && (size_t)2 * ny * cols * sizeof(float2) + ny * 16 > 64 * 1024) cols /= 2;
+    while (cols > 2 && ((nx + cols - 1) / cols) * batch < 256) cols /= 2;
     return cols;
 }
 
@@ -337,7 +343,7 @@ void launch_fft_solve(int ny, int nx, int batch, const FftArgs& a, float2* scrat
     make_plan(ny, &py);
     const size_t lds_row = (size_t)3 * nx * sizeof(float2) + (size_t)3 * nx * sizeof(float);
     hipLaunchKernelGGL(k_fft_rows_fwd, dim3(ny, batch), dim3(256), lds_row, st, px, ny, a, scratch);
-    const int cols = cols_for(ny);
+    const int cols = cols_for(ny, nx, batch);
     const size_t lds_col = (size_t)2 * ny * cols * sizeof(float2) + ny * sizeof(float2) +
                            (size_t)ny * sizeof(float) + (size_t)cols * sizeof(float);
     hipLaunchKernelGGL(k_fft_cols, dim3((nx + cols - 1) / cols, batch), dim3(256), lds_col, st, py, nx,
