@@ -502,21 +502,31 @@ __global__ __launch_bounds__(256) void k_pcg_matvec(PcgArgs a, int it) {
     float* pout = (cur ? a.p1 : a.p0) + zo;
     const float* pin = (cur ? a.p0 : a.p1) + zo;
     const float* zz = a.z + zo;
-    double pq = 0.0;
+    // all pixels' loads are issued before any result is used (the loop is
+    // unrolled; out-of-range pixels read pixel 0 and are not stored)
+    float pv[kPcgPix][5], wv[kPcgPix];
+#pragma unroll
     for (int s = 0; s < kPcgPix; ++s) {
-        const int p = blockIdx.x * kPcgBlock + s * 256 + threadIdx.x;
-        if (p >= npix) break;
+        int p = blockIdx.x * kPcgBlock + s * 256 + threadIdx.x;
+        p = p < npix ? p : 0;
         const int i = p / nx, k = p % nx;
         const int ip = (i + 1 == ny) ? 0 : i + 1, im = (i == 0) ? ny - 1 : i - 1;
         const int kp = (k + 1 == nx) ? 0 : k + 1, km = (k == 0) ? nx - 1 : k - 1;
         const int nb[5] = {i * nx + k, i * nx + kp, i * nx + km, ip * nx + k, im * nx + k};
-        float v[5];
 #pragma unroll
-        for (int q = 0; q < 5; ++q) v[q] = it == 0 ? zz[nb[q]] : fmaf(bcg, pin[nb[q]], zz[nb[q]]);
-        pout[p] = v[0];
-        const float qv = fmaf(a.w2[zo + p], v[0], a.beta * (4.f * v[0] - v[1] - v[2] - v[3] - v[4]));
+        for (int q = 0; q < 5; ++q) pv[s][q] = it == 0 ? zz[nb[q]] : fmaf(bcg, pin[nb[q]], zz[nb[q]]);
+        wv[s] = a.w2[zo + p];
+    }
+    double pq = 0.0;
+#pragma unroll
+    for (int s = 0; s < kPcgPix; ++s) {
+        const int p = blockIdx.x * kPcgBlock + s * 256 + threadIdx.x;
+        if (p >= npix) continue;
+        const float* u = pv[s];
+        pout[p] = u[0];
+        const float qv = fmaf(wv[s], u[0], a.beta * (4.f * u[0] - u[1] - u[2] - u[3] - u[4]));
         a.q[zo + p] = qv;
-        pq += (double)v[0] * qv;
+        pq += (double)u[0] * qv;
     }
     const double s_pq = block_sum<256>(pq, sh);
     if (threadIdx.x == 0) P[a.L.pq + blockIdx.x] = s_pq;
@@ -545,12 +555,23 @@ __global__ __launch_bounds__(256) void k_pcg_update(PcgArgs a, int it) {
     const float al = v[1] > 0.0 ? (float)(v[0] / v[1]) : 0.f;
     const size_t zo = (size_t)z * npix;
     const float* pd = (cur ? a.p1 : a.p0) + zo;
+    float xv[kPcgPix], pv[kPcgPix], qv[kPcgPix], rv[kPcgPix];
+#pragma unroll
+    for (int s = 0; s < kPcgPix; ++s) {   // loads first (see k_pcg_matvec)
+        int p = blockIdx.x * kPcgBlock + s * 256 + threadIdx.x;
+        p = p < npix ? p : 0;
+        xv[s] = a.x[zo + p];
+        pv[s] = pd[p];
+        qv[s] = a.q[zo + p];
+        rv[s] = a.r[zo + p];
+    }
     double rzn = 0.0, rr = 0.0;
+#pragma unroll
     for (int s = 0; s < kPcgPix; ++s) {
         const int p = blockIdx.x * kPcgBlock + s * 256 + threadIdx.x;
-        if (p >= npix) break;
-        a.x[zo + p] = fmaf(al, pd[p], a.x[zo + p]);
-        const float r = fmaf(-al, a.q[zo + p], a.r[zo + p]);
+        if (p >= npix) continue;
+        a.x[zo + p] = fmaf(al, pv[s], xv[s]);
+        const float r = fmaf(-al, qv[s], rv[s]);
         a.r[zo + p] = r;
         rr += (double)r * r;
         if (a.prec == PREC_JACOBI) {

@@ -504,7 +504,7 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_backproject(
                     const long long S = fix_s(fx);
                     const bool up = S >= 0;
                     const int maj0 = xm ? k0 : i0, mnr0 = xm ? i0 : k0;
-                    const long long ya = fix_a0(fx) + (long long)maj0 * S;
+                    const long long ya = fix_a0(fx) + (long long)(unsigned)maj0 * S;
                     const long long yb = ya + S;
                     const unsigned xmask = up ? ~0u : 0u;
                     const float wa = first_weight((unsigned)ya, xmask, fs.x);
