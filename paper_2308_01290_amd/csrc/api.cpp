@@ -203,9 +203,11 @@ static bool same_geom(const Geom& a, const Geom& b) {
            a.sid == b.sid && a.sdd == b.sdd;
 }
 
+// the layout ray_table_bytes(g) sizes: table_views(g) views (a quarter of
+// them for quarter-turn symmetric geometries)
 static void carve_table(const Geom& g, void* mem, RayTable* t) {
     char* p = static_cast<char*>(mem);
-    const size_t nr = (size_t)g.nv * g.nd;
+    const size_t nr = (size_t)table_views(g) * g.nd;
     t->fix = reinterpret_cast<int4*>(p);
     p += nr * sizeof(int4);
     t->flt = reinterpret_cast<float2*>(p);
@@ -432,6 +434,8 @@ struct BatchGeo {
     size_t rays = 0, views = 0;
     long long sino_total = 0;
     int nv_max = 0, nd_max = 0;
+    bool rev = false;   // pair blocks carry the reversed layouts (some slice may be quarter-turn symmetric)
+    int sym_mode = 0;   // back-projection: 0 no slice symmetric, 1 all, 2 mixed
 };
 
 // dedupe = false: every slice gets a table of its own (slots that change
@@ -459,8 +463,10 @@ static int make_batch(const dect_geometry* gin, int batch, BatchGeo* B, bool ded
             B->distinct.push_back(a);
             B->ray0.push_back((int)B->rays);
             B->view0.push_back((int)B->views);
-            B->rays += (size_t)a.nv * a.nd;
-            B->views += (size_t)a.nv;
+            // slots (no dedupe) reserve the full table: a later geometry may lack the symmetry
+            const int tv = dedupe ? table_views(a) : a.nv;
+            B->rays += (size_t)tv * a.nd;
+            B->views += (size_t)tv;
         }
         B->uniq[z] = u;
         B->sino0[z] = B->sino_total;
@@ -469,6 +475,15 @@ static int make_batch(const dect_geometry* gin, int batch, BatchGeo* B, bool ded
         B->nd_max = std::max(B->nd_max, a.nd);
     }
     if (B->rays > (size_t)INT32_MAX) return fail(DECT_EINVAL, "batch ray tables exceed 2^31 rays");
+    int nsym = 0;
+    for (const Geom& a : B->g) nsym += sym4(a) ? 1 : 0;
+    if (!dedupe) {   // slots: any admitted geometry may be symmetric
+        B->rev = grid_sym4(B->g[0]);
+        B->sym_mode = B->rev ? 2 : 0;
+    } else {
+        B->rev = nsym > 0;
+        B->sym_mode = nsym == 0 ? 0 : (nsym == batch ? 1 : 2);
+    }
     return DECT_OK;
 }
 
@@ -595,14 +610,15 @@ int dect_project(const dect_geometry* gin, const float* img, float* sino, int32_
     RayTable t;
     if (int rc = get_table(g, st, &t)) return rc;
     const int np = (batch + 1) / 2;
+    const PadLayout P = pad_layout(g, sym4(g));
     TempBuf tmp;
-    if (int rc = temp_alloc(&tmp, pad_elems(g) * np * sizeof(float2), st)) return rc;
+    if (int rc = temp_alloc(&tmp, P.pair * np * sizeof(float2), st)) return rc;
     float2* pad = static_cast<float2*>(tmp.p);
-    launch_pack_pairs(g, img, batch, pad, st);
+    launch_pack_pairs(g, P, img, batch, pad, st);
     ProjArgs a;
     a.out = sino;
     a.nout = batch;
-    launch_project(g, t, pad, np, PROJ_PLAIN, a, st);
+    launch_project(g, P, t, pad, np, PROJ_PLAIN, a, st);
     DECT_HIP(hipGetLastError());
     return DECT_OK;
 }
@@ -622,7 +638,7 @@ int dect_backproject(const dect_geometry* gin, const float* sino, float* img, in
     if (int rc = temp_alloc(&tmp, nray * np * sizeof(float2), st)) return rc;
     float2* sp = static_cast<float2*>(tmp.p);
     launch_pair_sinos(g, sino, batch, sp, st);
-    launch_backproject(g, t, sp, np, nullptr, img, batch, st);
+    launch_backproject(g, t, sp, np, nullptr, img, batch, st, false, sym4(g) ? 1 : 0);
     DECT_HIP(hipGetLastError());
     return DECT_OK;
 }
@@ -718,7 +734,7 @@ static size_t solver_layout(const BatchGeo& B, char* base, dect_solver* s, int s
     SliceDesc* desc = c.take<SliceDesc>((size_t)batch);
     float2* f = c.take<float2>(npix);
     float2* Bimg = c.take<float2>(npix);
-    float2* dpad = c.take<float2>(pad_elems(g) * batch);
+    float2* dpad = c.take<float2>(pad_elems(g, B.rev) * batch);
     float2* S = c.take<float2>(nsino);
     float2* zq = c.take<float2>(nsino);   // also the FBP filter scratch at init
     float2* fft = c.take<float2>(npix);
@@ -730,7 +746,8 @@ static size_t solver_layout(const BatchGeo& B, char* base, dect_solver* s, int s
     double* beta_d = c.take<double>((size_t)batch);
     double* kappa_d = c.take<double>((size_t)batch);
     unsigned* cnt = c.take<unsigned>((size_t)batch);
-    unsigned* dpad16 = storage != DECT_STORAGE_FP32 ? c.take<unsigned>(pad_elems(g) * batch) : nullptr;
+    unsigned* dpad16 =
+        storage != DECT_STORAGE_FP32 ? c.take<unsigned>(pad_elems(g, B.rev) * batch) : nullptr;
     PcgBufs pb;
     carve_pcg(c, g.ny, g.nx, batch, &pb);
     if (s) {
@@ -829,9 +846,10 @@ static int solver_create(const dect_geometry* geoms, const dect_params* p, int32
     }
     // zero borders of the padded direction layouts, counters and scalars once
     hipError_t e = hipSuccess;
-    e = e != hipSuccess ? e : hipMemsetAsync(s->dpad, 0, pad_elems(g) * batch * sizeof(float2), st);
+    e = e != hipSuccess ? e : hipMemsetAsync(s->dpad, 0, pad_elems(g, B.rev) * batch * sizeof(float2), st);
     if (s->dpad16)
-        e = e != hipSuccess ? e : hipMemsetAsync(s->dpad16, 0, pad_elems(g) * batch * sizeof(unsigned), st);
+        e = e != hipSuccess ? e
+                            : hipMemsetAsync(s->dpad16, 0, pad_elems(g, B.rev) * batch * sizeof(unsigned), st);
     e = e != hipSuccess ? e : hipMemsetAsync(s->cnt_proj, 0, sizeof(unsigned) * batch, st);
     e = e != hipSuccess ? e : hipMemsetAsync(s->pcg.st, 0, sizeof(PcgState) * batch, st);
     e = e != hipSuccess ? e
@@ -890,8 +908,11 @@ int dect_solver_destroy(dect_solver* s) {
     return DECT_OK;
 }
 
+static PadLayout solver_pad(const dect_solver* s) { return pad_layout(s->g, s->geo.rev); }
+
 static void project_residual(dect_solver* s, const float* lo, const float* hi) {
-    launch_pack_f2(s->g, s->f, s->batch, s->dpad, s->st);
+    const PadLayout P = solver_pad(s);
+    launch_pack_f2(s->g, P, s->f, s->batch, s->dpad, s->st);
     ProjArgs a;
     a.p_lo = lo;
     a.p_hi = hi;
@@ -901,7 +922,7 @@ static void project_residual(dect_solver* s, const float* lo, const float* hi) {
     a.c10 = (float)s->M.C[1][0];
     a.c11 = (float)s->M.C[1][1];
     a.res_bf16 = s->storage != DECT_STORAGE_FP32;
-    launch_project(s->g, s->tab, s->dpad, s->batch, PROJ_RESID, a, s->st);
+    launch_project(s->g, P, s->tab, s->dpad, s->batch, PROJ_RESID, a, s->st);
 }
 
 // BF16 state storage: the state images hold BF16 values from here on
@@ -1076,9 +1097,10 @@ static int one_iteration(dect_solver* s) {
     void* dir = a.bf16 ? static_cast<void*>(s->dpad16) : static_cast<void*>(s->dpad);
     // f-step: A^T of the combined residuals, gradient, A of the direction
     hipEvent_t t0 = mark(s);
-    launch_backproject(g, s->tab, s->S, s->batch, s->B, nullptr, 0, s->st, a.bf16);
+    launch_backproject(g, s->tab, s->S, s->batch, s->B, nullptr, 0, s->st, a.bf16, s->geo.sym_mode);
     mark_end(s, t0, s->ev_bp);
-    launch_grad(s->M, a, pad_layout(g), s->f, s->B, s->rho, s->t, dir, s->part_img, s->st);
+    const PadLayout P = solver_pad(s);
+    launch_grad(s->M, a, P, s->f, s->B, s->rho, s->t, dir, s->part_img, s->st);
     ProjArgs pa;
     pa.res = s->zq;
     pa.c00 = (float)s->M.C[0][0];
@@ -1096,12 +1118,12 @@ static int one_iteration(dect_solver* s) {
     pa.counter = s->cnt_proj;
     pa.pad_bf16 = pa.res_bf16 = a.bf16;
     hipEvent_t t1 = mark(s);
-    launch_project(g, s->tab, dir, s->batch, PROJ_LINESEARCH, pa, s->st);
+    launch_project(g, P, s->tab, dir, s->batch, PROJ_LINESEARCH, pa, s->st);
     mark_end(s, t1, s->ev_fp);
     rho_step(s);
     if (int rc = t_step(s)) return rc;
     // f^(k+1), residual sinograms
-    launch_update(a, pad_layout(g), s->tab, s->alpha, dir, s->f, s->S, s->zq, s->beta_d,
+    launch_update(a, P, s->tab, s->alpha, dir, s->f, s->S, s->zq, s->beta_d,
                   s->kappa_d, s->st);
     round_state(s, 0, s->batch);
     s->beta *= R.kappa;
@@ -1503,8 +1525,8 @@ int dect_engine_admit(dect_engine* e, const dect_geometry* gin, const float* lo,
                       (float)s->rp.p.rho_min, s->f + z * npix, s->rho + z * npix, s->t + z * npix, st);
     round_state(s, z, 1);
     // residual sinograms of the start
-    const PadLayout P = pad_layout(g);
-    launch_pack_f2(g, s->f + z * npix, 1, s->dpad + z * P.pair, st);
+    const PadLayout P = solver_pad(s);
+    launch_pack_f2(g, P, s->f + z * npix, 1, s->dpad + z * P.pair, st);
     RayTable tz = s->tab;
     tz.desc = s->tab.desc + z;
     tz.desc_stride = 0;
@@ -1521,7 +1543,7 @@ int dect_engine_admit(dect_engine* e, const dect_geometry* gin, const float* lo,
     a.c10 = (float)s->M.C[1][0];
     a.c11 = (float)s->M.C[1][1];
     a.res_bf16 = s->storage != DECT_STORAGE_FP32;
-    launch_project(g, tz, s->dpad + z * P.pair, 1, PROJ_RESID, a, st);
+    launch_project(g, P, tz, s->dpad + z * P.pair, 1, PROJ_RESID, a, st);
     // continuation schedule of this request
     const double kappa = std::pow(e->p.beta_max / s->rp.beta0, 1.0 / n_iter);
     launch_set_beta(s->beta_d, s->kappa_d, z, 1, s->rp.beta0, kappa, st);

@@ -28,6 +28,20 @@ struct Geom {
 };
 int resolve_geometry(const dect_geometry* in, Geom* out);
 
+// Quarter-turn symmetry: on a square grid whose side is a multiple of 32,
+// with a multiple of 4 views over a full circle, view v + nv/4 is view v
+// turned by 90 degrees about the centre, which maps pixel (i, k) to
+// (k, n - 1 - i).  The projector is then defined from the first quarter of
+// the views: ray (v + r nv/4, j) takes the weights of ray (v, j) on the pixels
+// turned r times.  Its table holds the first nv/4 views only, and the
+// back-projector evaluates each weight once for four views.
+inline bool sym4(const Geom& g) {
+    const double two_pi = 6.283185307179586;
+    return g.nx == g.ny && g.nx % 32 == 0 && g.nv >= 4 && g.nv % 4 == 0 &&
+           g.arc > two_pi * (1.0 - 1e-12) && g.arc < two_pi * (1.0 + 1e-12);
+}
+inline int table_views(const Geom& g) { return sym4(g) ? g.nv / 4 : g.nv; }
+
 // Per-ray traversal table, built on the device in FP64.
 // For ray (v, j) the ray is parametrised along its major axis (the pixel
 // axis it advances along by at most one minor pixel per step).  Coordinates
@@ -43,6 +57,7 @@ int resolve_geometry(const dect_geometry* in, Geom* out);
 //                    (inclusive, one step of margin; k_lo > k_hi: none);
 //   view[v]        = {cos, sin, h*(|cos| + |sin|), 0} for the voxel-driven
 //                    footprint (h = half pixel, mm).
+// With quarter-turn symmetry (sym4) the table holds views 0 .. nv/4 - 1.
 //
 // A batch may hold slices of different fan geometry (same image grid): the
 // tables of its distinct geometries sit back to back, and a per-slice
@@ -54,6 +69,7 @@ struct SliceDesc {
     float sid, sdd;        // source-isocentre, source-detector distance (mm)
     float u0, inv_pitch;   // detector coordinate of bin 0 (mm), 1 / bin pitch
     double eta;            // projection-data weight of eq. (10) for this geometry
+    int sym;               // quarter-turn symmetric (table of nv / 4 views)
 };
 struct RayTable {
     int4* fix = nullptr;
@@ -82,31 +98,44 @@ void launch_build_ray_table(const Geom& g, RayTable t, hipStream_t st);
 // minor coordinate is clamped into [-kPad, n + kPad) reads zeros only, and
 // zero lines past the last row (padN) or column (padT) of a non-square
 // image, so that every ray of a wavefront can step over the wavefront's
-// common major range.
+// common major range.  For quarter-turn symmetric projection (square image)
+// two more layouts follow, with every line's entries in reverse order:
+//   padNR: [n][n + 2*kPad], entry e of row i = image(i, n - 1 - e)
+//   padTR: [n][n + 2*kPad], entry e of column k = image(n - 1 - e, k)
 constexpr int kPad = 2;
 struct PadLayout {
     int ldN, ldT;     // line strides (elements) of padN and padT
     int lines;        // lines of each layout, max(nx, ny)
     size_t offT;      // offset of padT within a pair block
+    size_t offNR, offTR;   // offsets of padNR, padTR (rev only)
+    bool rev;
     size_t pair;      // elements per pair block
 };
-inline PadLayout pad_layout(const Geom& g) {
+inline bool grid_sym4(const Geom& g) { return g.nx == g.ny && g.nx % 32 == 0; }
+// rev: with the reversed layouts (needs a square grid, side a multiple of 32)
+inline PadLayout pad_layout(const Geom& g, bool rev = false) {
     PadLayout L;
     L.ldN = g.nx + 2 * kPad;
     L.ldT = g.ny + 2 * kPad;
     L.lines = g.nx > g.ny ? g.nx : g.ny;
     L.offT = (size_t)L.lines * L.ldN;
-    L.pair = L.offT + (size_t)L.lines * L.ldT;
+    L.rev = rev && grid_sym4(g);
+    L.offNR = L.offT + (size_t)L.lines * L.ldT;
+    L.offTR = L.offNR + (L.rev ? (size_t)L.lines * L.ldN : 0);
+    L.pair = L.offTR + (L.rev ? (size_t)L.lines * L.ldT : 0);
+    if (!L.rev) L.offNR = L.offTR = 0;
     return L;
 }
-inline size_t pad_elems(const Geom& g) { return pad_layout(g).pair; }
+inline size_t pad_elems(const Geom& g, bool rev = false) { return pad_layout(g, rev).pair; }
 
 // pack img[2z], img[2z+1] ([ny][nx] each, f32) into pair blocks z of `pad`
 // (every element of the blocks is written, the zero entries included);
 // nimg = number of source images (odd: the last pair's second channel is 0).
-void launch_pack_pairs(const Geom& g, const float* img, int nimg, float2* pad, hipStream_t st);
+void launch_pack_pairs(const Geom& g, const PadLayout& P, const float* img, int nimg, float2* pad,
+                       hipStream_t st);
 // pack a float2 image [ny][nx] (pairs) into pair blocks
-void launch_pack_f2(const Geom& g, const float2* src, int npairs, float2* pad, hipStream_t st);
+void launch_pack_f2(const Geom& g, const PadLayout& P, const float2* src, int npairs, float2* pad,
+                    hipStream_t st);
 // interleave sinograms s[2z], s[2z+1] into pairs (second channel 0 if missing)
 void launch_pair_sinos(const Geom& g, const float* sino, int nsino, float2* out, hipStream_t st);
 
@@ -140,15 +169,17 @@ struct ProjArgs {
 };
 int proj_nblocks(int nv_max, int nd_max);  // blocks per pair
 // pad: float2 pair blocks, or with a.pad_bf16 one 32-bit BF16 pair per entry
-void launch_project(const Geom& g, const RayTable& t, const void* pad, int npairs, int mode,
-                    const ProjArgs& a, hipStream_t st);
+void launch_project(const Geom& g, const PadLayout& P, const RayTable& t, const void* pad, int npairs,
+                    int mode, const ProjArgs& a, hipStream_t st);
 
 // ---- back-projector -------------------------------------------------------------
 // sino pairs [z][nv][nd] (float2, or BF16 pairs in 32-bit words) -> out pairs
 // [z][ny][nx] (float2) or split images.
+// sym_mode: 0 = no slice is quarter-turn symmetric, 1 = all are, 2 = mixed
+// (two launches, each skipping the other kind of slice)
 void launch_backproject(const Geom& g, const RayTable& t, const void* sino, int npairs,
                         float2* out_pairs, float* out_split, int nout, hipStream_t st,
-                        bool sino_bf16 = false);
+                        bool sino_bf16 = false, int sym_mode = 0);
 
 // ---- FBP ---------------------------------------------------------------------
 // q = filtered sinograms (scratch, [nsino][nv][nd]); img [nsino][ny][nx]

@@ -156,10 +156,16 @@ __global__ __launch_bounds__(256) void k_grad(ImgArgs a, GradConst gc, PadLayout
             const double e2 = (double)gc.ms10 * d.x + (double)gc.ms11 * d.y;
             cq += e1 * e1 + e2 * e2;
             const size_t o = z * P.pair + (size_t)(i0 + r) * P.ldN + (k0 + c) + kPad;
-            if (a.bf16)
-                dpad16[o] = bf16x2_pack(d.x, d.y);
-            else
+            // reversed row (quarter-turn symmetric projection)
+            const size_t orv = z * P.pair + P.offNR + (size_t)(i0 + r) * P.ldN + (nx - 1 - (k0 + c)) + kPad;
+            if (a.bf16) {
+                const unsigned pk = bf16x2_pack(d.x, d.y);
+                dpad16[o] = pk;
+                if (P.rev) dpad16[orv] = pk;
+            } else {
                 dpad[o] = d;
+                if (P.rev) dpad[orv] = d;
+            }
         }
     }
     __syncthreads();
@@ -173,11 +179,16 @@ __global__ __launch_bounds__(256) void k_grad(ImgArgs a, GradConst gc, PadLayout
         // transposed layout: row k, entries i
         if (k0 + ty < nx && i0 + tx < ny) {
             const size_t o = z * P.pair + P.offT + (size_t)(k0 + ty) * P.ldT + (i0 + tx) + kPad;
+            const size_t orv = z * P.pair + P.offTR + (size_t)(k0 + ty) * P.ldT + (ny - 1 - (i0 + tx)) + kPad;
             const float2 d = dL[tx][ty];
-            if (a.bf16)
-                dpad16[o] = bf16x2_pack(d.x, d.y);
-            else
+            if (a.bf16) {
+                const unsigned pk = bf16x2_pack(d.x, d.y);
+                dpad16[o] = pk;
+                if (P.rev) dpad16[orv] = pk;
+            } else {
                 dpad[o] = d;
+                if (P.rev) dpad[orv] = d;
+            }
         }
     }
     const int nblk = gridDim.x * gridDim.y;

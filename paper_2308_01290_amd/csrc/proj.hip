@@ -19,8 +19,8 @@
 namespace dect {
 
 size_t ray_table_bytes(const Geom& g) {
-    const size_t nr = (size_t)g.nv * g.nd;
-    return nr * (sizeof(int4) + sizeof(float2) + sizeof(int2)) + (size_t)g.nv * sizeof(float4);
+    const size_t nr = (size_t)table_views(g) * g.nd;
+    return nr * (sizeof(int4) + sizeof(float2) + sizeof(int2)) + (size_t)table_views(g) * sizeof(float4);
 }
 
 __device__ __forceinline__ long long fix_a0(int4 f) {
@@ -124,6 +124,7 @@ SliceDesc make_slice_desc(const Geom& g, int ray0, int view0, long long sino0, d
     d.u0 = (float)(-0.5 * (g.nd - 1) * g.pitch + g.offset);
     d.inv_pitch = (float)(1.0 / g.pitch);
     d.eta = eta;
+    d.sym = sym4(g) ? 1 : 0;
     return d;
 }
 
@@ -139,7 +140,7 @@ void launch_set_int(int* p, int value, hipStream_t st) {
 }
 
 void launch_build_ray_table(const Geom& g, RayTable t, hipStream_t st) {
-    dim3 grid((g.nd + 255) / 256, g.nv);
+    dim3 grid((g.nd + 255) / 256, table_views(g));
     hipLaunchKernelGGL(k_build_ray_table, grid, dim3(256), 0, st, g, t.fix, t.flt, t.span, t.view);
 }
 
@@ -156,6 +157,8 @@ __global__ __launch_bounds__(256) void k_pack(const SRC* __restrict__ src, int n
     const size_t npix = (size_t)nx * ny;
     float2* pn = pad + (size_t)z * P.pair;
     float2* pt = pn + P.offT;
+    float2* pnr = pn + P.offNR;   // reversed layouts (P.rev: square image)
+    float2* ptr = pn + P.offTR;
     const float2 zero = make_float2(0.f, 0.f);
     for (int r = ty; r < 32; r += 8) {
         const int i = by + r, k = bx + tx;
@@ -169,20 +172,28 @@ __global__ __launch_bounds__(256) void k_pack(const SRC* __restrict__ src, int n
                 if (2 * z + 1 < nsrc) val.y = s[(size_t)(2 * z + 1) * npix + (size_t)i * nx + k];
             }
             pn[(size_t)i * P.ldN + k + kPad] = val;
+            if (P.rev) pnr[(size_t)i * P.ldN + (nx - 1 - k) + kPad] = val;
         }
         tile[r][tx] = val;
         if (i < ny && tx < kPad) {   // zero ends of row i
             if (blockIdx.x == 0) pn[(size_t)i * P.ldN + tx] = zero;
             if (blockIdx.x == gridDim.x - 1) pn[(size_t)i * P.ldN + kPad + nx + tx] = zero;
+            if (P.rev && blockIdx.x == 0) pnr[(size_t)i * P.ldN + tx] = zero;
+            if (P.rev && blockIdx.x == gridDim.x - 1) pnr[(size_t)i * P.ldN + kPad + nx + tx] = zero;
         }
     }
     __syncthreads();
     for (int r = ty; r < 32; r += 8) {
         const int k = bx + r, i = by + tx;
-        if (k < nx && i < ny) pt[(size_t)k * P.ldT + i + kPad] = tile[tx][r];
+        if (k < nx && i < ny) {
+            pt[(size_t)k * P.ldT + i + kPad] = tile[tx][r];
+            if (P.rev) ptr[(size_t)k * P.ldT + (ny - 1 - i) + kPad] = tile[tx][r];
+        }
         if (k < nx && tx < kPad) {   // zero ends of column k
             if (blockIdx.y == 0) pt[(size_t)k * P.ldT + tx] = zero;
             if (blockIdx.y == gridDim.y - 1) pt[(size_t)k * P.ldT + kPad + ny + tx] = zero;
+            if (P.rev && blockIdx.y == 0) ptr[(size_t)k * P.ldT + tx] = zero;
+            if (P.rev && blockIdx.y == gridDim.y - 1) ptr[(size_t)k * P.ldT + kPad + ny + tx] = zero;
         }
     }
 }
@@ -198,26 +209,26 @@ __global__ void k_zero_lines(PadLayout P, int nx, int ny, float2* __restrict__ p
         b[P.offT + (size_t)nx * P.ldT + (e - nN)] = make_float2(0.f, 0.f);
 }
 
-static void launch_zero_lines(const Geom& g, int npairs, float2* pad, hipStream_t st) {
+static void launch_zero_lines(const Geom& g, const PadLayout& P, int npairs, float2* pad,
+                              hipStream_t st) {
     if (g.nx == g.ny) return;
-    const PadLayout P = pad_layout(g);
     const size_t n = (size_t)(P.lines - g.ny) * P.ldN + (size_t)(P.lines - g.nx) * P.ldT;
     hipLaunchKernelGGL(k_zero_lines, dim3((unsigned)((n + 255) / 256), npairs), dim3(256), 0, st, P,
                        g.nx, g.ny, pad);
 }
 
-void launch_pack_pairs(const Geom& g, const float* img, int nimg, float2* pad, hipStream_t st) {
+void launch_pack_pairs(const Geom& g, const PadLayout& P, const float* img, int nimg, float2* pad,
+                       hipStream_t st) {
     dim3 grid((g.nx + 31) / 32, (g.ny + 31) / 32, (nimg + 1) / 2);
-    hipLaunchKernelGGL(k_pack<float>, grid, dim3(256), 0, st, img, nimg, g.nx, g.ny, pad_layout(g),
-                       pad);
-    launch_zero_lines(g, (nimg + 1) / 2, pad, st);
+    hipLaunchKernelGGL(k_pack<float>, grid, dim3(256), 0, st, img, nimg, g.nx, g.ny, P, pad);
+    launch_zero_lines(g, P, (nimg + 1) / 2, pad, st);
 }
 
-void launch_pack_f2(const Geom& g, const float2* src, int npairs, float2* pad, hipStream_t st) {
+void launch_pack_f2(const Geom& g, const PadLayout& P, const float2* src, int npairs, float2* pad,
+                    hipStream_t st) {
     dim3 grid((g.nx + 31) / 32, (g.ny + 31) / 32, npairs);
-    hipLaunchKernelGGL(k_pack<float2>, grid, dim3(256), 0, st, src, 2 * npairs, g.nx, g.ny,
-                       pad_layout(g), pad);
-    launch_zero_lines(g, npairs, pad, st);
+    hipLaunchKernelGGL(k_pack<float2>, grid, dim3(256), 0, st, src, 2 * npairs, g.nx, g.ny, P, pad);
+    launch_zero_lines(g, P, npairs, pad, st);
 }
 
 __global__ void k_pair_sinos(const float* __restrict__ s, int nsino, size_t nray,
@@ -289,7 +300,15 @@ __global__ __launch_bounds__(256) void k_project(const void* __restrict__ pad, P
     const int j = blockIdx.x * 256 + threadIdx.x;
     const bool valid = j < nd && v < D.nv;   // the grid covers the batch's largest slice
     const size_t r = (size_t)v * nd + j;     // ray within the slice
-    const size_t rt = (size_t)D.ray0 + r;    // its table entry
+    // quarter-turn symmetry: view v = vt + rot * nv/4 takes ray (vt, j) of the
+    // table, applied to the image turned rot times
+    int rot = 0, vt = v;
+    if (D.sym) {
+        const int q4 = D.nv >> 2;
+        rot = min(v / q4, 3);
+        vt = v - rot * q4;
+    }
+    const size_t rt = (size_t)D.ray0 + (size_t)vt * nd + j;   // its table entry
     const long long s0 = D.sino0 + (long long)z * T.sino_zstride;
     const int4 fx = valid ? T.fix[rt] : make_int4(0, 0, 0, 0);
     const float2 fl = valid ? T.flt[rt] : make_float2(__builtin_inff(), 1.f);
@@ -307,7 +326,19 @@ __global__ __launch_bounds__(256) void k_project(const void* __restrict__ pad, P
     // step reads zeros only.  Byte offsets are 32-bit, relative to the pair block.
     const int rlo = up ? -kPad : 1 - kPad, rhi = up ? nmin : nmin + 1;
     const float wa = up ? 0.f : 1.f, wb = up ? 1.f : -1.f;   // weight of entry r': wa + wb * w0
-    const unsigned lstep = ES * (unsigned)(xmaj ? P.ldT : P.ldN);
+    // layout read at major step k: pixel (minor m, major k) of the turned image
+    // is entry m of line k (or nmaj - 1 - k) of padT / padN or their reversed
+    // copies (square images only when turned)
+    bool useT = xmaj, rev_line = false, rev_entry = false;
+    if (rot) {
+        useT = xmaj != ((rot & 1) != 0);
+        rev_line = xmaj ? rot >= 2 : (rot == 1 || rot == 2);
+        rev_entry = xmaj ? (rot == 1 || rot == 2) : rot >= 2;
+    }
+    const unsigned lbase = (unsigned)(useT ? (rev_entry ? P.offTR : P.offT) : (rev_entry ? P.offNR : 0));
+    const unsigned lstep_abs = ES * (unsigned)(useT ? P.ldT : P.ldN);
+    const unsigned lstep = rev_line ? 0u - lstep_abs : lstep_abs;   // modulo 2^32
+    const int nmaj = xmaj ? nx : ny;
     int klo = sp.x, khi = sp.y;
     if (klo > khi) {
         klo = INT_MAX;
@@ -316,7 +347,8 @@ __global__ __launch_bounds__(256) void k_project(const void* __restrict__ pad, P
     const int ks = wave_min(klo), ke = wave_max(khi);
     const int k0 = ks == INT_MAX ? 0 : ks;
     long long y = fix_a0(fx) + (long long)k0 * S;
-    unsigned loff = ES * (unsigned)((xmaj ? P.offT : 0) + kPad + (up ? 0 : -1)) + (unsigned)k0 * lstep;
+    const int kl0 = rev_line ? nmaj - 1 - k0 : k0;   // physical line of step k0
+    unsigned loff = ES * (lbase + (unsigned)(kPad + (up ? 0 : -1))) + (unsigned)kl0 * lstep_abs;
     const char* zb = reinterpret_cast<const char*>(pad) + (size_t)z * P.pair * ES;
     float s1 = 0.f, c1 = 0.f, s2 = 0.f, c2 = 0.f;
     const int nstep = ks <= ke ? ke - ks + 1 : 0;   // wave-uniform
@@ -401,10 +433,9 @@ __global__ __launch_bounds__(256) void k_project(const void* __restrict__ pad, P
     }
 }
 
-void launch_project(const Geom& g, const RayTable& t, const void* pad, int npairs, int mode,
-                    const ProjArgs& a, hipStream_t st) {
+void launch_project(const Geom& g, const PadLayout& P, const RayTable& t, const void* pad, int npairs,
+                    int mode, const ProjArgs& a, hipStream_t st) {
     dim3 grid((t.nd_max + 255) / 256, t.nv_max, npairs);
-    const PadLayout P = pad_layout(g);
     if (mode == PROJ_PLAIN)
         hipLaunchKernelGGL((k_project<PROJ_PLAIN, false, false>), grid, dim3(256), 0, st, pad, P, t,
                            g.nx, g.ny, a);
@@ -446,6 +477,7 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_backproject(
     __shared__ float red[kBpWaves][8][64];
     const int z = blockIdx.z;
     const SliceDesc D = T.desc[T.desc_stride * z];
+    if (D.sym) return;   // quarter-turn symmetric slices: k_backproject_sym
     const int nv = D.nv, nd = D.nd;
     const float sid = D.sid, sdd = D.sdd, u0 = D.u0, inv_pitch = D.inv_pitch;
     const int4* __restrict__ fix = T.fix + D.ray0;
@@ -565,16 +597,204 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_backproject(
     }
 }
 
+// ---------------------------------------------------------------------------
+// back-projector of quarter-turn symmetric slices.  The turn R(i, k) =
+// (k, n - 1 - i) maps tile T0 of the image's first quadrant to T1 = R T0,
+// T2 = R^2 T0 and T3 = R^3 T0, and ray (v + t nv/4, j) meets pixel R^t p with
+// the weight that ray (v, j) of the table has on p.  A block owns the four
+// tiles of one orbit with 16 wavefronts: wavefront w works on tile w & 3 and
+// table views v = w >> 2 (mod 4).  Each lane owns a 2 x 2 quad of its tile,
+// evaluates the weights of ray (v, j) on its quad once, exactly as the
+// voxel-driven kernel does, and accumulates them times the residuals of
+// views v + t nv/4, t = 0..3, for the quads R^t of its own.  The partial
+// sums reach the tiles in LDS in a fixed order (turn, view class), so the
+// result is deterministic.
+// ---------------------------------------------------------------------------
+constexpr int kBsWaves = 16;
+
+template <bool SB>
+__global__ __launch_bounds__(kBsWaves * 64) void k_backproject_sym(
+    const void* __restrict__ sino, RayTable T, int n, float dxmm, float2* __restrict__ out_pairs,
+    float* __restrict__ out_split, int nout) {
+    __shared__ float4 vs[kBpViewChunk];
+    __shared__ int4 sfix[kBsWaves][64];
+    __shared__ float2 sfl[kBsWaves][64];        // (2^-32/|s|, +-L)
+    __shared__ float4 ssn[kBsWaves][64][2];     // residual pairs of the four turns
+    // the four tiles' sums [tile][channel][row][column], in ssn's memory once
+    // every view is done
+    float(*acc_t)[2][16][17] = reinterpret_cast<float(*)[2][16][17]>(&ssn[0][0][0]);
+    static_assert(sizeof(ssn) >= sizeof(float) * 4 * 2 * 16 * 17, "tile sums");
+    const int z = blockIdx.z;
+    const SliceDesc D = T.desc[T.desc_stride * z];
+    if (!D.sym) return;
+    const int nd = D.nd, q4 = D.nv >> 2;
+    const float sid = D.sid, sdd = D.sdd, u0 = D.u0, inv_pitch = D.inv_pitch;
+    const int4* __restrict__ fix = T.fix + D.ray0;
+    const float2* __restrict__ flt = T.flt + D.ray0;
+    const float4* __restrict__ view = T.view + D.view0;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int a = w & 3, cls = w >> 2;
+    // tile origins (row, column) of T0..T3
+    const int ty0 = blockIdx.y * 16, tx0 = blockIdx.x * 16;
+    const int oy[4] = {ty0, tx0, n - 16 - ty0, n - 16 - tx0};
+    const int ox[4] = {tx0, n - 16 - ty0, n - 16 - tx0, ty0};
+    const int i0 = oy[a] + 2 * (lane >> 3), k0 = ox[a] + 2 * (lane & 7);
+    const float x = ((float)k0 + 0.5f - 0.5f * (float)(n - 1)) * dxmm;
+    const float y = ((float)i0 + 0.5f - 0.5f * (float)(n - 1)) * dxmm;
+    const long long sbase = D.sino0 + (long long)z * T.sino_zstride;
+    const float2* sz = reinterpret_cast<const float2*>(sino) + sbase;
+    const unsigned* szb = reinterpret_cast<const unsigned*>(sino) + sbase;
+    const size_t tstep = (size_t)q4 * nd;   // rays of one quarter of the views
+    // acc[t][q]: turn t, q = 2 * (2 * di + dk) + channel for pixel (i0 + di, k0 + dk)
+    float acc[4][8];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[t][q] = 0.f;
+    for (int v0 = 0; v0 < q4; v0 += kBpViewChunk) {
+        const int nvc = min(kBpViewChunk, q4 - v0);
+        __syncthreads();
+        for (int q = threadIdx.x; q < nvc; q += kBsWaves * 64) vs[q] = view[v0 + q];
+        __syncthreads();
+        for (int vv = cls; vv < nvc; vv += 4) {
+            const float4 vc = vs[vv];
+            const float e = 2.f * vc.z;
+            const float U = sid - (x * vc.x + y * vc.y);
+            const float W = y * vc.x - x * vc.y;
+            const float rm = __builtin_amdgcn_rcpf(U - e);
+            const float rp = __builtin_amdgcn_rcpf(U + e);
+            const float hi = W + e, lo = W - e;
+            const float umax = sdd * hi * (hi >= 0.f ? rm : rp);
+            const float umin = sdd * lo * (lo >= 0.f ? rp : rm);
+            int jl = max((int)ceilf((umin - u0) * inv_pitch - 1e-3f), 0);
+            int jh = min((int)floorf((umax - u0) * inv_pitch + 1e-3f), nd - 1);
+            if (jl > jh) {
+                jl = INT_MAX;
+                jh = INT_MIN;
+            }
+            const int Jlo = wave_min(jl), Jhi = wave_max(jh);
+            if (Jlo > Jhi) continue;   // wave-uniform
+            const int v = v0 + vv;
+            for (int base = Jlo; base <= Jhi; base += 64) {
+                const int jj = base + lane;
+                if (jj <= Jhi) {
+                    const size_t r = (size_t)v * nd + jj;
+                    float2 s4[4];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        s4[t] = SB ? bf16x2_unpack(szb[r + t * tstep]) : sz[r + t * tstep];
+                    sfix[w][lane] = fix[r];
+                    sfl[w][lane] = flt[r];
+                    ssn[w][lane][0] = make_float4(s4[0].x, s4[0].y, s4[1].x, s4[1].y);
+                    ssn[w][lane][1] = make_float4(s4[2].x, s4[2].y, s4[3].x, s4[3].y);
+                }
+                __builtin_amdgcn_wave_barrier();
+                const int ja = max(jl, base), jb = min(jh, base + 63);
+                for (int j = ja; j <= jb; ++j) {
+                    const int4 fx = sfix[w][j - base];
+                    const float2 fs = sfl[w][j - base];
+                    const bool xm = fs.y > 0.f;
+                    const long long S = fix_s(fx);
+                    const bool up = S >= 0;
+                    const int maj0 = xm ? k0 : i0, mnr0 = xm ? i0 : k0;
+                    const long long ya = fix_a0(fx) + (long long)(unsigned)maj0 * S;
+                    const long long yb = ya + S;
+                    const unsigned xmask = up ? ~0u : 0u;
+                    const float wa = first_weight((unsigned)ya, xmask, fs.x);
+                    const float wb = first_weight((unsigned)yb, xmask, fs.x);
+                    const int ea = (int)(ya >> 32) - mnr0, eb = (int)(yb >> 32) - mnr0;
+                    const int o0 = up ? -1 : 1, o1 = up ? 0 : 2;
+                    const float ca0 = ea == 0 ? wa : (ea == o0 ? 1.f - wa : 0.f);
+                    const float ca1 = ea == 1 ? wa : (ea == o1 ? 1.f - wa : 0.f);
+                    const float cb0 = eb == 0 ? wb : (eb == o0 ? 1.f - wb : 0.f);
+                    const float cb1 = eb == 1 ? wb : (eb == o1 ? 1.f - wb : 0.f);
+                    const float c01 = xm ? cb0 : ca1, c10 = xm ? ca1 : cb0;
+                    const float L = fabsf(fs.y);
+                    const float4 sA = ssn[w][j - base][0], sB = ssn[w][j - base][1];
+                    const float sv[8] = {sA.x, sA.y, sA.z, sA.w, sB.x, sB.y, sB.z, sB.w};
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const float s1 = L * sv[2 * t], s2 = L * sv[2 * t + 1];
+                        acc[t][0] = fmaf(ca0, s1, acc[t][0]);
+                        acc[t][1] = fmaf(ca0, s2, acc[t][1]);
+                        acc[t][2] = fmaf(c01, s1, acc[t][2]);
+                        acc[t][3] = fmaf(c01, s2, acc[t][3]);
+                        acc[t][4] = fmaf(c10, s1, acc[t][4]);
+                        acc[t][5] = fmaf(c10, s2, acc[t][5]);
+                        acc[t][6] = fmaf(cb1, s1, acc[t][6]);
+                        acc[t][7] = fmaf(cb1, s2, acc[t][7]);
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+    }
+    // the four tiles in LDS: turn t of tile a lands in tile (a + t) & 3; in each
+    // round one view class adds one turn, its four wavefronts into four tiles
+    __syncthreads();
+    for (int q = threadIdx.x; q < 4 * 2 * 16 * 17; q += kBsWaves * 64) (&acc_t[0][0][0][0])[q] = 0.f;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int b = (a + t) & 3;
+        for (int c = 0; c < 4; ++c) {
+            __syncthreads();
+            if (cls != c) continue;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                const int gi0 = i0 + (d >> 1), gk0 = k0 + (d & 1);
+                int gi = gi0, gk = gk0;   // R^t (gi0, gk0)
+                if (t == 1) {
+                    gi = gk0;
+                    gk = n - 1 - gi0;
+                } else if (t == 2) {
+                    gi = n - 1 - gi0;
+                    gk = n - 1 - gk0;
+                } else if (t == 3) {
+                    gi = n - 1 - gk0;
+                    gk = gi0;
+                }
+                const int li = gi - oy[b], lk = gk - ox[b];
+                acc_t[b][0][li][lk] += acc[t][2 * d];
+                acc_t[b][1][li][lk] += acc[t][2 * d + 1];
+            }
+        }
+    }
+    __syncthreads();
+    const size_t npix = (size_t)n * n;
+    for (int q = threadIdx.x; q < 4 * 256; q += kBsWaves * 64) {
+        const int b = q >> 8, li = (q >> 4) & 15, lk = q & 15;
+        const size_t p = (size_t)(oy[b] + li) * n + (ox[b] + lk);
+        const float s1 = acc_t[b][0][li][lk], s2 = acc_t[b][1][li][lk];
+        if (out_pairs) {
+            out_pairs[(size_t)z * npix + p] = make_float2(s1, s2);
+        } else {
+            out_split[(size_t)(2 * z) * npix + p] = s1;
+            if (2 * z + 1 < nout) out_split[(size_t)(2 * z + 1) * npix + p] = s2;
+        }
+    }
+}
+
 void launch_backproject(const Geom& g, const RayTable& t, const void* sino, int npairs,
                         float2* out_pairs, float* out_split, int nout, hipStream_t st,
-                        bool sino_bf16) {
-    dim3 grid((g.nx + 15) / 16, (g.ny + 15) / 16, npairs);
-    if (sino_bf16)
-        hipLaunchKernelGGL(k_backproject<true>, grid, dim3(kBpWaves * 64), 0, st, sino, t, g.nx, g.ny,
-                           (float)g.dx, out_pairs, out_split, nout);
-    else
-        hipLaunchKernelGGL(k_backproject<false>, grid, dim3(kBpWaves * 64), 0, st, sino, t, g.nx,
-                           g.ny, (float)g.dx, out_pairs, out_split, nout);
+                        bool sino_bf16, int sym_mode) {
+    if (sym_mode != 1) {
+        dim3 grid((g.nx + 15) / 16, (g.ny + 15) / 16, npairs);
+        if (sino_bf16)
+            hipLaunchKernelGGL(k_backproject<true>, grid, dim3(kBpWaves * 64), 0, st, sino, t, g.nx,
+                               g.ny, (float)g.dx, out_pairs, out_split, nout);
+        else
+            hipLaunchKernelGGL(k_backproject<false>, grid, dim3(kBpWaves * 64), 0, st, sino, t, g.nx,
+                               g.ny, (float)g.dx, out_pairs, out_split, nout);
+    }
+    if (sym_mode != 0 && grid_sym4(g)) {
+        dim3 grid(g.nx / 32, g.nx / 32, npairs);   // first-quadrant tiles
+        if (sino_bf16)
+            hipLaunchKernelGGL(k_backproject_sym<true>, grid, dim3(kBsWaves * 64), 0, st, sino, t, g.nx,
+                               (float)g.dx, out_pairs, out_split, nout);
+        else
+            hipLaunchKernelGGL(k_backproject_sym<false>, grid, dim3(kBsWaves * 64), 0, st, sino, t, g.nx,
+                               (float)g.dx, out_pairs, out_split, nout);
+    }
 }
 
 }  // namespace dect

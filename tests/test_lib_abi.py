@@ -147,7 +147,9 @@ def test_bf16_storage_workspace():
     g = dect.Geometry.of(P.geometry_slice512()).c()
     a = L.dect_solve_workspace_bytes(C.byref(g), C.byref(dect.default_params()), 2)
     b = L.dect_solve_workspace_bytes(C.byref(g), C.byref(dect.default_params(storage=1)), 2)
-    pad = 2 * 512 * (512 + 4)   # two padded layouts per image
+    # four padded layouts per image: rows, columns and both reversed (the
+    # 720-view 512^2 slice is quarter-turn symmetric)
+    pad = 4 * 512 * (512 + 4)
     assert 2 * pad * 4 <= b - a <= 2 * pad * 4 + 512
 
 
