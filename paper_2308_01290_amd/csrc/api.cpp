@@ -618,6 +618,7 @@ int dect_project(const dect_geometry* gin, const float* img, float* sino, int32_
     ProjArgs a;
     a.out = sino;
     a.nout = batch;
+    a.sym_all = sym4(g);
     launch_project(g, P, t, pad, np, PROJ_PLAIN, a, st);
     DECT_HIP(hipGetLastError());
     return DECT_OK;
@@ -922,6 +923,7 @@ static void project_residual(dect_solver* s, const float* lo, const float* hi) {
     a.c10 = (float)s->M.C[1][0];
     a.c11 = (float)s->M.C[1][1];
     a.res_bf16 = s->storage != DECT_STORAGE_FP32;
+    a.sym_all = s->geo.sym_mode == 1;
     launch_project(s->g, P, s->tab, s->dpad, s->batch, PROJ_RESID, a, s->st);
 }
 
@@ -1117,6 +1119,7 @@ static int one_iteration(dect_solver* s) {
     pa.alpha = s->alpha;
     pa.counter = s->cnt_proj;
     pa.pad_bf16 = pa.res_bf16 = a.bf16;
+    pa.sym_all = s->geo.sym_mode == 1;
     hipEvent_t t1 = mark(s);
     launch_project(g, P, s->tab, dir, s->batch, PROJ_LINESEARCH, pa, s->st);
     mark_end(s, t1, s->ev_fp);
@@ -1543,6 +1546,7 @@ int dect_engine_admit(dect_engine* e, const dect_geometry* gin, const float* lo,
     a.c10 = (float)s->M.C[1][0];
     a.c11 = (float)s->M.C[1][1];
     a.res_bf16 = s->storage != DECT_STORAGE_FP32;
+    a.sym_all = sym4(g);
     launch_project(g, P, tz, s->dpad + z * P.pair, 1, PROJ_RESID, a, st);
     // continuation schedule of this request
     const double kappa = std::pow(e->p.beta_max / s->rp.beta0, 1.0 / n_iter);

@@ -166,6 +166,9 @@ struct ProjArgs {
     // (RESID, LINESEARCH); LINESEARCH also reads BF16 pair blocks
     bool res_bf16 = false;
     bool pad_bf16 = false;
+    // every slice of the launch is quarter-turn symmetric: one lane per
+    // table ray produces its four turned rays (k_project4)
+    bool sym_all = false;
 };
 int proj_nblocks(int nv_max, int nd_max);  // blocks per pair
 // pad: float2 pair blocks, or with a.pad_bf16 one 32-bit BF16 pair per entry

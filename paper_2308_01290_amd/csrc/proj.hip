@@ -433,8 +433,176 @@ __global__ __launch_bounds__(256) void k_project(const void* __restrict__ pad, P
     }
 }
 
+// Forward projector of quarter-turn symmetric slices: lane j of block vt
+// steps ray (vt, j) of the table once and reads the four turned images at
+// every step, producing rays (vt + t nv/4, j), t = 0..3.  The traversal, the
+// clamp and the step weight are shared by the four rays; each ray's value is
+// summed exactly as k_project sums it (same steps, same grouping), so the two
+// kernels agree bit for bit.  Line-search partials go to the same per-view
+// block slots.
+template <int MODE, bool PB, bool RB>
+__global__ __launch_bounds__(256) void k_project4(const void* __restrict__ pad, PadLayout P,
+                                                  RayTable T, int n, ProjArgs a) {
+    constexpr unsigned ES = PB ? 4u : 8u;
+    constexpr int LS = PB ? 2 : 3;
+    const int vt = blockIdx.y, z = blockIdx.z;
+    const SliceDesc D = T.desc[T.desc_stride * z];
+    const int nd = D.nd, q4 = D.nv >> 2;
+    if (!D.sym || vt >= q4) return;   // block-uniform
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    const bool valid = j < nd;
+    const size_t rt = (size_t)D.ray0 + (size_t)vt * nd + j;
+    const long long s0 = D.sino0 + (long long)z * T.sino_zstride;
+    const int4 fx = valid ? T.fix[rt] : make_int4(0, 0, 0, 0);
+    const float2 fl = valid ? T.flt[rt] : make_float2(__builtin_inff(), 1.f);
+    const int2 sp = valid ? T.span[rt] : make_int2(1, 0);
+    const bool xmaj = fl.y > 0.f;
+    const float L = fabsf(fl.y);
+    const float ainv32 = fl.x;
+    const long long S = fix_s(fx);
+    const bool up = S >= 0;
+    const unsigned xmask = up ? ~0u : 0u;
+    const int rlo = up ? -kPad : 1 - kPad, rhi = up ? n : n + 1;
+    const float wa = up ? 0.f : 1.f, wb = up ? 1.f : -1.f;
+    int klo = sp.x, khi = sp.y;
+    if (klo > khi) {
+        klo = INT_MAX;
+        khi = INT_MIN;
+    }
+    const int ks = wave_min(klo), ke = wave_max(khi);
+    const int k0 = ks == INT_MAX ? 0 : ks;
+    const unsigned lstep_abs = ES * (unsigned)P.ldN;   // square image: ldN == ldT
+    unsigned loff[4], lstep[4];
+#pragma unroll
+    for (int rot = 0; rot < 4; ++rot) {
+        bool useT = xmaj, rev_line = false, rev_entry = false;
+        if (rot) {
+            useT = xmaj != ((rot & 1) != 0);
+            rev_line = xmaj ? rot >= 2 : (rot == 1 || rot == 2);
+            rev_entry = xmaj ? (rot == 1 || rot == 2) : rot >= 2;
+        }
+        const unsigned lbase =
+            (unsigned)(useT ? (rev_entry ? P.offTR : P.offT) : (rev_entry ? P.offNR : 0));
+        const int kl0 = rev_line ? n - 1 - k0 : k0;
+        loff[rot] = ES * (lbase + (unsigned)(kPad + (up ? 0 : -1))) + (unsigned)kl0 * lstep_abs;
+        lstep[rot] = rev_line ? 0u - lstep_abs : lstep_abs;
+    }
+    long long y = fix_a0(fx) + (long long)k0 * S;
+    const char* zb = reinterpret_cast<const char*>(pad) + (size_t)z * P.pair * ES;
+    float s1[4], c1[4], s2[4], c2[4];
+#pragma unroll
+    for (int rot = 0; rot < 4; ++rot) s1[rot] = c1[rot] = s2[rot] = c2[rot] = 0.f;
+    const int nstep = ks <= ke ? ke - ks + 1 : 0;   // wave-uniform
+    int k = 0;
+    for (; k + 4 <= nstep; k += 4) {
+        unsigned eo[4];
+        float W[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            eo[u] = (unsigned)clamp_med3((int)(y >> 32), rlo, rhi) << LS;
+            W[u] = fmaf(wb, first_weight((unsigned)y, xmask, ainv32), wa);
+            y += S;
+        }
+#pragma unroll
+        for (int rot = 0; rot < 4; ++rot) {
+            float2 A[4], B[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) load_step<PB>(zb, loff[rot] + (unsigned)u * lstep[rot] + eo[u], A[u], B[u]);
+            float v1[4], v2[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                v1[u] = fmaf(W[u], A[u].x - B[u].x, B[u].x);
+                v2[u] = fmaf(W[u], A[u].y - B[u].y, B[u].y);
+            }
+            kahan_add(s1[rot], c1[rot], (v1[0] + v1[1]) + (v1[2] + v1[3]));
+            kahan_add(s2[rot], c2[rot], (v2[0] + v2[1]) + (v2[2] + v2[3]));
+            loff[rot] += 4u * lstep[rot];
+        }
+    }
+    for (; k < nstep; ++k) {
+        const unsigned eo = (unsigned)clamp_med3((int)(y >> 32), rlo, rhi) << LS;
+        const float W = fmaf(wb, first_weight((unsigned)y, xmask, ainv32), wa);
+#pragma unroll
+        for (int rot = 0; rot < 4; ++rot) {
+            float2 A, B;
+            load_step<PB>(zb, loff[rot] + eo, A, B);
+            kahan_add(s1[rot], c1[rot], fmaf(W, A.x - B.x, B.x));
+            kahan_add(s2[rot], c2[rot], fmaf(W, A.y - B.y, B.y));
+            loff[rot] += lstep[rot];
+        }
+        y += S;
+    }
+    const size_t nray = (size_t)D.nv * nd;
+    double part[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int rot = 0; rot < 4; ++rot) {
+        const double Y1 = (double)L * ((double)s1[rot] - (double)c1[rot]);
+        const double Y2 = (double)L * ((double)s2[rot] - (double)c2[rot]);
+        const size_t r = (size_t)(vt + rot * q4) * nd + j;   // ray of view vt + rot nv/4
+        if (!valid) continue;
+        if constexpr (MODE == PROJ_PLAIN) {
+            a.out[(size_t)(2 * s0) + r] = (float)Y1;
+            if (2 * z + 1 < a.nout) a.out[(size_t)(2 * s0) + nray + r] = (float)Y2;
+        } else if constexpr (MODE == PROJ_RESID) {
+            const double rl = (double)a.c00 * Y1 + (double)a.c01 * Y2 - (double)a.p_lo[s0 - a.p_base + r];
+            const double rh = (double)a.c10 * Y1 + (double)a.c11 * Y2 - (double)a.p_hi[s0 - a.p_base + r];
+            store_res<RB>(a.res, s0 + r, (float)(D.eta * ((double)a.c00 * rl + (double)a.c10 * rh)),
+                          (float)(D.eta * ((double)a.c01 * rl + (double)a.c11 * rh)));
+        } else {
+            const double yl = (double)a.c00 * Y1 + (double)a.c01 * Y2;
+            const double yh = (double)a.c10 * Y1 + (double)a.c11 * Y2;
+            store_res<RB>(a.res, s0 + r, (float)(D.eta * ((double)a.c00 * yl + (double)a.c10 * yh)),
+                          (float)(D.eta * ((double)a.c01 * yl + (double)a.c11 * yh)));
+            part[rot] = D.eta * (yl * yl + yh * yh);
+        }
+    }
+    if constexpr (MODE == PROJ_LINESEARCH) {
+        __shared__ double sh[4];
+        const int nbx = (nd + 255) / 256;
+        if ((int)blockIdx.x >= nbx) return;
+        const int nblk = nbx * D.nv;
+        double* zp = a.partials + (size_t)z * gridDim.x * gridDim.y * 4;
+#pragma unroll
+        for (int rot = 0; rot < 4; ++rot) {
+            const double bs = block_sum<256>(part[rot], sh);
+            if (threadIdx.x == 0) zp[(vt + rot * q4) * nbx + blockIdx.x] = bs;
+        }
+        if (last_block_arrive(a.counter + z, (unsigned)(nbx * q4))) {
+            const double den_data = block_sum_array<256>(zp, nblk, 1, sh);
+            const double* ip = a.img_partials + (size_t)z * a.img_nblocks * 3;
+            const double num = block_sum_array<256>(ip + 0, a.img_nblocks, 3, sh);
+            const double coup = block_sum_array<256>(ip + 1, a.img_nblocks, 3, sh);
+            const double reg = block_sum_array<256>(ip + 2, a.img_nblocks, 3, sh);
+            if (threadIdx.x == 0) {
+                const double wr = a.beta_z ? 2.0 * a.beta_z[z] : a.w_reg;
+                const double den = a.w_data * den_data + a.w_coup * coup + wr * reg;
+                a.alpha[z] = den > 0.0 ? num / den : 0.0;
+            }
+        }
+    }
+}
+
 void launch_project(const Geom& g, const PadLayout& P, const RayTable& t, const void* pad, int npairs,
                     int mode, const ProjArgs& a, hipStream_t st) {
+    if (a.sym_all && P.rev) {
+        dim3 grid4((t.nd_max + 255) / 256, (t.nv_max + 3) / 4, npairs);
+        if (mode == PROJ_PLAIN)
+            hipLaunchKernelGGL((k_project4<PROJ_PLAIN, false, false>), grid4, dim3(256), 0, st, pad, P, t,
+                               g.nx, a);
+        else if (mode == PROJ_RESID && a.res_bf16)
+            hipLaunchKernelGGL((k_project4<PROJ_RESID, false, true>), grid4, dim3(256), 0, st, pad, P, t,
+                               g.nx, a);
+        else if (mode == PROJ_RESID)
+            hipLaunchKernelGGL((k_project4<PROJ_RESID, false, false>), grid4, dim3(256), 0, st, pad, P, t,
+                               g.nx, a);
+        else if (a.pad_bf16)
+            hipLaunchKernelGGL((k_project4<PROJ_LINESEARCH, true, true>), grid4, dim3(256), 0, st, pad, P,
+                               t, g.nx, a);
+        else
+            hipLaunchKernelGGL((k_project4<PROJ_LINESEARCH, false, false>), grid4, dim3(256), 0, st, pad,
+                               P, t, g.nx, a);
+        return;
+    }
     dim3 grid((t.nd_max + 255) / 256, t.nv_max, npairs);
     if (mode == PROJ_PLAIN)
         hipLaunchKernelGGL((k_project<PROJ_PLAIN, false, false>), grid, dim3(256), 0, st, pad, P, t,
