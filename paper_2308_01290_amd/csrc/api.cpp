@@ -390,12 +390,23 @@ static void apply_prec(const PcgArgs& a, int it, const PcgBufs& b, float2* fft_s
 static int run_pcg(PcgArgs& a, const PcgBufs& b, int max_iter, int first_chunk,
                    float2* fft_scratch, hipStream_t st, int* iters_out) {
     if (a.prec == PREC_MG) launch_mg_setup(b.mg_plan, a.w2, b.mg, a.batch, st);
-    apply_prec(a, -1, b, fft_scratch, st);
+    // with the multigrid preconditioner on sizes whose finest V-cycle kernel
+    // can also apply A, the pipelined form: one reduction per iteration
+    const bool piped = a.prec == PREC_MG && mg_pipelined_ok(b.mg_plan);
+    if (piped)
+        launch_pcg_mg_prec_w(a, 0, b.mg_plan, b.mg, st);
+    else
+        apply_prec(a, -1, b, fft_scratch, st);
     int it = 0;
     int chunk = std::max(2, first_chunk);
     std::vector<PcgState> hs(a.batch);
     while (true) {
         for (int c = 0; c < chunk && it < max_iter; ++c, ++it) {
+            if (piped) {
+                launch_pcg_cg_update(a, it, st);
+                launch_pcg_mg_prec_w(a, it + 1, b.mg_plan, b.mg, st);
+                continue;
+            }
             launch_pcg_matvec(a, it, st);
             launch_pcg_update(a, it, st);
             apply_prec(a, it, b, fft_scratch, st);

@@ -312,7 +312,10 @@ struct PcgState {   // per slice, read by the host
 };
 struct PcgParts {   // per-slice partial-sum layout (doubles)
     int nblk, nrz;  // blocks of the pixel kernels; entries of an rz sum
-    size_t init0, init1, pq, rz, rr, zstride;   // offsets within a slice
+    size_t init0, init1, pq, rz, rr;   // offsets within a slice
+    size_t dl;      // pipelined PCG: <u, w> partials, two parity slots of nrz
+    size_t sc;      // pipelined PCG: (gamma, alpha) of the last two iterations
+    size_t zstride;
 };
 PcgParts pcg_parts(int ny, int nx);
 enum PcgPrec { PREC_JACOBI = 1, PREC_FFT = 2, PREC_MG = 3 };
@@ -342,6 +345,14 @@ void launch_pcg_update(const PcgArgs& a, int it, hipStream_t st);
 void launch_pcg_check(const PcgArgs& a, int done_iters, hipStream_t st);
 // FFT preconditioner z = (c + beta L)^-1 r, c = mean(w^2), with <r, z> partials
 void launch_pcg_fft_prec(const PcgArgs& a, int it, float2* scratch, hipStream_t st);
+// Pipelined PCG (one reduction per iteration, Chronopoulos and Gear) with
+// the multigrid preconditioner: iteration i takes u_i = M r_i, w_i = A u_i
+// and the partial sums of gamma_i = <r_i, u_i>, delta_i = <u_i, w_i> (from
+// the V-cycle's last kernel), forms beta_i = gamma_i / gamma_(i-1) and
+// alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_(i-1)), then
+// p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s.  It first
+// stops the slice when ||r_i||^2 <= tol2 ||r_0||^2.  p is p0, s is p1.
+void launch_pcg_cg_update(const PcgArgs& a, int i, hipStream_t st);
 
 // ---- multigrid V-cycle preconditioner for diag(c) + beta L -----------------------
 constexpr int kMgMaxLevels = 12;
@@ -366,7 +377,12 @@ void launch_mg_setup(const MgPlan& P, const float* w2, float* mg, int batch, hip
 // z = V(r); <r, z> partials into dot[z*dot_zstride + 0..P.nrz)
 void launch_mg_vcycle(const MgPlan& P, const float* r, const float* w2, float* z, float* mg,
                       int batch, float beta, const double* beta_z, const int* skip,
-                      size_t skip_zstride, double* dot, size_t dot_zstride, hipStream_t st);
+                      size_t skip_zstride, double* dot, size_t dot_zstride, hipStream_t st,
+                      float* wout = nullptr, double* dot2 = nullptr);
 void launch_pcg_mg_prec(const PcgArgs& a, int it, const MgPlan& P, float* mg, hipStream_t st);
+// the V-cycle as the pipelined PCG uses it (needs mg_pipelined_ok: level 0 a
+// pair level above at least one more tile level)
+bool mg_pipelined_ok(const MgPlan& P);
+void launch_pcg_mg_prec_w(const PcgArgs& a, int i, const MgPlan& P, float* mg, hipStream_t st);
 
 }  // namespace dect

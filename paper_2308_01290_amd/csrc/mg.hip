@@ -376,13 +376,22 @@ __global__ __launch_bounds__(kPairThreads) void k_mg_down2(MgPair A, const int* 
 }
 
 // up: level l + 1 from its saved iterate and e_(l+2), then level l; with `dot`
-// (finest level) the block's <b0, out> goes to dot[z*dot_zstride + block]
+// (finest level) the block's <b0, out> goes to dot[z*dot_zstride + block].
+// W (finest level of a pipelined PCG): the level-l region carries one more
+// halo pixel, so the last sweep yields u = out on the core plus one ring and
+// the block also writes w = A u on the core (A = diag(c0) + beta L) and the
+// partial sum <u, w> to dot2.  u is the same as without W, bit for bit.
+template <bool W>
 __global__ __launch_bounds__(kPairThreads) void k_mg_up2(MgPair A, const int* skip,
                                                          size_t skip_zstride, double* dot,
-                                                         size_t dot_zstride) {
-    __shared__ float B0[kU0][kU0 + 1], C0[kU0][kU0 + 1], Y0[2][kU0][kU0 + 1];
+                                                         size_t dot_zstride, float* wout,
+                                                         double* dot2) {
+    constexpr int H0 = W ? kMgNu + 1 : kMgNu;   // level-l halo of the loaded region
+    constexpr int U0 = kCore2 + 2 * H0;
+    __shared__ float B0[U0][U0 + 1], C0[U0][U0 + 1], Y0[2][U0][U0 + 1];
     __shared__ float B1[kU1][kU1 + 1], C1[kU1][kU1 + 1], Y1[2][kU1][kU1 + 1];
     __shared__ double sh[kPairThreads / kWave];
+    static_assert((H0 + 1) / 2 == kUh1, "level l + 1 region covers the parents of the level-l region");
     const int z = blockIdx.z;
     if (mg_skip(skip, skip_zstride, z)) return;
     const int ny0 = A.ny0, nx0 = A.nx0, ny1 = ny0 / 2, nx1 = nx0 / 2, nx2 = nx1 / 2;
@@ -404,10 +413,9 @@ __global__ __launch_bounds__(kPairThreads) void k_mg_up2(MgPair A, const int* sk
         }
         const float* b0 = A.b0 + (size_t)z * A.zs_b0;
         const float* c0 = A.c0 + (size_t)z * A.zs_c0;
-        for (int t = threadIdx.x; t < kU0 * kU0; t += kPairThreads) {
-            const int r = t / kU0, s = t % kU0;
-            const size_t g = (size_t)wrap_near(i0 - kMgNu + r, ny0) * nx0 +
-                             wrap_near(k0 - kMgNu + s, nx0);
+        for (int t = threadIdx.x; t < U0 * U0; t += kPairThreads) {
+            const int r = t / U0, s = t % U0;
+            const size_t g = (size_t)wrap_near(i0 - H0 + r, ny0) * nx0 + wrap_near(k0 - H0 + s, nx0);
             B0[r][s] = b0[g];
             C0[r][s] = c0[g];
         }
@@ -420,35 +428,58 @@ __global__ __launch_bounds__(kPairThreads) void k_mg_up2(MgPair A, const int* sk
         __syncthreads();
     }
     const float (*E1)[kU1 + 1] = Y1[kMgNu & 1];   // e_(l+1), valid on [nu, kU1 - nu)
-    // level l: y0 = xs0 + P e_(l+1) on [-nu, 32 + nu)
+    // level l: y0 = xs0 + P e_(l+1) on [-H0, 32 + H0)
     const float* xs0 = A.xs0 + (size_t)z * A.zs_xs0;
-    for (int t = threadIdx.x; t < kU0 * kU0; t += kPairThreads) {
-        const int r = t / kU0, s = t % kU0;
-        const size_t g = (size_t)wrap_near(i0 - kMgNu + r, ny0) * nx0 +
-                         wrap_near(k0 - kMgNu + s, nx0);
-        // parent of level-l row i0 - nu + r, relative to i0 / 2, plus the region offset H1
-        const int pr = ((r + kMgNu) >> 1) - kMgNu + H1, ps = ((s + kMgNu) >> 1) - kMgNu + H1;
+    for (int t = threadIdx.x; t < U0 * U0; t += kPairThreads) {
+        const int r = t / U0, s = t % U0;
+        const size_t g = (size_t)wrap_near(i0 - H0 + r, ny0) * nx0 + wrap_near(k0 - H0 + s, nx0);
+        // parent of level-l row i0 - H0 + r, relative to i0 / 2, plus the region offset H1
+        const int pr = ((r + H0) >> 1) - H0 + H1, ps = ((s + H0) >> 1) - H0 + H1;
         Y0[0][r][s] = xs0[g] + E1[pr][ps];
     }
     __syncthreads();
 #pragma unroll
     for (int q = 1; q < kMgNu; ++q) {
-        pair_sweep<kU0>(Y0[(q - 1) & 1], Y0[q & 1], B0, C0, q, kU0 - 2 * q, be0);
+        pair_sweep<U0>(Y0[(q - 1) & 1], Y0[q & 1], B0, C0, q, U0 - 2 * q, be0);
         __syncthreads();
     }
-    const float (*Yp)[kU0 + 1] = Y0[(kMgNu - 1) & 1];
+    const float (*Yp)[U0 + 1] = Y0[(kMgNu - 1) & 1];
     float* out = A.e0 + (size_t)z * A.zs_e0;
-    double part = 0.0;
-    for (int t = threadIdx.x; t < kCore2 * kCore2; t += kPairThreads) {
-        const int r = kMgNu + t / kCore2, s = kMgNu + t % kCore2;
-        const float ns = Yp[r - 1][s] + Yp[r + 1][s] + Yp[r][s - 1] + Yp[r][s + 1];
-        const float y = jac(Yp[r][s], B0[r][s], C0[r][s], be0, ns);
-        out[(size_t)(i0 + r - kMgNu) * nx0 + (k0 + s - kMgNu)] = y;
-        part += (double)y * (double)B0[r][s];
+    double part = 0.0, part2 = 0.0;
+    if constexpr (!W) {
+        for (int t = threadIdx.x; t < kCore2 * kCore2; t += kPairThreads) {
+            const int r = kMgNu + t / kCore2, s = kMgNu + t % kCore2;
+            const float ns = Yp[r - 1][s] + Yp[r + 1][s] + Yp[r][s - 1] + Yp[r][s + 1];
+            const float y = jac(Yp[r][s], B0[r][s], C0[r][s], be0, ns);
+            out[(size_t)(i0 + r - kMgNu) * nx0 + (k0 + s - kMgNu)] = y;
+            part += (double)y * (double)B0[r][s];
+        }
+    } else {
+        // last sweep on the core and one ring, into the free buffer
+        float (*Yu)[U0 + 1] = Y0[kMgNu & 1];
+        pair_sweep<U0>(Yp, Yu, B0, C0, kMgNu, U0 - 2 * kMgNu, be0);
+        __syncthreads();
+        float* wo = wout + (size_t)z * A.zs_e0;
+        for (int t = threadIdx.x; t < kCore2 * kCore2; t += kPairThreads) {
+            const int r = H0 + t / kCore2, s = H0 + t % kCore2;
+            const float u = Yu[r][s];
+            // the PCG operator as k_pcg_matvec evaluates it
+            const float wv = fmaf(C0[r][s], u,
+                                  be0 * (4.f * u - Yu[r][s + 1] - Yu[r][s - 1] - Yu[r + 1][s] - Yu[r - 1][s]));
+            const size_t g = (size_t)(i0 + r - H0) * nx0 + (k0 + s - H0);
+            out[g] = u;
+            wo[g] = wv;
+            part += (double)u * (double)B0[r][s];
+            part2 += (double)u * (double)wv;
+        }
     }
     if (dot) {
         const double v = block_sum<kPairThreads>(part, sh);
         if (threadIdx.x == 0) dot[(size_t)z * dot_zstride + blockIdx.y * gridDim.x + blockIdx.x] = v;
+    }
+    if (W && dot2) {
+        const double v = block_sum<kPairThreads>(part2, sh);
+        if (threadIdx.x == 0) dot2[(size_t)z * dot_zstride + blockIdx.y * gridDim.x + blockIdx.x] = v;
     }
 }
 
@@ -710,7 +741,8 @@ void launch_mg_setup(const MgPlan& P, const float* w2, float* mg, int batch, hip
 
 void launch_mg_vcycle(const MgPlan& P, const float* r, const float* w2, float* z, float* mg,
                       int batch, float beta, const double* beta_z, const int* skip,
-                      size_t skip_zstride, double* dot, size_t dot_zstride, hipStream_t st) {
+                      size_t skip_zstride, double* dot, size_t dot_zstride, hipStream_t st,
+                      float* wout, double* dot2) {
     const size_t n0 = (size_t)P.ny[0] * P.nx[0];
     float bl[kMgMaxLevels], sc[kMgMaxLevels];   // level beta; level scale 4^-l
     bl[0] = beta;
@@ -800,10 +832,14 @@ void launch_mg_vcycle(const MgPlan& P, const float* r, const float* w2, float* z
     for (int q = ntop - 1; q >= 0; --q) {
         const int l = top[q];
         double* d = l == 0 ? dot : nullptr;
-        if (P.pair[l]) {
-            hipLaunchKernelGGL(k_mg_up2, dim3(P.nx[l] / kCore2, P.ny[l] / kCore2, batch),
+        if (P.pair[l] && l == 0 && wout) {
+            hipLaunchKernelGGL(k_mg_up2<true>, dim3(P.nx[l] / kCore2, P.ny[l] / kCore2, batch),
                                dim3(kPairThreads), 0, st, pair(l), skip, skip_zstride, d,
-                               dot_zstride);
+                               dot_zstride, wout, dot2);
+        } else if (P.pair[l]) {
+            hipLaunchKernelGGL(k_mg_up2<false>, dim3(P.nx[l] / kCore2, P.ny[l] / kCore2, batch),
+                               dim3(kPairThreads), 0, st, pair(l), skip, skip_zstride, d,
+                               dot_zstride, nullptr, nullptr);
         } else {
             MgLevel L = level(l);
             L.e = mg + P.e[l + 1];
@@ -821,7 +857,18 @@ void launch_pcg_mg_prec(const PcgArgs& a, int it, const MgPlan& P, float* mg, hi
     const int slot = it < 0 ? 1 : (it & 1);
     launch_mg_vcycle(P, a.r, a.w2, a.z, mg, a.batch, a.beta, a.beta_z, &a.st[0].done,
                      sizeof(PcgState) / sizeof(int), a.parts + a.L.rz + (size_t)slot * a.L.nrz,
-                     a.L.zstride, st);
+                     a.L.zstride, st, nullptr, nullptr);
+}
+
+bool mg_pipelined_ok(const MgPlan& P) { return P.ok && P.ngrid >= 2 && P.pair[0]; }
+
+void launch_pcg_mg_prec_w(const PcgArgs& a, int i, const MgPlan& P, float* mg, hipStream_t st) {
+    // u_i = V(r_i) into z, w_i = A u_i into q; gamma_i = <r_i, u_i> and
+    // delta_i = <u_i, w_i> partials into parity slot i & 1
+    const int slot = i & 1;
+    launch_mg_vcycle(P, a.r, a.w2, a.z, mg, a.batch, a.beta, a.beta_z, &a.st[0].done,
+                     sizeof(PcgState) / sizeof(int), a.parts + a.L.rz + (size_t)slot * a.L.nrz,
+                     a.L.zstride, st, a.q, a.parts + a.L.dl + (size_t)slot * a.L.nrz);
 }
 
 }  // namespace dect
