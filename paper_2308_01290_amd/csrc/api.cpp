@@ -521,6 +521,14 @@ struct dect_solver {
                                      // B holds f^(k+1) during an iteration
     unsigned* cnt_proj;
     PcgBufs pcg;
+    // Concurrency within an iteration: the f-step and the rho_e step run on
+    // `side` while the t' PCG runs on st (all three read iterate k only);
+    // t' is double-buffered (the PCG writes t_next) and the side stream has
+    // its own FFT scratch.  side == nullptr: everything on st.
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    float* t_next = nullptr;
+    float2* fft2 = nullptr;
     int k;
     double beta;
     int last_pcg;
@@ -542,21 +550,58 @@ static hipEvent_t take_event(dect_solver* s) {
 }
 
 // record a start event (returns nullptr when timing is off)
-static hipEvent_t mark(dect_solver* s) {
+static hipEvent_t mark(dect_solver* s, hipStream_t st) {
     if (!s->timing) return nullptr;
     hipEvent_t e = take_event(s);
-    if (e) (void)hipEventRecord(e, s->st);
+    if (e) (void)hipEventRecord(e, st);
     return e;
 }
-static void mark_end(dect_solver* s, hipEvent_t start, std::vector<std::pair<hipEvent_t, hipEvent_t>>& v) {
+static void mark_end(dect_solver* s, hipStream_t st, hipEvent_t start,
+                     std::vector<std::pair<hipEvent_t, hipEvent_t>>& v) {
     if (!start) return;
     hipEvent_t e = take_event(s);
     if (!e) {
         s->ev_pool.push_back(start);
         return;
     }
-    (void)hipEventRecord(e, s->st);
+    (void)hipEventRecord(e, st);
     v.emplace_back(start, e);
+}
+
+// second stream and fork/join events (default priority); without them the
+// iteration runs on the solver's stream alone
+static void make_side(dect_solver* s) {
+    if (hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking) != hipSuccess) {
+        s->side = nullptr;
+        return;
+    }
+    if (hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming) != hipSuccess) {
+        if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
+        s->ev_fork = nullptr;
+        (void)hipStreamDestroy(s->side);
+        s->side = nullptr;
+    }
+}
+static void free_side(dect_solver* s) {
+    if (!s->side) return;
+    (void)hipStreamSynchronize(s->side);
+    (void)hipEventDestroy(s->ev_fork);
+    (void)hipEventDestroy(s->ev_join);
+    (void)hipStreamDestroy(s->side);
+    s->side = nullptr;
+}
+// stream for the side work of an iteration, forked from st
+static hipStream_t fork_side(dect_solver* s) {
+    if (!s->side) return s->st;
+    (void)hipEventRecord(s->ev_fork, s->st);
+    (void)hipStreamWaitEvent(s->side, s->ev_fork, 0);
+    return s->side;
+}
+static void join_side(dect_solver* s) {
+    if (!s->side) return;
+    (void)hipEventRecord(s->ev_join, s->side);
+    (void)hipStreamWaitEvent(s->st, s->ev_join, 0);
 }
 
 extern "C" {
@@ -752,6 +797,8 @@ static size_t solver_layout(const BatchGeo& B, char* base, dect_solver* s, int s
     float2* fft = c.take<float2>(npix);
     float* rho = c.take<float>(npix);
     float* tt = c.take<float>(npix);
+    float* tnext = c.take<float>(npix);
+    float2* fft2 = c.take<float2>(npix);
     double* part_img = c.take<double>((size_t)batch * grad_nblocks(g.ny, g.nx) * 3);
     double* part_proj = c.take<double>((size_t)batch * proj_nblocks(B.nv_max, B.nd_max));
     double* alpha = c.take<double>((size_t)batch);
@@ -780,6 +827,8 @@ static size_t solver_layout(const BatchGeo& B, char* base, dect_solver* s, int s
         s->fft = fft;
         s->rho = rho;
         s->t = tt;
+        s->t_next = tnext;
+        s->fft2 = fft2;
         s->muL = pb.r;   // init-time aliases
         s->muH = pb.z;
         s->fbpq = reinterpret_cast<float*>(zq);
@@ -883,6 +932,7 @@ static int solver_create(const dect_geometry* geoms, const dect_params* p, int32
     s->k = 0;
     s->beta = s->rp.beta0;
     s->last_pcg = 0;
+    make_side(s);
     *out = s;
     DECT_HIP(hipGetLastError());
     return DECT_OK;
@@ -915,6 +965,7 @@ int dect_solver_destroy(dect_solver* s) {
         (void)hipEventDestroy(p.second);
     }
     for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
+    free_side(s);
     if (s->owns_ws) dev_free(&s->own);
     delete s;
     return DECT_OK;
@@ -991,7 +1042,7 @@ int dect_solver_set_state(dect_solver* s, const float* lo, const float* hi, cons
 
 // rho_e step, subproblem (13b) by the FFT closed form (reads f^(k), rho^(k);
 // writes rho^(k+1) in place)
-static void rho_step(dect_solver* s) {
+static void rho_step(dect_solver* s, hipStream_t st, float2* scratch) {
     const Geom& g = s->g;
     const Resolved& R = s->rp;
     FftArgs fa;
@@ -1011,7 +1062,7 @@ static void rho_step(dect_solver* s) {
     fa.lam = R.p.lambda;
     fa.c = 1.0;
     fa.out = s->rho;
-    launch_fft_solve(g.ny, g.nx, s->batch, fa, s->fft, s->st);
+    launch_fft_solve(g.ny, g.nx, s->batch, fa, scratch, st);
 }
 
 // t' step, subproblem (13c) by PCG (reads f^(k), t'^(k); in place)
@@ -1019,7 +1070,8 @@ static int t_step(dect_solver* s) {
     const Geom& g = s->g;
     const Resolved& R = s->rp;
     PcgArgs pc;
-    fill_pcg_args(&pc, s->pcg, g.ny, g.nx, s->batch, s->t);
+    fill_pcg_args(&pc, s->pcg, g.ny, g.nx, s->batch, s->t_next);
+    pc.x0 = s->t;   // t'^(k) stays readable for the concurrent f-step
     pc.beta = (float)s->beta;
     pc.thr = (float)(R.p.lambda / s->beta);
     pc.tol2 = R.p.t_tol * R.p.t_tol;
@@ -1041,7 +1093,10 @@ static int one_iteration_image(dect_solver* s) {
     const Geom& g = s->g;
     const Resolved& R = s->rp;
     const Model& M = s->M;
-    hipEvent_t t0 = mark(s);
+    // f-step and rho_e step on the side stream, t' step on st (concurrently)
+    const hipStream_t side = fork_side(s);
+    float2* scratch = s->side ? s->fft2 : s->fft;
+    hipEvent_t t0 = mark(s, side);
     for (int comp = 0; comp < 2; ++comp) {
         FftArgs fa;
         fa.src = FFT_SRC_IMGF;
@@ -1075,12 +1130,15 @@ static int one_iteration_image(dect_solver* s) {
         fa.thr = (float)(R.p.lambda / s->beta);
         fa.beta_z = s->beta_d;
         fa.lam = R.p.lambda;
-        launch_fft_solve(g.ny, g.nx, s->batch, fa, s->fft, s->st);
+        launch_fft_solve(g.ny, g.nx, s->batch, fa, scratch, side);
     }
-    mark_end(s, t0, s->ev_bp);
-    rho_step(s);
-    if (int rc = t_step(s)) return rc;
+    mark_end(s, side, t0, s->ev_bp);
+    rho_step(s, side, scratch);
+    const int rc = t_step(s);
+    join_side(s);
+    if (rc) return rc;
     std::swap(s->f, s->B);
+    std::swap(s->t, s->t_next);
     s->beta *= R.kappa;
     s->k += 1;
     launch_set_beta(s->beta_d, s->kappa_d, 0, s->batch, s->beta, R.kappa, s->st);
@@ -1108,12 +1166,14 @@ static int one_iteration(dect_solver* s) {
     a.lam = R.p.lambda;
     a.bf16 = s->storage != DECT_STORAGE_FP32;
     void* dir = a.bf16 ? static_cast<void*>(s->dpad16) : static_cast<void*>(s->dpad);
-    // f-step: A^T of the combined residuals, gradient, A of the direction
-    hipEvent_t t0 = mark(s);
-    launch_backproject(g, s->tab, s->S, s->batch, s->B, nullptr, 0, s->st, a.bf16, s->geo.sym_mode);
-    mark_end(s, t0, s->ev_bp);
+    // f-step (A^T of the combined residuals, gradient, A of the direction) and
+    // rho_e step on the side stream, t' step on st: all three read iterate k
+    const hipStream_t side = fork_side(s);
+    hipEvent_t t0 = mark(s, side);
+    launch_backproject(g, s->tab, s->S, s->batch, s->B, nullptr, 0, side, a.bf16, s->geo.sym_mode);
+    mark_end(s, side, t0, s->ev_bp);
     const PadLayout P = solver_pad(s);
-    launch_grad(s->M, a, P, s->f, s->B, s->rho, s->t, dir, s->part_img, s->st);
+    launch_grad(s->M, a, P, s->f, s->B, s->rho, s->t, dir, s->part_img, side);
     ProjArgs pa;
     pa.res = s->zq;
     pa.c00 = (float)s->M.C[0][0];
@@ -1131,11 +1191,14 @@ static int one_iteration(dect_solver* s) {
     pa.counter = s->cnt_proj;
     pa.pad_bf16 = pa.res_bf16 = a.bf16;
     pa.sym_all = s->geo.sym_mode == 1;
-    hipEvent_t t1 = mark(s);
-    launch_project(g, P, s->tab, dir, s->batch, PROJ_LINESEARCH, pa, s->st);
-    mark_end(s, t1, s->ev_fp);
-    rho_step(s);
-    if (int rc = t_step(s)) return rc;
+    hipEvent_t t1 = mark(s, side);
+    launch_project(g, P, s->tab, dir, s->batch, PROJ_LINESEARCH, pa, side);
+    mark_end(s, side, t1, s->ev_fp);
+    rho_step(s, side, s->side ? s->fft2 : s->fft);
+    const int rc = t_step(s);
+    join_side(s);
+    if (rc) return rc;
+    std::swap(s->t, s->t_next);
     // f^(k+1), residual sinograms
     launch_update(a, P, s->tab, s->alpha, dir, s->f, s->S, s->zq, s->beta_d,
                   s->kappa_d, s->st);
@@ -1241,6 +1304,8 @@ static size_t image_layout(int nx, int ny, int batch, char* base, dect_solver* s
     float2* fft = c.take<float2>(npix);
     float* rho = c.take<float>(npix);
     float* tt = c.take<float>(npix);
+    float* tnext = c.take<float>(npix);
+    float2* fft2 = c.take<float2>(npix);
     float* muL = c.take<float>(npix);
     float* muH = c.take<float>(npix);
     double* beta_d = c.take<double>((size_t)batch);
@@ -1253,6 +1318,8 @@ static size_t image_layout(int nx, int ny, int batch, char* base, dect_solver* s
         s->fft = fft;
         s->rho = rho;
         s->t = tt;
+        s->t_next = tnext;
+        s->fft2 = fft2;
         s->muL = muL;
         s->muH = muH;
         s->beta_d = beta_d;
@@ -1327,6 +1394,7 @@ int dect_image_solver_create(int32_t n_x, int32_t n_y, const dect_params* p, int
     s->k = 0;
     s->beta = s->rp.beta0;
     s->last_pcg = 0;
+    make_side(s);
     *out = s;
     return DECT_OK;
 }

@@ -329,6 +329,7 @@ struct PcgArgs {
     int prec;                // PcgPrec
     int nrz_used;            // entries of the <r, z> partial sums this preconditioner writes
     float* x;                // in: x0 (also HT input), out: solution
+    const float* x0 = nullptr;   // when set: x0 (and HT input), x only written
     float *r, *z, *p0, *p1, *q, *w2;
     double* parts;           // [batch][PcgParts::zstride]
     PcgParts L;

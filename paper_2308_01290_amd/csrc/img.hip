@@ -411,7 +411,7 @@ __global__ __launch_bounds__(256) void k_pcg_init(PcgArgs a, ModelF M, const flo
     slice_beta_thr(a, z);
     const size_t zo = (size_t)z * npix;
     double* P = a.parts + (size_t)z * a.L.zstride;
-    const float* x = a.x + zo;
+    const float* x = (a.x0 ? a.x0 : a.x) + zo;
     double rz = 0.0, rr = 0.0, ws = 0.0;
     for (int q = 0; q < kPcgPix; ++q) {
         const int p = blockIdx.x * kPcgBlock + q * 256 + threadIdx.x;
@@ -435,6 +435,7 @@ __global__ __launch_bounds__(256) void k_pcg_init(PcgArgs a, ModelF M, const flo
         if (v_out) v_out[zo + p] = kept.y;
         // r0 = b - A x0 = w (g - w x0) - beta D^T S(x0)
         const float r = (float)(w * (g - w * (double)x[p])) - a.beta * dts;
+        if (a.x0) a.x[zo + p] = x[p];
         const float w2 = (float)(w * w);
         a.w2[zo + p] = w2;
         a.r[zo + p] = r;
