@@ -387,43 +387,83 @@ static void apply_prec(const PcgArgs& a, int it, const PcgBufs& b, float2* fft_s
 // Runs PCG iterations (after an init kernel) until every slice converged or
 // max_iter.  The host checks convergence once per chunk of iterations; the
 // first chunk is sized from the previous solve.  Returns the largest count.
-static int run_pcg(PcgArgs& a, const PcgBufs& b, int max_iter, int first_chunk,
-                   float2* fft_scratch, hipStream_t st, int* iters_out) {
+// A PCG solve in two halves: pcg_enqueue puts the set-up and a first chunk of
+// iterations on the stream and returns at once; pcg_finish waits for the
+// host-visible stopping flags and enqueues further chunks until every slice
+// stopped (or max_iter).  The host checks once per chunk; the first chunk is
+// sized from the previous solve.
+struct PcgRun {
+    PcgArgs a;
+    int it = 0, max_iter = 0;
+    bool piped = false;        // pipelined form (multigrid with the fused last kernel)
+    PcgState* hs = nullptr;    // host copy of the flags (pinned when the caller has it)
+    std::vector<PcgState> own;
+};
+
+static void pcg_chunk(PcgRun& R, const PcgBufs& b, float2* fft_scratch, hipStream_t st, int chunk) {
+    PcgArgs& a = R.a;
+    for (int c = 0; c < chunk && R.it < R.max_iter; ++c, ++R.it) {
+        if (R.piped) {
+            launch_pcg_cg_update(a, R.it, st);
+            launch_pcg_mg_prec_w(a, R.it + 1, b.mg_plan, b.mg, st);
+            continue;
+        }
+        launch_pcg_matvec(a, R.it, st);
+        launch_pcg_update(a, R.it, st);
+        apply_prec(a, R.it, b, fft_scratch, st);
+    }
+    launch_pcg_check(a, R.it, st);
+}
+
+static int pcg_enqueue(PcgRun& R, const PcgBufs& b, float2* fft_scratch, hipStream_t st,
+                       int first_chunk, PcgState* pinned) {
+    PcgArgs& a = R.a;
     if (a.prec == PREC_MG) launch_mg_setup(b.mg_plan, a.w2, b.mg, a.batch, st);
     // with the multigrid preconditioner on sizes whose finest V-cycle kernel
     // can also apply A, the pipelined form: one reduction per iteration
-    const bool piped = a.prec == PREC_MG && mg_pipelined_ok(b.mg_plan);
-    if (piped)
+    R.piped = a.prec == PREC_MG && mg_pipelined_ok(b.mg_plan);
+    if (R.piped)
         launch_pcg_mg_prec_w(a, 0, b.mg_plan, b.mg, st);
     else
         apply_prec(a, -1, b, fft_scratch, st);
-    int it = 0;
-    int chunk = std::max(2, first_chunk);
-    std::vector<PcgState> hs(a.batch);
+    R.it = 0;
+    if (pinned) {
+        R.hs = pinned;
+    } else {
+        R.own.resize(a.batch);
+        R.hs = R.own.data();
+    }
+    pcg_chunk(R, b, fft_scratch, st, std::max(2, first_chunk));
+    DECT_HIP(hipGetLastError());
+    DECT_HIP(hipMemcpyAsync(R.hs, a.st, sizeof(PcgState) * a.batch, hipMemcpyDeviceToHost, st));
+    return DECT_OK;
+}
+
+static int pcg_finish(PcgRun& R, const PcgBufs& b, float2* fft_scratch, hipStream_t st,
+                      int* iters_out) {
+    const int batch = R.a.batch;
     while (true) {
-        for (int c = 0; c < chunk && it < max_iter; ++c, ++it) {
-            if (piped) {
-                launch_pcg_cg_update(a, it, st);
-                launch_pcg_mg_prec_w(a, it + 1, b.mg_plan, b.mg, st);
-                continue;
-            }
-            launch_pcg_matvec(a, it, st);
-            launch_pcg_update(a, it, st);
-            apply_prec(a, it, b, fft_scratch, st);
-        }
-        launch_pcg_check(a, it, st);
-        DECT_HIP(hipGetLastError());
-        DECT_HIP(hipMemcpyAsync(hs.data(), a.st, sizeof(PcgState) * a.batch, hipMemcpyDeviceToHost, st));
         DECT_HIP(hipStreamSynchronize(st));
         bool all = true;
-        for (int z = 0; z < a.batch; ++z) all = all && hs[z].done;
-        if (all || it >= max_iter) break;
-        chunk = 4;
+        for (int z = 0; z < batch; ++z) all = all && R.hs[z].done;
+        if (all || R.it >= R.max_iter) break;
+        pcg_chunk(R, b, fft_scratch, st, 4);
+        DECT_HIP(hipGetLastError());
+        DECT_HIP(hipMemcpyAsync(R.hs, R.a.st, sizeof(PcgState) * batch, hipMemcpyDeviceToHost, st));
     }
     int mx = 0;
-    for (int z = 0; z < a.batch; ++z) mx = std::max(mx, hs[z].iters);
+    for (int z = 0; z < batch; ++z) mx = std::max(mx, R.hs[z].iters);
     if (iters_out) *iters_out = mx;
     return DECT_OK;
+}
+
+static int run_pcg(PcgArgs& a, const PcgBufs& b, int max_iter, int first_chunk,
+                   float2* fft_scratch, hipStream_t st, int* iters_out) {
+    PcgRun R;
+    R.a = a;
+    R.max_iter = max_iter;
+    if (int rc = pcg_enqueue(R, b, fft_scratch, st, first_chunk, nullptr)) return rc;
+    return pcg_finish(R, b, fft_scratch, st, iters_out);
 }
 
 }  // namespace dect
@@ -527,6 +567,12 @@ struct dect_solver {
     // its own FFT scratch.  side == nullptr: everything on st.
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // software pipelining of consecutive iterations (see one_iteration)
+    hipEvent_t ev_init = nullptr, ev_side = nullptr, ev_upd = nullptr, ev_tdone = nullptr;
+    bool bp_pending = false;    // this iteration's back-projection is already on `side`
+    bool upd_pending = false;   // the last f update ran on `side`, not yet joined
+    PcgState* hs_pinned = nullptr;
+    PcgRun prun;
     float* t_next = nullptr;
     float2* fft2 = nullptr;
     int k;
@@ -571,25 +617,34 @@ static void mark_end(dect_solver* s, hipStream_t st, hipEvent_t start,
 // second stream and fork/join events (default priority); without them the
 // iteration runs on the solver's stream alone
 static void make_side(dect_solver* s) {
+    if (hipHostMalloc(reinterpret_cast<void**>(&s->hs_pinned), sizeof(PcgState) * s->batch) !=
+        hipSuccess)
+        s->hs_pinned = nullptr;
     if (hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking) != hipSuccess) {
         s->side = nullptr;
         return;
     }
-    if (hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming) != hipSuccess) {
-        if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
-        s->ev_fork = nullptr;
+    hipEvent_t* evs[6] = {&s->ev_fork, &s->ev_join, &s->ev_init, &s->ev_side, &s->ev_upd, &s->ev_tdone};
+    bool ok = true;
+    for (hipEvent_t* e : evs) ok = ok && hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        for (hipEvent_t* e : evs)
+            if (*e) (void)hipEventDestroy(*e);
+        for (hipEvent_t* e : evs) *e = nullptr;
         (void)hipStreamDestroy(s->side);
         s->side = nullptr;
     }
 }
 static void free_side(dect_solver* s) {
-    if (!s->side) return;
-    (void)hipStreamSynchronize(s->side);
-    (void)hipEventDestroy(s->ev_fork);
-    (void)hipEventDestroy(s->ev_join);
-    (void)hipStreamDestroy(s->side);
-    s->side = nullptr;
+    if (s->side) {
+        (void)hipStreamSynchronize(s->side);
+        for (hipEvent_t e : {s->ev_fork, s->ev_join, s->ev_init, s->ev_side, s->ev_upd, s->ev_tdone})
+            (void)hipEventDestroy(e);
+        (void)hipStreamDestroy(s->side);
+        s->side = nullptr;
+    }
+    if (s->hs_pinned) (void)hipHostFree(s->hs_pinned);
+    s->hs_pinned = nullptr;
 }
 // stream for the side work of an iteration, forked from st
 static hipStream_t fork_side(dect_solver* s) {
@@ -1066,10 +1121,14 @@ static void rho_step(dect_solver* s, hipStream_t st, float2* scratch) {
 }
 
 // t' step, subproblem (13c) by PCG (reads f^(k), t'^(k); in place)
-static int t_step(dect_solver* s) {
+// t' step, first half: the initial residual (reads f^(k) and t'^(k); the
+// solution goes to t_next) and the first chunk of PCG iterations on st.
+// `after_init`, if given, is recorded on st once f^(k) has been read.
+static int t_step_start(dect_solver* s, hipEvent_t after_init) {
     const Geom& g = s->g;
     const Resolved& R = s->rp;
-    PcgArgs pc;
+    PcgArgs& pc = s->prun.a;
+    pc = PcgArgs{};
     fill_pcg_args(&pc, s->pcg, g.ny, g.nx, s->batch, s->t_next);
     pc.x0 = s->t;   // t'^(k) stays readable for the concurrent f-step
     pc.beta = (float)s->beta;
@@ -1080,8 +1139,15 @@ static int t_step(dect_solver* s) {
     pc.active = s->active_d;
     if (int rc = choose_prec(R.p.t_precond, s->pcg, s->beta, &pc)) return rc;
     launch_pcg_init_model(s->M, pc, s->f, s->st);
+    if (after_init) DECT_HIP(hipEventRecord(after_init, s->st));
+    s->prun.max_iter = R.p.t_maxit;
+    return pcg_enqueue(s->prun, s->pcg, s->fft, s->st, s->last_pcg + 2, s->hs_pinned);
+}
+
+// second half: wait for the stopping flags, more chunks while needed
+static int t_step_finish(dect_solver* s) {
     int iters = 0;
-    if (int rc = run_pcg(pc, s->pcg, R.p.t_maxit, s->last_pcg + 2, s->fft, s->st, &iters)) return rc;
+    if (int rc = pcg_finish(s->prun, s->pcg, s->fft, s->st, &iters)) return rc;
     s->last_pcg = iters;
     return DECT_OK;
 }
@@ -1093,8 +1159,10 @@ static int one_iteration_image(dect_solver* s) {
     const Geom& g = s->g;
     const Resolved& R = s->rp;
     const Model& M = s->M;
-    // f-step and rho_e step on the side stream, t' step on st (concurrently)
+    // t' step on st, enqueued first; f-step and rho_e step on the side stream
+    // (all read iterate k; the f-step writes f^(k+1) into B)
     const hipStream_t side = fork_side(s);
+    if (int rc = t_step_start(s, nullptr)) return rc;
     float2* scratch = s->side ? s->fft2 : s->fft;
     hipEvent_t t0 = mark(s, side);
     for (int comp = 0; comp < 2; ++comp) {
@@ -1134,7 +1202,7 @@ static int one_iteration_image(dect_solver* s) {
     }
     mark_end(s, side, t0, s->ev_bp);
     rho_step(s, side, scratch);
-    const int rc = t_step(s);
+    const int rc = t_step_finish(s);
     join_side(s);
     if (rc) return rc;
     std::swap(s->f, s->B);
@@ -1146,7 +1214,17 @@ static int one_iteration_image(dect_solver* s) {
     return DECT_OK;
 }
 
-static int one_iteration(dect_solver* s) {
+// Outer iteration k of the sinogram form.  With the side stream:
+//   st:   t' step (initial residual reads f^(k), t'^(k); PCG writes t_next),
+//         then beta <- kappa beta once the side work has read beta^(k);
+//   side: back-projection of S^(k), gradient, forward projection and line
+//         search, rho_e step; then, once the PCG has read f^(k), the update
+//         f^(k+1), S^(k+1) and, when another iteration follows (`more`), its
+//         back-projection, which needs S^(k+1) only.
+// So the host's wait for the PCG stopping flags overlaps the next
+// back-projection.  Events order every hand-over between the streams; the
+// iteration after one with `more` starts with its back-projection queued.
+static int one_iteration(dect_solver* s, bool more = false) {
     if (s->image) return one_iteration_image(s);
     const Geom& g = s->g;
     const Resolved& R = s->rp;
@@ -1166,13 +1244,25 @@ static int one_iteration(dect_solver* s) {
     a.lam = R.p.lambda;
     a.bf16 = s->storage != DECT_STORAGE_FP32;
     void* dir = a.bf16 ? static_cast<void*>(s->dpad16) : static_cast<void*>(s->dpad);
-    // f-step (A^T of the combined residuals, gradient, A of the direction) and
-    // rho_e step on the side stream, t' step on st: all three read iterate k
-    const hipStream_t side = fork_side(s);
-    hipEvent_t t0 = mark(s, side);
-    launch_backproject(g, s->tab, s->S, s->batch, s->B, nullptr, 0, side, a.bf16, s->geo.sym_mode);
-    mark_end(s, side, t0, s->ev_bp);
     const PadLayout P = solver_pad(s);
+    const bool two = s->side != nullptr;
+    const hipStream_t side = two ? s->side : s->st;
+    // st: the t' step first (f^(k) from the previous update on `side`)
+    if (two && s->upd_pending) DECT_HIP(hipStreamWaitEvent(s->st, s->ev_upd, 0));
+    if (two && !s->bp_pending) DECT_HIP(hipEventRecord(s->ev_fork, s->st));
+    if (int rc = t_step_start(s, two ? s->ev_init : nullptr)) return rc;
+    // side: f-step and rho_e step
+    if (two) {
+        if (!s->bp_pending)
+            DECT_HIP(hipStreamWaitEvent(side, s->ev_fork, 0));
+        else
+            DECT_HIP(hipStreamWaitEvent(side, s->ev_tdone, 0));   // t'^(k), beta^(k)
+    }
+    if (!s->bp_pending) {
+        hipEvent_t t0 = mark(s, side);
+        launch_backproject(g, s->tab, s->S, s->batch, s->B, nullptr, 0, side, a.bf16, s->geo.sym_mode);
+        mark_end(s, side, t0, s->ev_bp);
+    }
     launch_grad(s->M, a, P, s->f, s->B, s->rho, s->t, dir, s->part_img, side);
     ProjArgs pa;
     pa.res = s->zq;
@@ -1194,15 +1284,36 @@ static int one_iteration(dect_solver* s) {
     hipEvent_t t1 = mark(s, side);
     launch_project(g, P, s->tab, dir, s->batch, PROJ_LINESEARCH, pa, side);
     mark_end(s, side, t1, s->ev_fp);
-    rho_step(s, side, s->side ? s->fft2 : s->fft);
-    const int rc = t_step(s);
-    join_side(s);
-    if (rc) return rc;
+    rho_step(s, side, two ? s->fft2 : s->fft);
+    if (two) {
+        DECT_HIP(hipEventRecord(s->ev_side, side));          // beta^(k) no longer read there
+        DECT_HIP(hipStreamWaitEvent(side, s->ev_init, 0));   // f^(k) read by the PCG
+    }
+    // f^(k+1), residual sinograms (beta is stepped on st below)
+    launch_update(a, P, s->tab, s->alpha, dir, s->f, s->S, s->zq, nullptr, nullptr, side);
+    if (two) DECT_HIP(hipEventRecord(s->ev_upd, side));
+    s->bp_pending = false;
+    if (two && more) {   // next back-projection while the host waits for the PCG
+        hipEvent_t t2 = mark(s, side);
+        launch_backproject(g, s->tab, s->S, s->batch, s->B, nullptr, 0, side, a.bf16, s->geo.sym_mode);
+        mark_end(s, side, t2, s->ev_bp);
+        s->bp_pending = true;
+    }
+    s->upd_pending = two;
+    if (int rc = t_step_finish(s)) return rc;
+    // st: beta^(k+1) once the side work has read beta^(k)
+    if (two) DECT_HIP(hipStreamWaitEvent(s->st, s->ev_side, 0));
+    launch_step_beta(s->beta_d, s->kappa_d, s->batch, s->st);
     std::swap(s->t, s->t_next);
-    // f^(k+1), residual sinograms
-    launch_update(a, P, s->tab, s->alpha, dir, s->f, s->S, s->zq, s->beta_d,
-                  s->kappa_d, s->st);
-    round_state(s, 0, s->batch);
+    if (s->storage == DECT_STORAGE_BF16_STATE) {
+        if (two) DECT_HIP(hipStreamWaitEvent(s->st, s->ev_upd, 0));
+        round_state(s, 0, s->batch);
+    }
+    if (two) DECT_HIP(hipEventRecord(s->ev_tdone, s->st));
+    if (two && !more) {   // join: everything of this iteration is ordered before st's next work
+        DECT_HIP(hipStreamWaitEvent(s->st, s->ev_upd, 0));
+        s->upd_pending = false;
+    }
     s->beta *= R.kappa;
     s->k += 1;
     DECT_HIP(hipGetLastError());
@@ -1212,7 +1323,7 @@ static int one_iteration(dect_solver* s) {
 int dect_solver_iterate(dect_solver* s, int32_t n) {
     if (!s || n < 0) return fail(DECT_EINVAL, "dect_solver_iterate: bad arguments");
     for (int i = 0; i < n; ++i)
-        if (int rc = one_iteration(s)) return rc;
+        if (int rc = one_iteration(s, i + 1 < n)) return rc;
     return DECT_OK;
 }
 

@@ -285,6 +285,15 @@ __global__ void k_round_state(size_t n, float2* __restrict__ f, float* __restric
     t[i] = bf16_round(t[i]);
 }
 
+__global__ void k_step_beta(double* beta_z, const double* kappa_z, int n) {
+    const int z = blockIdx.x * blockDim.x + threadIdx.x;
+    if (z < n) beta_z[z] *= kappa_z[z];
+}
+
+void launch_step_beta(double* beta_z, const double* kappa_z, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_step_beta, dim3((n + 63) / 64), dim3(64), 0, st, beta_z, kappa_z, n);
+}
+
 void launch_round_state(size_t n, float2* f, float* rho, float* t, hipStream_t st) {
     hipLaunchKernelGGL(k_round_state, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, f, rho, t);
 }
