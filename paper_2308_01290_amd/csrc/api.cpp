@@ -415,8 +415,8 @@ static void pcg_chunk(PcgRun& R, const PcgBufs& b, float2* fft_scratch, hipStrea
     launch_pcg_check(a, R.it, st);
 }
 
-static int pcg_enqueue(PcgRun& R, const PcgBufs& b, float2* fft_scratch, hipStream_t st,
-                       int first_chunk, PcgState* pinned) {
+// set-up: preconditioner data and the first preconditioner application
+static void pcg_setup(PcgRun& R, const PcgBufs& b, float2* fft_scratch, hipStream_t st) {
     PcgArgs& a = R.a;
     if (a.prec == PREC_MG) launch_mg_setup(b.mg_plan, a.w2, b.mg, a.batch, st);
     // with the multigrid preconditioner on sizes whose finest V-cycle kernel
@@ -427,6 +427,12 @@ static int pcg_enqueue(PcgRun& R, const PcgBufs& b, float2* fft_scratch, hipStre
     else
         apply_prec(a, -1, b, fft_scratch, st);
     R.it = 0;
+}
+
+// the first chunk of iterations and the read-back of the stopping flags
+static int pcg_first_chunk(PcgRun& R, const PcgBufs& b, float2* fft_scratch, hipStream_t st,
+                           int first_chunk, PcgState* pinned) {
+    PcgArgs& a = R.a;
     if (pinned) {
         R.hs = pinned;
     } else {
@@ -437,6 +443,12 @@ static int pcg_enqueue(PcgRun& R, const PcgBufs& b, float2* fft_scratch, hipStre
     DECT_HIP(hipGetLastError());
     DECT_HIP(hipMemcpyAsync(R.hs, a.st, sizeof(PcgState) * a.batch, hipMemcpyDeviceToHost, st));
     return DECT_OK;
+}
+
+static int pcg_enqueue(PcgRun& R, const PcgBufs& b, float2* fft_scratch, hipStream_t st,
+                       int first_chunk, PcgState* pinned) {
+    pcg_setup(R, b, fft_scratch, st);
+    return pcg_first_chunk(R, b, fft_scratch, st, first_chunk, pinned);
 }
 
 static int pcg_finish(PcgRun& R, const PcgBufs& b, float2* fft_scratch, hipStream_t st,
@@ -566,7 +578,9 @@ struct dect_solver {
     // t' is double-buffered (the PCG writes t_next) and the side stream has
     // its own FFT scratch.  side == nullptr: everything on st.
     hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipStream_t pst = nullptr;   // the t' PCG's stream while an iterate call runs
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_entry = nullptr, ev_mdone = nullptr;
+    bool in_pipe = false;        // inside a run of pipelined iterations (pst, side forked)
     // software pipelining of consecutive iterations (see one_iteration)
     hipEvent_t ev_init = nullptr, ev_side = nullptr, ev_upd = nullptr, ev_tdone = nullptr;
     bool bp_pending = false;    // this iteration's back-projection is already on `side`
@@ -618,45 +632,71 @@ static void mark_end(dect_solver* s, hipStream_t st, hipEvent_t start,
 // iteration runs on the solver's stream alone
 static void make_side(dect_solver* s) {
     if (hipHostMalloc(reinterpret_cast<void**>(&s->hs_pinned), sizeof(PcgState) * s->batch) !=
-        hipSuccess)
+        hipSuccess) {
         s->hs_pinned = nullptr;
-    if (hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking) != hipSuccess) {
-        s->side = nullptr;
+        (void)hipGetLastError();
+    }
+    if (hipStreamCreateWithFlags(&s->pst, hipStreamNonBlocking) != hipSuccess) {
+        s->pst = nullptr;
+        (void)hipGetLastError();
         return;
     }
-    hipEvent_t* evs[6] = {&s->ev_fork, &s->ev_join, &s->ev_init, &s->ev_side, &s->ev_upd, &s->ev_tdone};
+    if (hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking) != hipSuccess) {
+        s->side = nullptr;
+        (void)hipGetLastError();
+        (void)hipStreamDestroy(s->pst);
+        s->pst = nullptr;
+        return;
+    }
+    hipEvent_t* evs[8] = {&s->ev_fork, &s->ev_join, &s->ev_init,  &s->ev_side,
+                          &s->ev_upd,  &s->ev_tdone, &s->ev_entry, &s->ev_mdone};
     bool ok = true;
     for (hipEvent_t* e : evs) ok = ok && hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
     if (!ok) {
+        (void)hipGetLastError();
         for (hipEvent_t* e : evs)
             if (*e) (void)hipEventDestroy(*e);
         for (hipEvent_t* e : evs) *e = nullptr;
         (void)hipStreamDestroy(s->side);
-        s->side = nullptr;
+        (void)hipStreamDestroy(s->pst);
+        s->side = s->pst = nullptr;
     }
 }
 static void free_side(dect_solver* s) {
     if (s->side) {
         (void)hipStreamSynchronize(s->side);
-        for (hipEvent_t e : {s->ev_fork, s->ev_join, s->ev_init, s->ev_side, s->ev_upd, s->ev_tdone})
+        (void)hipStreamSynchronize(s->pst);
+        for (hipEvent_t e : {s->ev_fork, s->ev_join, s->ev_init, s->ev_side, s->ev_upd, s->ev_tdone,
+                             s->ev_entry, s->ev_mdone})
             (void)hipEventDestroy(e);
         (void)hipStreamDestroy(s->side);
-        s->side = nullptr;
+        (void)hipStreamDestroy(s->pst);
+        s->side = s->pst = nullptr;
     }
     if (s->hs_pinned) (void)hipHostFree(s->hs_pinned);
     s->hs_pinned = nullptr;
 }
 // stream for the side work of an iteration, forked from st
-static hipStream_t fork_side(dect_solver* s) {
+// entry of an iterate call: the PCG stream and the side stream start after
+// the caller's stream; returns the PCG stream (the caller's without them)
+static hipStream_t enter_iter(dect_solver* s) {
     if (!s->side) return s->st;
-    (void)hipEventRecord(s->ev_fork, s->st);
-    (void)hipStreamWaitEvent(s->side, s->ev_fork, 0);
-    return s->side;
+    if (!s->in_pipe) {
+        (void)hipEventRecord(s->ev_entry, s->st);
+        (void)hipStreamWaitEvent(s->pst, s->ev_entry, 0);
+        (void)hipStreamWaitEvent(s->side, s->ev_entry, 0);
+        s->in_pipe = true;
+    }
+    return s->pst;
 }
-static void join_side(dect_solver* s) {
-    if (!s->side) return;
+// exit: the caller's stream waits for both
+static void leave_iter(dect_solver* s) {
+    if (!s->side || !s->in_pipe) return;
+    (void)hipEventRecord(s->ev_mdone, s->pst);
     (void)hipEventRecord(s->ev_join, s->side);
+    (void)hipStreamWaitEvent(s->st, s->ev_mdone, 0);
     (void)hipStreamWaitEvent(s->st, s->ev_join, 0);
+    s->in_pipe = false;
 }
 
 extern "C" {
@@ -1045,11 +1085,12 @@ static void project_residual(dect_solver* s, const float* lo, const float* hi) {
 }
 
 // BF16 state storage: the state images hold BF16 values from here on
-static void round_state(dect_solver* s, int z0, int n) {
+static void round_state(dect_solver* s, int z0, int n, hipStream_t st) {
     if (s->storage != DECT_STORAGE_BF16_STATE || n < 1) return;
     const size_t npix = (size_t)s->g.nx * s->g.ny;
-    launch_round_state(npix * n, s->f + z0 * npix, s->rho + z0 * npix, s->t + z0 * npix, s->st);
+    launch_round_state(npix * n, s->f + z0 * npix, s->rho + z0 * npix, s->t + z0 * npix, st);
 }
+static void round_state(dect_solver* s, int z0, int n) { round_state(s, z0, n, s->st); }
 
 int dect_solver_init(dect_solver* s, const float* lo, const float* hi) {
     if (!s || !lo || !hi) return fail(DECT_EINVAL, "dect_solver_init: NULL argument");
@@ -1124,7 +1165,7 @@ static void rho_step(dect_solver* s, hipStream_t st, float2* scratch) {
 // t' step, first half: the initial residual (reads f^(k) and t'^(k); the
 // solution goes to t_next) and the first chunk of PCG iterations on st.
 // `after_init`, if given, is recorded on st once f^(k) has been read.
-static int t_step_start(dect_solver* s, hipEvent_t after_init) {
+static int t_step_start(dect_solver* s, hipStream_t ms, hipEvent_t after_init) {
     const Geom& g = s->g;
     const Resolved& R = s->rp;
     PcgArgs& pc = s->prun.a;
@@ -1138,16 +1179,23 @@ static int t_step_start(dect_solver* s, hipEvent_t after_init) {
     pc.lam = R.p.lambda;
     pc.active = s->active_d;
     if (int rc = choose_prec(R.p.t_precond, s->pcg, s->beta, &pc)) return rc;
-    launch_pcg_init_model(s->M, pc, s->f, s->st);
-    if (after_init) DECT_HIP(hipEventRecord(after_init, s->st));
+    launch_pcg_init_model(s->M, pc, s->f, ms);
+    if (after_init) DECT_HIP(hipEventRecord(after_init, ms));
     s->prun.max_iter = R.p.t_maxit;
-    return pcg_enqueue(s->prun, s->pcg, s->fft, s->st, s->last_pcg + 2, s->hs_pinned);
+    pcg_setup(s->prun, s->pcg, s->fft, ms);
+    return DECT_OK;
+}
+
+// the first chunk of PCG iterations (after t_step_start; the host enqueues the
+// other stream's work in between so that it is not queued behind this chunk)
+static int t_step_chunk(dect_solver* s, hipStream_t ms) {
+    return pcg_first_chunk(s->prun, s->pcg, s->fft, ms, s->last_pcg + 2, s->hs_pinned);
 }
 
 // second half: wait for the stopping flags, more chunks while needed
-static int t_step_finish(dect_solver* s) {
+static int t_step_finish(dect_solver* s, hipStream_t ms) {
     int iters = 0;
-    if (int rc = pcg_finish(s->prun, s->pcg, s->fft, s->st, &iters)) return rc;
+    if (int rc = pcg_finish(s->prun, s->pcg, s->fft, ms, &iters)) return rc;
     s->last_pcg = iters;
     return DECT_OK;
 }
@@ -1155,15 +1203,19 @@ static int t_step_finish(dect_solver* s) {
 // One outer iteration of the image-domain form: f1 and f2 by the FFT closed
 // forms of (13a) (each with the other basis at iterate k), then the rho_e and
 // t' steps, all reading iterate k; f^(k+1) is built in B and swapped in.
-static int one_iteration_image(dect_solver* s) {
+static int one_iteration_image(dect_solver* s, bool more) {
     const Geom& g = s->g;
     const Resolved& R = s->rp;
     const Model& M = s->M;
-    // t' step on st, enqueued first; f-step and rho_e step on the side stream
-    // (all read iterate k; the f-step writes f^(k+1) into B)
-    const hipStream_t side = fork_side(s);
-    if (int rc = t_step_start(s, nullptr)) return rc;
-    float2* scratch = s->side ? s->fft2 : s->fft;
+    // t' step on the PCG stream, enqueued first; f-step and rho_e step on the
+    // side stream (all read iterate k; the f-step writes f^(k+1) into B)
+    const hipStream_t ms = enter_iter(s);
+    const bool two = s->side != nullptr;
+    const hipStream_t side = two ? s->side : s->st;
+    if (two && s->upd_pending) DECT_HIP(hipStreamWaitEvent(ms, s->ev_upd, 0));     // f^(k)
+    if (int rc = t_step_start(s, ms, nullptr)) return rc;
+    if (two && s->upd_pending) DECT_HIP(hipStreamWaitEvent(side, s->ev_tdone, 0));  // t'^(k), beta^(k)
+    float2* scratch = two ? s->fft2 : s->fft;
     hipEvent_t t0 = mark(s, side);
     for (int comp = 0; comp < 2; ++comp) {
         FftArgs fa;
@@ -1202,14 +1254,21 @@ static int one_iteration_image(dect_solver* s) {
     }
     mark_end(s, side, t0, s->ev_bp);
     rho_step(s, side, scratch);
-    const int rc = t_step_finish(s);
-    join_side(s);
-    if (rc) return rc;
+    if (two) DECT_HIP(hipEventRecord(s->ev_upd, side));
+    if (int rc = t_step_chunk(s, ms)) return rc;
+    if (int rc = t_step_finish(s, ms)) return rc;
+    if (two) DECT_HIP(hipStreamWaitEvent(ms, s->ev_upd, 0));   // side done with beta^(k), t'^(k)
     std::swap(s->f, s->B);
     std::swap(s->t, s->t_next);
     s->beta *= R.kappa;
     s->k += 1;
-    launch_set_beta(s->beta_d, s->kappa_d, 0, s->batch, s->beta, R.kappa, s->st);
+    launch_set_beta(s->beta_d, s->kappa_d, 0, s->batch, s->beta, R.kappa, ms);
+    if (two) DECT_HIP(hipEventRecord(s->ev_tdone, ms));
+    s->upd_pending = two;
+    if (!more) {
+        leave_iter(s);
+        s->upd_pending = false;
+    }
     DECT_HIP(hipGetLastError());
     return DECT_OK;
 }
@@ -1225,7 +1284,7 @@ static int one_iteration_image(dect_solver* s) {
 // back-projection.  Events order every hand-over between the streams; the
 // iteration after one with `more` starts with its back-projection queued.
 static int one_iteration(dect_solver* s, bool more = false) {
-    if (s->image) return one_iteration_image(s);
+    if (s->image) return one_iteration_image(s, more);
     const Geom& g = s->g;
     const Resolved& R = s->rp;
     const double beta = s->beta;
@@ -1245,19 +1304,14 @@ static int one_iteration(dect_solver* s, bool more = false) {
     a.bf16 = s->storage != DECT_STORAGE_FP32;
     void* dir = a.bf16 ? static_cast<void*>(s->dpad16) : static_cast<void*>(s->dpad);
     const PadLayout P = solver_pad(s);
+    const hipStream_t ms = enter_iter(s);   // the PCG's stream
     const bool two = s->side != nullptr;
     const hipStream_t side = two ? s->side : s->st;
-    // st: the t' step first (f^(k) from the previous update on `side`)
-    if (two && s->upd_pending) DECT_HIP(hipStreamWaitEvent(s->st, s->ev_upd, 0));
-    if (two && !s->bp_pending) DECT_HIP(hipEventRecord(s->ev_fork, s->st));
-    if (int rc = t_step_start(s, two ? s->ev_init : nullptr)) return rc;
-    // side: f-step and rho_e step
-    if (two) {
-        if (!s->bp_pending)
-            DECT_HIP(hipStreamWaitEvent(side, s->ev_fork, 0));
-        else
-            DECT_HIP(hipStreamWaitEvent(side, s->ev_tdone, 0));   // t'^(k), beta^(k)
-    }
+    // ms: the t' step first (f^(k) from the previous update on `side`)
+    if (two && s->upd_pending) DECT_HIP(hipStreamWaitEvent(ms, s->ev_upd, 0));
+    if (int rc = t_step_start(s, ms, two ? s->ev_init : nullptr)) return rc;
+    // side: f-step and rho_e step (t'^(k), beta^(k) from the previous iteration on ms)
+    if (two && s->upd_pending) DECT_HIP(hipStreamWaitEvent(side, s->ev_tdone, 0));
     if (!s->bp_pending) {
         hipEvent_t t0 = mark(s, side);
         launch_backproject(g, s->tab, s->S, s->batch, s->B, nullptr, 0, side, a.bf16, s->geo.sym_mode);
@@ -1300,19 +1354,21 @@ static int one_iteration(dect_solver* s, bool more = false) {
         s->bp_pending = true;
     }
     s->upd_pending = two;
-    if (int rc = t_step_finish(s)) return rc;
-    // st: beta^(k+1) once the side work has read beta^(k)
-    if (two) DECT_HIP(hipStreamWaitEvent(s->st, s->ev_side, 0));
-    launch_step_beta(s->beta_d, s->kappa_d, s->batch, s->st);
+    if (int rc = t_step_chunk(s, ms)) return rc;
+    if (int rc = t_step_finish(s, ms)) return rc;
+    // ms: beta^(k+1) once the side work has read beta^(k)
+    if (two) DECT_HIP(hipStreamWaitEvent(ms, s->ev_side, 0));
+    launch_step_beta(s->beta_d, s->kappa_d, s->batch, ms);
     std::swap(s->t, s->t_next);
     if (s->storage == DECT_STORAGE_BF16_STATE) {
-        if (two) DECT_HIP(hipStreamWaitEvent(s->st, s->ev_upd, 0));
-        round_state(s, 0, s->batch);
+        if (two) DECT_HIP(hipStreamWaitEvent(ms, s->ev_upd, 0));
+        round_state(s, 0, s->batch, ms);
     }
-    if (two) DECT_HIP(hipEventRecord(s->ev_tdone, s->st));
-    if (two && !more) {   // join: everything of this iteration is ordered before st's next work
-        DECT_HIP(hipStreamWaitEvent(s->st, s->ev_upd, 0));
+    if (two) DECT_HIP(hipEventRecord(s->ev_tdone, ms));
+    if (!more) {   // join: the caller's stream waits for both streams
+        leave_iter(s);
         s->upd_pending = false;
+        s->bp_pending = false;
     }
     s->beta *= R.kappa;
     s->k += 1;
@@ -1322,8 +1378,13 @@ static int one_iteration(dect_solver* s, bool more = false) {
 
 int dect_solver_iterate(dect_solver* s, int32_t n) {
     if (!s || n < 0) return fail(DECT_EINVAL, "dect_solver_iterate: bad arguments");
-    for (int i = 0; i < n; ++i)
-        if (int rc = one_iteration(s, i + 1 < n)) return rc;
+    for (int i = 0; i < n; ++i) {
+        if (int rc = one_iteration(s, i + 1 < n)) {
+            leave_iter(s);   // the caller's stream still orders after everything enqueued
+            s->upd_pending = s->bp_pending = false;
+            return rc;
+        }
+    }
     return DECT_OK;
 }
 

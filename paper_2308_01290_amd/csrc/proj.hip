@@ -11,6 +11,7 @@
 // The minor coordinate is a 32.32 fixed-point integer that each step advances
 // by the slope exactly, so crossings are placed to 2^-32 pixel however flat
 // the ray; projector and back-projector derive identical weights from it.
+#include <algorithm>
 #include <climits>
 
 #include "dect_internal.h"
@@ -776,14 +777,17 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_backproject(
 // voxel-driven kernel does, and accumulates them times the residuals of
 // views v + t nv/4, t = 0..3, for the quads R^t of its own.  The partial
 // sums reach the tiles in LDS in a fixed order (turn, view class), so the
-// result is deterministic.
+// result is deterministic.  The grid is capped below the CU count and blocks
+// loop over the orbits, so that a few CUs stay free of these long-lived
+// workgroups for the short kernels of the concurrent PCG.
 // ---------------------------------------------------------------------------
 constexpr int kBsWaves = 16;
+constexpr int kBsFreeCUs = 32;
 
 template <bool SB>
 __global__ __launch_bounds__(kBsWaves * 64) void k_backproject_sym(
     const void* __restrict__ sino, RayTable T, int n, float dxmm, float2* __restrict__ out_pairs,
-    float* __restrict__ out_split, int nout) {
+    float* __restrict__ out_split, int nout, int norb_z) {
     __shared__ float4 vs[kBpViewChunk];
     __shared__ int4 sfix[kBsWaves][64];
     __shared__ float2 sfl[kBsWaves][64];        // (2^-32/|s|, +-L)
@@ -792,9 +796,12 @@ __global__ __launch_bounds__(kBsWaves * 64) void k_backproject_sym(
     // every view is done
     float(*acc_t)[2][16][17] = reinterpret_cast<float(*)[2][16][17]>(&ssn[0][0][0]);
     static_assert(sizeof(ssn) >= sizeof(float) * 4 * 2 * 16 * 17, "tile sums");
-    const int z = blockIdx.z;
+    const int nq = n / 32;   // orbits per axis (first-quadrant tiles)
+    for (int orb = blockIdx.x; orb < nq * nq * norb_z; orb += gridDim.x) {
+    const int z = orb / (nq * nq);
+    const int obx = orb % nq, oby = (orb / nq) % nq;
     const SliceDesc D = T.desc[T.desc_stride * z];
-    if (!D.sym) return;
+    if (!D.sym) continue;   // block-uniform
     const int nd = D.nd, q4 = D.nv >> 2;
     const float sid = D.sid, sdd = D.sdd, u0 = D.u0, inv_pitch = D.inv_pitch;
     const int4* __restrict__ fix = T.fix + D.ray0;
@@ -803,7 +810,7 @@ __global__ __launch_bounds__(kBsWaves * 64) void k_backproject_sym(
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int a = w & 3, cls = w >> 2;
     // tile origins (row, column) of T0..T3
-    const int ty0 = blockIdx.y * 16, tx0 = blockIdx.x * 16;
+    const int ty0 = oby * 16, tx0 = obx * 16;
     const int oy[4] = {ty0, tx0, n - 16 - ty0, n - 16 - tx0};
     const int ox[4] = {tx0, n - 16 - ty0, n - 16 - tx0, ty0};
     const int i0 = oy[a] + 2 * (lane >> 3), k0 = ox[a] + 2 * (lane & 7);
@@ -940,6 +947,20 @@ __global__ __launch_bounds__(kBsWaves * 64) void k_backproject_sym(
             if (2 * z + 1 < nout) out_split[(size_t)(2 * z + 1) * npix + p] = s2;
         }
     }
+    }   // orbits
+}
+
+static int sym_bp_blocks() {
+    static const int cap = [] {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            (void)hipGetLastError();
+            return 224;
+        }
+        return std::max(ncu - kBsFreeCUs, ncu / 2);
+    }();
+    return cap;
 }
 
 void launch_backproject(const Geom& g, const RayTable& t, const void* sino, int npairs,
@@ -955,13 +976,14 @@ void launch_backproject(const Geom& g, const RayTable& t, const void* sino, int 
                                g.ny, (float)g.dx, out_pairs, out_split, nout);
     }
     if (sym_mode != 0 && grid_sym4(g)) {
-        dim3 grid(g.nx / 32, g.nx / 32, npairs);   // first-quadrant tiles
+        const int norb = (g.nx / 32) * (g.nx / 32) * npairs;   // tile orbits of all pairs
+        dim3 grid(std::min(norb, sym_bp_blocks()));
         if (sino_bf16)
             hipLaunchKernelGGL(k_backproject_sym<true>, grid, dim3(kBsWaves * 64), 0, st, sino, t, g.nx,
-                               (float)g.dx, out_pairs, out_split, nout);
+                               (float)g.dx, out_pairs, out_split, nout, npairs);
         else
             hipLaunchKernelGGL(k_backproject_sym<false>, grid, dim3(kBsWaves * 64), 0, st, sino, t, g.nx,
-                               (float)g.dx, out_pairs, out_split, nout);
+                               (float)g.dx, out_pairs, out_split, nout, npairs);
     }
 }
 
