@@ -438,6 +438,19 @@ def main():
     nnz = count_nonzeros(g)
     bp_avg_s = bp_ms / max(bp_n, 1) / 1e3
     fp_avg_s = fp_ms / max(fp_n, 1) / 1e3
+    # the same back-projection of both channels alone on the GPU (the stand-alone
+    # operator: pairing the two sinograms, then the kernel), for comparison with
+    # the in-solve duration, where it shares the GPU with the concurrent PCG
+    sino2 = torch.stack([lo[0], hi[0]])
+    for _ in range(3):
+        dect.backproject(g, sino2)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dect.backproject(g, sino2)
+    e1.record()
+    torch.cuda.synchronize()
+    bp_alone_s = e0.elapsed_time(e1) / 10 / 1e3
     # algorithmic work of one back-projection launch: both channels of the
     # sparse transpose product, one multiply-add per nonzero and channel
     bp_flops = 2 * 2 * nnz
@@ -467,6 +480,8 @@ def main():
         "projector": {
             "system_matrix_nonzeros": nnz,
             "backproject_ms": 1e3 * bp_avg_s,
+            "backproject_alone_ms": 1e3 * bp_alone_s,
+            "backproject_alone_tflops": 2 * 2 * nnz / bp_alone_s / 1e12,
             "project_ms": 1e3 * fp_avg_s,
             "backproject_visits_per_s": 2 * nnz / bp_avg_s,
             "project_visits_per_s": 2 * nnz / fp_avg_s,
