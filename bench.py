@@ -451,6 +451,17 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     bp_alone_s = e0.elapsed_time(e1) / 10 / 1e3
+    # the forward projection of the image pair alone (plain mode: the same
+    # traversal and reads as the solver's line-search projection)
+    img2 = torch.stack([Z[0], R[0]])
+    for _ in range(3):
+        dect.project(g, img2)
+    e0.record()
+    for _ in range(10):
+        dect.project(g, img2)
+    e1.record()
+    torch.cuda.synchronize()
+    fp_alone_s = e0.elapsed_time(e1) / 10 / 1e3
     # algorithmic work of one back-projection launch: both channels of the
     # sparse transpose product, one multiply-add per nonzero and channel
     bp_flops = 2 * 2 * nnz
@@ -483,6 +494,7 @@ def main():
             "backproject_alone_ms": 1e3 * bp_alone_s,
             "backproject_alone_tflops": 2 * 2 * nnz / bp_alone_s / 1e12,
             "project_ms": 1e3 * fp_avg_s,
+            "project_alone_ms": 1e3 * fp_alone_s,
             "backproject_visits_per_s": 2 * nnz / bp_avg_s,
             "project_visits_per_s": 2 * nnz / fp_avg_s,
             "backproject_algorithmic_hbm_gbs": bp_bytes / bp_avg_s / 1e9,

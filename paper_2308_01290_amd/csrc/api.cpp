@@ -374,7 +374,6 @@ static int choose_prec(int want, const PcgBufs& b, double beta, PcgArgs* a) {
                     a->nx, a->ny);
     a->prec = prec;
     a->nrz_used = prec == PREC_JACOBI ? a->L.nblk : (prec == PREC_FFT ? a->ny : b.mg_plan.nrz);
-    if (prec == PREC_MG) DECT_HIP(mg_init());
     return DECT_OK;
 }
 
@@ -418,7 +417,9 @@ static void pcg_chunk(PcgRun& R, const PcgBufs& b, float2* fft_scratch, hipStrea
 // set-up: preconditioner data and the first preconditioner application
 static void pcg_setup(PcgRun& R, const PcgBufs& b, float2* fft_scratch, hipStream_t st) {
     PcgArgs& a = R.a;
-    if (a.prec == PREC_MG) launch_mg_setup(b.mg_plan, a.w2, b.mg, a.batch, st);
+    if (a.prec == PREC_MG)
+        launch_mg_setup(b.mg_plan, a.w2, b.mg, a.batch, a.beta, a.beta_z, &a.st[0].done,
+                        sizeof(PcgState) / sizeof(int), st);
     // with the multigrid preconditioner on sizes whose finest V-cycle kernel
     // can also apply A, the pipelined form: one reduction per iteration
     R.piped = a.prec == PREC_MG && mg_pipelined_ok(b.mg_plan);

@@ -359,24 +359,30 @@ void launch_pcg_cg_update(const PcgArgs& a, int i, hipStream_t st);
 
 // ---- multigrid V-cycle preconditioner for diag(c) + beta L -----------------------
 constexpr int kMgMaxLevels = 12;
-constexpr int kMgDenseMax = 64;      // unknowns of the coarsest grid (dense solve)
+constexpr int kMgDenseMax = 64;      // unknowns of the exactly solved grid, at most
+constexpr int kMgExactMax = 16;      //   and the first grid this small is the one
+constexpr int kMgCoarseB = 3;        // smoothed levels of the in-LDS part (32 -> 16 -> 8)
 struct MgPlan {
     bool ok = false;                 // sizes admit the V-cycle
     int nlev = 0, ngrid = 0, ncoarse = 0;   // all levels; tile-kernel levels; in-LDS levels
+    int ncb = 0, ne = 0;             // smoothed in-LDS levels; unknowns of the exact level
     int ny[kMgMaxLevels] = {}, nx[kMgMaxLevels] = {};
     // per-slice offsets (floats) into the level buffer: xs0 = saved iterate of
-    // level 0; b, c, xs, e of tile levels 1..ngrid
+    // level 0; b, c, xs, e of tile levels 1..ngrid; set-up data of the in-LDS
+    // part: omega / diag of its smoothed levels (id), the diagonals of all
+    // but the first (cb), the exact level's inverse (gi, ne x ne)
     size_t xs0 = 0, b[kMgMaxLevels] = {}, c[kMgMaxLevels] = {}, xs[kMgMaxLevels] = {},
            e[kMgMaxLevels] = {};
+    size_t id[kMgCoarseB] = {}, cb[kMgCoarseB] = {}, gi = 0;
     size_t zstride = 0;              // floats per slice
-    size_t coarse_lds = 0;           // dynamic LDS bytes of the in-LDS kernel
     int nrz = 0;                     // <r, z> partials one V-cycle writes
     bool pair[kMgMaxLevels] = {};    // tile levels l and l + 1 run in one kernel each way
 };
 MgPlan mg_plan(int ny, int nx);
-hipError_t mg_init();                // once per process: LDS limit of the in-LDS kernel
-// c pyramid of the tile levels from w2 (once per linear solve)
-void launch_mg_setup(const MgPlan& P, const float* w2, float* mg, int batch, hipStream_t st);
+// once per linear solve: c pyramid from w2 and the in-LDS part's set-up data
+// (inverse diagonals, exact-level inverse) for beta (or beta_z[z] per slice)
+void launch_mg_setup(const MgPlan& P, const float* w2, float* mg, int batch, float beta,
+                     const double* beta_z, const int* skip, size_t skip_zstride, hipStream_t st);
 // z = V(r); <r, z> partials into dot[z*dot_zstride + 0..P.nrz)
 void launch_mg_vcycle(const MgPlan& P, const float* r, const float* w2, float* z, float* mg,
                       int batch, float beta, const double* beta_z, const int* skip,

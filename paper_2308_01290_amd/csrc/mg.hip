@@ -7,18 +7,18 @@
 // average of c_(l-1).  Transfers: restriction = 2x2 average, prolongation =
 // piecewise constant (R = P^T / 4).  Smoothing: kMgNu damped-Jacobi sweeps
 // (omega = 0.8) before the coarse correction, starting from zero, and kMgNu
-// after it.  The coarsest grid (an odd side, or 1 x 1; at most 64 unknowns) is
-// solved exactly by Gaussian elimination.  The V-cycle is therefore a fixed
-// symmetric linear map, as PCG requires; it has no atomics, so it is
-// deterministic.
+// after it.  The first grid of at most 16 unknowns (else the coarsest one,
+// an odd side, which must have at most 64) is solved exactly with A_l^-1,
+// computed once per linear solve (FP64 Gauss-Jordan, symmetrised).  The V-cycle is therefore a fixed symmetric linear map, as
+// PCG requires; it has no atomics, so it is deterministic.
 //
 // Kernels: levels whose larger side exceeds 32 run as tile kernels going
 // down (sweeps, residual, restriction) and up (prolongation, sweeps), two
 // levels per kernel where the finer one splits into 32 x 32 cores (its halo
 // then covers both levels' sweeps, so the coarser level needs no launch of
-// its own), else one level on 16 x 16 tiles with a kMgNu-pixel halo; all
-// levels of 32 and below run in one workgroup per slice with every level
-// resident in LDS.
+// its own), else one level on 16 x 16 tiles with a kMgNu-pixel halo; the
+// levels of 32 and below run in one workgroup per slice, one thread per
+// pixel, neighbours exchanged through LDS.
 #include <algorithm>
 
 #include "dect_internal.h"
@@ -29,16 +29,7 @@ namespace dect {
 constexpr float kOmega = 0.8f;
 constexpr int kMgNu = 3;                  // smoothing sweeps before and after the correction
 constexpr int kMgCoarseMax = 32;          // larger side at which the in-LDS kernel takes over
-constexpr int kMgCoarseThreads = 1024;
-constexpr size_t kMgLdsMax = 160 * 1024;  // LDS of one workgroup on gfx950
-constexpr size_t kMgLdsStatic = 1024;     // reserved for the in-LDS kernel's static arrays
-
-// (t / n, t % n) for t < 2^12, n <= 64: floor((t + 1/2) / n) in FP32 is exact
-// there (the fraction stays at least 1/(2n) away from an integer)
-__device__ __forceinline__ void divmod_small(int t, int n, float inv_n, int& q, int& r) {
-    q = (int)(((float)t + 0.5f) * inv_n);
-    r = t - q * n;
-}
+constexpr int kMgCoarseThreads = 1024;    // one thread per pixel of the largest in-LDS level
 
 // one damped-Jacobi sweep at a pixel: x + omega (b - A x) / diag(A)
 __device__ __forceinline__ float jac(float x, float b, float c, float beta, float nsum) {
@@ -91,13 +82,28 @@ MgPlan mg_plan(int ny, int nx) {
         P.e[q] = off;
         off += n;
     }
+    // in-LDS part: the first level with at most kMgExactMax unknowns (else the
+    // coarsest, at most kMgDenseMax) is solved exactly, the ones above it
+    // (at most kMgCoarseB) are smoothed; the set-up data computed once per
+    // linear solve follows the tile levels
+    const int g0 = P.ngrid;
+    int q = 0;
+    while (ok && q + 1 < P.ncoarse && P.ny[g0 + q] * P.nx[g0 + q] > kMgExactMax) ++q;
+    ok = ok && q <= kMgCoarseB && P.ny[g0 + q] * P.nx[g0 + q] <= kMgDenseMax;
+    if (ok) {
+        P.ncb = q;
+        P.ne = P.ny[g0 + q] * P.nx[g0 + q];
+        for (int l = 0; l < P.ncb; ++l) {
+            const size_t n = (size_t)P.ny[g0 + l] * P.nx[g0 + l];
+            P.id[l] = off;
+            off += n;
+            P.cb[l] = off;   // (the first level's diagonal is the level buffer's own)
+            off += l > 0 ? n : 0;
+        }
+        P.gi = off;
+        off += (size_t)P.ne * P.ne;
+    }
     P.zstride = (off + 63) & ~(size_t)63;
-    size_t lds = 0;
-    for (int q = P.ngrid; q < P.nlev; ++q) lds += 3 * (size_t)P.ny[q] * P.nx[q];
-    lds += 2 * (size_t)P.ny[P.ngrid] * P.nx[P.ngrid];
-    lds += (size_t)nc * (nc + 1) + 2 * (size_t)nc;
-    P.coarse_lds = lds * sizeof(float);
-    ok = ok && P.coarse_lds + kMgLdsStatic <= kMgLdsMax;
     // pair tile levels from the top: l and l + 1 share a kernel when level l
     // splits into 32 x 32 cores
     for (int q = 0; q < P.ngrid;) {
@@ -484,251 +490,297 @@ __global__ __launch_bounds__(kPairThreads) void k_mg_up2(MgPair A, const int* sk
 }
 
 // ---------------------------------------------------------------------------
-// all levels with larger side <= 32 in one workgroup per slice, in LDS
+// the in-LDS part: all levels with larger side <= 32, one workgroup per slice.
+// The levels above the exact one (at most kMgCoarseB) are smoothed with one
+// thread per pixel (pixel values in registers, neighbours exchanged through
+// LDS); the exact level is solved with its inverse, computed once per linear
+// solve by k_mg_coarse_setup together with the inverse diagonals
+// omega / diag(A_l) of the smoothed levels.
 // ---------------------------------------------------------------------------
 struct MgCoarse {
     const float* b;       // right-hand side of the first in-LDS level
     const float* c;       // its diagonal
     float* e;             // its correction (output)
     size_t zs_b, zs_c, zs_e;
+    const float* aux;     // per-slice set-up data (level buffer), stride zs_aux:
+    size_t zs_aux;        //   omega / diag and diagonal of smoothed level q at
+    size_t o_id[kMgCoarseB], o_c[kMgCoarseB], o_g;   // o_id[q], o_c[q] (q >= 1), inverse at o_g
     float beta;           // beta of the first in-LDS level, or with beta_z:
     const double* beta_z; //   beta_z[z] * scale
     float scale;
-    int nlev;             // in-LDS levels (>= 1); the last is solved exactly
-    int ny[kMgMaxLevels], nx[kMgMaxLevels];
+    int ncb, ne;          // smoothed levels; unknowns of the exact level
+    int ny[kMgCoarseB + 1], nx[kMgCoarseB + 1];   // levels 0..ncb (repeated past ncb)
     double* dot;          // optional <b, e> (when this is the finest level)
     size_t dot_zstride;
 };
 
-// Work split of the in-LDS kernel: levels with more than 64 pixels use the whole
-// workgroup (phases end in a workgroup barrier); the smaller ones run on the
-// first wavefront alone, whose LDS accesses are ordered among themselves, so
-// their phases end in a wavefront-level fence only.
-struct Team {
-    int tid, n;
-    bool wave;
-    __device__ void sync() const {
-        if (wave) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        } else {
-            __syncthreads();
-        }
+// one pixel of a smoothed in-LDS level, owned by thread t < ny * nx
+struct MgPx {
+    bool on;
+    int self, nb[4], par;   // own index, periodic neighbours, parent on the next level
+    float b, c, id, xs;     // rhs, diagonal, omega / (c + 4 beta), saved pre-smoothed iterate
+};
+
+__device__ __forceinline__ MgPx mg_px(int t, int ny, int nx, int nxc) {
+    MgPx P;
+    P.on = t < ny * nx;
+    const int i = P.on ? t / nx : 0, k = P.on ? t - i * nx : 0;
+    const int ip = i + 1 == ny ? 0 : i + 1, im = i == 0 ? ny - 1 : i - 1;
+    const int kp = k + 1 == nx ? 0 : k + 1, km = k == 0 ? nx - 1 : k - 1;
+    P.self = t;
+    P.nb[0] = ip * nx + k;
+    P.nb[1] = im * nx + k;
+    P.nb[2] = i * nx + kp;
+    P.nb[3] = i * nx + km;
+    P.par = (i / 2) * nxc + k / 2;
+    P.b = P.c = P.id = P.xs = 0.f;
+    return P;
+}
+
+constexpr int kMgLdsPx = kMgCoarseMax * kMgCoarseMax;   // pixels of the largest in-LDS level
+
+// Ping-pong exchange buffers: publish() writes this thread's value into the
+// other buffer and waits for the workgroup; every read of a published buffer
+// comes before the next publish, so a buffer is rewritten only after the
+// barrier that follows all reads of its previous contents.
+struct MgX {
+    float (*X)[kMgLdsPx];
+    int cur;
+    __device__ void publish(const MgPx& P, float v) {
+        cur ^= 1;
+        if (P.on) X[cur][P.self] = v;
+        __syncthreads();
+    }
+    __device__ float nsum(const MgPx& P) const {
+        return X[cur][P.nb[0]] + X[cur][P.nb[1]] + X[cur][P.nb[2]] + X[cur][P.nb[3]];
     }
 };
 
-// y = one damped-Jacobi sweep of x (x = 0 when from_zero), periodic grid
-__device__ void lds_sweep(const Team& T, const float* x, const float* b, const float* c, float* y,
-                          int ny, int nx, float beta, bool from_zero) {
-    const float inv_nx = 1.f / (float)nx;
-    for (int t = T.tid; t < ny * nx; t += T.n) {
-        if (from_zero) {
-            y[t] = kOmega * b[t] / (c[t] + 4.f * beta);
-            continue;
-        }
-        int i, k;
-        divmod_small(t, nx, inv_nx, i, k);
-        const int ip = (i + 1 == ny) ? 0 : i + 1, im = (i == 0) ? ny - 1 : i - 1;
-        const int kp = (k + 1 == nx) ? 0 : k + 1, km = (k == 0) ? nx - 1 : k - 1;
-        const float ns = x[ip * nx + k] + x[im * nx + k] + x[i * nx + kp] + x[i * nx + km];
-        y[t] = jac(x[t], b[t], c[t], beta, ns);
-    }
-    T.sync();
+__device__ __forceinline__ float mg_apply(const MgPx& P, float x, float beta, float ns) {
+    return fmaf(P.c, x, beta * (4.f * x - ns));   // (A x) at the pixel
 }
 
-// 2x2 average of a level-l array (row length nxf) into the next level
-__device__ void lds_restrict(const Team& T, const float* f, int nxf, float* cg, int nyc, int nxc) {
-    const float inv_nxc = 1.f / (float)nxc;
-    for (int t = T.tid; t < nyc * nxc; t += T.n) {
-        int i, k;
-        divmod_small(t, nxc, inv_nxc, i, k);
-        const int a = (2 * i) * nxf + 2 * k;
-        cg[t] = 0.25f * (f[a] + f[a + 1] + f[a + nxf] + f[a + nxf + 1]);
+// down at a smoothed level: kMgNu sweeps from zero, then the residual is
+// published (the caller restricts it before its next publish)
+__device__ __forceinline__ void mg_lds_down(MgPx& P, float beta, MgX& E) {
+    float x = P.id * P.b;   // first sweep from zero
+#pragma unroll
+    for (int q = 2; q <= kMgNu; ++q) {
+        E.publish(P, x);
+        if (P.on) x = fmaf(P.id, P.b - mg_apply(P, x, beta, E.nsum(P)), x);
     }
-    T.sync();
+    P.xs = x;
+    E.publish(P, x);
+    const float r = P.on ? P.b - mg_apply(P, x, beta, E.nsum(P)) : 0.f;
+    E.publish(P, r);
 }
 
-struct CoarseLds {
-    float* base;
-    const int *ny, *nx, *off;
-    __device__ float* b(int l) const { return base + off[l]; }
-    __device__ float* c(int l) const { return base + off[l] + ny[l] * nx[l]; }
-    __device__ float* x(int l) const { return base + off[l] + 2 * ny[l] * nx[l]; }
-};
+// 2 x 2 average of the published level (row length nxf) at coarse pixel t
+__device__ __forceinline__ float mg_lds_restrict(const MgX& E, int t, int nxf, int nxc) {
+    const int i = t / nxc, k = t - i * nxc;
+    const float* R = E.X[E.cur];
+    const int a = (2 * i) * nxf + 2 * k;
+    return 0.25f * (R[a] + R[a + 1] + R[a + nxf] + R[a + nxf + 1]);
+}
 
-// down at level l: nu sweeps from zero (sweep q lands in x_l when nu - q is
-// even, else in t0), residual into t0, restriction into b_(l+1)
-__device__ void coarse_down(const Team& T, const CoarseLds& S, int l, float beta, float* t0) {
-    const int ny = S.ny[l], nx = S.nx[l];
-    float* src = nullptr;
+// up at a smoothed level: y0 = xs + P e_c, then kMgNu sweeps; returns y
+__device__ __forceinline__ float mg_lds_up(const MgPx& P, float beta, float ec, MgX& E) {
+    float y = P.xs + ec;
+#pragma unroll
     for (int q = 1; q <= kMgNu; ++q) {
-        float* dst = ((kMgNu - q) & 1) ? t0 : S.x(l);
-        lds_sweep(T, src, S.b(l), S.c(l), dst, ny, nx, beta, q == 1);
-        src = dst;
+        E.publish(P, y);
+        if (P.on) y = fmaf(P.id, P.b - mg_apply(P, y, beta, E.nsum(P)), y);
     }
-    const float* x = S.x(l);
-    const float* bb = S.b(l);
-    const float* cc = S.c(l);
-    const float inv_nx = 1.f / (float)nx;
-    for (int t = T.tid; t < ny * nx; t += T.n) {
-        int i, k;
-        divmod_small(t, nx, inv_nx, i, k);
-        const int ip = (i + 1 == ny) ? 0 : i + 1, im = (i == 0) ? ny - 1 : i - 1;
-        const int kp = (k + 1 == nx) ? 0 : k + 1, km = (k == 0) ? nx - 1 : k - 1;
-        const float ns = x[ip * nx + k] + x[im * nx + k] + x[i * nx + kp] + x[i * nx + km];
-        t0[t] = bb[t] - (cc[t] * x[t] + beta * (4.f * x[t] - ns));
-    }
-    T.sync();
-    lds_restrict(T, t0, nx, S.b(l + 1), S.ny[l + 1], S.nx[l + 1]);
-}
-
-// up at level l: y0 = xs_l + P e_(l+1) (e_(l+1) is in x_(l+1)) into t0; nu
-// sweeps, the last into x_l (sweep q lands in x_l when nu - q is even, else t1)
-__device__ void coarse_up(const Team& T, const CoarseLds& S, int l, float beta, float* t0,
-                          float* t1) {
-    const int ny = S.ny[l], nx = S.nx[l], nxc = S.nx[l + 1];
-    const float inv_nx = 1.f / (float)nx;
-    const float* xc = S.x(l + 1);
-    float* xf = S.x(l);
-    for (int t = T.tid; t < ny * nx; t += T.n) {
-        int i, k;
-        divmod_small(t, nx, inv_nx, i, k);
-        t0[t] = xf[t] + xc[(i / 2) * nxc + k / 2];
-    }
-    T.sync();
-    float* src = t0;
-    for (int q = 1; q <= kMgNu; ++q) {
-        float* dst = ((kMgNu - q) & 1) ? t1 : xf;
-        lds_sweep(T, src, S.b(l), S.c(l), dst, ny, nx, beta, false);
-        src = dst;
-    }
-}
-
-// coarsest level l: Gaussian elimination (the matrix is SPD), result in x_l;
-// one thread owns each row while the matrix is built, one lane per unknown in
-// the back substitution (nc <= 64, so that runs on the first wavefront)
-__device__ void coarse_solve(const Team& T, const CoarseLds& S, int l, float beta, float* dense) {
-    const int ny = S.ny[l], nx = S.nx[l], nc = ny * nx, ld = nc + 1;
-    float* A = dense;
-    float* rhs = A + nc * ld;
-    float* lc = rhs + nc;
-    for (int t = T.tid; t < nc; t += T.n) {
-        float* row = A + t * ld;
-        for (int j = 0; j < nc; ++j) row[j] = 0.f;
-        const int i = t / nx, k = t % nx;
-        const int ip = (i + 1 == ny) ? 0 : i + 1, im = (i == 0) ? ny - 1 : i - 1;
-        const int kp = (k + 1 == nx) ? 0 : k + 1, km = (k == 0) ? nx - 1 : k - 1;
-        const int nb[4] = {ip * nx + k, im * nx + k, i * nx + kp, i * nx + km};
-        float d = S.c(l)[t];   // a neighbour that wraps onto t itself adds nothing
-        for (int q = 0; q < 4; ++q) {
-            if (nb[q] == t) continue;
-            row[nb[q]] -= beta;
-            d += beta;
-        }
-        row[t] = d;
-        rhs[t] = S.b(l)[t];
-    }
-    T.sync();
-    for (int k = 0; k + 1 < nc; ++k) {
-        const float piv = A[k * ld + k];
-        const float inv = piv > 0.f ? 1.f / piv : 0.f;
-        for (int i = k + 1 + T.tid; i < nc; i += T.n) lc[i] = A[i * ld + k] * inv;
-        T.sync();
-        const int w = nc - k;   // columns k..nc-1; column k carries the rhs update
-        for (int idx = T.tid; idx < (nc - k - 1) * w; idx += T.n) {
-            const int i = k + 1 + idx / w, j = k + idx % w;
-            if (j == k)
-                rhs[i] -= lc[i] * rhs[k];
-            else
-                A[i * ld + j] -= lc[i] * A[k * ld + j];
-        }
-        T.sync();
-    }
-    if (T.tid < kWave) {
-        const int lane = T.tid;
-        float xv = 0.f;
-        for (int i = nc - 1; i >= 0; --i) {
-            const float part = (lane > i && lane < nc) ? A[i * ld + lane] * xv : 0.f;
-            const float s = wave_sum(part);
-            if (lane == i) {
-                const float piv = A[i * ld + i];
-                xv = piv > 0.f ? (rhs[i] - s) / piv : 0.f;
-            }
-        }
-        if (lane < nc) S.x(l)[lane] = xv;
-    }
-    T.sync();
+    return y;
 }
 
 __global__ __launch_bounds__(kMgCoarseThreads) void k_mg_coarse(MgCoarse G, const int* skip,
                                                                  size_t skip_zstride) {
-    extern __shared__ float lds[];
+    __shared__ float X[2][kMgLdsPx];
+    __shared__ float BE[kMgDenseMax], EE[kMgDenseMax];
     __shared__ double sh[kMgCoarseThreads / kWave];
-    __shared__ int s_ny[kMgMaxLevels], s_nx[kMgMaxLevels], s_off[kMgMaxLevels + 1];
     const int z = blockIdx.x;
     if (mg_skip(skip, skip_zstride, z)) return;
-    if (threadIdx.x == 0) {   // level l: b, c, x at lds + s_off[l] + {0, 1, 2} * n_l
-        int o = 0;
-        for (int l = 0; l < kMgMaxLevels; ++l) {
-            s_ny[l] = G.ny[l];
-            s_nx[l] = G.nx[l];
-            s_off[l] = o;
-            if (l < G.nlev) o += 3 * G.ny[l] * G.nx[l];
+    const int t = threadIdx.x;
+    const float beta0 = G.beta_z ? (float)G.beta_z[z] * G.scale : G.beta;
+    const float* aux = G.aux + (size_t)z * G.zs_aux;
+    const int ncb = G.ncb, ne = G.ne;
+    // row t / 16 of the exact level's inverse, columns t % 16 + 16 m
+    const int grow = t >> 4, gpart = t & 15;
+    float gv[kMgDenseMax / 16];
+#pragma unroll
+    for (int m = 0; m < kMgDenseMax / 16; ++m) {
+        const int j = gpart + 16 * m;
+        gv[m] = grow < ne && j < ne ? aux[G.o_g + (size_t)grow * ne + j] : 0.f;
+    }
+    MgX E{X, 1};
+    MgPx P[kMgCoarseB];
+    float bl[kMgCoarseB];
+#pragma unroll
+    for (int q = 0; q < kMgCoarseB; ++q) {
+        P[q] = mg_px(t, G.ny[q], G.nx[q], G.nx[q + 1]);
+        P[q].on = P[q].on && q < ncb;
+        bl[q] = q == 0 ? beta0 : 0.25f * bl[q - 1];
+        if (P[q].on) {
+            P[q].c = q == 0 ? G.c[(size_t)z * G.zs_c + t] : aux[G.o_c[q] + t];
+            P[q].id = aux[G.o_id[q] + t];
         }
-        s_off[kMgMaxLevels] = o;
+    }
+    const float b0 = t < G.ny[0] * G.nx[0] ? G.b[(size_t)z * G.zs_b + t] : 0.f;
+    P[0].b = b0;
+    float be = b0;   // rhs of the exact level at pixel t (t < ne)
+#pragma unroll
+    for (int q = 0; q < kMgCoarseB; ++q) {
+        if (q >= ncb) break;   // uniform
+        if (q > 0 && P[q].on) P[q].b = mg_lds_restrict(E, t, G.nx[q - 1], G.nx[q]);
+        mg_lds_down(P[q], bl[q], E);
+        if (q + 1 == ncb) be = t < ne ? mg_lds_restrict(E, t, G.nx[q], G.nx[q + 1]) : 0.f;
+    }
+    if (t < kMgDenseMax) BE[t] = t < ne ? be : 0.f;
+    __syncthreads();
+    {
+        // e = A_e^-1 b_e: 16 lanes per row, a fixed reduction order
+        float acc = 0.f;
+#pragma unroll
+        for (int m = 0; m < kMgDenseMax / 16; ++m) acc = fmaf(gv[m], BE[gpart + 16 * m], acc);
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
+        if (gpart == 0 && grow < kMgDenseMax) EE[grow] = acc;
     }
     __syncthreads();
-    const CoarseLds S{lds, s_ny, s_nx, s_off};
-    const int n0 = s_ny[0] * s_nx[0];
-    float* t0 = lds + s_off[kMgMaxLevels];
-    float* t1 = t0 + n0;
-    float* dense = t0 + 2 * n0;
-    // first level with at most 64 pixels: it and all below run on one wavefront
-    int cut = 0;
-    while (cut < G.nlev && s_ny[cut] * s_nx[cut] > kWave) ++cut;
-    const Team B{(int)threadIdx.x, (int)blockDim.x, false};
-    const Team W{(int)threadIdx.x, kWave, true};
-    for (int t = threadIdx.x; t < n0; t += blockDim.x) {
-        S.b(0)[t] = G.b[(size_t)z * G.zs_b + t];
-        S.c(0)[t] = G.c[(size_t)z * G.zs_c + t];
+    float y = t < ne ? EE[t] : 0.f;   // correction at pixel t of the current level
+#pragma unroll
+    for (int q = kMgCoarseB - 1; q >= 0; --q) {
+        if (q >= ncb) continue;   // uniform
+        const float ec = P[q].on ? (q + 1 == ncb ? EE[P[q].par] : E.X[E.cur][P[q].par]) : 0.f;
+        y = mg_lds_up(P[q], bl[q], ec, E);
+        if (q > 0) E.publish(P[q], y);
     }
-    __syncthreads();
-    float beta[kMgMaxLevels];
-    beta[0] = G.beta_z ? (float)G.beta_z[z] * G.scale : G.beta;
-    for (int l = 1; l < kMgMaxLevels; ++l) beta[l] = 0.25f * beta[l - 1];
-    for (int l = 0; l + 1 < cut; ++l) lds_restrict(B, S.c(l), s_nx[l], S.c(l + 1), s_ny[l + 1], s_nx[l + 1]);
-    for (int l = 0; l < cut && l + 1 < G.nlev; ++l) coarse_down(B, S, l, beta[l], t0);
-    if (threadIdx.x < kWave) {
-        for (int l = cut > 0 ? cut - 1 : 0; l + 1 < G.nlev; ++l)
-            if (l + 1 >= cut)
-                lds_restrict(W, S.c(l), s_nx[l], S.c(l + 1), s_ny[l + 1], s_nx[l + 1]);
-        for (int l = cut; l + 1 < G.nlev; ++l) coarse_down(W, S, l, beta[l], t0);
-        coarse_solve(W, S, G.nlev - 1, beta[G.nlev - 1], dense);
-        for (int l = G.nlev - 2; l >= cut; --l) coarse_up(W, S, l, beta[l], t0, t1);
-    }
-    __syncthreads();
-    for (int l = min(cut, G.nlev - 1) - 1; l >= 0; --l) coarse_up(B, S, l, beta[l], t0, t1);
     double dot = 0.0;
-    for (int t = threadIdx.x; t < n0; t += blockDim.x) {
-        G.e[(size_t)z * G.zs_e + t] = S.x(0)[t];
-        dot += (double)S.x(0)[t] * (double)S.b(0)[t];
+    if (t < G.ny[0] * G.nx[0]) {
+        G.e[(size_t)z * G.zs_e + t] = y;
+        dot = (double)y * (double)b0;
     }
     if (G.dot) {
         const double v = block_sum<kMgCoarseThreads>(dot, sh);
-        if (threadIdx.x == 0) G.dot[(size_t)z * G.dot_zstride] = v;
+        if (t == 0) G.dot[(size_t)z * G.dot_zstride] = v;
     }
 }
 
-// ---------------------------------------------------------------------------
-hipError_t mg_init() {
-    static hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mg_coarse),
-                                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                                              (int)(kMgLdsMax - kMgLdsStatic));
-    return e;
+// Once per linear solve: the diagonals of the in-LDS levels (2 x 2 averages
+// of the first one), omega / diag(A_l) of the smoothed ones, and the exact
+// level's inverse A_e^-1 by Gauss-Jordan elimination in FP64 (A_e is SPD; a
+// pivot that has fallen below 1e-12 of its diagonal, a numerically singular
+// direction, is dropped from the inverse), symmetrised and stored in FP32.
+struct MgCoarseSetup {
+    const float* c;       // diagonal of the first in-LDS level
+    size_t zs_c;
+    float* aux;
+    size_t zs_aux, o_id[kMgCoarseB], o_c[kMgCoarseB], o_g;
+    float beta;
+    const double* beta_z;
+    float scale;
+    int ncb, ne;
+    int ny[kMgCoarseB + 1], nx[kMgCoarseB + 1];
+};
+
+__global__ __launch_bounds__(kMgCoarseThreads) void k_mg_coarse_setup(MgCoarseSetup S, const int* skip,
+                                                                       size_t skip_zstride) {
+    __shared__ float cl[2][kMgLdsPx];
+    __shared__ double A[kMgDenseMax][kMgDenseMax + 1];
+    __shared__ double dg[kMgDenseMax], fc[2][kMgDenseMax];
+    const int z = blockIdx.x;
+    if (mg_skip(skip, skip_zstride, z)) return;
+    const int t = threadIdx.x;
+    float* aux = S.aux + (size_t)z * S.zs_aux;
+    float be = S.beta_z ? (float)S.beta_z[z] * S.scale : S.beta;
+    int cur = 0;
+    if (t < S.ny[0] * S.nx[0]) cl[0][t] = S.c[(size_t)z * S.zs_c + t];
+    __syncthreads();
+    for (int q = 0; q < S.ncb; ++q) {
+        if (t < S.ny[q] * S.nx[q]) {
+            aux[S.o_id[q] + t] = kOmega / (cl[cur][t] + 4.f * be);
+            if (q > 0) aux[S.o_c[q] + t] = cl[cur][t];
+        }
+        const int nxf = S.nx[q], nxc = S.nx[q + 1];
+        if (t < S.ny[q + 1] * nxc) {
+            const int i = t / nxc, k = t - i * nxc;
+            const int a = (2 * i) * nxf + 2 * k;
+            cl[cur ^ 1][t] = 0.25f * (cl[cur][a] + cl[cur][a + 1] + cl[cur][a + nxf] + cl[cur][a + nxf + 1]);
+        }
+        __syncthreads();
+        cur ^= 1;
+        be *= 0.25f;
+    }
+    // A_e = diag(c_e) + beta_e L on the periodic grid, one row per thread, as
+    // the sweeps apply it: c x + beta (4 x - neighbours), a neighbour that
+    // wraps onto the pixel itself included
+    const int ny = S.ny[S.ncb], nx = S.nx[S.ncb], ne = S.ne;
+    if (t < ne) {
+        for (int j = 0; j < ne; ++j) A[t][j] = 0.0;
+        const int i = t / nx, k = t - i * nx;
+        const int ip = i + 1 == ny ? 0 : i + 1, im = i == 0 ? ny - 1 : i - 1;
+        const int kp = k + 1 == nx ? 0 : k + 1, km = k == 0 ? nx - 1 : k - 1;
+        A[t][t] = (double)cl[cur][t] + 4.0 * (double)be;
+        A[t][ip * nx + k] -= (double)be;
+        A[t][im * nx + k] -= (double)be;
+        A[t][i * nx + kp] -= (double)be;
+        A[t][i * nx + km] -= (double)be;
+    }
+    __syncthreads();
+    if (t < ne) {
+        dg[t] = A[t][t];
+        fc[0][t] = A[t][0];
+    }
+    __syncthreads();
+    // in-place Gauss-Jordan; fc[k & 1] holds column k as it is before step k.
+    // Thread t updates row t / 16, columns t % 16 + 16 m.
+    const int gi = t >> 4, gj = t & 15;
+    for (int k = 0; k < ne; ++k) {
+        const double* f = fc[k & 1];
+        double* fn = fc[(k + 1) & 1];
+        const double p = f[k];
+        const double inv = p > 1e-12 * dg[k] ? 1.0 / p : 0.0;
+        if (t < ne) {
+            const double v = (t == k ? 1.0 : A[k][t]) * inv;
+            A[k][t] = v;
+            if (t == k + 1) fn[k] = v;
+        }
+        __syncthreads();
+        if (gi < ne && gi != k) {
+            const double fi = f[gi];
+#pragma unroll
+            for (int m = 0; m < kMgDenseMax / 16; ++m) {
+                const int j = gj + 16 * m;
+                if (j >= ne) break;
+                const double v = (j == k ? 0.0 : A[gi][j]) - fi * A[k][j];
+                A[gi][j] = v;
+                if (j == k + 1) fn[gi] = v;
+            }
+        }
+        __syncthreads();
+    }
+    if (gi < ne) {
+#pragma unroll
+        for (int m = 0; m < kMgDenseMax / 16; ++m) {
+            const int j = gj + 16 * m;
+            if (j >= ne) break;
+            aux[S.o_g + (size_t)gi * ne + j] = (float)(0.5 * (A[gi][j] + A[j][gi]));
+        }
+    }
 }
 
-void launch_mg_setup(const MgPlan& P, const float* w2, float* mg, int batch, hipStream_t st) {
+// dimensions of in-LDS levels 0..kMgCoarseB (the exact level repeated past ncb)
+static void coarse_dims(const MgPlan& P, int* ny, int* nx) {
+    for (int q = 0; q <= kMgCoarseB; ++q) {
+        const int l = P.ngrid + std::min(q, P.ncb);
+        ny[q] = P.ny[l];
+        nx[q] = P.nx[l];
+    }
+}
+
+void launch_mg_setup(const MgPlan& P, const float* w2, float* mg, int batch, float beta,
+                     const double* beta_z, const int* skip, size_t skip_zstride, hipStream_t st) {
     const size_t n0 = (size_t)P.ny[0] * P.nx[0];
     for (int l = 0; l < P.ngrid; ++l) {
         const float* cf = l == 0 ? w2 : mg + P.c[l];
@@ -737,6 +789,26 @@ void launch_mg_setup(const MgPlan& P, const float* w2, float* mg, int batch, hip
         hipLaunchKernelGGL(k_mg_restrict_c, dim3((n + 255) / 256, batch), dim3(256), 0, st, cf, cfz,
                            P.ny[l], P.nx[l], mg + P.c[l + 1], P.zstride);
     }
+    const int g0 = P.ngrid;
+    const float sc = std::ldexp(1.f, -2 * g0);   // beta scale 4^-g0 of the first in-LDS level
+    MgCoarseSetup S;
+    S.c = g0 == 0 ? w2 : mg + P.c[g0];
+    S.zs_c = g0 == 0 ? n0 : P.zstride;
+    S.aux = mg;
+    S.zs_aux = P.zstride;
+    for (int q = 0; q < kMgCoarseB; ++q) {
+        S.o_id[q] = P.id[q];
+        S.o_c[q] = P.cb[q];
+    }
+    S.o_g = P.gi;
+    S.beta = beta * sc;
+    S.beta_z = beta_z;
+    S.scale = sc;
+    S.ncb = P.ncb;
+    S.ne = P.ne;
+    coarse_dims(P, S.ny, S.nx);
+    hipLaunchKernelGGL(k_mg_coarse_setup, dim3(batch), dim3(kMgCoarseThreads), 0, st, S, skip,
+                       skip_zstride);
 }
 
 void launch_mg_vcycle(const MgPlan& P, const float* r, const float* w2, float* z, float* mg,
@@ -814,18 +886,22 @@ void launch_mg_vcycle(const MgPlan& P, const float* r, const float* w2, float* z
     G.zs_c = g0 == 0 ? n0 : P.zstride;
     G.e = g0 == 0 ? z : mg + P.e[g0];
     G.zs_e = g0 == 0 ? n0 : P.zstride;
+    G.aux = mg;
+    G.zs_aux = P.zstride;
+    for (int q = 0; q < kMgCoarseB; ++q) {
+        G.o_id[q] = P.id[q];
+        G.o_c[q] = P.cb[q];
+    }
+    G.o_g = P.gi;
     G.beta = bl[g0];
     G.beta_z = beta_z;
     G.scale = sc[g0];
-    G.nlev = P.ncoarse;
-    for (int q = 0; q < kMgMaxLevels; ++q) {
-        G.ny[q] = q < P.ncoarse ? P.ny[g0 + q] : 0;
-        G.nx[q] = q < P.ncoarse ? P.nx[g0 + q] : 0;
-    }
+    G.ncb = P.ncb;
+    G.ne = P.ne;
+    coarse_dims(P, G.ny, G.nx);
     G.dot = g0 == 0 ? dot : nullptr;
     G.dot_zstride = dot_zstride;
-    hipLaunchKernelGGL(k_mg_coarse, dim3(batch), dim3(kMgCoarseThreads), P.coarse_lds, st, G, skip,
-                       skip_zstride);
+    hipLaunchKernelGGL(k_mg_coarse, dim3(batch), dim3(kMgCoarseThreads), 0, st, G, skip, skip_zstride);
     // up: walk the same grouping from the bottom
     int top[kMgMaxLevels], ntop = 0;
     for (int l = 0; l < P.ngrid; l += P.pair[l] ? 2 : 1) top[ntop++] = l;

@@ -777,12 +777,11 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_backproject(
 // voxel-driven kernel does, and accumulates them times the residuals of
 // views v + t nv/4, t = 0..3, for the quads R^t of its own.  The partial
 // sums reach the tiles in LDS in a fixed order (turn, view class), so the
-// result is deterministic.  The grid is capped below the CU count and blocks
-// loop over the orbits, so that a few CUs stay free of these long-lived
-// workgroups for the short kernels of the concurrent PCG.
+// result is deterministic.  The grid covers at most half the CUs and blocks
+// loop over the orbits, so that the short kernels of the concurrent PCG find
+// CUs free of these long-lived workgroups.
 // ---------------------------------------------------------------------------
 constexpr int kBsWaves = 16;
-constexpr int kBsFreeCUs = 32;
 
 template <bool SB>
 __global__ __launch_bounds__(kBsWaves * 64) void k_backproject_sym(
@@ -950,17 +949,21 @@ __global__ __launch_bounds__(kBsWaves * 64) void k_backproject_sym(
     }   // orbits
 }
 
-static int sym_bp_blocks() {
-    static const int cap = [] {
+// Workgroups of the symmetric back-projector for `norb` orbits: at most half
+// the CUs (the PCG kernels of the concurrent stream run on the other half),
+// spread so that every block takes the same number of orbits.
+static int sym_bp_grid(int norb) {
+    static const int half = [] {
         int dev = 0, ncu = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
             (void)hipGetLastError();
-            return 224;
+            return 128;
         }
-        return std::max(ncu - kBsFreeCUs, ncu / 2);
+        return std::max(ncu / 2, 1);
     }();
-    return cap;
+    const int rounds = (norb + half - 1) / half;
+    return (norb + rounds - 1) / rounds;
 }
 
 void launch_backproject(const Geom& g, const RayTable& t, const void* sino, int npairs,
@@ -977,7 +980,7 @@ void launch_backproject(const Geom& g, const RayTable& t, const void* sino, int 
     }
     if (sym_mode != 0 && grid_sym4(g)) {
         const int norb = (g.nx / 32) * (g.nx / 32) * npairs;   // tile orbits of all pairs
-        dim3 grid(std::min(norb, sym_bp_blocks()));
+        dim3 grid(sym_bp_grid(norb));
         if (sino_bf16)
             hipLaunchKernelGGL(k_backproject_sym<true>, grid, dim3(kBsWaves * 64), 0, st, sino, t, g.nx,
                                (float)g.dx, out_pairs, out_split, nout, npairs);
