@@ -574,12 +574,17 @@ struct dect_solver {
                                      // B holds f^(k+1) during an iteration
     unsigned* cnt_proj;
     PcgBufs pcg;
-    // Concurrency within an iteration: the f-step and the rho_e step run on
-    // `side` while the t' PCG runs on st (all three read iterate k only);
-    // t' is double-buffered (the PCG writes t_next) and the side stream has
-    // its own FFT scratch.  side == nullptr: everything on st.
+    // Concurrency within an iteration: the f-step runs on `side` and the
+    // rho_e step on `rst` (or on `side`) while the t' PCG runs on pst (all
+    // read iterate k only); t' is double-buffered (the PCG writes t_next) and
+    // the rho_e step has its own FFT scratch.  side == nullptr: everything on st.
     hipStream_t side = nullptr;
     hipStream_t pst = nullptr;   // the t' PCG's stream while an iterate call runs
+    // sinogram form: the rho_e step on a third stream, concurrent with the
+    // forward projection (after the gradient has read rho^(k); the f update
+    // and the beta step wait for it); nullptr: on `side`
+    hipStream_t rst = nullptr;
+    hipEvent_t ev_grad = nullptr, ev_rho = nullptr, ev_rjoin = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_entry = nullptr, ev_mdone = nullptr;
     bool in_pipe = false;        // inside a run of pipelined iterations (pst, side forked)
     // software pipelining of consecutive iterations (see one_iteration)
@@ -661,9 +666,29 @@ static void make_side(dect_solver* s) {
         (void)hipStreamDestroy(s->side);
         (void)hipStreamDestroy(s->pst);
         s->side = s->pst = nullptr;
+        return;
+    }
+    // optional third stream for the rho_e step
+    hipEvent_t* revs[3] = {&s->ev_grad, &s->ev_rho, &s->ev_rjoin};
+    bool rok = hipStreamCreateWithFlags(&s->rst, hipStreamNonBlocking) == hipSuccess;
+    for (hipEvent_t* e : revs)
+        rok = rok && hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
+    if (!rok) {
+        (void)hipGetLastError();
+        for (hipEvent_t* e : revs)
+            if (*e) (void)hipEventDestroy(*e);
+        for (hipEvent_t* e : revs) *e = nullptr;
+        if (s->rst) (void)hipStreamDestroy(s->rst);
+        s->rst = nullptr;
     }
 }
 static void free_side(dect_solver* s) {
+    if (s->rst) {
+        (void)hipStreamSynchronize(s->rst);
+        for (hipEvent_t e : {s->ev_grad, s->ev_rho, s->ev_rjoin}) (void)hipEventDestroy(e);
+        (void)hipStreamDestroy(s->rst);
+        s->rst = nullptr;
+    }
     if (s->side) {
         (void)hipStreamSynchronize(s->side);
         (void)hipStreamSynchronize(s->pst);
@@ -677,26 +702,31 @@ static void free_side(dect_solver* s) {
     if (s->hs_pinned) (void)hipHostFree(s->hs_pinned);
     s->hs_pinned = nullptr;
 }
-// stream for the side work of an iteration, forked from st
-// entry of an iterate call: the PCG stream and the side stream start after
-// the caller's stream; returns the PCG stream (the caller's without them)
+// entry of an iterate call: the PCG stream, the side stream and the rho_e
+// stream start after the caller's stream; returns the PCG stream (the
+// caller's without them)
 static hipStream_t enter_iter(dect_solver* s) {
     if (!s->side) return s->st;
     if (!s->in_pipe) {
         (void)hipEventRecord(s->ev_entry, s->st);
         (void)hipStreamWaitEvent(s->pst, s->ev_entry, 0);
         (void)hipStreamWaitEvent(s->side, s->ev_entry, 0);
+        if (s->rst) (void)hipStreamWaitEvent(s->rst, s->ev_entry, 0);
         s->in_pipe = true;
     }
     return s->pst;
 }
-// exit: the caller's stream waits for both
+// exit: the caller's stream waits for all of them
 static void leave_iter(dect_solver* s) {
     if (!s->side || !s->in_pipe) return;
     (void)hipEventRecord(s->ev_mdone, s->pst);
     (void)hipEventRecord(s->ev_join, s->side);
     (void)hipStreamWaitEvent(s->st, s->ev_mdone, 0);
     (void)hipStreamWaitEvent(s->st, s->ev_join, 0);
+    if (s->rst) {
+        (void)hipEventRecord(s->ev_rjoin, s->rst);
+        (void)hipStreamWaitEvent(s->st, s->ev_rjoin, 0);
+    }
     s->in_pipe = false;
 }
 
@@ -1319,6 +1349,14 @@ static int one_iteration(dect_solver* s, bool more = false) {
         mark_end(s, side, t0, s->ev_bp);
     }
     launch_grad(s->M, a, P, s->f, s->B, s->rho, s->t, dir, s->part_img, side);
+    // rho_e step on its own stream once the gradient has read rho^(k)
+    const hipStream_t rs = two && s->rst ? s->rst : nullptr;
+    if (rs) {
+        DECT_HIP(hipEventRecord(s->ev_grad, side));
+        DECT_HIP(hipStreamWaitEvent(rs, s->ev_grad, 0));
+        rho_step(s, rs, s->fft2);
+        DECT_HIP(hipEventRecord(s->ev_rho, rs));
+    }
     ProjArgs pa;
     pa.res = s->zq;
     pa.c00 = (float)s->M.C[0][0];
@@ -1339,10 +1377,12 @@ static int one_iteration(dect_solver* s, bool more = false) {
     hipEvent_t t1 = mark(s, side);
     launch_project(g, P, s->tab, dir, s->batch, PROJ_LINESEARCH, pa, side);
     mark_end(s, side, t1, s->ev_fp);
-    rho_step(s, side, two ? s->fft2 : s->fft);
+    if (!rs) rho_step(s, side, two ? s->fft2 : s->fft);
     if (two) {
         DECT_HIP(hipEventRecord(s->ev_side, side));          // beta^(k) no longer read there
         DECT_HIP(hipStreamWaitEvent(side, s->ev_init, 0));   // f^(k) read by the PCG
+        // f^(k) read by the rho_e step; the next gradient reads rho^(k+1)
+        if (rs) DECT_HIP(hipStreamWaitEvent(side, s->ev_rho, 0));
     }
     // f^(k+1), residual sinograms (beta is stepped on st below)
     launch_update(a, P, s->tab, s->alpha, dir, s->f, s->S, s->zq, nullptr, nullptr, side);
@@ -1357,8 +1397,9 @@ static int one_iteration(dect_solver* s, bool more = false) {
     s->upd_pending = two;
     if (int rc = t_step_chunk(s, ms)) return rc;
     if (int rc = t_step_finish(s, ms)) return rc;
-    // ms: beta^(k+1) once the side work has read beta^(k)
+    // ms: beta^(k+1) once the side work and the rho_e step have read beta^(k)
     if (two) DECT_HIP(hipStreamWaitEvent(ms, s->ev_side, 0));
+    if (rs) DECT_HIP(hipStreamWaitEvent(ms, s->ev_rho, 0));
     launch_step_beta(s->beta_d, s->kappa_d, s->batch, ms);
     std::swap(s->t, s->t_next);
     if (s->storage == DECT_STORAGE_BF16_STATE) {
