@@ -642,7 +642,7 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_backproject(
     float2* __restrict__ out_pairs, float* __restrict__ out_split, int nout) {
     __shared__ float4 vs[kBpViewChunk];
     __shared__ int4 sfix[kBpWaves][64];
-    __shared__ float4 sray[kBpWaves][64];      // (2^-32/|s|, +-L, sino lo, sino hi)
+    __shared__ float4 sray[kBpWaves][64];      // (2^-32/|s|, +-L, L sino lo, L sino hi)
     __shared__ float red[kBpWaves][8][64];
     const int z = blockIdx.z;
     const SliceDesc D = T.desc[T.desc_stride * z];
@@ -693,8 +693,9 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_backproject(
                     const size_t r = (size_t)v * nd + jj;
                     const float2 fl = flt[r];
                     const float2 sv = SB ? bf16x2_unpack(szb[r]) : sz[r];
+                    const float L = fabsf(fl.y);
                     sfix[w][lane] = fix[r];
-                    sray[w][lane] = make_float4(fl.x, fl.y, sv.x, sv.y);
+                    sray[w][lane] = make_float4(fl.x, fl.y, L * sv.x, L * sv.y);
                 }
                 __builtin_amdgcn_wave_barrier();
                 const int ja = max(jl, base), jb = min(jh, base + 63);
@@ -720,8 +721,7 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_backproject(
                     const float cb1 = eb == 1 ? wb : (eb == o1 ? 1.f - wb : 0.f);
                     // (major, minor) offsets -> (row, column) offsets of the quad
                     const float c01 = xm ? cb0 : ca1, c10 = xm ? ca1 : cb0;
-                    const float L = fabsf(fs.y);
-                    const float s1 = L * fs.z, s2 = L * fs.w;
+                    const float s1 = fs.z, s2 = fs.w;
                     a00x = fmaf(ca0, s1, a00x);
                     a00y = fmaf(ca0, s2, a00y);
                     a01x = fmaf(c01, s1, a01x);
@@ -790,7 +790,7 @@ __global__ __launch_bounds__(kBsWaves * 64) void k_backproject_sym(
     __shared__ float4 vs[kBpViewChunk];
     __shared__ int4 sfix[kBsWaves][64];
     __shared__ float2 sfl[kBsWaves][64];        // (2^-32/|s|, +-L)
-    __shared__ float4 ssn[kBsWaves][64][2];     // residual pairs of the four turns
+    __shared__ float4 ssn[kBsWaves][64][2];     // L times the residual pairs of the four turns
     // the four tiles' sums [tile][channel][row][column], in ssn's memory once
     // every view is done
     float(*acc_t)[2][16][17] = reinterpret_cast<float(*)[2][16][17]>(&ssn[0][0][0]);
@@ -857,10 +857,12 @@ __global__ __launch_bounds__(kBsWaves * 64) void k_backproject_sym(
 #pragma unroll
                     for (int t = 0; t < 4; ++t)
                         s4[t] = SB ? bf16x2_unpack(szb[r + t * tstep]) : sz[r + t * tstep];
+                    const float2 fl = flt[r];
+                    const float L = fabsf(fl.y);
                     sfix[w][lane] = fix[r];
-                    sfl[w][lane] = flt[r];
-                    ssn[w][lane][0] = make_float4(s4[0].x, s4[0].y, s4[1].x, s4[1].y);
-                    ssn[w][lane][1] = make_float4(s4[2].x, s4[2].y, s4[3].x, s4[3].y);
+                    sfl[w][lane] = fl;
+                    ssn[w][lane][0] = make_float4(L * s4[0].x, L * s4[0].y, L * s4[1].x, L * s4[1].y);
+                    ssn[w][lane][1] = make_float4(L * s4[2].x, L * s4[2].y, L * s4[3].x, L * s4[3].y);
                 }
                 __builtin_amdgcn_wave_barrier();
                 const int ja = max(jl, base), jb = min(jh, base + 63);
@@ -883,12 +885,11 @@ __global__ __launch_bounds__(kBsWaves * 64) void k_backproject_sym(
                     const float cb0 = eb == 0 ? wb : (eb == o0 ? 1.f - wb : 0.f);
                     const float cb1 = eb == 1 ? wb : (eb == o1 ? 1.f - wb : 0.f);
                     const float c01 = xm ? cb0 : ca1, c10 = xm ? ca1 : cb0;
-                    const float L = fabsf(fs.y);
                     const float4 sA = ssn[w][j - base][0], sB = ssn[w][j - base][1];
                     const float sv[8] = {sA.x, sA.y, sA.z, sA.w, sB.x, sB.y, sB.z, sB.w};
 #pragma unroll
                     for (int t = 0; t < 4; ++t) {
-                        const float s1 = L * sv[2 * t], s2 = L * sv[2 * t + 1];
+                        const float s1 = sv[2 * t], s2 = sv[2 * t + 1];
                         acc[t][0] = fmaf(ca0, s1, acc[t][0]);
                         acc[t][1] = fmaf(ca0, s2, acc[t][1]);
                         acc[t][2] = fmaf(c01, s1, acc[t][2]);
