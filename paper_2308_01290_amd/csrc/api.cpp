@@ -383,14 +383,17 @@ static void apply_prec(const PcgArgs& a, int it, const PcgBufs& b, float2* fft_s
     if (a.prec == PREC_MG) launch_pcg_mg_prec(a, it, b.mg_plan, b.mg, st);
 }
 
-// Runs PCG iterations (after an init kernel) until every slice converged or
-// max_iter.  The host checks convergence once per chunk of iterations; the
-// first chunk is sized from the previous solve.  Returns the largest count.
 // A PCG solve in two halves: pcg_enqueue puts the set-up and a first chunk of
 // iterations on the stream and returns at once; pcg_finish waits for the
 // host-visible stopping flags and enqueues further chunks until every slice
-// stopped (or max_iter).  The host checks once per chunk; the first chunk is
-// sized from the previous solve.
+// stopped (or max_iter).  The host checks once per chunk.  The first chunk is
+// as long as the previous solve of the same solver took (successive t' steps
+// need about the same count, and an iteration enqueued past the stop still
+// costs its launches), further chunks kPcgMoreChunk iterations, doubling up
+// to kPcgMaxChunk.
+constexpr int kPcgMoreChunk = 2;
+constexpr int kPcgMaxChunk = 64;
+
 struct PcgRun {
     PcgArgs a;
     int it = 0, max_iter = 0;
@@ -455,12 +458,14 @@ static int pcg_enqueue(PcgRun& R, const PcgBufs& b, float2* fft_scratch, hipStre
 static int pcg_finish(PcgRun& R, const PcgBufs& b, float2* fft_scratch, hipStream_t st,
                       int* iters_out) {
     const int batch = R.a.batch;
+    int more = kPcgMoreChunk;
     while (true) {
         DECT_HIP(hipStreamSynchronize(st));
         bool all = true;
         for (int z = 0; z < batch; ++z) all = all && R.hs[z].done;
         if (all || R.it >= R.max_iter) break;
-        pcg_chunk(R, b, fft_scratch, st, 4);
+        pcg_chunk(R, b, fft_scratch, st, more);
+        more = std::min(2 * more, kPcgMaxChunk);
         DECT_HIP(hipGetLastError());
         DECT_HIP(hipMemcpyAsync(R.hs, R.a.st, sizeof(PcgState) * batch, hipMemcpyDeviceToHost, st));
     }
@@ -1220,7 +1225,7 @@ static int t_step_start(dect_solver* s, hipStream_t ms, hipEvent_t after_init) {
 // the first chunk of PCG iterations (after t_step_start; the host enqueues the
 // other stream's work in between so that it is not queued behind this chunk)
 static int t_step_chunk(dect_solver* s, hipStream_t ms) {
-    return pcg_first_chunk(s->prun, s->pcg, s->fft, ms, s->last_pcg + 2, s->hs_pinned);
+    return pcg_first_chunk(s->prun, s->pcg, s->fft, ms, s->last_pcg, s->hs_pinned);
 }
 
 // second half: wait for the stopping flags, more chunks while needed
