@@ -777,9 +777,9 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_backproject(
 // voxel-driven kernel does, and accumulates them times the residuals of
 // views v + t nv/4, t = 0..3, for the quads R^t of its own.  The partial
 // sums reach the tiles in LDS in a fixed order (turn, view class), so the
-// result is deterministic.  The grid covers at most half the CUs and blocks
-// loop over the orbits, so that the short kernels of the concurrent PCG find
-// CUs free of these long-lived workgroups.
+// result is deterministic.  Blocks loop over the orbits; for one slice the
+// grid covers at most half the CUs, so that the short kernels of the
+// concurrent PCG find CUs free of these long-lived workgroups.
 // ---------------------------------------------------------------------------
 constexpr int kBsWaves = 16;
 
@@ -950,20 +950,23 @@ __global__ __launch_bounds__(kBsWaves * 64) void k_backproject_sym(
     }   // orbits
 }
 
-// Workgroups of the symmetric back-projector for `norb` orbits: at most half
-// the CUs (the PCG kernels of the concurrent stream run on the other half),
-// spread so that every block takes the same number of orbits.
+// Workgroups of the symmetric back-projector for `norb` orbits, spread so that
+// every block takes the same number of orbits.  Up to one orbit per CU (a
+// single slice), at most half the CUs: the latency-bound PCG kernels of the
+// concurrent stream run on the other half.  Larger batches, where every
+// stream's work is throughput-bound, take all CUs.
 static int sym_bp_grid(int norb) {
-    static const int half = [] {
-        int dev = 0, ncu = 0;
+    static const int ncu = [] {
+        int dev = 0, n = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
             (void)hipGetLastError();
-            return 128;
+            return 256;
         }
-        return std::max(ncu / 2, 1);
+        return std::max(n, 2);
     }();
-    const int rounds = (norb + half - 1) / half;
+    const int cap = norb <= ncu ? ncu / 2 : ncu;
+    const int rounds = (norb + cap - 1) / cap;
     return (norb + rounds - 1) / rounds;
 }
 
