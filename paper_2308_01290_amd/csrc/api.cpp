@@ -504,7 +504,7 @@ struct BatchGeo {
     long long sino_total = 0;
     int nv_max = 0, nd_max = 0;
     bool rev = false;   // pair blocks carry the reversed layouts (some slice may be quarter-turn symmetric)
-    int sym_mode = 0;   // back-projection: 0 no slice symmetric, 1 all, 2 mixed
+    int kinds = kSlicePlain;   // kSlice* bits of the slices (which back-projectors run)
 };
 
 // dedupe = false: every slice gets a table of its own (slots that change
@@ -544,14 +544,14 @@ static int make_batch(const dect_geometry* gin, int batch, BatchGeo* B, bool ded
         B->nd_max = std::max(B->nd_max, a.nd);
     }
     if (B->rays > (size_t)INT32_MAX) return fail(DECT_EINVAL, "batch ray tables exceed 2^31 rays");
-    int nsym = 0;
-    for (const Geom& a : B->g) nsym += sym4(a) ? 1 : 0;
+    int kinds = 0;
+    for (const Geom& a : B->g) kinds |= slice_kind(a);
     if (!dedupe) {   // slots: any admitted geometry may be symmetric
         B->rev = grid_sym4(B->g[0]);
-        B->sym_mode = B->rev ? 2 : 0;
+        B->kinds = B->rev ? (kSlicePlain | kSliceQuarter | kSliceOcto) : kSlicePlain;
     } else {
-        B->rev = nsym > 0;
-        B->sym_mode = nsym == 0 ? 0 : (nsym == batch ? 1 : 2);
+        B->rev = (kinds & ~kSlicePlain) != 0;
+        B->kinds = kinds;
     }
     return DECT_OK;
 }
@@ -826,7 +826,7 @@ int dect_backproject(const dect_geometry* gin, const float* sino, float* img, in
     if (int rc = temp_alloc(&tmp, nray * np * sizeof(float2), st)) return rc;
     float2* sp = static_cast<float2*>(tmp.p);
     launch_pair_sinos(g, sino, batch, sp, st);
-    launch_backproject(g, t, sp, np, nullptr, img, batch, st, false, sym4(g) ? 1 : 0);
+    launch_backproject(g, t, sp, np, nullptr, img, batch, st, false, slice_kind(g));
     DECT_HIP(hipGetLastError());
     return DECT_OK;
 }
@@ -1116,7 +1116,7 @@ static void project_residual(dect_solver* s, const float* lo, const float* hi) {
     a.c10 = (float)s->M.C[1][0];
     a.c11 = (float)s->M.C[1][1];
     a.res_bf16 = s->storage != DECT_STORAGE_FP32;
-    a.sym_all = s->geo.sym_mode == 1;
+    a.sym_all = !(s->geo.kinds & kSlicePlain);
     launch_project(s->g, P, s->tab, s->dpad, s->batch, PROJ_RESID, a, s->st);
 }
 
@@ -1350,7 +1350,7 @@ static int one_iteration(dect_solver* s, bool more = false) {
     if (two && s->upd_pending) DECT_HIP(hipStreamWaitEvent(side, s->ev_tdone, 0));
     if (!s->bp_pending) {
         hipEvent_t t0 = mark(s, side);
-        launch_backproject(g, s->tab, s->S, s->batch, s->B, nullptr, 0, side, a.bf16, s->geo.sym_mode);
+        launch_backproject(g, s->tab, s->S, s->batch, s->B, nullptr, 0, side, a.bf16, s->geo.kinds);
         mark_end(s, side, t0, s->ev_bp);
     }
     launch_grad(s->M, a, P, s->f, s->B, s->rho, s->t, dir, s->part_img, side);
@@ -1378,7 +1378,7 @@ static int one_iteration(dect_solver* s, bool more = false) {
     pa.alpha = s->alpha;
     pa.counter = s->cnt_proj;
     pa.pad_bf16 = pa.res_bf16 = a.bf16;
-    pa.sym_all = s->geo.sym_mode == 1;
+    pa.sym_all = !(s->geo.kinds & kSlicePlain);
     hipEvent_t t1 = mark(s, side);
     launch_project(g, P, s->tab, dir, s->batch, PROJ_LINESEARCH, pa, side);
     mark_end(s, side, t1, s->ev_fp);
@@ -1395,7 +1395,7 @@ static int one_iteration(dect_solver* s, bool more = false) {
     s->bp_pending = false;
     if (two && more) {   // next back-projection while the host waits for the PCG
         hipEvent_t t2 = mark(s, side);
-        launch_backproject(g, s->tab, s->S, s->batch, s->B, nullptr, 0, side, a.bf16, s->geo.sym_mode);
+        launch_backproject(g, s->tab, s->S, s->batch, s->B, nullptr, 0, side, a.bf16, s->geo.kinds);
         mark_end(s, side, t2, s->ev_bp);
         s->bp_pending = true;
     }

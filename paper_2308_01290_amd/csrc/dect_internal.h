@@ -41,6 +41,20 @@ inline bool sym4(const Geom& g) {
            g.arc > two_pi * (1.0 - 1e-12) && g.arc < two_pi * (1.0 + 1e-12);
 }
 inline int table_views(const Geom& g) { return sym4(g) ? g.nv / 4 : g.nv; }
+// Transpose symmetry on top of the quarter turns: with the detector centred
+// and the first view at angle 0, view nv/4 - v is view v reflected about the
+// image diagonal with the bins reversed, which maps pixel (i, k) to (k, i).
+// The table's views nv/8 < v < nv/4 are then defined as the transposes of
+// views nv/4 - v, and the back-projector evaluates each weight once for
+// eight views.
+inline bool sym8(const Geom& g) {
+    return sym4(g) && g.angle0 == 0.0 && g.offset == 0.0;
+}
+// slice kinds, as bits: which back-projection kernels a batch needs
+enum { kSlicePlain = 1, kSliceQuarter = 2, kSliceOcto = 4 };
+inline int slice_kind(const Geom& g) {
+    return sym8(g) ? kSliceOcto : (sym4(g) ? kSliceQuarter : kSlicePlain);
+}
 
 // Per-ray traversal table, built on the device in FP64.
 // For ray (v, j) the ray is parametrised along its major axis (the pixel
@@ -69,7 +83,8 @@ struct SliceDesc {
     float sid, sdd;        // source-isocentre, source-detector distance (mm)
     float u0, inv_pitch;   // detector coordinate of bin 0 (mm), 1 / bin pitch
     double eta;            // projection-data weight of eq. (10) for this geometry
-    int sym;               // quarter-turn symmetric (table of nv / 4 views)
+    int sym;               // 1: quarter-turn symmetric (table of nv / 4 views); 2: also
+                           // transpose-symmetric (views nv/8 < v < nv/4 derived)
 };
 struct RayTable {
     int4* fix = nullptr;
@@ -178,11 +193,11 @@ void launch_project(const Geom& g, const PadLayout& P, const RayTable& t, const 
 // ---- back-projector -------------------------------------------------------------
 // sino pairs [z][nv][nd] (float2, or BF16 pairs in 32-bit words) -> out pairs
 // [z][ny][nx] (float2) or split images.
-// sym_mode: 0 = no slice is quarter-turn symmetric, 1 = all are, 2 = mixed
+// kinds: the kSlice* bits of the pairs' slices (one kernel per kind present)
 // (two launches, each skipping the other kind of slice)
 void launch_backproject(const Geom& g, const RayTable& t, const void* sino, int npairs,
                         float2* out_pairs, float* out_split, int nout, hipStream_t st,
-                        bool sino_bf16 = false, int sym_mode = 0);
+                        bool sino_bf16 = false, int kinds = kSlicePlain);
 
 // ---- FBP ---------------------------------------------------------------------
 // q = filtered sinograms (scratch, [nsino][nv][nd]); img [nsino][ny][nx]

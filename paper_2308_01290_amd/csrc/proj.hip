@@ -41,18 +41,27 @@ __device__ __forceinline__ float first_weight(unsigned lo, unsigned xmask, float
 // ---------------------------------------------------------------------------
 // ray table (FP64 geometry, FP32 storage)
 // ---------------------------------------------------------------------------
-__global__ void k_build_ray_table(Geom g, int4* __restrict__ fix, float2* __restrict__ flt,
+// xq > 0 (slices with the transpose symmetry, xq = nv / 4): the rays of views
+// xq/2 < v < xq are the transposes of rays (xq - v, nd - 1 - j), the same
+// fixed-point entries with the other major axis, so that the transpose is an
+// exact symmetry of the projector
+__global__ void k_build_ray_table(Geom g, int xq, int4* __restrict__ fix, float2* __restrict__ flt,
                                   int2* __restrict__ span, float4* __restrict__ view) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int v = blockIdx.y;
+    const int j0 = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v0 = blockIdx.y;
+    if (j0 == 0) {
+        const double th0 = g.angle0 + (double)v0 * (g.arc / (double)g.nv);
+        double sn0, cs0;
+        sincos(th0, &sn0, &cs0);
+        const double h = 0.5 * g.dx;
+        view[v0] = make_float4((float)cs0, (float)sn0, (float)(h * (fabs(cs0) + fabs(sn0))), 0.f);
+    }
+    if (j0 >= g.nd) return;
+    const bool tr = xq > 0 && 2 * v0 > xq;
+    const int v = tr ? xq - v0 : v0, j = tr ? g.nd - 1 - j0 : j0;
     const double th = g.angle0 + (double)v * (g.arc / (double)g.nv);
     double sn, cs;
     sincos(th, &sn, &cs);
-    if (j == 0) {
-        const double h = 0.5 * g.dx;
-        view[v] = make_float4((float)cs, (float)sn, (float)(h * (fabs(cs) + fabs(sn))), 0.f);
-    }
-    if (j >= g.nd) return;
     const double u = ((double)j - 0.5 * (double)(g.nd - 1)) * g.pitch + g.offset;
     const double Sx = g.sid * cs, Sy = g.sid * sn;
     const double Qx = -(g.sdd - g.sid) * cs - u * sn;
@@ -105,11 +114,11 @@ __global__ void k_build_ray_table(Geom g, int4* __restrict__ fix, float2* __rest
     }
     const long long A0 = llrint(a0 * 4294967296.0);
     const long long S = llrint(slope * 4294967296.0);
-    const size_t r = (size_t)v * g.nd + j;
+    const size_t r = (size_t)v0 * g.nd + j0;
     fix[r] = make_int4((int)(unsigned)(A0 & 0xffffffffLL), (int)(A0 >> 32),
                        (int)(unsigned)(S & 0xffffffffLL), (int)(S >> 32));
     flt[r] = make_float2(slope == 0.0 ? __builtin_inff() : (float)(fabs(1.0 / slope) * 0x1p-32),
-                         xmaj ? (float)L : -(float)L);
+                         xmaj != tr ? (float)L : -(float)L);
     span[r] = make_int2(klo, khi);
 }
 
@@ -125,7 +134,7 @@ SliceDesc make_slice_desc(const Geom& g, int ray0, int view0, long long sino0, d
     d.u0 = (float)(-0.5 * (g.nd - 1) * g.pitch + g.offset);
     d.inv_pitch = (float)(1.0 / g.pitch);
     d.eta = eta;
-    d.sym = sym4(g) ? 1 : 0;
+    d.sym = sym8(g) ? 2 : (sym4(g) ? 1 : 0);
     return d;
 }
 
@@ -142,7 +151,8 @@ void launch_set_int(int* p, int value, hipStream_t st) {
 
 void launch_build_ray_table(const Geom& g, RayTable t, hipStream_t st) {
     dim3 grid((g.nd + 255) / 256, table_views(g));
-    hipLaunchKernelGGL(k_build_ray_table, grid, dim3(256), 0, st, g, t.fix, t.flt, t.span, t.view);
+    hipLaunchKernelGGL(k_build_ray_table, grid, dim3(256), 0, st, g, sym8(g) ? g.nv / 4 : 0, t.fix,
+                       t.flt, t.span, t.view);
 }
 
 // ---------------------------------------------------------------------------
@@ -800,7 +810,7 @@ __global__ __launch_bounds__(kBsWaves * 64) void k_backproject_sym(
     const int z = orb / (nq * nq);
     const int obx = orb % nq, oby = (orb / nq) % nq;
     const SliceDesc D = T.desc[T.desc_stride * z];
-    if (!D.sym) continue;   // block-uniform
+    if (D.sym != 1) continue;   // block-uniform (sym == 2: k_backproject_sym8)
     const int nd = D.nd, q4 = D.nv >> 2;
     const float sid = D.sid, sdd = D.sdd, u0 = D.u0, inv_pitch = D.inv_pitch;
     const int4* __restrict__ fix = T.fix + D.ray0;
@@ -950,6 +960,260 @@ __global__ __launch_bounds__(kBsWaves * 64) void k_backproject_sym(
     }   // orbits
 }
 
+// ---------------------------------------------------------------------------
+// back-projector of slices with the transpose symmetry as well (sym == 2).
+// T(i, k) = (k, i) maps ray (v, j) of the table to ray (nv/4 - v, nd - 1 - j),
+// whose table entry is its exact transpose, and T R^s = R^-s T.  The tiles of
+// the image's first quadrant fall into orbits of the group generated by R and
+// T: a pair (P, P^T) of off-diagonal tiles and their turns (8 tiles), or one
+// diagonal tile and its turns (4 tiles).  A lane evaluates the weights of
+// table ray (v, j), v <= nv/8, on its quad q once and adds them, times the
+// residuals of the rays R^t r and R^t T r, to the pixels R^t q and R^t T q
+// (views v = 0 and v = nv/8 are their own transposes' turns and take the
+// four turns only).  A work unit is one 8-tile orbit or two 4-tile orbits,
+// so the units of a slice are of equal size: 16 wavefronts as 8 tiles x 2
+// view classes, or 4 tiles x 4 classes.  The partial sums reach the tiles in
+// LDS in a fixed order, so the result is deterministic.
+// ---------------------------------------------------------------------------
+constexpr int kB8Waves = 16;
+
+// work units of one slice: 8-tile orbits, then pairs of 4-tile orbits
+__host__ __device__ inline int sym8_units(int n) {
+    const int nq = n / 32;
+    return nq * (nq - 1) / 2 + (nq + 1) / 2;
+}
+
+template <bool SB>
+__global__ __launch_bounds__(kB8Waves * 64) void k_backproject_sym8(
+    const void* __restrict__ sino, RayTable T, int n, float dxmm, float2* __restrict__ out_pairs,
+    float* __restrict__ out_split, int nout, int npairs) {
+    __shared__ float4 vs[kBpViewChunk];
+    __shared__ int4 sfix[kB8Waves][64];
+    __shared__ float2 sfl[kB8Waves][64];        // (2^-32/|s|, +-L)
+    __shared__ float4 ssn[kB8Waves][64][4];     // L times the residual pairs of R^t r, then of R^t T r
+    // the tiles' sums [tile][channel][row][column], in ssn's memory once every
+    // view is done
+    float(*acc_t)[2][16][17] = reinterpret_cast<float(*)[2][16][17]>(&ssn[0][0][0]);
+    static_assert(sizeof(ssn) >= sizeof(float) * 8 * 2 * 16 * 17, "tile sums");
+    const int nq = n / 32;
+    const int nheavy = nq * (nq - 1) / 2, nunit = sym8_units(n);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int unit = blockIdx.x; unit < nunit * npairs; unit += gridDim.x) {
+    const int z = unit / nunit, u = unit - z * nunit;
+    const SliceDesc D = T.desc[T.desc_stride * z];
+    if (D.sym != 2) continue;   // block-uniform
+    // the unit's orbits, by the first-quadrant tile row and column of P
+    int norb = 1, pa[2], pb[2];
+    if (u < nheavy) {
+        int a = 0, r = u;
+        while (r >= nq - 1 - a) {
+            r -= nq - 1 - a;
+            ++a;
+        }
+        pa[0] = a;
+        pb[0] = a + 1 + r;
+        pa[1] = pb[1] = 0;
+    } else {
+        const int d0 = 2 * (u - nheavy);
+        norb = min(2, nq - d0);
+        pa[0] = pb[0] = d0;
+        pa[1] = pb[1] = d0 + 1;
+    }
+    const int nd = D.nd, q4 = D.nv >> 2, vmax = q4 >> 1;
+    const float sid = D.sid, sdd = D.sdd, u0 = D.u0, inv_pitch = D.inv_pitch;
+    const int4* __restrict__ fix = T.fix + D.ray0;
+    const float2* __restrict__ flt = T.flt + D.ray0;
+    const float4* __restrict__ view = T.view + D.view0;
+    const long long sbase = D.sino0 + (long long)z * T.sino_zstride;
+    const float2* sz = reinterpret_cast<const float2*>(sino) + sbase;
+    const unsigned* szb = reinterpret_cast<const unsigned*>(sino) + sbase;
+    const size_t tstep = (size_t)q4 * nd;   // rays of one quarter of the views
+    for (int o = 0; o < norb; ++o) {
+    const bool heavy = pa[o] != pb[o];   // block-uniform
+    const int ntile = heavy ? 8 : 4, ncls = heavy ? 2 : 4;
+    const int d = heavy ? (w & 7) : (w & 3), cls = heavy ? (w >> 3) : (w >> 2);
+    // tile d = 4 f + s is R^s of P (f = 0) or of P^T (f = 1); R maps the tile
+    // at (ty, tx) to the one at (tx, n - 16 - ty)
+    int oy[8], ox[8];
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+        const int ty = 16 * (f ? pb[o] : pa[o]), tx = 16 * (f ? pa[o] : pb[o]);
+        oy[4 * f + 0] = ty;
+        ox[4 * f + 0] = tx;
+        oy[4 * f + 1] = tx;
+        ox[4 * f + 1] = n - 16 - ty;
+        oy[4 * f + 2] = n - 16 - ty;
+        ox[4 * f + 2] = n - 16 - tx;
+        oy[4 * f + 3] = n - 16 - tx;
+        ox[4 * f + 3] = ty;
+    }
+    const int i0 = oy[d] + 2 * (lane >> 3), k0 = ox[d] + 2 * (lane & 7);
+    const float x = ((float)k0 + 0.5f - 0.5f * (float)(n - 1)) * dxmm;
+    const float y = ((float)i0 + 0.5f - 0.5f * (float)(n - 1)) * dxmm;
+    // acc[t][q]: ray R^t r at pixel R^t (i0 + di, k0 + dk), q = 2 (2 di + dk) + channel;
+    // acx[t][q]: ray R^t T r at pixel R^t T (i0 + di, k0 + dk)
+    float acc[4][8], acx[4][8];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[t][q] = acx[t][q] = 0.f;
+    for (int v0 = 0; v0 <= vmax; v0 += kBpViewChunk) {
+        const int nvc = min(kBpViewChunk, vmax + 1 - v0);
+        __syncthreads();
+        for (int q = threadIdx.x; q < nvc; q += kB8Waves * 64) vs[q] = view[v0 + q];
+        __syncthreads();
+        for (int vv = cls; vv < nvc; vv += ncls) {
+            const int v = v0 + vv;
+            const bool pair = v > 0 && 2 * v != q4;   // wave-uniform
+            const int vx = q4 - v;                    // table view of T r (with bins reversed)
+            const float4 vc = vs[vv];
+            const float e = 2.f * vc.z;
+            const float U = sid - (x * vc.x + y * vc.y);
+            const float W = y * vc.x - x * vc.y;
+            const float rm = __builtin_amdgcn_rcpf(U - e);
+            const float rp = __builtin_amdgcn_rcpf(U + e);
+            const float hi = W + e, lo = W - e;
+            const float umax = sdd * hi * (hi >= 0.f ? rm : rp);
+            const float umin = sdd * lo * (lo >= 0.f ? rp : rm);
+            int jl = max((int)ceilf((umin - u0) * inv_pitch - 1e-3f), 0);
+            int jh = min((int)floorf((umax - u0) * inv_pitch + 1e-3f), nd - 1);
+            if (jl > jh) {
+                jl = INT_MAX;
+                jh = INT_MIN;
+            }
+            const int Jlo = wave_min(jl), Jhi = wave_max(jh);
+            if (Jlo > Jhi) continue;   // wave-uniform
+            for (int base = Jlo; base <= Jhi; base += 64) {
+                const int jj = base + lane;
+                if (jj <= Jhi) {
+                    const size_t r = (size_t)v * nd + jj;
+                    const float2 fl = flt[r];
+                    const float L = fabsf(fl.y);
+                    float2 s4[4];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        s4[t] = SB ? bf16x2_unpack(szb[r + t * tstep]) : sz[r + t * tstep];
+                    sfix[w][lane] = fix[r];
+                    sfl[w][lane] = fl;
+                    ssn[w][lane][0] = make_float4(L * s4[0].x, L * s4[0].y, L * s4[1].x, L * s4[1].y);
+                    ssn[w][lane][1] = make_float4(L * s4[2].x, L * s4[2].y, L * s4[3].x, L * s4[3].y);
+                    if (pair) {
+                        const size_t rx = (size_t)vx * nd + (nd - 1 - jj);
+#pragma unroll
+                        for (int t = 0; t < 4; ++t)
+                            s4[t] = SB ? bf16x2_unpack(szb[rx + t * tstep]) : sz[rx + t * tstep];
+                        ssn[w][lane][2] = make_float4(L * s4[0].x, L * s4[0].y, L * s4[1].x, L * s4[1].y);
+                        ssn[w][lane][3] = make_float4(L * s4[2].x, L * s4[2].y, L * s4[3].x, L * s4[3].y);
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
+                const int ja = max(jl, base), jb = min(jh, base + 63);
+                for (int j = ja; j <= jb; ++j) {
+                    const int4 fx = sfix[w][j - base];
+                    const float2 fs = sfl[w][j - base];
+                    const bool xm = fs.y > 0.f;
+                    const long long S = fix_s(fx);
+                    const bool up = S >= 0;
+                    const int maj0 = xm ? k0 : i0, mnr0 = xm ? i0 : k0;
+                    const long long ya = fix_a0(fx) + (long long)(unsigned)maj0 * S;
+                    const long long yb = ya + S;
+                    const unsigned xmask = up ? ~0u : 0u;
+                    const float wa = first_weight((unsigned)ya, xmask, fs.x);
+                    const float wb = first_weight((unsigned)yb, xmask, fs.x);
+                    const int ea = (int)(ya >> 32) - mnr0, eb = (int)(yb >> 32) - mnr0;
+                    const int o0 = up ? -1 : 1, o1 = up ? 0 : 2;
+                    const float ca0 = ea == 0 ? wa : (ea == o0 ? 1.f - wa : 0.f);
+                    const float ca1 = ea == 1 ? wa : (ea == o1 ? 1.f - wa : 0.f);
+                    const float cb0 = eb == 0 ? wb : (eb == o0 ? 1.f - wb : 0.f);
+                    const float cb1 = eb == 1 ? wb : (eb == o1 ? 1.f - wb : 0.f);
+                    const float c01 = xm ? cb0 : ca1, c10 = xm ? ca1 : cb0;
+                    const float4 sA = ssn[w][j - base][0], sB = ssn[w][j - base][1];
+                    const float sv[8] = {sA.x, sA.y, sA.z, sA.w, sB.x, sB.y, sB.z, sB.w};
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const float s1 = sv[2 * t], s2 = sv[2 * t + 1];
+                        acc[t][0] = fmaf(ca0, s1, acc[t][0]);
+                        acc[t][1] = fmaf(ca0, s2, acc[t][1]);
+                        acc[t][2] = fmaf(c01, s1, acc[t][2]);
+                        acc[t][3] = fmaf(c01, s2, acc[t][3]);
+                        acc[t][4] = fmaf(c10, s1, acc[t][4]);
+                        acc[t][5] = fmaf(c10, s2, acc[t][5]);
+                        acc[t][6] = fmaf(cb1, s1, acc[t][6]);
+                        acc[t][7] = fmaf(cb1, s2, acc[t][7]);
+                    }
+                    if (pair) {
+                        const float4 sC = ssn[w][j - base][2], sD = ssn[w][j - base][3];
+                        const float sx[8] = {sC.x, sC.y, sC.z, sC.w, sD.x, sD.y, sD.z, sD.w};
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            const float s1 = sx[2 * t], s2 = sx[2 * t + 1];
+                            acx[t][0] = fmaf(ca0, s1, acx[t][0]);
+                            acx[t][1] = fmaf(ca0, s2, acx[t][1]);
+                            acx[t][2] = fmaf(c01, s1, acx[t][2]);
+                            acx[t][3] = fmaf(c01, s2, acx[t][3]);
+                            acx[t][4] = fmaf(c10, s1, acx[t][4]);
+                            acx[t][5] = fmaf(c10, s2, acx[t][5]);
+                            acx[t][6] = fmaf(cb1, s1, acx[t][6]);
+                            acx[t][7] = fmaf(cb1, s2, acx[t][7]);
+                        }
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+    }
+    // the tiles in LDS: in each round (image g, turn t, view class c) the
+    // wavefronts of class c add into distinct tiles; R^t maps tile 4 f + s to
+    // 4 f + (s + t) mod 4, R^t T to 4 (1 - f) + (t - s) mod 4 (for a 4-tile
+    // orbit P^T = P: tile (t - s) mod 4)
+    __syncthreads();
+    for (int q = threadIdx.x; q < ntile * 2 * 16 * 17; q += kB8Waves * 64) (&acc_t[0][0][0][0])[q] = 0.f;
+    const int f = d >> 2, s = d & 3;
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int b = g == 0 ? 4 * f + ((s + t) & 3) : (heavy ? 4 * (1 - f) : 0) + ((t - s) & 3);
+            for (int c = 0; c < ncls; ++c) {
+                __syncthreads();
+                if (cls != c) continue;
+#pragma unroll
+                for (int dq = 0; dq < 4; ++dq) {
+                    const int pi = i0 + (dq >> 1), pk = k0 + (dq & 1);
+                    int gi = g ? pk : pi, gk = g ? pi : pk;   // T p for g = 1
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) {   // R^t: R(i, k) = (k, n - 1 - i)
+                        if (r < t) {
+                            const int ni = gk;
+                            gk = n - 1 - gi;
+                            gi = ni;
+                        }
+                    }
+                    const int li = gi - oy[b], lk = gk - ox[b];
+                    acc_t[b][0][li][lk] += g ? acx[t][2 * dq] : acc[t][2 * dq];
+                    acc_t[b][1][li][lk] += g ? acx[t][2 * dq + 1] : acc[t][2 * dq + 1];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const size_t npix = (size_t)n * n;
+    for (int q = threadIdx.x; q < ntile * 256; q += kB8Waves * 64) {
+        const int b = q >> 8, li = (q >> 4) & 15, lk = q & 15;
+        const size_t p = (size_t)(oy[b] + li) * n + (ox[b] + lk);
+        const float s1 = acc_t[b][0][li][lk], s2 = acc_t[b][1][li][lk];
+        if (out_pairs) {
+            out_pairs[(size_t)z * npix + p] = make_float2(s1, s2);
+        } else {
+            out_split[(size_t)(2 * z) * npix + p] = s1;
+            if (2 * z + 1 < nout) out_split[(size_t)(2 * z + 1) * npix + p] = s2;
+        }
+    }
+    __syncthreads();   // acc_t (in ssn) is reused by the next orbit
+    }   // orbits of the unit
+    }   // units
+}
+
 // Workgroups of the symmetric back-projector for `norb` orbits, spread so that
 // every block takes the same number of orbits.  Up to one orbit per CU (a
 // single slice), at most half the CUs: the latency-bound PCG kernels of the
@@ -972,8 +1236,8 @@ static int sym_bp_grid(int norb) {
 
 void launch_backproject(const Geom& g, const RayTable& t, const void* sino, int npairs,
                         float2* out_pairs, float* out_split, int nout, hipStream_t st,
-                        bool sino_bf16, int sym_mode) {
-    if (sym_mode != 1) {
+                        bool sino_bf16, int kinds) {
+    if (kinds & kSlicePlain) {
         dim3 grid((g.nx + 15) / 16, (g.ny + 15) / 16, npairs);
         if (sino_bf16)
             hipLaunchKernelGGL(k_backproject<true>, grid, dim3(kBpWaves * 64), 0, st, sino, t, g.nx,
@@ -982,7 +1246,7 @@ void launch_backproject(const Geom& g, const RayTable& t, const void* sino, int 
             hipLaunchKernelGGL(k_backproject<false>, grid, dim3(kBpWaves * 64), 0, st, sino, t, g.nx,
                                g.ny, (float)g.dx, out_pairs, out_split, nout);
     }
-    if (sym_mode != 0 && grid_sym4(g)) {
+    if ((kinds & kSliceQuarter) && grid_sym4(g)) {
         const int norb = (g.nx / 32) * (g.nx / 32) * npairs;   // tile orbits of all pairs
         dim3 grid(sym_bp_grid(norb));
         if (sino_bf16)
@@ -990,6 +1254,16 @@ void launch_backproject(const Geom& g, const RayTable& t, const void* sino, int 
                                (float)g.dx, out_pairs, out_split, nout, npairs);
         else
             hipLaunchKernelGGL(k_backproject_sym<false>, grid, dim3(kBsWaves * 64), 0, st, sino, t, g.nx,
+                               (float)g.dx, out_pairs, out_split, nout, npairs);
+    }
+    if ((kinds & kSliceOcto) && grid_sym4(g)) {
+        const int nunit = sym8_units(g.nx) * npairs;   // work units of all pairs
+        dim3 grid(sym_bp_grid(nunit));
+        if (sino_bf16)
+            hipLaunchKernelGGL(k_backproject_sym8<true>, grid, dim3(kB8Waves * 64), 0, st, sino, t, g.nx,
+                               (float)g.dx, out_pairs, out_split, nout, npairs);
+        else
+            hipLaunchKernelGGL(k_backproject_sym8<false>, grid, dim3(kB8Waves * 64), 0, st, sino, t, g.nx,
                                (float)g.dx, out_pairs, out_split, nout, npairs);
     }
 }
