@@ -500,9 +500,9 @@ def main():
             "backproject_algorithmic_hbm_gbs": bp_bytes / bp_avg_s / 1e9,
             "project_algorithmic_hbm_gbs": fp_bytes / fp_avg_s / 1e9,
         },
-        "roofline": {"kernel": "k_backproject_sym", "bound": "alu", "achieved": achieved,
+        "roofline": {"kernel": "k_backproject_sym8", "bound": "alu", "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": measured_traffic("k_backproject_sym") if storage == 0 else None},
+                     "traffic": measured_traffic("k_backproject_sym8") if storage == 0 else None},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, pL, pH, args.cpu_iters)

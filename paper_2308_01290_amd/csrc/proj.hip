@@ -977,6 +977,10 @@ __global__ __launch_bounds__(kBsWaves * 64) void k_backproject_sym(
 // ---------------------------------------------------------------------------
 constexpr int kB8Waves = 16;
 
+__device__ __forceinline__ float uniform_f(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+
 // work units of one slice: 8-tile orbits, then pairs of 4-tile orbits
 __host__ __device__ inline int sym8_units(int n) {
     const int nq = n / 32;
@@ -1020,7 +1024,10 @@ __global__ __launch_bounds__(kB8Waves * 64) void k_backproject_sym8(
         pa[1] = pb[1] = d0 + 1;
     }
     const int nd = D.nd, q4 = D.nv >> 2, vmax = q4 >> 1;
-    const float sid = D.sid, sdd = D.sdd, u0 = D.u0, inv_pitch = D.inv_pitch;
+    // slice constants in scalar registers (uniform; as vector registers they
+    // would be spilled across the view loop)
+    const float sid = uniform_f(D.sid), sdd = uniform_f(D.sdd), u0 = uniform_f(D.u0),
+                inv_pitch = uniform_f(D.inv_pitch);
     const int4* __restrict__ fix = T.fix + D.ray0;
     const float2* __restrict__ flt = T.flt + D.ray0;
     const float4* __restrict__ view = T.view + D.view0;
