@@ -320,6 +320,7 @@ struct Carver {
 
 struct PcgBufs {
     float *r, *z, *p0, *p1, *q, *w2;
+    float *r2, *p1b;    // pipelined PCG: second r and s buffers
     double* parts;
     PcgState* st;
     PcgParts L;
@@ -336,6 +337,8 @@ static void carve_pcg(Carver& c, int ny, int nx, int batch, PcgBufs* b) {
     b->p1 = c.take<float>(n);
     b->q = c.take<float>(n);
     b->w2 = c.take<float>(n);
+    b->r2 = c.take<float>(n);
+    b->p1b = c.take<float>(n);
     b->parts = c.take<double>((size_t)batch * b->L.zstride);
     b->st = c.take<PcgState>((size_t)batch);
     b->mg_plan = mg_plan(ny, nx);
@@ -353,6 +356,8 @@ static void fill_pcg_args(PcgArgs* a, const PcgBufs& b, int ny, int nx, int batc
     a->p1 = b.p1;
     a->q = b.q;
     a->w2 = b.w2;
+    a->r2 = b.r2;
+    a->p1b = b.p1b;
     a->parts = b.parts;
     a->L = b.L;
     a->st = b.st;
@@ -406,8 +411,7 @@ static void pcg_chunk(PcgRun& R, const PcgBufs& b, float2* fft_scratch, hipStrea
     PcgArgs& a = R.a;
     for (int c = 0; c < chunk && R.it < R.max_iter; ++c, ++R.it) {
         if (R.piped) {
-            launch_pcg_cg_update(a, R.it, st);
-            launch_pcg_mg_prec_w(a, R.it + 1, b.mg_plan, b.mg, st);
+            launch_pcg_mg_prec_w_upd(a, R.it, b.mg_plan, b.mg, st);
             continue;
         }
         launch_pcg_matvec(a, R.it, st);

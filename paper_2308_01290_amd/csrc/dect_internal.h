@@ -348,6 +348,7 @@ struct PcgArgs {
     float* x;                // in: x0 (also HT input), out: solution
     const float* x0 = nullptr;   // when set: x0 (and HT input), x only written
     float *r, *z, *p0, *p1, *q, *w2;
+    float *r2 = nullptr, *p1b = nullptr;   // pipelined PCG: second r and s buffers
     double* parts;           // [batch][PcgParts::zstride]
     PcgParts L;
     PcgState* st;            // [batch]
@@ -369,8 +370,9 @@ void launch_pcg_fft_prec(const PcgArgs& a, int it, float2* scratch, hipStream_t 
 // the V-cycle's last kernel), forms beta_i = gamma_i / gamma_(i-1) and
 // alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_(i-1)), then
 // p = u + beta p, s = w + beta s, x += alpha p, r -= alpha s.  It first
-// stops the slice when ||r_i||^2 <= tol2 ||r_0||^2.  p is p0, s is p1.
-void launch_pcg_cg_update(const PcgArgs& a, int i, hipStream_t st);
+// stops the slice when ||r_i||^2 <= tol2 ||r_0||^2.  p is p0; r and s
+// alternate between (r, r2) and (p1, p1b) by parity.  The update runs inside
+// the first kernel of the next V-cycle: launch_pcg_mg_prec_w_upd below.
 
 // ---- multigrid V-cycle preconditioner for diag(c) + beta L -----------------------
 constexpr int kMgMaxLevels = 12;
@@ -394,6 +396,7 @@ struct MgPlan {
     bool pair[kMgMaxLevels] = {};    // tile levels l and l + 1 run in one kernel each way
 };
 MgPlan mg_plan(int ny, int nx);
+struct CgUpd;   // pipelined PCG update fused into a V-cycle (mg.hip)
 // once per linear solve: c pyramid from w2 and the in-LDS part's set-up data
 // (inverse diagonals, exact-level inverse) for beta (or beta_z[z] per slice)
 void launch_mg_setup(const MgPlan& P, const float* w2, float* mg, int batch, float beta,
@@ -402,11 +405,16 @@ void launch_mg_setup(const MgPlan& P, const float* w2, float* mg, int batch, flo
 void launch_mg_vcycle(const MgPlan& P, const float* r, const float* w2, float* z, float* mg,
                       int batch, float beta, const double* beta_z, const int* skip,
                       size_t skip_zstride, double* dot, size_t dot_zstride, hipStream_t st,
-                      float* wout = nullptr, double* dot2 = nullptr);
+                      float* wout = nullptr, double* dot2 = nullptr,
+                      const CgUpd* upd = nullptr);
 void launch_pcg_mg_prec(const PcgArgs& a, int it, const MgPlan& P, float* mg, hipStream_t st);
 // the V-cycle as the pipelined PCG uses it (needs mg_pipelined_ok: level 0 a
 // pair level above at least one more tile level)
 bool mg_pipelined_ok(const MgPlan& P);
 void launch_pcg_mg_prec_w(const PcgArgs& a, int i, const MgPlan& P, float* mg, hipStream_t st);
+// iteration i of the pipelined PCG in one V-cycle: the update fused into its
+// first kernel, then u, w and the partial sums of iteration i + 1; needs r2
+// and p1b
+void launch_pcg_mg_prec_w_upd(const PcgArgs& a, int i, const MgPlan& P, float* mg, hipStream_t st);
 
 }  // namespace dect

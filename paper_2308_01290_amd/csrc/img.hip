@@ -615,91 +615,6 @@ void launch_pcg_update(const PcgArgs& a, int it, hipStream_t st) {
     hipLaunchKernelGGL(k_pcg_update, dim3(a.L.nblk, a.batch), dim3(256), 0, st, a, it);
 }
 
-// Pipelined PCG, iteration i (see launch_pcg_cg_update): u = z, w = q,
-// p = p0, s = p1.
-__global__ __launch_bounds__(256) void k_pcg_cg_update(PcgArgs a, int i) {
-    __shared__ double sh[4];
-    __shared__ double shn[16];
-    const int npix = a.nx * a.ny;
-    const int z = blockIdx.y;
-    slice_beta_thr(a, z);
-    if (a.st[z].done) return;
-    double* P = a.parts + (size_t)z * a.L.zstride;
-    const int cur = i & 1, prev = cur ^ 1;
-    const int nrz = a.nrz_used;
-    double v[4] = {0.0, 0.0, 0.0, 0.0};   // gamma_i, delta_i, ||r_i||^2, ||r_0||^2
-    {
-        const double* g = P + a.L.rz + (size_t)cur * a.L.nrz;
-        const double* d = P + a.L.dl + (size_t)cur * a.L.nrz;
-        const double* rrp = P + a.L.rr + (size_t)prev * a.L.nblk;
-        const double* r0p = P + a.L.init0;
-        for (int t = threadIdx.x; t < nrz; t += 256) {
-            v[0] += g[t];
-            v[1] += d[t];
-        }
-        for (int t = threadIdx.x; t < a.L.nblk; t += 256) {
-            v[2] += rrp[t];
-            v[3] += r0p[t];
-        }
-    }
-    block_sum_n<256, 4>(v, shn);
-    const double gam = v[0], del = v[1];
-    if (v[2] <= a.tol2 * v[3]) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            a.st[z].done = 1;
-            a.st[z].iters = i;
-        }
-        return;
-    }
-    double beta = 0.0, alpha;
-    if (i == 0) {
-        alpha = del > 0.0 ? gam / del : 0.0;
-    } else {
-        const double gam_p = P[a.L.sc + 2 * prev], alpha_p = P[a.L.sc + 2 * prev + 1];
-        beta = gam_p > 0.0 ? gam / gam_p : 0.0;
-        const double den = alpha_p != 0.0 ? del - beta * gam / alpha_p : 0.0;
-        alpha = den > 0.0 ? gam / den : 0.0;
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        P[a.L.sc + 2 * cur] = gam;
-        P[a.L.sc + 2 * cur + 1] = alpha;
-    }
-    const float bf = (float)beta, af = (float)alpha;
-    const size_t zo = (size_t)z * npix;
-    float uv[kPcgPix], wv[kPcgPix], pv[kPcgPix], sv[kPcgPix], xv[kPcgPix], rv[kPcgPix];
-#pragma unroll
-    for (int q = 0; q < kPcgPix; ++q) {   // loads first (see k_pcg_matvec)
-        int p = blockIdx.x * kPcgBlock + q * 256 + threadIdx.x;
-        p = p < npix ? p : 0;
-        uv[q] = a.z[zo + p];
-        wv[q] = a.q[zo + p];
-        pv[q] = i == 0 ? 0.f : a.p0[zo + p];
-        sv[q] = i == 0 ? 0.f : a.p1[zo + p];
-        xv[q] = a.x[zo + p];
-        rv[q] = a.r[zo + p];
-    }
-    double rr = 0.0;
-#pragma unroll
-    for (int q = 0; q < kPcgPix; ++q) {
-        const int p = blockIdx.x * kPcgBlock + q * 256 + threadIdx.x;
-        if (p >= npix) continue;
-        const float pn = fmaf(bf, pv[q], uv[q]);
-        const float sn = fmaf(bf, sv[q], wv[q]);
-        a.p0[zo + p] = pn;
-        a.p1[zo + p] = sn;
-        a.x[zo + p] = fmaf(af, pn, xv[q]);
-        const float r = fmaf(-af, sn, rv[q]);
-        a.r[zo + p] = r;
-        rr += (double)r * r;
-    }
-    const double s_rr = block_sum<256>(rr, sh);
-    if (threadIdx.x == 0) P[a.L.rr + (size_t)cur * a.L.nblk + blockIdx.x] = s_rr;
-}
-
-void launch_pcg_cg_update(const PcgArgs& a, int i, hipStream_t st) {
-    hipLaunchKernelGGL(k_pcg_cg_update, dim3(a.L.nblk, a.batch), dim3(256), 0, st, a, i);
-}
-
 __global__ __launch_bounds__(256) void k_pcg_check(PcgArgs a, int n) {
     __shared__ double sh[4];
     __shared__ double bc;

@@ -299,11 +299,39 @@ struct MgPair {
     size_t zsm;        // per-slice stride of the level buffer
 };
 
+// The update of a pipelined PCG iteration, fused into the first kernel of the
+// next V-cycle (UPD): every block reduces the iteration's partial sums to
+// alpha and beta (or stops the slice when ||r_i||^2 <= tol2 ||r_0||^2), forms
+// r_(i+1) = r_i - alpha (w_i + beta s_(i-1)) on its whole region (the core and
+// the halo the sweeps need), uses it as the right-hand side, and writes
+// p = u + beta p, s, x += alpha p, r_(i+1) and the ||r_(i+1)||^2 partial for
+// its core.  r and s are double-buffered (neighbouring blocks read the old
+// ones on their halos).
+struct CgUpd {
+    const float* r_old;   // r_i
+    float* r_new;         // r_(i+1)
+    const float* s_old;   // s_(i-1) (not read at i = 0)
+    float* s_new;         // s_i
+    const float* u;       // u_i = M r_i
+    const float* w;       // w_i = A u_i
+    float* p;             // in place on the core
+    float* x;             // in place on the core
+    size_t zs;            // per-slice stride of these images
+    int it;
+    double* parts;
+    PcgParts L;
+    int nrz_used;
+    double tol2;
+    PcgState* st;
+};
+
+template <bool UPD>
 __global__ __launch_bounds__(kPairThreads) void k_mg_down2(MgPair A, const int* skip,
-                                                           size_t skip_zstride) {
+                                                           size_t skip_zstride, CgUpd U) {
     __shared__ float B0[kD0][kD0 + 1], C0[kD0][kD0 + 1], X0[2][kD0][kD0 + 1];
     __shared__ float B1[kD1][kD1 + 1], C1[kD1][kD1 + 1], X1[2][kD1][kD1 + 1];
     __shared__ float R1[kTile][kTile + 1];
+    __shared__ double shn[4 * (kPairThreads / kWave)];
     const int z = blockIdx.z;
     if (mg_skip(skip, skip_zstride, z)) return;
     constexpr int H0 = 3 * kMgNu;
@@ -312,13 +340,105 @@ __global__ __launch_bounds__(kPairThreads) void k_mg_down2(MgPair A, const int* 
     const float be0 = A.beta_z ? (float)A.beta_z[z] * A.scale : A.beta0, be1 = 0.25f * be0;
     const float* b0 = A.b0 + (size_t)z * A.zs_b0;
     const float* c0 = A.c0 + (size_t)z * A.zs_c0;
-    for (int t = threadIdx.x; t < kD0 * kD0; t += kPairThreads) {
+    // UPD: the region's r_i, w_i, s_(i-1) (and the core's u, p, x) are loaded
+    // before the partial sums are reduced, so the two latencies overlap
+    constexpr int kReg = (kD0 * kD0 + kPairThreads - 1) / kPairThreads;
+    float lr[kReg], lw[kReg], ls[kReg], lu[kReg], lp[kReg], lx[kReg];
+    if constexpr (UPD) {
+#pragma unroll
+        for (int m = 0; m < kReg; ++m) {
+            const int t = threadIdx.x + m * kPairThreads;
+            lr[m] = lw[m] = ls[m] = lu[m] = lp[m] = lx[m] = 0.f;
+            if (t >= kD0 * kD0) continue;
+            const int r = t / kD0, s = t % kD0;
+            const size_t gz = (size_t)z * U.zs +
+                              (size_t)wrap_near(i0 - H0 + r, ny0) * nx0 + wrap_near(k0 - H0 + s, nx0);
+            lr[m] = U.r_old[gz];
+            lw[m] = U.w[gz];
+            if (U.it > 0) ls[m] = U.s_old[gz];
+            if (r >= H0 && r < H0 + kCore2 && s >= H0 && s < H0 + kCore2) {
+                lu[m] = U.u[gz];
+                if (U.it > 0) lp[m] = U.p[gz];
+                lx[m] = U.x[gz];
+            }
+        }
+    }
+    float af = 0.f, bf = 0.f;
+    double* P = nullptr;
+    int cur = 0;
+    if constexpr (UPD) {
+        P = U.parts + (size_t)z * U.L.zstride;
+        cur = U.it & 1;
+        const int prev = cur ^ 1;
+        double v[4] = {0.0, 0.0, 0.0, 0.0};   // gamma_i, delta_i, ||r_i||^2, ||r_0||^2
+        const double* g = P + U.L.rz + (size_t)cur * U.L.nrz;
+        const double* d = P + U.L.dl + (size_t)cur * U.L.nrz;
+        const double* rrp = P + U.L.rr + (size_t)prev * U.L.nblk;
+        const double* r0p = P + U.L.init0;
+        for (int t = threadIdx.x; t < U.nrz_used; t += kPairThreads) {
+            v[0] += g[t];
+            v[1] += d[t];
+        }
+        for (int t = threadIdx.x; t < U.L.nblk; t += kPairThreads) {
+            v[2] += rrp[t];
+            v[3] += r0p[t];
+        }
+        block_sum_n<kPairThreads, 4>(v, shn);
+        const double gam = v[0], del = v[1];
+        if (v[2] <= U.tol2 * v[3]) {   // the same decision in every block
+            if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+                U.st[z].done = 1;
+                U.st[z].iters = U.it;
+            }
+            return;
+        }
+        double beta = 0.0, alpha;
+        if (U.it == 0) {
+            alpha = del > 0.0 ? gam / del : 0.0;
+        } else {
+            const double gam_p = P[U.L.sc + 2 * prev], alpha_p = P[U.L.sc + 2 * prev + 1];
+            beta = gam_p > 0.0 ? gam / gam_p : 0.0;
+            const double den = alpha_p != 0.0 ? del - beta * gam / alpha_p : 0.0;
+            alpha = den > 0.0 ? gam / den : 0.0;
+        }
+        if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+            P[U.L.sc + 2 * cur] = gam;
+            P[U.L.sc + 2 * cur + 1] = alpha;
+        }
+        af = (float)alpha;
+        bf = (float)beta;
+    }
+    double rr = 0.0;
+#pragma unroll
+    for (int m = 0; m < kReg; ++m) {
+        const int t = threadIdx.x + m * kPairThreads;
+        if (t >= kD0 * kD0) continue;
         const int r = t / kD0, s = t % kD0;
         const size_t g = (size_t)wrap_near(i0 - H0 + r, ny0) * nx0 + wrap_near(k0 - H0 + s, nx0);
-        const float bb = b0[g], cc = c0[g];
+        float bb;
+        if constexpr (UPD) {
+            const float sn = fmaf(bf, ls[m], lw[m]);
+            bb = fmaf(-af, sn, lr[m]);
+            if (r >= H0 && r < H0 + kCore2 && s >= H0 && s < H0 + kCore2) {
+                const size_t gz = (size_t)z * U.zs + g;
+                const float pn = fmaf(bf, lp[m], lu[m]);
+                U.p[gz] = pn;
+                U.s_new[gz] = sn;
+                U.x[gz] = fmaf(af, pn, lx[m]);
+                U.r_new[gz] = bb;
+                rr += (double)bb * bb;
+            }
+        } else {
+            bb = b0[g];
+        }
+        const float cc = c0[g];
         B0[r][s] = bb;
         C0[r][s] = cc;
         X0[0][r][s] = kOmega * bb / (cc + 4.f * be0);
+    }
+    if constexpr (UPD) {
+        const double s_rr = block_sum<kPairThreads>(rr, shn);
+        if (threadIdx.x == 0) P[U.L.rr + (size_t)cur * U.L.nblk + blockIdx.y * gridDim.x + blockIdx.x] = s_rr;
     }
     const float* c1 = A.c1 + (size_t)z * A.zsm;
     for (int t = threadIdx.x; t < kD1 * kD1; t += kPairThreads) {
@@ -814,7 +934,7 @@ void launch_mg_setup(const MgPlan& P, const float* w2, float* mg, int batch, flo
 void launch_mg_vcycle(const MgPlan& P, const float* r, const float* w2, float* z, float* mg,
                       int batch, float beta, const double* beta_z, const int* skip,
                       size_t skip_zstride, double* dot, size_t dot_zstride, hipStream_t st,
-                      float* wout, double* dot2) {
+                      float* wout, double* dot2, const CgUpd* upd) {
     const size_t n0 = (size_t)P.ny[0] * P.nx[0];
     float bl[kMgMaxLevels], sc[kMgMaxLevels];   // level beta; level scale 4^-l
     bl[0] = beta;
@@ -866,9 +986,13 @@ void launch_mg_vcycle(const MgPlan& P, const float* r, const float* w2, float* z
         return A;
     };
     for (int l = 0; l < P.ngrid;) {
-        if (P.pair[l]) {
-            hipLaunchKernelGGL(k_mg_down2, dim3(P.nx[l] / kCore2, P.ny[l] / kCore2, batch),
-                               dim3(kPairThreads), 0, st, pair(l), skip, skip_zstride);
+        if (P.pair[l] && l == 0 && upd) {
+            hipLaunchKernelGGL(k_mg_down2<true>, dim3(P.nx[l] / kCore2, P.ny[l] / kCore2, batch),
+                               dim3(kPairThreads), 0, st, pair(l), skip, skip_zstride, *upd);
+            l += 2;
+        } else if (P.pair[l]) {
+            hipLaunchKernelGGL(k_mg_down2<false>, dim3(P.nx[l] / kCore2, P.ny[l] / kCore2, batch),
+                               dim3(kPairThreads), 0, st, pair(l), skip, skip_zstride, CgUpd{});
             l += 2;
         } else {
             MgLevel L = level(l);
@@ -936,7 +1060,38 @@ void launch_pcg_mg_prec(const PcgArgs& a, int it, const MgPlan& P, float* mg, hi
                      a.L.zstride, st, nullptr, nullptr);
 }
 
-bool mg_pipelined_ok(const MgPlan& P) { return P.ok && P.ngrid >= 2 && P.pair[0]; }
+bool mg_pipelined_ok(const MgPlan& P) {
+    // (the fused update writes one ||r||^2 partial per 32 x 32 core, as many as
+    // the PCG's pixel kernels write per 1024 pixels)
+    return P.ok && P.ngrid >= 2 && P.pair[0];
+}
+
+void launch_pcg_mg_prec_w_upd(const PcgArgs& a, int i, const MgPlan& P, float* mg, hipStream_t st) {
+    // iteration i's update fused into the V-cycle of r_(i+1): r and s live in
+    // (r, r2) and (p1, p1b) by parity
+    float* rb[2] = {a.r, a.r2};
+    float* sb[2] = {a.p1, a.p1b};
+    CgUpd U;
+    U.r_old = rb[i & 1];
+    U.r_new = rb[(i + 1) & 1];
+    U.s_old = sb[i & 1];
+    U.s_new = sb[(i + 1) & 1];
+    U.u = a.z;
+    U.w = a.q;
+    U.p = a.p0;
+    U.x = a.x;
+    U.zs = (size_t)a.ny * a.nx;
+    U.it = i;
+    U.parts = a.parts;
+    U.L = a.L;
+    U.nrz_used = a.nrz_used;
+    U.tol2 = a.tol2;
+    U.st = a.st;
+    const int slot = (i + 1) & 1;
+    launch_mg_vcycle(P, U.r_new, a.w2, a.z, mg, a.batch, a.beta, a.beta_z, &a.st[0].done,
+                     sizeof(PcgState) / sizeof(int), a.parts + a.L.rz + (size_t)slot * a.L.nrz,
+                     a.L.zstride, st, a.q, a.parts + a.L.dl + (size_t)slot * a.L.nrz, &U);
+}
 
 void launch_pcg_mg_prec_w(const PcgArgs& a, int i, const MgPlan& P, float* mg, hipStream_t st) {
     // u_i = V(r_i) into z, w_i = A u_i into q; gamma_i = <r_i, u_i> and
