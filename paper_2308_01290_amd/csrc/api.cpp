@@ -1350,6 +1350,13 @@ static int one_iteration(dect_solver* s, bool more = false) {
     // ms: the t' step first (f^(k) from the previous update on `side`)
     if (two && s->upd_pending) DECT_HIP(hipStreamWaitEvent(ms, s->ev_upd, 0));
     if (int rc = t_step_start(s, ms, two ? s->ev_init : nullptr)) return rc;
+    // With the next back-projection already queued on `side` (pipelined
+    // iterations), the PCG's first chunk is enqueued first: the side stream
+    // has that much work ahead while the host enqueues the chunk, and the PCG
+    // does not wait behind the host's side enqueues
+    const bool chunk_first = two && s->bp_pending;
+    if (chunk_first)
+        if (int rc = t_step_chunk(s, ms)) return rc;
     // side: f-step and rho_e step (t'^(k), beta^(k) from the previous iteration on ms)
     if (two && s->upd_pending) DECT_HIP(hipStreamWaitEvent(side, s->ev_tdone, 0));
     if (!s->bp_pending) {
@@ -1404,7 +1411,8 @@ static int one_iteration(dect_solver* s, bool more = false) {
         s->bp_pending = true;
     }
     s->upd_pending = two;
-    if (int rc = t_step_chunk(s, ms)) return rc;
+    if (!chunk_first)
+        if (int rc = t_step_chunk(s, ms)) return rc;
     if (int rc = t_step_finish(s, ms)) return rc;
     // ms: beta^(k+1) once the side work and the rho_e step have read beta^(k)
     if (two) DECT_HIP(hipStreamWaitEvent(ms, s->ev_side, 0));
