@@ -17,10 +17,29 @@ PROJ_TOL = 1e-5
 
 
 def geoms():
-    return {"small": P.geometry_small(), "ragged": ragged_geometry()}
+    return {
+        "small": P.geometry_small(),
+        "ragged": ragged_geometry(),
+        # square grid, side a multiple of 32, views a multiple of 4: the
+        # quarter-turn symmetric projector; the detector offset and the first
+        # view away from 0 break the transpose symmetry (four-fold kernels)
+        "quarter": P.FanGeometry(n_x=64, n_y=64, pixel_mm=1.0, n_views=64, n_det=96, sid_mm=500.0,
+                                 sdd_mm=800.0, det_offset_mm=0.25, angle0_rad=0.1).resolved(),
+        # transpose-symmetric (eight-fold back-projector): three tiles of 32
+        # per side (an odd count, one work unit with a single diagonal orbit)
+        # and nv/4 = 18 even (view 9 is its own transpose)
+        "octo_odd": P.FanGeometry(n_x=96, n_y=96, pixel_mm=1.0, n_views=72, n_det=160, sid_mm=600.0,
+                                  sdd_mm=900.0).resolved(),
+        # one tile orbit, four views (nv/4 = 1: view 0 only)
+        "octo_tiny": P.FanGeometry(n_x=32, n_y=32, pixel_mm=1.0, n_views=4, n_det=48, sid_mm=300.0,
+                                   sdd_mm=450.0).resolved(),
+    }
 
 
-@pytest.mark.parametrize("name", ["small", "ragged"])
+SYM = ["quarter", "octo_odd", "octo_tiny"]
+
+
+@pytest.mark.parametrize("name", ["small", "ragged"] + SYM)
 @pytest.mark.parametrize("batch", [1, 3])
 def test_project_matches_oracle_random(name, batch):
     g = geoms()[name]
@@ -45,7 +64,7 @@ def test_project_matches_oracle_per_ray_on_phantom():
     assert np.max(np.abs(got - ref)[big] / ref[big]) <= PROJ_TOL
 
 
-@pytest.mark.parametrize("name", ["small", "ragged"])
+@pytest.mark.parametrize("name", ["small", "ragged"] + SYM)
 @pytest.mark.parametrize("batch", [1, 2, 3])
 def test_backproject_matches_oracle(name, batch):
     g = geoms()[name]
@@ -57,7 +76,7 @@ def test_backproject_matches_oracle(name, batch):
         assert rel_inf(got[b], ref[b]) <= PROJ_TOL, (name, b)
 
 
-@pytest.mark.parametrize("name", ["small", "ragged"])
+@pytest.mark.parametrize("name", ["small", "ragged"] + SYM)
 def test_adjointness_on_gpu(name):
     g = geoms()[name]
     rng = np.random.default_rng(21)
