@@ -497,6 +497,11 @@ def main():
             "project_alone_ms": 1e3 * fp_alone_s,
             "backproject_visits_per_s": 2 * nnz / bp_avg_s,
             "project_visits_per_s": 2 * nnz / fp_avg_s,
+            # effective touch bandwidth: every (pixel, ray) visit of both images
+            # counted as one 4-byte access; not HBM traffic (the images and
+            # sinograms are reread from L2 and the Infinity Cache)
+            "backproject_effective_touch_gbs": 2 * nnz * 4 / bp_avg_s / 1e9,
+            "project_effective_touch_gbs": 2 * nnz * 4 / fp_avg_s / 1e9,
             "backproject_algorithmic_hbm_gbs": bp_bytes / bp_avg_s / 1e9,
             "project_algorithmic_hbm_gbs": fp_bytes / fp_avg_s / 1e9,
         },
