@@ -1254,6 +1254,10 @@ static int one_iteration_image(dect_solver* s, bool more) {
     const hipStream_t side = two ? s->side : s->st;
     if (two && s->upd_pending) DECT_HIP(hipStreamWaitEvent(ms, s->ev_upd, 0));     // f^(k)
     if (int rc = t_step_start(s, ms, nullptr)) return rc;
+    // the t' PCG is this form's critical path: its first chunk is enqueued
+    // before the side stream's f-step
+    if (two)
+        if (int rc = t_step_chunk(s, ms)) return rc;
     if (two && s->upd_pending) DECT_HIP(hipStreamWaitEvent(side, s->ev_tdone, 0));  // t'^(k), beta^(k)
     float2* scratch = two ? s->fft2 : s->fft;
     hipEvent_t t0 = mark(s, side);
@@ -1295,7 +1299,8 @@ static int one_iteration_image(dect_solver* s, bool more) {
     mark_end(s, side, t0, s->ev_bp);
     rho_step(s, side, scratch);
     if (two) DECT_HIP(hipEventRecord(s->ev_upd, side));
-    if (int rc = t_step_chunk(s, ms)) return rc;
+    if (!two)
+        if (int rc = t_step_chunk(s, ms)) return rc;
     if (int rc = t_step_finish(s, ms)) return rc;
     if (two) DECT_HIP(hipStreamWaitEvent(ms, s->ev_upd, 0));   // side done with beta^(k), t'^(k)
     std::swap(s->f, s->B);
