@@ -167,7 +167,14 @@ int dect_attenuation(const dect_params* p, const double* Z, const double* rho_e,
  * times the ray's chord length through each pixel square (exact, Siddon-type
  * traversal, FP32 with compensated ray sums).  img [batch][n_y][n_x] ->
  * sino [batch][n_views][n_det].  Needs a device-side table the library keeps
- * per geometry (allocated on first use). */
+ * per geometry (allocated on first use).  A square image (n_x = n_y, a
+ * multiple of 32) with a full turn of views (arc 2*pi, n_views a multiple of
+ * 4) is closed under quarter turns of the scanner: the table then holds a
+ * quarter of the views and each ray's traversal serves four rays; with
+ * angle0 = 0 and det_offset = 0 the image diagonal is a further mirror and
+ * the back-projector evaluates each chord once for eight rays.  The chord
+ * lengths are those of the same rays, so results agree with the general
+ * traversal within FP32 rounding. */
 int dect_project(const dect_geometry* g, const float* img, float* sino, int32_t batch,
                  hipStream_t stream);
 
