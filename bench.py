@@ -121,6 +121,18 @@ def _uneven_slice(i):
     return g, pL.astype(np.float32), pH.astype(np.float32)
 
 
+def tune(args, sol, lo, hi, default_mode):
+    """Autotune `sol` on its inputs when asked; returns (schedule, seconds)."""
+    if (args.schedule or default_mode) != "autotune":
+        return sol.schedule(), 0.0
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    chosen, _ = sol.autotune(lo, hi, iters=4, reps=3)
+    torch.cuda.synchronize()
+    return chosen, time.perf_counter() - t0
+
+
 def bench_uneven(args):
     """64 uneven slices, 50 iterations each: batched by image size against one
     slice at a time; a step solves all 64 slices."""
@@ -146,6 +158,12 @@ def bench_uneven(args):
     for g, pL, pH in data:
         single.append((dect.Solver(g, params), torch.as_tensor(pL[None], device=dev),
                        torch.as_tensor(pH[None], device=dev)))
+
+    schedules, t_tune = [], 0.0
+    for sol, lo, hi in batched:
+        sc, dt = tune(args, sol, lo, hi, "autotune")
+        schedules.append(sc)
+        t_tune += dt
 
     def run(solvers):
         out = []
@@ -185,6 +203,8 @@ def bench_uneven(args):
         "one_slice_at_a_time": {"value": n_slices / t_s, "unit": "slices/s", "ms_per_step": 1e3 * t_s},
         "speedup": t_s / t_b,
         "results_identical_to_one_at_a_time": same,
+        "schedule": {"mode": args.schedule or "autotune", "per_group": schedules,
+                     "autotune_s": t_tune},
     }
     print(json.dumps(out), flush=True)
 
@@ -282,6 +302,7 @@ def bench_image(args):
     lo = torch.as_tensor(L[None].astype(np.float32), device=dev)
     hi = torch.as_tensor(H[None].astype(np.float32), device=dev)
     sol = dect.ImageSolver(g.n_x, g.n_y, params)
+    schedule, t_tune = tune(args, sol, lo, hi, "default")
     Z = torch.empty((1, g.n_y, g.n_x), device=dev)
     R = torch.empty_like(Z)
 
@@ -331,6 +352,7 @@ def bench_image(args):
         "roofline": {"kernel": "f-step (k_fft_rows_fwd + k_fft_cols + k_fft_rows_inv, both bases)",
                      "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": None},
+        "schedule": {"mode": args.schedule or "default", "chosen": schedule, "autotune_s": t_tune},
     }
     if not args.no_cpu_baseline:
         from oracle import image as I
@@ -366,6 +388,10 @@ def main():
     ap.add_argument("--storage", choices=["fp32", "bf16", "bf16_state"], default="fp32",
                     help="slice512: storage of the projector operands (bf16) and also of the "
                          "state images (bf16_state)")
+    ap.add_argument("--schedule", choices=["default", "autotune"], default=None,
+                    help="launch schedule of the timed solvers: the library default, or the one "
+                         "the library's autotuner picks on the workload before the warmup "
+                         "(default: autotune for uneven64, default otherwise)")
     ap.add_argument("--rates", default="20,50,100,200", help="serve: arrival rates (req/s)")
     ap.add_argument("--requests", type=int, default=96, help="serve: requests per rate")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -410,6 +436,7 @@ def main():
     lo = torch.as_tensor(pL[None], device=dev)
     hi = torch.as_tensor(pH[None], device=dev)
     sol = dect.Solver(g, params, batch=1)
+    schedule, t_tune = tune(args, sol, lo, hi, "default")
     Z = torch.empty((1, g.n_y, g.n_x), device=dev)
     R = torch.empty_like(Z)
 
@@ -508,6 +535,7 @@ def main():
         "roofline": {"kernel": "k_backproject_sym8", "bound": "alu", "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": measured_traffic("k_backproject_sym8") if storage == 0 else None},
+        "schedule": {"mode": args.schedule or "default", "chosen": schedule, "autotune_s": t_tune},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, pL, pH, args.cpu_iters)

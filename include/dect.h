@@ -269,6 +269,68 @@ int dect_solver_finish(dect_solver* s, float* Z, float* rho_e);
  * t' step (HOST query; synchronises the solver's stream). */
 int dect_solver_stats(const dect_solver* s, int32_t* k, int32_t* last_pcg_iters);
 
+/* Launch schedule of a solver's outer iterations.  Every choice changes only
+ * how the work is mapped onto the device, never an operation or its
+ * summation order, so results are bit-identical under every schedule.
+ *   fp_rays_per_lane  forward projection of square quarter-turn symmetric
+ *                     slices: 4 = each lane steps one table ray and sums its
+ *                     four turned rays; 1 = one ray per lane (the kernel of
+ *                     the general case).  Batches with a slice of neither
+ *                     symmetry always use 1.
+ *   bp_cu_percent     workgroups of the symmetric back-projectors as a
+ *                     percentage of the CUs (0 = automatic: half the CUs up
+ *                     to one tile orbit per CU, all CUs beyond; else 10..400)
+ *   rho_stream        1 = the rho_e step of the sinogram form on a stream of
+ *                     its own, 0 = on the f-step's stream
+ *   graphs            1 = the t' PCG's first chunk per outer iteration
+ *                     replayed from a HIP graph (see dect_solver_set_graphs)
+ *   pcg_chunk_extra   PCG iterations enqueued in the first chunk beyond the
+ *                     previous outer iteration's count (0..8); the device
+ *                     stopping test makes extra iterations free of effect
+ * A new solver starts with {4, 0, 1, 0, 0}. */
+typedef struct dect_schedule {
+    int32_t fp_rays_per_lane;
+    int32_t bp_cu_percent;
+    int32_t rho_stream;
+    int32_t graphs;
+    int32_t pcg_chunk_extra;
+} dect_schedule;
+
+/* Read or replace the schedule (DECT_EINVAL for a NULL argument or a value
+ * outside the ranges above; set takes effect at the next iterate call). */
+int dect_solver_get_schedule(const dect_solver* s, dect_schedule* out);
+int dect_solver_set_schedule(dect_solver* s, const dect_schedule* in);
+
+/* Autotuner: times `iters` outer iterations from dect_solver_init (or
+ * dect_image_solver_init for an image-domain solver) on the given inputs,
+ * `reps` times per candidate schedule (median), over the knobs above one at
+ * a time (coordinate descent from the current schedule; a change is kept
+ * when it is at least 2% faster), and leaves the fastest schedule set.
+ * Timing is by HIP events on the solver's stream around each trial's
+ * iterations.  sino_lo/sino_hi: DEVICE pointers as for dect_solver_init (the
+ * attenuation images for an image-domain solver).  chosen and ms_per_iter
+ * (the chosen schedule's median time per outer iteration) may be NULL.  The
+ * solver's iterate is left at the last trial's: call dect_solver_init (or
+ * set_state) before solving.  iters in 1..100, reps in 1..20. */
+int dect_solver_autotune(dect_solver* s, const float* sino_lo, const float* sino_hi,
+                         int32_t iters, int32_t reps, dect_schedule* chosen,
+                         double* ms_per_iter);
+
+/* Graph replay of the t' PCG's launch-bound inner loop: with enable != 0,
+ * the first chunk of PCG iterations of every outer iteration (the multigrid
+ * V-cycles with the fused update, about five small kernels per PCG
+ * iteration) is captured once per chunk length and pair of t' buffers as a
+ * HIP graph and replayed with one hipGraphLaunch.  Applies when the
+ * multigrid PCG is in use and the solver has its own streams (a caller
+ * stream that is the legacy NULL stream still gets them); otherwise the
+ * iterations are launched one by one as before.  The replayed launches are
+ * those of the eager path, so results are bit-identical.  The solver keeps at
+ * most 16 instantiated graphs (dropped, after a stream synchronisation, when
+ * the cache is full, when graphs are disabled, and by dect_solver_destroy).
+ * Same as setting dect_schedule.graphs.  Returns DECT_EINVAL for a NULL
+ * solver. */
+int dect_solver_set_graphs(dect_solver* s, int enable);
+
 /* Optional timing of the two system-matrix kernels: when enabled, the solver
  * records HIP events on its stream around every back-projection and forward
  * projection launch of the outer iterations.  dect_solver_timing synchronises

@@ -607,11 +607,24 @@ struct dect_solver {
     int k;
     double beta;
     int last_pcg;
+    // the t' PCG's first chunk of each outer iteration as one graph launch
+    // (dect_solver_set_graphs): instantiated graphs by chunk length and the
+    // solution / start buffers they were captured with
+    struct ChunkGraph {
+        int chunk;
+        const float* x;
+        const float* x0;
+        hipGraphExec_t exec;
+    };
+    std::vector<ChunkGraph> chunk_graphs;
+    dect_schedule sched{4, 0, 1, 0, 0};   // launch schedule (dect_solver_set_schedule)
     // optional kernel timing: event pairs in launch order
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_bp, ev_fp;
 };
+
+static void drop_chunk_graphs(dect_solver* s);
 
 static hipEvent_t take_event(dect_solver* s) {
     hipEvent_t e = nullptr;
@@ -1100,6 +1113,7 @@ int dect_solver_destroy(dect_solver* s) {
         (void)hipEventDestroy(p.second);
     }
     for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
+    drop_chunk_graphs(s);
     free_side(s);
     if (s->owns_ws) dev_free(&s->own);
     delete s;
@@ -1226,10 +1240,66 @@ static int t_step_start(dect_solver* s, hipStream_t ms, hipEvent_t after_init) {
     return DECT_OK;
 }
 
+constexpr size_t kMaxChunkGraphs = 16;
+
+static void drop_chunk_graphs(dect_solver* s) {
+    if (s->chunk_graphs.empty()) return;
+    (void)hipStreamSynchronize(s->pst ? s->pst : s->st);   // no replay in flight
+    for (auto& c : s->chunk_graphs) (void)hipGraphExecDestroy(c.exec);
+    s->chunk_graphs.clear();
+}
+
+// The first chunk replayed from a graph.  Within one solver the chunk's
+// kernels take the same arguments in every outer iteration except the t'
+// buffers (solution and start alternate between two) and the chunk length:
+// beta reaches every kernel through the per-slice device array, and the
+// stopping test runs on the device (kernels of a finished slice return at
+// once).  So one graph per (length, buffers), captured from the eager
+// launch sequence, replays exactly the launches that sequence makes.
+static int pcg_chunk_graph(dect_solver* s, hipStream_t ms) {
+    PcgRun& R = s->prun;
+    PcgArgs& a = R.a;
+    if (s->hs_pinned) {
+        R.hs = s->hs_pinned;
+    } else {
+        R.own.resize(a.batch);
+        R.hs = R.own.data();
+    }
+    const int it0 = R.it;
+    const int chunk = std::min(std::max(2, s->last_pcg + s->sched.pcg_chunk_extra), R.max_iter - it0);
+    hipGraphExec_t ex = nullptr;
+    for (const auto& c : s->chunk_graphs)
+        if (c.chunk == chunk && c.x == a.x && c.x0 == a.x0) ex = c.exec;
+    if (!ex) {
+        if (s->chunk_graphs.size() >= kMaxChunkGraphs) drop_chunk_graphs(s);
+        DECT_HIP(hipStreamBeginCapture(ms, hipStreamCaptureModeThreadLocal));
+        pcg_chunk(R, s->pcg, s->fft, ms, chunk);
+        hipGraph_t gr = nullptr;
+        const hipError_t e = hipStreamEndCapture(ms, &gr);
+        R.it = it0;   // captured, not run
+        if (e != hipSuccess)
+            return fail(DECT_EDEVICE, "PCG chunk capture failed: %s", hipGetErrorString(e));
+        const hipError_t e2 = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        if (e2 != hipSuccess)
+            return fail(DECT_EDEVICE, "PCG chunk graph instantiation failed: %s", hipGetErrorString(e2));
+        s->chunk_graphs.push_back({chunk, a.x, a.x0, ex});
+    }
+    DECT_HIP(hipGraphLaunch(ex, ms));
+    R.it = it0 + chunk;
+    DECT_HIP(hipMemcpyAsync(R.hs, a.st, sizeof(PcgState) * a.batch, hipMemcpyDeviceToHost, ms));
+    return DECT_OK;
+}
+
 // the first chunk of PCG iterations (after t_step_start; the host enqueues the
 // other stream's work in between so that it is not queued behind this chunk)
 static int t_step_chunk(dect_solver* s, hipStream_t ms) {
-    return pcg_first_chunk(s->prun, s->pcg, s->fft, ms, s->last_pcg, s->hs_pinned);
+    // graphs for the pipelined multigrid PCG (its whole chunk is kernels), on
+    // a stream of the solver's own (the legacy null stream cannot capture)
+    if (s->sched.graphs && s->prun.piped && ms == s->pst && ms && s->prun.max_iter > s->prun.it)
+        return pcg_chunk_graph(s, ms);
+    return pcg_first_chunk(s->prun, s->pcg, s->fft, ms, s->last_pcg + s->sched.pcg_chunk_extra,
+                           s->hs_pinned);
 }
 
 // second half: wait for the stopping flags, more chunks while needed
@@ -1366,12 +1436,13 @@ static int one_iteration(dect_solver* s, bool more = false) {
     if (two && s->upd_pending) DECT_HIP(hipStreamWaitEvent(side, s->ev_tdone, 0));
     if (!s->bp_pending) {
         hipEvent_t t0 = mark(s, side);
-        launch_backproject(g, s->tab, s->S, s->batch, s->B, nullptr, 0, side, a.bf16, s->geo.kinds);
+        launch_backproject(g, s->tab, s->S, s->batch, s->B, nullptr, 0, side, a.bf16, s->geo.kinds,
+                           s->sched.bp_cu_percent);
         mark_end(s, side, t0, s->ev_bp);
     }
     launch_grad(s->M, a, P, s->f, s->B, s->rho, s->t, dir, s->part_img, side);
     // rho_e step on its own stream once the gradient has read rho^(k)
-    const hipStream_t rs = two && s->rst ? s->rst : nullptr;
+    const hipStream_t rs = two && s->rst && s->sched.rho_stream ? s->rst : nullptr;
     if (rs) {
         DECT_HIP(hipEventRecord(s->ev_grad, side));
         DECT_HIP(hipStreamWaitEvent(rs, s->ev_grad, 0));
@@ -1394,7 +1465,7 @@ static int one_iteration(dect_solver* s, bool more = false) {
     pa.alpha = s->alpha;
     pa.counter = s->cnt_proj;
     pa.pad_bf16 = pa.res_bf16 = a.bf16;
-    pa.sym_all = !(s->geo.kinds & kSlicePlain);
+    pa.sym_all = !(s->geo.kinds & kSlicePlain) && s->sched.fp_rays_per_lane == 4;
     hipEvent_t t1 = mark(s, side);
     launch_project(g, P, s->tab, dir, s->batch, PROJ_LINESEARCH, pa, side);
     mark_end(s, side, t1, s->ev_fp);
@@ -1411,7 +1482,8 @@ static int one_iteration(dect_solver* s, bool more = false) {
     s->bp_pending = false;
     if (two && more) {   // next back-projection while the host waits for the PCG
         hipEvent_t t2 = mark(s, side);
-        launch_backproject(g, s->tab, s->S, s->batch, s->B, nullptr, 0, side, a.bf16, s->geo.kinds);
+        launch_backproject(g, s->tab, s->S, s->batch, s->B, nullptr, 0, side, a.bf16, s->geo.kinds,
+                           s->sched.bp_cu_percent);
         mark_end(s, side, t2, s->ev_bp);
         s->bp_pending = true;
     }
@@ -1476,6 +1548,116 @@ int dect_solver_stats(const dect_solver* s, int32_t* k, int32_t* last_pcg_iters)
     DECT_HIP(hipStreamSynchronize(s->st));
     if (k) *k = s->k;
     if (last_pcg_iters) *last_pcg_iters = s->last_pcg;
+    return DECT_OK;
+}
+
+int dect_solver_set_graphs(dect_solver* s, int enable) {
+    if (!s) return fail(DECT_EINVAL, "solver is NULL");
+    if (s->in_pipe) return fail(DECT_EINVAL, "dect_solver_set_graphs: iterations in flight");
+    if (!enable) drop_chunk_graphs(s);
+    s->sched.graphs = enable != 0;
+    return DECT_OK;
+}
+
+static bool schedule_ok(const dect_schedule& c) {
+    return (c.fp_rays_per_lane == 1 || c.fp_rays_per_lane == 4) &&
+           (c.bp_cu_percent == 0 || (c.bp_cu_percent >= 10 && c.bp_cu_percent <= 400)) &&
+           (c.rho_stream == 0 || c.rho_stream == 1) && (c.graphs == 0 || c.graphs == 1) &&
+           c.pcg_chunk_extra >= 0 && c.pcg_chunk_extra <= 8;
+}
+
+int dect_solver_get_schedule(const dect_solver* s, dect_schedule* out) {
+    if (!s || !out) return fail(DECT_EINVAL, "dect_solver_get_schedule: NULL argument");
+    *out = s->sched;
+    return DECT_OK;
+}
+
+int dect_solver_set_schedule(dect_solver* s, const dect_schedule* in) {
+    if (!s || !in) return fail(DECT_EINVAL, "dect_solver_set_schedule: NULL argument");
+    if (!schedule_ok(*in)) return fail(DECT_EINVAL, "dect_solver_set_schedule: value out of range");
+    if (s->in_pipe) return fail(DECT_EINVAL, "dect_solver_set_schedule: iterations in flight");
+    if (!in->graphs) drop_chunk_graphs(s);
+    s->sched = *in;
+    return DECT_OK;
+}
+
+// one autotuner trial: init, then `iters` outer iterations timed on the
+// solver's stream
+static int tune_trial(dect_solver* s, const float* lo, const float* hi, int iters, hipEvent_t e0,
+                      hipEvent_t e1, float* ms) {
+    int rc = s->image ? dect_image_solver_init(s, lo, hi) : dect_solver_init(s, lo, hi);
+    if (rc) return rc;
+    DECT_HIP(hipEventRecord(e0, s->st));
+    if ((rc = dect_solver_iterate(s, iters))) return rc;
+    DECT_HIP(hipEventRecord(e1, s->st));
+    DECT_HIP(hipEventSynchronize(e1));
+    DECT_HIP(hipEventElapsedTime(ms, e0, e1));
+    return DECT_OK;
+}
+
+int dect_solver_autotune(dect_solver* s, const float* lo, const float* hi, int32_t iters,
+                         int32_t reps, dect_schedule* chosen, double* ms_per_iter) {
+    if (!s || !lo || !hi) return fail(DECT_EINVAL, "dect_solver_autotune: NULL argument");
+    if (iters < 1 || iters > 100 || reps < 1 || reps > 20)
+        return fail(DECT_EINVAL, "dect_solver_autotune: iters must be in 1..100, reps in 1..20");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    DECT_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(DECT_EDEVICE, "dect_solver_autotune: hipEventCreate failed");
+    }
+    const dect_schedule start = s->sched;
+    // median time per iteration of schedule c, after one untimed trial
+    // (ray tables, graph capture)
+    auto measure = [&](const dect_schedule& c, double* out) -> int {
+        s->sched = c;
+        if (!c.graphs) drop_chunk_graphs(s);
+        std::vector<float> t((size_t)reps + 1);
+        for (int r = 0; r <= reps; ++r)
+            if (int rc = tune_trial(s, lo, hi, iters, e0, e1, &t[(size_t)r])) return rc;
+        std::sort(t.begin() + 1, t.end());
+        *out = (double)t[1 + (size_t)reps / 2] / iters;
+        return DECT_OK;
+    };
+    // the knobs that matter for this solver
+    std::vector<std::pair<int32_t dect_schedule::*, std::vector<int32_t>>> knobs;
+    if (!s->image) {
+        if (!(s->geo.kinds & kSlicePlain)) knobs.push_back({&dect_schedule::fp_rays_per_lane, {4, 1}});
+        if (s->geo.kinds & (kSliceQuarter | kSliceOcto))
+            knobs.push_back({&dect_schedule::bp_cu_percent, {0, 25, 50, 75, 100}});
+        if (s->rst) knobs.push_back({&dect_schedule::rho_stream, {1, 0}});
+    }
+    knobs.push_back({&dect_schedule::graphs, {0, 1}});
+    knobs.push_back({&dect_schedule::pcg_chunk_extra, {0, 1, 2}});
+    dect_schedule best = start;
+    double tbest = 0.0;
+    int rc = measure(best, &tbest);
+    for (size_t k = 0; rc == DECT_OK && k < knobs.size(); ++k) {
+        const auto field = knobs[k].first;
+        const int32_t base = best.*field;
+        for (int32_t v : knobs[k].second) {
+            if (v == base) continue;
+            dect_schedule c = best;
+            c.*field = v;
+            double t = 0.0;
+            if ((rc = measure(c, &t))) break;
+            if (t < 0.98 * tbest) {
+                best = c;
+                tbest = t;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) {
+        s->sched = start;
+        drop_chunk_graphs(s);
+        return rc;
+    }
+    s->sched = best;
+    if (!best.graphs) drop_chunk_graphs(s);
+    if (chosen) *chosen = best;
+    if (ms_per_iter) *ms_per_iter = tbest;
     return DECT_OK;
 }
 

@@ -195,9 +195,11 @@ void launch_project(const Geom& g, const PadLayout& P, const RayTable& t, const 
 // [z][ny][nx] (float2) or split images.
 // kinds: the kSlice* bits of the pairs' slices (one kernel per kind present)
 // (two launches, each skipping the other kind of slice)
+// bp_pct: workgroups of the symmetric kernels as a percentage of the CUs
+// (0: half of them up to one orbit per CU, all of them beyond)
 void launch_backproject(const Geom& g, const RayTable& t, const void* sino, int npairs,
                         float2* out_pairs, float* out_split, int nout, hipStream_t st,
-                        bool sino_bf16 = false, int kinds = kSlicePlain);
+                        bool sino_bf16 = false, int kinds = kSlicePlain, int bp_pct = 0);
 
 // ---- FBP ---------------------------------------------------------------------
 // q = filtered sinograms (scratch, [nsino][nv][nd]); img [nsino][ny][nx]

@@ -1222,11 +1222,12 @@ __global__ __launch_bounds__(kB8Waves * 64) void k_backproject_sym8(
 }
 
 // Workgroups of the symmetric back-projector for `norb` orbits, spread so that
-// every block takes the same number of orbits.  Up to one orbit per CU (a
-// single slice), at most half the CUs: the latency-bound PCG kernels of the
-// concurrent stream run on the other half.  Larger batches, where every
-// stream's work is throughput-bound, take all CUs.
-static int sym_bp_grid(int norb) {
+// every block takes the same number of orbits.  By default (pct = 0): up to
+// one orbit per CU (a single slice), at most half the CUs, so that the
+// latency-bound PCG kernels of the concurrent stream run on the other half;
+// larger batches, where every stream's work is throughput-bound, take all
+// CUs.  pct > 0 caps the workgroups at pct percent of the CUs instead.
+static int sym_bp_grid(int norb, int pct) {
     static const int ncu = [] {
         int dev = 0, n = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
@@ -1236,14 +1237,14 @@ static int sym_bp_grid(int norb) {
         }
         return std::max(n, 2);
     }();
-    const int cap = norb <= ncu ? ncu / 2 : ncu;
+    const int cap = pct > 0 ? std::max(1, ncu * pct / 100) : (norb <= ncu ? ncu / 2 : ncu);
     const int rounds = (norb + cap - 1) / cap;
     return (norb + rounds - 1) / rounds;
 }
 
 void launch_backproject(const Geom& g, const RayTable& t, const void* sino, int npairs,
                         float2* out_pairs, float* out_split, int nout, hipStream_t st,
-                        bool sino_bf16, int kinds) {
+                        bool sino_bf16, int kinds, int bp_pct) {
     if (kinds & kSlicePlain) {
         dim3 grid((g.nx + 15) / 16, (g.ny + 15) / 16, npairs);
         if (sino_bf16)
@@ -1255,7 +1256,7 @@ void launch_backproject(const Geom& g, const RayTable& t, const void* sino, int 
     }
     if ((kinds & kSliceQuarter) && grid_sym4(g)) {
         const int norb = (g.nx / 32) * (g.nx / 32) * npairs;   // tile orbits of all pairs
-        dim3 grid(sym_bp_grid(norb));
+        dim3 grid(sym_bp_grid(norb, bp_pct));
         if (sino_bf16)
             hipLaunchKernelGGL(k_backproject_sym<true>, grid, dim3(kBsWaves * 64), 0, st, sino, t, g.nx,
                                (float)g.dx, out_pairs, out_split, nout, npairs);
@@ -1265,7 +1266,7 @@ void launch_backproject(const Geom& g, const RayTable& t, const void* sino, int 
     }
     if ((kinds & kSliceOcto) && grid_sym4(g)) {
         const int nunit = sym8_units(g.nx) * npairs;   // work units of all pairs
-        dim3 grid(sym_bp_grid(nunit));
+        dim3 grid(sym_bp_grid(nunit, bp_pct));
         if (sino_bf16)
             hipLaunchKernelGGL(k_backproject_sym8<true>, grid, dim3(kB8Waves * 64), 0, st, sino, t, g.nx,
                                (float)g.dx, out_pairs, out_split, nout, npairs);

@@ -41,12 +41,22 @@ class _Params(C.Structure):
                 ("t_precond", C.c_int32), ("storage", C.c_int32)]
 
 
+class _Schedule(C.Structure):
+    _fields_ = [("fp_rays_per_lane", C.c_int32), ("bp_cu_percent", C.c_int32),
+                ("rho_stream", C.c_int32), ("graphs", C.c_int32), ("pcg_chunk_extra", C.c_int32)]
+
+
+SCHEDULE_KEYS = [f[0] for f in _Schedule._fields_]
+
+
 EXPORTS = [
     "dect_default_params", "dect_resolve_geometry", "dect_attenuation", "dect_project",
     "dect_backproject", "dect_fbp", "dect_l0_step_workspace_bytes", "dect_l0_step",
     "dect_solve_workspace_bytes", "dect_solver_create", "dect_solver_destroy", "dect_solver_init",
     "dect_solver_set_state", "dect_solver_iterate", "dect_solver_get_state", "dect_solver_finish",
-    "dect_solver_stats", "dect_solver_enable_timing", "dect_solver_timing", "dect_solve",
+    "dect_solver_stats", "dect_solver_get_schedule", "dect_solver_set_schedule",
+    "dect_solver_autotune", "dect_solver_set_graphs", "dect_solver_enable_timing",
+    "dect_solver_timing", "dect_solve",
     "dect_solve_workspace_bytes_multi", "dect_solver_create_multi", "dect_solve_multi",
     "dect_engine_workspace_bytes", "dect_engine_create", "dect_engine_destroy", "dect_engine_admit",
     "dect_engine_step", "dect_engine_status", "dect_engine_completed",
@@ -92,6 +102,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.dect_solver_get_state.argtypes = [vp, vp, vp, vp, vp]
     L.dect_solver_finish.argtypes = [vp, vp, vp]
     L.dect_solver_stats.argtypes = [vp, P(C.c_int32), P(C.c_int32)]
+    L.dect_solver_get_schedule.argtypes = [vp, P(_Schedule)]
+    L.dect_solver_set_schedule.argtypes = [vp, P(_Schedule)]
+    L.dect_solver_autotune.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, P(_Schedule), P(C.c_double)]
+    L.dect_solver_set_graphs.argtypes = [vp, C.c_int]
     L.dect_solver_enable_timing.argtypes = [vp, C.c_int]
     L.dect_solver_timing.argtypes = [vp, P(C.c_double), P(C.c_int32), P(C.c_double), P(C.c_int32)]
     L.dect_solve.argtypes = [vp, vp, G, Pp, vp, vp, C.c_int32, vp, C.c_size_t, vp]
@@ -380,6 +394,9 @@ class Solver:
         return torch.empty((self.batch, self.geom.n_y, self.geom.n_x), device=self.device,
                            dtype=torch.float32)
 
+    def _check_inputs(self, lo, hi):
+        self._check_sinos(lo, hi)
+
     def init(self, sino_lo, sino_hi):
         self._check_sinos(sino_lo, sino_hi)
         _check(lib().dect_solver_init(self._h, _ptr(sino_lo), _ptr(sino_hi)), "dect_solver_init")
@@ -409,6 +426,39 @@ class Solver:
         Z, rho = self._img(), self._img()
         _check(lib().dect_solver_finish(self._h, _ptr(Z), _ptr(rho)), "dect_solver_finish")
         return Z, rho
+
+    def schedule(self):
+        """The launch schedule as a dict (see dect_schedule)."""
+        sc = _Schedule()
+        _check(lib().dect_solver_get_schedule(self._h, C.byref(sc)), "dect_solver_get_schedule")
+        return {k: int(getattr(sc, k)) for k in SCHEDULE_KEYS}
+
+    def set_schedule(self, **kw):
+        """Change schedule fields by name; results do not depend on them."""
+        cur = self.schedule()
+        for k, v in kw.items():
+            if k not in cur:
+                raise KeyError(k)
+            cur[k] = int(v)
+        sc = _Schedule(**cur)
+        _check(lib().dect_solver_set_schedule(self._h, C.byref(sc)), "dect_solver_set_schedule")
+        return self
+
+    def autotune(self, lo, hi, iters: int = 8, reps: int = 3):
+        """Time candidate schedules on these inputs, keep the fastest; returns
+        (schedule dict, ms per outer iteration).  The iterate is left at the
+        last trial's: init before solving."""
+        self._check_inputs(lo, hi)
+        sc, ms = _Schedule(), C.c_double()
+        _check(lib().dect_solver_autotune(self._h, _ptr(lo), _ptr(hi), int(iters), int(reps),
+                                          C.byref(sc), C.byref(ms)), "dect_solver_autotune")
+        return {k: int(getattr(sc, k)) for k in SCHEDULE_KEYS}, float(ms.value)
+
+    def set_graphs(self, on: bool = True):
+        """Replay each outer iteration's first chunk of PCG iterations from a
+        captured HIP graph (bit-identical to launching them one by one)."""
+        _check(lib().dect_solver_set_graphs(self._h, 1 if on else 0), "dect_solver_set_graphs")
+        return self
 
     def enable_timing(self, on: bool = True):
         _check(lib().dect_solver_enable_timing(self._h, 1 if on else 0), "dect_solver_enable_timing")
@@ -452,6 +502,9 @@ class ImageSolver(Solver):
             _dev_f32(a, (self.n_y, self.n_x), name)
             if _batch(a) != self.batch:
                 raise ValueError(f"{name} holds {_batch(a)} images, the solver {self.batch}")
+
+    def _check_inputs(self, lo, hi):
+        self._check_mu(lo, hi)
 
     def init(self, mu_lo, mu_hi):
         self._check_mu(mu_lo, mu_hi)
