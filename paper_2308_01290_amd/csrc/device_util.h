@@ -18,15 +18,26 @@ __device__ __forceinline__ float wave_sum(float v) {
     for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
     return v;
 }
+// Minimum / maximum of an int over the wavefront, returned in every lane
+// (wave-uniform).  Within each row of 16 lanes by DPP: the two quad
+// butterflies (quad_perm [1,0,3,2] and [2,3,0,1]), then the half-row and row
+// mirrors, after which every lane of a row holds the row's result; then the
+// four rows through readlane.  All 64 lanes must be active.
+template <typename Op>
+__device__ __forceinline__ int wave_reduce_i32(int v, Op op) {
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));    // quad_perm [1,0,3,2]
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));    // quad_perm [2,3,0,1]
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));   // row_half_mirror
+    v = op(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));   // row_mirror
+    const int a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
+    const int c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
+    return op(op(a, b), op(c, d));
+}
 __device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, kWave));
-    return v;
+    return wave_reduce_i32(v, [](int x, int y) { return min(x, y); });
 }
 __device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
-    return v;
+    return wave_reduce_i32(v, [](int x, int y) { return max(x, y); });
 }
 
 // Sum of `v` over a 1-D block of NT threads, fixed order; result valid in

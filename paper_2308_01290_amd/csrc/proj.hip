@@ -37,6 +37,12 @@ __device__ __forceinline__ long long fix_s(int4 f) {
 __device__ __forceinline__ float first_weight(unsigned lo, unsigned xmask, float ainv32) {
     return fminf((float)(lo ^ xmask) * ainv32, 1.0f);
 }
+// The same for a step [l, l + |s|] given by its lower end l (any direction):
+// the fraction below the next boundary, (2^32 - lo) * ainv32 with the
+// distance exact in fixed-point units, capped at 1 (s = 0: ainv32 = inf, 1).
+__device__ __forceinline__ float lower_weight(unsigned lo, float ainv32) {
+    return fminf(fmaf((float)(~lo), ainv32, ainv32), 1.0f);
+}
 
 // ---------------------------------------------------------------------------
 // ray table (FP64 geometry, FP32 storage)
@@ -355,7 +361,7 @@ __global__ __launch_bounds__(256) void k_project(const void* __restrict__ pad, P
         klo = INT_MAX;
         khi = INT_MIN;
     }
-    const int ks = wave_min(klo), ke = wave_max(khi);
+    const int ks = max(wave_min(klo), 0), ke = min(wave_max(khi), max(nx, ny) - 1);
     const int k0 = ks == INT_MAX ? 0 : ks;
     long long y = fix_a0(fx) + (long long)k0 * S;
     const int kl0 = rev_line ? nmaj - 1 - k0 : k0;   // physical line of step k0
@@ -480,7 +486,7 @@ __global__ __launch_bounds__(256) void k_project4(const void* __restrict__ pad, 
         klo = INT_MAX;
         khi = INT_MIN;
     }
-    const int ks = wave_min(klo), ke = wave_max(khi);
+    const int ks = max(wave_min(klo), 0), ke = min(wave_max(khi), n - 1);
     const int k0 = ks == INT_MAX ? 0 : ks;
     const unsigned lstep_abs = ES * (unsigned)P.ldN;   // square image: ldN == ldT
     unsigned loff[4], lstep[4];
@@ -694,7 +700,8 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_backproject(
                 jl = INT_MAX;
                 jh = INT_MIN;
             }
-            const int Jlo = wave_min(jl), Jhi = wave_max(jh);
+            // (clamped to the detector: empty stays empty)
+            const int Jlo = max(wave_min(jl), 0), Jhi = min(wave_max(jh), nd - 1);
             if (Jlo > Jhi) continue;   // wave-uniform
             const int v = v0 + vv;
             for (int base = Jlo; base <= Jhi; base += 64) {
@@ -856,7 +863,8 @@ __global__ __launch_bounds__(kBsWaves * 64) void k_backproject_sym(
                 jl = INT_MAX;
                 jh = INT_MIN;
             }
-            const int Jlo = wave_min(jl), Jhi = wave_max(jh);
+            // (clamped to the detector: empty stays empty)
+            const int Jlo = max(wave_min(jl), 0), Jhi = min(wave_max(jh), nd - 1);
             if (Jlo > Jhi) continue;   // wave-uniform
             const int v = v0 + vv;
             for (int base = Jlo; base <= Jhi; base += 64) {
@@ -991,10 +999,19 @@ template <bool SB>
 __global__ __launch_bounds__(kB8Waves * 64) void k_backproject_sym8(
     const void* __restrict__ sino, RayTable T, int n, float dxmm, float2* __restrict__ out_pairs,
     float* __restrict__ out_split, int nout, int npairs) {
+    // staged rays, one struct so that the arrays read per ray in the
+    // innermost loop sit at the lowest LDS addresses (constant offsets that
+    // fit the ds_read offset field)
+    struct Stage {
+        int4 fix[kB8Waves][64];
+        float2 fl[kB8Waves][64];        // (2^-32/|s|, +-L)
+        float4 sn[kB8Waves][64][4];     // L times the residual pairs of R^t r, then of R^t T r
+    };
+    __shared__ Stage stg;
     __shared__ float4 vs[kBpViewChunk];
-    __shared__ int4 sfix[kB8Waves][64];
-    __shared__ float2 sfl[kB8Waves][64];        // (2^-32/|s|, +-L)
-    __shared__ float4 ssn[kB8Waves][64][4];     // L times the residual pairs of R^t r, then of R^t T r
+    auto& sfix = stg.fix;
+    auto& sfl = stg.fl;
+    auto& ssn = stg.sn;
     // the tiles' sums [tile][channel][row][column], in ssn's memory once every
     // view is done
     float(*acc_t)[2][16][17] = reinterpret_cast<float(*)[2][16][17]>(&ssn[0][0][0]);
@@ -1054,7 +1071,9 @@ __global__ __launch_bounds__(kB8Waves * 64) void k_backproject_sym8(
         oy[4 * f + 3] = n - 16 - tx;
         ox[4 * f + 3] = ty;
     }
-    const int i0 = oy[d] + 2 * (lane >> 3), k0 = ox[d] + 2 * (lane & 7);
+    const int di = 2 * (lane >> 3), dk = 2 * (lane & 7);   // the lane's quad in the tile
+    const int ty = oy[d], tx = ox[d];
+    const int i0 = ty + di, k0 = tx + dk;
     const float x = ((float)k0 + 0.5f - 0.5f * (float)(n - 1)) * dxmm;
     const float y = ((float)i0 + 0.5f - 0.5f * (float)(n - 1)) * dxmm;
     // acc[t][q]: ray R^t r at pixel R^t (i0 + di, k0 + dk), q = 2 (2 di + dk) + channel;
@@ -1088,7 +1107,8 @@ __global__ __launch_bounds__(kB8Waves * 64) void k_backproject_sym8(
                 jl = INT_MAX;
                 jh = INT_MIN;
             }
-            const int Jlo = wave_min(jl), Jhi = wave_max(jh);
+            // (clamped to the detector: empty stays empty)
+            const int Jlo = max(wave_min(jl), 0), Jhi = min(wave_max(jh), nd - 1);
             if (Jlo > Jhi) continue;   // wave-uniform
             for (int base = Jlo; base <= Jhi; base += 64) {
                 const int jj = base + lane;
@@ -1100,7 +1120,16 @@ __global__ __launch_bounds__(kB8Waves * 64) void k_backproject_sym8(
 #pragma unroll
                     for (int t = 0; t < 4; ++t)
                         s4[t] = SB ? bf16x2_unpack(szb[r + t * tstep]) : sz[r + t * tstep];
-                    sfix[w][lane] = fix[r];
+                    // the ray's minor coordinate on the tile's first major
+                    // line, relative to the tile's first minor line and
+                    // moved to the lower end of the ray's minor extent over
+                    // that line's step (fixed point, exact)
+                    const int4 f4 = fix[r];
+                    const long long Sr = fix_s(f4);
+                    const bool xr = fl.y > 0.f;
+                    const long long a = fix_a0(f4) + (long long)(xr ? tx : ty) * Sr -
+                                        ((long long)(xr ? ty : tx) << 32) + (Sr < 0 ? Sr : 0);
+                    sfix[w][lane] = make_int4((int)(unsigned)a, (int)(a >> 32), f4.z, f4.w);
                     sfl[w][lane] = fl;
                     ssn[w][lane][0] = make_float4(L * s4[0].x, L * s4[0].y, L * s4[1].x, L * s4[1].y);
                     ssn[w][lane][1] = make_float4(L * s4[2].x, L * s4[2].y, L * s4[3].x, L * s4[3].y);
@@ -1119,20 +1148,27 @@ __global__ __launch_bounds__(kB8Waves * 64) void k_backproject_sym8(
                     const int4 fx = sfix[w][j - base];
                     const float2 fs = sfl[w][j - base];
                     const bool xm = fs.y > 0.f;
-                    const long long S = fix_s(fx);
-                    const bool up = S >= 0;
-                    const int maj0 = xm ? k0 : i0, mnr0 = xm ? i0 : k0;
-                    const long long ya = fix_a0(fx) + (long long)(unsigned)maj0 * S;
-                    const long long yb = ya + S;
-                    const unsigned xmask = up ? ~0u : 0u;
-                    const float wa = first_weight((unsigned)ya, xmask, fs.x);
-                    const float wb = first_weight((unsigned)yb, xmask, fs.x);
-                    const int ea = (int)(ya >> 32) - mnr0, eb = (int)(yb >> 32) - mnr0;
-                    const int o0 = up ? -1 : 1, o1 = up ? 0 : 2;
-                    const float ca0 = ea == 0 ? wa : (ea == o0 ? 1.f - wa : 0.f);
-                    const float ca1 = ea == 1 ? wa : (ea == o1 ? 1.f - wa : 0.f);
-                    const float cb0 = eb == 0 ? wb : (eb == o0 ? 1.f - wb : 0.f);
-                    const float cb1 = eb == 1 ? wb : (eb == o1 ? 1.f - wb : 0.f);
+                    // the quad's offset in the tile along the ray's major and minor axes
+                    const int dm = xm ? dk : di, dn = xm ? di : dk;
+                    // lower ends la, lb of the ray's minor extent over the
+                    // quad's two major steps: a + dm S (dm <= 14, so the high
+                    // word takes dm times S's high word, 0 or -1), then + S
+                    const unsigned long long t =
+                        (((unsigned long long)(unsigned)fx.y << 32) | (unsigned)fx.x) +
+                        (unsigned long long)(unsigned)dm * (unsigned)fx.z;
+                    const long long la =
+                        (long long)((((unsigned long long)((unsigned)(t >> 32) + (unsigned)__mul24(dm, fx.w))) << 32) |
+                                    (unsigned)t);
+                    const long long lb = la + fix_s(fx);
+                    // row floor(l) takes the part of the step below the next
+                    // boundary, the row above it the rest
+                    const float wa = lower_weight((unsigned)la, fs.x);
+                    const float wb = lower_weight((unsigned)lb, fs.x);
+                    const int ea = (int)(la >> 32) - dn, eb = (int)(lb >> 32) - dn;
+                    const float ca0 = ea == 0 ? wa : (ea == -1 ? 1.f - wa : 0.f);
+                    const float ca1 = ea == 1 ? wa : (ea == 0 ? 1.f - wa : 0.f);
+                    const float cb0 = eb == 0 ? wb : (eb == -1 ? 1.f - wb : 0.f);
+                    const float cb1 = eb == 1 ? wb : (eb == 0 ? 1.f - wb : 0.f);
                     const float c01 = xm ? cb0 : ca1, c10 = xm ? ca1 : cb0;
                     const float4 sA = ssn[w][j - base][0], sB = ssn[w][j - base][1];
                     const float sv[8] = {sA.x, sA.y, sA.z, sA.w, sB.x, sB.y, sB.z, sB.w};
