@@ -1088,10 +1088,9 @@ __global__ __launch_bounds__(kB8Waves * 64) void k_backproject_sym8(
         __syncthreads();
         for (int q = threadIdx.x; q < nvc; q += kB8Waves * 64) vs[q] = view[v0 + q];
         __syncthreads();
-        for (int vv = cls; vv < nvc; vv += ncls) {
-            const int v = v0 + vv;
-            const bool pair = v > 0 && 2 * v != q4;   // wave-uniform
-            const int vx = q4 - v;                    // table view of T r (with bins reversed)
+        // the lane's bins whose rays can reach its quad in view vv of the
+        // chunk (the circle through the quad's corners); empty: INT_MAX, INT_MIN
+        auto window = [&](int vv, int& jl, int& jh) {
             const float4 vc = vs[vv];
             const float e = 2.f * vc.z;
             const float U = sid - (x * vc.x + y * vc.y);
@@ -1101,106 +1100,152 @@ __global__ __launch_bounds__(kB8Waves * 64) void k_backproject_sym8(
             const float hi = W + e, lo = W - e;
             const float umax = sdd * hi * (hi >= 0.f ? rm : rp);
             const float umin = sdd * lo * (lo >= 0.f ? rp : rm);
-            int jl = max((int)ceilf((umin - u0) * inv_pitch - 1e-3f), 0);
-            int jh = min((int)floorf((umax - u0) * inv_pitch + 1e-3f), nd - 1);
+            jl = max((int)ceilf((umin - u0) * inv_pitch - 1e-3f), 0);
+            jh = min((int)floorf((umax - u0) * inv_pitch + 1e-3f), nd - 1);
             if (jl > jh) {
                 jl = INT_MAX;
                 jh = INT_MIN;
             }
-            // (clamped to the detector: empty stays empty)
-            const int Jlo = max(wave_min(jl), 0), Jhi = min(wave_max(jh), nd - 1);
-            if (Jlo > Jhi) continue;   // wave-uniform
-            for (int base = Jlo; base <= Jhi; base += 64) {
-                const int jj = base + lane;
-                if (jj <= Jhi) {
-                    const size_t r = (size_t)v * nd + jj;
-                    const float2 fl = flt[r];
-                    const float L = fabsf(fl.y);
-                    float2 s4[4];
+        };
+        // stage ray (v, jj) of the table in slot sl of this wavefront: its
+        // fixed-point entry made tile-relative, its step data, and L times the
+        // residual pairs of its four turns (and, for a pair view pr, of the
+        // turns of its transpose, ray (q4 - v, nd - 1 - jj))
+        auto stage = [&](int v, int jj, int sl, bool pr) {
+            const size_t r = (size_t)v * nd + jj;
+            const float2 fl = flt[r];
+            const float L = fabsf(fl.y);
+            float2 s4[4];
 #pragma unroll
-                    for (int t = 0; t < 4; ++t)
-                        s4[t] = SB ? bf16x2_unpack(szb[r + t * tstep]) : sz[r + t * tstep];
-                    // the ray's minor coordinate on the tile's first major
-                    // line, relative to the tile's first minor line and
-                    // moved to the lower end of the ray's minor extent over
-                    // that line's step (fixed point, exact)
-                    const int4 f4 = fix[r];
-                    const long long Sr = fix_s(f4);
-                    const bool xr = fl.y > 0.f;
-                    const long long a = fix_a0(f4) + (long long)(xr ? tx : ty) * Sr -
-                                        ((long long)(xr ? ty : tx) << 32) + (Sr < 0 ? Sr : 0);
-                    sfix[w][lane] = make_int4((int)(unsigned)a, (int)(a >> 32), f4.z, f4.w);
-                    sfl[w][lane] = fl;
-                    ssn[w][lane][0] = make_float4(L * s4[0].x, L * s4[0].y, L * s4[1].x, L * s4[1].y);
-                    ssn[w][lane][1] = make_float4(L * s4[2].x, L * s4[2].y, L * s4[3].x, L * s4[3].y);
-                    if (pair) {
-                        const size_t rx = (size_t)vx * nd + (nd - 1 - jj);
+            for (int t = 0; t < 4; ++t) s4[t] = SB ? bf16x2_unpack(szb[r + t * tstep]) : sz[r + t * tstep];
+            // the ray's minor coordinate on the tile's first major line,
+            // relative to the tile's first minor line and moved to the lower
+            // end of the ray's minor extent over that line's step (fixed
+            // point, exact)
+            const int4 f4 = fix[r];
+            const long long Sr = fix_s(f4);
+            const bool xr = fl.y > 0.f;
+            const long long a = fix_a0(f4) + (long long)(xr ? tx : ty) * Sr -
+                                ((long long)(xr ? ty : tx) << 32) + (Sr < 0 ? Sr : 0);
+            sfix[w][sl] = make_int4((int)(unsigned)a, (int)(a >> 32), f4.z, f4.w);
+            sfl[w][sl] = fl;
+            ssn[w][sl][0] = make_float4(L * s4[0].x, L * s4[0].y, L * s4[1].x, L * s4[1].y);
+            ssn[w][sl][1] = make_float4(L * s4[2].x, L * s4[2].y, L * s4[3].x, L * s4[3].y);
+            if (pr) {
+                const size_t rx = (size_t)(q4 - v) * nd + (nd - 1 - jj);
 #pragma unroll
-                        for (int t = 0; t < 4; ++t)
-                            s4[t] = SB ? bf16x2_unpack(szb[rx + t * tstep]) : sz[rx + t * tstep];
-                        ssn[w][lane][2] = make_float4(L * s4[0].x, L * s4[0].y, L * s4[1].x, L * s4[1].y);
-                        ssn[w][lane][3] = make_float4(L * s4[2].x, L * s4[2].y, L * s4[3].x, L * s4[3].y);
-                    }
+                for (int t = 0; t < 4; ++t)
+                    s4[t] = SB ? bf16x2_unpack(szb[rx + t * tstep]) : sz[rx + t * tstep];
+                ssn[w][sl][2] = make_float4(L * s4[0].x, L * s4[0].y, L * s4[1].x, L * s4[1].y);
+                ssn[w][sl][3] = make_float4(L * s4[2].x, L * s4[2].y, L * s4[3].x, L * s4[3].y);
+            }
+        };
+        // the lane's chords of bins ja..jb, staged from slot s0 for bin j0
+        auto chords = [&](int ja, int jb, int s0, int j0, bool pr) {
+            for (int j = ja; j <= jb; ++j) {
+                const int4 fx = sfix[w][s0 + j - j0];
+                const float2 fs = sfl[w][s0 + j - j0];
+                const bool xm = fs.y > 0.f;
+                // the quad's offset in the tile along the ray's major and minor axes
+                const int dm = xm ? dk : di, dn = xm ? di : dk;
+                // lower ends la, lb of the ray's minor extent over the
+                // quad's two major steps: a + dm S (dm <= 14, so the high
+                // word takes dm times S's high word, 0 or -1), then + S
+                const unsigned long long t =
+                    (((unsigned long long)(unsigned)fx.y << 32) | (unsigned)fx.x) +
+                    (unsigned long long)(unsigned)dm * (unsigned)fx.z;
+                const long long la =
+                    (long long)((((unsigned long long)((unsigned)(t >> 32) + (unsigned)__mul24(dm, fx.w))) << 32) |
+                                (unsigned)t);
+                const long long lb = la + fix_s(fx);
+                // row floor(l) takes the part of the step below the next
+                // boundary, the row above it the rest
+                const float wa = lower_weight((unsigned)la, fs.x);
+                const float wb = lower_weight((unsigned)lb, fs.x);
+                const int ea = (int)(la >> 32) - dn, eb = (int)(lb >> 32) - dn;
+                const float ca0 = ea == 0 ? wa : (ea == -1 ? 1.f - wa : 0.f);
+                const float ca1 = ea == 1 ? wa : (ea == 0 ? 1.f - wa : 0.f);
+                const float cb0 = eb == 0 ? wb : (eb == -1 ? 1.f - wb : 0.f);
+                const float cb1 = eb == 1 ? wb : (eb == 0 ? 1.f - wb : 0.f);
+                const float c01 = xm ? cb0 : ca1, c10 = xm ? ca1 : cb0;
+                const float4 sA = ssn[w][s0 + j - j0][0], sB = ssn[w][s0 + j - j0][1];
+                const float sv[8] = {sA.x, sA.y, sA.z, sA.w, sB.x, sB.y, sB.z, sB.w};
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const float s1 = sv[2 * t], s2 = sv[2 * t + 1];
+                    acc[t][0] = fmaf(ca0, s1, acc[t][0]);
+                    acc[t][1] = fmaf(ca0, s2, acc[t][1]);
+                    acc[t][2] = fmaf(c01, s1, acc[t][2]);
+                    acc[t][3] = fmaf(c01, s2, acc[t][3]);
+                    acc[t][4] = fmaf(c10, s1, acc[t][4]);
+                    acc[t][5] = fmaf(c10, s2, acc[t][5]);
+                    acc[t][6] = fmaf(cb1, s1, acc[t][6]);
+                    acc[t][7] = fmaf(cb1, s2, acc[t][7]);
                 }
-                __builtin_amdgcn_wave_barrier();
-                const int ja = max(jl, base), jb = min(jh, base + 63);
-                for (int j = ja; j <= jb; ++j) {
-                    const int4 fx = sfix[w][j - base];
-                    const float2 fs = sfl[w][j - base];
-                    const bool xm = fs.y > 0.f;
-                    // the quad's offset in the tile along the ray's major and minor axes
-                    const int dm = xm ? dk : di, dn = xm ? di : dk;
-                    // lower ends la, lb of the ray's minor extent over the
-                    // quad's two major steps: a + dm S (dm <= 14, so the high
-                    // word takes dm times S's high word, 0 or -1), then + S
-                    const unsigned long long t =
-                        (((unsigned long long)(unsigned)fx.y << 32) | (unsigned)fx.x) +
-                        (unsigned long long)(unsigned)dm * (unsigned)fx.z;
-                    const long long la =
-                        (long long)((((unsigned long long)((unsigned)(t >> 32) + (unsigned)__mul24(dm, fx.w))) << 32) |
-                                    (unsigned)t);
-                    const long long lb = la + fix_s(fx);
-                    // row floor(l) takes the part of the step below the next
-                    // boundary, the row above it the rest
-                    const float wa = lower_weight((unsigned)la, fs.x);
-                    const float wb = lower_weight((unsigned)lb, fs.x);
-                    const int ea = (int)(la >> 32) - dn, eb = (int)(lb >> 32) - dn;
-                    const float ca0 = ea == 0 ? wa : (ea == -1 ? 1.f - wa : 0.f);
-                    const float ca1 = ea == 1 ? wa : (ea == 0 ? 1.f - wa : 0.f);
-                    const float cb0 = eb == 0 ? wb : (eb == -1 ? 1.f - wb : 0.f);
-                    const float cb1 = eb == 1 ? wb : (eb == 0 ? 1.f - wb : 0.f);
-                    const float c01 = xm ? cb0 : ca1, c10 = xm ? ca1 : cb0;
-                    const float4 sA = ssn[w][j - base][0], sB = ssn[w][j - base][1];
-                    const float sv[8] = {sA.x, sA.y, sA.z, sA.w, sB.x, sB.y, sB.z, sB.w};
+                if (pr) {
+                    const float4 sC = ssn[w][s0 + j - j0][2], sD = ssn[w][s0 + j - j0][3];
+                    const float sx[8] = {sC.x, sC.y, sC.z, sC.w, sD.x, sD.y, sD.z, sD.w};
 #pragma unroll
                     for (int t = 0; t < 4; ++t) {
-                        const float s1 = sv[2 * t], s2 = sv[2 * t + 1];
-                        acc[t][0] = fmaf(ca0, s1, acc[t][0]);
-                        acc[t][1] = fmaf(ca0, s2, acc[t][1]);
-                        acc[t][2] = fmaf(c01, s1, acc[t][2]);
-                        acc[t][3] = fmaf(c01, s2, acc[t][3]);
-                        acc[t][4] = fmaf(c10, s1, acc[t][4]);
-                        acc[t][5] = fmaf(c10, s2, acc[t][5]);
-                        acc[t][6] = fmaf(cb1, s1, acc[t][6]);
-                        acc[t][7] = fmaf(cb1, s2, acc[t][7]);
-                    }
-                    if (pair) {
-                        const float4 sC = ssn[w][j - base][2], sD = ssn[w][j - base][3];
-                        const float sx[8] = {sC.x, sC.y, sC.z, sC.w, sD.x, sD.y, sD.z, sD.w};
-#pragma unroll
-                        for (int t = 0; t < 4; ++t) {
-                            const float s1 = sx[2 * t], s2 = sx[2 * t + 1];
-                            acx[t][0] = fmaf(ca0, s1, acx[t][0]);
-                            acx[t][1] = fmaf(ca0, s2, acx[t][1]);
-                            acx[t][2] = fmaf(c01, s1, acx[t][2]);
-                            acx[t][3] = fmaf(c01, s2, acx[t][3]);
-                            acx[t][4] = fmaf(c10, s1, acx[t][4]);
-                            acx[t][5] = fmaf(c10, s2, acx[t][5]);
-                            acx[t][6] = fmaf(cb1, s1, acx[t][6]);
-                            acx[t][7] = fmaf(cb1, s2, acx[t][7]);
-                        }
+                        const float s1 = sx[2 * t], s2 = sx[2 * t + 1];
+                        acx[t][0] = fmaf(ca0, s1, acx[t][0]);
+                        acx[t][1] = fmaf(ca0, s2, acx[t][1]);
+                        acx[t][2] = fmaf(c01, s1, acx[t][2]);
+                        acx[t][3] = fmaf(c01, s2, acx[t][3]);
+                        acx[t][4] = fmaf(c10, s1, acx[t][4]);
+                        acx[t][5] = fmaf(c10, s2, acx[t][5]);
+                        acx[t][6] = fmaf(cb1, s1, acx[t][6]);
+                        acx[t][7] = fmaf(cb1, s2, acx[t][7]);
                     }
                 }
+            }
+        };
+        // views vv and vv + ncls of the class, in rounds of one staging each:
+        // both views in one round (halves of the wavefront) when both windows
+        // fit 32 bins, else view A's 64-bin rounds, then view B's.  Every
+        // accumulator takes the views in the same order, bins ascending.
+        for (int vv = cls; vv < nvc; vv += 2 * ncls) {
+            const int vb = vv + ncls;
+            const bool two = vb < nvc;   // wave-uniform
+            const int vA = v0 + vv, vB = v0 + vb;
+            const bool prA = vA > 0 && 2 * vA != q4, prB = vB > 0 && 2 * vB != q4;
+            int jlA, jhA, jlB = INT_MAX, jhB = INT_MIN;
+            window(vv, jlA, jhA);
+            if (two) window(vb, jlB, jhB);
+            // (clamped to the detector: empty stays empty)
+            const int JloA = max(wave_min(jlA), 0), JhiA = min(wave_max(jhA), nd - 1);
+            const int JloB = two ? max(wave_min(jlB), 0) : INT_MAX;
+            const int JhiB = two ? min(wave_max(jhB), nd - 1) : INT_MIN;
+            const bool emA = JloA > JhiA, emB = JloB > JhiB;   // wave-uniform
+            const bool packed = (emA || JhiA - JloA < 32) && (emB || JhiB - JloB < 32);
+            const int nA = emA ? 0 : (JhiA - JloA) / 64 + 1, nB = emB ? 0 : (JhiB - JloB) / 64 + 1;
+            const int nround = packed ? 1 : nA + nB;
+            for (int rd = 0; rd < nround; ++rd) {
+                // bins baseA..hiA of view A in slots from 0, baseB..hiB of
+                // view B in slots from sB (an empty part has hi = INT_MIN)
+                int baseA = 0, hiA = INT_MIN, baseB = 0, hiB = INT_MIN, sB = 64;
+                if (packed) {   // (an empty view keeps base 0: Jlo is INT_MAX there)
+                    baseA = emA ? 0 : JloA;
+                    hiA = emA ? INT_MIN : JhiA;
+                    baseB = emB ? 0 : JloB;
+                    hiB = emB ? INT_MIN : JhiB;
+                    sB = 32;
+                } else if (rd < nA) {
+                    baseA = JloA + 64 * rd;
+                    hiA = min(JhiA, baseA + 63);
+                } else {
+                    baseB = JloB + 64 * (rd - nA);
+                    hiB = min(JhiB, baseB + 63);
+                    sB = 0;
+                }
+                const bool hb = lane >= sB;   // this lane's slot holds view B
+                const int jj = hb ? baseB + (lane - sB) : baseA + lane;   // no overflow: base <= nd - 1
+                if (jj >= 0 && jj <= (hb ? hiB : hiA)) stage(hb ? vB : vA, jj, lane, hb ? prB : prA);
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll 1
+                for (int h = 0; h < 2; ++h)
+                    chords(h ? max(jlB, baseB) : max(jlA, baseA), h ? min(jhB, hiB) : min(jhA, hiA),
+                           h ? sB : 0, h ? baseB : baseA, h ? prB : prA);
                 __builtin_amdgcn_wave_barrier();
             }
         }
