@@ -47,7 +47,7 @@ enum {
     DECT_EWORKSPACE = -2,   /* caller workspace too small or misaligned     */
     DECT_ENOMEM = -3,       /* device allocation failed                     */
     DECT_EDEVICE = -4,      /* a HIP runtime call failed                    */
-    DECT_EUNSUPPORTED = -5, /* valid request this build does not implement  */
+    DECT_EUNSUPPORTED = -5, /* valid request the library does not implement */
     DECT_EBUSY = -6         /* no free slot (dect_engine_admit)             */
 };
 
@@ -88,7 +88,7 @@ typedef struct dect_geometry {
  *                        normalisations that give water unit curvature)
  *   n_iter               outer iterations K of Algorithm 1 (>= 1)
  *   f_inner              steepest-descent/CG steps on the f-subproblem per
- *                        outer iteration (this build: 1)
+ *                        outer iteration (this library: 1)
  *   t_tol, t_maxit       PCG tolerance (relative residual) and cap of the
  *                        Z^m subproblem (1e-7, 200); Z = Zw*t'^(1/m) is
  *                        ill-conditioned where t' is small, which is what

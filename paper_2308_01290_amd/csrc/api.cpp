@@ -107,7 +107,7 @@ static int check_params(const dect_params* p) {
         return fail(DECT_EINVAL, "lambda, beta0, kappa, eta, xi must be >= 0 and beta_max > 0");
     if (p->n_iter < 1) return fail(DECT_EINVAL, "n_iter must be >= 1");
     if (p->f_inner != 1)
-        return fail(DECT_EUNSUPPORTED, "f_inner = %d: this build runs one f-step per iteration",
+        return fail(DECT_EUNSUPPORTED, "f_inner = %d: the library runs one f-step per iteration",
                     p->f_inner);
     if (!(p->t_tol > 0) || p->t_maxit < 1) return fail(DECT_EINVAL, "t_tol > 0 and t_maxit >= 1");
     if (!(p->t_min > 0)) return fail(DECT_EINVAL, "t_min must be > 0");
