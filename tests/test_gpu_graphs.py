@@ -81,3 +81,17 @@ def test_graphs_image_form():
         assert np.array_equal(Zg, Ze) and np.array_equal(Rg, Re), rep
         assert sg == se, rep
         eager_work_between(g)
+
+
+@pytest.mark.parametrize("storage", [dect.DECT_STORAGE_BF16, dect.DECT_STORAGE_BF16 + 1])
+def test_graphs_with_bf16_storage(storage):
+    g, _, pL, pH = workload("small")
+    params = dect.default_params(n_iter=6, storage=storage)
+    lo, hi = cuda(pL[None]), cuda(pH[None])
+    Ze, Re, se = run(dect.Solver(g, params), lo, hi, 6)
+    sol = dect.Solver(g, params).set_graphs(True)
+    for rep in range(2):
+        Zg, Rg, sg = run(sol, lo, hi, 6)
+        assert np.array_equal(Zg, Ze) and np.array_equal(Rg, Re), (storage, rep)
+        assert sg == se
+        eager_work_between(g)
