@@ -83,7 +83,7 @@ def test_graphs_image_form():
         eager_work_between(g)
 
 
-@pytest.mark.parametrize("storage", [dect.DECT_STORAGE_BF16, dect.DECT_STORAGE_BF16 + 1])
+@pytest.mark.parametrize("storage", [dect.DECT_STORAGE_BF16, dect.DECT_STORAGE_BF16_STATE])
 def test_graphs_with_bf16_storage(storage):
     g, _, pL, pH = workload("small")
     params = dect.default_params(n_iter=6, storage=storage)
