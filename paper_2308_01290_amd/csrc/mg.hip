@@ -143,6 +143,42 @@ __global__ void k_mg_restrict_c(const float* __restrict__ cf, size_t cf_zstride,
     cc[(size_t)z * cc_zstride + p] = 0.25f * (f[a] + f[a + 1] + f[a + nxf] + f[a + nxf + 1]);
 }
 
+// All G tile levels of the coefficient pyramid in one pass: a workgroup takes
+// a 2^G x 2^G tile of level 0 and writes its cells of levels 1..G, each the
+// mean of 2 x 2 cells of the level below, summed in k_mg_restrict_c's order
+// (so the pyramid is the same bit for bit).  Needs every level an exact half
+// of the one below.
+struct MgCOffs {
+    size_t c[kMgMaxLevels];   // per-slice offsets of the levels in the level buffer
+};
+template <int G>
+__global__ __launch_bounds__(1 << (2 * G)) void k_mg_restrict_c_all(const float* __restrict__ c0,
+                                                                    size_t c0_zstride, int nx0,
+                                                                    float* __restrict__ mg,
+                                                                    MgCOffs O, size_t zstride) {
+    constexpr int T = 1 << G;   // tile side at level 0
+    __shared__ float t[2][T * T];
+    const int z = blockIdx.z;
+    const int i0 = blockIdx.y * T, k0 = blockIdx.x * T;
+    const int tid = threadIdx.x;
+    t[0][tid] = c0[(size_t)z * c0_zstride + (size_t)(i0 + tid / T) * nx0 + (k0 + tid % T)];
+    __syncthreads();
+    int src = 0;
+#pragma unroll
+    for (int l = 1; l <= G; ++l) {
+        const int n = T >> (l - 1), m = n >> 1, nxl = nx0 >> l;
+        if (tid < m * m) {
+            const int a = tid / m, b = tid % m;
+            const float* f = t[src] + (2 * a) * n + 2 * b;
+            const float v = 0.25f * (f[0] + f[1] + f[n] + f[n + 1]);
+            t[src ^ 1][tid] = v;
+            mg[O.c[l] + (size_t)z * zstride + (size_t)((i0 >> l) + a) * nxl + ((k0 >> l) + b)] = v;
+        }
+        __syncthreads();
+        src ^= 1;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // tile kernels: 16 x 16 pixels of one level per workgroup, two-pixel halo
 // ---------------------------------------------------------------------------
@@ -902,12 +938,42 @@ static void coarse_dims(const MgPlan& P, int* ny, int* nx) {
 void launch_mg_setup(const MgPlan& P, const float* w2, float* mg, int batch, float beta,
                      const double* beta_z, const int* skip, size_t skip_zstride, hipStream_t st) {
     const size_t n0 = (size_t)P.ny[0] * P.nx[0];
-    for (int l = 0; l < P.ngrid; ++l) {
-        const float* cf = l == 0 ? w2 : mg + P.c[l];
-        const size_t cfz = l == 0 ? n0 : P.zstride;
-        const int n = P.ny[l + 1] * P.nx[l + 1];
-        hipLaunchKernelGGL(k_mg_restrict_c, dim3((n + 255) / 256, batch), dim3(256), 0, st, cf, cfz,
-                           P.ny[l], P.nx[l], mg + P.c[l + 1], P.zstride);
+    // the tile levels' coefficients: one pass when levels 1..G halve exactly
+    // and G <= 4, else one launch per level
+    const int G = P.ngrid;
+    bool halves = G >= 1 && G <= 4 && P.ny[0] % (1 << G) == 0 && P.nx[0] % (1 << G) == 0;
+    for (int l = 1; halves && l <= G; ++l)
+        halves = P.ny[l] == P.ny[0] >> l && P.nx[l] == P.nx[0] >> l;
+    if (halves) {
+        MgCOffs O{};
+        for (int l = 1; l <= G; ++l) O.c[l] = P.c[l];
+        const dim3 grid(P.nx[0] >> G, P.ny[0] >> G, batch);
+        switch (G) {
+            case 1:
+                hipLaunchKernelGGL(k_mg_restrict_c_all<1>, grid, dim3(4), 0, st, w2, n0, P.nx[0], mg, O,
+                                   P.zstride);
+                break;
+            case 2:
+                hipLaunchKernelGGL(k_mg_restrict_c_all<2>, grid, dim3(16), 0, st, w2, n0, P.nx[0], mg, O,
+                                   P.zstride);
+                break;
+            case 3:
+                hipLaunchKernelGGL(k_mg_restrict_c_all<3>, grid, dim3(64), 0, st, w2, n0, P.nx[0], mg, O,
+                                   P.zstride);
+                break;
+            default:
+                hipLaunchKernelGGL(k_mg_restrict_c_all<4>, grid, dim3(256), 0, st, w2, n0, P.nx[0], mg, O,
+                                   P.zstride);
+                break;
+        }
+    } else {
+        for (int l = 0; l < P.ngrid; ++l) {
+            const float* cf = l == 0 ? w2 : mg + P.c[l];
+            const size_t cfz = l == 0 ? n0 : P.zstride;
+            const int n = P.ny[l + 1] * P.nx[l + 1];
+            hipLaunchKernelGGL(k_mg_restrict_c, dim3((n + 255) / 256, batch), dim3(256), 0, st, cf, cfz,
+                               P.ny[l], P.nx[l], mg + P.c[l + 1], P.zstride);
+        }
     }
     const int g0 = P.ngrid;
     const float sc = std::ldexp(1.f, -2 * g0);   // beta scale 4^-g0 of the first in-LDS level
