@@ -359,6 +359,9 @@ struct CgUpd {
     int nrz_used;
     double tol2;
     PcgState* st;
+    // k_mg_down2<false> only: 1 = first run the stopping test of the residual
+    // that iteration `it`'s update wrote (see there)
+    int check;
 };
 
 template <bool UPD>
@@ -370,6 +373,32 @@ __global__ __launch_bounds__(kPairThreads) void k_mg_down2(MgPair A, const int* 
     __shared__ double shn[4 * (kPairThreads / kWave)];
     const int z = blockIdx.z;
     if (mg_skip(skip, skip_zstride, z)) return;
+    if constexpr (!UPD) {
+        // Second kernel of a pipelined PCG iteration's V-cycle: the stopping
+        // test of r_(it+1), which the iteration's first kernel has just
+        // written, reduced exactly as the next iteration's first kernel
+        // would (same partial sums, same block reduction), so the decision
+        // and the recorded count are the same; a converged slice stops here
+        // and the rest of this V-cycle, whose result would go unused, skips.
+        if (U.check) {
+            const double* P = U.parts + (size_t)z * U.L.zstride;
+            const double* rrc = P + U.L.rr + (size_t)(U.it & 1) * U.L.nblk;
+            const double* r0p = P + U.L.init0;
+            double v[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int t = threadIdx.x; t < U.L.nblk; t += kPairThreads) {
+                v[2] += rrc[t];
+                v[3] += r0p[t];
+            }
+            block_sum_n<kPairThreads, 4>(v, shn);
+            if (v[2] <= U.tol2 * v[3]) {   // the same decision in every block
+                if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+                    U.st[z].done = 1;
+                    U.st[z].iters = U.it + 1;
+                }
+                return;
+            }
+        }
+    }
     constexpr int H0 = 3 * kMgNu;
     const int ny0 = A.ny0, nx0 = A.nx0, ny1 = ny0 / 2, nx1 = nx0 / 2;
     const int i0 = blockIdx.y * kCore2, k0 = blockIdx.x * kCore2;
@@ -1057,8 +1086,15 @@ void launch_mg_vcycle(const MgPlan& P, const float* r, const float* w2, float* z
                                dim3(kPairThreads), 0, st, pair(l), skip, skip_zstride, *upd);
             l += 2;
         } else if (P.pair[l]) {
+            // after the fused update (level pair 0 with upd): with the early
+            // stopping test
+            CgUpd c{};
+            if (upd && l == 2 && P.pair[0]) {
+                c = *upd;
+                c.check = 1;
+            }
             hipLaunchKernelGGL(k_mg_down2<false>, dim3(P.nx[l] / kCore2, P.ny[l] / kCore2, batch),
-                               dim3(kPairThreads), 0, st, pair(l), skip, skip_zstride, CgUpd{});
+                               dim3(kPairThreads), 0, st, pair(l), skip, skip_zstride, c);
             l += 2;
         } else {
             MgLevel L = level(l);
@@ -1137,7 +1173,7 @@ void launch_pcg_mg_prec_w_upd(const PcgArgs& a, int i, const MgPlan& P, float* m
     // (r, r2) and (p1, p1b) by parity
     float* rb[2] = {a.r, a.r2};
     float* sb[2] = {a.p1, a.p1b};
-    CgUpd U;
+    CgUpd U{};
     U.r_old = rb[i & 1];
     U.r_new = rb[(i + 1) & 1];
     U.s_old = sb[i & 1];
