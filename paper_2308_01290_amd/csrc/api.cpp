@@ -403,6 +403,7 @@ struct PcgRun {
     PcgArgs a;
     int it = 0, max_iter = 0;
     bool piped = false;        // pipelined form (multigrid with the fused last kernel)
+    bool early = false;        // piped, and each iteration tests its own new residual
     PcgState* hs = nullptr;    // host copy of the flags (pinned when the caller has it)
     std::vector<PcgState> own;
 };
@@ -418,7 +419,9 @@ static void pcg_chunk(PcgRun& R, const PcgBufs& b, float2* fft_scratch, hipStrea
         launch_pcg_update(a, R.it, st);
         apply_prec(a, R.it, b, fft_scratch, st);
     }
-    launch_pcg_check(a, R.it, st);
+    // with the early test the chunk's last V-cycle has already tested the
+    // last residual; a slice left running then counts the host's iterations
+    if (!R.early) launch_pcg_check(a, R.it, st);
 }
 
 // set-up: preconditioner data and the first preconditioner application
@@ -430,6 +433,7 @@ static void pcg_setup(PcgRun& R, const PcgBufs& b, float2* fft_scratch, hipStrea
     // with the multigrid preconditioner on sizes whose finest V-cycle kernel
     // can also apply A, the pipelined form: one reduction per iteration
     R.piped = a.prec == PREC_MG && mg_pipelined_ok(b.mg_plan);
+    R.early = R.piped && mg_early_stop(b.mg_plan);
     if (R.piped)
         launch_pcg_mg_prec_w(a, 0, b.mg_plan, b.mg, st);
     else
@@ -474,7 +478,7 @@ static int pcg_finish(PcgRun& R, const PcgBufs& b, float2* fft_scratch, hipStrea
         DECT_HIP(hipMemcpyAsync(R.hs, R.a.st, sizeof(PcgState) * batch, hipMemcpyDeviceToHost, st));
     }
     int mx = 0;
-    for (int z = 0; z < batch; ++z) mx = std::max(mx, R.hs[z].iters);
+    for (int z = 0; z < batch; ++z) mx = std::max(mx, R.hs[z].done ? R.hs[z].iters : R.it);
     if (iters_out) *iters_out = mx;
     return DECT_OK;
 }

@@ -413,6 +413,9 @@ void launch_pcg_mg_prec(const PcgArgs& a, int it, const MgPlan& P, float* mg, hi
 // the V-cycle as the pipelined PCG uses it (needs mg_pipelined_ok: level 0 a
 // pair level above at least one more tile level)
 bool mg_pipelined_ok(const MgPlan& P);
+// pipelined iterations test their new residual within their own V-cycle (then
+// a chunk needs no separate check kernel)
+bool mg_early_stop(const MgPlan& P);
 void launch_pcg_mg_prec_w(const PcgArgs& a, int i, const MgPlan& P, float* mg, hipStream_t st);
 // iteration i of the pipelined PCG in one V-cycle: the update fused into its
 // first kernel, then u, w and the partial sums of iteration i + 1; needs r2

@@ -1168,6 +1168,12 @@ bool mg_pipelined_ok(const MgPlan& P) {
     return P.ok && P.ngrid >= 2 && P.pair[0];
 }
 
+bool mg_early_stop(const MgPlan& P) {
+    // the V-cycle's second kernel is a level pair (k_mg_down2<false>): it runs
+    // the stopping test of the residual the iteration's update wrote
+    return mg_pipelined_ok(P) && P.ngrid > 2 && P.pair[2];
+}
+
 void launch_pcg_mg_prec_w_upd(const PcgArgs& a, int i, const MgPlan& P, float* mg, hipStream_t st) {
     // iteration i's update fused into the V-cycle of r_(i+1): r and s live in
     // (r, r2) and (p1, p1b) by parity
