@@ -56,3 +56,30 @@ def test_uneven_solver_handle_matches_one_shot():
     assert np.array_equal(Z, Z2) and np.array_equal(R, R2)
     with pytest.raises(ValueError):
         sol.init(lo[:-1].contiguous(), hi[:-1].contiguous())
+
+
+@pytest.mark.parametrize("n", [256, 384])
+def test_grid_sizes_of_the_multigrid_paths(n):
+    """256^2 (three tile levels: the one-pass w^2 pyramid with G = 3 and the PCG's
+    chunk check kernel) and 384^2 (four tile levels of non-power-of-two sides: the
+    pyramid with G = 4 and the V-cycle's early stopping test): two slices of
+    different fan geometry on one grid solve in a batch exactly as alone."""
+    phys = Physics()
+    g1 = P.FanGeometry(n_x=n, n_y=n, pixel_mm=0.8, n_views=360, n_det=2 * n, sid_mm=1000.0,
+                       sdd_mm=1500.0).resolved()
+    g2 = P.FanGeometry(n_x=n, n_y=n, pixel_mm=0.8, n_views=240, n_det=2 * n - 40, sid_mm=900.0,
+                       sdd_mm=1400.0, det_offset_mm=0.3).resolved()
+    data = []
+    for i, g in enumerate((g1, g2)):
+        ph = P.phantom_disk_inserts(seed=40 + i, radius=0.3 * n, n_inserts=5, semi=(0.03 * n, 0.07 * n))
+        pL, pH = P.analytic_sinograms(ph, g, phys.mu_pair)
+        data.append((g, P.poisson_log(pL, 1e5, 50 + i).astype(np.float32),
+                     P.poisson_log(pH, 1e5, 60 + i).astype(np.float32)))
+    params = dect.default_params(n_iter=4)
+    lo = dect.concat_sinograms([cuda(d[1]) for d in data])
+    hi = dect.concat_sinograms([cuda(d[2]) for d in data])
+    Zb, Rb = (host(x) for x in dect.solve_multi(lo, hi, [d[0] for d in data], params))
+    for z, (g, pL, pH) in enumerate(data):
+        Z1, R1 = (host(x)[0] for x in dect.solve(cuda(pL[None]), cuda(pH[None]), g, params))
+        assert np.array_equal(Zb[z], Z1) and np.array_equal(Rb[z], R1), (n, z)
+        assert np.isfinite(Z1).all() and (R1 > 0.5).mean() > 0.05
