@@ -412,6 +412,13 @@ int dect_engine_admit(dect_engine* e, const dect_geometry* g, const float* sino_
                       int32_t* slot_out);
 /* One outer iteration of every occupied slot. */
 int dect_engine_step(dect_engine* e);
+/* Up to n outer iterations of every occupied slot, pipelined across the
+ * iterations like dect_solver_iterate, and no more than the first slot to
+ * complete still needs (so that its slot can be refilled after the call).
+ * The results equal those of as many dect_engine_step calls.  *done_iters
+ * (HOST, nullable) receives the number run (0 with no occupied slot).
+ * DECT_EINVAL for a NULL engine or n < 1. */
+int dect_engine_step_n(dect_engine* e, int32_t n, int32_t* done_iters);
 /* Occupied and free slots (HOST pointers, nullable). */
 int dect_engine_status(const dect_engine* e, int32_t* active, int32_t* free_slots);
 /* Slots completed since the last call, oldest first (HOST array of cap). */

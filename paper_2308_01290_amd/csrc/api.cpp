@@ -2063,28 +2063,36 @@ int dect_engine_admit(dect_engine* e, const dect_geometry* gin, const float* lo,
     return DECT_OK;
 }
 
-int dect_engine_step(dect_engine* e) {
-    if (!e) return fail(DECT_EINVAL, "engine is NULL");
+int dect_engine_step_n(dect_engine* e, int32_t n, int32_t* done_iters) {
+    if (!e || n < 1) return fail(DECT_EINVAL, "dect_engine_step_n: engine is NULL or n < 1");
+    if (done_iters) *done_iters = 0;
     bool any = false;
     for (int z = 0; z < e->slots; ++z) any = any || e->busy[z];
     if (!any) return DECT_OK;
     dect_solver* s = e->s;
     // launches cover the slots up to the highest occupied one (admission fills
-    // the lowest free slot first)
-    int hw = 0;
+    // the lowest free slot first); at most as many iterations as the first
+    // slot to complete still needs
+    int hw = 0, m = n;
     for (int z = 0; z < e->slots; ++z)
-        if (e->busy[z]) hw = z + 1;
+        if (e->busy[z]) {
+            hw = z + 1;
+            m = std::min(m, e->K[z] - e->k[z]);
+        }
     s->batch = hw;
-    const int rc = one_iteration(s);
+    int rc = DECT_OK;
+    for (int i = 0; i < m && rc == DECT_OK; ++i) rc = one_iteration(s, i + 1 < m);   // pipelined
     s->batch = e->slots;
     if (rc) return rc;
+    if (done_iters) *done_iters = m;
     const size_t npix = (size_t)s->g.nx * s->g.ny;
     SliceDesc none = s->hdesc[0];
     none.nv = 0;
     none.nd = 0;
     for (int z = 0; z < e->slots; ++z) {
         if (!e->busy[z]) continue;
-        if (++e->k[z] < e->K[z]) continue;
+        e->k[z] += m;
+        if (e->k[z] < e->K[z]) continue;
         launch_finish(s->M, s->g.ny, s->g.nx, 1, s->rho + z * npix, s->t + z * npix,
                       (float)s->rp.p.rho_min, s->rp.p.t_min, e->Zout[z], e->Rout[z], s->st);
         launch_set_desc(const_cast<SliceDesc*>(s->tab.desc), z, none, s->st);
@@ -2095,6 +2103,8 @@ int dect_engine_step(dect_engine* e) {
     DECT_HIP(hipGetLastError());
     return DECT_OK;
 }
+
+int dect_engine_step(dect_engine* e) { return dect_engine_step_n(e, 1, nullptr); }
 
 int dect_engine_status(const dect_engine* e, int32_t* active, int32_t* free_slots) {
     if (!e) return fail(DECT_EINVAL, "engine is NULL");

@@ -59,7 +59,7 @@ EXPORTS = [
     "dect_solver_timing", "dect_solve",
     "dect_solve_workspace_bytes_multi", "dect_solver_create_multi", "dect_solve_multi",
     "dect_engine_workspace_bytes", "dect_engine_create", "dect_engine_destroy", "dect_engine_admit",
-    "dect_engine_step", "dect_engine_status", "dect_engine_completed",
+    "dect_engine_step", "dect_engine_step_n", "dect_engine_status", "dect_engine_completed",
     "dect_image_workspace_bytes", "dect_image_solver_create", "dect_image_solver_init",
     "dect_image_solver_set_state", "dect_solve_image",
     "dect_last_error",
@@ -120,6 +120,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.dect_engine_destroy.argtypes = [vp]
     L.dect_engine_admit.argtypes = [vp, G, vp, vp, i32, vp, vp, P(i32)]
     L.dect_engine_step.argtypes = [vp]
+    L.dect_engine_step_n.argtypes = [vp, i32, P(i32)]
     L.dect_engine_status.argtypes = [vp, P(i32), P(i32)]
     L.dect_engine_completed.argtypes = [vp, P(i32), i32, P(i32)]
     L.dect_image_workspace_bytes.argtypes = [i32, i32, Pp, i32]
@@ -634,8 +635,12 @@ class Engine:
         self._keep[slot.value] = (sino_lo, sino_hi, Z, rho)
         return slot.value
 
-    def step(self):
-        _check(lib().dect_engine_step(self._h), "dect_engine_step")
+    def step(self, n: int = 1) -> int:
+        """Up to n outer iterations of every occupied slot (pipelined), no more
+        than the first slot to complete needs; returns the number run."""
+        done = C.c_int32()
+        _check(lib().dect_engine_step_n(self._h, int(n), C.byref(done)), "dect_engine_step_n")
+        return int(done.value)
 
     def status(self):
         a, f = C.c_int32(), C.c_int32()

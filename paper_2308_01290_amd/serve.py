@@ -50,7 +50,11 @@ class Server:
     """Routes requests to per-size engines and steps them."""
 
     def __init__(self, specs: List[EngineSpec], params=None, hbm_budget_bytes: float = 200e9,
-                 device="cuda"):
+                 device="cuda", iters_per_step: int = 4):
+        # outer iterations per step: pipelined within the step, and a step ends
+        # early when a slot completes, so a freed slot waits for no more than
+        # this many iterations of the others before it is refilled
+        self.iters_per_step = int(iters_per_step)
         self.params = params if params is not None else dect.default_params()
         self.engines: Dict[int, dect.Engine] = {}
         self.queues: Dict[int, Deque[Request]] = {}
@@ -94,15 +98,16 @@ class Server:
                 self.running[n][slot] = r
 
     def step(self, clock) -> List[Request]:
-        """Admit what fits, advance every engine with work by one outer
-        iteration, and return the requests that completed (their maps are
+        """Admit what fits, advance every engine with work by up to
+        `iters_per_step` outer iterations (fewer when a slot completes
+        sooner), and return the requests that completed (their maps are
         synchronised)."""
         import torch
         self._admit(clock())
         stepped = False
         for n, eng in self.engines.items():
             if self.running[n]:
-                eng.step()
+                eng.step(self.iters_per_step)
                 stepped = True
         if not stepped:
             return []

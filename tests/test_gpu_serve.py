@@ -65,3 +65,37 @@ def test_engine_rejects_what_it_cannot_hold():
     assert eng.admit(small, cuda(z), cuda(z), 2) == 0
     assert eng.admit(small, cuda(z), cuda(z), 2) is None   # the only slot is busy
     assert eng.status() == (1, 0)
+
+
+def test_multi_iteration_steps_stop_at_a_completion_and_equal_each_alone():
+    reqs = requests()
+    eng = dect.Engine(128, 128, 1.0, slots=3, max_views=240, max_det=300)
+    pending = list(range(len(reqs)))
+    slot_of, results, runs = {}, {}, []
+    while len(results) < len(reqs):
+        while pending:
+            i = pending[0]
+            g, pL, pH, K = reqs[i]
+            s = eng.admit(g, cuda(pL), cuda(pH), K)
+            if s is None:
+                break
+            slot_of[s] = i
+            pending.pop(0)
+        n = eng.step(4)
+        runs.append(n)
+        assert 1 <= n <= 4
+        done = eng.completed()
+        for s, Z, R in done:
+            results[slot_of.pop(s)] = (host(Z), host(R))
+        # a step shorter than asked ends with a completion
+        assert n == 4 or done
+        assert len(runs) < 60
+    # budgets 3, 5, 4, 2, 6 in 3 slots: the first step stops at the first completion (3)
+    assert runs[0] == 3
+    for i, (g, pL, pH, K) in enumerate(reqs):
+        Z1, R1 = (host(x)[0] for x in dect.solve(cuda(pL[None]), cuda(pH[None]), g,
+                                                  dect.default_params(n_iter=K)))
+        assert np.array_equal(results[i][0], Z1) and np.array_equal(results[i][1], R1), i
+    assert eng.step(4) == 0
+    with pytest.raises(dect.DectError):
+        eng.step(0)
