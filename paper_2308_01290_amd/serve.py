@@ -55,6 +55,7 @@ class Server:
         # early when a slot completes, so a freed slot waits for no more than
         # this many iterations of the others before it is refilled
         self.iters_per_step = int(iters_per_step)
+        self._pool = None
         self.params = params if params is not None else dect.default_params()
         self.engines: Dict[int, dect.Engine] = {}
         self.queues: Dict[int, Deque[Request]] = {}
@@ -104,13 +105,19 @@ class Server:
         synchronised)."""
         import torch
         self._admit(clock())
-        stepped = False
-        for n, eng in self.engines.items():
-            if self.running[n]:
-                eng.step(self.iters_per_step)
-                stepped = True
-        if not stepped:
+        active = [eng for n, eng in self.engines.items() if self.running[n]]
+        if not active:
             return []
+        if len(active) == 1:
+            active[0].step(self.iters_per_step)
+        else:
+            # one host thread per engine: each engine's PCG waits on the host
+            # once per iteration, and the engines' streams overlap on the
+            # device only if those waits do (the library calls release the GIL)
+            if self._pool is None:
+                from concurrent.futures import ThreadPoolExecutor
+                self._pool = ThreadPoolExecutor(max_workers=len(self.engines))
+            list(self._pool.map(lambda e: e.step(self.iters_per_step), active))
         torch.cuda.synchronize()
         now = clock()
         out = []
