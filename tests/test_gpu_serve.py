@@ -99,3 +99,29 @@ def test_multi_iteration_steps_stop_at_a_completion_and_equal_each_alone():
     assert eng.step(4) == 0
     with pytest.raises(dect.DectError):
         eng.step(0)
+
+
+def test_server_with_two_sizes_threads_equal_each_alone():
+    """The server steps its per-size engines from one host thread each; every
+    result must still equal the slice solved alone."""
+    from paper_2308_01290_amd.serve import EngineSpec, Request, Server
+    phys = Physics()
+    reqs = []
+    for i, (n, v, d, K) in enumerate([(64, 96, 120, 3), (96, 120, 160, 4), (64, 80, 100, 5),
+                                      (96, 100, 150, 2), (64, 96, 110, 4)]):
+        g = P.FanGeometry(n_x=n, n_y=n, pixel_mm=1.0, n_views=v, n_det=d, sid_mm=800.0,
+                          sdd_mm=1200.0, det_offset_mm=0.2 * (i % 2)).resolved()
+        ph = P.phantom_disk_inserts(seed=70 + i, radius=0.35 * n, n_inserts=3,
+                                    semi=(0.04 * n, 0.08 * n))
+        pL, pH = P.analytic_sinograms(ph, g, phys.mu_pair)
+        reqs.append(Request(g, cuda(P.poisson_log(pL, 1e5, 80 + i).astype(np.float32)),
+                            cuda(P.poisson_log(pH, 1e5, 90 + i).astype(np.float32)), K,
+                            arrival=0.001 * i, tag=i))
+    server = Server([EngineSpec(64, 1.0, 2, 128, 128), EngineSpec(96, 1.0, 2, 128, 192)],
+                    iters_per_step=3)
+    done = server.run(reqs)
+    assert len(done) == len(reqs)
+    for r in done:
+        Z1, R1 = (host(x)[0] for x in dect.solve(r.sino_lo[None], r.sino_hi[None], r.geom,
+                                                  dect.default_params(n_iter=r.n_iter)))
+        assert np.array_equal(host(r.Z), Z1) and np.array_equal(host(r.rho), R1), r.tag
