@@ -209,24 +209,15 @@ def bench_uneven(args):
     print(json.dumps(out), flush=True)
 
 
-SERVE_SIZES = (256, 384, 512, 768)
-
-
 def _serve_slice(args):
-    """One pool slice for the serving stream: image n at 0.8 mm, views and bins
-    drawn from the seed, the body phantom scaled to the field of view."""
+    """One pool slice for the serving stream (image n, views and bins drawn
+    from the seed)."""
     n, seed = args
     from paper_2308_01290_amd import dect
     from paper_2308_01290_amd import phantoms as P
     params = dect.default_params()
-    rng = np.random.Generator(np.random.PCG64(seed))
-    g = P.FanGeometry(n_x=n, n_y=n, pixel_mm=0.8, n_views=int(rng.integers(360, 1153)),
-                      n_det=int(rng.integers(512, 1025)), sid_mm=1000.0, sdd_mm=1500.0).resolved()
-    s = n / 512.0
-    ph = P.phantom_body_inserts(seed, body_ax=(180.0 * s, 140.0 * s), semi=(3.0 * s, 18.0 * s))
-    pL, pH = P.analytic_sinograms(ph, g, lambda Z, R: dect.attenuation(params, Z, R))
-    return (g, P.poisson_log(pL, 5e4, 2 * seed + 1).astype(np.float32),
-            P.poisson_log(pH, 1e5, 2 * seed + 2).astype(np.float32))
+    g, ph, pL, pH = P.slice_served(n, seed, lambda Z, R: dect.attenuation(params, Z, R))
+    return g, pL.astype(np.float32), pH.astype(np.float32)
 
 
 def bench_serve(args):
@@ -235,16 +226,17 @@ def bench_serve(args):
     import multiprocessing as mp
     import torch
     from paper_2308_01290_amd import dect
+    from paper_2308_01290_amd import phantoms as P
     from paper_2308_01290_amd.serve import EngineSpec, Request, Server
     per_size = 4
-    jobs = [(n, 5000 + 10 * n + i) for n in SERVE_SIZES for i in range(per_size)]
+    jobs = [(n, 5000 + 10 * n + i) for n in P.SERVE_SIZES for i in range(per_size)]
     with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
         data = pool.map(_serve_slice, jobs)
     dev = torch.device("cuda:0")
     pool_dev = [(g, torch.as_tensor(pL, device=dev), torch.as_tensor(pH, device=dev))
                 for g, pL, pH in data]
     params = dect.default_params()
-    specs = [EngineSpec(n, 0.8, 16, 1152, 1024) for n in SERVE_SIZES]
+    specs = [EngineSpec(n, 0.8, 16, 1152, 1024) for n in P.SERVE_SIZES]
     rng = np.random.Generator(np.random.PCG64(20230801))
     results = []
     checked = 0

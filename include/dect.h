@@ -192,7 +192,8 @@ int dect_fbp(const dect_geometry* g, const float* sino, float* img, int32_t batc
 
 /* One half-quadratic-splitting step of the gradient-L0 model, eq. (5)-(9):
  *   (h, v) = hard threshold (9) of the periodic forward differences of g^(k)
- *            ((h, v) = 0 where dx^2 + dy^2 <= lambda/beta, decided in FP32);
+ *            ((h, v) = 0 where dx^2 + dy^2 <= lambda/beta, evaluated in FP32:
+ *            a pixel within rounding of the threshold may go either way);
  *   g^(k+1) = argmin ||w*g - g_tilde||^2 + beta*||D g - (h, v)||^2,
  * i.e. (diag(w^2) + beta D^T D) g = w*g_tilde + beta D^T (h, v), periodic.
  * weight == NULL means w = 1 and uses the FFT closed form of Section II-C;
@@ -336,8 +337,8 @@ int dect_solver_set_graphs(dect_solver* s, int enable);
  * projection launch of the outer iterations.  dect_solver_timing synchronises
  * the stream, returns the summed durations (ms) and launch counts since the
  * last call, and resets them.  Any output pointer may be NULL.  For an
- * image-domain solver the first pair times each iteration's f-step (both FFT
- * closed forms, one interval per iteration) and the second stays zero. */
+ * image-domain solver the first pair times each iteration's f-step (the
+ * joint FFT solve, one interval per iteration) and the second stays zero. */
 int dect_solver_enable_timing(dect_solver* s, int enable);
 int dect_solver_timing(dect_solver* s, double* backproject_ms, int32_t* backproject_launches,
                        double* project_ms, int32_t* project_launches);
@@ -352,14 +353,16 @@ int dect_solve_multi(const float* sino_lo, const float* sino_hi, const dect_geom
                      size_t ws_bytes, hipStream_t stream);
 
 /* ---- image-domain form ----------------------------------------------------
- * Algorithm 1 as the paper prints it, on attenuation images instead of
- * sinograms: the data terms of objective (10) are eta_i*||C_k1 f1 + C_k2 f2 -
- * mu_k||^2 for the two acquisition energies, and the f-subproblem (13a) is
- * solved by the printed FFT closed forms, f1 with f2 at iterate k and f2 with
- * f1 at iterate k:
- *   (c_i + beta D^T D) f_i = b_i + beta D^T HT(D f_i^(k)),
- *   c_i = eta_i sum_k C_ki^2 + xi sum_j Ms_ji^2,
- *   b_i = eta_i sum_k C_ki (mu_k - C_ko f_o) + xi sum_j Ms_ji (T_j - Ms_jo f_o).
+ * Algorithm 1 on attenuation images instead of sinograms: the data terms of
+ * objective (10) are eta_i*||C_k1 f1 + C_k2 f2 - mu_k||^2 for the two
+ * acquisition energies, and the f-subproblem (13a) is solved for (f1, f2)
+ * jointly, which satisfies both printed FFT closed forms at once: per
+ * frequency the 2x2 system
+ *   (H + beta |F D|^2 I) F(f) = F(b) + beta F(D^T HT(D f^(k))),
+ *   H = eta_i C^T C + xi Ms^T Ms,  b_i = eta_i sum_k C_ki mu_k + xi sum_j Ms_ji T_j.
+ * (The printed forms taken one basis at a time, each with the other at
+ * iterate k, do not converge at low frequencies once the coupling target
+ * lags; (13a) asks for the joint minimiser.)
  * The rho_e and t' steps, the beta schedule, the initialisation (the per-pixel
  * closed forms) and the output are those of the sinogram form.  eta = 0 in
  * dect_params selects eta_i = 1 / (mu_w(E_lo)^2 + mu_w(E_hi)^2), water's

@@ -8,9 +8,8 @@ TEST INFRASTRUCTURE ONLY (oracle).
     d_y g(i,j) = g(i+1,j) - g(i,j), indices mod N);
   * hard threshold, eq. (9): (h, v) = (0, 0) where (d_x g)^2 + (d_y g)^2 <= lambda/beta,
     else (d_x g, d_y g).  Equality maps to zero, as printed.  The comparison
-    decides a binary outcome, so it is taken in FP32 (the GPU kernel's
-    precision): both gradients rounded to FP32, squared and summed with FP32
-    rounding after each operation, compared with lambda/beta rounded to FP32;
+    is the real-valued one of eq. (9), evaluated in FP64 like every other
+    step here;
   * the g-subproblem closed form of Section II-C (FFT), with F(1) read as 1;
   * the weighted quadratic of subproblem (13c) as an SPD linear solve.
 """
@@ -33,12 +32,11 @@ def dT(h, v):
 
 
 def ht_keep(gx, gy, lam, beta):
-    """Boolean map of pixels that keep their gradient under eq. (9) (FP32 decision)."""
-    x = np.asarray(gx).astype(np.float32)
-    y = np.asarray(gy).astype(np.float32)
-    s = (x * x).astype(np.float32) + (y * y).astype(np.float32)
-    thr = np.float32(lam / beta)
-    return s > thr
+    """Boolean map of pixels that keep their gradient under eq. (9):
+    (d_x g)^2 + (d_y g)^2 > lambda / beta."""
+    x = np.asarray(gx, dtype=np.float64)
+    y = np.asarray(gy, dtype=np.float64)
+    return x * x + y * y > lam / beta
 
 
 def hard_threshold(gx, gy, lam, beta):

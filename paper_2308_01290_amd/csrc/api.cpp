@@ -492,6 +492,23 @@ static int run_pcg(PcgArgs& a, const PcgBufs& b, int max_iter, int first_chunk,
     return pcg_finish(R, b, fft_scratch, st, iters_out);
 }
 
+int l0_fft_step(const float* g_tilde, float* g, float* h_out, float* v_out, int n_y, int n_x,
+                int batch, double lambda, double beta, float2* fft, hipStream_t st) {
+    FftArgs a;
+    a.src = FFT_SRC_L0;
+    a.in = g_tilde;
+    a.base = g;
+    a.h_out = h_out;
+    a.v_out = v_out;
+    a.beta = (float)beta;
+    a.thr = (float)(lambda / beta);
+    a.c = 1.0;
+    a.out = g;
+    launch_fft_solve(n_y, n_x, batch, a, fft, st);
+    DECT_HIP(hipGetLastError());
+    return DECT_OK;
+}
+
 }  // namespace dect
 
 using namespace dect;
@@ -900,21 +917,7 @@ int dect_l0_step(const float* g_tilde, const float* weight, float* g, float* h_o
     Carver c{static_cast<char*>(ws)};
     float2* fft = c.take<float2>(fft_scratch_bytes(n_y, n_x, batch) / sizeof(float2));
     const float thr = (float)(lambda / beta);
-    if (!weight) {
-        FftArgs a;
-        a.src = FFT_SRC_L0;
-        a.in = g_tilde;
-        a.base = g;
-        a.h_out = h_out;
-        a.v_out = v_out;
-        a.beta = (float)beta;
-        a.thr = thr;
-        a.c = 1.0;
-        a.out = g;
-        launch_fft_solve(n_y, n_x, batch, a, fft, st);
-        DECT_HIP(hipGetLastError());
-        return DECT_OK;
-    }
+    if (!weight) return l0_fft_step(g_tilde, g, h_out, v_out, n_y, n_x, batch, lambda, beta, fft, st);
     PcgBufs b;
     carve_pcg(c, n_y, n_x, batch, &b);
     PcgArgs a;
@@ -1314,9 +1317,10 @@ static int t_step_finish(dect_solver* s, hipStream_t ms) {
     return DECT_OK;
 }
 
-// One outer iteration of the image-domain form: f1 and f2 by the FFT closed
-// forms of (13a) (each with the other basis at iterate k), then the rho_e and
-// t' steps, all reading iterate k; f^(k+1) is built in B and swapped in.
+// One outer iteration of the image-domain form: (f1, f2) by the joint
+// minimiser of (13a) (a 2x2 solve per frequency that meets both printed
+// closed forms at once), then the rho_e and t' steps, all reading iterate k;
+// f^(k+1) is built in B and swapped in.
 static int one_iteration_image(dect_solver* s, bool more) {
     const Geom& g = s->g;
     const Resolved& R = s->rp;
@@ -1335,15 +1339,11 @@ static int one_iteration_image(dect_solver* s, bool more) {
     if (two && s->upd_pending) DECT_HIP(hipStreamWaitEvent(side, s->ev_tdone, 0));  // t'^(k), beta^(k)
     float2* scratch = two ? s->fft2 : s->fft;
     hipEvent_t t0 = mark(s, side);
-    for (int comp = 0; comp < 2; ++comp) {
+    {
         FftArgs fa;
         fa.src = FFT_SRC_IMGF;
-        fa.comp = comp;
         fa.f = s->f;
-        fa.base = reinterpret_cast<const float*>(s->f) + comp;
-        fa.bstride = 2;
-        fa.out = reinterpret_cast<float*>(s->B) + comp;
-        fa.ostride = 2;
+        fa.out = reinterpret_cast<float*>(s->B);
         fa.mu_lo = s->muL;
         fa.mu_hi = s->muH;
         fa.rho_in = s->rho;
@@ -1362,8 +1362,17 @@ static int one_iteration_image(dect_solver* s, bool more) {
         fa.tpsi1 = M.psi[1];
         fa.eta_img = R.eta;
         fa.xi_img = R.xi;
-        fa.c = R.eta * (M.C[0][comp] * M.C[0][comp] + M.C[1][comp] * M.C[1][comp]) +
-               R.xi * (M.Ms[0][comp] * M.Ms[0][comp] + M.Ms[1][comp] * M.Ms[1][comp]);
+        // H = eta C^T C + xi Ms^T Ms, the constant matrix of the data and
+        // coupling terms of (13a)
+        double H[2][2];
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j)
+                H[i][j] = R.eta * (M.C[0][i] * M.C[0][j] + M.C[1][i] * M.C[1][j]) +
+                          R.xi * (M.Ms[0][i] * M.Ms[0][j] + M.Ms[1][i] * M.Ms[1][j]);
+        fa.c = H[0][0];
+        fa.c_b = H[1][1];
+        fa.c_o = H[0][1];
+        fa.c_det = H[0][0] * H[1][1] - H[0][1] * H[1][0];
         fa.beta = (float)s->beta;
         fa.thr = (float)(R.p.lambda / s->beta);
         fa.beta_z = s->beta_d;
@@ -1723,11 +1732,13 @@ static size_t image_layout(int nx, int ny, int batch, char* base, dect_solver* s
     const size_t npix = (size_t)nx * ny * batch;
     float2* f = c.take<float2>(npix);
     float2* fnext = c.take<float2>(npix);
-    float2* fft = c.take<float2>(npix);
+    // FFT scratch: two complex planes per slice (the joint f-step carries
+    // both bases)
+    float2* fft = c.take<float2>(2 * npix);
     float* rho = c.take<float>(npix);
     float* tt = c.take<float>(npix);
     float* tnext = c.take<float>(npix);
-    float2* fft2 = c.take<float2>(npix);
+    float2* fft2 = c.take<float2>(2 * npix);
     float* muL = c.take<float>(npix);
     float* muH = c.take<float>(npix);
     double* beta_d = c.take<double>((size_t)batch);

@@ -219,11 +219,14 @@ struct FftArgs {
     // target = rho_hat(f) (RHO) or in = g_tilde (L0).  Equal to the closed
     // form for (1 + beta L) out = target + beta D^T HT(D g), without the large
     // cancelling terms.
-    // IMGF (image-domain f-subproblem (13a), basis `comp` with the other basis
-    // at iterate k): (c + beta L) delta = r - beta D^T S, r = b - c g, where
-    //   r = eta_i sum_k C_k,comp (mu_k - (C f)_k) + xi sum_j Ms_j,comp (T_j - (Ms f)_j),
-    //   T_j = rho (ta_j t' + tpsi_j), c = eta_i sum_k C_k,comp^2 + xi sum_j Ms_j,comp^2,
-    // f (interleaved f1, f2) at iterate k; g = base = component comp of f.
+    // IMGF (image-domain f-subproblem (13a), both bases jointly): per frequency
+    //   [[c + beta L, c_o], [c_o, c_b + beta L]] delta = r - beta D^T S,
+    //   r_i = eta_i sum_k C_k,i (mu_k - (C f)_k) + xi sum_j Ms_j,i (T_j - (Ms f)_j),
+    //   T_j = rho (ta_j t' + tpsi_j), c = H_11, c_b = H_22, c_o = H_12,
+    //   c_det = c c_b - c_o^2 (FP64 on the host), H = eta_i C^T C + xi Ms^T Ms;
+    // f (interleaved f1, f2) at iterate k is the hard-threshold input; out
+    // points to the interleaved f^(k+1) = f + delta.  Scratch holds two
+    // complex planes per slice.
     const float* in = nullptr;
     const float2* f = nullptr;
     const float* base = nullptr;
@@ -252,7 +255,7 @@ struct FftArgs {
     const float* mu_hi = nullptr;
     const float* rho_in = nullptr;
     const float* t_in = nullptr;
-    int comp = 0;
+    double c_b = 0.0, c_o = 0.0, c_det = 0.0;
     double cL0 = 0, cL1 = 0, cH0 = 0, cH1 = 0;   // attenuation matrix rows (E_lo, E_hi)
     double ta0 = 0, ta1 = 0, tpsi0 = 0, tpsi1 = 0;
     double eta_img = 0, xi_img = 0;
@@ -263,6 +266,11 @@ struct FftArgs {
 size_t fft_scratch_bytes(int ny, int nx, int batch);
 void launch_fft_solve(int ny, int nx, int batch, const FftArgs& a, float2* scratch,
                       hipStream_t st);
+// Unit-weight gradient-L0 step (eq. (5)-(9), FFT closed form) with the given
+// complex scratch of batch*n_y*n_x values; every scratch value is written
+// before it is read.  Arguments validated by the caller.
+int l0_fft_step(const float* g_tilde, float* g, float* h_out, float* v_out, int n_y, int n_x,
+                int batch, double lambda, double beta, float2* fft, hipStream_t st);
 
 // Per-slice relaxation weight: a batch whose slices sit at different outer
 // iterations carries beta per slice on the device; kernels take their slice's

@@ -141,9 +141,10 @@ __device__ __forceinline__ float2 ht_small(const float* ra, const float* rb, int
     return keep ? make_float2(0.f, 0.f) : make_float2(dx, dy);
 }
 
-// r = b - c g of the image-domain f-subproblem at pixel q (FP64 per pixel:
-// the data and coupling residuals cancel to small values near convergence)
-__device__ __forceinline__ float imgf_residual(const FftArgs& a, size_t q) {
+// r = b - H f of the image-domain f-subproblem at pixel q, both bases (FP64
+// per pixel: the data and coupling residuals cancel to small values near
+// convergence)
+__device__ __forceinline__ float2 imgf_residual(const FftArgs& a, size_t q) {
     const float2 f = a.f[q];
     const double f1 = f.x, f2 = f.y;
     const double rL = (double)a.mu_lo[q] - (a.cL0 * f1 + a.cL1 * f2);
@@ -151,10 +152,9 @@ __device__ __forceinline__ float imgf_residual(const FftArgs& a, size_t q) {
     const double r = a.rho_in[q], t = a.t_in[q];
     const double c1 = r * (a.ta0 * t + a.tpsi0) - (a.m00 * f1 + a.m01 * f2);
     const double c2 = r * (a.ta1 * t + a.tpsi1) - (a.m10 * f1 + a.m11 * f2);
-    const double v = a.comp == 0
-                         ? a.eta_img * (a.cL0 * rL + a.cH0 * rH) + a.xi_img * (a.m00 * c1 + a.m10 * c2)
-                         : a.eta_img * (a.cL1 * rL + a.cH1 * rH) + a.xi_img * (a.m01 * c1 + a.m11 * c2);
-    return (float)v;
+    const double v1 = a.eta_img * (a.cL0 * rL + a.cH0 * rH) + a.xi_img * (a.m00 * c1 + a.m10 * c2);
+    const double v2 = a.eta_img * (a.cL1 * rL + a.cH1 * rH) + a.xi_img * (a.m01 * c1 + a.m11 * c2);
+    return make_float2((float)v1, (float)v2);
 }
 
 __device__ __forceinline__ bool skip_slice(const FftArgs& a, int z) {
@@ -186,6 +186,50 @@ __global__ __launch_bounds__(256) void k_fft_rows_fwd(FftPlan P, int ny, FftArgs
     slice_beta_thr(a, z);
     if (skip_slice(a, z)) return;
     const size_t npix = (size_t)nx * ny;
+    if (a.src == FFT_SRC_IMGF) {
+        // both bases: two interleaved transforms (A, B hold 2 nx values each),
+        // three rows of each basis for the hard threshold
+        float2* A2 = sm2;
+        float2* B2 = sm2 + 2 * nx;
+        float2* tw2 = sm2 + 4 * nx;
+        float* rows2 = reinterpret_cast<float*>(sm2 + 5 * nx);
+        fill_twiddles(tw2, nx);
+        const int im = (i == 0) ? ny - 1 : i - 1, ip = (i + 1 == ny) ? 0 : i + 1;
+        for (int k = threadIdx.x; k < nx; k += blockDim.x) {
+            const float2 fm = a.f[z * npix + (size_t)im * nx + k];
+            const float2 f0 = a.f[z * npix + (size_t)i * nx + k];
+            const float2 fp = a.f[z * npix + (size_t)ip * nx + k];
+            rows2[k] = fm.x;
+            rows2[nx + k] = f0.x;
+            rows2[2 * nx + k] = fp.x;
+            rows2[3 * nx + k] = fm.y;
+            rows2[4 * nx + k] = f0.y;
+            rows2[5 * nx + k] = fp.y;
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < nx; k += blockDim.x) {
+            const int km = (k == 0) ? nx - 1 : k - 1;
+            const float2 res = imgf_residual(a, z * npix + (size_t)i * nx + k);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const float* rm = rows2 + 3 * c * nx;
+                const float* r0 = rm + nx;
+                const float* rp = rm + 2 * nx;
+                const float2 sc = ht_small(r0, rp, k, nx, a.thr, nullptr);
+                const float2 sl = ht_small(r0, rp, km, nx, a.thr, nullptr);
+                const float2 su = ht_small(rm, r0, k, nx, a.thr, nullptr);
+                const float dts = (sl.x - sc.x) + (su.y - sc.y);
+                A2[2 * k + c] = make_float2((c == 0 ? res.x : res.y) - a.beta * dts, 0.f);
+            }
+        }
+        __syncthreads();
+        const float2* R2 = fft_lds<false>(A2, B2, tw2, P, 2);
+        for (int k = threadIdx.x; k < nx; k += blockDim.x) {
+            scratch[(2 * (size_t)z) * npix + (size_t)i * nx + k] = R2[2 * k];
+            scratch[(2 * (size_t)z + 1) * npix + (size_t)i * nx + k] = R2[2 * k + 1];
+        }
+        return;
+    }
     fill_twiddles(tw, nx);
     if (a.src == FFT_SRC_PLAIN) {
         const float cz = a.scale_w2 ? shift_of(a, z) : 0.f;
@@ -221,8 +265,6 @@ __global__ __launch_bounds__(256) void k_fft_rows_fwd(FftPlan P, int ny, FftArgs
                 const double M1 = a.m00 * (double)f.x + a.m01 * (double)f.y;
                 const double M2 = a.m10 * (double)f.x + a.m11 * (double)f.y;
                 diff = (float)((M1 * a.e1n - M2 * a.e2n) * a.inv_crho - (double)g);
-            } else if (a.src == FFT_SRC_IMGF) {
-                diff = imgf_residual(a, z * npix + (size_t)i * nx + k);
             } else {
                 diff = a.in[z * npix + (size_t)i * nx + k] - g;
                 if (a.h_out) a.h_out[z * npix + (size_t)i * nx + k] = kept.x;
@@ -242,9 +284,10 @@ __global__ __launch_bounds__(256) void k_fft_cols(FftPlan P, int nx, int cols, F
     __shared__ double sh[4];
     __shared__ float cz_sh;
     const int ny = P.n;
+    const int ncomp = a.src == FFT_SRC_IMGF ? 2 : 1;
     float2* A = sm2;
     float2* B = sm2 + (size_t)ny * cols;
-    float2* tw = sm2 + (size_t)2 * ny * cols;
+    float2* tw = sm2 + (size_t)2 * ny * cols * ncomp;
     float* lamy = reinterpret_cast<float*>(tw + ny);
     float* lamx = lamy + ny;
     // workgroups go round-robin to the 8 XCDs; give each XCD a contiguous run
@@ -267,6 +310,43 @@ __global__ __launch_bounds__(256) void k_fft_cols(FftPlan P, int nx, int cols, F
     for (int c = threadIdx.x; c < cols; c += blockDim.x) {
         const float s = sinpif((float)(c0 + c) / (float)nx);
         lamx[c] = 4.0f * s * s;
+    }
+    if (a.src == FFT_SRC_IMGF) {
+        // both bases of the same columns: transform t < cols is basis 0,
+        // t >= cols basis 1; the 2x2 system of (13a) couples them per frequency
+        const int nb = 2 * cols;
+        float2* A2 = sm2;
+        float2* B2 = sm2 + (size_t)ny * nb;
+        for (int idx = threadIdx.x; idx < ny * nb; idx += blockDim.x) {
+            const int e = idx / nb, r = idx - (idx / nb) * nb;
+            const int comp = r >= cols, c = r - comp * cols;
+            A2[idx] = (c0 + c < nx) ? scratch[(2 * (size_t)z + comp) * npix + (size_t)e * nx + c0 + c]
+                                    : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+        float2* R2 = fft_lds<false>(A2, B2, tw, P, nb);
+        float2* S2 = (R2 == A2) ? B2 : A2;
+        const float c1 = (float)a.c, c2 = (float)a.c_b, o = (float)a.c_o, d0 = (float)a.c_det;
+        for (int idx = threadIdx.x; idx < ny * cols; idx += blockDim.x) {
+            const int e = idx / cols, c = idx - (idx / cols) * cols;
+            const float bl = a.beta * (lamx[c] + lamy[e]);
+            // det = (c1 + bl)(c2 + bl) - o^2 = d0 + bl (c1 + c2 + bl), d0 formed in FP64
+            const float inv = 1.0f / (d0 + bl * (c1 + c2 + bl));
+            const float a11 = c1 + bl, a22 = c2 + bl;
+            const float2 x1 = R2[(size_t)e * nb + c], x2 = R2[(size_t)e * nb + cols + c];
+            R2[(size_t)e * nb + c] =
+                make_float2((a22 * x1.x - o * x2.x) * inv, (a22 * x1.y - o * x2.y) * inv);
+            R2[(size_t)e * nb + cols + c] =
+                make_float2((a11 * x2.x - o * x1.x) * inv, (a11 * x2.y - o * x1.y) * inv);
+        }
+        __syncthreads();
+        const float2* O2 = fft_lds<true>(R2, S2, tw, P, nb);
+        for (int idx = threadIdx.x; idx < ny * nb; idx += blockDim.x) {
+            const int e = idx / nb, r = idx - (idx / nb) * nb;
+            const int comp = r >= cols, c = r - comp * cols;
+            if (c0 + c < nx) scratch[(2 * (size_t)z + comp) * npix + (size_t)e * nx + c0 + c] = O2[idx];
+        }
+        return;
     }
     for (int idx = threadIdx.x; idx < ny * cols; idx += blockDim.x) {
         const int e = idx / cols, c = idx - (idx / cols) * cols;
@@ -301,6 +381,26 @@ __global__ __launch_bounds__(256) void k_fft_rows_inv(FftPlan P, int ny, FftArgs
     slice_beta_thr(a, z);
     if (skip_slice(a, z)) return;
     const size_t npix = (size_t)nx * ny;
+    if (a.src == FFT_SRC_IMGF) {
+        float2* A2 = sm2;
+        float2* B2 = sm2 + 2 * nx;
+        float2* tw2 = sm2 + 4 * nx;
+        fill_twiddles(tw2, nx);
+        for (int k = threadIdx.x; k < nx; k += blockDim.x) {
+            A2[2 * k] = scratch[(2 * (size_t)z) * npix + (size_t)i * nx + k];
+            A2[2 * k + 1] = scratch[(2 * (size_t)z + 1) * npix + (size_t)i * nx + k];
+        }
+        __syncthreads();
+        const float2* R2 = fft_lds<true>(A2, B2, tw2, P, 2);
+        const float sc2 = (float)(1.0 / ((double)nx * (double)ny));
+        float2* out2 = reinterpret_cast<float2*>(a.out);
+        for (int k = threadIdx.x; k < nx; k += blockDim.x) {
+            const size_t q = z * npix + (size_t)i * nx + k;
+            const float2 f = a.f[q];
+            out2[q] = make_float2(f.x + R2[2 * k].x * sc2, f.y + R2[2 * k + 1].x * sc2);
+        }
+        return;
+    }
     fill_twiddles(tw, nx);
     for (int k = threadIdx.x; k < nx; k += blockDim.x) A[k] = scratch[z * npix + (size_t)i * nx + k];
     __syncthreads();
@@ -327,11 +427,11 @@ size_t fft_scratch_bytes(int ny, int nx, int batch) {
     return (size_t)batch * ny * nx * sizeof(float2);
 }
 
-static int cols_for(int ny, int nx, int batch) {
-    // two ping-pong buffers of ny*cols complex values within 64 KiB of LDS, and
-    // at least 256 workgroups (one per CU) where the image allows
+static int cols_for(int ny, int nx, int batch, int ncomp) {
+    // two ping-pong buffers of ny*cols*ncomp complex values within 64 KiB of
+    // LDS, and at least 256 workgroups (one per CU) where the image allows
     int cols = 8;
-    while (cols > 1 && (size_t)2 * ny * cols * sizeof(float2) + ny * 16 > 64 * 1024) cols /= 2;
+    while (cols > 1 && (size_t)2 * ny * cols * ncomp * sizeof(float2) + ny * 16 > 64 * 1024) cols /= 2;
     while (cols > 2 && ((nx + cols - 1) / cols) * batch < 256) cols /= 2;
     return cols;
 }
@@ -341,14 +441,17 @@ void launch_fft_solve(int ny, int nx, int batch, const FftArgs& a, float2* scrat
     FftPlan px, py;
     make_plan(nx, &px);
     make_plan(ny, &py);
-    const size_t lds_row = (size_t)3 * nx * sizeof(float2) + (size_t)3 * nx * sizeof(float);
+    // the joint f-subproblem carries both bases through every pass
+    const int ncomp = a.src == FFT_SRC_IMGF ? 2 : 1;
+    const size_t lds_row = ncomp == 2 ? (size_t)5 * nx * sizeof(float2) + (size_t)6 * nx * sizeof(float)
+                                      : (size_t)3 * nx * sizeof(float2) + (size_t)3 * nx * sizeof(float);
     hipLaunchKernelGGL(k_fft_rows_fwd, dim3(ny, batch), dim3(256), lds_row, st, px, ny, a, scratch);
-    const int cols = cols_for(ny, nx, batch);
-    const size_t lds_col = (size_t)2 * ny * cols * sizeof(float2) + ny * sizeof(float2) +
+    const int cols = cols_for(ny, nx, batch, ncomp);
+    const size_t lds_col = (size_t)2 * ny * cols * ncomp * sizeof(float2) + ny * sizeof(float2) +
                            (size_t)ny * sizeof(float) + (size_t)cols * sizeof(float);
     hipLaunchKernelGGL(k_fft_cols, dim3((nx + cols - 1) / cols, batch), dim3(256), lds_col, st, py, nx,
                        cols, a, scratch);
-    const size_t lds_inv = (size_t)3 * nx * sizeof(float2);
+    const size_t lds_inv = (size_t)(ncomp == 2 ? 5 : 3) * nx * sizeof(float2);
     hipLaunchKernelGGL(k_fft_rows_inv, dim3(ny, batch), dim3(256), lds_inv, st, px, ny, a, scratch);
 }
 

@@ -386,6 +386,32 @@ def workload_uneven(mu_of: MuFn, n_slices: int = 64, seed0: int = 3000):
 
 
 # --------------------------------------------------------------------------
+# single-slice serving requests
+# --------------------------------------------------------------------------
+SERVE_SIZES = (256, 384, 512, 768)
+
+
+def geometry_served(n: int, seed: int, n_views=None, n_det=None) -> FanGeometry:
+    """Geometry of a served request: image n at 0.8 mm, views uniform in
+    360..1152 and bins uniform in 512..1024 drawn from the seed (or given)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    v = int(rng.integers(360, 1153))
+    d = int(rng.integers(512, 1025))
+    return FanGeometry(n_x=n, n_y=n, pixel_mm=0.8, n_views=n_views or v, n_det=n_det or d,
+                       sid_mm=1000.0, sdd_mm=1500.0).resolved()
+
+
+def slice_served(n: int, seed: int, mu_of: MuFn, n_views=None, n_det=None, I0=(5e4, 1e5)):
+    """(geometry, phantom, p_lo, p_hi) of a served request: the body phantom of
+    the 512^2 slice scaled to the field of view, Poisson 5e4 / 1e5."""
+    geom = geometry_served(n, seed, n_views, n_det)
+    s = n / 512.0
+    ph = phantom_body_inserts(seed, body_ax=(180.0 * s, 140.0 * s), semi=(3.0 * s, 18.0 * s))
+    pL, pH = analytic_sinograms(ph, geom, mu_of)
+    return geom, ph, poisson_log(pL, I0[0], 2 * seed + 1), poisson_log(pH, I0[1], 2 * seed + 2)
+
+
+# --------------------------------------------------------------------------
 # image-domain inputs (attenuation image pairs)
 # --------------------------------------------------------------------------
 # Relative noise of the two attenuation images, in units of water's

@@ -1,45 +1,75 @@
 """The FP64 oracle's own sensitivity on the 512^2 slice: how many body pixels
-move by more than the end-to-end tolerance when the oracle itself is
-perturbed at or above FP32 rounding level.
+move past the end-to-end bars (tests/e2e.py) when the oracle itself is run
+with the arithmetic the GPU path documents, or perturbed otherwise.
 
 The hard threshold of the gradient-L0 step (eq. (9)) makes the K-iteration
 map discontinuous, so the oracle run twice on inputs that differ by a
 rounding error already disagrees at isolated pixels.  This script measures
-that envelope against the stored result of make_golden.py; the bound on the
-fraction of such pixels in the GPU end-to-end test is set from it.  Calls
-only the oracle and the seeded input generator.
+that envelope against the stored result of make_golden.py.  Calls only the
+oracle and the seeded input generator.
 
-Modes (each is one 50-iteration solve, about 15-20 minutes on 8 cores):
-    input  EPS        input sinograms times (1 + EPS * N(0, 1))
-    round32           iterate rounded to FP32 after every outer iteration
-    noise  EF ET      after every outer iteration f1, f2, rho_e times
-                      (1 + EF * N(0, 1)) and t' times (1 + ET * N(0, 1))
+Modes (each is one 50-iteration solve, 15-25 minutes on 8 cores):
+    fp32 RMODE   the GPU path's documented arithmetic: every iterate (f1, f2,
+                 rho_e, t') rounded to FP32 after every outer iteration
+                 (RMODE nearest or zero: round to nearest, or toward zero),
+                 and the t' solve stopped at ||r|| <= 1e-7 ||r_0|| from its
+                 warm start (the GPU's stopping rule) instead of 1e-12 ||b||
+    input EPS    input sinograms times (1 + EPS * N(0, 1))
+    noise EF ET  after every outer iteration f1, f2, rho_e times
+                 (1 + EF * N(0, 1)) and t' times (1 + ET * N(0, 1))
 
-    python tests/golden/oracle_envelope.py round32
-    python tests/golden/oracle_envelope.py noise 1e-6 1e-5
+    python tests/golden/oracle_envelope.py fp32 nearest [--json]
+
+--json records the fractions in slice512_envelope.json under the mode's
+name.  The GPU end-to-end tests allow a fraction of body pixels past each
+bar of twice the larger of the two fp32 realisations (nearest, zero): the
+GPU rounds at every operation, not only the stored iterate, and the factor
+two is fixed here, before any GPU result is compared with it.
 """
+import json
 import os
 import sys
 
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
 
+from oracle import l0  # noqa: E402
 from oracle import solve as S  # noqa: E402
 from oracle.physics import Physics  # noqa: E402
 from paper_2308_01290_amd import phantoms as P  # noqa: E402
+from tests import e2e  # noqa: E402
 
-TOL_RHO = 1e-3
-
-
-def body_mask(ph, g, erode=2):
-    from scipy.ndimage import binary_erosion
-    lab = P.label_map(ph, g)
-    return binary_erosion(lab[1:].sum(0) > 0.999, iterations=erode)
+ENVELOPE_JSON = os.path.join(HERE, "slice512_envelope.json")
+GPU_T_TOL = 1e-7
 
 
-def run(mode, args):
+def round32(x, mode):
+    y = x.astype(np.float32)
+    if mode == "zero":
+        # toward zero: step back one ulp where nearest rounding went outward
+        out = np.abs(y.astype(np.float64)) > np.abs(x)
+        y = np.where(out, np.nextafter(y, np.float32(0)), y)
+    return y.astype(np.float64)
+
+
+def t_step_gpu_rule(st, phys, params):
+    """The t' subproblem (13c) as in the oracle, stopped at the GPU's rule."""
+    M1, M2 = phys.synth(st.f1, st.f2)
+    Ww = phys.W_water()
+    w = phys.W(M1, M2) / Ww
+    gt = phys.d_t(M1, M2) / Ww
+    h, v = l0.ht_of(st.t, params.lam, st.beta)
+    b = w * gt + st.beta * l0.dT(h, v)
+    r0 = float(np.linalg.norm(b - l0.weighted_apply(st.t, w * w, st.beta)))
+    rtol = GPU_T_TOL * r0 / max(float(np.linalg.norm(b)), 1e-300)
+    t, _, _ = l0.weighted_solve(w, gt, h, v, st.beta, x0=st.t, rtol=rtol)
+    return t
+
+
+def run(mode, args, write_json):
     phys = Physics()
     g, ph, pL, pH = P.workload_slice512(phys.mu_pair)
     a = pL.astype(np.float32).astype(np.float64)
@@ -52,8 +82,8 @@ def run(mode, args):
         b = b * (1 + eps * rng.standard_normal(b.shape))
 
     def after(st):
-        if mode == "round32":
-            r = lambda x: x.astype(np.float32).astype(np.float64)  # noqa: E731
+        if mode == "fp32":
+            r = lambda x: round32(x, args[0])  # noqa: E731
             return S.State(r(st.f1), r(st.f2), r(st.rho), r(st.t), st.beta, st.k)
         if mode == "noise":
             ef, et = float(args[0]), float(args[1])
@@ -62,20 +92,38 @@ def run(mode, args):
         return st
 
     st = after(S.init_state(a, b, g, phys, params))
-    for _ in range(params.n_iter):
-        st = after(S.iterate(st, a, b, g, phys, params))
+    for k in range(params.n_iter):
+        if mode == "fp32":
+            f1, f2 = S.f_step(st, a, b, g, phys, params)
+            st = S.State(f1, f2, S.rho_step(st, phys, params), t_step_gpu_rule(st, phys, params),
+                         st.beta * params.kappa, st.k + 1)
+        else:
+            st = S.iterate(st, a, b, g, phys, params)
+        st = after(st)
+        print(f"iteration {k + 1}", flush=True)
     Z, R = S.finalize(st, phys, params)
     gold = np.load(os.path.join(HERE, "slice512_K50.npz"))
     Zr, Rr = gold["Z"].astype(np.float64), gold["rho"].astype(np.float64)
-    body = body_mask(ph, g)
-    mz = body & (Zr >= 2) & (Z >= 2)
-    dz = np.abs(Z - Zr)[mz]
-    dr = (np.abs(R - Rr) / np.abs(Rr))[body]
-    nbad = int((dr > TOL_RHO).sum())
-    print(f"{mode} {' '.join(args)}: max|dZ|(Z>=2)={dz.max():.3g}; rel rho max={dr.max():.3g} "
-          f"p99={np.quantile(dr, 0.99):.3g}; > {TOL_RHO:g}: {nbad}/{body.sum()} "
-          f"= {nbad / body.sum():.3g}")
+    lab, body = e2e.body_mask(ph, g)
+    v = e2e.violations(Z, R, Zr, Rr, body)
+    fz, fr = e2e.fractions(v)
+    tag = " ".join([mode] + list(args))
+    print(f"{tag}: {v}; fractions z/t' {fz:.3g} rho {fr:.3g}", flush=True)
+    if write_json:
+        data = json.load(open(ENVELOPE_JSON)) if os.path.exists(ENVELOPE_JSON) else {}
+        data[tag] = dict(v, z_t_fraction=fz, rho_fraction=fr)
+        with open(ENVELOPE_JSON, "w") as fh:
+            json.dump(data, fh, indent=1, sort_keys=True)
+
+
+def allowed_fractions():
+    """Allowed violation fractions (Z-or-t', rho_e) of the GPU end-to-end
+    tests: twice the larger fp32 realisation."""
+    data = json.load(open(ENVELOPE_JSON))
+    runs = [data["fp32 nearest"], data["fp32 zero"]]
+    return (2.0 * max(r["z_t_fraction"] for r in runs), 2.0 * max(r["rho_fraction"] for r in runs))
 
 
 if __name__ == "__main__":
-    run(sys.argv[1], sys.argv[2:])
+    argv = [x for x in sys.argv[1:] if x != "--json"]
+    run(argv[0], argv[1:], "--json" in sys.argv)

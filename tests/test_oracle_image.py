@@ -16,27 +16,23 @@ def rand_state(rng, shape, beta):
     return State(f1, f2, rho, t, beta, 0)
 
 
-def phi_i(x, i, st, muL, muH, phys, params, hv):
-    """Subproblem (13a) in f_i with the other basis at iterate k, written out
-    from objective (12) term by term."""
+def phi_f(x1, x2, st, muL, muH, phys, params, hv1, hv2):
+    """Subproblem (13a) in (f1, f2), written out from objective (12) term by term."""
     C, m = phys.C(), phys.Msyn()
     T = coupling_target(st, phys)
-    fo = (st.f1, st.f2)[1 - i]
-    fs = [None, None]
-    fs[i], fs[1 - i] = x, fo
     val = 0.0
     for k, mu in enumerate((muL, muH)):
-        val += params.eta * np.sum((C[k, 0] * fs[0] + C[k, 1] * fs[1] - mu) ** 2)
+        val += params.eta * np.sum((C[k, 0] * x1 + C[k, 1] * x2 - mu) ** 2)
     for j in range(2):
-        val += params.xi * np.sum((m[j, 0] * fs[0] + m[j, 1] * fs[1] - T[j]) ** 2)
-    h, v = hv
-    val += st.beta * (np.sum((l0.dx(x) - h) ** 2) + np.sum((l0.dy(x) - v) ** 2))
+        val += params.xi * np.sum((m[j, 0] * x1 + m[j, 1] * x2 - T[j]) ** 2)
+    for x, (h, v) in ((x1, hv1), (x2, hv2)):
+        val += st.beta * (np.sum((l0.dx(x) - h) ** 2) + np.sum((l0.dy(x) - v) ** 2))
     return val
 
 
-def test_f_closed_form_is_the_subproblem_minimiser():
-    """The FFT solution has zero gradient of the written-out subproblem and any
-    perturbation raises it (so b_i, c_i and the FFT denominators agree)."""
+def test_f_step_is_the_joint_subproblem_minimiser():
+    """The joint FFT solve has zero gradient of the written-out subproblem
+    (13a) in both bases at once, and any perturbation of (f1, f2) raises it."""
     rng = np.random.default_rng(3)
     phys = Physics()
     params = I.resolved(Params(), phys)
@@ -44,21 +40,93 @@ def test_f_closed_form_is_the_subproblem_minimiser():
     st = rand_state(rng, shape, beta=0.7)
     muL, muH = phys.mu_pair(7.42 + rng.standard_normal(shape), 1.0 + 0.1 * rng.standard_normal(shape))
     f1, f2 = I.f_step(st, muL, muH, phys, params)
-    for i, x in enumerate((f1, f2)):
-        hv = l0.ht_of((st.f1, st.f2)[i], params.lam, st.beta)
-        base = phi_i(x, i, st, muL, muH, phys, params, hv)
-        for _ in range(5):
-            d = rng.standard_normal(shape)
-            for eps in (1e-3, -1e-3):
-                assert phi_i(x + eps * d, i, st, muL, muH, phys, params, hv) > base
-        # central differences along coordinate directions vanish at the minimiser
-        g = np.zeros(shape)
-        for idx in [(0, 0), (3, 4), (11, 9), (6, 2)]:
-            e = np.zeros(shape)
-            e[idx] = 1e-4
-            g[idx] = (phi_i(x + e, i, st, muL, muH, phys, params, hv)
-                      - phi_i(x - e, i, st, muL, muH, phys, params, hv)) / 2e-4
-            assert abs(g[idx]) < 1e-6 * max(1.0, base)
+    hv1 = l0.ht_of(st.f1, params.lam, st.beta)
+    hv2 = l0.ht_of(st.f2, params.lam, st.beta)
+    base = phi_f(f1, f2, st, muL, muH, phys, params, hv1, hv2)
+    for _ in range(5):
+        d1, d2 = rng.standard_normal((2,) + shape)
+        for eps in (1e-3, -1e-3):
+            assert phi_f(f1 + eps * d1, f2 + eps * d2, st, muL, muH, phys, params, hv1, hv2) > base
+    for idx in [(0, 0), (3, 4), (11, 9), (6, 2)]:
+        e = np.zeros(shape)
+        e[idx] = 1e-4
+        for grad in ((phi_f(f1 + e, f2, st, muL, muH, phys, params, hv1, hv2)
+                      - phi_f(f1 - e, f2, st, muL, muH, phys, params, hv1, hv2)) / 2e-4,
+                     (phi_f(f1, f2 + e, st, muL, muH, phys, params, hv1, hv2)
+                      - phi_f(f1, f2 - e, st, muL, muH, phys, params, hv1, hv2)) / 2e-4):
+            assert abs(grad) < 1e-6 * max(1.0, base)
+
+
+def test_printed_closed_forms_each_minimise_one_basis():
+    """Each printed closed form (the other basis at iterate k) minimises (13a)
+    in its own basis: the Jacobi pair the joint reading replaces."""
+    rng = np.random.default_rng(5)
+    phys = Physics()
+    params = I.resolved(Params(), phys)
+    shape = (12, 10)
+    st = rand_state(rng, shape, beta=0.7)
+    muL, muH = phys.mu_pair(7.42 + rng.standard_normal(shape), 1.0 + 0.1 * rng.standard_normal(shape))
+    f1, f2 = I.f_step_jacobi(st, muL, muH, phys, params)
+    hv1 = l0.ht_of(st.f1, params.lam, st.beta)
+    hv2 = l0.ht_of(st.f2, params.lam, st.beta)
+    b1 = phi_f(f1, st.f2, st, muL, muH, phys, params, hv1, hv2)
+    b2 = phi_f(st.f1, f2, st, muL, muH, phys, params, hv1, hv2)
+    for _ in range(5):
+        d = rng.standard_normal(shape)
+        for eps in (1e-3, -1e-3):
+            assert phi_f(f1 + eps * d, st.f2, st, muL, muH, phys, params, hv1, hv2) > b1
+            assert phi_f(st.f1, f2 + eps * d, st, muL, muH, phys, params, hv1, hv2) > b2
+
+
+def test_joint_step_contracts_where_printed_pair_grows():
+    """Linearised about a fixed point, at zero frequency (the beta terms
+    vanish there), one outer iteration maps an error (e_f^(k), e_f^(k-1)) to
+    e_f^(k+1) through the coupling target built from rho_e^(k), t'^(k), which
+    the closed forms (4a,b) invert exactly: T(f^(k-1)) = Ms f^(k-1).  The
+    printed pair, D e^(k+1) = -O e^(k) + Hc e^(k-1) (H = D + O), has spectral
+    radius above 1; the joint step, H e^(k+1) = Hc e^(k-1), below 1."""
+    phys = Physics()
+    params = I.resolved(Params(), phys)
+    C, m = phys.C(), phys.Msyn()
+    Hc = params.xi * m.T @ m
+    H = params.eta * C.T @ C + Hc
+    D = np.diag(np.diag(H))
+    O = H - D
+    z = np.zeros((2, 2))
+    jac = np.block([[-np.linalg.solve(D, O), np.linalg.solve(D, Hc)], [np.eye(2), z]])
+    joint = np.block([[z, np.linalg.solve(H, Hc)], [np.eye(2), z]])
+    assert max(abs(np.linalg.eigvals(jac))) > 1.5
+    assert max(abs(np.linalg.eigvals(joint))) < 0.95
+
+
+def noisy_disk(n, seed=7):
+    phys = Physics()
+    g = P.FanGeometry(n_x=n, n_y=n, pixel_mm=1.0, n_views=8, n_det=8, sid_mm=1000.0, sdd_mm=1500.0)
+    r = 0.42 * n
+    ph = P.phantom_disk_inserts(seed=seed, radius=r, n_inserts=3, semi=(0.08 * r, 0.18 * r))
+    L, H = P.noisy_mu_pair(ph, g, phys.mu_pair, seed + 1)
+    return phys, g, ph, L, H
+
+
+def test_noisy_solve_stays_bounded():
+    """A noisy 64^2 attenuation image pair (15 / 10 HU white noise), 50 outer
+    iterations: the joint reading stays bounded, water rho_e within 3% of 1
+    and water Z within 0.3 of 7.42 (the L0 model's own bias at this noise), while
+    the printed Jacobi pair taken literally grows without bound."""
+    from scipy.ndimage import binary_erosion
+    phys, g, ph, L, H = noisy_disk(64)
+    water = binary_erosion(P.label_map(ph, g)[1] > 0.999, iterations=2)
+    params = I.resolved(Params(n_iter=50), phys)
+    Z, R = I.solve(L, H, phys, Params(n_iter=50))
+    assert np.abs(R).max() < 2.5
+    assert abs(R[water].mean() - 1.0) <= 0.03
+    assert abs(Z[water].mean() - phys.Zw) <= 0.3
+    st = I.init_from_mu(L, H, phys, params)
+    for _ in range(50):
+        f1, f2 = I.f_step_jacobi(st, L, H, phys, params)
+        st = State(f1, f2, I.rho_step(st, phys, params), I.t_step(st, phys, params),
+                   st.beta * params.kappa, st.k + 1)
+    assert np.abs(st.rho).max() > 100.0
 
 
 def test_fft_solve_c_matches_dense_solve():
@@ -113,12 +181,15 @@ def test_noise_free_start_is_exact():
 
 
 def test_noise_free_inserts_recovered():
-    """Piecewise-constant materials without noise, with jumps well above the
-    gradient-L0 threshold: after 10 outer iterations each region's interior
-    mean is within 1% in rho_e and 0.15 in Z (the splitting's coupling
-    shifts thin regions slightly; contrast below the threshold would be
-    merged, which is the method's intended behaviour, not checked here)."""
+    """Piecewise-constant materials without noise: after 10 outer iterations
+    each region's interior mean is within 2% in rho_e and 0.35 in Z.  The
+    remaining bias is the L0 model's own: at beta^(0) = 2 lambda the threshold
+    lambda/beta = 0.5 exceeds these inserts' squared jumps in f1, f2, so the
+    first iterations smooth their edges before the threshold falls below the
+    jumps, and the exact (joint) f-step carries that smoothing into the
+    interior means (about 1.5% and 0.27 at worst here)."""
     for seed in (5, 6):
         for e, Zi, Ri in _inserts_case(seed, 10):
-            assert abs(Ri.mean() - e.rho_e) <= 0.01 * e.rho_e, (seed, e)
-            assert abs(Zi.mean() - e.Z) <= 0.15, (seed, e)
+            assert abs(Ri.mean() - e.rho_e) <= 0.02 * e.rho_e, (seed, e)
+            assert abs(Zi.mean() - e.Z) <= 0.35, (seed, e)
+
