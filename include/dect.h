@@ -207,6 +207,21 @@ int dect_l0_step(const float* g_tilde, const float* weight, float* g, float* h_o
                  int32_t n_y, int32_t n_x, int32_t batch, double lambda, double beta,
                  double tol, int32_t max_iter, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Allocation-free variant of dect_l0_step with unit weight (the FFT closed
+ * form), for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  It
+ * allocates nothing: its complex scratch is a static device array in the
+ * library, one per GPU (held until the process ends), of
+ * dect_l0_step_static_max_values() float2 values (2^21, 16 MiB); batch*n_y*n_x
+ * above that returns DECT_EINVAL before anything is enqueued.  Every call on a
+ * GPU shares that array, so calls that overlap on one GPU (other streams or
+ * threads) race; calls ordered on one stream do not.  Arguments, layout,
+ * results and other errors are those of dect_l0_step with weight = NULL; the
+ * results equal dect_l0_step's bit for bit (same kernels, same order). */
+size_t dect_l0_step_static_max_values(void);
+int dect_l0_step_static(const float* g_tilde, float* g, float* h_out, float* v_out, int32_t n_y,
+                        int32_t n_x, int32_t batch, double lambda, double beta, hipStream_t stream);
+
 /* ---- solver -------------------------------------------------------------
  * A solver holds one batch of slices that share parameters and the image grid
  * (n_x, n_y, pixel_mm), and all per-iteration state on the device: basis

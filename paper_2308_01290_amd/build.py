@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdect.so")
-SOURCES = ["api.cpp", "proj.hip", "fbp.hip", "fft.hip", "img.hip", "mg.hip"]
+SOURCES = ["api.cpp", "proj.hip", "fbp.hip", "fft.hip", "img.hip", "mg.hip", "l0_static.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

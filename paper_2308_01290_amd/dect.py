@@ -52,6 +52,7 @@ SCHEDULE_KEYS = [f[0] for f in _Schedule._fields_]
 EXPORTS = [
     "dect_default_params", "dect_resolve_geometry", "dect_attenuation", "dect_project",
     "dect_backproject", "dect_fbp", "dect_l0_step_workspace_bytes", "dect_l0_step",
+    "dect_l0_step_static_max_values", "dect_l0_step_static",
     "dect_solve_workspace_bytes", "dect_solver_create", "dect_solver_destroy", "dect_solver_init",
     "dect_solver_set_state", "dect_solver_iterate", "dect_solver_get_state", "dect_solver_finish",
     "dect_solver_stats", "dect_solver_get_schedule", "dect_solver_set_schedule",
@@ -92,6 +93,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.dect_l0_step_workspace_bytes.restype = C.c_size_t
     L.dect_l0_step.argtypes = [vp, vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_double,
                                C.c_double, C.c_double, C.c_int32, vp, C.c_size_t, vp]
+    L.dect_l0_step_static_max_values.argtypes = []
+    L.dect_l0_step_static_max_values.restype = C.c_size_t
+    L.dect_l0_step_static.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_double,
+                                      C.c_double, vp]
     L.dect_solve_workspace_bytes.argtypes = [G, Pp, C.c_int32]
     L.dect_solve_workspace_bytes.restype = C.c_size_t
     L.dect_solver_create.argtypes = [G, Pp, C.c_int32, vp, C.c_size_t, vp, P(vp)]
@@ -317,6 +322,23 @@ def l0_step(g_tilde, g, lam, beta, weight=None, tol=1e-6, max_iter=200, return_h
                                _batch(g), float(lam), float(beta), float(tol), int(max_iter), None, 0,
                                C.c_void_p(_stream(stream))), "dect_l0_step")
     return (g, h, v) if return_hv else g
+
+
+def l0_step_static(g_tilde, g, lam, beta, h=None, v=None, stream=None):
+    """The allocation-free unit-weight HQS step (in place on g; h, v are
+    optional caller-allocated outputs); see include/dect.h."""
+    ny, nx = g.shape[-2:]
+    _dev_f32(g, (ny, nx), "g")
+    _dev_f32(g_tilde, (ny, nx), "g_tilde")
+    for t, name in ((g_tilde, "g_tilde"), (h, "h"), (v, "v")):
+        if t is not None:
+            _dev_f32(t, (ny, nx), name)
+            if tuple(t.shape) != tuple(g.shape):
+                raise ValueError(f"{name} has shape {tuple(t.shape)}, g has {tuple(g.shape)}")
+    _check(lib().dect_l0_step_static(_ptr(g_tilde), _ptr(g), _ptr(h), _ptr(v), ny, nx, _batch(g),
+                                      float(lam), float(beta), C.c_void_p(_stream(stream))),
+           "dect_l0_step_static")
+    return g
 
 
 def _geometry_array(geoms):
