@@ -92,7 +92,10 @@ def measured_traffic(kernel: str):
 
 def cpu_baseline(g, pL, pH, iters: int):
     """The FP64 oracle (as it stands) on the host cores: FBP start plus `iters`
-    outer iterations, extrapolated to the 50-iteration solve."""
+    outer iterations, extrapolated to the 50-iteration solve.  A 1-core figure
+    comes from one forward and one back-projection of one channel (the
+    oracle's dominant work) timed on 1 core and on all cores."""
+    from oracle import operators as O
     from oracle import solve as S
     from oracle.physics import Physics
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -107,10 +110,25 @@ def cpu_baseline(g, pL, pH, iters: int):
         st = S.iterate(st, a, b, g, phys, params, nthreads=threads)
     t2 = time.perf_counter()
     per_slice = (t1 - t0) + N_ITER * (t2 - t1) / iters
+
+    def fp_bp(nthreads):
+        s0 = time.perf_counter()
+        O.project(g, st.f2, nthreads)
+        O.backproject(g, a, nthreads)
+        return time.perf_counter() - s0
+
+    t_all = fp_bp(threads)
+    t_one = fp_bp(1)
+    per_slice_1 = per_slice * t_one / t_all
     return {"value": 1.0 / per_slice, "unit": "slices/s", "cores": threads, "kind": "oracle",
             "sample": f"FBP start + {iters} of {N_ITER} outer iterations on the same 512^2 slice "
                       f"({t2 - t0:.1f} s), extrapolated to {N_ITER} iterations "
-                      f"({per_slice:.1f} s per slice)"}
+                      f"({per_slice:.1f} s per slice)",
+            "one_core": {"value": 1.0 / per_slice_1, "unit": "slices/s", "cores": 1,
+                         "sample": f"one forward and one back-projection of one channel: "
+                                   f"{t_one:.2f} s on 1 core, {t_all:.2f} s on {threads}; the "
+                                   f"all-core solve time scaled by that ratio "
+                                   f"({per_slice_1:.0f} s per slice)"}}
 
 
 def _uneven_slice(i):
@@ -220,9 +238,11 @@ def _serve_slice(args):
     return g, pL.astype(np.float32), pH.astype(np.float32)
 
 
-def bench_serve(args):
-    """Poisson streams of single-slice requests through the continuous-batching
-    server; per rate: latency p50/p99 (arrival to maps ready) and slices/s."""
+def serve_streams(rates, n_requests, seed=20230801, budget_bytes=200e9):
+    """Poisson streams of single-slice requests (image 256-768, 360-1152 views,
+    20-80 iterations) through the continuous-batching server, one stream per
+    rate; per rate: latency p50/p99 (arrival to maps ready) and slices/s.  Two
+    requests per rate are re-solved alone and compared bit for bit."""
     import multiprocessing as mp
     import torch
     from paper_2308_01290_amd import dect
@@ -237,15 +257,15 @@ def bench_serve(args):
                 for g, pL, pH in data]
     params = dect.default_params()
     specs = [EngineSpec(n, 0.8, 16, 1152, 1024) for n in P.SERVE_SIZES]
-    rng = np.random.Generator(np.random.PCG64(20230801))
+    rng = np.random.Generator(np.random.PCG64(seed))
     results = []
     checked = 0
     identical = True
-    for rate in [float(r) for r in args.rates.split(",")]:
-        server = Server(specs, params)
+    for rate in rates:
+        server = Server(specs, params, hbm_budget_bytes=budget_bytes)
         t = 0.0
         reqs = []
-        for i in range(args.requests):
+        for i in range(n_requests):
             t += rng.exponential(1.0 / rate)
             g, lo, hi = pool_dev[int(rng.integers(len(pool_dev)))]
             reqs.append(Request(g, lo, hi, int(rng.integers(20, 81)), arrival=t, tag=i))
@@ -258,25 +278,36 @@ def bench_serve(args):
                         "p99_ms": 1e3 * float(np.percentile(lat, 99)),
                         "mean_ms": 1e3 * float(lat.mean()),
                         "slices_per_s": len(reqs) / wall,
-                        "hbm_gb": server.hbm_bytes / 1e9})
+                        "hbm_peak_gb": server.hbm_peak / 1e9,
+                        "engines_created": server.engines_created})
         # a served request equals the same slice solved alone
         for r in reqs[:2]:
             Z1, R1 = dect.solve(r.sino_lo[None], r.sino_hi[None], r.geom, dect.default_params(n_iter=r.n_iter))
             identical = identical and bool(torch.equal(Z1[0], r.Z)) and bool(torch.equal(R1[0], r.rho))
             checked += 1
+        server.close()
         del server
+    return results, {"checked": checked, "identical": identical}
+
+
+SERVE_WORKLOAD = ("Poisson arrivals of single-slice requests: image 256/384/512/768 at 0.8 mm, "
+                  "views 360-1152, bins 512-1024, iterations 20-80; engines of 16 slots per image "
+                  "size created on demand under a 200 GB HBM budget")
+
+
+def bench_serve(args):
+    """Poisson streams of single-slice requests through the continuous-batching
+    server; per rate: latency p50/p99 (arrival to maps ready) and slices/s."""
+    results, same = serve_streams([float(r) for r in args.rates.split(",")], args.requests)
     mid = results[len(results) // 2]
     out = {
         "metric": "served p99 latency (single-slice requests, 256-768^2, 360-1152 views, 20-80 iters)",
         "value": mid["p99_ms"], "unit": "ms", "n_gpus": 1, "steps": len(results), "warmup": 0,
         "ms_per_step": None, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "Poisson arrivals of single-slice requests: image 256/384/512/768 at "
-                               "0.8 mm, views 360-1152, bins 512-1024, iterations 20-80; one "
-                               "16-slot engine per image size under a 200 GB HBM budget",
-                   "value_at_rate_req_s": mid["rate_req_s"]},
+        "config": {"workload": SERVE_WORKLOAD, "value_at_rate_req_s": mid["rate_req_s"]},
         "per_rate": results,
-        "served_equals_alone": {"checked": checked, "identical": identical},
+        "served_equals_alone": same,
     }
     print(json.dumps(out), flush=True)
 
@@ -386,6 +417,8 @@ def main():
                          "(default: autotune for uneven64, default otherwise)")
     ap.add_argument("--rates", default="20,50,100,200", help="serve: arrival rates (req/s)")
     ap.add_argument("--requests", type=int, default=96, help="serve: requests per rate")
+    ap.add_argument("--served-requests", type=int, default=48,
+                    help="slice512: requests of the served leg at 20 req/s (0: none)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first copy a device buffer of this many MiB once: the reference "
                          "kernel of known traffic for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
@@ -529,6 +562,10 @@ def main():
                      "traffic": measured_traffic("k_backproject_sym8") if storage == 0 else None},
         "schedule": {"mode": args.schedule or "default", "chosen": schedule, "autotune_s": t_tune},
     }
+    if args.served_requests > 0:
+        # the metric's served part: a short Poisson stream at 20 req/s
+        results, same = serve_streams([20.0], args.served_requests)
+        out["served"] = dict(results[0], workload=SERVE_WORKLOAD, served_equals_alone=same)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, pL, pH, args.cpu_iters)
     print(json.dumps(out), flush=True)

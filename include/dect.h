@@ -437,6 +437,12 @@ int dect_engine_step(dect_engine* e);
  * (HOST, nullable) receives the number run (0 with no occupied slot).
  * DECT_EINVAL for a NULL engine or n < 1. */
 int dect_engine_step_n(dect_engine* e, int32_t n, int32_t* done_iters);
+/* Cancel the request in `slot` between steps: the slot is freed at once
+ * (admittable again), the request's outputs are never written and it is not
+ * reported by dect_engine_completed.  The other slots' results are unchanged
+ * (each slot follows its own iteration).  DECT_EINVAL when the slot holds no
+ * request. */
+int dect_engine_cancel(dect_engine* e, int32_t slot);
 /* Occupied and free slots (HOST pointers, nullable). */
 int dect_engine_status(const dect_engine* e, int32_t* active, int32_t* free_slots);
 /* Slots completed since the last call, oldest first (HOST array of cap). */

@@ -2117,6 +2117,22 @@ int dect_engine_step_n(dect_engine* e, int32_t n, int32_t* done_iters) {
 
 int dect_engine_step(dect_engine* e) { return dect_engine_step_n(e, 1, nullptr); }
 
+int dect_engine_cancel(dect_engine* e, int32_t slot) {
+    if (!e) return fail(DECT_EINVAL, "dect_engine_cancel: engine is NULL");
+    if (slot < 0 || slot >= e->slots || !e->busy[slot])
+        return fail(DECT_EINVAL, "dect_engine_cancel: slot %d holds no request", slot);
+    dect_solver* s = e->s;
+    SliceDesc none = s->hdesc[0];
+    none.nv = 0;
+    none.nd = 0;
+    launch_set_desc(const_cast<SliceDesc*>(s->tab.desc), slot, none, s->st);
+    launch_set_int(s->active_d + slot, 0, s->st);
+    DECT_HIP(hipGetLastError());
+    e->busy[slot] = 0;
+    e->Zout[slot] = e->Rout[slot] = nullptr;
+    return DECT_OK;
+}
+
 int dect_engine_status(const dect_engine* e, int32_t* active, int32_t* free_slots) {
     if (!e) return fail(DECT_EINVAL, "engine is NULL");
     int n = 0;

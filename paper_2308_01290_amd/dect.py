@@ -61,6 +61,7 @@ EXPORTS = [
     "dect_solve_workspace_bytes_multi", "dect_solver_create_multi", "dect_solve_multi",
     "dect_engine_workspace_bytes", "dect_engine_create", "dect_engine_destroy", "dect_engine_admit",
     "dect_engine_step", "dect_engine_step_n", "dect_engine_status", "dect_engine_completed",
+    "dect_engine_cancel",
     "dect_image_workspace_bytes", "dect_image_solver_create", "dect_image_solver_init",
     "dect_image_solver_set_state", "dect_solve_image",
     "dect_last_error",
@@ -127,6 +128,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.dect_engine_step.argtypes = [vp]
     L.dect_engine_step_n.argtypes = [vp, i32, P(i32)]
     L.dect_engine_status.argtypes = [vp, P(i32), P(i32)]
+    L.dect_engine_cancel.argtypes = [vp, i32]
     L.dect_engine_completed.argtypes = [vp, P(i32), i32, P(i32)]
     L.dect_image_workspace_bytes.argtypes = [i32, i32, Pp, i32]
     L.dect_image_workspace_bytes.restype = C.c_size_t
@@ -314,6 +316,9 @@ def l0_step(g_tilde, g, lam, beta, weight=None, tol=1e-6, max_iter=200, return_h
     _dev_f32(g_tilde, (ny, nx), "g_tilde")
     if weight is not None:
         _dev_f32(weight, (ny, nx), "weight")
+    for t, name in ((g_tilde, "g_tilde"), (weight, "weight")):
+        if t is not None and tuple(t.shape) != tuple(g.shape):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, g has {tuple(g.shape)}")
     h = v = None
     if return_hv:
         h = torch.empty_like(g)
@@ -663,6 +668,11 @@ class Engine:
         done = C.c_int32()
         _check(lib().dect_engine_step_n(self._h, int(n), C.byref(done)), "dect_engine_step_n")
         return int(done.value)
+
+    def cancel(self, slot: int):
+        """Free an occupied slot between steps; its outputs are never written."""
+        _check(lib().dect_engine_cancel(self._h, int(slot)), "dect_engine_cancel")
+        self._keep.pop(int(slot), None)
 
     def status(self):
         a, f = C.c_int32(), C.c_int32()

@@ -125,3 +125,50 @@ def test_server_with_two_sizes_threads_equal_each_alone():
         Z1, R1 = (host(x)[0] for x in dect.solve(r.sino_lo[None], r.sino_hi[None], r.geom,
                                                   dect.default_params(n_iter=r.n_iter)))
         assert np.array_equal(host(r.Z), Z1) and np.array_equal(host(r.rho), R1), r.tag
+
+
+def test_server_budget_admission_and_cancel_equal_each_alone():
+    """An HBM budget that holds one engine at a time: the two sizes take turns
+    (the idle engine is retired to make room), a request cancelled mid-solve
+    never writes its maps, a queued one is dropped, and every completed
+    result equals the slice solved alone."""
+    from paper_2308_01290_amd.serve import CANCELLED, DONE, EngineSpec, Request, Server
+    phys = Physics()
+    specs = [EngineSpec(64, 1.0, 2, 128, 128), EngineSpec(96, 1.0, 2, 128, 192)]
+    lib = dect.lib()
+    params = dect.default_params()
+    nbytes = [lib.dect_engine_workspace_bytes(s.n, s.n, s.pixel_mm, s.slots, s.max_views, s.max_det,
+                                              params) for s in specs]
+    budget = max(nbytes) + min(nbytes) // 2
+    reqs = []
+    for i, (n, v, d, K) in enumerate([(64, 96, 120, 6), (96, 120, 160, 3), (64, 80, 100, 2),
+                                      (96, 100, 150, 2), (64, 96, 110, 3)]):
+        g = P.FanGeometry(n_x=n, n_y=n, pixel_mm=1.0, n_views=v, n_det=d, sid_mm=800.0,
+                          sdd_mm=1200.0).resolved()
+        ph = P.phantom_disk_inserts(seed=170 + i, radius=0.35 * n, n_inserts=3,
+                                    semi=(0.04 * n, 0.08 * n))
+        pL, pH = P.analytic_sinograms(ph, g, phys.mu_pair)
+        reqs.append(Request(g, cuda(P.poisson_log(pL, 1e5, 180 + i).astype(np.float32)),
+                            cuda(P.poisson_log(pH, 1e5, 190 + i).astype(np.float32)), K, tag=i))
+    server = Server(specs, hbm_budget_bytes=budget, iters_per_step=2)
+    for r in reqs:
+        assert server.submit(r)
+    t = [0.0]
+    clock = lambda: t[0]  # noqa: E731
+    server.step(clock)                       # 64^2 engine: requests 0 and 2 running
+    assert reqs[0].status == "running" and reqs[1].status == "queued"
+    assert server.cancel(reqs[0])            # mid-solve (2 of its 6 iterations done)
+    assert server.cancel(reqs[4])            # still queued
+    while server.pending():
+        t[0] += 1.0
+        server.step(clock)
+        assert server.hbm_bytes <= budget
+    assert server.hbm_peak <= budget and server.engines_retired >= 1
+    assert reqs[0].status == CANCELLED and reqs[0].Z is None
+    assert reqs[4].status == CANCELLED and reqs[4].Z is None
+    for r in (reqs[1], reqs[2], reqs[3]):
+        assert r.status == DONE
+        Z1, R1 = (host(x)[0] for x in dect.solve(r.sino_lo[None], r.sino_hi[None], r.geom,
+                                                  dect.default_params(n_iter=r.n_iter)))
+        assert np.array_equal(host(r.Z), Z1) and np.array_equal(host(r.rho), R1), r.tag
+    server.close()
