@@ -1149,7 +1149,7 @@ static void project_residual(dect_solver* s, const float* lo, const float* hi) {
 static void round_state(dect_solver* s, int z0, int n, hipStream_t st) {
     if (s->storage != DECT_STORAGE_BF16_STATE || n < 1) return;
     const size_t npix = (size_t)s->g.nx * s->g.ny;
-    launch_round_state(npix * n, s->f + z0 * npix, s->rho + z0 * npix, s->t + z0 * npix, st);
+    launch_round_state(npix, n, s->f + z0 * npix, s->rho + z0 * npix, s->t + z0 * npix, s->beta_d + z0, st);
 }
 static void round_state(dect_solver* s, int z0, int n) { round_state(s, z0, n, s->st); }
 
@@ -1168,11 +1168,11 @@ int dect_solver_init(dect_solver* s, const float* lo, const float* hi) {
     }
     launch_init_state(s->M, g.ny, g.nx, s->batch, s->muL, s->muH, (float)s->rp.p.rho_min, s->f,
                       s->rho, s->t, s->st);
-    round_state(s, 0, s->batch);
-    project_residual(s, lo, hi);
     s->k = 0;
     s->beta = s->rp.beta0;
     launch_set_beta(s->beta_d, s->kappa_d, 0, s->batch, s->beta, s->rp.kappa, s->st);
+    round_state(s, 0, s->batch);   // (seeded by beta^(0))
+    project_residual(s, lo, hi);
     DECT_HIP(hipGetLastError());
     return DECT_OK;
 }
@@ -1187,12 +1187,12 @@ int dect_solver_set_state(dect_solver* s, const float* lo, const float* hi, cons
     launch_join_f2(s->g.nx * s->g.ny, s->batch, f1, f2, s->f, s->st);
     DECT_HIP(hipMemcpyAsync(s->rho, rho, npix * sizeof(float), hipMemcpyDeviceToDevice, s->st));
     DECT_HIP(hipMemcpyAsync(s->t, t, npix * sizeof(float), hipMemcpyDeviceToDevice, s->st));
-    round_state(s, 0, s->batch);
-    project_residual(s, lo, hi);
     s->k = k;
     s->beta = s->rp.beta0;
     for (int i = 0; i < k; ++i) s->beta *= s->rp.kappa;
     launch_set_beta(s->beta_d, s->kappa_d, 0, s->batch, s->beta, s->rp.kappa, s->st);
+    round_state(s, 0, s->batch);   // (seeded by beta^(k))
+    project_residual(s, lo, hi);
     DECT_HIP(hipGetLastError());
     return DECT_OK;
 }
@@ -2038,6 +2038,9 @@ int dect_engine_admit(dect_engine* e, const dect_geometry* gin, const float* lo,
     launch_fbp(g, hi, 1, q, s->muH + z * npix, st);
     launch_init_state(s->M, g.ny, g.nx, 1, s->muL + z * npix, s->muH + z * npix,
                       (float)s->rp.p.rho_min, s->f + z * npix, s->rho + z * npix, s->t + z * npix, st);
+    // continuation schedule of this request (beta^(0) also seeds the rounding below)
+    const double kappa = std::pow(e->p.beta_max / s->rp.beta0, 1.0 / n_iter);
+    launch_set_beta(s->beta_d, s->kappa_d, z, 1, s->rp.beta0, kappa, st);
     round_state(s, z, 1);
     // residual sinograms of the start
     const PadLayout P = solver_pad(s);
@@ -2060,9 +2063,6 @@ int dect_engine_admit(dect_engine* e, const dect_geometry* gin, const float* lo,
     a.res_bf16 = s->storage != DECT_STORAGE_FP32;
     a.sym_all = sym4(g);
     launch_project(g, P, tz, s->dpad + z * P.pair, 1, PROJ_RESID, a, st);
-    // continuation schedule of this request
-    const double kappa = std::pow(e->p.beta_max / s->rp.beta0, 1.0 / n_iter);
-    launch_set_beta(s->beta_d, s->kappa_d, z, 1, s->rp.beta0, kappa, st);
     launch_set_int(s->active_d + z, 1, st);
     DECT_HIP(hipGetLastError());
     e->busy[z] = 1;

@@ -316,7 +316,8 @@ void launch_grad(const Model& M, const ImgArgs& a, const PadLayout& P, const flo
 void launch_update(const ImgArgs& a, const PadLayout& P, const RayTable& T, const double* alpha,
                    const void* dpad, float2* f, void* S, const void* zq, double* beta_z,
                    const double* kappa_z, hipStream_t st);
-void launch_round_state(size_t n, float2* f, float* rho, float* t, hipStream_t st);
+void launch_round_state(size_t npix, int batch, float2* f, float* rho, float* t, const double* beta_z,
+                        hipStream_t st);
 // continuation: beta_z[z] *= kappa_z[z] for z < n
 void launch_step_beta(double* beta_z, const double* kappa_z, int n, hipStream_t st);
 // beta_z[z0 .. z0+n) = beta, kappa_z[...] = kappa

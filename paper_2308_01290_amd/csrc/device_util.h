@@ -123,6 +123,39 @@ __device__ __forceinline__ float bf16_hi(unsigned w) { return __uint_as_float(w 
 __device__ __forceinline__ float2 bf16x2_unpack(unsigned w) { return make_float2(bf16_lo(w), bf16_hi(w)); }
 __device__ __forceinline__ float bf16_round(float x) { return __uint_as_float(bf16_bits(x) << 16); }
 
+// Stochastic rounding to BF16 for values that accumulate small updates (the
+// residual sinograms, the state images): adding 16 uniform random bits below
+// the kept ones before truncating rounds the magnitude up with probability
+// equal to the dropped fraction, so the stored value is unbiased and an update
+// below half a BF16 ulp survives in expectation instead of being rounded away.
+// Non-finite inputs round to nearest.  The bits come from the finaliser of
+// MurmurHash3 (Appleby) over an element index and a per-slice seed, so the
+// rounding is deterministic.
+__device__ __forceinline__ unsigned fmix32(unsigned h) {
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+__device__ __forceinline__ unsigned seed_of(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    return fmix32((unsigned)b ^ fmix32((unsigned)(b >> 32)));
+}
+__device__ __forceinline__ unsigned bf16_bits_sr(float x, unsigned r16) {
+    const unsigned u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return bf16_bits(x);
+    return (u + (r16 & 0xffffu)) >> 16;
+}
+// x takes the low 16 random bits, y the high 16
+__device__ __forceinline__ unsigned bf16x2_pack_sr(float x, float y, unsigned r) {
+    return bf16_bits_sr(x, r) | (bf16_bits_sr(y, r >> 16) << 16);
+}
+__device__ __forceinline__ float bf16_round_sr(float x, unsigned r16) {
+    return __uint_as_float(bf16_bits_sr(x, r16) << 16);
+}
+
 __device__ __forceinline__ int wrap(int i, int n) {
     i %= n;
     return i < 0 ? i + n : i;

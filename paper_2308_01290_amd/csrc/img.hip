@@ -247,10 +247,13 @@ __global__ void k_update(int ny, int nx, PadLayout P, RayTable T, const double* 
     if (r < (size_t)D.nv * D.nd) {
         const size_t o = (size_t)(D.sino0 + (long long)z * T.sino_zstride) + r;
         if constexpr (BF) {
+            // the residuals accumulate alpha-scaled updates: stochastic
+            // rounding, seeded by this slice's step alpha (new every iteration)
             const float2 q = bf16x2_unpack(static_cast<const unsigned*>(zq_v)[o]);
             unsigned* S = static_cast<unsigned*>(S_v);
             const float2 v = bf16x2_unpack(S[o]);
-            S[o] = bf16x2_pack(fmaf(al, q.x, v.x), fmaf(al, q.y, v.y));
+            const unsigned rb = fmix32((unsigned)r ^ seed_of(alpha[z]));
+            S[o] = bf16x2_pack_sr(fmaf(al, q.x, v.x), fmaf(al, q.y, v.y), rb);
         } else {
             const float2 q = static_cast<const float2*>(zq_v)[o];
             float2* S = static_cast<float2*>(S_v);
@@ -274,15 +277,21 @@ void launch_update(const ImgArgs& a, const PadLayout& P, const RayTable& T, cons
                            st, a.ny, a.nx, P, T, alpha, dpad, f, S, zq, beta_z, kappa_z);
 }
 
-// state images rounded to BF16 (the values BF16 storage of f1, f2, rho_e, t' holds)
-__global__ void k_round_state(size_t n, float2* __restrict__ f, float* __restrict__ rho,
-                              float* __restrict__ t) {
+// state images rounded to BF16 (the values BF16 storage of f1, f2, rho_e, t'
+// holds), stochastically: each iteration's small updates survive in
+// expectation.  Seeded per slice by its beta (new every iteration).
+__global__ void k_round_state(size_t npix, int batch, float2* __restrict__ f, float* __restrict__ rho,
+                              float* __restrict__ t, const double* __restrict__ beta_z) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= npix * (size_t)batch) return;
+    const int z = (int)(i / npix);
+    const unsigned seed = seed_of(beta_z[z]);
+    const unsigned r1 = fmix32((unsigned)(2 * (i - z * npix)) ^ seed);
+    const unsigned r2 = fmix32((unsigned)(2 * (i - z * npix) + 1) ^ seed);
     const float2 v = f[i];
-    f[i] = make_float2(bf16_round(v.x), bf16_round(v.y));
-    rho[i] = bf16_round(rho[i]);
-    t[i] = bf16_round(t[i]);
+    f[i] = make_float2(bf16_round_sr(v.x, r1), bf16_round_sr(v.y, r1 >> 16));
+    rho[i] = bf16_round_sr(rho[i], r2);
+    t[i] = bf16_round_sr(t[i], r2 >> 16);
 }
 
 __global__ void k_step_beta(double* beta_z, const double* kappa_z, int n) {
@@ -294,8 +303,11 @@ void launch_step_beta(double* beta_z, const double* kappa_z, int n, hipStream_t 
     hipLaunchKernelGGL(k_step_beta, dim3((n + 63) / 64), dim3(64), 0, st, beta_z, kappa_z, n);
 }
 
-void launch_round_state(size_t n, float2* f, float* rho, float* t, hipStream_t st) {
-    hipLaunchKernelGGL(k_round_state, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, f, rho, t);
+void launch_round_state(size_t npix, int batch, float2* f, float* rho, float* t, const double* beta_z,
+                        hipStream_t st) {
+    const size_t n = npix * (size_t)batch;
+    hipLaunchKernelGGL(k_round_state, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, npix, batch, f,
+                       rho, t, beta_z);
 }
 
 __global__ void k_set_beta(double* beta_z, double* kappa_z, int z0, int n, double beta, double kappa) {

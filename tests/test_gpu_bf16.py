@@ -4,8 +4,10 @@ storage, and the accuracy each reaches against the FP64 oracle.
 DECT_STORAGE_BF16 stores the projector operands (search direction, residual
 and line-search sinograms) in BF16; DECT_STORAGE_BF16_STATE also rounds the
 state images f1, f2, rho_e, t' to BF16 after every write.  BF16 keeps 8
-significant bits, so a stored value is within 2^-8 of its FP32 value
-(relative, round to nearest: the unit roundoff)."""
+significant bits: rounded to nearest (the direction) a stored value is within
+2^-8 of its FP32 value (relative, the unit roundoff); the quantities that
+accumulate small updates (residual sinograms, state images) are rounded
+stochastically, within one BF16 ulp (2^-7 relative) and unbiased."""
 import os
 
 import numpy as np
@@ -73,7 +75,23 @@ def test_bf16_state_set_state_stores_rounded_values():
     sol.set_state(cuda(pL[None]), cuda(pH[None]), *(cuda(a[None]) for a in imgs), k=0)
     for a, ref in zip((host(x)[0] for x in sol.state()), imgs):
         assert is_bf16(a)
-        assert np.abs(a - ref).max() <= U_BF16 * np.abs(ref).max()
+        # stochastic rounding: within one ulp, below 2 U |x| for every x
+        assert np.all(np.abs(a - ref) <= 2 * U_BF16 * np.abs(ref))
+
+
+def test_bf16_state_rounding_is_unbiased():
+    """A constant state between two BF16 values, 1 + 2^-10 (an eighth of the
+    way from 1 to the next value, 1 + 2^-7): nearest rounding would store 1
+    everywhere and lose the difference; stochastic rounding stores the upper
+    value at about an eighth of the pixels, so the mean is kept."""
+    g, ph, pL, pH = workload("small")
+    c = 1.0 + 2.0 ** -10
+    imgs = [np.full((g.n_y, g.n_x), c) for _ in range(4)]
+    sol = dect.Solver(g, dect.default_params(n_iter=4, storage=dect.DECT_STORAGE_BF16_STATE))
+    sol.set_state(cuda(pL[None]), cuda(pH[None]), *(cuda(a[None]) for a in imgs), k=0)
+    for a in (host(x)[0] for x in sol.state()):
+        assert set(np.unique(a)) <= {1.0, 1.0 + 2.0 ** -7}
+        assert abs(a.mean() - c) <= 1e-4
 
 
 def test_bf16_batch_equals_single():
@@ -109,17 +127,22 @@ def report(tag, a):
     print(tag + ": " + ", ".join(f"{k}={v:.3g}" for k, v in a.items()))
 
 
-# The FP32 path's tolerances are |dZ| <= 0.02 and rel rho_e <= 1e-3.  With
-# BF16 operand storage the insert means stay within |dZ| 0.02 and reach rel
-# rho_e of about 1e-3 on the 512^2 slice (0.96e-3 to 1.0e-3 as the rounding
-# order of the projector changes): at the tolerance, not safely inside it.
-# Pointwise a few per cent of pixels exceed the tolerances (the residuals
-# lose bits the converged iterate depends on).  BF16 state storage exceeds
-# them almost everywhere (an update below half a BF16 ulp of the iterate is
-# rounded away, so the iteration stalls near its start).  The tests pin the
-# operand mode's insert means at twice the rho_e tolerance, so that a change
-# of rounding order does not flip the verdict, and record the figures.
+# Bounds fixed before the runs they judge.  Insert means (2-pixel eroded
+# regions) must meet the FP32 path's tolerances themselves: |dZ| <= 0.02 and
+# rel rho_e <= 1e-3.  Pointwise, BF16 storage cannot: its resolution is the
+# bound.  With BF16 operands the state is FP32 and the residuals lose what
+# their rounding drops, so p99 rel rho_e <= 2^-8 (half a BF16 ulp).  With the
+# state in BF16, rho_e itself is a stored BF16 value (within one ulp after
+# stochastic rounding): p99 rel rho_e <= 2^-7, and p99 |dZ| <= 0.05 (two ulps
+# of t' at the largest insert Z of 14, through Z = Zw t'^(1/m)).
 TOL_Z, TOL_RHO = 0.02, 1e-3
+P99_RHO = {1: 2.0 ** -8, 2: 2.0 ** -7}
+P99_Z = {1: TOL_Z, 2: 0.05}
+
+
+def check_bf16(a, storage):
+    assert a["insert_mean_dz"] <= TOL_Z and a["insert_mean_drho"] <= TOL_RHO
+    assert a["p99_drho"] <= P99_RHO[storage] and a["p99_dz"] <= P99_Z[storage]
 
 
 @pytest.mark.parametrize("storage", [1, 2])
@@ -130,9 +153,7 @@ def test_bf16_small_against_oracle(storage):
                                            dect.default_params(n_iter=10, storage=storage)))
     a = accuracy(Z, R, Zr, Rr, ph, g)
     report(f"storage={storage} small K=10", a)
-    assert np.isfinite(Z).all() and np.isfinite(R).all()
-    if storage == dect.DECT_STORAGE_BF16:
-        assert a["insert_mean_dz"] <= TOL_Z and a["insert_mean_drho"] <= 2 * TOL_RHO
+    check_bf16(a, storage)
 
 
 @pytest.mark.parametrize("storage", [1, 2])
@@ -143,6 +164,4 @@ def test_bf16_slice512_against_stored_oracle(storage):
                                            dect.default_params(n_iter=50, storage=storage)))
     a = accuracy(Z, R, gold["Z"].astype(np.float64), gold["rho"].astype(np.float64), ph, g)
     report(f"storage={storage} slice512 K=50", a)
-    assert np.isfinite(Z).all() and np.isfinite(R).all()
-    if storage == dect.DECT_STORAGE_BF16:
-        assert a["insert_mean_dz"] <= TOL_Z and a["insert_mean_drho"] <= 2 * TOL_RHO
+    check_bf16(a, storage)
