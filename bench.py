@@ -152,8 +152,9 @@ def tune(args, sol, lo, hi, default_mode):
 
 
 def bench_uneven(args):
-    """64 uneven slices, 50 iterations each: batched by image size against one
-    slice at a time; a step solves all 64 slices."""
+    """64 uneven slices of mixed image sizes, 50 iterations each: one handle
+    for the whole batch (one uneven-batch solver per image size, iterated
+    together) against one slice at a time; a step solves all 64 slices."""
     import multiprocessing as mp
     import torch
     from paper_2308_01290_amd import dect
@@ -163,52 +164,55 @@ def bench_uneven(args):
         data = pool.map(_uneven_slice, range(n_slices))
     params = dect.default_params(n_iter=N_ITER)
     dev = torch.device("cuda:0")
+    geoms = [d[0] for d in data]
     groups = {}
-    for i, (g, pL, pH) in enumerate(data):
+    for i, g in enumerate(geoms):
         groups.setdefault(g.n_x, []).append(i)
-    batched = []
-    for n, idx in sorted(groups.items()):
-        geoms = [data[i][0] for i in idx]
-        lo = dect.concat_sinograms([torch.as_tensor(data[i][1], device=dev) for i in idx])
-        hi = dect.concat_sinograms([torch.as_tensor(data[i][2], device=dev) for i in idx])
-        batched.append((dect.Solver(geoms, params), lo, hi))
+    lo = dect.concat_sinograms([torch.as_tensor(d[1], device=dev) for d in data])
+    hi = dect.concat_sinograms([torch.as_tensor(d[2], device=dev) for d in data])
+    batch = dect.UnevenSolver(geoms, params)
     single = []
     for g, pL, pH in data:
         single.append((dect.Solver(g, params), torch.as_tensor(pL[None], device=dev),
                        torch.as_tensor(pH[None], device=dev)))
+    t_tune = 0.0
+    if (args.schedule or "autotune") == "autotune":
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        batch.autotune(lo, hi, iters=4, reps=3)
+        torch.cuda.synchronize()
+        t_tune = time.perf_counter() - t0
+    schedules = [batch.schedule(q) for q in range(batch.groups())]
 
-    schedules, t_tune = [], 0.0
-    for sol, lo, hi in batched:
-        sc, dt = tune(args, sol, lo, hi, "autotune")
-        schedules.append(sc)
-        t_tune += dt
+    def run_batch():
+        batch.init(lo, hi)
+        batch.iterate(N_ITER)
+        return batch.finish()
 
-    def run(solvers):
+    def run_single():
         out = []
-        for sol, lo, hi in solvers:
-            sol.init(lo, hi)
+        for sol, a, b in single:
+            sol.init(a, b)
             sol.iterate(N_ITER)
             out.append(sol.finish())
         return out
 
-    def timed(solvers, steps, warmup):
+    def timed(fn, steps, warmup):
         for _ in range(warmup):
-            run(solvers)
+            fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            res = run(solvers)
+            res = fn()
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps, res
 
-    t_b, res_b = timed(batched, args.steps, args.warmup)
-    t_s, res_s = timed(single, max(1, args.steps // 2), 1)
+    t_b, (Zb, Rb) = timed(run_batch, args.steps, args.warmup)
+    t_s, res_s = timed(run_single, max(1, args.steps // 2), 1)
     # the batch must give each slice's own result
     same = True
-    for (n, idx), (Zb, Rb) in zip(sorted(groups.items()), res_b):
-        for j, i in enumerate(idx):
-            Zs, Rs = res_s[i]
-            same = same and bool(torch.equal(Zb[j], Zs[0])) and bool(torch.equal(Rb[j], Rs[0]))
+    for i, (z, r) in enumerate(zip(dect.split_images(Zb, geoms), dect.split_images(Rb, geoms))):
+        same = same and bool(torch.equal(z, res_s[i][0][0])) and bool(torch.equal(r, res_s[i][1][0]))
     out = {
         "metric": "uneven batch slices/s (64 slices, 256-512^2, 360-984 views, 50 iters)",
         "value": n_slices / t_b, "unit": "slices/s", "n_gpus": 1, "steps": args.steps,

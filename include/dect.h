@@ -367,6 +367,39 @@ int dect_solve_multi(const float* sino_lo, const float* sino_hi, const dect_geom
                      const dect_params* p, float* Z_out, float* rho_out, int32_t batch, void* ws,
                      size_t ws_bytes, hipStream_t stream);
 
+/* ---- batches of mixed image sizes ------------------------------------------
+ * One handle for a batch of slices whose image grids differ too (n_x, n_y,
+ * pixel_mm), as in a batch of 256^2, 384^2 and 512^2 slices.  Slices of one
+ * image grid form a group that runs as one uneven batch (every launch of an
+ * iteration covers the whole group, see dect_solver_create_multi); an
+ * iteration enqueues the work of every group before it waits for any group's
+ * PCG stopping flags, so the groups overlap on the device.  Every slice's
+ * result equals its solve alone (dect_solve of that slice), bit for bit.
+ * Sinograms: slices back to back in the order of geoms (slice z starts at
+ * element sum_{z'<z} n_views(z') n_det(z')); images likewise (slice z at
+ * element sum_{z'<z} n_x(z') n_y(z')).  All DEVICE, caller-owned; init reads
+ * the sinograms during its enqueued work only.  The library allocates each
+ * group's workspace (stream-ordered on `stream`).  Errors as for the solver
+ * calls; parameters are shared (n_iter is used by dect_solve_uneven only). */
+typedef struct dect_uneven dect_uneven;
+int dect_uneven_create(const dect_geometry* geoms, int32_t batch, const dect_params* p,
+                       hipStream_t stream, dect_uneven** out);
+int dect_uneven_destroy(dect_uneven* u);
+/* Number of image-grid groups (HOST pointer). */
+int dect_uneven_groups(const dect_uneven* u, int32_t* n_groups);
+int dect_uneven_init(dect_uneven* u, const float* sino_lo, const float* sino_hi);
+int dect_uneven_iterate(dect_uneven* u, int32_t n);
+int dect_uneven_finish(dect_uneven* u, float* Z_out, float* rho_out);
+/* dect_solver_autotune on each group (iters, reps as there; the inputs as
+ * for dect_uneven_init), and each group's chosen schedule. */
+int dect_uneven_autotune(dect_uneven* u, const float* sino_lo, const float* sino_hi, int32_t iters,
+                         int32_t reps);
+int dect_uneven_get_schedule(const dect_uneven* u, int32_t group, dect_schedule* out);
+/* Whole solve of such a batch: create, init, n_iter iterations, finish, destroy. */
+int dect_solve_uneven(const float* sino_lo, const float* sino_hi, const dect_geometry* geoms,
+                      const dect_params* p, float* Z_out, float* rho_out, int32_t batch,
+                      hipStream_t stream);
+
 /* ---- image-domain form ----------------------------------------------------
  * Algorithm 1 on attenuation images instead of sinograms: the data terms of
  * objective (10) are eta_i*||C_k1 f1 + C_k2 f2 - mu_k||^2 for the two

@@ -1411,8 +1411,12 @@ static int one_iteration_image(dect_solver* s, bool more) {
 // So the host's wait for the PCG stopping flags overlaps the next
 // back-projection.  Events order every hand-over between the streams; the
 // iteration after one with `more` starts with its back-projection queued.
-static int one_iteration(dect_solver* s, bool more = false) {
-    if (s->image) return one_iteration_image(s, more);
+// The iteration in two halves: iter_enqueue puts all of its work on the
+// streams (the PCG's first chunk included) and returns; iter_complete waits
+// for the PCG's stopping flags, enqueues further chunks while needed and
+// finishes the iteration.  Several solvers can have their halves interleaved
+// (enqueue all, then complete each) so that their work overlaps on the device.
+static int iter_enqueue(dect_solver* s, bool more) {
     const Geom& g = s->g;
     const Resolved& R = s->rp;
     const double beta = s->beta;
@@ -1503,6 +1507,14 @@ static int one_iteration(dect_solver* s, bool more = false) {
     s->upd_pending = two;
     if (!chunk_first)
         if (int rc = t_step_chunk(s, ms)) return rc;
+    return DECT_OK;
+}
+
+static int iter_complete(dect_solver* s, bool more) {
+    const Resolved& R = s->rp;
+    const bool two = s->side != nullptr;
+    const hipStream_t ms = two ? s->pst : s->st;
+    const hipStream_t rs = two && s->rst && s->sched.rho_stream ? s->rst : nullptr;
     if (int rc = t_step_finish(s, ms)) return rc;
     // ms: beta^(k+1) once the side work and the rho_e step have read beta^(k)
     if (two) DECT_HIP(hipStreamWaitEvent(ms, s->ev_side, 0));
@@ -1523,6 +1535,12 @@ static int one_iteration(dect_solver* s, bool more = false) {
     s->k += 1;
     DECT_HIP(hipGetLastError());
     return DECT_OK;
+}
+
+static int one_iteration(dect_solver* s, bool more = false) {
+    if (s->image) return one_iteration_image(s, more);
+    if (int rc = iter_enqueue(s, more)) return rc;
+    return iter_complete(s, more);
 }
 
 int dect_solver_iterate(dect_solver* s, int32_t n) {
@@ -1711,6 +1729,190 @@ int dect_solve_multi(const float* lo, const float* hi, const dect_geometry* geom
     if (!rc) rc = dect_solver_iterate(s, p->n_iter);
     if (!rc) rc = dect_solver_finish(s, Z, rho);
     dect_solver_destroy(s);
+    return rc;
+}
+
+// ---- uneven batches of mixed image sizes ------------------------------------
+// The slices are grouped by image grid (n_x, n_y, pixel_mm); each group is an
+// uneven-batch solver whose launches cover all of its slices.  An iteration
+// enqueues every group's work before it waits for any group's PCG stopping
+// flags, so the groups' kernels overlap on the device.
+struct dect_uneven {
+    std::vector<dect_solver*> grp;
+    std::vector<std::vector<int>> members;    // per group: slice indices, ascending
+    std::vector<long long> sino0, img0;       // per slice: offsets in the caller's arrays
+    std::vector<long long> gsino;             // per group: its sinogram elements
+    std::vector<size_t> gimg;                 // per group: its image elements
+    std::vector<Geom> g;                      // per slice
+    hipStream_t st = nullptr;
+    int batch = 0;
+};
+
+static void uneven_free(dect_uneven* u) {
+    if (!u) return;
+    for (dect_solver* s : u->grp) dect_solver_destroy(s);
+    delete u;
+}
+
+int dect_uneven_create(const dect_geometry* geoms, int32_t batch, const dect_params* p, hipStream_t st,
+                       dect_uneven** out) {
+    if (!out) return fail(DECT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!geoms || !p || batch < 1) return fail(DECT_EINVAL, "dect_uneven_create: bad arguments");
+    dect_uneven* u = new dect_uneven();
+    u->st = st;
+    u->batch = batch;
+    u->g.resize(batch);
+    u->sino0.resize(batch);
+    u->img0.resize(batch);
+    long long so = 0, io = 0;
+    for (int z = 0; z < batch; ++z) {
+        if (int rc = resolve_geometry(&geoms[z], &u->g[z])) {
+            uneven_free(u);
+            return rc;
+        }
+        u->sino0[z] = so;
+        u->img0[z] = io;
+        so += (long long)u->g[z].nv * u->g[z].nd;
+        io += (long long)u->g[z].nx * u->g[z].ny;
+    }
+    // groups in order of first appearance
+    for (int z = 0; z < batch; ++z) {
+        int gi = -1;
+        for (size_t q = 0; q < u->members.size() && gi < 0; ++q) {
+            const Geom& a = u->g[u->members[q][0]];
+            if (a.nx == u->g[z].nx && a.ny == u->g[z].ny && a.dx == u->g[z].dx) gi = (int)q;
+        }
+        if (gi < 0) {
+            gi = (int)u->members.size();
+            u->members.emplace_back();
+        }
+        u->members[gi].push_back(z);
+    }
+    for (const auto& m : u->members) {
+        std::vector<dect_geometry> gs;
+        long long ns = 0;
+        for (int z : m) {
+            gs.push_back(geoms[z]);
+            ns += (long long)u->g[z].nv * u->g[z].nd;
+        }
+        dect_solver* s = nullptr;
+        if (int rc = dect_solver_create_multi(gs.data(), p, (int32_t)gs.size(), nullptr, 0, st, &s)) {
+            uneven_free(u);
+            return rc;
+        }
+        u->grp.push_back(s);
+        u->gsino.push_back(ns);
+        u->gimg.push_back((size_t)u->g[m[0]].nx * u->g[m[0]].ny * m.size());
+    }
+    *out = u;
+    return DECT_OK;
+}
+
+int dect_uneven_destroy(dect_uneven* u) {
+    uneven_free(u);
+    return DECT_OK;
+}
+
+int dect_uneven_groups(const dect_uneven* u, int32_t* n_groups) {
+    if (!u || !n_groups) return fail(DECT_EINVAL, "dect_uneven_groups: bad arguments");
+    *n_groups = (int32_t)u->grp.size();
+    return DECT_OK;
+}
+
+// a group's sinograms back to back (the order dect_solver_init reads)
+static int gather_group(dect_uneven* u, size_t q, const float* lo, const float* hi, TempBuf* buf) {
+    if (int rc = temp_alloc(buf, 2 * sizeof(float) * (size_t)u->gsino[q], u->st)) return rc;
+    float* dlo = static_cast<float*>(buf->p);
+    float* dhi = dlo + u->gsino[q];
+    long long o = 0;
+    for (int z : u->members[q]) {
+        const size_t n = (size_t)u->g[z].nv * u->g[z].nd;
+        DECT_HIP(hipMemcpyAsync(dlo + o, lo + u->sino0[z], n * sizeof(float), hipMemcpyDeviceToDevice, u->st));
+        DECT_HIP(hipMemcpyAsync(dhi + o, hi + u->sino0[z], n * sizeof(float), hipMemcpyDeviceToDevice, u->st));
+        o += (long long)n;
+    }
+    return DECT_OK;
+}
+
+int dect_uneven_init(dect_uneven* u, const float* lo, const float* hi) {
+    if (!u || !lo || !hi) return fail(DECT_EINVAL, "dect_uneven_init: NULL argument");
+    for (size_t q = 0; q < u->grp.size(); ++q) {
+        TempBuf buf;   // stream-ordered: freed after the init's enqueued reads
+        if (int rc = gather_group(u, q, lo, hi, &buf)) return rc;
+        const float* dlo = static_cast<const float*>(buf.p);
+        if (int rc = dect_solver_init(u->grp[q], dlo, dlo + u->gsino[q])) return rc;
+    }
+    return DECT_OK;
+}
+
+int dect_uneven_iterate(dect_uneven* u, int32_t n) {
+    if (!u || n < 0) return fail(DECT_EINVAL, "dect_uneven_iterate: bad arguments");
+    for (int i = 0; i < n; ++i) {
+        const bool more = i + 1 < n;
+        int rc = DECT_OK;
+        for (dect_solver* s : u->grp)
+            if (!rc) rc = iter_enqueue(s, more);
+        for (dect_solver* s : u->grp)
+            if (!rc) rc = iter_complete(s, more);
+        if (rc) {
+            for (dect_solver* s : u->grp) {
+                leave_iter(s);
+                s->upd_pending = s->bp_pending = false;
+            }
+            return rc;
+        }
+    }
+    return DECT_OK;
+}
+
+int dect_uneven_finish(dect_uneven* u, float* Z, float* rho_e) {
+    if (!u || (!Z && !rho_e)) return fail(DECT_EINVAL, "dect_uneven_finish: bad arguments");
+    for (size_t q = 0; q < u->grp.size(); ++q) {
+        TempBuf buf;
+        if (int rc = temp_alloc(&buf, 2 * sizeof(float) * u->gimg[q], u->st)) return rc;
+        float* gz = static_cast<float*>(buf.p);
+        float* gr = gz + u->gimg[q];
+        if (int rc = dect_solver_finish(u->grp[q], gz, gr)) return rc;
+        size_t o = 0;
+        for (int z : u->members[q]) {
+            const size_t n = (size_t)u->g[z].nx * u->g[z].ny;
+            if (Z) DECT_HIP(hipMemcpyAsync(Z + u->img0[z], gz + o, n * sizeof(float), hipMemcpyDeviceToDevice, u->st));
+            if (rho_e)
+                DECT_HIP(hipMemcpyAsync(rho_e + u->img0[z], gr + o, n * sizeof(float), hipMemcpyDeviceToDevice, u->st));
+            o += n;
+        }
+    }
+    return DECT_OK;
+}
+
+int dect_uneven_autotune(dect_uneven* u, const float* lo, const float* hi, int32_t iters, int32_t reps) {
+    if (!u || !lo || !hi) return fail(DECT_EINVAL, "dect_uneven_autotune: NULL argument");
+    for (size_t q = 0; q < u->grp.size(); ++q) {
+        TempBuf buf;
+        if (int rc = gather_group(u, q, lo, hi, &buf)) return rc;
+        const float* dlo = static_cast<const float*>(buf.p);
+        if (int rc = dect_solver_autotune(u->grp[q], dlo, dlo + u->gsino[q], iters, reps, nullptr, nullptr))
+            return rc;
+    }
+    return DECT_OK;
+}
+
+int dect_uneven_get_schedule(const dect_uneven* u, int32_t group, dect_schedule* out) {
+    if (!u || group < 0 || group >= (int32_t)u->grp.size())
+        return fail(DECT_EINVAL, "dect_uneven_get_schedule: bad group");
+    return dect_solver_get_schedule(u->grp[group], out);
+}
+
+int dect_solve_uneven(const float* lo, const float* hi, const dect_geometry* geoms, const dect_params* p,
+                      float* Z, float* rho_e, int32_t batch, hipStream_t st) {
+    if (!lo || !hi || (!Z && !rho_e)) return fail(DECT_EINVAL, "dect_solve_uneven: NULL array");
+    dect_uneven* u = nullptr;
+    if (int rc = dect_uneven_create(geoms, batch, p, st, &u)) return rc;
+    int rc = dect_uneven_init(u, lo, hi);
+    if (!rc) rc = dect_uneven_iterate(u, p->n_iter);
+    if (!rc) rc = dect_uneven_finish(u, Z, rho_e);
+    dect_uneven_destroy(u);
     return rc;
 }
 

@@ -62,6 +62,9 @@ EXPORTS = [
     "dect_engine_workspace_bytes", "dect_engine_create", "dect_engine_destroy", "dect_engine_admit",
     "dect_engine_step", "dect_engine_step_n", "dect_engine_status", "dect_engine_completed",
     "dect_engine_cancel",
+    "dect_uneven_create", "dect_uneven_destroy", "dect_uneven_groups", "dect_uneven_init",
+    "dect_uneven_iterate", "dect_uneven_finish", "dect_uneven_autotune", "dect_uneven_get_schedule",
+    "dect_solve_uneven",
     "dect_image_workspace_bytes", "dect_image_solver_create", "dect_image_solver_init",
     "dect_image_solver_set_state", "dect_solve_image",
     "dect_last_error",
@@ -129,6 +132,15 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.dect_engine_step_n.argtypes = [vp, i32, P(i32)]
     L.dect_engine_status.argtypes = [vp, P(i32), P(i32)]
     L.dect_engine_cancel.argtypes = [vp, i32]
+    L.dect_uneven_create.argtypes = [G, i32, Pp, vp, P(vp)]
+    L.dect_uneven_destroy.argtypes = [vp]
+    L.dect_uneven_groups.argtypes = [vp, P(i32)]
+    L.dect_uneven_init.argtypes = [vp, vp, vp]
+    L.dect_uneven_iterate.argtypes = [vp, i32]
+    L.dect_uneven_finish.argtypes = [vp, vp, vp]
+    L.dect_uneven_autotune.argtypes = [vp, vp, vp, i32, i32]
+    L.dect_uneven_get_schedule.argtypes = [vp, i32, P(_Schedule)]
+    L.dect_solve_uneven.argtypes = [vp, vp, G, Pp, vp, vp, i32, vp]
     L.dect_engine_completed.argtypes = [vp, P(i32), i32, P(i32)]
     L.dect_image_workspace_bytes.argtypes = [i32, i32, Pp, i32]
     L.dect_image_workspace_bytes.restype = C.c_size_t
@@ -611,6 +623,108 @@ def solve_multi(sino_lo, sino_hi, geoms, params=None, stream=None):
     R = torch.empty_like(Z)
     _check(lib().dect_solve_multi(_ptr(sino_lo), _ptr(sino_hi), arr, C.byref(p), _ptr(Z), _ptr(R), b,
                                   None, 0, C.c_void_p(_stream(stream))), "dect_solve_multi")
+    return Z, R
+
+
+def image_elements(geoms) -> int:
+    """Length of the back-to-back images of a batch of mixed image sizes."""
+    return sum(int(Geometry.of(g).n_x) * int(Geometry.of(g).n_y) for g in geoms)
+
+
+def split_images(flat, geoms):
+    """[n_y, n_x] views of the slices' back-to-back images."""
+    out, o = [], 0
+    for g in geoms:
+        g = Geometry.of(g)
+        n = int(g.n_x) * int(g.n_y)
+        out.append(flat[o:o + n].view(int(g.n_y), int(g.n_x)))
+        o += n
+    return out
+
+
+class UnevenSolver:
+    """A batch of slices of mixed image sizes (and views, bins, detectors): one
+    uneven-batch solver per image grid, iterated together (see include/dect.h).
+    Sinograms and images go back to back in slice order."""
+
+    def __init__(self, geoms, params=None, device="cuda", stream=None):
+        self.params = params if params is not None else default_params()
+        self.geoms, arr = _geometry_array(geoms)
+        self.batch = len(self.geoms)
+        self.device = device
+        h = C.c_void_p()
+        _check(lib().dect_uneven_create(arr, self.batch, C.byref(self.params),
+                                        C.c_void_p(_stream(stream)), C.byref(h)), "dect_uneven_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dect_uneven_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def groups(self) -> int:
+        n = C.c_int32()
+        _check(lib().dect_uneven_groups(self._h, C.byref(n)), "dect_uneven_groups")
+        return int(n.value)
+
+    def _check_sinos(self, lo, hi):
+        n = sinogram_elements(self.geoms)
+        for name, t in (("sino_lo", lo), ("sino_hi", hi)):
+            _dev_f32(t, (t.shape[-1],), name)
+            if t.numel() != n:
+                raise ValueError(f"{name} has {t.numel()} elements, the batch needs {n}")
+
+    def init(self, lo, hi):
+        self._check_sinos(lo, hi)
+        _check(lib().dect_uneven_init(self._h, _ptr(lo), _ptr(hi)), "dect_uneven_init")
+        return self
+
+    def iterate(self, n: int = 1):
+        _check(lib().dect_uneven_iterate(self._h, int(n)), "dect_uneven_iterate")
+        return self
+
+    def finish(self):
+        """(Z, rho_e): back-to-back images (see split_images)."""
+        torch = _torch()
+        n = image_elements(self.geoms)
+        Z = torch.empty(n, device=self.device, dtype=torch.float32)
+        R = torch.empty_like(Z)
+        _check(lib().dect_uneven_finish(self._h, _ptr(Z), _ptr(R)), "dect_uneven_finish")
+        return Z, R
+
+    def autotune(self, lo, hi, iters: int = 4, reps: int = 3):
+        self._check_sinos(lo, hi)
+        _check(lib().dect_uneven_autotune(self._h, _ptr(lo), _ptr(hi), int(iters), int(reps)),
+               "dect_uneven_autotune")
+        return [self.schedule(q) for q in range(self.groups())]
+
+    def schedule(self, group: int):
+        sc = _Schedule()
+        _check(lib().dect_uneven_get_schedule(self._h, int(group), C.byref(sc)), "dect_uneven_get_schedule")
+        return {k: getattr(sc, k) for k in SCHEDULE_KEYS}
+
+
+def solve_uneven(sino_lo, sino_hi, geoms, params=None, stream=None):
+    """Whole solve of a batch of mixed image sizes -> (Z, rho_e) back to back."""
+    torch = _torch()
+    gs, arr = _geometry_array(geoms)
+    p = params if params is not None else default_params()
+    n = sinogram_elements(gs)
+    for name, t in (("sino_lo", sino_lo), ("sino_hi", sino_hi)):
+        _dev_f32(t, (t.shape[-1],), name)
+        if t.numel() != n:
+            raise ValueError(f"{name} has {t.numel()} elements, the batch needs {n}")
+    m = image_elements(gs)
+    Z = torch.empty(m, device=sino_lo.device, dtype=torch.float32)
+    R = torch.empty_like(Z)
+    _check(lib().dect_solve_uneven(_ptr(sino_lo), _ptr(sino_hi), arr, C.byref(p), _ptr(Z), _ptr(R),
+                                   len(gs), C.c_void_p(_stream(stream))), "dect_solve_uneven")
     return Z, R
 
 

@@ -41,16 +41,27 @@ def f32(x):
     return np.asarray(x, dtype=np.float32).astype(np.float64)
 
 
+OUT_DIR = [HERE]
+
+
 def save(name, Z, R, dt, n_iter, **meta):
-    out = os.path.join(HERE, name)
+    out = os.path.join(OUT_DIR[0], name)
     np.savez_compressed(out, Z=Z.astype(np.float32), rho=R.astype(np.float32),
                         seconds=np.float64(dt), n_iter=np.int32(n_iter), **meta)
     print(f"wrote {out} in {dt:.1f} s", flush=True)
 
 
 def sino_case(name, g, pL, pH, n_iter, threads, phys, **meta):
+    """The oracle's solve (init, n_iter iterations, output), one progress line
+    per iteration."""
     t0 = time.time()
-    Z, R = S.solve(f32(pL), f32(pH), g, phys, S.Params(n_iter=n_iter), nthreads=threads or None)
+    a, b = f32(pL), f32(pH)
+    params = S.Params(n_iter=n_iter).resolved(phys, g)
+    st = S.init_state(a, b, g, phys, params, threads or None)
+    for k in range(n_iter):
+        st = S.iterate(st, a, b, g, phys, params, threads or None)
+        print(f"{name}: iteration {k + 1}/{n_iter} ({time.time() - t0:.0f} s)", flush=True)
+    Z, R = S.finalize(st, phys, params)
     save(name, Z, R, time.time() - t0, n_iter, **meta)
 
 
@@ -73,21 +84,35 @@ def uneven(args, phys):
         sino_case(f"uneven_{seed}_K50.npz", g, pL, pH, 50, args.threads, phys, seed=np.int32(seed))
 
 
+def served_one(args, phys, n, seed, views):
+    g, ph, pL, pH = P.slice_served(n, seed, phys.mu_pair, n_views=views)
+    sino_case(f"served_{n}_{views}_K{SERVED_K}.npz", g, pL, pH, SERVED_K, args.threads, phys,
+              seed=np.int32(seed))
+
+
 def served(args, phys):
     for n, seed, views in SERVED:
-        g, ph, pL, pH = P.slice_served(n, seed, phys.mu_pair, n_views=views)
-        sino_case(f"served_{n}_{views}_K{SERVED_K}.npz", g, pL, pH, SERVED_K, args.threads, phys,
-                  seed=np.int32(seed))
+        served_one(args, phys, n, seed, views)
+
+
+def uneven_one(args, phys, seed):
+    g, ph, pL, pH = P.slice_uneven(seed, phys.mu_pair)
+    sino_case(f"uneven_{seed}_K50.npz", g, pL, pH, 50, args.threads, phys, seed=np.int32(seed))
 
 
 MODES = {"slice512": slice512, "image512": image512, "uneven": uneven, "served": served}
+MODES.update({f"uneven{seed}": (lambda a, p, s=seed: uneven_one(a, p, s)) for seed in UNEVEN_SEEDS})
+MODES.update({f"served{n}": (lambda a, p, c=(n, seed, v): served_one(a, p, *c)) for n, seed, v in SERVED})
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("modes", nargs="+", choices=sorted(MODES))
     ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--out-dir", default=HERE, help="where the .npz files go")
     args = ap.parse_args()
+    OUT_DIR[0] = args.out_dir
+    os.makedirs(args.out_dir, exist_ok=True)
     phys = Physics()
     for m in args.modes:
         MODES[m](args, phys)

@@ -18,10 +18,10 @@ Modes (each is one 50-iteration solve, 15-25 minutes on 8 cores):
     noise EF ET  after every outer iteration f1, f2, rho_e times
                  (1 + EF * N(0, 1)) and t' times (1 + ET * N(0, 1))
 
-    python tests/golden/oracle_envelope.py fp32 nearest [--json]
+    python tests/golden/oracle_envelope.py fp32 nearest [--json[=PATH]]
 
---json records the fractions in slice512_envelope.json under the mode's
-name.  The GPU end-to-end tests allow a fraction of body pixels past each
+--json records the fractions in slice512_envelope.json (or PATH) under the
+mode's name.  The GPU end-to-end tests allow a fraction of body pixels past each
 bar of twice the larger of the two fp32 realisations (nearest, zero): the
 GPU rounds at every operation, not only the stored iterate, and the factor
 two is fixed here, before any GPU result is compared with it.
@@ -69,7 +69,7 @@ def t_step_gpu_rule(st, phys, params):
     return t
 
 
-def run(mode, args, write_json):
+def run(mode, args, json_path):
     phys = Physics()
     g, ph, pL, pH = P.workload_slice512(phys.mu_pair)
     a = pL.astype(np.float32).astype(np.float64)
@@ -109,10 +109,10 @@ def run(mode, args, write_json):
     fz, fr = e2e.fractions(v)
     tag = " ".join([mode] + list(args))
     print(f"{tag}: {v}; fractions z/t' {fz:.3g} rho {fr:.3g}", flush=True)
-    if write_json:
-        data = json.load(open(ENVELOPE_JSON)) if os.path.exists(ENVELOPE_JSON) else {}
+    if json_path:
+        data = json.load(open(json_path)) if os.path.exists(json_path) else {}
         data[tag] = dict(v, z_t_fraction=fz, rho_fraction=fr)
-        with open(ENVELOPE_JSON, "w") as fh:
+        with open(json_path, "w") as fh:
             json.dump(data, fh, indent=1, sort_keys=True)
 
 
@@ -125,5 +125,7 @@ def allowed_fractions():
 
 
 if __name__ == "__main__":
-    argv = [x for x in sys.argv[1:] if x != "--json"]
-    run(argv[0], argv[1:], "--json" in sys.argv)
+    argv = [x for x in sys.argv[1:] if not x.startswith("--json")]
+    js = [x for x in sys.argv[1:] if x.startswith("--json")]
+    path = (js[0].split("=", 1)[1] if "=" in js[0] else ENVELOPE_JSON) if js else None
+    run(argv[0], argv[1:], path)

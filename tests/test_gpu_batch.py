@@ -83,3 +83,33 @@ def test_grid_sizes_of_the_multigrid_paths(n):
         Z1, R1 = (host(x)[0] for x in dect.solve(cuda(pL[None]), cuda(pH[None]), g, params))
         assert np.array_equal(Zb[z], Z1) and np.array_equal(Rb[z], R1), (n, z)
         assert np.isfinite(Z1).all() and (R1 > 0.5).mean() > 0.05
+
+
+def test_mixed_image_sizes_equal_each_alone():
+    """A batch of mixed image sizes (64^2, 96^2, 64^2, 96x48) through one
+    handle: the groups iterate together, and every slice's maps equal its solve
+    alone bit for bit; the outputs go back to back in slice order."""
+    phys = Physics()
+    specs = [(64, 64, 90, 120, 0.0), (96, 96, 120, 160, 0.3), (64, 64, 80, 100, -0.2), (96, 48, 70, 128, 0.1)]
+    geoms, los, his = [], [], []
+    for i, (nx, ny, v, d, off) in enumerate(specs):
+        g = P.FanGeometry(n_x=nx, n_y=ny, pixel_mm=1.0, n_views=v, n_det=d, sid_mm=800.0,
+                          sdd_mm=1200.0, det_offset_mm=off, angle0_rad=0.05 * i).resolved()
+        ph = P.phantom_disk_inserts(seed=210 + i, radius=0.3 * min(nx, ny), n_inserts=2,
+                                    semi=(0.04 * min(nx, ny), 0.08 * min(nx, ny)))
+        pL, pH = P.analytic_sinograms(ph, g, phys.mu_pair)
+        geoms.append(g)
+        los.append(cuda(P.poisson_log(pL, 1e5, 220 + i).astype(np.float32)))
+        his.append(cuda(P.poisson_log(pH, 1e5, 230 + i).astype(np.float32)))
+    K = 4
+    params = dect.default_params(n_iter=K)
+    sol = dect.UnevenSolver(geoms, params)
+    assert sol.groups() == 3
+    lo, hi = dect.concat_sinograms(los), dect.concat_sinograms(his)
+    Z, R = sol.init(lo, hi).iterate(K).finish()
+    Zs, Rs = dect.split_images(Z, geoms), dect.split_images(R, geoms)
+    Z2, R2 = dect.solve_uneven(lo, hi, geoms, params)
+    assert np.array_equal(host(Z2), host(Z)) and np.array_equal(host(R2), host(R))
+    for i, g in enumerate(geoms):
+        Z1, R1 = (host(x)[0] for x in dect.solve(los[i][None], his[i][None], g, params))
+        assert np.array_equal(host(Zs[i]), Z1) and np.array_equal(host(Rs[i]), R1), i

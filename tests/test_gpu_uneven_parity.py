@@ -78,25 +78,22 @@ def test_served_geometry_first_iteration_matches_oracle(n, seed, views):
 
 
 def test_uneven_batch_matches_stored_oracle():
-    """The four slices solved as the uneven-batch path runs them: slices of
-    one image size together in one uneven batch (both 384^2 slices in one
-    launch per kernel and iteration), 50 iterations."""
-    cases = {seed: uneven_case(seed) for seed in UNEVEN_SEEDS}
-    groups = {}
-    for seed, c in cases.items():
-        groups.setdefault(c[1].n_x, []).append(seed)
-    assert sorted(len(v) for v in groups.values()) == [1, 1, 2]
-    for n, seeds in groups.items():
-        geoms = [cases[s][1] for s in seeds]
-        lo = dect.concat_sinograms([cuda(cases[s][3]) for s in seeds])
-        hi = dect.concat_sinograms([cuda(cases[s][4]) for s in seeds])
-        Z, R = dect.solve_multi(lo, hi, geoms, dect.default_params(n_iter=50))
-        Z, R = host(Z), host(R)
-        for i, s in enumerate(seeds):
-            Zr, Rr, K = gold(f"uneven_{s}_K50.npz")
-            assert K == 50
-            phys, g, ph, _, _ = cases[s]
-            check_end_to_end(Z[i], R[i], Zr, Rr, ph, g, f"uneven {s} ({n}^2, batch of {len(seeds)})")
+    """The four slices solved as the uneven-batch path runs them: one handle
+    for the mixed image sizes (both 384^2 slices in one launch per kernel and
+    iteration, the three image-size groups iterated together), 50 iterations."""
+    cases = [uneven_case(seed) for seed in UNEVEN_SEEDS]
+    geoms = [c[1] for c in cases]
+    lo = dect.concat_sinograms([cuda(c[3]) for c in cases])
+    hi = dect.concat_sinograms([cuda(c[4]) for c in cases])
+    sol = dect.UnevenSolver(geoms, dect.default_params(n_iter=50))
+    assert sol.groups() == 3
+    Z, R = sol.init(lo, hi).iterate(50).finish()
+    Zs, Rs = dect.split_images(Z, geoms), dect.split_images(R, geoms)
+    for i, (seed, (phys, g, ph, _, _)) in enumerate(zip(UNEVEN_SEEDS, cases)):
+        Zr, Rr, K = gold(f"uneven_{seed}_K50.npz")
+        assert K == 50
+        check_end_to_end(host(Zs[i]), host(Rs[i]), Zr, Rr, ph, g,
+                         f"uneven {seed} ({g.n_x}^2, {g.n_views}x{g.n_det})")
 
 
 def test_served_requests_match_stored_oracle():

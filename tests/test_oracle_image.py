@@ -193,3 +193,21 @@ def test_noise_free_inserts_recovered():
             assert abs(Ri.mean() - e.rho_e) <= 0.02 * e.rho_e, (seed, e)
             assert abs(Zi.mean() - e.Z) <= 0.35, (seed, e)
 
+
+
+def test_stored_image512_result_is_physical():
+    """The stored 512^2 image-domain result (make_golden.py image512, oracle
+    only) is a bounded solution: water rho_e within 3% of 1, water Z within
+    0.5 of 7.42, and no pixel with |rho_e| above 2.5 (the inserts reach 1.7)."""
+    import os
+    from scipy.ndimage import binary_erosion
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "image512_K50.npz")
+    gold = np.load(path)
+    phys = Physics()
+    g = P.geometry_slice512()
+    ph = P.phantom_body_inserts(2308)
+    water = binary_erosion(P.label_map(ph, g)[1] > 0.999, iterations=2)
+    R, Z = gold["rho"].astype(np.float64), gold["Z"].astype(np.float64)
+    assert np.abs(R).max() < 2.5
+    assert abs(R[water].mean() - 1.0) <= 0.03
+    assert abs(Z[water].mean() - phys.Zw) <= 0.5
