@@ -32,7 +32,8 @@
  *   pixel (row i, column k) is the half-open square
  *     [x0 + k*dx, x0 + (k+1)*dx) x [y0 + i*dx, y0 + (i+1)*dx),
  *     x0 = -nx*dx/2, y0 = -ny*dx/2;
- *   view v: theta = angle0 + v*arc/nv, source S = sid*(cos, sin);
+ *   view v: theta = angle0 + v*arc/nv, source S = sid*(cos, sin) (exact at
+ *   multiples of 90 degrees);
  *   detector centre -(sdd - sid)*(cos, sin), axis e = (-sin, cos);
  *   bin j centre: u_j = (j - (nd-1)/2)*pitch + offset along e;
  *   ray (v, j) = line from S to the bin centre.
@@ -54,9 +55,27 @@ typedef struct {
     double pitch, offset, sid, sdd;
 } OraGeom;
 
+/* cos and sin of view angle th; at an exact multiple of 90 degrees (to 1e-12
+ * rad) the exact values, so that such a view's rays are exactly parallel to
+ * the grid and a ray on a grid line is decided by the half-open rule above,
+ * not by the rounding of cos(pi/2) etc. */
+static void view_cos_sin(double th, double *c, double *s) {
+    const double q = th / (0.5 * M_PI);
+    const double qr = floor(q + 0.5);
+    if (fabs(q - qr) * (0.5 * M_PI) < 1e-12) {
+        const long k = ((long)qr % 4 + 4) % 4;
+        *c = k == 0 ? 1.0 : (k == 2 ? -1.0 : 0.0);
+        *s = k == 1 ? 1.0 : (k == 3 ? -1.0 : 0.0);
+        return;
+    }
+    *c = cos(th);
+    *s = sin(th);
+}
+
 static void ray_of(const OraGeom *g, int v, int j, double S[2], double Q[2]) {
     double th = g->angle0 + (double)v * (g->arc / (double)g->nv);
-    double c = cos(th), s = sin(th);
+    double c, s;
+    view_cos_sin(th, &c, &s);
     double u = ((double)j - 0.5 * (double)(g->nd - 1)) * g->pitch + g->offset;
     S[0] = g->sid * c;
     S[1] = g->sid * s;

@@ -1162,8 +1162,8 @@ int dect_solver_init(dect_solver* s, const float* lo, const float* hi) {
     for (int z = 0; z < s->batch;) {   // one FBP per run of slices with the same geometry
         int e = z + 1;
         while (e < s->batch && B.uniq[e] == B.uniq[z]) ++e;
-        launch_fbp(B.g[z], lo + B.sino0[z], e - z, s->fbpq, s->muL + z * npix, s->st);
-        launch_fbp(B.g[z], hi + B.sino0[z], e - z, s->fbpq, s->muH + z * npix, s->st);
+        launch_fbp_pair(B.g[z], lo + B.sino0[z], hi + B.sino0[z], e - z, s->fbpq, s->muL + z * npix,
+                        s->muH + z * npix, s->st);
         z = e;
     }
     launch_init_state(s->M, g.ny, g.nx, s->batch, s->muL, s->muH, (float)s->rp.p.rho_min, s->f,
@@ -2236,8 +2236,7 @@ int dect_engine_admit(dect_engine* e, const dect_geometry* gin, const float* lo,
     launch_set_desc(const_cast<SliceDesc*>(s->tab.desc), z, d, st);
     // FBP start and closed forms for this slot only
     float* q = reinterpret_cast<float*>(s->zq + s0);
-    launch_fbp(g, lo, 1, q, s->muL + z * npix, st);
-    launch_fbp(g, hi, 1, q, s->muH + z * npix, st);
+    launch_fbp_pair(g, lo, hi, 1, q, s->muL + z * npix, s->muH + z * npix, st);
     launch_init_state(s->M, g.ny, g.nx, 1, s->muL + z * npix, s->muH + z * npix,
                       (float)s->rp.p.rho_min, s->f + z * npix, s->rho + z * npix, s->t + z * npix, st);
     // continuation schedule of this request (beta^(0) also seeds the rounding below)

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstddef>
 #include <cstdint>
 
@@ -35,10 +36,32 @@ int resolve_geometry(const dect_geometry* in, Geom* out);
 // the views: ray (v + r nv/4, j) takes the weights of ray (v, j) on the pixels
 // turned r times.  Its table holds the first nv/4 views only, and the
 // back-projector evaluates each weight once for four views.
+//
+// Not when a ray runs exactly along a grid line: a view at a multiple of 90
+// degrees whose detector has a bin centre straight across the isocentre (an
+// odd bin count on a centred detector) has its central ray on the grid line
+// through the centre (the side is even).  The chord of such a ray goes to one
+// pixel by the half-open rule, and a quarter turn does not preserve which
+// side of the line that is; those slices take the per-view projector.
+inline bool axis_ray_on_grid_line(const Geom& g) {
+    const double half_pi = 1.5707963267948966;
+    const double dth = g.arc / g.nv;
+    bool axis_view = false;
+    for (int r = 0; r < 4 && !axis_view; ++r) {
+        const double v = (r * half_pi - g.angle0) / dth;
+        const double vr = std::floor(v + 0.5);
+        axis_view = std::fabs(v - vr) < 1e-9 && vr >= 0.0 && vr < g.nv;
+    }
+    if (!axis_view) return false;
+    const double c = 0.5 * (g.nd - 1) - g.offset / g.pitch;   // bin index at u = 0
+    const double cr = std::floor(c + 0.5);
+    return std::fabs(c - cr) < 1e-9 && cr >= 0.0 && cr < g.nd;
+}
 inline bool sym4(const Geom& g) {
     const double two_pi = 6.283185307179586;
     return g.nx == g.ny && g.nx % 32 == 0 && g.nv >= 4 && g.nv % 4 == 0 &&
-           g.arc > two_pi * (1.0 - 1e-12) && g.arc < two_pi * (1.0 + 1e-12);
+           g.arc > two_pi * (1.0 - 1e-12) && g.arc < two_pi * (1.0 + 1e-12) &&
+           !axis_ray_on_grid_line(g);
 }
 inline int table_views(const Geom& g) { return sym4(g) ? g.nv / 4 : g.nv; }
 // Transpose symmetry on top of the quarter turns: with the detector centred
@@ -203,6 +226,9 @@ void launch_backproject(const Geom& g, const RayTable& t, const void* sino, int 
 
 // ---- FBP ---------------------------------------------------------------------
 // q = filtered sinograms (scratch, [nsino][nv][nd]); img [nsino][ny][nx]
+// both sinograms of nsino slices of one geometry; q: scratch of 2*nsino*nv*nd floats
+void launch_fbp_pair(const Geom& g, const float* sino_a, const float* sino_b, int nsino, float* q,
+                     float* img_a, float* img_b, hipStream_t st);
 void launch_fbp(const Geom& g, const float* sino, int nsino, float* q, float* img,
                 hipStream_t st);
 

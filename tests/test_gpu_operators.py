@@ -18,6 +18,7 @@ PROJ_TOL = 1e-5
 
 def geoms():
     return {
+        "gridline_offset": gridline_offset(),
         "small": P.geometry_small(),
         "ragged": ragged_geometry(),
         # square grid, side a multiple of 32, views a multiple of 4: the
@@ -33,10 +34,25 @@ def geoms():
         # one tile orbit, four views (nv/4 = 1: view 0 only)
         "octo_tiny": P.FanGeometry(n_x=32, n_y=32, pixel_mm=1.0, n_views=4, n_det=48, sid_mm=300.0,
                                    sdd_mm=450.0).resolved(),
+        # rays exactly on a grid line: an odd bin count on a centred detector
+        # puts the central ray of the views at 0, 90, 180, 270 degrees on the
+        # line through the centre (the half-open rule decides its pixel); and a
+        # half-bin detector offset with an even count does the same off the
+        # transpose symmetry
+        "gridline_odd": P.FanGeometry(n_x=64, n_y=64, pixel_mm=1.0, n_views=32, n_det=95, sid_mm=500.0,
+                                      sdd_mm=800.0).resolved(),
     }
 
 
-SYM = ["quarter", "octo_odd", "octo_tiny"]
+def gridline_offset():
+    g = P.FanGeometry(n_x=64, n_y=64, pixel_mm=1.0, n_views=32, n_det=96, sid_mm=500.0,
+                      sdd_mm=800.0).resolved()
+    return P.FanGeometry(n_x=64, n_y=64, pixel_mm=1.0, n_views=32, n_det=96, sid_mm=500.0,
+                         sdd_mm=800.0, det_pitch_mm=g.det_pitch_mm,
+                         det_offset_mm=-0.5 * g.det_pitch_mm).resolved()
+
+
+SYM = ["quarter", "octo_odd", "octo_tiny", "gridline_odd", "gridline_offset"]
 
 
 @pytest.mark.parametrize("name", ["small", "ragged"] + SYM)

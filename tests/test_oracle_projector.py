@@ -31,13 +31,29 @@ def test_siddon_equals_bruteforce_clipping(geom):
 
 
 def test_rays_along_grid_lines_follow_half_open_rule():
-    """View 0 with an odd detector puts the central ray exactly on y = 0, the
-    boundary between rows n_y/2-1 and n_y/2: it belongs to row n_y/2 only."""
+    """An odd detector puts the central ray of the views at 0, 90, 180 and 270
+    degrees exactly on the line through the centre (y = 0 or x = 0), the
+    boundary between rows (columns) n/2-1 and n/2.  A pixel is the half-open
+    square [x, x + dx) x [y, y + dx), so the whole chord belongs to row n_y/2
+    (views 0 and 2) or column n_x/2 (views 1 and 3), one pixel length in each
+    of the four pixels along it."""
     g = tiny(nx=4, ny=4, nv=4, nd=5)
-    pix, ln = ops.ray_chords(g, 0, 2)
-    rows = sorted(set((pix // g.n_x).tolist()))
-    assert rows == [2]
-    assert abs(ln.sum() - 4.0) < 1e-12
+    for v in range(4):
+        pix, ln = ops.ray_chords(g, v, 2)
+        rows = sorted(set((pix // g.n_x).tolist()))
+        cols = sorted(set((pix % g.n_x).tolist()))
+        if v % 2 == 0:
+            assert rows == [2] and cols == [0, 1, 2, 3], v
+        else:
+            assert cols == [2] and rows == [0, 1, 2, 3], v
+        assert np.allclose(ln, 1.0, atol=1e-12), v
+    # a half-bin detector offset with an even count does the same
+    g2 = tiny(nx=4, ny=4, nv=4, nd=6)
+    g2 = tiny(nx=4, ny=4, nv=4, nd=6, offset=-0.5 * g2.det_pitch_mm)
+    for v in range(4):
+        pix, ln = ops.ray_chords(g2, v, 3)
+        sel = (pix // g2.n_x) if v % 2 == 0 else (pix % g2.n_x)
+        assert set(sel.tolist()) == {2} and np.allclose(ln, 1.0, atol=1e-12), v
     assert ops.clip_chord(g, 0, 2, 1, 0) == 0.0
     assert abs(ops.clip_chord(g, 0, 2, 2, 0) - 1.0) < 1e-12
 
