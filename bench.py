@@ -140,7 +140,10 @@ def _uneven_slice(i):
 
 
 def tune(args, sol, lo, hi, default_mode):
-    """Autotune `sol` on its inputs when asked; returns (schedule, seconds)."""
+    """Autotune `sol` on its inputs when asked, or apply --set; returns
+    (schedule, seconds)."""
+    if args.set:
+        sol.set_schedule(**dict((kv.split("=")[0], int(kv.split("=")[1])) for kv in args.set))
     if (args.schedule or default_mode) != "autotune":
         return sol.schedule(), 0.0
     import torch
@@ -355,9 +358,9 @@ def bench_image(args):
     value = args.steps / elapsed
     npix = g.n_x * g.n_y
     fs_avg_s = fs_ms / max(fs_n, 1) / 1e3
-    # algorithmic HBM bytes of one f-step (both closed forms): per basis, read
-    # f (8 B), mu_L, mu_H, rho_e, t' (16 B) and write f_i (4 B) per pixel
-    fs_bytes = 2 * 28 * npix
+    # algorithmic HBM bytes of one f-step (the joint 2x2 solve of both bases):
+    # per pixel read f (8 B), mu_L, mu_H, rho_e, t' (16 B) and write f (8 B)
+    fs_bytes = 32 * npix
     achieved = fs_bytes / fs_avg_s / 1e9
     out = {
         "metric": "512^2 image-domain solves/s (50 iters)",
@@ -419,6 +422,8 @@ def main():
                     help="launch schedule of the timed solvers: the library default, or the one "
                          "the library's autotuner picks on the workload before the warmup "
                          "(default: autotune for uneven64, default otherwise)")
+    ap.add_argument("--set", nargs="*", default=[], metavar="KEY=VALUE",
+                    help="slice512 / image512: schedule fields (dect_schedule) set before timing")
     ap.add_argument("--rates", default="20,50,100,200", help="serve: arrival rates (req/s)")
     ap.add_argument("--requests", type=int, default=96, help="serve: requests per rate")
     ap.add_argument("--served-requests", type=int, default=48,

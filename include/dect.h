@@ -288,11 +288,12 @@ int dect_solver_stats(const dect_solver* s, int32_t* k, int32_t* last_pcg_iters)
 /* Launch schedule of a solver's outer iterations.  Every choice changes only
  * how the work is mapped onto the device, never an operation or its
  * summation order, so results are bit-identical under every schedule.
- *   fp_rays_per_lane  forward projection of square quarter-turn symmetric
- *                     slices: 4 = each lane steps one table ray and sums its
- *                     four turned rays; 1 = one ray per lane (the kernel of
- *                     the general case).  Batches with a slice of neither
- *                     symmetry always use 1.
+ *   fp_rays_per_lane  line-search forward projection of square quarter-turn
+ *                     symmetric slices: 4 = each lane steps one table ray
+ *                     and sums its four turned rays; 1 = one ray per lane
+ *                     (the kernel of the general case).  Slices of neither
+ *                     symmetry always take 1, in a launch of their own when
+ *                     the batch mixes the two kinds.
  *   bp_cu_percent     workgroups of the symmetric back-projectors as a
  *                     percentage of the CUs (0 = automatic: half the CUs up
  *                     to one tile orbit per CU, all CUs beyond; else 10..400)
@@ -303,13 +304,20 @@ int dect_solver_stats(const dect_solver* s, int32_t* k, int32_t* last_pcg_iters)
  *   pcg_chunk_extra   PCG iterations enqueued in the first chunk beyond the
  *                     previous outer iteration's count (0..8); the device
  *                     stopping test makes extra iterations free of effect
- * A new solver starts with {4, 0, 1, 0, 0}. */
+ *   pcg_chunk_first   order in which the host enqueues an outer iteration
+ *                     once the previous one's back-projection is queued:
+ *                     1 = the PCG's first chunk, then the f-step and rho_e
+ *                     work; 0 = the PCG's set-up, then the f-step and rho_e
+ *                     work, then the chunk (the f-step's kernels then need not
+ *                     wait for the host to enqueue the chunk)
+ * A new solver starts with {4, 0, 1, 0, 0, 1}. */
 typedef struct dect_schedule {
     int32_t fp_rays_per_lane;
     int32_t bp_cu_percent;
     int32_t rho_stream;
     int32_t graphs;
     int32_t pcg_chunk_extra;
+    int32_t pcg_chunk_first;
 } dect_schedule;
 
 /* Read or replace the schedule (DECT_EINVAL for a NULL argument or a value

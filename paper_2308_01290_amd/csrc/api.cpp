@@ -638,7 +638,7 @@ struct dect_solver {
         hipGraphExec_t exec;
     };
     std::vector<ChunkGraph> chunk_graphs;
-    dect_schedule sched{4, 0, 1, 0, 0};   // launch schedule (dect_solver_set_schedule)
+    dect_schedule sched{4, 0, 1, 0, 0, 1};   // launch schedule (dect_solver_set_schedule)
     // optional kernel timing: event pairs in launch order
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -843,7 +843,7 @@ int dect_project(const dect_geometry* gin, const float* img, float* sino, int32_
     ProjArgs a;
     a.out = sino;
     a.nout = batch;
-    a.sym_all = sym4(g);
+    a.four_ray = sym4(g);
     launch_project(g, P, t, pad, np, PROJ_PLAIN, a, st);
     DECT_HIP(hipGetLastError());
     return DECT_OK;
@@ -1141,7 +1141,8 @@ static void project_residual(dect_solver* s, const float* lo, const float* hi) {
     a.c10 = (float)s->M.C[1][0];
     a.c11 = (float)s->M.C[1][1];
     a.res_bf16 = s->storage != DECT_STORAGE_FP32;
-    a.sym_all = !(s->geo.kinds & kSlicePlain);
+    a.four_ray = (s->geo.kinds & ~kSlicePlain) != 0;
+    a.has_plain = (s->geo.kinds & kSlicePlain) != 0;
     launch_project(s->g, P, s->tab, s->dpad, s->batch, PROJ_RESID, a, s->st);
 }
 
@@ -1446,7 +1447,7 @@ static int iter_enqueue(dect_solver* s, bool more) {
     // iterations), the PCG's first chunk is enqueued first: the side stream
     // has that much work ahead while the host enqueues the chunk, and the PCG
     // does not wait behind the host's side enqueues
-    const bool chunk_first = two && s->bp_pending;
+    const bool chunk_first = two && s->bp_pending && s->sched.pcg_chunk_first;
     if (chunk_first)
         if (int rc = t_step_chunk(s, ms)) return rc;
     // side: f-step and rho_e step (t'^(k), beta^(k) from the previous iteration on ms)
@@ -1482,7 +1483,8 @@ static int iter_enqueue(dect_solver* s, bool more) {
     pa.alpha = s->alpha;
     pa.counter = s->cnt_proj;
     pa.pad_bf16 = pa.res_bf16 = a.bf16;
-    pa.sym_all = !(s->geo.kinds & kSlicePlain) && s->sched.fp_rays_per_lane == 4;
+    pa.four_ray = (s->geo.kinds & ~kSlicePlain) != 0 && s->sched.fp_rays_per_lane == 4;
+    pa.has_plain = (s->geo.kinds & kSlicePlain) != 0;
     hipEvent_t t1 = mark(s, side);
     launch_project(g, P, s->tab, dir, s->batch, PROJ_LINESEARCH, pa, side);
     mark_end(s, side, t1, s->ev_fp);
@@ -1594,7 +1596,8 @@ static bool schedule_ok(const dect_schedule& c) {
     return (c.fp_rays_per_lane == 1 || c.fp_rays_per_lane == 4) &&
            (c.bp_cu_percent == 0 || (c.bp_cu_percent >= 10 && c.bp_cu_percent <= 400)) &&
            (c.rho_stream == 0 || c.rho_stream == 1) && (c.graphs == 0 || c.graphs == 1) &&
-           c.pcg_chunk_extra >= 0 && c.pcg_chunk_extra <= 8;
+           c.pcg_chunk_extra >= 0 && c.pcg_chunk_extra <= 8 &&
+           (c.pcg_chunk_first == 0 || c.pcg_chunk_first == 1);
 }
 
 int dect_solver_get_schedule(const dect_solver* s, dect_schedule* out) {
@@ -1653,13 +1656,14 @@ int dect_solver_autotune(dect_solver* s, const float* lo, const float* hi, int32
     // the knobs that matter for this solver
     std::vector<std::pair<int32_t dect_schedule::*, std::vector<int32_t>>> knobs;
     if (!s->image) {
-        if (!(s->geo.kinds & kSlicePlain)) knobs.push_back({&dect_schedule::fp_rays_per_lane, {4, 1}});
+        if (s->geo.kinds & ~kSlicePlain) knobs.push_back({&dect_schedule::fp_rays_per_lane, {4, 1}});
         if (s->geo.kinds & (kSliceQuarter | kSliceOcto))
             knobs.push_back({&dect_schedule::bp_cu_percent, {0, 25, 50, 75, 100}});
         if (s->rst) knobs.push_back({&dect_schedule::rho_stream, {1, 0}});
     }
     knobs.push_back({&dect_schedule::graphs, {0, 1}});
     knobs.push_back({&dect_schedule::pcg_chunk_extra, {0, 1, 2}});
+    if (!s->image) knobs.push_back({&dect_schedule::pcg_chunk_first, {1, 0}});
     dect_schedule best = start;
     double tbest = 0.0;
     int rc = measure(best, &tbest);
@@ -2262,7 +2266,7 @@ int dect_engine_admit(dect_engine* e, const dect_geometry* gin, const float* lo,
     a.c10 = (float)s->M.C[1][0];
     a.c11 = (float)s->M.C[1][1];
     a.res_bf16 = s->storage != DECT_STORAGE_FP32;
-    a.sym_all = sym4(g);
+    a.four_ray = sym4(g);
     launch_project(g, P, tz, s->dpad + z * P.pair, 1, PROJ_RESID, a, st);
     launch_set_int(s->active_d + z, 1, st);
     DECT_HIP(hipGetLastError());

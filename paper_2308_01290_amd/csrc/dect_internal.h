@@ -204,9 +204,15 @@ struct ProjArgs {
     // (RESID, LINESEARCH); LINESEARCH also reads BF16 pair blocks
     bool res_bf16 = false;
     bool pad_bf16 = false;
-    // every slice of the launch is quarter-turn symmetric: one lane per
-    // table ray produces its four turned rays (k_project4)
-    bool sym_all = false;
+    // four_ray: the quarter-turn symmetric slices take the four-ray form
+    // (k_project4: one lane per table ray produces its four turned rays);
+    // has_plain: the batch also holds slices of neither symmetry, which then
+    // take the per-view form (k_project) in a second launch.  Both forms give
+    // a slice's rays bit for bit alike.
+    bool four_ray = false;
+    bool has_plain = false;
+    bool plain_only = false;     // (set by launch_project) k_project skips symmetric slices
+    size_t part_stride = 0;      // (set by launch_project) partials per slice
 };
 int proj_nblocks(int nv_max, int nd_max);  // blocks per pair
 // pad: float2 pair blocks, or with a.pad_bf16 one 32-bit BF16 pair per entry

@@ -282,7 +282,9 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
     s = t;
 }
 
-int proj_nblocks(int nv, int nd) { return ((nd + 255) / 256) * nv; }
+// line-search partials per slice: blocks of 256 bins times views rounded up
+// to a multiple of 4 (the four-ray form's grid), the same stride in both forms
+int proj_nblocks(int nv, int nd) { return ((nd + 255) / 256) * ((nv + 3) & ~3); }
 
 // the two minor entries of one major step: float2 (f1, f2) per pixel, or one
 // 32-bit word of two BF16 values per pixel
@@ -306,13 +308,19 @@ __device__ __forceinline__ void store_res(float2* res, long long i, float x, flo
 }
 
 // PB: the pair blocks hold BF16 pairs; RB: the output sinogram pairs are BF16
+// Both forward-projector forms compute every value exactly as written (no
+// contraction of the epilogue's products into fused multiply-adds, which the
+// compiler could otherwise choose differently in the two kernels), so that a
+// symmetric slice's rays are the same bit for bit in either form.
 template <int MODE, bool PB, bool RB>
 __global__ __launch_bounds__(256) void k_project(const void* __restrict__ pad, PadLayout P,
                                                  RayTable T, int nx, int ny, ProjArgs a) {
+#pragma clang fp contract(off)
     constexpr unsigned ES = PB ? 4u : 8u;   // bytes per pixel entry
     constexpr int LS = PB ? 2 : 3;
     const int v = blockIdx.y, z = blockIdx.z;
     const SliceDesc D = T.desc[T.desc_stride * z];
+    if (a.plain_only && D.sym) return;   // block-uniform: k_project4 takes this slice
     const int nd = D.nd;
     const int j = blockIdx.x * 256 + threadIdx.x;
     const bool valid = j < nd && v < D.nv;   // the grid covers the batch's largest slice
@@ -432,7 +440,7 @@ __global__ __launch_bounds__(256) void k_project(const void* __restrict__ pad, P
         if (v >= D.nv || (int)blockIdx.x >= nbx) return;
         const int nblk = nbx * D.nv;
         const int bid = v * nbx + blockIdx.x;
-        double* zp = a.partials + (size_t)z * gridDim.x * gridDim.y;
+        double* zp = a.partials + (size_t)z * a.part_stride;
         const double bs = block_sum<256>(part, sh);
         if (threadIdx.x == 0) zp[bid] = bs;
         if (last_block_arrive(a.counter + z, (unsigned)nblk)) {
@@ -460,6 +468,7 @@ __global__ __launch_bounds__(256) void k_project(const void* __restrict__ pad, P
 template <int MODE, bool PB, bool RB>
 __global__ __launch_bounds__(256) void k_project4(const void* __restrict__ pad, PadLayout P,
                                                   RayTable T, int n, ProjArgs a) {
+#pragma clang fp contract(off)
     constexpr unsigned ES = PB ? 4u : 8u;
     constexpr int LS = PB ? 2 : 3;
     const int vt = blockIdx.y, z = blockIdx.z;
@@ -578,7 +587,7 @@ __global__ __launch_bounds__(256) void k_project4(const void* __restrict__ pad, 
         const int nbx = (nd + 255) / 256;
         if ((int)blockIdx.x >= nbx) return;
         const int nblk = nbx * D.nv;
-        double* zp = a.partials + (size_t)z * gridDim.x * gridDim.y * 4;
+        double* zp = a.partials + (size_t)z * a.part_stride;
 #pragma unroll
         for (int rot = 0; rot < 4; ++rot) {
             const double bs = block_sum<256>(part[rot], sh);
@@ -600,8 +609,11 @@ __global__ __launch_bounds__(256) void k_project4(const void* __restrict__ pad, 
 }
 
 void launch_project(const Geom& g, const PadLayout& P, const RayTable& t, const void* pad, int npairs,
-                    int mode, const ProjArgs& a, hipStream_t st) {
-    if (a.sym_all && P.rev) {
+                    int mode, const ProjArgs& a_in, hipStream_t st) {
+    ProjArgs a = a_in;
+    a.part_stride = (size_t)proj_nblocks(t.nv_max, t.nd_max);
+    a.plain_only = false;
+    if (a.four_ray && P.rev) {
         dim3 grid4((t.nd_max + 255) / 256, (t.nv_max + 3) / 4, npairs);
         if (mode == PROJ_PLAIN)
             hipLaunchKernelGGL((k_project4<PROJ_PLAIN, false, false>), grid4, dim3(256), 0, st, pad, P, t,
@@ -618,7 +630,8 @@ void launch_project(const Geom& g, const PadLayout& P, const RayTable& t, const 
         else
             hipLaunchKernelGGL((k_project4<PROJ_LINESEARCH, false, false>), grid4, dim3(256), 0, st, pad,
                                P, t, g.nx, a);
-        return;
+        if (!a.has_plain) return;
+        a.plain_only = true;   // the other slices in the per-view form
     }
     dim3 grid((t.nd_max + 255) / 256, t.nv_max, npairs);
     if (mode == PROJ_PLAIN)

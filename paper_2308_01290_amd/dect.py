@@ -43,7 +43,8 @@ class _Params(C.Structure):
 
 class _Schedule(C.Structure):
     _fields_ = [("fp_rays_per_lane", C.c_int32), ("bp_cu_percent", C.c_int32),
-                ("rho_stream", C.c_int32), ("graphs", C.c_int32), ("pcg_chunk_extra", C.c_int32)]
+                ("rho_stream", C.c_int32), ("graphs", C.c_int32), ("pcg_chunk_extra", C.c_int32),
+                ("pcg_chunk_first", C.c_int32)]
 
 
 SCHEDULE_KEYS = [f[0] for f in _Schedule._fields_]

@@ -113,3 +113,38 @@ def test_mixed_image_sizes_equal_each_alone():
     for i, g in enumerate(geoms):
         Z1, R1 = (host(x)[0] for x in dect.solve(los[i][None], his[i][None], g, params))
         assert np.array_equal(host(Zs[i]), Z1) and np.array_equal(host(Rs[i]), R1), i
+
+
+def test_mixed_symmetry_group_equals_each_alone():
+    """One image grid, slices of both projector kinds: an eight-fold symmetric
+    slice (even bin count, centred detector, views a multiple of 4), one whose
+    axis views put a central ray on a grid line (odd bin count) and one with
+    150 views (not a multiple of 4, the largest view count of the batch).  The
+    symmetric slice takes the four-ray projector and the others the per-view
+    one, in launches of their own; each slice equals its solve alone bit for
+    bit, also under the one-ray-per-lane schedule."""
+    phys = Physics()
+    specs = [(120, 160, 0.0), (96, 157, 0.0), (150, 176, 0.25)]   # views, bins, offset (mm)
+    geoms, los, his = [], [], []
+    for i, (v, d, off) in enumerate(specs):
+        g = P.FanGeometry(n_x=128, n_y=128, pixel_mm=1.0, n_views=v, n_det=d, sid_mm=800.0,
+                          sdd_mm=1200.0, det_offset_mm=off).resolved()
+        ph = P.phantom_disk_inserts(seed=240 + i, radius=40.0, n_inserts=3, semi=(5.0, 10.0))
+        pL, pH = P.analytic_sinograms(ph, g, phys.mu_pair)
+        geoms.append(g)
+        los.append(cuda(P.poisson_log(pL, 1e5, 250 + i).astype(np.float32)))
+        his.append(cuda(P.poisson_log(pH, 1e5, 260 + i).astype(np.float32)))
+    K = 5
+    params = dect.default_params(n_iter=K)
+    lo, hi = dect.concat_sinograms(los), dect.concat_sinograms(his)
+    alone = [tuple(host(x)[0] for x in dect.solve(los[i][None], his[i][None], g, params))
+             for i, g in enumerate(geoms)]
+    for sched in ({}, {"fp_rays_per_lane": 1}):
+        sol = dect.Solver(geoms, params)
+        if sched:
+            sol.set_schedule(**sched)
+        sol.init(lo, hi).iterate(K)
+        Z, R = (host(x) for x in sol.finish())
+        sol.close()
+        for i in range(len(geoms)):
+            assert np.array_equal(Z[i], alone[i][0]) and np.array_equal(R[i], alone[i][1]), (i, sched)

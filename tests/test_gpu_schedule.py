@@ -12,7 +12,7 @@ from tests.test_gpu_batch import uneven_inputs
 pytestmark = pytest.mark.gpu
 
 DEFAULT = {"fp_rays_per_lane": 4, "bp_cu_percent": 0, "rho_stream": 1, "graphs": 0,
-           "pcg_chunk_extra": 0}
+           "pcg_chunk_extra": 0, "pcg_chunk_first": 1}
 
 VARIANTS = [
     {"fp_rays_per_lane": 1},
@@ -22,7 +22,9 @@ VARIANTS = [
     {"rho_stream": 0},
     {"graphs": 1},
     {"pcg_chunk_extra": 3},
-    {"fp_rays_per_lane": 1, "bp_cu_percent": 10, "rho_stream": 0, "graphs": 1, "pcg_chunk_extra": 8},
+    {"pcg_chunk_first": 0},
+    {"fp_rays_per_lane": 1, "bp_cu_percent": 10, "rho_stream": 0, "graphs": 1, "pcg_chunk_extra": 8,
+     "pcg_chunk_first": 0},
 ]
 
 
@@ -102,7 +104,7 @@ def test_autotune_image_form():
 
 @pytest.mark.parametrize("bad", [{"fp_rays_per_lane": 2}, {"bp_cu_percent": 5},
                                  {"bp_cu_percent": 401}, {"rho_stream": 2}, {"graphs": -1},
-                                 {"pcg_chunk_extra": 9}])
+                                 {"pcg_chunk_extra": 9}, {"pcg_chunk_first": 2}])
 def test_schedule_values_out_of_range_rejected(bad):
     g, lo, hi = small_case()
     sol = dect.Solver(g, dect.default_params(n_iter=2))
