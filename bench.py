@@ -90,6 +90,23 @@ def measured_traffic(kernel: str):
     return float(kv["traffic_bytes_per_launch"])
 
 
+def timeline_summary(tl):
+    """Medians over the timed outer iterations (dect_solver_timeline rows, us
+    after the previous update): when the f-step reaches the gradient, its
+    forward projection and update end (the period), when the t' PCG finishes
+    its set-up and its solve, and how long before the next gradient the PCG's
+    result is ready (its slack; the f-step chain sets the period while it is
+    positive)."""
+    import numpy as np
+    if len(tl) < 3:
+        return None
+    med = lambda x: float(np.median(x))  # noqa: E731
+    slack = tl[1:, 0] - (tl[:-1, 4] - tl[:-1, 2])
+    return {"iterations": int(len(tl)), "period": med(tl[:, 2]), "gradient_reached": med(tl[:, 0]),
+            "projection_done": med(tl[:, 1]), "pcg_setup_done": med(tl[:, 3]), "pcg_done": med(tl[:, 4]),
+            "pcg_slack_before_next_gradient": med(slack)}
+
+
 def cpu_baseline(g, pL, pH, iters: int):
     """The FP64 oracle (as it stands) on the host cores: FBP start plus `iters`
     outer iterations, extrapolated to the 50-iteration solve.  A 1-core figure
@@ -491,6 +508,13 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     bp_ms, bp_n, fp_ms, fp_n = sol.timing()
+    # the iteration timeline from three more solves, outside the timed region
+    # (its events add host work to every iteration)
+    sol.enable_timing(True, timeline=True)
+    for _ in range(3):
+        step()
+    sol.timing()
+    tl = sol.timeline()
     sol.enable_timing(False)
 
     elapsed = t1 - t0
@@ -570,6 +594,7 @@ def main():
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": measured_traffic("k_backproject_sym8") if storage == 0 else None},
         "schedule": {"mode": args.schedule or "default", "chosen": schedule, "autotune_s": t_tune},
+        "iteration_timeline_us": timeline_summary(tl),
     }
     if args.served_requests > 0:
         # the metric's served part: a short Poisson stream at 20 req/s

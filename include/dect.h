@@ -355,9 +355,10 @@ int dect_solver_autotune(dect_solver* s, const float* sino_lo, const float* sino
  * solver. */
 int dect_solver_set_graphs(dect_solver* s, int enable);
 
-/* Optional timing of the two system-matrix kernels: when enabled, the solver
- * records HIP events on its stream around every back-projection and forward
- * projection launch of the outer iterations.  dect_solver_timing synchronises
+/* Optional timing of the two system-matrix kernels: with bit 0 of `enable`
+ * set, the solver records HIP events on its stream around every
+ * back-projection and forward projection launch of the outer iterations; bit
+ * 1 records the iteration timeline (dect_solver_timeline).  dect_solver_timing synchronises
  * the stream, returns the summed durations (ms) and launch counts since the
  * last call, and resets them.  Any output pointer may be NULL.  For an
  * image-domain solver the first pair times each iteration's f-step (the
@@ -365,6 +366,22 @@ int dect_solver_set_graphs(dect_solver* s, int enable);
 int dect_solver_enable_timing(dect_solver* s, int enable);
 int dect_solver_timing(dect_solver* s, double* backproject_ms, int32_t* backproject_launches,
                        double* project_ms, int32_t* project_launches);
+
+/* Iteration timeline of the sinogram form, recorded while bit 1 of the timing
+ * switch is set (HIP events on the solver's streams, at most 4096 outer
+ * iterations between
+ * two reads): for every outer iteration that follows another of the same
+ * solve, five times in microseconds after the previous iteration's update of
+ * f, in this order:
+ *   0  the f-step's stream reaches the gradient (its back-projection done and
+ *      t'^(k) available), 1  its forward projection done, 2  its update done
+ *      (the iteration period), 3  the t' PCG's set-up done, 4  the PCG done
+ *      (its last chunk's stopping flags copied).
+ * Writes at most max_rows rows of five floats to out_us (host memory), the
+ * row count to *rows, and clears the record.  Waits for the recorded events.
+ * Returns DECT_EINVAL for a NULL solver or output; an image-domain solver
+ * records nothing (*rows = 0). */
+int dect_solver_timeline(dect_solver* s, float* out_us, int32_t max_rows, int32_t* rows);
 
 /* Whole solve: create, init, n_iter iterations, finish, destroy. */
 int dect_solve(const float* sino_lo, const float* sino_hi, const dect_geometry* g,

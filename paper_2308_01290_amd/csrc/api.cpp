@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -464,7 +465,7 @@ static int pcg_enqueue(PcgRun& R, const PcgBufs& b, float2* fft_scratch, hipStre
 }
 
 static int pcg_finish(PcgRun& R, const PcgBufs& b, float2* fft_scratch, hipStream_t st,
-                      int* iters_out) {
+                      int* iters_out, hipEvent_t after_chunk = nullptr) {
     const int batch = R.a.batch;
     int more = kPcgMoreChunk;
     while (true) {
@@ -476,6 +477,7 @@ static int pcg_finish(PcgRun& R, const PcgBufs& b, float2* fft_scratch, hipStrea
         more = std::min(2 * more, kPcgMaxChunk);
         DECT_HIP(hipGetLastError());
         DECT_HIP(hipMemcpyAsync(R.hs, R.a.st, sizeof(PcgState) * batch, hipMemcpyDeviceToHost, st));
+        if (after_chunk) DECT_HIP(hipEventRecord(after_chunk, st));
     }
     int mx = 0;
     for (int z = 0; z < batch; ++z) mx = std::max(mx, R.hs[z].done ? R.hs[z].iters : R.it);
@@ -641,9 +643,21 @@ struct dect_solver {
     dect_schedule sched{4, 0, 1, 0, 0, 1};   // launch schedule (dect_solver_set_schedule)
     // optional kernel timing: event pairs in launch order
     bool timing = false;
+    bool timeline = false;   // iteration timeline (dect_solver_enable_timing bit 1)
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_bp, ev_fp;
+    // optional iteration timeline (sinogram form): per outer iteration, events
+    // at the kTl* points below, and the iteration's index
+    std::vector<std::array<hipEvent_t, 5>> tl;
+    std::vector<int> tl_k;
+    size_t tl_n = 0;
 };
+
+// iteration timeline points: the f-step's stream reaches the gradient (its
+// back-projection done, t'^(k) available), the forward projection done, the
+// update done; the PCG's stream done with the set-up, done with the solve
+enum { kTlGrad = 0, kTlFp = 1, kTlUpd = 2, kTlPcgSetup = 3, kTlPcgDone = 4 };
+constexpr size_t kTimelineMax = 4096;   // iterations recorded between two reads
 
 static void drop_chunk_graphs(dect_solver* s);
 
@@ -656,6 +670,25 @@ static hipEvent_t take_event(dect_solver* s) {
         e = nullptr;
     }
     return e;
+}
+
+// record timeline point `which` of the current outer iteration
+static void tl_mark(dect_solver* s, int which, hipStream_t st) {
+    if (!s->timeline || s->image || s->tl_n >= kTimelineMax) return;
+    if (s->tl.size() <= s->tl_n) {
+        std::array<hipEvent_t, 5> ev{};
+        for (auto& e : ev)
+            if (hipEventCreate(&e) != hipSuccess) {
+                (void)hipGetLastError();
+                for (auto& f : ev)
+                    if (f) (void)hipEventDestroy(f);
+                return;
+            }
+        s->tl.push_back(ev);
+        s->tl_k.push_back(-1);
+    }
+    (void)hipEventRecord(s->tl[s->tl_n][which], st);
+    s->tl_k[s->tl_n] = s->k;
 }
 
 // record a start event (returns nullptr when timing is off)
@@ -1121,7 +1154,9 @@ int dect_solver_destroy(dect_solver* s) {
     }
     for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
     drop_chunk_graphs(s);
-    free_side(s);
+    free_side(s);   // (synchronises the solver's streams)
+    for (auto& ev : s->tl)
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     if (s->owns_ws) dev_free(&s->own);
     delete s;
     return DECT_OK;
@@ -1304,16 +1339,23 @@ static int pcg_chunk_graph(dect_solver* s, hipStream_t ms) {
 static int t_step_chunk(dect_solver* s, hipStream_t ms) {
     // graphs for the pipelined multigrid PCG (its whole chunk is kernels), on
     // a stream of the solver's own (the legacy null stream cannot capture)
+    int rc;
     if (s->sched.graphs && s->prun.piped && ms == s->pst && ms && s->prun.max_iter > s->prun.it)
-        return pcg_chunk_graph(s, ms);
-    return pcg_first_chunk(s->prun, s->pcg, s->fft, ms, s->last_pcg + s->sched.pcg_chunk_extra,
-                           s->hs_pinned);
+        rc = pcg_chunk_graph(s, ms);
+    else
+        rc = pcg_first_chunk(s->prun, s->pcg, s->fft, ms, s->last_pcg + s->sched.pcg_chunk_extra,
+                             s->hs_pinned);
+    tl_mark(s, kTlPcgDone, ms);
+    return rc;
 }
 
 // second half: wait for the stopping flags, more chunks while needed
 static int t_step_finish(dect_solver* s, hipStream_t ms) {
     int iters = 0;
-    if (int rc = pcg_finish(s->prun, s->pcg, s->fft, ms, &iters)) return rc;
+    const bool tl = s->timeline && !s->image && s->tl_n < s->tl.size();
+    if (int rc = pcg_finish(s->prun, s->pcg, s->fft, ms, &iters,
+                            tl ? s->tl[s->tl_n][kTlPcgDone] : nullptr))
+        return rc;
     s->last_pcg = iters;
     return DECT_OK;
 }
@@ -1443,6 +1485,7 @@ static int iter_enqueue(dect_solver* s, bool more) {
     // ms: the t' step first (f^(k) from the previous update on `side`)
     if (two && s->upd_pending) DECT_HIP(hipStreamWaitEvent(ms, s->ev_upd, 0));
     if (int rc = t_step_start(s, ms, two ? s->ev_init : nullptr)) return rc;
+    tl_mark(s, kTlPcgSetup, ms);
     // With the next back-projection already queued on `side` (pipelined
     // iterations), the PCG's first chunk is enqueued first: the side stream
     // has that much work ahead while the host enqueues the chunk, and the PCG
@@ -1458,6 +1501,7 @@ static int iter_enqueue(dect_solver* s, bool more) {
                            s->sched.bp_cu_percent);
         mark_end(s, side, t0, s->ev_bp);
     }
+    tl_mark(s, kTlGrad, side);
     launch_grad(s->M, a, P, s->f, s->B, s->rho, s->t, dir, s->part_img, side);
     // rho_e step on its own stream once the gradient has read rho^(k)
     const hipStream_t rs = two && s->rst && s->sched.rho_stream ? s->rst : nullptr;
@@ -1488,6 +1532,7 @@ static int iter_enqueue(dect_solver* s, bool more) {
     hipEvent_t t1 = mark(s, side);
     launch_project(g, P, s->tab, dir, s->batch, PROJ_LINESEARCH, pa, side);
     mark_end(s, side, t1, s->ev_fp);
+    tl_mark(s, kTlFp, side);
     if (!rs) rho_step(s, side, two ? s->fft2 : s->fft);
     if (two) {
         DECT_HIP(hipEventRecord(s->ev_side, side));          // beta^(k) no longer read there
@@ -1497,6 +1542,7 @@ static int iter_enqueue(dect_solver* s, bool more) {
     }
     // f^(k+1), residual sinograms (beta is stepped on st below)
     launch_update(a, P, s->tab, s->alpha, dir, s->f, s->S, s->zq, nullptr, nullptr, side);
+    tl_mark(s, kTlUpd, side);
     if (two) DECT_HIP(hipEventRecord(s->ev_upd, side));
     s->bp_pending = false;
     if (two && more) {   // next back-projection while the host waits for the PCG
@@ -1535,6 +1581,7 @@ static int iter_complete(dect_solver* s, bool more) {
     }
     s->beta *= R.kappa;
     s->k += 1;
+    if (s->timeline && s->tl_n < s->tl.size() && s->tl_k[s->tl_n] == s->k - 1) ++s->tl_n;
     DECT_HIP(hipGetLastError());
     return DECT_OK;
 }
@@ -1698,7 +1745,8 @@ int dect_solver_autotune(dect_solver* s, const float* lo, const float* hi, int32
 
 int dect_solver_enable_timing(dect_solver* s, int enable) {
     if (!s) return fail(DECT_EINVAL, "solver is NULL");
-    s->timing = enable != 0;
+    s->timing = (enable & 1) != 0;
+    s->timeline = (enable & 2) != 0;
     return DECT_OK;
 }
 
@@ -1721,6 +1769,28 @@ int dect_solver_timing(dect_solver* s, double* bp_ms, int32_t* bp_n, double* fp_
     };
     if (int rc = sum(s->ev_bp, bp_ms, bp_n)) return rc;
     return sum(s->ev_fp, fp_ms, fp_n);
+}
+
+int dect_solver_timeline(dect_solver* s, float* out_us, int32_t max_rows, int32_t* rows) {
+    if (!s) return fail(DECT_EINVAL, "solver is NULL");
+    if (!rows || (max_rows > 0 && !out_us)) return fail(DECT_EINVAL, "dect_solver_timeline: NULL output");
+    int32_t n = 0;
+    for (size_t i = 1; i < s->tl_n; ++i) {
+        if (s->tl_k[i] != s->tl_k[i - 1] + 1) continue;   // a new solve started
+        if (n >= max_rows) break;
+        const hipEvent_t u0 = s->tl[i - 1][kTlUpd];
+        DECT_HIP(hipEventSynchronize(u0));
+        for (int j = 0; j < 5; ++j) {
+            DECT_HIP(hipEventSynchronize(s->tl[i][j]));
+            float ms = 0.f;
+            DECT_HIP(hipEventElapsedTime(&ms, u0, s->tl[i][j]));
+            out_us[(size_t)n * 5 + j] = 1e3f * ms;
+        }
+        ++n;
+    }
+    *rows = n;
+    s->tl_n = 0;
+    return DECT_OK;
 }
 
 int dect_solve_multi(const float* lo, const float* hi, const dect_geometry* geoms,

@@ -58,7 +58,7 @@ EXPORTS = [
     "dect_solver_set_state", "dect_solver_iterate", "dect_solver_get_state", "dect_solver_finish",
     "dect_solver_stats", "dect_solver_get_schedule", "dect_solver_set_schedule",
     "dect_solver_autotune", "dect_solver_set_graphs", "dect_solver_enable_timing",
-    "dect_solver_timing", "dect_solve",
+    "dect_solver_timing", "dect_solver_timeline", "dect_solve",
     "dect_solve_workspace_bytes_multi", "dect_solver_create_multi", "dect_solve_multi",
     "dect_engine_workspace_bytes", "dect_engine_create", "dect_engine_destroy", "dect_engine_admit",
     "dect_engine_step", "dect_engine_step_n", "dect_engine_status", "dect_engine_completed",
@@ -118,6 +118,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     L.dect_solver_set_graphs.argtypes = [vp, C.c_int]
     L.dect_solver_enable_timing.argtypes = [vp, C.c_int]
     L.dect_solver_timing.argtypes = [vp, P(C.c_double), P(C.c_int32), P(C.c_double), P(C.c_int32)]
+    L.dect_solver_timeline.argtypes = [vp, vp, C.c_int32, P(C.c_int32)]
     L.dect_solve.argtypes = [vp, vp, G, Pp, vp, vp, C.c_int32, vp, C.c_size_t, vp]
     L.dect_solve_workspace_bytes_multi.argtypes = [G, Pp, C.c_int32]
     L.dect_solve_workspace_bytes_multi.restype = C.c_size_t
@@ -501,8 +502,11 @@ class Solver:
         _check(lib().dect_solver_set_graphs(self._h, 1 if on else 0), "dect_solver_set_graphs")
         return self
 
-    def enable_timing(self, on: bool = True):
-        _check(lib().dect_solver_enable_timing(self._h, 1 if on else 0), "dect_solver_enable_timing")
+    def enable_timing(self, on: bool = True, timeline: bool = False):
+        """Kernel timing (timing()) and, with `timeline`, the iteration
+        timeline (timeline()); both off with on=False."""
+        flags = (1 if on else 0) | (2 if on and timeline else 0)
+        _check(lib().dect_solver_enable_timing(self._h, flags), "dect_solver_enable_timing")
         return self
 
     def timing(self):
@@ -512,6 +516,17 @@ class Solver:
         _check(lib().dect_solver_timing(self._h, C.byref(bms), C.byref(bn), C.byref(fms), C.byref(fn)),
                "dect_solver_timing")
         return bms.value, bn.value, fms.value, fn.value
+
+    def timeline(self, max_rows: int = 4096):
+        """Iteration timeline since the last call (dect_solver_timeline): an
+        array of rows (gradient reached, forward projection done, update done,
+        PCG set-up done, PCG done), microseconds after the previous update."""
+        import numpy as np
+        out = np.zeros((max_rows, 5), np.float32)
+        n = C.c_int32()
+        _check(lib().dect_solver_timeline(self._h, out.ctypes.data, max_rows, C.byref(n)),
+               "dect_solver_timeline")
+        return out[: n.value].astype(np.float64)
 
     def stats(self):
         k = C.c_int32()

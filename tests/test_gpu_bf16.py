@@ -151,16 +151,20 @@ def check_bf16(a, storage):
 #   2^-8 relative; from beta ~ 600 on the hard-threshold level lambda/beta falls
 #   below a squared step, so quantisation steps pass eq. (9) as edges and the
 #   relaxation keeps them: the state cannot settle below that.
-# * BF16 operands at 512^2: insert means off by 1.6e-3 in rho_e (bound 1e-3);
-#   the residual sinograms hold 8 significant bits of a small difference.
+# * BF16 operands at 512^2: the insert means' rho_e error is 0.7e-3 to 1.6e-3
+#   against the bound 1e-3, depending on the projectors' rounding order (the
+#   residual sinograms hold 8 significant bits of a small difference), so the
+#   case is borderline: it is expected to fail, and a pass is not an error.
 XFAIL_BF16 = {("small", 2), ("slice512", 1), ("slice512", 2)}
+BORDERLINE_BF16 = {("slice512", 1)}
 
 
 def bf16_case(size, storage):
     marks = []
     if (size, storage) in XFAIL_BF16:
-        marks.append(pytest.mark.xfail(strict=True, reason="BF16 storage misses the stated bound "
-                                                         "(figures in the design notes)"))
+        marks.append(pytest.mark.xfail(strict=(size, storage) not in BORDERLINE_BF16,
+                                       reason="BF16 storage misses the stated bound "
+                                              "(figures in the design notes)"))
     return pytest.param(storage, marks=marks, id=f"storage{storage}")
 
 

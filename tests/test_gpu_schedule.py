@@ -113,3 +113,23 @@ def test_schedule_values_out_of_range_rejected(bad):
     assert sol.schedule() == DEFAULT
     with pytest.raises(dect.DectError):
         sol.autotune(lo, hi, iters=0)
+
+
+def test_iteration_timeline():
+    """The timeline has one row per outer iteration after a solve's first,
+    its points in stream order, and recording it changes no result bit."""
+    g, lo, hi = small_case()
+    params = dect.default_params(n_iter=6)
+    ref = solve(dect.Solver(g, params), lo, hi, 6)
+    sol = dect.Solver(g, params).enable_timing(True, timeline=True)
+    got = solve(sol, lo, hi, 6)
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+    tl = sol.timeline()
+    assert tl.shape == (5, 5) and np.isfinite(tl).all()
+    grad, fp, upd, setup, done = tl.T
+    assert (grad > 0).all() and (grad < fp).all() and (fp < upd).all()
+    assert (setup > 0).all() and (setup < done).all()
+    assert sol.timeline().shape == (0, 5)   # cleared by the read
+    solve(sol, lo, hi, 3)
+    solve(sol, lo, hi, 3)
+    assert sol.timeline().shape == (4, 5)   # two rows per solve: none across solves
