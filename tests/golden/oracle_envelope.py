@@ -12,7 +12,7 @@ Modes (each is one 50-iteration solve, 15-25 minutes on 8 cores):
     fp32 RMODE   the GPU path's documented arithmetic: every iterate (f1, f2,
                  rho_e, t') rounded to FP32 after every outer iteration
                  (RMODE nearest or zero: round to nearest, or toward zero),
-                 and the t' solve stopped at ||r|| <= 1e-9 ||b|| from its
+                 and the t' solve stopped at ||r|| <= 1e-7 ||r_0|| from its
                  warm start (the GPU's stopping rule) instead of 1e-12 ||b||
     input EPS    input sinograms times (1 + EPS * N(0, 1))
     noise EF ET  after every outer iteration f1, f2, rho_e times
@@ -43,7 +43,7 @@ from paper_2308_01290_amd import phantoms as P  # noqa: E402
 from tests import e2e  # noqa: E402
 
 ENVELOPE_JSON = os.path.join(HERE, "slice512_envelope.json")
-GPU_T_TOL = 1e-9
+GPU_T_TOL = 1e-7
 
 
 def round32(x, mode):
@@ -62,7 +62,10 @@ def t_step_gpu_rule(st, phys, params):
     w = phys.W(M1, M2) / Ww
     gt = phys.d_t(M1, M2) / Ww
     h, v = l0.ht_of(st.t, params.lam, st.beta)
-    t, _, _ = l0.weighted_solve(w, gt, h, v, st.beta, x0=st.t, rtol=GPU_T_TOL)
+    b = w * gt + st.beta * l0.dT(h, v)
+    r0 = float(np.linalg.norm(b - l0.weighted_apply(st.t, w * w, st.beta)))
+    rtol = GPU_T_TOL * r0 / max(float(np.linalg.norm(b)), 1e-300)
+    t, _, _ = l0.weighted_solve(w, gt, h, v, st.beta, x0=st.t, rtol=rtol)
     return t
 
 
