@@ -681,7 +681,7 @@ __global__ __launch_bounds__(kBpWaves * 64) void k_backproject(
     const int4* __restrict__ fix = T.fix + D.ray0;
     const float2* __restrict__ flt = T.flt + D.ray0;
     const float4* __restrict__ view = T.view + D.view0;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // w: wave-uniform
     const int i0 = blockIdx.y * 16 + 2 * (lane >> 3), k0 = blockIdx.x * 16 + 2 * (lane & 7);
     // quad centre (between pixels k0, k0 + 1 and rows i0, i0 + 1)
     const float x = ((float)k0 + 0.5f - 0.5f * (float)(nx - 1)) * dxmm;
@@ -836,7 +836,7 @@ __global__ __launch_bounds__(kBsWaves * 64) void k_backproject_sym(
     const int4* __restrict__ fix = T.fix + D.ray0;
     const float2* __restrict__ flt = T.flt + D.ray0;
     const float4* __restrict__ view = T.view + D.view0;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // w: wave-uniform
     const int a = w & 3, cls = w >> 2;
     // tile origins (row, column) of T0..T3
     const int ty0 = oby * 16, tx0 = obx * 16;
@@ -1031,7 +1031,9 @@ __global__ __launch_bounds__(kB8Waves * 64) void k_backproject_sym8(
     static_assert(sizeof(ssn) >= sizeof(float) * 8 * 2 * 16 * 17, "tile sums");
     const int nq = n / 32;
     const int nheavy = nq * (nq - 1) / 2, nunit = sym8_units(n);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // the wavefront index in a scalar register (wave-uniform; as a vector
+    // register, values derived from it are spilled across the view loop)
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (int unit = blockIdx.x; unit < nunit * npairs; unit += gridDim.x) {
     const int z = unit / nunit, u = unit - z * nunit;
     const SliceDesc D = T.desc[T.desc_stride * z];
