@@ -604,7 +604,6 @@ struct dect_solver {
     unsigned* dpad16 = nullptr;      // BF16 storage: the direction's pair blocks, one word per entry
     bool image = false;              // image-domain form: inputs are mu_lo, mu_hi in muL, muH;
                                      // B holds f^(k+1) during an iteration
-    unsigned* cnt_proj;
     PcgBufs pcg;
     // Concurrency within an iteration: the f-step runs on `side` and the
     // rho_e step on `rst` (or on `side`) while the t' PCG runs on pst (all
@@ -992,7 +991,6 @@ static size_t solver_layout(const BatchGeo& B, char* base, dect_solver* s, int s
     double* alpha = c.take<double>((size_t)batch);
     double* beta_d = c.take<double>((size_t)batch);
     double* kappa_d = c.take<double>((size_t)batch);
-    unsigned* cnt = c.take<unsigned>((size_t)batch);
     unsigned* dpad16 =
         storage != DECT_STORAGE_FP32 ? c.take<unsigned>(pad_elems(g, B.rev) * batch) : nullptr;
     PcgBufs pb;
@@ -1023,7 +1021,6 @@ static size_t solver_layout(const BatchGeo& B, char* base, dect_solver* s, int s
         s->part_img = part_img;
         s->part_proj = part_proj;
         s->alpha = alpha;
-        s->cnt_proj = cnt;
         s->pcg = pb;
     }
     return c.off;
@@ -1093,13 +1090,12 @@ static int solver_create(const dect_geometry* geoms, const dect_params* p, int32
         const int u = B.uniq[z];
         s->hdesc[z] = make_slice_desc(B.g[z], B.ray0[u], B.view0[u], B.sino0[z], eta_of(p, B.g[z]));
     }
-    // zero borders of the padded direction layouts, counters and scalars once
+    // zero borders of the padded direction layouts and the PCG scalars once
     hipError_t e = hipSuccess;
     e = e != hipSuccess ? e : hipMemsetAsync(s->dpad, 0, pad_elems(g, B.rev) * batch * sizeof(float2), st);
     if (s->dpad16)
         e = e != hipSuccess ? e
                             : hipMemsetAsync(s->dpad16, 0, pad_elems(g, B.rev) * batch * sizeof(unsigned), st);
-    e = e != hipSuccess ? e : hipMemsetAsync(s->cnt_proj, 0, sizeof(unsigned) * batch, st);
     e = e != hipSuccess ? e : hipMemsetAsync(s->pcg.st, 0, sizeof(PcgState) * batch, st);
     e = e != hipSuccess ? e
                         : hipMemcpyAsync(const_cast<SliceDesc*>(s->tab.desc), s->hdesc.data(),
@@ -1525,7 +1521,6 @@ static int iter_enqueue(dect_solver* s, bool more) {
     pa.w_reg = 2.0 * beta;
     pa.beta_z = s->beta_d;
     pa.alpha = s->alpha;
-    pa.counter = s->cnt_proj;
     pa.pad_bf16 = pa.res_bf16 = a.bf16;
     pa.four_ray = (s->geo.kinds & ~kSlicePlain) != 0 && s->sched.fp_rays_per_lane == 4;
     pa.has_plain = (s->geo.kinds & kSlicePlain) != 0;

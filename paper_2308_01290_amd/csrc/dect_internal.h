@@ -193,13 +193,12 @@ struct ProjArgs {
     float2* res = nullptr;
     float c00 = 0, c01 = 0, c10 = 0, c11 = 0;   // C[k][i] = mu_i(E_k)
     double* partials = nullptr;                  // [z][nblocks]
-    // line-search finish (last block): alpha[z] = num / den
+    // line-search step (k_alpha, after the rays): alpha[z] = num / den
     const double* img_partials = nullptr;        // [z][img_nblocks][3]
     int img_nblocks = 0;
     double w_data = 0, w_coup = 0, w_reg = 0;    // 2, 2 xi, 2 beta
     const double* beta_z = nullptr;              // per-slice beta (then w_reg = 2 beta_z[z])
     double* alpha = nullptr;                     // [z]
-    unsigned* counter = nullptr;                 // [z]
     // BF16 storage: res holds one 32-bit word of two BF16 values per ray
     // (RESID, LINESEARCH); LINESEARCH also reads BF16 pair blocks
     bool res_bf16 = false;

@@ -1,5 +1,5 @@
 // Device helpers shared by the library's kernels (wave64 reductions,
-// deterministic block partials, last-block completion).
+// deterministic block partials).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -77,27 +77,6 @@ __device__ __forceinline__ void block_sum_n(double (&v)[N], double* sh) {
         v[c] = r;
     }
     __syncthreads();
-}
-
-// Called by every thread of a block after thread 0 stored the block's
-// partials.  Returns true in every thread of the last block to arrive; its
-// loads after this call see all blocks' partials.  The last block resets the
-// counter for the next launch.
-__device__ __forceinline__ bool last_block_arrive(unsigned* counter, unsigned nblocks) {
-    __shared__ int am_last;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned prev = atomicAdd(counter, 1u);
-        am_last = (prev == nblocks - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    const bool last = am_last != 0;
-    if (last) {
-        __threadfence();
-        if (threadIdx.x == 0) atomicExch(counter, 0u);
-    }
-    return last;
 }
 
 // Deterministic sum of n doubles at stride `stride` (fixed tree order), done

@@ -438,23 +438,10 @@ __global__ __launch_bounds__(256) void k_project(const void* __restrict__ pad, P
         // slice of the batch), so a slice reduces exactly as it does alone
         const int nbx = (nd + 255) / 256;
         if (v >= D.nv || (int)blockIdx.x >= nbx) return;
-        const int nblk = nbx * D.nv;
         const int bid = v * nbx + blockIdx.x;
         double* zp = a.partials + (size_t)z * a.part_stride;
         const double bs = block_sum<256>(part, sh);
         if (threadIdx.x == 0) zp[bid] = bs;
-        if (last_block_arrive(a.counter + z, (unsigned)nblk)) {
-            const double den_data = block_sum_array<256>(zp, nblk, 1, sh);
-            const double* ip = a.img_partials + (size_t)z * a.img_nblocks * 3;
-            const double num = block_sum_array<256>(ip + 0, a.img_nblocks, 3, sh);
-            const double coup = block_sum_array<256>(ip + 1, a.img_nblocks, 3, sh);
-            const double reg = block_sum_array<256>(ip + 2, a.img_nblocks, 3, sh);
-            if (threadIdx.x == 0) {
-                const double wr = a.beta_z ? 2.0 * a.beta_z[z] : a.w_reg;
-                const double den = a.w_data * den_data + a.w_coup * coup + wr * reg;
-                a.alpha[z] = den > 0.0 ? num / den : 0.0;
-            }
-        }
     }
 }
 
@@ -586,33 +573,38 @@ __global__ __launch_bounds__(256) void k_project4(const void* __restrict__ pad, 
         __shared__ double sh[4];
         const int nbx = (nd + 255) / 256;
         if ((int)blockIdx.x >= nbx) return;
-        const int nblk = nbx * D.nv;
         double* zp = a.partials + (size_t)z * a.part_stride;
 #pragma unroll
         for (int rot = 0; rot < 4; ++rot) {
             const double bs = block_sum<256>(part[rot], sh);
             if (threadIdx.x == 0) zp[(vt + rot * q4) * nbx + blockIdx.x] = bs;
         }
-        if (last_block_arrive(a.counter + z, (unsigned)(nbx * q4))) {
-            const double den_data = block_sum_array<256>(zp, nblk, 1, sh);
-            const double* ip = a.img_partials + (size_t)z * a.img_nblocks * 3;
-            const double num = block_sum_array<256>(ip + 0, a.img_nblocks, 3, sh);
-            const double coup = block_sum_array<256>(ip + 1, a.img_nblocks, 3, sh);
-            const double reg = block_sum_array<256>(ip + 2, a.img_nblocks, 3, sh);
-            if (threadIdx.x == 0) {
-                const double wr = a.beta_z ? 2.0 * a.beta_z[z] : a.w_reg;
-                const double den = a.w_data * den_data + a.w_coup * coup + wr * reg;
-                a.alpha[z] = den > 0.0 ? num / den : 0.0;
-            }
-        }
     }
 }
 
-void launch_project(const Geom& g, const PadLayout& P, const RayTable& t, const void* pad, int npairs,
-                    int mode, const ProjArgs& a_in, hipStream_t st) {
-    ProjArgs a = a_in;
-    a.part_stride = (size_t)proj_nblocks(t.nv_max, t.nd_max);
-    a.plain_only = false;
+// Exact line-search step of each slice, one block per slice: alpha = num / den
+// from the gradient kernel's image partials (num, coupling, regulariser) and
+// the projector's per-block data partials, each summed in its fixed slot
+// order, so a slice's step does not depend on the batch or the launch form.
+__global__ __launch_bounds__(256) void k_alpha(RayTable T, ProjArgs a) {
+    __shared__ double sh[4];
+    const int z = blockIdx.x;
+    const SliceDesc D = T.desc[T.desc_stride * z];
+    const int nblk = ((D.nd + 255) / 256) * D.nv;
+    const double den_data = block_sum_array<256>(a.partials + (size_t)z * a.part_stride, nblk, 1, sh);
+    const double* ip = a.img_partials + (size_t)z * a.img_nblocks * 3;
+    const double num = block_sum_array<256>(ip + 0, a.img_nblocks, 3, sh);
+    const double coup = block_sum_array<256>(ip + 1, a.img_nblocks, 3, sh);
+    const double reg = block_sum_array<256>(ip + 2, a.img_nblocks, 3, sh);
+    if (threadIdx.x == 0) {
+        const double wr = a.beta_z ? 2.0 * a.beta_z[z] : a.w_reg;
+        const double den = a.w_data * den_data + a.w_coup * coup + wr * reg;
+        a.alpha[z] = den > 0.0 ? num / den : 0.0;
+    }
+}
+
+static void launch_rays(const Geom& g, const PadLayout& P, const RayTable& t, const void* pad, int npairs,
+                        int mode, ProjArgs a, hipStream_t st) {
     if (a.four_ray && P.rev) {
         dim3 grid4((t.nd_max + 255) / 256, (t.nv_max + 3) / 4, npairs);
         if (mode == PROJ_PLAIN)
@@ -649,6 +641,15 @@ void launch_project(const Geom& g, const PadLayout& P, const RayTable& t, const 
     else
         hipLaunchKernelGGL((k_project<PROJ_LINESEARCH, false, false>), grid, dim3(256), 0, st, pad,
                            P, t, g.nx, g.ny, a);
+}
+
+void launch_project(const Geom& g, const PadLayout& P, const RayTable& t, const void* pad, int npairs,
+                    int mode, const ProjArgs& a_in, hipStream_t st) {
+    ProjArgs a = a_in;
+    a.part_stride = (size_t)proj_nblocks(t.nv_max, t.nd_max);
+    a.plain_only = false;
+    launch_rays(g, P, t, pad, npairs, mode, a, st);
+    if (mode == PROJ_LINESEARCH) hipLaunchKernelGGL(k_alpha, dim3(npairs), dim3(256), 0, st, t, a);
 }
 
 // ---------------------------------------------------------------------------
@@ -1008,6 +1009,65 @@ __host__ __device__ inline int sym8_units(int n) {
     return nq * (nq - 1) / 2 + (nq + 1) / 2;
 }
 
+// Work item of the block's r-th round.  Workgroups go round-robin to the 8
+// XCDs, each with its own L2, so the items are relabelled to give the blocks
+// of one XCD a contiguous run of items (slot b + r G keeps its block and
+// round, so every block does the same amount of work as without relabelling).
+__device__ __forceinline__ int sym8_xcd_item(int b, int r, int G, int N) {
+    const int x = b & 7, R = N / G, rem = N - R * G;
+    int off = 0;
+    for (int y = 0; y < x; ++y) off += R * ((G + 7 - y) >> 3) + ((rem + 7 - y) >> 3);
+    return off + r * ((G + 7 - x) >> 3) + (b >> 3);
+}
+
+// The orbits of work unit u of a slice, in an order where consecutive units
+// are close in the image.  The first-quadrant tile pairs (a, b), a <= b, fall
+// into 4 x 4 blocks (A, B), A <= B: first the diagonal blocks (A, A), each
+// with its off-diagonal pairs row by row, then its diagonal tiles two at a
+// time; then the off-diagonal blocks row by row, each with its 16 pairs row
+// by row.  At 512^2 (16 x 16 tiles) that gives every XCD two diagonal blocks
+// or one 64 x 64 pixel block, whose sinogram windows overlap.
+__device__ __forceinline__ void sym8_unit_orbits(int u, int nq, int& norb, int pa[2], int pb[2]) {
+    const int nb = (nq + 3) >> 2;
+    int r = u;
+    norb = 1;
+    pa[1] = pb[1] = 0;
+    for (int A = 0; A < nb; ++A) {
+        const int ha = min(4, nq - 4 * A), nh = ha * (ha - 1) / 2;
+        if (r < nh) {
+            int a = 0;
+            while (r >= ha - 1 - a) {
+                r -= ha - 1 - a;
+                ++a;
+            }
+            pa[0] = 4 * A + a;
+            pb[0] = 4 * A + a + 1 + r;
+            return;
+        }
+        r -= nh;
+        if (r < (ha + 1) / 2) {
+            const int d0 = 4 * A + 2 * r;
+            norb = min(2, nq - d0);
+            pa[0] = pb[0] = d0;
+            pa[1] = pb[1] = d0 + 1;
+            return;
+        }
+        r -= (ha + 1) / 2;
+    }
+    for (int A = 0; A < nb; ++A) {
+        const int ha = min(4, nq - 4 * A);
+        for (int B = A + 1; B < nb; ++B) {
+            const int hb = min(4, nq - 4 * B);
+            if (r < ha * hb) {
+                pa[0] = 4 * A + r / hb;
+                pb[0] = 4 * B + r % hb;
+                return;
+            }
+            r -= ha * hb;
+        }
+    }
+}
+
 template <bool SB>
 __global__ __launch_bounds__(kB8Waves * 64) void k_backproject_sym8(
     const void* __restrict__ sino, RayTable T, int n, float dxmm, float2* __restrict__ out_pairs,
@@ -1030,31 +1090,18 @@ __global__ __launch_bounds__(kB8Waves * 64) void k_backproject_sym8(
     float(*acc_t)[2][16][17] = reinterpret_cast<float(*)[2][16][17]>(&ssn[0][0][0]);
     static_assert(sizeof(ssn) >= sizeof(float) * 8 * 2 * 16 * 17, "tile sums");
     const int nq = n / 32;
-    const int nheavy = nq * (nq - 1) / 2, nunit = sym8_units(n);
+    const int nunit = sym8_units(n), nitem = nunit * npairs;
     // the wavefront index in a scalar register (wave-uniform; as a vector
     // register, values derived from it are spilled across the view loop)
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (int unit = blockIdx.x; unit < nunit * npairs; unit += gridDim.x) {
+    for (int slot = blockIdx.x, round = 0; slot < nitem; slot += gridDim.x, ++round) {
+    const int unit = sym8_xcd_item(blockIdx.x, round, gridDim.x, nitem);
     const int z = unit / nunit, u = unit - z * nunit;
     const SliceDesc D = T.desc[T.desc_stride * z];
     if (D.sym != 2) continue;   // block-uniform
     // the unit's orbits, by the first-quadrant tile row and column of P
-    int norb = 1, pa[2], pb[2];
-    if (u < nheavy) {
-        int a = 0, r = u;
-        while (r >= nq - 1 - a) {
-            r -= nq - 1 - a;
-            ++a;
-        }
-        pa[0] = a;
-        pb[0] = a + 1 + r;
-        pa[1] = pb[1] = 0;
-    } else {
-        const int d0 = 2 * (u - nheavy);
-        norb = min(2, nq - d0);
-        pa[0] = pb[0] = d0;
-        pa[1] = pb[1] = d0 + 1;
-    }
+    int norb, pa[2], pb[2];
+    sym8_unit_orbits(u, nq, norb, pa, pb);
     const int nd = D.nd, q4 = D.nv >> 2, vmax = q4 >> 1;
     // slice constants in scalar registers (uniform; as vector registers they
     // would be spilled across the view loop)
