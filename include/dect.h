@@ -357,8 +357,10 @@ int dect_solver_set_graphs(dect_solver* s, int enable);
 
 /* Optional timing of the two system-matrix kernels: with bit 0 of `enable`
  * set, the solver records HIP events on its stream around every
- * back-projection and forward projection launch of the outer iterations; bit
- * 1 records the iteration timeline (dect_solver_timeline).  dect_solver_timing synchronises
+ * back-projection and forward projection launch of the outer iterations
+ * (with bit 2 also set, around the back-projections only, which halves the
+ * events in the iteration); bit 1 records the iteration timeline
+ * (dect_solver_timeline).  dect_solver_timing synchronises
  * the stream, returns the summed durations (ms) and launch counts since the
  * last call, and resets them.  Any output pointer may be NULL.  For an
  * image-domain solver the first pair times each iteration's f-step (the

@@ -619,7 +619,7 @@ struct dect_solver {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_entry = nullptr, ev_mdone = nullptr;
     bool in_pipe = false;        // inside a run of pipelined iterations (pst, side forked)
     // software pipelining of consecutive iterations (see one_iteration)
-    hipEvent_t ev_init = nullptr, ev_side = nullptr, ev_upd = nullptr, ev_tdone = nullptr;
+    hipEvent_t ev_init = nullptr, ev_upd = nullptr, ev_tdone = nullptr;
     bool bp_pending = false;    // this iteration's back-projection is already on `side`
     bool upd_pending = false;   // the last f update ran on `side`, not yet joined
     PcgState* hs_pinned = nullptr;
@@ -642,6 +642,7 @@ struct dect_solver {
     dect_schedule sched{4, 0, 1, 0, 0, 1};   // launch schedule (dect_solver_set_schedule)
     // optional kernel timing: event pairs in launch order
     bool timing = false;
+    bool timing_fp = false;  // the forward projections too (not with bit 2)
     bool timeline = false;   // iteration timeline (dect_solver_enable_timing bit 1)
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_bp, ev_fp;
@@ -729,8 +730,8 @@ static void make_side(dect_solver* s) {
         s->pst = nullptr;
         return;
     }
-    hipEvent_t* evs[8] = {&s->ev_fork, &s->ev_join, &s->ev_init,  &s->ev_side,
-                          &s->ev_upd,  &s->ev_tdone, &s->ev_entry, &s->ev_mdone};
+    hipEvent_t* evs[7] = {&s->ev_fork,  &s->ev_join,  &s->ev_init, &s->ev_upd,
+                          &s->ev_tdone, &s->ev_entry, &s->ev_mdone};
     bool ok = true;
     for (hipEvent_t* e : evs) ok = ok && hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
     if (!ok) {
@@ -767,8 +768,8 @@ static void free_side(dect_solver* s) {
     if (s->side) {
         (void)hipStreamSynchronize(s->side);
         (void)hipStreamSynchronize(s->pst);
-        for (hipEvent_t e : {s->ev_fork, s->ev_join, s->ev_init, s->ev_side, s->ev_upd, s->ev_tdone,
-                             s->ev_entry, s->ev_mdone})
+        for (hipEvent_t e : {s->ev_fork, s->ev_join, s->ev_init, s->ev_upd, s->ev_tdone, s->ev_entry,
+                             s->ev_mdone})
             (void)hipEventDestroy(e);
         (void)hipStreamDestroy(s->side);
         (void)hipStreamDestroy(s->pst);
@@ -1505,6 +1506,9 @@ static int iter_enqueue(dect_solver* s, bool more) {
         DECT_HIP(hipEventRecord(s->ev_grad, side));
         DECT_HIP(hipStreamWaitEvent(rs, s->ev_grad, 0));
         rho_step(s, rs, s->fft2);
+        // ev_rho also orders after the PCG's read of f^(k), so the update
+        // below waits for one event instead of two
+        if (two) DECT_HIP(hipStreamWaitEvent(rs, s->ev_init, 0));
         DECT_HIP(hipEventRecord(s->ev_rho, rs));
     }
     ProjArgs pa;
@@ -1524,16 +1528,15 @@ static int iter_enqueue(dect_solver* s, bool more) {
     pa.pad_bf16 = pa.res_bf16 = a.bf16;
     pa.four_ray = (s->geo.kinds & ~kSlicePlain) != 0 && s->sched.fp_rays_per_lane == 4;
     pa.has_plain = (s->geo.kinds & kSlicePlain) != 0;
-    hipEvent_t t1 = mark(s, side);
+    hipEvent_t t1 = s->timing_fp ? mark(s, side) : nullptr;
     launch_project(g, P, s->tab, dir, s->batch, PROJ_LINESEARCH, pa, side);
     mark_end(s, side, t1, s->ev_fp);
     tl_mark(s, kTlFp, side);
     if (!rs) rho_step(s, side, two ? s->fft2 : s->fft);
     if (two) {
-        DECT_HIP(hipEventRecord(s->ev_side, side));          // beta^(k) no longer read there
-        DECT_HIP(hipStreamWaitEvent(side, s->ev_init, 0));   // f^(k) read by the PCG
-        // f^(k) read by the rho_e step; the next gradient reads rho^(k+1)
-        if (rs) DECT_HIP(hipStreamWaitEvent(side, s->ev_rho, 0));
+        // f^(k) read by the PCG and by the rho_e step (whose event orders
+        // after the PCG's); the next gradient reads rho^(k+1)
+        DECT_HIP(hipStreamWaitEvent(side, rs ? s->ev_rho : s->ev_init, 0));
     }
     // f^(k+1), residual sinograms (beta is stepped on st below)
     launch_update(a, P, s->tab, s->alpha, dir, s->f, s->S, s->zq, nullptr, nullptr, side);
@@ -1559,8 +1562,9 @@ static int iter_complete(dect_solver* s, bool more) {
     const hipStream_t ms = two ? s->pst : s->st;
     const hipStream_t rs = two && s->rst && s->sched.rho_stream ? s->rst : nullptr;
     if (int rc = t_step_finish(s, ms)) return rc;
-    // ms: beta^(k+1) once the side work and the rho_e step have read beta^(k)
-    if (two) DECT_HIP(hipStreamWaitEvent(ms, s->ev_side, 0));
+    // ms: beta^(k+1) once the side work (up to its update, recorded in
+    // ev_upd) and the rho_e step have read beta^(k)
+    if (two) DECT_HIP(hipStreamWaitEvent(ms, s->ev_upd, 0));
     if (rs) DECT_HIP(hipStreamWaitEvent(ms, s->ev_rho, 0));
     launch_step_beta(s->beta_d, s->kappa_d, s->batch, ms);
     std::swap(s->t, s->t_next);
@@ -1741,6 +1745,7 @@ int dect_solver_autotune(dect_solver* s, const float* lo, const float* hi, int32
 int dect_solver_enable_timing(dect_solver* s, int enable) {
     if (!s) return fail(DECT_EINVAL, "solver is NULL");
     s->timing = (enable & 1) != 0;
+    s->timing_fp = s->timing && (enable & 4) == 0;
     s->timeline = (enable & 2) != 0;
     return DECT_OK;
 }

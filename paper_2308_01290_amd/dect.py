@@ -502,10 +502,11 @@ class Solver:
         _check(lib().dect_solver_set_graphs(self._h, 1 if on else 0), "dect_solver_set_graphs")
         return self
 
-    def enable_timing(self, on: bool = True, timeline: bool = False):
+    def enable_timing(self, on: bool = True, timeline: bool = False, bp_only: bool = False):
         """Kernel timing (timing()) and, with `timeline`, the iteration
-        timeline (timeline()); both off with on=False."""
-        flags = (1 if on else 0) | (2 if on and timeline else 0)
+        timeline (timeline()); both off with on=False.  With `bp_only` the
+        forward projections are not timed (half the events per iteration)."""
+        flags = (1 if on else 0) | (2 if on and timeline else 0) | (4 if on and bp_only else 0)
         _check(lib().dect_solver_enable_timing(self._h, flags), "dect_solver_enable_timing")
         return self
 

@@ -133,3 +133,21 @@ def test_iteration_timeline():
     solve(sol, lo, hi, 3)
     solve(sol, lo, hi, 3)
     assert sol.timeline().shape == (4, 5)   # two rows per solve: none across solves
+
+
+def test_kernel_timing_back_projections_only():
+    """Timing the back-projections only records no forward-projection
+    intervals and as many back-projection ones; no result bit changes."""
+    g, lo, hi = small_case()
+    params = dect.default_params(n_iter=6)
+    ref = solve(dect.Solver(g, params), lo, hi, 6)
+    sol = dect.Solver(g, params).enable_timing(True)
+    full = solve(sol, lo, hi, 6)
+    bp_ms, bp_n, fp_ms, fp_n = sol.timing()
+    sol.enable_timing(True, bp_only=True)
+    only = solve(sol, lo, hi, 6)
+    bp_ms2, bp_n2, fp_ms2, fp_n2 = sol.timing()
+    assert bp_n > 0 and fp_n > 0 and bp_ms > 0.0 and fp_ms > 0.0
+    assert bp_n2 == bp_n and bp_ms2 > 0.0 and fp_n2 == 0 and fp_ms2 == 0.0
+    for got in (full, only):
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
