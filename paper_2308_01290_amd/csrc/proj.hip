@@ -266,7 +266,7 @@ void launch_pair_sinos(const Geom& g, const float* sino, int nsino, float2* out,
 }
 
 // ---------------------------------------------------------------------------
-// forward projector: one lane per ray, 256 adjacent bins of one view per block
+// forward projector: one lane per ray, kProjLanes adjacent bins of one view per block
 // ---------------------------------------------------------------------------
 // clamp to [lo, hi] (lo <= hi) in one VALU operation
 __device__ __forceinline__ int clamp_med3(int x, int lo, int hi) {
@@ -282,9 +282,12 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
     s = t;
 }
 
-// line-search partials per slice: blocks of 256 bins times views rounded up
+// lanes (bins) per projector block
+constexpr int kProjLanes = 128;
+
+// line-search partials per slice: blocks of kProjLanes bins times views rounded up
 // to a multiple of 4 (the four-ray form's grid), the same stride in both forms
-int proj_nblocks(int nv, int nd) { return ((nd + 255) / 256) * ((nv + 3) & ~3); }
+int proj_nblocks(int nv, int nd) { return ((nd + kProjLanes - 1) / kProjLanes) * ((nv + 3) & ~3); }
 
 // the two minor entries of one major step: float2 (f1, f2) per pixel, or one
 // 32-bit word of two BF16 values per pixel
@@ -313,7 +316,7 @@ __device__ __forceinline__ void store_res(float2* res, long long i, float x, flo
 // compiler could otherwise choose differently in the two kernels), so that a
 // symmetric slice's rays are the same bit for bit in either form.
 template <int MODE, bool PB, bool RB>
-__global__ __launch_bounds__(256) void k_project(const void* __restrict__ pad, PadLayout P,
+__global__ __launch_bounds__(kProjLanes) void k_project(const void* __restrict__ pad, PadLayout P,
                                                  RayTable T, int nx, int ny, ProjArgs a) {
 #pragma clang fp contract(off)
     constexpr unsigned ES = PB ? 4u : 8u;   // bytes per pixel entry
@@ -322,7 +325,7 @@ __global__ __launch_bounds__(256) void k_project(const void* __restrict__ pad, P
     const SliceDesc D = T.desc[T.desc_stride * z];
     if (a.plain_only && D.sym) return;   // block-uniform: k_project4 takes this slice
     const int nd = D.nd;
-    const int j = blockIdx.x * 256 + threadIdx.x;
+    const int j = blockIdx.x * kProjLanes + threadIdx.x;
     const bool valid = j < nd && v < D.nv;   // the grid covers the batch's largest slice
     const size_t r = (size_t)v * nd + j;     // ray within the slice
     // quarter-turn symmetry: view v = vt + rot * nv/4 takes ray (vt, j) of the
@@ -425,7 +428,7 @@ __global__ __launch_bounds__(256) void k_project(const void* __restrict__ pad, P
                           (float)(D.eta * ((double)a.c01 * rl + (double)a.c11 * rh)));
         }
     } else {   // PROJ_LINESEARCH
-        __shared__ double sh[4];
+        __shared__ double sh[kProjLanes / 64];
         double part = 0.0;
         if (valid) {
             const double yl = (double)a.c00 * Y1 + (double)a.c01 * Y2;
@@ -436,11 +439,11 @@ __global__ __launch_bounds__(256) void k_project(const void* __restrict__ pad, P
         }
         // partials in the slice's own block order (the launch may cover a larger
         // slice of the batch), so a slice reduces exactly as it does alone
-        const int nbx = (nd + 255) / 256;
+        const int nbx = (nd + kProjLanes - 1) / kProjLanes;
         if (v >= D.nv || (int)blockIdx.x >= nbx) return;
         const int bid = v * nbx + blockIdx.x;
         double* zp = a.partials + (size_t)z * a.part_stride;
-        const double bs = block_sum<256>(part, sh);
+        const double bs = block_sum<kProjLanes>(part, sh);
         if (threadIdx.x == 0) zp[bid] = bs;
     }
 }
@@ -453,7 +456,7 @@ __global__ __launch_bounds__(256) void k_project(const void* __restrict__ pad, P
 // kernels agree bit for bit.  Line-search partials go to the same per-view
 // block slots.
 template <int MODE, bool PB, bool RB>
-__global__ __launch_bounds__(256) void k_project4(const void* __restrict__ pad, PadLayout P,
+__global__ __launch_bounds__(kProjLanes) void k_project4(const void* __restrict__ pad, PadLayout P,
                                                   RayTable T, int n, ProjArgs a) {
 #pragma clang fp contract(off)
     constexpr unsigned ES = PB ? 4u : 8u;
@@ -462,7 +465,7 @@ __global__ __launch_bounds__(256) void k_project4(const void* __restrict__ pad, 
     const SliceDesc D = T.desc[T.desc_stride * z];
     const int nd = D.nd, q4 = D.nv >> 2;
     if (!D.sym || vt >= q4) return;   // block-uniform
-    const int j = blockIdx.x * 256 + threadIdx.x;
+    const int j = blockIdx.x * kProjLanes + threadIdx.x;
     const bool valid = j < nd;
     const size_t rt = (size_t)D.ray0 + (size_t)vt * nd + j;
     const long long s0 = D.sino0 + (long long)z * T.sino_zstride;
@@ -570,13 +573,13 @@ __global__ __launch_bounds__(256) void k_project4(const void* __restrict__ pad, 
         }
     }
     if constexpr (MODE == PROJ_LINESEARCH) {
-        __shared__ double sh[4];
-        const int nbx = (nd + 255) / 256;
+        __shared__ double sh[kProjLanes / 64];
+        const int nbx = (nd + kProjLanes - 1) / kProjLanes;
         if ((int)blockIdx.x >= nbx) return;
         double* zp = a.partials + (size_t)z * a.part_stride;
 #pragma unroll
         for (int rot = 0; rot < 4; ++rot) {
-            const double bs = block_sum<256>(part[rot], sh);
+            const double bs = block_sum<kProjLanes>(part[rot], sh);
             if (threadIdx.x == 0) zp[(vt + rot * q4) * nbx + blockIdx.x] = bs;
         }
     }
@@ -586,60 +589,68 @@ __global__ __launch_bounds__(256) void k_project4(const void* __restrict__ pad, 
 // from the gradient kernel's image partials (num, coupling, regulariser) and
 // the projector's per-block data partials, each summed in its fixed slot
 // order, so a slice's step does not depend on the batch or the launch form.
-__global__ __launch_bounds__(256) void k_alpha(RayTable T, ProjArgs a) {
-    __shared__ double sh[4];
+constexpr int kAlphaThreads = 1024;
+
+__global__ __launch_bounds__(kAlphaThreads) void k_alpha(RayTable T, ProjArgs a) {
+    __shared__ double sh[4 * (kAlphaThreads / 64)];
     const int z = blockIdx.x;
     const SliceDesc D = T.desc[T.desc_stride * z];
-    const int nblk = ((D.nd + 255) / 256) * D.nv;
-    const double den_data = block_sum_array<256>(a.partials + (size_t)z * a.part_stride, nblk, 1, sh);
+    const int nblk = ((D.nd + kProjLanes - 1) / kProjLanes) * D.nv;
+    const double* zp = a.partials + (size_t)z * a.part_stride;
     const double* ip = a.img_partials + (size_t)z * a.img_nblocks * 3;
-    const double num = block_sum_array<256>(ip + 0, a.img_nblocks, 3, sh);
-    const double coup = block_sum_array<256>(ip + 1, a.img_nblocks, 3, sh);
-    const double reg = block_sum_array<256>(ip + 2, a.img_nblocks, 3, sh);
+    // (data, num, coupling, regulariser), each thread over its own slots
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < nblk; i += kAlphaThreads) s[0] += zp[i];
+    for (int i = threadIdx.x; i < a.img_nblocks; i += kAlphaThreads) {
+        s[1] += ip[3 * i];
+        s[2] += ip[3 * i + 1];
+        s[3] += ip[3 * i + 2];
+    }
+    block_sum_n<kAlphaThreads, 4>(s, sh);
     if (threadIdx.x == 0) {
         const double wr = a.beta_z ? 2.0 * a.beta_z[z] : a.w_reg;
-        const double den = a.w_data * den_data + a.w_coup * coup + wr * reg;
-        a.alpha[z] = den > 0.0 ? num / den : 0.0;
+        const double den = a.w_data * s[0] + a.w_coup * s[2] + wr * s[3];
+        a.alpha[z] = den > 0.0 ? s[1] / den : 0.0;
     }
 }
 
 static void launch_rays(const Geom& g, const PadLayout& P, const RayTable& t, const void* pad, int npairs,
                         int mode, ProjArgs a, hipStream_t st) {
     if (a.four_ray && P.rev) {
-        dim3 grid4((t.nd_max + 255) / 256, (t.nv_max + 3) / 4, npairs);
+        dim3 grid4((t.nd_max + kProjLanes - 1) / kProjLanes, (t.nv_max + 3) / 4, npairs);
         if (mode == PROJ_PLAIN)
-            hipLaunchKernelGGL((k_project4<PROJ_PLAIN, false, false>), grid4, dim3(256), 0, st, pad, P, t,
+            hipLaunchKernelGGL((k_project4<PROJ_PLAIN, false, false>), grid4, dim3(kProjLanes), 0, st, pad, P, t,
                                g.nx, a);
         else if (mode == PROJ_RESID && a.res_bf16)
-            hipLaunchKernelGGL((k_project4<PROJ_RESID, false, true>), grid4, dim3(256), 0, st, pad, P, t,
+            hipLaunchKernelGGL((k_project4<PROJ_RESID, false, true>), grid4, dim3(kProjLanes), 0, st, pad, P, t,
                                g.nx, a);
         else if (mode == PROJ_RESID)
-            hipLaunchKernelGGL((k_project4<PROJ_RESID, false, false>), grid4, dim3(256), 0, st, pad, P, t,
+            hipLaunchKernelGGL((k_project4<PROJ_RESID, false, false>), grid4, dim3(kProjLanes), 0, st, pad, P, t,
                                g.nx, a);
         else if (a.pad_bf16)
-            hipLaunchKernelGGL((k_project4<PROJ_LINESEARCH, true, true>), grid4, dim3(256), 0, st, pad, P,
+            hipLaunchKernelGGL((k_project4<PROJ_LINESEARCH, true, true>), grid4, dim3(kProjLanes), 0, st, pad, P,
                                t, g.nx, a);
         else
-            hipLaunchKernelGGL((k_project4<PROJ_LINESEARCH, false, false>), grid4, dim3(256), 0, st, pad,
+            hipLaunchKernelGGL((k_project4<PROJ_LINESEARCH, false, false>), grid4, dim3(kProjLanes), 0, st, pad,
                                P, t, g.nx, a);
         if (!a.has_plain) return;
         a.plain_only = true;   // the other slices in the per-view form
     }
-    dim3 grid((t.nd_max + 255) / 256, t.nv_max, npairs);
+    dim3 grid((t.nd_max + kProjLanes - 1) / kProjLanes, t.nv_max, npairs);
     if (mode == PROJ_PLAIN)
-        hipLaunchKernelGGL((k_project<PROJ_PLAIN, false, false>), grid, dim3(256), 0, st, pad, P, t,
+        hipLaunchKernelGGL((k_project<PROJ_PLAIN, false, false>), grid, dim3(kProjLanes), 0, st, pad, P, t,
                            g.nx, g.ny, a);
     else if (mode == PROJ_RESID && a.res_bf16)
-        hipLaunchKernelGGL((k_project<PROJ_RESID, false, true>), grid, dim3(256), 0, st, pad, P, t,
+        hipLaunchKernelGGL((k_project<PROJ_RESID, false, true>), grid, dim3(kProjLanes), 0, st, pad, P, t,
                            g.nx, g.ny, a);
     else if (mode == PROJ_RESID)
-        hipLaunchKernelGGL((k_project<PROJ_RESID, false, false>), grid, dim3(256), 0, st, pad, P, t,
+        hipLaunchKernelGGL((k_project<PROJ_RESID, false, false>), grid, dim3(kProjLanes), 0, st, pad, P, t,
                            g.nx, g.ny, a);
     else if (a.pad_bf16)
-        hipLaunchKernelGGL((k_project<PROJ_LINESEARCH, true, true>), grid, dim3(256), 0, st, pad, P,
+        hipLaunchKernelGGL((k_project<PROJ_LINESEARCH, true, true>), grid, dim3(kProjLanes), 0, st, pad, P,
                            t, g.nx, g.ny, a);
     else
-        hipLaunchKernelGGL((k_project<PROJ_LINESEARCH, false, false>), grid, dim3(256), 0, st, pad,
+        hipLaunchKernelGGL((k_project<PROJ_LINESEARCH, false, false>), grid, dim3(kProjLanes), 0, st, pad,
                            P, t, g.nx, g.ny, a);
 }
 
@@ -649,7 +660,8 @@ void launch_project(const Geom& g, const PadLayout& P, const RayTable& t, const 
     a.part_stride = (size_t)proj_nblocks(t.nv_max, t.nd_max);
     a.plain_only = false;
     launch_rays(g, P, t, pad, npairs, mode, a, st);
-    if (mode == PROJ_LINESEARCH) hipLaunchKernelGGL(k_alpha, dim3(npairs), dim3(256), 0, st, t, a);
+    if (mode == PROJ_LINESEARCH)
+        hipLaunchKernelGGL(k_alpha, dim3(npairs), dim3(kAlphaThreads), 0, st, t, a);
 }
 
 // ---------------------------------------------------------------------------
