@@ -445,6 +445,9 @@ def main():
     ap.add_argument("--requests", type=int, default=96, help="serve: requests per rate")
     ap.add_argument("--served-requests", type=int, default=48,
                     help="slice512: requests of the served leg at 20 req/s (0: none)")
+    ap.add_argument("--batch", type=int, default=1,
+                    help="slice512: solve this many copies of the slice per launch (one solver, "
+                         "batch slices; value counts every slice)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first copy a device buffer of this many MiB once: the reference "
                          "kernel of known traffic for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
@@ -484,11 +487,14 @@ def main():
     pL = pL.astype(np.float32)
     pH = pH.astype(np.float32)
     dev = torch.device("cuda:0")
-    lo = torch.as_tensor(pL[None], device=dev)
-    hi = torch.as_tensor(pH[None], device=dev)
-    sol = dect.Solver(g, params, batch=1)
+    nb = args.batch
+    if nb < 1:
+        raise SystemExit("--batch must be at least 1")
+    lo = torch.as_tensor(np.repeat(pL[None], nb, 0), device=dev)
+    hi = torch.as_tensor(np.repeat(pH[None], nb, 0), device=dev)
+    sol = dect.Solver(g, params, batch=nb)
     schedule, t_tune = tune(args, sol, lo, hi, "default")
-    Z = torch.empty((1, g.n_y, g.n_x), device=dev)
+    Z = torch.empty((nb, g.n_y, g.n_x), device=dev)
     R = torch.empty_like(Z)
 
     def step():
@@ -521,8 +527,11 @@ def main():
 
     elapsed = t1 - t0
     ms_per_step = 1e3 * elapsed / args.steps
-    value = args.steps / elapsed
+    value = nb * args.steps / elapsed
     nnz = count_nonzeros(g)
+    # every copy of the slice must come out bit-identical to the first
+    batch_identical = bool(all(torch.equal(Z[i], Z[0]) and torch.equal(R[i], R[0])
+                               for i in range(1, nb)))
     bp_avg_s = bp_ms / max(bp_n, 1) / 1e3
     fp_avg_s = fp_ms / max(fp_n, 1) / 1e3
     # the same back-projection of both channels alone on the GPU (the stand-alone
@@ -550,8 +559,9 @@ def main():
     torch.cuda.synchronize()
     fp_alone_s = e0.elapsed_time(e1) / 10 / 1e3
     # algorithmic work of one back-projection launch: both channels of the
-    # sparse transpose product, one multiply-add per nonzero and channel
-    bp_flops = 2 * 2 * nnz
+    # sparse transpose product, one multiply-add per nonzero and channel, for
+    # each slice of the batch
+    bp_flops = 2 * 2 * nnz * nb
     achieved = bp_flops / bp_avg_s / 1e12
     nray = g.n_views * g.n_det
     npix = g.n_x * g.n_y
@@ -571,33 +581,38 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "512x512 slice at 0.8 mm, 720 views, 736 bins, SID 1000 / SDD 1500 mm, "
-                               "water body + 40 inserts, Poisson 5e4/1e5, 50 outer iterations",
+                               "water body + 40 inserts, Poisson 5e4/1e5, 50 outer iterations"
+                               + (f", {nb} copies per launch" if nb > 1 else ""),
                    "image": [g.n_y, g.n_x], "views": g.n_views, "bins": g.n_det,
-                   "iterations": N_ITER, "slices_per_solve": 1, "storage": args.storage},
+                   "iterations": N_ITER, "slices_per_solve": nb, "storage": args.storage},
         "rays_per_s": 4.0 * nray * N_ITER * value,
         "projector": {
             "system_matrix_nonzeros": nnz,
+            # in-solve durations per launch (a launch covers the whole batch);
+            # the alone figures are for one slice
             "backproject_ms": 1e3 * bp_avg_s,
             "backproject_alone_ms": 1e3 * bp_alone_s,
             "backproject_alone_tflops": 2 * 2 * nnz / bp_alone_s / 1e12,
             "project_ms": 1e3 * fp_avg_s,
             "project_alone_ms": 1e3 * fp_alone_s,
-            "backproject_visits_per_s": 2 * nnz / bp_avg_s,
-            "project_visits_per_s": 2 * nnz / fp_avg_s,
+            "backproject_visits_per_s": 2 * nnz * nb / bp_avg_s,
+            "project_visits_per_s": 2 * nnz * nb / fp_avg_s,
             # effective touch bandwidth: every (pixel, ray) visit of both images
             # counted as one 4-byte access; not HBM traffic (the images and
             # sinograms are reread from L2 and the Infinity Cache)
-            "backproject_effective_touch_gbs": 2 * nnz * 4 / bp_avg_s / 1e9,
-            "project_effective_touch_gbs": 2 * nnz * 4 / fp_avg_s / 1e9,
-            "backproject_algorithmic_hbm_gbs": bp_bytes / bp_avg_s / 1e9,
-            "project_algorithmic_hbm_gbs": fp_bytes / fp_avg_s / 1e9,
+            "backproject_effective_touch_gbs": 2 * nnz * nb * 4 / bp_avg_s / 1e9,
+            "project_effective_touch_gbs": 2 * nnz * nb * 4 / fp_avg_s / 1e9,
+            "backproject_algorithmic_hbm_gbs": bp_bytes * nb / bp_avg_s / 1e9,
+            "project_algorithmic_hbm_gbs": fp_bytes * nb / fp_avg_s / 1e9,
         },
         "roofline": {"kernel": "k_backproject_sym8", "bound": "alu", "achieved": achieved,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": measured_traffic("k_backproject_sym8") if storage == 0 else None},
+                     "traffic": measured_traffic("k_backproject_sym8") if storage == 0 and nb == 1 else None},
         "schedule": {"mode": args.schedule or "default", "chosen": schedule, "autotune_s": t_tune},
         "iteration_timeline_us": timeline_summary(tl),
     }
+    if nb > 1:
+        out["batch_slices_identical"] = batch_identical
     if args.served_requests > 0:
         # the metric's served part: a short Poisson stream at 20 req/s
         results, same = serve_streams([20.0], args.served_requests)
