@@ -598,9 +598,13 @@ __global__ __launch_bounds__(kAlphaThreads) void k_alpha(RayTable T, ProjArgs a)
     const int nblk = ((D.nd + kProjLanes - 1) / kProjLanes) * D.nv;
     const double* zp = a.partials + (size_t)z * a.part_stride;
     const double* ip = a.img_partials + (size_t)z * a.img_nblocks * 3;
-    // (data, num, coupling, regulariser), each thread over its own slots
+    // (data, num, coupling, regulariser), each thread over its own slots in
+    // ascending order (unrolled so that the loads are issued together; the
+    // additions keep their order)
     double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
     for (int i = threadIdx.x; i < nblk; i += kAlphaThreads) s[0] += zp[i];
+#pragma unroll 2
     for (int i = threadIdx.x; i < a.img_nblocks; i += kAlphaThreads) {
         s[1] += ip[3 * i];
         s[2] += ip[3 * i + 1];
