@@ -1029,6 +1029,8 @@ __host__ __device__ inline int sym8_units(int n) {
 // XCDs, each with its own L2, so the items are relabelled to give the blocks
 // of one XCD a contiguous run of items (slot b + r G keeps its block and
 // round, so every block does the same amount of work as without relabelling).
+// Only for launches whose slices are all eight-fold symmetric: the units of
+// other slices are skipped, and a run of them would leave its XCD idle.
 __device__ __forceinline__ int sym8_xcd_item(int b, int r, int G, int N) {
     const int x = b & 7, R = N / G, rem = N - R * G;
     int off = 0;
@@ -1087,7 +1089,7 @@ __device__ __forceinline__ void sym8_unit_orbits(int u, int nq, int& norb, int p
 template <bool SB>
 __global__ __launch_bounds__(kB8Waves * 64) void k_backproject_sym8(
     const void* __restrict__ sino, RayTable T, int n, float dxmm, float2* __restrict__ out_pairs,
-    float* __restrict__ out_split, int nout, int npairs) {
+    float* __restrict__ out_split, int nout, int npairs, bool by_xcd) {
     // staged rays, one struct so that the arrays read per ray in the
     // innermost loop sit at the lowest LDS addresses (constant offsets that
     // fit the ds_read offset field)
@@ -1111,7 +1113,7 @@ __global__ __launch_bounds__(kB8Waves * 64) void k_backproject_sym8(
     // register, values derived from it are spilled across the view loop)
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (int slot = blockIdx.x, round = 0; slot < nitem; slot += gridDim.x, ++round) {
-    const int unit = sym8_xcd_item(blockIdx.x, round, gridDim.x, nitem);
+    const int unit = by_xcd ? sym8_xcd_item(blockIdx.x, round, gridDim.x, nitem) : slot;
     const int z = unit / nunit, u = unit - z * nunit;
     const SliceDesc D = T.desc[T.desc_stride * z];
     if (D.sym != 2) continue;   // block-uniform
@@ -1426,12 +1428,13 @@ void launch_backproject(const Geom& g, const RayTable& t, const void* sino, int 
     if ((kinds & kSliceOcto) && grid_sym4(g)) {
         const int nunit = sym8_units(g.nx) * npairs;   // work units of all pairs
         dim3 grid(sym_bp_grid(nunit, bp_pct));
+        const bool by_xcd = kinds == kSliceOcto;
         if (sino_bf16)
             hipLaunchKernelGGL(k_backproject_sym8<true>, grid, dim3(kB8Waves * 64), 0, st, sino, t, g.nx,
-                               (float)g.dx, out_pairs, out_split, nout, npairs);
+                               (float)g.dx, out_pairs, out_split, nout, npairs, by_xcd);
         else
             hipLaunchKernelGGL(k_backproject_sym8<false>, grid, dim3(kB8Waves * 64), 0, st, sino, t, g.nx,
-                               (float)g.dx, out_pairs, out_split, nout, npairs);
+                               (float)g.dx, out_pairs, out_split, nout, npairs, by_xcd);
     }
 }
 

@@ -5,7 +5,8 @@ that the blocks of one XCD take a contiguous run of items, and the order of
 a slice's units over the first-quadrant tile pairs.
 
 The integer arithmetic is replayed as the kernel and its launcher compute
-it.  The test checks, for image sizes from one tile to 2048 pixels, batches
+it (the back-projector relabels its units when every slice of the launch
+is eight-fold symmetric; other launches take the units in slot order).  The test checks, for image sizes from one tile to 2048 pixels, batches
 of several slices and every back-projector share the schedule accepts:
   * every (slice, unit) item is processed exactly once, and every block
     processes as many items as it would without the relabelling;
