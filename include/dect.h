@@ -417,8 +417,11 @@ int dect_uneven_groups(const dect_uneven* u, int32_t* n_groups);
 int dect_uneven_init(dect_uneven* u, const float* sino_lo, const float* sino_hi);
 int dect_uneven_iterate(dect_uneven* u, int32_t n);
 int dect_uneven_finish(dect_uneven* u, float* Z_out, float* rho_out);
-/* dect_solver_autotune on each group (iters, reps as there; the inputs as
- * for dect_uneven_init), and each group's chosen schedule. */
+/* dect_solver_autotune on each group alone (iters, reps as there; the inputs
+ * as for dect_uneven_init); then, one group at a time, a group's choice is
+ * kept only if the whole handle (its groups' iterations interleaved) runs at
+ * least 2% faster with it than without.  The handle's iterate is left at the
+ * last trial's: init before solving. */
 int dect_uneven_autotune(dect_uneven* u, const float* sino_lo, const float* sino_hi, int32_t iters,
                          int32_t reps);
 int dect_uneven_get_schedule(const dect_uneven* u, int32_t group, dect_schedule* out);

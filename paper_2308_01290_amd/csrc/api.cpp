@@ -1960,16 +1960,79 @@ int dect_uneven_finish(dect_uneven* u, float* Z, float* rho_e) {
     return DECT_OK;
 }
 
+// one trial of the whole handle: init, then `iters` interleaved outer
+// iterations of every group, timed on the handle's stream
+static int uneven_trial(dect_uneven* u, const float* lo, const float* hi, int iters, hipEvent_t e0,
+                        hipEvent_t e1, float* ms) {
+    if (int rc = dect_uneven_init(u, lo, hi)) return rc;
+    DECT_HIP(hipEventRecord(e0, u->st));
+    if (int rc = dect_uneven_iterate(u, iters)) return rc;
+    DECT_HIP(hipEventRecord(e1, u->st));
+    DECT_HIP(hipEventSynchronize(e1));
+    DECT_HIP(hipEventElapsedTime(ms, e0, e1));
+    return DECT_OK;
+}
+
 int dect_uneven_autotune(dect_uneven* u, const float* lo, const float* hi, int32_t iters, int32_t reps) {
     if (!u || !lo || !hi) return fail(DECT_EINVAL, "dect_uneven_autotune: NULL argument");
-    for (size_t q = 0; q < u->grp.size(); ++q) {
+    if (iters < 1 || iters > 100 || reps < 1 || reps > 20)
+        return fail(DECT_EINVAL, "dect_uneven_autotune: iters must be in 1..100, reps in 1..20");
+    const size_t ng = u->grp.size();
+    std::vector<dect_schedule> start(ng), tuned(ng);
+    for (size_t q = 0; q < ng; ++q) start[q] = u->grp[q]->sched;
+    // each group alone
+    for (size_t q = 0; q < ng; ++q) {
         TempBuf buf;
         if (int rc = gather_group(u, q, lo, hi, &buf)) return rc;
         const float* dlo = static_cast<const float*>(buf.p);
-        if (int rc = dect_solver_autotune(u->grp[q], dlo, dlo + u->gsino[q], iters, reps, nullptr, nullptr))
+        if (int rc = dect_solver_autotune(u->grp[q], dlo, dlo + u->gsino[q], iters, reps, &tuned[q], nullptr))
             return rc;
     }
-    return DECT_OK;
+    // The groups share the device while their iterations interleave, so a
+    // group's choice is kept only if the whole handle runs at least 2%
+    // faster with it (one group at a time, from the starting schedules).
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    DECT_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(DECT_EDEVICE, "dect_uneven_autotune: hipEventCreate failed");
+    }
+    auto apply = [&](const std::vector<dect_schedule>& sc) -> int {
+        for (size_t q = 0; q < ng; ++q)
+            if (int rc = dect_solver_set_schedule(u->grp[q], &sc[q])) return rc;
+        return DECT_OK;
+    };
+    // median over `reps` trials after one untimed trial
+    auto measure = [&](const std::vector<dect_schedule>& sc, double* out) -> int {
+        if (int rc = apply(sc)) return rc;
+        std::vector<float> t((size_t)reps + 1);
+        for (int r = 0; r <= reps; ++r)
+            if (int rc = uneven_trial(u, lo, hi, iters, e0, e1, &t[(size_t)r])) return rc;
+        std::sort(t.begin() + 1, t.end());
+        *out = (double)t[1 + (size_t)reps / 2];
+        return DECT_OK;
+    };
+    std::vector<dect_schedule> best = start;
+    double tbest = 0.0;
+    int rc = measure(best, &tbest);
+    for (size_t q = 0; rc == DECT_OK && q < ng; ++q) {
+        if (std::memcmp(&tuned[q], &best[q], sizeof(dect_schedule)) == 0) continue;
+        std::vector<dect_schedule> c = best;
+        c[q] = tuned[q];
+        double t = 0.0;
+        if ((rc = measure(c, &t))) break;
+        if (t < 0.98 * tbest) {
+            best = c;
+            tbest = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) {
+        (void)apply(start);
+        return rc;
+    }
+    return apply(best);
 }
 
 int dect_uneven_get_schedule(const dect_uneven* u, int32_t group, dect_schedule* out) {

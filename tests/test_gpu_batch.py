@@ -85,10 +85,7 @@ def test_grid_sizes_of_the_multigrid_paths(n):
         assert np.isfinite(Z1).all() and (R1 > 0.5).mean() > 0.05
 
 
-def test_mixed_image_sizes_equal_each_alone():
-    """A batch of mixed image sizes (64^2, 96^2, 64^2, 96x48) through one
-    handle: the groups iterate together, and every slice's maps equal its solve
-    alone bit for bit; the outputs go back to back in slice order."""
+def mixed_sizes():
     phys = Physics()
     specs = [(64, 64, 90, 120, 0.0), (96, 96, 120, 160, 0.3), (64, 64, 80, 100, -0.2), (96, 48, 70, 128, 0.1)]
     geoms, los, his = [], [], []
@@ -101,6 +98,14 @@ def test_mixed_image_sizes_equal_each_alone():
         geoms.append(g)
         los.append(cuda(P.poisson_log(pL, 1e5, 220 + i).astype(np.float32)))
         his.append(cuda(P.poisson_log(pH, 1e5, 230 + i).astype(np.float32)))
+    return geoms, los, his
+
+
+def test_mixed_image_sizes_equal_each_alone():
+    """A batch of mixed image sizes (64^2, 96^2, 64^2, 96x48) through one
+    handle: the groups iterate together, and every slice's maps equal its solve
+    alone bit for bit; the outputs go back to back in slice order."""
+    geoms, los, his = mixed_sizes()
     K = 4
     params = dect.default_params(n_iter=K)
     sol = dect.UnevenSolver(geoms, params)
@@ -113,6 +118,24 @@ def test_mixed_image_sizes_equal_each_alone():
     for i, g in enumerate(geoms):
         Z1, R1 = (host(x)[0] for x in dect.solve(los[i][None], his[i][None], g, params))
         assert np.array_equal(host(Zs[i]), Z1) and np.array_equal(host(Rs[i]), R1), i
+
+
+def test_uneven_autotune_keeps_results():
+    """The handle's autotuner (each group alone, then each group's choice
+    confirmed on the whole handle) leaves valid schedules and the same maps."""
+    geoms, los, his = mixed_sizes()
+    K = 4
+    params = dect.default_params(n_iter=K)
+    lo, hi = dect.concat_sinograms(los), dect.concat_sinograms(his)
+    ref = [host(x) for x in dect.UnevenSolver(geoms, params).init(lo, hi).iterate(K).finish()]
+    sol = dect.UnevenSolver(geoms, params)
+    chosen = sol.autotune(lo, hi, iters=2, reps=1)
+    assert len(chosen) == sol.groups() == 3
+    assert all(c == sol.schedule(q) for q, c in enumerate(chosen))
+    got = [host(x) for x in sol.init(lo, hi).iterate(K).finish()]
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+    with pytest.raises(dect.DectError):
+        sol.autotune(lo, hi, iters=0)
 
 
 def test_mixed_symmetry_group_equals_each_alone():
