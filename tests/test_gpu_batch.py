@@ -171,3 +171,35 @@ def test_mixed_symmetry_group_equals_each_alone():
         sol.close()
         for i in range(len(geoms)):
             assert np.array_equal(Z[i], alone[i][0]) and np.array_equal(R[i], alone[i][1]), (i, sched)
+
+
+@pytest.mark.parametrize("pct", [0, 10, 15])
+def test_symmetric_batch_over_several_back_projector_rounds(pct):
+    """Eight slices of one eight-fold symmetric geometry (128^2, 120 views,
+    160 bins, 64 back-projector units) in one solver: one round of 64 blocks
+    by default; with a back-projector share of 10% of 256 CUs three rounds
+    of 22 blocks (not a multiple of the 8 XCDs, the last round partial),
+    with 15% two rounds of 32.  The units are relabelled so that each XCD's
+    blocks hold a contiguous run.  Every slice equals its solve alone bit
+    for bit."""
+    phys = Physics()
+    g = P.FanGeometry(n_x=128, n_y=128, pixel_mm=1.0, n_views=120, n_det=160, sid_mm=800.0,
+                      sdd_mm=1200.0).resolved()
+    los, his = [], []
+    for i in range(8):
+        ph = P.phantom_disk_inserts(seed=270 + i, radius=40.0, n_inserts=3, semi=(5.0, 10.0))
+        pL, pH = P.analytic_sinograms(ph, g, phys.mu_pair)
+        los.append(P.poisson_log(pL, 1e5, 280 + i).astype(np.float32))
+        his.append(P.poisson_log(pH, 1e5, 290 + i).astype(np.float32))
+    K = 3
+    params = dect.default_params(n_iter=K)
+    alone = [tuple(host(x)[0] for x in dect.solve(cuda(los[i][None]), cuda(his[i][None]), g, params))
+             for i in range(8)]
+    sol = dect.Solver(g, params, batch=8)
+    if pct:
+        sol.set_schedule(bp_cu_percent=pct)
+    sol.init(cuda(np.stack(los)), cuda(np.stack(his))).iterate(K)
+    Z, R = (host(x) for x in sol.finish())
+    sol.close()
+    for i in range(8):
+        assert np.array_equal(Z[i], alone[i][0]) and np.array_equal(R[i], alone[i][1]), (i, pct)
