@@ -107,6 +107,41 @@ def timeline_summary(tl):
             "pcg_slack_before_next_gradient": med(slack)}
 
 
+def small_workload_times(threads):
+    """The 128^2 workload (180 views, 256 bins, 10 iterations): the whole
+    oracle solve on all host cores, and the same solve on the GPU (a solver
+    kept across solves, as in the timed 512^2 steps; median of five after one
+    untimed)."""
+    import torch
+    from oracle import solve as S
+    from oracle.physics import Physics
+    from paper_2308_01290_amd import dect
+    from paper_2308_01290_amd import phantoms as P
+    phys = Physics()
+    g, _, pL, pH = P.workload_small(phys.mu_pair)
+    k = 10
+    t0 = time.perf_counter()
+    S.solve(pL.astype(np.float64), pH.astype(np.float64), g, phys, S.Params(n_iter=k), nthreads=threads)
+    t_cpu = time.perf_counter() - t0
+    dev = torch.device("cuda:0")
+    lo = torch.as_tensor(pL.astype(np.float32)[None], device=dev)
+    hi = torch.as_tensor(pH.astype(np.float32)[None], device=dev)
+    sol = dect.Solver(g, dect.default_params(n_iter=k))
+    ts = []
+    for r in range(6):
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        sol.init(lo, hi)
+        sol.iterate(k)
+        sol.finish()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - s0)
+    sol.close()
+    t_gpu = float(np.median(ts[1:]))
+    return {"workload": "128x128 at 1 mm, 180 views, 256 bins, 10 outer iterations",
+            "oracle_s_per_slice": t_cpu, "oracle_cores": threads, "gpu_ms_per_slice": 1e3 * t_gpu}
+
+
 def cpu_baseline(g, pL, pH, iters: int):
     """The FP64 oracle (as it stands) on the host cores: FBP start plus `iters`
     outer iterations, extrapolated to the 50-iteration solve.  A 1-core figure
@@ -138,6 +173,7 @@ def cpu_baseline(g, pL, pH, iters: int):
     t_one = fp_bp(1)
     per_slice_1 = per_slice * t_one / t_all
     return {"value": 1.0 / per_slice, "unit": "slices/s", "cores": threads, "kind": "oracle",
+            "small_workload": small_workload_times(threads),
             "sample": f"FBP start + {iters} of {N_ITER} outer iterations on the same 512^2 slice "
                       f"({t2 - t0:.1f} s), extrapolated to {N_ITER} iterations "
                       f"({per_slice:.1f} s per slice)",
